@@ -1,0 +1,223 @@
+"""The gDC time step (paper Sec. 3), the Euler-Maruyama step (Appendix D) and
+the force models of the synthetic workloads.
+
+One gDC step from x^n = (Y^n, q^n) (Lie-algebra elements reset to 0):
+  1. draw the stress noise; u_brev = L^-1 D W for this step (Sec. 4.2/5:
+     only J depends on the configuration, so the field is reused);
+  2. v_brev^n = J(x^n) u_brev, calV^n = (K^T K)^+ K^T v_brev^n (eq. unconst,
+     eq. sol_unconst);
+  3. nu = 1 + dt/2 (d_x . calV)^n, the divergence by forward differences
+     (eq. FD) with translations scaled by L_p (footnote of step 3), or by
+     random finite differences (eq. rfd_div);
+  4. x^m = x^n + dt/2 calV^n, q^m = exp(u^m) . q^n;
+  5. solve the full saddle problem at x^m with the same W (eq. step5);
+  6. x^{n+1} = x^n + nu dt V^m, q^{n+1} = exp(u^{n+1}) . q^n.
+
+Readings where the paper is silent: nu is one scalar for the whole
+suspension (the sum over p and i in eq. FD); the update uses
+u^{n+1} = nu dt Omega^m literally (no dexpinv factor); forces act only at
+the midpoint; L_p = max blob-blob distance in body p, or the blob radius for
+a single blob.
+
+Oracle code: test infrastructure only.
+"""
+
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy.spatial import cKDTree
+
+from . import fcm, noise, philox, rigid
+from .quaternion import qexp, qmul
+
+
+@dataclass
+class Forces:
+    """Force model of the synthetic workloads.
+    steric_k, steric_cutoff: harmonic blob-pair repulsion V = (k/2)(r - b)^2
+      for r < b between blobs of different bodies (the harmonic potential of
+      Sec. 6.3 used between blob pairs; k = 40 kT/(a b), b = 2.2 a there);
+    const_force: (6,) force and torque applied to every body;
+    shear_rate: imposed background flow u_inf = rate (y - L_y/2) e_x, with y
+      measured from the body's wrapped centre so the flow is continuous
+      across each body (not Lees-Edwards)."""
+    steric_k: float = 0.0
+    steric_cutoff: float = 0.0
+    const_force: np.ndarray = field(default_factory=lambda: np.zeros(6))
+    shear_rate: float = 0.0
+
+
+@dataclass
+class Config:
+    susp: rigid.Suspension
+    kT: float
+    dt: float
+    seed: int
+    forces: Forces
+    fd_delta: float = 1e-6
+    divergence: str = "fd"      # "fd" or "rfd"
+
+
+def body_length(shape, a):
+    """L_p: the maximum distance between two blobs of the body (footnote to
+    step 3); the blob radius a for a one-blob body."""
+    b = np.asarray(shape)
+    if b.shape[0] < 2:
+        return a
+    d = b[:, None, :] - b[None, :, :]
+    return float(np.sqrt((d * d).sum(-1)).max())
+
+
+def steric_blob_forces(cfg: Config, r):
+    """Blob forces of the harmonic pair repulsion, minimum image, pairs of
+    blobs in different bodies only.  -> (M, 3)."""
+    f = np.zeros_like(r)
+    F = cfg.forces
+    if F.steric_k == 0.0 or F.steric_cutoff <= 0.0:
+        return f
+    grid = cfg.susp.fcm.grid
+    rw = r - grid.L * np.floor(r / grid.L)
+    tree = cKDTree(rw, boxsize=grid.L)
+    pairs = tree.query_pairs(F.steric_cutoff, output_type="ndarray")
+    if pairs.size == 0:
+        return f
+    body = cfg.susp.bodies.body_of_blob()
+    pairs = pairs[body[pairs[:, 0]] != body[pairs[:, 1]]]
+    d = rw[pairs[:, 0]] - rw[pairs[:, 1]]
+    d = d - grid.L * np.round(d / grid.L)
+    dist = np.sqrt((d * d).sum(-1))
+    inside = dist < F.steric_cutoff
+    pairs, d, dist = pairs[inside], d[inside], dist[inside]
+    mag = F.steric_k * (F.steric_cutoff - dist)        # -dV/dr > 0: repulsive
+    fij = (mag / dist)[:, None] * d
+    np.add.at(f, pairs[:, 0], fij)
+    np.add.at(f, pairs[:, 1], -fij)
+    return f
+
+
+def body_forces(cfg: Config, Y, r):
+    """F^m: (N, 6) force and torque on each body = K^T f_blob + constant."""
+    b = cfg.susp.bodies
+    F = rigid.KT_apply(b, Y, r, steric_blob_forces(cfg, r))
+    return F + np.asarray(cfg.forces.const_force, dtype=np.float64)[None, :]
+
+
+def background_flow(cfg: Config, Y, r):
+    """u_inf at every blob (zero unless a shear rate is set)."""
+    out = np.zeros_like(r)
+    g = cfg.forces.shear_rate
+    if g == 0.0:
+        return out
+    Ly = cfg.susp.fcm.grid.L[1]
+    b = cfg.susp.bodies
+    Yb = np.asarray(Y).reshape(-1, 3)[b.body_of_blob()]
+    ywrap = (Yb[:, 1] - Ly * np.floor(Yb[:, 1] / Ly)) + (r[:, 1] - Yb[:, 1])
+    out[:, 0] = g * (ywrap - 0.5 * Ly)
+    return out
+
+
+def fluct_field(cfg: Config, step):
+    p = cfg.susp.fcm
+    return noise.fourier_field(p.grid, cfg.kT, p.eta, cfg.dt, cfg.seed, step)
+
+
+def averaged(cfg: Config, r, u):
+    p = cfg.susp.fcm
+    W = fcm.weight_matrix(r, p.grid, p.sigma, p.rc)
+    return fcm.interp(W, u, p.grid)
+
+
+def predictor(cfg: Config, Y, q, ufl):
+    """Steps 2-3: calV^n (N, 6) and the per-body forward-difference
+    divergences d_p, so that nu = 1 + dt/2 sum_p d_p.
+
+    Perturbing body p alone changes only calV^(p) (calV is per body and the
+    field is fixed), so the six perturbations are applied to all bodies at
+    once and differenced body by body."""
+    b = cfg.susp.bodies
+    Y = np.asarray(Y, dtype=np.float64).reshape(-1, 3)
+    q = np.asarray(q, dtype=np.float64).reshape(-1, 4)
+    r = rigid.blob_positions(b, Y, q)
+    calV = rigid.lsq_velocity(b, Y, r, averaged(cfg, r, ufl))
+    delta = cfg.fd_delta
+    Lp = np.array([body_length(b.shapes[s], cfg.susp.a) for s in b.body_shape])
+    d = np.zeros(b.N)
+    for al in range(3):
+        Yp = Y.copy()
+        Yp[:, al] += delta * Lp
+        rp = rigid.blob_positions(b, Yp, q)
+        Vp = rigid.lsq_velocity(b, Yp, rp, averaged(cfg, rp, ufl))
+        d += (Vp[:, al] - calV[:, al]) / (delta * Lp)
+    for al in range(3):
+        e = np.zeros((b.N, 3))
+        e[:, al] = delta
+        qp = qmul(qexp(e), q)
+        rp = rigid.blob_positions(b, Y, qp)
+        Vp = rigid.lsq_velocity(b, Y, rp, averaged(cfg, rp, ufl))
+        d += (Vp[:, 3 + al] - calV[:, 3 + al]) / delta
+    return calV, d
+
+
+def rfd_divergence(cfg: Config, Y, q, ufl, calV, step):
+    """Random finite difference (eq. rfd_div): W~ ~ N(0,1)^{6N} from Philox
+    (stage 1, counter c0 = body, two calls of which the first six normals are
+    used), translations scaled by L_p; returns per-body terms d_p whose sum
+    has the divergence as its expectation.  Parity unpinned beyond the
+    statistical law E[sum d_p] = d_x . calV."""
+    b = cfg.susp.bodies
+    Y = np.asarray(Y, dtype=np.float64).reshape(-1, 3)
+    q = np.asarray(q, dtype=np.float64).reshape(-1, 4)
+    idx = np.arange(b.N, dtype=np.uint64)
+    z = np.concatenate([philox.normals(cfg.seed, idx, 16 * noise.STAGE_RFD + c, step)
+                        for c in range(2)], axis=-1)[:, :6]
+    delta = cfg.fd_delta
+    Lp = np.array([body_length(b.shapes[s], cfg.susp.a) for s in b.body_shape])
+    Yp = Y + delta * Lp[:, None] * z[:, :3]
+    qp = qmul(qexp(delta * z[:, 3:]), q)
+    rp = rigid.blob_positions(b, Yp, qp)
+    Vp = rigid.lsq_velocity(b, Yp, rp, averaged(cfg, rp, ufl))
+    dV = Vp - calV
+    return (z[:, :3] * dV[:, :3]).sum(-1) / (delta * Lp) + (z[:, 3:] * dV[:, 3:]).sum(-1) / delta
+
+
+def midpoint(cfg: Config, Y, q, calV):
+    """Step 4: Y^m = Y^n + dt/2 calV_U, q^m = exp(dt/2 calV_Omega) . q^n."""
+    h = 0.5 * cfg.dt
+    return Y + h * calV[:, :3], qmul(qexp(h * calV[:, 3:]), q)
+
+
+def corrector_solve(cfg: Config, Ym, qm, ufl, tol=1e-12, dense=None):
+    """Step 5 at x^m: V^m from the saddle problem with slip v_brev^m + u_inf
+    and body forces F^m."""
+    b = cfg.susp.bodies
+    rm = rigid.blob_positions(b, Ym, qm)
+    slip = averaged(cfg, rm, ufl) + background_flow(cfg, Ym, rm)
+    F = body_forces(cfg, Ym, rm)
+    lam, V, info = rigid.solve_saddle(cfg.susp, Ym, rm, slip, F, tol=tol, dense=dense)
+    return V, info
+
+
+def gdc_step(cfg: Config, Y, q, step, tol=1e-12, dense=None):
+    """One gDC step (Sec. 3).  Returns (Y^{n+1}, q^{n+1}, diagnostics)."""
+    Y = np.asarray(Y, dtype=np.float64).reshape(-1, 3)
+    q = np.asarray(q, dtype=np.float64).reshape(-1, 4)
+    ufl = fluct_field(cfg, step)
+    calV, d = predictor(cfg, Y, q, ufl)
+    if cfg.divergence == "rfd":
+        d = rfd_divergence(cfg, Y, q, ufl, calV, step)
+    nu = 1.0 + 0.5 * cfg.dt * d.sum()
+    Ym, qm = midpoint(cfg, Y, q, calV)
+    V, info = corrector_solve(cfg, Ym, qm, ufl, tol=tol, dense=dense)
+    Y1 = Y + nu * cfg.dt * V[:, :3]
+    q1 = qmul(qexp(nu * cfg.dt * V[:, 3:]), q)
+    return Y1, q1, {"nu": nu, "calV": calV, "d": d, "V": V, **info}
+
+
+def em_step(cfg: Config, Y, q, step, tol=1e-12, dense=None):
+    """Euler-Maruyama (Appendix D): the full saddle problem at x^n with the
+    same random slip, x^{n+1} = x^n + dt V^n.  No drift correction."""
+    Y = np.asarray(Y, dtype=np.float64).reshape(-1, 3)
+    q = np.asarray(q, dtype=np.float64).reshape(-1, 4)
+    ufl = fluct_field(cfg, step)
+    V, info = corrector_solve(cfg, Y, q, ufl, tol=tol, dense=dense)
+    return Y + cfg.dt * V[:, :3], qmul(qexp(cfg.dt * V[:, 3:]), q), {"V": V, **info}

@@ -1,0 +1,243 @@
+"""Seeded synthetic inputs shared by the tests, the oracle runs and the bench.
+
+This module only builds inputs: body shapes (body-frame blob offsets),
+suspension parameters, and non-overlapping initial positions and
+orientations.  It holds none of the method's arithmetic (no mobility, no
+noise of the method, no time stepping); the placement check rotates blob
+offsets with its own axis-angle (Rodrigues) routine, used for nothing else.
+Both the HIP library and the oracle recompute blob positions themselves.
+
+Workloads (sizes of the five suspensions the paper's method is exercised on):
+  rods8        8 rods x 5 blobs, L = 32a, grid 48^3, dt = 0.01, no forces, FP64
+  rods1000     1,000 rods x 10 blobs, L = 128a, grid 128^3, dt = 0.005,
+               harmonic blob-pair repulsion (cutoff 2.2a)
+  mixed4096    1,366 rods(10) + 1,365 boomerangs(15) + 1,365 tetrahedra(4),
+               L = 256a, grid 256^3, constant force e_z on every body
+  serving      256 requests of N rods (10 blobs), N log-uniform in [8, 2048],
+               box at 5% blob volume fraction, grid from {32,48,64,96,128}
+  rods32768    32,768 rods x 10 blobs, L = 384a, grid 384^3, axes within 15
+               degrees of z, shear rate 0.1 plus the pair repulsion
+Common: a = 1, eta = 1/(6 pi), kT = 1, sigma = a/sqrt(pi), cutoff 3a.
+"""
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+A = 1.0
+ETA = 1.0 / (6.0 * math.pi)
+KT = 1.0
+SIGMA = A / math.sqrt(math.pi)
+
+
+# ------------------------------------------------------------------ shapes
+
+def _centred(b):
+    b = np.asarray(b, dtype=np.float64)
+    return b - b.mean(axis=0)
+
+
+def rod(n_blobs, spacing=2.0 * A):
+    """Straight rod of collinear blobs along the body z axis."""
+    return _centred([[0.0, 0.0, spacing * i] for i in range(n_blobs)])
+
+
+def boomerang(spacing=A):
+    """L-shaped boomerang: a corner blob plus 7 blobs along each of the body
+    x and y axes at the given spacing (15 blobs, two 8-blob arms)."""
+    pts = [[0.0, 0.0, 0.0]]
+    pts += [[spacing * i, 0.0, 0.0] for i in range(1, 8)]
+    pts += [[0.0, spacing * i, 0.0] for i in range(1, 8)]
+    return _centred(pts)
+
+
+def tetrahedron(edge=2.0 * A):
+    """Regular tetrahedron of 4 blobs with the given edge length."""
+    s = edge / (2.0 * math.sqrt(2.0))
+    return _centred([[s, s, s], [s, -s, -s], [-s, s, -s], [-s, -s, s]])
+
+
+# ------------------------------------------------------------------ configs
+
+@dataclass
+class Workload:
+    name: str
+    L: tuple
+    n: tuple
+    shapes: list
+    body_shape: np.ndarray
+    dt: float
+    steps: int
+    noise_seed: int
+    placement_seed: int
+    precision: str = "fp32"
+    a: float = A
+    sigma: float = SIGMA
+    rc: float = 3.0 * A
+    eta: float = ETA
+    kT: float = KT
+    steric_k: float = 0.0
+    steric_cutoff: float = 0.0
+    const_force: tuple = (0.0, 0.0, 0.0, 0.0, 0.0, 0.0)
+    shear_rate: float = 0.0
+    nematic_cap_deg: float = 0.0     # 0: orientations uniform on S^3
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def N(self):
+        return int(len(self.body_shape))
+
+    @property
+    def M(self):
+        return int(sum(len(self.shapes[s]) for s in self.body_shape))
+
+    @property
+    def G(self):
+        return int(np.prod(self.n))
+
+
+def _steric():
+    b = 2.2 * A
+    return dict(steric_k=40.0 * KT / (A * b), steric_cutoff=b)
+
+
+def rods8():
+    return Workload("rods8", (32.0,) * 3, (48,) * 3, [rod(5)], np.zeros(8, np.int64),
+                    dt=0.01, steps=100, noise_seed=0, placement_seed=1000, precision="fp64")
+
+
+def rods1000(precision="fp32"):
+    return Workload("rods1000", (128.0,) * 3, (128,) * 3, [rod(10)], np.zeros(1000, np.int64),
+                    dt=0.005, steps=1000, noise_seed=2, placement_seed=1002,
+                    precision=precision, **_steric())
+
+
+def mixed4096():
+    body_shape = np.concatenate([np.zeros(1366, np.int64), np.ones(1365, np.int64),
+                                 np.full(1365, 2, np.int64)])
+    return Workload("mixed4096", (256.0,) * 3, (256,) * 3,
+                    [rod(10), boomerang(), tetrahedron()], body_shape,
+                    dt=0.005, steps=100, noise_seed=3, placement_seed=1003,
+                    const_force=(0.0, 0.0, 1.0, 0.0, 0.0, 0.0))
+
+
+def rods32768(steric=True):
+    kw = _steric() if steric else {}
+    return Workload("rods32768", (384.0,) * 3, (384,) * 3, [rod(10)],
+                    np.zeros(32768, np.int64), dt=0.005, steps=10000, noise_seed=5,
+                    placement_seed=1005, shear_rate=0.1, nematic_cap_deg=15.0, **kw)
+
+
+def small_case(name="tiny", n_bodies=4, n=16, L=16.0, shapes=None, body_shape=None,
+               precision="fp64", seed=7, **kw):
+    """Small suspensions for parity tests (oracle runs in seconds)."""
+    shapes = shapes if shapes is not None else [rod(3)]
+    if body_shape is None:
+        body_shape = np.arange(n_bodies) % len(shapes)
+    Ls = tuple(L) if isinstance(L, (tuple, list)) else (float(L),) * 3
+    ns = tuple(n) if isinstance(n, (tuple, list)) else (int(n),) * 3
+    return Workload(name, Ls, ns, shapes, np.asarray(body_shape, np.int64), dt=kw.pop("dt", 0.01),
+                    steps=kw.pop("steps", 3), noise_seed=seed, placement_seed=seed + 1000,
+                    precision=precision, **kw)
+
+
+def serving_requests(n_requests=256, seed=4):
+    """The serving stream: N log-uniform in [8, 2048] rods of 10 blobs, box at
+    5% volume fraction, grid the smallest of {32,48,64,96,128} >= L/a,
+    50 steps, noise seed = request index, Poisson arrivals at unit rate."""
+    rng = np.random.default_rng(seed)
+    grids = [32, 48, 64, 96, 128]
+    out = []
+    t = 0.0
+    for r in range(n_requests):
+        N = int(round(math.exp(rng.uniform(math.log(8), math.log(2048)))))
+        L = (10 * N * (4.0 / 3.0) * math.pi * A ** 3 / 0.05) ** (1.0 / 3.0)
+        n = next(g for g in grids if g >= L / A)
+        t += rng.exponential(1.0)
+        w = Workload(f"req{r}", (L,) * 3, (n,) * 3, [rod(10)], np.zeros(N, np.int64),
+                     dt=0.005, steps=50, noise_seed=r, placement_seed=10000 + r)
+        w.extra["arrival"] = t
+        out.append(w)
+    return out
+
+
+# ------------------------------------------------------- initial placement
+
+def _rodrigues(axis, angle, v):
+    """Rotate vectors v (k, 3) about the unit axis by angle (right hand)."""
+    c, s = math.cos(angle), math.sin(angle)
+    return v * c + np.cross(axis, v) * s + np.outer(v @ axis, axis) * (1.0 - c)
+
+
+def _random_orientation(rng, cap_deg):
+    """(quaternion, axis, angle).  cap_deg = 0: uniform on S^3 (normalised
+    four normals); otherwise the body z axis uniform in the cap of half-angle
+    cap_deg about the lab z axis (no spin: rods are symmetric about it)."""
+    if cap_deg <= 0.0:
+        q = rng.standard_normal(4)
+        q /= np.linalg.norm(q)
+        if q[0] < 0:
+            q = -q
+        angle = 2.0 * math.acos(min(1.0, q[0]))
+        v = q[1:]
+        nv = np.linalg.norm(v)
+        axis = v / nv if nv > 0 else np.array([0.0, 0.0, 1.0])
+        return q, axis, angle
+    cmin = math.cos(math.radians(cap_deg))
+    ct = rng.uniform(cmin, 1.0)
+    phi = rng.uniform(0.0, 2.0 * math.pi)
+    e = np.array([math.sqrt(1 - ct * ct) * math.cos(phi), math.sqrt(1 - ct * ct) * math.sin(phi), ct])
+    axis = np.cross([0.0, 0.0, 1.0], e)
+    na = np.linalg.norm(axis)
+    angle = math.acos(ct)
+    axis = axis / na if na > 1e-15 else np.array([1.0, 0.0, 0.0])
+    q = np.concatenate([[math.cos(angle / 2)], math.sin(angle / 2) * axis])
+    return q, axis, angle
+
+
+def initial_state(w: Workload, min_dist=2.0 * A, max_tries=2000):
+    """Centres uniform in the box, orientations as described, rejecting any
+    placement that puts a blob within min_dist (minimum image) of a blob of
+    another body.  Returns Y (N, 3) and q (N, 4), FP64."""
+    rng = np.random.default_rng(w.placement_seed)
+    L = np.asarray(w.L, dtype=np.float64)
+    cell = max(min_dist, 1e-9)
+    nc = np.maximum((L // cell).astype(int), 1)
+    bins = {}
+    Y = np.zeros((w.N, 3))
+    Q = np.zeros((w.N, 4))
+
+    def key(p):
+        return tuple((np.floor(p / (L / nc)).astype(int)) % nc)
+
+    for p in range(w.N):
+        b = w.shapes[w.body_shape[p]]
+        for _ in range(max_tries):
+            c = rng.uniform(0.0, 1.0, 3) * L
+            q, axis, angle = _random_orientation(rng, w.nematic_cap_deg)
+            pts = c + _rodrigues(axis, angle, b)
+            ok = True
+            for x in pts:
+                k = key(x - L * np.floor(x / L))
+                for dk in np.ndindex(3, 3, 3):
+                    kk = tuple((np.array(k) + np.array(dk) - 1) % nc)
+                    for y in bins.get(kk, ()):
+                        d = x - y
+                        d -= L * np.round(d / L)
+                        if d @ d < min_dist * min_dist:
+                            ok = False
+                            break
+                    if not ok:
+                        break
+                if not ok:
+                    break
+            if ok:
+                break
+        else:
+            raise RuntimeError(f"could not place body {p} of {w.name}")
+        Y[p], Q[p] = c, q
+        for x in pts:
+            xw = x - L * np.floor(x / L)
+            bins.setdefault(key(xw), []).append(xw)
+    return Y, Q
