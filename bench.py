@@ -1,0 +1,128 @@
+"""Throughput of the gDC step on one MI355X: blob-steps/s with p50/p99 step
+latency, on the 1,000-rod suspension (10,000 blobs, L = 128a, grid 128^3,
+FP32 grid with FP64 body algebra, harmonic pair repulsion, dt = 0.005).
+
+One step is the whole hot path: stress noise and the random velocity field,
+the least-squares velocity and the finite-difference drift factor, the
+midpoint move, pair forces, the full saddle solve by GMRES, and the update.
+Inputs stay resident in HBM (device tensors) for the timed region.
+
+The GMRES tolerance is the loosest in a ladder whose FP32 body-mobility
+solve stays within 1e-5 (relative L2) of the library's FP64 solve (itself
+parity-tested against the FP64 oracle), on the first state with a probe force
+F ~ N(0,1) per body.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "blob-steps/sec of gDC step at 1e-5 rel mobility error; p50/p99 step latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def calibrate(g, wl, w, Y0, q0, target=1e-5):
+    import numpy as np
+    rng = np.random.default_rng(1234)
+    F = rng.standard_normal((w.N, 6))
+    ref = g.Suspension(**wl.library_kwargs(w, precision="fp64", gmres_tol=1e-12, gmres_maxit=1000))
+    Vref = ref.mobility_apply("body", Y0, q0, F)
+    ref.close()
+    chosen = None
+    for tol in [1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7]:
+        s = g.Suspension(**wl.library_kwargs(w, precision="fp32", gmres_tol=tol, gmres_maxit=500))
+        V = s.mobility_apply("body", Y0, q0, F, allow_notconv=True)
+        s.close()
+        err = float(np.linalg.norm(V - Vref) / np.linalg.norm(Vref))
+        if err <= target:
+            chosen = (tol, err)
+            break
+    if chosen is None:
+        raise RuntimeError("no GMRES tolerance reaches the target mobility error")
+    return chosen
+
+
+def cpu_baseline(w, Y0, q0, tol):
+    """The FP64 oracle, as it stands, on one step of the same workload."""
+    import numpy as np
+    from oracle import fcm, gdc, rigid
+    cores = len(os.sched_getaffinity(0))
+    fcm.DEFAULT_WORKERS = cores
+    p = fcm.FcmParams(fcm.Grid(w.L, w.n), w.eta, w.sigma, w.rc)
+    cfg = gdc.Config(rigid.Suspension(p, rigid.Bodies(w.shapes, w.body_shape), w.a), w.kT, w.dt,
+                     w.noise_seed, gdc.Forces(w.steric_k, w.steric_cutoff,
+                                              np.asarray(w.const_force, dtype=np.float64), w.shear_rate))
+    t0 = time.perf_counter()
+    gdc.gdc_step(cfg, Y0, q0, 0, tol=tol)
+    dt = time.perf_counter() - t0
+    return {"value": w.M / dt, "unit": "blob-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"one gDC step of the same 1,000-rod suspension from the same state, "
+                      f"GMRES tol {tol:g}, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the sharding design); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2106_00449_amd as g
+    import workloads as wl
+
+    w = wl.rods1000("fp32")
+    Y0, q0 = wl.initial_state(w)
+    tol, err = calibrate(g, wl, w, Y0, q0)
+
+    stream = torch.cuda.current_stream()
+    s = g.Suspension(**wl.library_kwargs(w, gmres_tol=tol, gmres_maxit=500, stream=stream.cuda_stream))
+    Y = torch.tensor(Y0, dtype=torch.float64, device="cuda")
+    q = torch.tensor(q0, dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        s.step(Y, q, 1)
+    torch.cuda.synchronize()
+    lat, its, nus = [], [], []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        st = s.step(Y, q, 1)
+        lat.append(time.perf_counter() - t0)
+        its.append(st["gmres_iterations"])
+        nus.append(st["nu"])
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    value = w.M * args.steps / total
+    lat_ms = np.array(lat) * 1e3
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "blob-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": total * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "rods1000: 1,000 rods x 10 blobs (10,000 blobs), L=128a, grid 128^3, "
+                               "FP32 grid / FP64 bodies and Krylov, harmonic pair repulsion 2.2a, dt=0.005",
+                   "gmres_tol": tol, "mobility_rel_err": err,
+                   "gmres_iterations_mean": float(np.mean(its)),
+                   "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+                   "nu_mean": float(np.mean(nus))},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, Y0, q0, tol)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * gdc.h -- C ABI of the MI355X (gfx950) library for the generalised
+ * drift-correcting (gDC) Brownian-dynamics step of rigid multiblob particles
+ * with fluctuating force-coupling (FCM) hydrodynamics in a periodic box.
+ *
+ * Method: Westwood, Delmotte & Keaveny, "A generalised drift-correcting time
+ * integration scheme for Brownian suspensions of rigid particles with
+ * arbitrary shape", arXiv 2106.00449.  Paper sections are cited per entry.
+ *
+ * Conventions common to every entry point
+ *   - Arrays are row-major FP64 at the boundary in both precision modes.
+ *     Y: N x 3 body reference points (unwrapped, box coordinates);
+ *     q: N x 4 unit quaternions, scalar first, Hamilton product (Appendix A);
+ *     blob vectors (lambda, v): M x 3 with the blobs of body 0 first, then
+ *     body 1, ..., each body's blobs in its shape's order;
+ *     body vectors (F, V): N x 6 = (force or velocity, torque or angular
+ *     velocity), lab frame.
+ *     Grid fields: 3 x n0 x n1 x n2 (component, then axis 0, 1, 2 of the box;
+ *     axis 2 fastest); grid point g sits at (g0 dx0, g1 dx1, g2 dx2).
+ *   - memspace = GDC_HOST: the pointers are host memory, the library copies
+ *     in and out and synchronises its stream before returning.
+ *     memspace = GDC_DEVICE: the pointers are device memory on the handle's
+ *     device, read and written in stream order on the handle's stream; the
+ *     call still synchronises where it must read a scalar back (GMRES
+ *     convergence) and before returning.
+ *   - The caller owns every array passed in or out.  The library owns all
+ *     state inside a handle until gdc_free.  A handle is used by one thread
+ *     at a time; distinct handles are independent.
+ *   - Return value: GDC_OK (0) or a negative error code; nothing aborts or
+ *     throws across the ABI.  gdc_last_error() gives a message for the most
+ *     recent failure on the calling thread.
+ *   - Units are the caller's; with a = 1, eta = 1/(6 pi) and kT = 1 the
+ *     one-blob mobility and the diffusive time a^2/D are 1 (Sec. 6.2).
+ */
+#ifndef GDC_H
+#define GDC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GDC_OK = 0,
+  GDC_EINVAL = -1,    /* bad argument: sizes, non-unit quaternion, grid size */
+  GDC_ENOMEM = -2,    /* device or host allocation failed */
+  GDC_ENOTCONV = -3,  /* GMRES hit its iteration limit; outputs still written */
+  GDC_ENUMERIC = -4,  /* NaN or Inf in a result */
+  GDC_EDEVICE = -5    /* a HIP runtime error */
+};
+
+enum { GDC_FP32 = 0, GDC_FP64 = 1 };          /* grid precision */
+enum { GDC_HOST = 0, GDC_DEVICE = 1 };        /* memspace */
+enum { GDC_BLOB = 0, GDC_BODY = 1 };          /* gdc_mobility_apply mode */
+enum { GDC_SCHEME_GDC = 0, GDC_SCHEME_EM = 1 };
+enum { GDC_DIV_FD = 0, GDC_DIV_RFD = 1 };
+
+/* A rigid body shape: n_blobs body-frame blob offsets b_i (n_blobs x 3);
+ * a body with reference point Y and orientation q has blobs at
+ * r_i = Y + R(q) b_i (Sec. 2, eq. quaternion_rotation_matrix). */
+typedef struct {
+  int n_blobs;
+  const double* b;
+} gdc_shape;
+
+/* Forces applied at the midpoint of each step (Sec. 3, step 5).
+ *   steric_k, steric_cutoff: harmonic repulsion V(r) = k/2 (r - cutoff)^2 for
+ *     r < cutoff between blobs of different bodies (the harmonic potential of
+ *     Sec. 6.3 applied to blob pairs); 0 disables it.
+ *   const_force: force and torque added to every body.
+ *   shear_rate: background flow u(r) = rate (y - L1/2) e_x at each blob, y
+ *     measured from the body's wrapped reference point (not Lees-Edwards). */
+typedef struct {
+  double steric_k;
+  double steric_cutoff;
+  double const_force[6];
+  double shear_rate;
+} gdc_forces;
+
+/* Suspension and solver parameters (Sec. 2-4, Sec. 6.1).
+ *   L[3], n[3]: periodic box and grid; each n_d even, of the form 2^a 3^b,
+ *     8 <= n_d <= 512.
+ *   a: blob radius; sigma: Gaussian envelope width (0 -> a/sqrt(pi), Sec. 4.2);
+ *   trunc: envelope cutoff radius (0 -> 3a, Sec. 6.1), below min(L)/2.
+ *   eta, kT, dt: viscosity, thermal energy, time step.
+ *   fd_delta: finite-difference parameter of step 3 (0 -> 1e-6, Sec. 6.2).
+ *   gmres_tol: relative residual of the step-5 saddle solve (0 -> 1e-6);
+ *   gmres_maxit (0 -> 200), gmres_restart (0 -> 50).
+ *   precision: GDC_FP32 (grid in FP32, bodies and Krylov in FP64) or GDC_FP64.
+ *   scheme: GDC_SCHEME_GDC (Sec. 3) or GDC_SCHEME_EM (Appendix D).
+ *   divergence: GDC_DIV_FD (eq. FD) or GDC_DIV_RFD (eq. rfd_div).
+ *   seed: Philox4x32-10 key of every random number of the run.
+ *   shapes[n_shapes]; body_shape[n_bodies]: shape index of each body.
+ *   device: HIP device ordinal; stream: a hipStream_t or NULL (the library
+ *     then creates its own stream at default priority). */
+typedef struct {
+  double L[3];
+  int n[3];
+  double a, sigma, trunc, eta, kT, dt, fd_delta;
+  double gmres_tol;
+  int gmres_maxit, gmres_restart;
+  int precision, scheme, divergence;
+  uint64_t seed;
+  int n_shapes;
+  const gdc_shape* shapes;
+  int n_bodies;
+  const int* body_shape;
+  gdc_forces forces;
+  int device;
+  void* stream;
+} gdc_config;
+
+/* Per-call statistics of gdc_step (values of the last step taken). */
+typedef struct {
+  int steps_done;
+  int gmres_iterations;      /* preconditioned GMRES iterations, last step */
+  double gmres_relres;       /* final relative residual, last step */
+  double nu;                 /* drift factor nu of the last step (Sec. 3, step 3) */
+  int nu_nonpositive;        /* steps of this call whose nu was <= 0 */
+  double ms;                 /* wall time of the call */
+} gdc_stats;
+
+typedef struct gdc_handle gdc_handle;
+
+/* Validate cfg, copy what the library needs (shapes are copied), allocate
+ * the device arena and build the per-shape tables (pseudo-inverse of K^T K,
+ * null-space projector, preconditioner inverse).  *out receives the handle.
+ * Errors: GDC_EINVAL (bad sizes or parameters), GDC_ENOMEM, GDC_EDEVICE. */
+int gdc_init(const gdc_config* cfg, gdc_handle** out);
+
+/* Release everything the handle owns.  NULL is accepted. */
+void gdc_free(gdc_handle* h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* gdc_last_error(void);
+
+/* Apply the deterministic mobility at configuration (Y, q) (Sec. 2.2, 4.2).
+ *   mode GDC_BLOB: in = lambda (M x 3) -> out = M_FCM lambda (M x 3),
+ *     M_FCM = J L^-1 S: Gaussian spreading, spectral Stokes solve with the
+ *     k = 0 and Nyquist modes removed, trapezoidal averaging.
+ *   mode GDC_BODY: in = F (N x 6) -> out = V = N F (N x 6), the solution of
+ *     the saddle problem [[M, -K], [-K^T, 0]] [lambda; V] = [0; -F] (eq.
+ *     saddle_point_sys) by right-preconditioned GMRES to gmres_tol with the
+ *     block-diagonal preconditioner of Sec. 2.2.  Degrees of freedom that move
+ *     no blob (spin of a straight rod, rotation of a one-blob body) are held
+ *     at zero and the matching torque component is ignored.
+ * No noise.  Errors: GDC_EINVAL, GDC_ENOTCONV (out still written),
+ * GDC_ENUMERIC, GDC_EDEVICE. */
+int gdc_mobility_apply(gdc_handle* h, int mode, const double* Y, const double* q,
+                       const double* in, double* out, int memspace);
+
+/* Advance (Y, q) in place by n_steps steps of the configured scheme (Sec. 3:
+ * noise, least-squares velocity, finite-difference or RFD divergence, midpoint,
+ * full saddle solve with the same noise, update; or Appendix D).  The noise of
+ * internal step s uses Philox counters keyed by (seed, s); the internal step
+ * counter starts at 0 and advances by one per step.  st may be NULL.
+ * Errors: GDC_EINVAL, GDC_ENOTCONV (the step is still taken), GDC_ENUMERIC,
+ * GDC_EDEVICE. */
+int gdc_step(gdc_handle* h, int n_steps, double* Y, double* q, int memspace, gdc_stats* st);
+
+/* Internal step counter (checkpoint / resume: with the same state and
+ * counter a resumed run repeats an uninterrupted one exactly). */
+int gdc_get_step(const gdc_handle* h, uint64_t* step);
+int gdc_set_step(gdc_handle* h, uint64_t step);
+
+/* The random velocity field u_brev = L^-1 D W of step `step` (Sec. 4.2, 5):
+ * 3 x n0 x n1 x n2, FP64 (rounded from FP32 in FP32 mode).  The stress
+ * spectrum is drawn in Fourier space: per stored half-spectrum mode 12
+ * normals (Re, Im of W_xx, W_yy, W_zz, W_xy, W_xz, W_yz), scaled to the law of
+ * the real-space construction of Sec. 6.1. */
+int gdc_fluct_velocity(gdc_handle* h, uint64_t step, double* u, int memspace);
+
+/* Steps 1-3 of Sec. 3 at (Y, q) for step `step`: calV (N x 6), the
+ * least-squares rigid velocity of the averaged random velocities (eq.
+ * sol_unconst), and d (N), each body's term of the divergence, so that
+ * nu = 1 + dt/2 sum_p d_p (eq. FD, or eq. rfd_div in RFD mode). */
+int gdc_predictor(gdc_handle* h, const double* Y, const double* q, uint64_t step,
+                  double* calV, double* d, int memspace);
+
+/* The library's normal generator, for checking the noise contract: for
+ * c0 in [c0_begin, c0_begin + count), Philox4x32-10 with key = seed and
+ * counter (c0, c1, step lo, step hi), each word pair turned into two normals
+ * by Box-Muller; out (host, count x 4). */
+int gdc_philox_normals(gdc_handle* h, uint64_t seed, uint32_t c1, uint64_t step,
+                       uint32_t c0_begin, int count, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GDC_H */

@@ -29,6 +29,11 @@ import scipy.fft
 import scipy.sparse
 
 
+# Threads for scipy.fft (None: scipy's default of one); callers that time the
+# oracle may set the host's core count here.
+DEFAULT_WORKERS = None
+
+
 @dataclass
 class Grid:
     L: np.ndarray  # (3,) box lengths
@@ -134,6 +139,7 @@ def project_spectrum(fh, grid, eta):
 
 def stokes_solve(f, grid, eta, workers=None):
     """u = L^-1 f on the periodic grid (Sec. 4.2): rfftn, projection, irfftn."""
+    workers = DEFAULT_WORKERS if workers is None else workers
     fh = scipy.fft.rfftn(f, axes=(1, 2, 3), workers=workers)
     uh = project_spectrum(fh, grid, eta)
     return scipy.fft.irfftn(uh, s=grid.n, axes=(1, 2, 3), workers=workers)

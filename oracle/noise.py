@@ -34,6 +34,7 @@ import numpy as np
 import scipy.fft
 
 from . import philox
+from . import fcm
 from .fcm import Grid, wavevectors, project_spectrum
 
 STAGE_STRESS = 0
@@ -112,7 +113,7 @@ def fluct_velocity_from_spectrum(Wh, grid: Grid, eta):
     projection, inverse DFT."""
     g = divergence_spectrum(Wh, grid)
     uh = project_spectrum(g, grid, eta)
-    return scipy.fft.irfftn(uh, s=grid.n, axes=(1, 2, 3))
+    return scipy.fft.irfftn(uh, s=grid.n, axes=(1, 2, 3), workers=fcm.DEFAULT_WORKERS)
 
 
 def fourier_field(grid: Grid, kT, eta, dt, seed, step):

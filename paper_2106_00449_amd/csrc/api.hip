@@ -1,0 +1,1019 @@
+// C ABI of libgdc: handle set-up, the mobility operators, the device GMRES
+// driver and the gDC / Euler-Maruyama step orchestration.
+//
+// Everything per step runs on the handle's stream; the host reads back only
+// the GMRES Hessenberg column of each iteration (to decide convergence) and
+// the step's drift factor nu for the statistics.
+
+#include "gdc_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+
+namespace gdc {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(std::string("launch of ") + what + ": " + hipGetErrorString(e));
+    return GDC_EDEVICE;
+  }
+  return GDC_OK;
+}
+
+namespace {
+
+constexpr int DOT_BLOCKS = 512;
+constexpr int HCOLS = 64;       // device scratch per Hessenberg column section
+constexpr double PINV_RCOND = 1e-10;
+
+// ------------------------------------------------------------ host linear algebra
+
+// Symmetric eigen-decomposition by cyclic Jacobi rotations (n small).
+void jacobi_eigen(int n, std::vector<double> A, std::vector<double>& evals, std::vector<double>& evecs) {
+  evecs.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i) evecs[i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += A[i * n + j] * A[i * n + j];
+        if (i != j) off += A[i * n + j] * A[i * n + j];
+      }
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {  // A <- J^T A J
+          const double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - s * akq;
+          A[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - s * aqk;
+          A[q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = evecs[k * n + p], vkq = evecs[k * n + q];
+          evecs[k * n + p] = c * vkp - s * vkq;
+          evecs[k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  evals.resize(n);
+  for (int i = 0; i < n; ++i) evals[i] = A[i * n + i];
+}
+
+// Inverse by Gauss-Jordan elimination with partial pivoting; false if singular.
+bool invert(int n, std::vector<double> A, std::vector<double>& inv) {
+  inv.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+    if (std::fabs(A[piv * n + c]) < 1e-300) return false;
+    if (piv != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(A[c * n + k], A[piv * n + k]);
+        std::swap(inv[c * n + k], inv[piv * n + k]);
+      }
+    const double d = 1.0 / A[c * n + c];
+    for (int k = 0; k < n; ++k) {
+      A[c * n + k] *= d;
+      inv[c * n + k] *= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = A[r * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        A[r * n + k] -= f * A[c * n + k];
+        inv[r * n + k] -= f * inv[c * n + k];
+      }
+    }
+  }
+  return true;
+}
+
+// Unbounded RPY tensor for equal radii a at separation d (3x3 row-major).
+void rpy(const double* d, double a, double eta, double* T) {
+  const double r = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  const double pi = 3.14159265358979323846;
+  if (r == 0.0) {
+    for (int k = 0; k < 9; ++k) T[k] = (k % 4 == 0) ? 1.0 / (6.0 * pi * eta * a) : 0.0;
+    return;
+  }
+  double ci, cr;
+  if (r >= 2.0 * a) {
+    ci = (1.0 + 2.0 * a * a / (3.0 * r * r)) / (8.0 * pi * eta * r);
+    cr = (1.0 - 2.0 * a * a / (r * r)) / (8.0 * pi * eta * r);
+  } else {
+    ci = (1.0 - 9.0 * r / (32.0 * a)) / (6.0 * pi * eta * a);
+    cr = (3.0 * r / (32.0 * a)) / (6.0 * pi * eta * a);
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) T[3 * i + j] = (i == j ? ci : 0.0) + cr * d[i] * d[j] / (r * r);
+}
+
+struct ShapeHost {
+  int nb = 0;
+  std::vector<double> b;       // nb x 3
+  double Lp = 0.0;
+  double pinv[36];
+  double null[36];
+  bool has_null = false;
+  std::vector<double> precT;   // D x D transposed inverse, D = 3 nb + 6
+};
+
+// Builds K^T K (body frame), its pseudo-inverse, the null-space projector and
+// the inverse of the preconditioner block [[M_RPY, -K], [-K^T, -Pi]].
+bool build_shape(ShapeHost& S, double a, double eta, std::string& err) {
+  const int nb = S.nb;
+  std::vector<double> A(36, 0.0);
+  for (int i = 0; i < nb; ++i) {
+    const double* r = &S.b[3 * i];
+    // K_i = [I, [x r]]  with [x r] = -[r x]
+    double Ki[18];
+    for (int k = 0; k < 18; ++k) Ki[k] = 0.0;
+    for (int k = 0; k < 3; ++k) Ki[6 * k + k] = 1.0;
+    const double cx[9] = {0, -r[2], r[1], r[2], 0, -r[0], -r[1], r[0], 0};  // [r x]
+    for (int row = 0; row < 3; ++row)
+      for (int col = 0; col < 3; ++col) Ki[6 * row + 3 + col] = -cx[3 * row + col];
+    for (int p = 0; p < 6; ++p)
+      for (int q = 0; q < 6; ++q)
+        for (int k = 0; k < 3; ++k) A[6 * p + q] += Ki[6 * k + p] * Ki[6 * k + q];
+  }
+  std::vector<double> ev, V;
+  jacobi_eigen(6, A, ev, V);
+  double emax = 0.0;
+  for (double e : ev) emax = std::max(emax, std::fabs(e));
+  for (int k = 0; k < 36; ++k) S.pinv[k] = S.null[k] = 0.0;
+  for (int m = 0; m < 6; ++m) {
+    const bool keep = ev[m] > PINV_RCOND * emax;
+    if (!keep) S.has_null = true;
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) {
+        const double vv = V[i * 6 + m] * V[j * 6 + m];
+        if (keep)
+          S.pinv[6 * i + j] += vv / ev[m];
+        else
+          S.null[6 * i + j] += vv;
+      }
+  }
+  double Lp = 0.0;
+  for (int i = 0; i < nb; ++i)
+    for (int j = i + 1; j < nb; ++j) {
+      double d2 = 0.0;
+      for (int k = 0; k < 3; ++k) d2 += (S.b[3 * i + k] - S.b[3 * j + k]) * (S.b[3 * i + k] - S.b[3 * j + k]);
+      Lp = std::max(Lp, std::sqrt(d2));
+    }
+  S.Lp = nb < 2 ? a : Lp;
+  const int D = 3 * nb + 6;
+  std::vector<double> P(D * D, 0.0);
+  for (int i = 0; i < nb; ++i)
+    for (int j = 0; j < nb; ++j) {
+      double d[3] = {S.b[3 * i] - S.b[3 * j], S.b[3 * i + 1] - S.b[3 * j + 1], S.b[3 * i + 2] - S.b[3 * j + 2]};
+      double T[9];
+      rpy(d, a, eta, T);
+      for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) P[(3 * i + p) * D + 3 * j + q] = T[3 * p + q];
+    }
+  for (int i = 0; i < nb; ++i) {
+    const double* r = &S.b[3 * i];
+    const double cx[9] = {0, -r[2], r[1], r[2], 0, -r[0], -r[1], r[0], 0};
+    for (int k = 0; k < 3; ++k) {
+      P[(3 * i + k) * D + 3 * nb + k] = -1.0;
+      P[(3 * nb + k) * D + 3 * i + k] = -1.0;
+      for (int c = 0; c < 3; ++c) {
+        // -K: -[x r] = [r x];  -K^T: ([r x])^T
+        P[(3 * i + k) * D + 3 * nb + 3 + c] = cx[3 * k + c];
+        P[(3 * nb + 3 + c) * D + 3 * i + k] = cx[3 * k + c];
+      }
+    }
+  }
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) P[(3 * nb + i) * D + 3 * nb + j] = -S.null[6 * i + j];
+  std::vector<double> inv;
+  if (!invert(D, P, inv)) {
+    err = "singular preconditioner block";
+    return false;
+  }
+  S.precT.assign(D * D, 0.0);
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) S.precT[j * D + i] = inv[i * D + j];
+  return true;
+}
+
+template <typename T>
+int dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  const hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+    return GDC_ENOMEM;
+  }
+  return GDC_OK;
+}
+
+}  // namespace
+}  // namespace gdc
+
+using namespace gdc;
+
+struct gdc_handle {
+  gdc_config cfg{};
+  int N = 0, M = 0;
+  long long nx = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int precision = GDC_FP32;
+  size_t rsize = 4;
+  uint64_t step = 0;
+  GridGeom geom{};
+  int maxdim = 0;
+  int restart = 50, maxit = 200;
+  double tol = 1e-6;
+  int nc[3] = {0, 0, 0};
+  int cell_cap = 0;
+  std::vector<ShapeHost> shapes;
+  std::vector<int> body_shape;
+
+  std::vector<void*> allocs;
+  void* grid[3] = {nullptr, nullptr, nullptr};
+  void* grid_fl = nullptr;
+  void* tw[3] = {nullptr, nullptr, nullptr};
+  BodyTables bt{};
+  double *Y = nullptr, *q = nullptr, *Ym = nullptr, *qm = nullptr, *r = nullptr, *rm = nullptr;
+  double *v = nullptr, *vd = nullptr, *dr = nullptr, *wrfd = nullptr, *calV = nullptr, *dp = nullptr, *nu = nullptr;
+  double *F = nullptr, *fblob = nullptr, *cforce = nullptr, *io = nullptr;
+  int *cell_count = nullptr, *cell_list = nullptr, *flags = nullptr;
+  double *Vb = nullptr, *w = nullptr, *z = nullptr, *xacc = nullptr, *rhs = nullptr, *sol = nullptr;
+  double *hdev = nullptr, *partial = nullptr;
+  double* hhost = nullptr;   // pinned readback
+
+  ~gdc_handle() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (hhost) (void)hipHostFree(hhost);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+
+  template <typename T>
+  int alloc(T** p, size_t count) {
+    GDC_TRY(dalloc(p, count));
+    allocs.push_back((void*)*p);
+    return GDC_OK;
+  }
+};
+
+namespace {
+
+int validate(const gdc_config* c) {
+  auto bad = [](const std::string& m) {
+    set_error(m);
+    return GDC_EINVAL;
+  };
+  if (!c) return bad("cfg is NULL");
+  for (int d = 0; d < 3; ++d) {
+    if (!(c->L[d] > 0.0)) return bad("L must be positive");
+    if (c->n[d] % 2 != 0 || !fft_size_supported(c->n[d]))
+      return bad("grid size must be even, 2^a 3^b and in [8, 512]");
+  }
+  if (!(c->a > 0.0) || c->sigma < 0.0 || c->trunc < 0.0) return bad("a must be > 0, sigma and trunc >= 0");
+  if (!(c->eta > 0.0) || c->kT < 0.0 || !(c->dt > 0.0)) return bad("eta, dt must be > 0 and kT >= 0");
+  if (c->fd_delta < 0.0 || c->gmres_tol < 0.0 || c->gmres_maxit < 0 || c->gmres_restart < 0)
+    return bad("negative solver parameter");
+  if (c->gmres_restart > 60) return bad("gmres_restart must be <= 60");
+  if (c->precision != GDC_FP32 && c->precision != GDC_FP64) return bad("precision must be GDC_FP32 or GDC_FP64");
+  if (c->scheme != GDC_SCHEME_GDC && c->scheme != GDC_SCHEME_EM) return bad("unknown scheme");
+  if (c->divergence != GDC_DIV_FD && c->divergence != GDC_DIV_RFD) return bad("unknown divergence mode");
+  if (c->n_shapes < 1 || !c->shapes) return bad("at least one shape is required");
+  if (c->n_bodies < 1 || !c->body_shape) return bad("at least one body is required");
+  long long M = 0;
+  for (int s = 0; s < c->n_shapes; ++s)
+    if (c->shapes[s].n_blobs < 1 || !c->shapes[s].b) return bad("every shape needs at least one blob");
+  for (int p = 0; p < c->n_bodies; ++p) {
+    if (c->body_shape[p] < 0 || c->body_shape[p] >= c->n_shapes) return bad("body_shape out of range");
+    M += c->shapes[c->body_shape[p]].n_blobs;
+  }
+  if (M > (1LL << 30)) return bad("too many blobs");
+  if (c->forces.steric_k < 0.0 || c->forces.steric_cutoff < 0.0) return bad("steric parameters must be >= 0");
+  return GDC_OK;
+}
+
+template <typename R>
+const Cx<R>* const* tw_of(gdc_handle* h) {
+  return reinterpret_cast<const Cx<R>* const*>(h->tw);
+}
+
+// v = M_FCM lam at blob positions r (all device, FP64 at the ends).
+template <typename R>
+int apply_mobility(gdc_handle* h, const double* r, const double* lam, double* out) {
+  const GridGeom& g = h->geom;
+  R* f = (R*)h->grid[0];
+  GDC_TRY(fill_zero(f, 3 * (size_t)g.G * sizeof(R), h->stream));
+  GDC_TRY(spread<R>(g, r, lam, f, h->M, h->stream));
+  GDC_TRY(stokes_solve<R>(g, tw_of<R>(h), f, (Cx<R>*)h->grid[1], (Cx<R>*)h->grid[2], h->stream));
+  return interp<R>(g, r, f, out, h->M, g.dV, h->stream);
+}
+
+// y = [[M, -K], [-K^T, -Pi]] x at (Y, q, r).
+template <typename R>
+int apply_saddle(gdc_handle* h, const double* Y, const double* q, const double* r, const double* x, double* y) {
+  const long long m3 = 3LL * h->M;
+  GDC_TRY(apply_mobility<R>(h, r, x, y));
+  return saddle_rigid_terms(h->bt, Y, q, r, x, x + m3, y, y + m3, h->stream);
+}
+
+struct GmresResult {
+  int its = 0;
+  double relres = 0.0;
+  bool converged = false;
+};
+
+// Right-preconditioned restarted GMRES (Saad & Schultz) on the saddle system
+// with classical Gram-Schmidt and one reorthogonalisation, zero initial
+// guess.  Solution (x = P^-1 u) written to h->sol.
+template <typename R>
+int gmres(gdc_handle* h, const double* Y, const double* q, const double* r, GmresResult& res) {
+  const long long n = h->nx;
+  const int m = h->restart;
+  hipStream_t s = h->stream;
+  double* hh = h->hhost;
+  // |b|
+  GDC_TRY(multi_dot(h->rhs, n, 1, h->rhs, n, h->partial, DOT_BLOCKS, h->hdev, s));
+  GDC_HIP(hipMemcpyAsync(hh, h->hdev, sizeof(double), hipMemcpyDeviceToHost, s));
+  GDC_HIP(hipStreamSynchronize(s));
+  const double nb = std::sqrt(hh[0]);
+  GDC_TRY(fill_zero(h->xacc, (size_t)((n * 8 + 15) / 16 * 16), s));
+  if (nb == 0.0) {
+    GDC_TRY(fill_zero(h->sol, (size_t)((n * 8 + 15) / 16 * 16), s));
+    res = GmresResult{0, 0.0, true};
+    return GDC_OK;
+  }
+  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  int its = 0;
+  bool first = true;
+  double est = 1.0;
+  bool converged = false;
+  while (true) {
+    double* V0 = h->Vb;
+    if (first) {
+      GDC_TRY(copy_scaled(h->rhs, 1.0, h->w, n, s));
+    } else {
+      // w = b - A P^-1 xacc
+      GDC_TRY(precond_apply(h->bt, q, h->xacc, h->z, h->maxdim, s));
+      GDC_TRY(apply_saddle<R>(h, Y, q, r, h->z, h->w));
+      GDC_TRY(sub_from(h->rhs, h->w, n, s));
+    }
+    first = false;
+    GDC_TRY(multi_dot(h->w, n, 1, h->w, n, h->partial, DOT_BLOCKS, h->hdev + 2 * HCOLS, s));
+    GDC_HIP(hipMemcpyAsync(hh, h->hdev + 2 * HCOLS, sizeof(double), hipMemcpyDeviceToHost, s));
+    GDC_HIP(hipStreamSynchronize(s));
+    const double beta = std::sqrt(hh[0]);
+    est = beta / nb;
+    if (est <= h->tol || its >= h->maxit) {
+      converged = est <= h->tol;
+      break;
+    }
+    GDC_TRY(scale_by_inv_sqrt(h->w, h->hdev + 2 * HCOLS, V0, n, s));
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int kdone = 0;
+    for (int k = 0; k < m; ++k) {
+      double* Vk = h->Vb + n * k;
+      double* Vk1 = h->Vb + n * (k + 1);
+      GDC_TRY(precond_apply(h->bt, q, Vk, h->z, h->maxdim, s));
+      GDC_TRY(apply_saddle<R>(h, Y, q, r, h->z, h->w));
+      double* h1 = h->hdev;
+      double* h2 = h->hdev + HCOLS;
+      double* nr = h->hdev + 2 * HCOLS;
+      GDC_TRY(multi_dot(h->Vb, n, k + 1, h->w, n, h->partial, DOT_BLOCKS, h1, s));
+      GDC_TRY(multi_axpy(h->w, h->Vb, n, k + 1, h1, -1.0, n, s));
+      GDC_TRY(multi_dot(h->Vb, n, k + 1, h->w, n, h->partial, DOT_BLOCKS, h2, s));
+      GDC_TRY(multi_axpy(h->w, h->Vb, n, k + 1, h2, -1.0, n, s));
+      GDC_TRY(multi_dot(h->w, n, 1, h->w, n, h->partial, DOT_BLOCKS, nr, s));
+      GDC_TRY(scale_by_inv_sqrt(h->w, nr, Vk1, n, s));
+      GDC_HIP(hipMemcpyAsync(hh, h->hdev, 3 * HCOLS * sizeof(double), hipMemcpyDeviceToHost, s));
+      GDC_HIP(hipStreamSynchronize(s));
+      for (int j = 0; j <= k; ++j) H[j * m + k] = hh[j] + hh[HCOLS + j];
+      H[(k + 1) * m + k] = std::sqrt(hh[2 * HCOLS]);
+      for (int j = 0; j < k; ++j) {
+        const double t = cs[j] * H[j * m + k] + sn[j] * H[(j + 1) * m + k];
+        H[(j + 1) * m + k] = -sn[j] * H[j * m + k] + cs[j] * H[(j + 1) * m + k];
+        H[j * m + k] = t;
+      }
+      const double den = std::hypot(H[k * m + k], H[(k + 1) * m + k]);
+      cs[k] = den > 0 ? H[k * m + k] / den : 1.0;
+      sn[k] = den > 0 ? H[(k + 1) * m + k] / den : 0.0;
+      H[k * m + k] = den;
+      H[(k + 1) * m + k] = 0.0;
+      g[k + 1] = -sn[k] * g[k];
+      g[k] = cs[k] * g[k];
+      ++its;
+      kdone = k + 1;
+      est = std::fabs(g[k + 1]) / nb;
+      if (est <= h->tol || its >= h->maxit || H[k * m + k] == 0.0) break;
+    }
+    for (int i = kdone - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int j = i + 1; j < kdone; ++j) t -= H[i * m + j] * y[j];
+      y[i] = H[i * m + i] != 0.0 ? t / H[i * m + i] : 0.0;
+    }
+    // y goes through the pinned buffer: an async copy must not read pageable memory
+    std::copy(y.begin(), y.begin() + kdone, hh + 3 * HCOLS);
+    GDC_HIP(hipMemcpyAsync(h->hdev + 3 * HCOLS, hh + 3 * HCOLS, kdone * sizeof(double), hipMemcpyHostToDevice, s));
+    GDC_TRY(multi_axpy(h->xacc, h->Vb, n, kdone, h->hdev + 3 * HCOLS, 1.0, n, s));
+    if (est <= h->tol) {
+      converged = true;
+      break;
+    }
+    if (its >= h->maxit) break;
+  }
+  GDC_TRY(precond_apply(h->bt, q, h->xacc, h->sol, h->maxdim, s));
+  res.its = its;
+  res.relres = est;
+  res.converged = converged;
+  return GDC_OK;
+}
+
+// Blob forces and body forces/torques at (Y, q, r) into h->F.
+int forces_at(gdc_handle* h, const double* Y, const double* r) {
+  const gdc_forces& f = h->cfg.forces;
+  const double* fb = nullptr;
+  if (f.steric_k > 0.0 && f.steric_cutoff > 0.0) {
+    GDC_TRY(steric_forces(h->bt, h->geom, r, f.steric_k, f.steric_cutoff, h->cell_count, h->cell_list,
+                          h->cell_cap, h->nc, h->flags, h->fblob, h->stream));
+    fb = h->fblob;
+  }
+  return body_forces(h->bt, Y, r, fb, h->cforce, h->F, h->stream);
+}
+
+// Random velocity field of step `step` into h->grid_fl.
+template <typename R>
+int make_fluct(gdc_handle* h, uint64_t step) {
+  const GridGeom& g = h->geom;
+  if (h->cfg.kT == 0.0) return fill_zero(h->grid_fl, 3 * (size_t)g.G * sizeof(R), h->stream);
+  return fluct_field<R>(g, tw_of<R>(h), (R*)h->grid_fl, (Cx<R>*)h->grid[1], (Cx<R>*)h->grid[2], h->cfg.seed,
+                        step, h->cfg.kT, h->cfg.dt, h->stream);
+}
+
+// Steps 2-3 at the state in (h->Y, h->q): calV, d_p and nu on the device.
+template <typename R>
+int predictor_dev(gdc_handle* h, uint64_t step) {
+  hipStream_t s = h->stream;
+  const int mode = h->cfg.divergence == GDC_DIV_RFD ? 1 : 0;
+  GDC_TRY(blob_positions(h->bt, h->Y, h->q, h->r, s));
+  GDC_TRY(fd_displacements(h->bt, h->q, h->cfg.fd_delta, mode, h->cfg.seed, step, h->dr, h->wrfd, s));
+  GDC_TRY(interp_fd<R>(h->geom, h->r, h->dr, mode == 1 ? 1 : 6, (const R*)h->grid_fl, h->v, h->vd, h->M, s));
+  GDC_TRY(body_lsq_div(h->bt, h->q, h->v, h->vd, h->wrfd, h->cfg.fd_delta, mode, h->calV, h->dp, s));
+  return nu_reduce(h->dp, h->N, 0.5 * h->cfg.dt, h->nu, s);
+}
+
+template <typename R>
+int one_step(gdc_handle* h, GmresResult& gr, double& nu_out) {
+  hipStream_t s = h->stream;
+  const uint64_t step = h->step;
+  GDC_TRY(make_fluct<R>(h, step));
+  const double* Ym = h->Y;
+  const double* qm = h->q;
+  if (h->cfg.scheme == GDC_SCHEME_GDC) {
+    GDC_TRY(predictor_dev<R>(h, step));
+    GDC_TRY(midpoint(h->bt, h->Y, h->q, h->calV, 0.5 * h->cfg.dt, h->Ym, h->qm, s));
+    Ym = h->Ym;
+    qm = h->qm;
+  }
+  GDC_TRY(blob_positions(h->bt, Ym, qm, h->rm, s));
+  GDC_TRY(forces_at(h, Ym, h->rm));
+  GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_fl, h->v, h->M, h->geom.dV, s));
+  GDC_TRY(rhs_build(h->bt, qm, Ym, h->rm, h->v, h->F, h->cfg.forces.shear_rate, h->geom.L[1], h->rhs, s));
+  GDC_TRY(gmres<R>(h, Ym, qm, h->rm, gr));
+  const bool gdc_scheme = h->cfg.scheme == GDC_SCHEME_GDC;
+  GDC_TRY(update(h->bt, h->Y, h->q, h->sol + 3LL * h->M, gdc_scheme ? h->nu : nullptr, h->cfg.dt, s));
+  if (gdc_scheme) {
+    GDC_HIP(hipMemcpyAsync(h->hhost + 4 * HCOLS, h->nu, sizeof(double), hipMemcpyDeviceToHost, s));
+    GDC_HIP(hipStreamSynchronize(s));
+    nu_out = h->hhost[4 * HCOLS];
+  } else {
+    nu_out = 1.0;
+  }
+  h->step += 1;
+  return GDC_OK;
+}
+
+int copy_in(gdc_handle* h, double* dst, const double* src, size_t count, int memspace) {
+  const hipMemcpyKind kind = memspace == GDC_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  GDC_HIP(hipMemcpyAsync(dst, src, count * sizeof(double), kind, h->stream));
+  return GDC_OK;
+}
+
+int copy_out(gdc_handle* h, double* dst, const double* src, size_t count, int memspace) {
+  const hipMemcpyKind kind = memspace == GDC_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  GDC_HIP(hipMemcpyAsync(dst, src, count * sizeof(double), kind, h->stream));
+  return GDC_OK;
+}
+
+int check_quaternions(const gdc_handle* h, const double* Y, const double* q, int memspace) {
+  if (memspace != GDC_HOST) return GDC_OK;
+  for (long long k = 0; k < 3LL * h->N; ++k)
+    if (!std::isfinite(Y[k])) {
+      set_error("non-finite position of body " + std::to_string(k / 3));
+      return GDC_EINVAL;
+    }
+  for (int p = 0; p < h->N; ++p) {
+    const double* qp = q + 4LL * p;
+    const double nrm = std::sqrt(qp[0] * qp[0] + qp[1] * qp[1] + qp[2] * qp[2] + qp[3] * qp[3]);
+    if (!(std::fabs(nrm - 1.0) <= 1e-6)) {
+      set_error("quaternion " + std::to_string(p) + " is not of unit norm");
+      return GDC_EINVAL;
+    }
+  }
+  return GDC_OK;
+}
+
+int load_state(gdc_handle* h, const double* Y, const double* q, int memspace) {
+  if (!Y || !q) {
+    set_error("Y and q are required");
+    return GDC_EINVAL;
+  }
+  if (memspace != GDC_HOST && memspace != GDC_DEVICE) {
+    set_error("memspace must be GDC_HOST or GDC_DEVICE");
+    return GDC_EINVAL;
+  }
+  GDC_TRY(check_quaternions(h, Y, q, memspace));
+  GDC_TRY(copy_in(h, h->Y, Y, 3 * (size_t)h->N, memspace));
+  return copy_in(h, h->q, q, 4 * (size_t)h->N, memspace);
+}
+
+int finish(gdc_handle* h) {
+  GDC_HIP(hipStreamSynchronize(h->stream));
+  return GDC_OK;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int d) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    (void)hipSetDevice(d);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+template <typename R>
+int init_grid_tables(gdc_handle* h) {
+  for (int d = 0; d < 3; ++d) {
+    const int n = h->geom.n[d];
+    std::vector<Cx<R>> t(n);
+    for (int k = 0; k < n; ++k) {
+      const long double ang = 2.0L * 3.141592653589793238462643383279503L * (long double)k / (long double)n;
+      t[k] = Cx<R>{(R)std::cos(ang), (R)(-std::sin(ang))};
+    }
+    Cx<R>* dptr = nullptr;
+    GDC_TRY(h->alloc(&dptr, n));
+    GDC_HIP(hipMemcpy(dptr, t.data(), n * sizeof(Cx<R>), hipMemcpyHostToDevice));
+    h->tw[d] = dptr;
+  }
+  // The three work fields are one allocation, so grid[1] and grid[2] together
+  // also hold a 3 x G FP64 field.
+  R* base = nullptr;
+  GDC_TRY(h->alloc(&base, 9 * (size_t)h->geom.G));
+  for (int k = 0; k < 3; ++k) h->grid[k] = base + 3 * (size_t)h->geom.G * k;
+  R* p = nullptr;
+  GDC_TRY(h->alloc(&p, 3 * (size_t)h->geom.G));
+  h->grid_fl = p;
+  return GDC_OK;
+}
+
+int init_impl(const gdc_config* cfg, gdc_handle* h) {
+  GDC_TRY(validate(cfg));
+  h->cfg = *cfg;
+  h->cfg.shapes = nullptr;
+  h->cfg.body_shape = nullptr;
+  gdc_config& c = h->cfg;
+  if (c.sigma == 0.0) c.sigma = c.a / std::sqrt(3.14159265358979323846);
+  if (c.trunc == 0.0) c.trunc = 3.0 * c.a;
+  if (c.fd_delta == 0.0) c.fd_delta = 1e-6;
+  if (c.gmres_tol == 0.0) c.gmres_tol = 1e-6;
+  if (c.gmres_maxit == 0) c.gmres_maxit = 200;
+  if (c.gmres_restart == 0) c.gmres_restart = 50;
+  h->tol = c.gmres_tol;
+  h->maxit = c.gmres_maxit;
+  h->restart = c.gmres_restart;
+  h->precision = c.precision;
+  h->rsize = c.precision == GDC_FP64 ? 8 : 4;
+  h->device = c.device;
+
+  GridGeom& g = h->geom;
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = c.n[d];
+    g.L[d] = c.L[d];
+    g.dx[d] = c.L[d] / c.n[d];
+    g.inv_dx[d] = 1.0 / g.dx[d];
+    if (!(2.0 * c.trunc < c.L[d])) {
+      set_error("the envelope cutoff must be below half the box length");
+      return GDC_EINVAL;
+    }
+    g.P[d] = (int)std::floor(2.0 * c.trunc / g.dx[d]) + 1;
+  }
+  g.n2h = g.n[2] / 2;
+  g.G = (long long)g.n[0] * g.n[1] * g.n[2];
+  g.dV = g.dx[0] * g.dx[1] * g.dx[2];
+  g.eta = c.eta;
+  g.sigma = c.sigma;
+  g.rc = c.trunc;
+  g.rc2 = c.trunc * c.trunc;
+  g.inv2s2 = 1.0 / (2.0 * c.sigma * c.sigma);
+  g.wnorm = std::pow(2.0 * 3.14159265358979323846 * c.sigma * c.sigma, -1.5);
+
+  // shapes and bodies
+  h->N = cfg->n_bodies;
+  h->shapes.resize(cfg->n_shapes);
+  std::vector<double> shape_b;
+  std::vector<int> shape_boff(cfg->n_shapes + 1, 0);
+  std::vector<double> pinv(36 * cfg->n_shapes), nul(36 * cfg->n_shapes), Lp(cfg->n_shapes);
+  std::vector<double> precT;
+  std::vector<long long> prec_off(cfg->n_shapes);
+  for (int s = 0; s < cfg->n_shapes; ++s) {
+    ShapeHost& S = h->shapes[s];
+    S.nb = cfg->shapes[s].n_blobs;
+    S.b.assign(cfg->shapes[s].b, cfg->shapes[s].b + 3 * S.nb);
+    std::string err;
+    if (!build_shape(S, c.a, c.eta, err)) {
+      set_error("shape " + std::to_string(s) + ": " + err);
+      return GDC_EINVAL;
+    }
+    shape_boff[s + 1] = shape_boff[s] + S.nb;
+    shape_b.insert(shape_b.end(), S.b.begin(), S.b.end());
+    std::memcpy(&pinv[36 * s], S.pinv, sizeof(S.pinv));
+    std::memcpy(&nul[36 * s], S.null, sizeof(S.null));
+    Lp[s] = S.Lp;
+    prec_off[s] = (long long)precT.size();
+    precT.insert(precT.end(), S.precT.begin(), S.precT.end());
+    h->maxdim = std::max(h->maxdim, 3 * S.nb + 6);
+  }
+  h->body_shape.assign(cfg->body_shape, cfg->body_shape + h->N);
+  std::vector<int> body_off(h->N + 1, 0);
+  for (int p = 0; p < h->N; ++p) body_off[p + 1] = body_off[p] + h->shapes[h->body_shape[p]].nb;
+  h->M = body_off[h->N];
+  std::vector<int> blob_body(h->M), blob_local(h->M);
+  for (int p = 0; p < h->N; ++p)
+    for (int k = 0; k < body_off[p + 1] - body_off[p]; ++k) {
+      blob_body[body_off[p] + k] = p;
+      blob_local[body_off[p] + k] = k;
+    }
+  h->nx = 3LL * h->M + 6LL * h->N;
+
+  // device
+  int ndev = 0;
+  GDC_HIP(hipGetDeviceCount(&ndev));
+  if (c.device < 0 || c.device >= ndev) {
+    set_error("device ordinal out of range");
+    return GDC_EINVAL;
+  }
+  GDC_HIP(hipSetDevice(c.device));
+  if (c.stream) {
+    h->stream = (hipStream_t)c.stream;
+  } else {
+    GDC_HIP(hipStreamCreate(&h->stream));
+    h->own_stream = true;
+  }
+
+  auto upload = [&](auto** dst, const auto& vec) -> int {
+    using T = typename std::remove_reference<decltype(vec)>::type::value_type;
+    T* p = nullptr;
+    GDC_TRY(h->alloc(&p, vec.size()));
+    GDC_HIP(hipMemcpy(p, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice));
+    *dst = p;
+    return GDC_OK;
+  };
+  BodyTables& B = h->bt;
+  B.N = h->N;
+  B.M = h->M;
+  B.n_shapes = cfg->n_shapes;
+  int *d_bs, *d_boff, *d_bb, *d_bl, *d_sboff;
+  double *d_sb, *d_pinv, *d_null, *d_Lp, *d_prec;
+  long long* d_poff;
+  GDC_TRY(upload(&d_bs, h->body_shape));
+  GDC_TRY(upload(&d_boff, body_off));
+  GDC_TRY(upload(&d_bb, blob_body));
+  GDC_TRY(upload(&d_bl, blob_local));
+  GDC_TRY(upload(&d_sb, shape_b));
+  GDC_TRY(upload(&d_sboff, shape_boff));
+  GDC_TRY(upload(&d_pinv, pinv));
+  GDC_TRY(upload(&d_null, nul));
+  GDC_TRY(upload(&d_Lp, Lp));
+  GDC_TRY(upload(&d_prec, precT));
+  GDC_TRY(upload(&d_poff, prec_off));
+  B.body_shape = d_bs;
+  B.body_off = d_boff;
+  B.blob_body = d_bb;
+  B.blob_local = d_bl;
+  B.shape_b = d_sb;
+  B.shape_boff = d_sboff;
+  B.shape_pinv = d_pinv;
+  B.shape_null = d_null;
+  B.shape_Lp = d_Lp;
+  B.shape_precT = d_prec;
+  B.shape_prec_off = d_poff;
+
+  const size_t N = h->N, M = h->M;
+  GDC_TRY(h->alloc(&h->Y, 3 * N));
+  GDC_TRY(h->alloc(&h->q, 4 * N));
+  GDC_TRY(h->alloc(&h->Ym, 3 * N));
+  GDC_TRY(h->alloc(&h->qm, 4 * N));
+  GDC_TRY(h->alloc(&h->r, 3 * M));
+  GDC_TRY(h->alloc(&h->rm, 3 * M));
+  GDC_TRY(h->alloc(&h->v, 3 * M));
+  GDC_TRY(h->alloc(&h->vd, 18 * M));
+  GDC_TRY(h->alloc(&h->dr, 18 * M));
+  GDC_TRY(h->alloc(&h->wrfd, 6 * N));
+  GDC_TRY(h->alloc(&h->calV, 6 * N));
+  GDC_TRY(h->alloc(&h->dp, N));
+  GDC_TRY(h->alloc(&h->nu, 2));
+  GDC_TRY(h->alloc(&h->F, 6 * N));
+  GDC_TRY(h->alloc(&h->fblob, 3 * M));
+  GDC_TRY(h->alloc(&h->flags, 4));
+  GDC_TRY(h->alloc(&h->io, std::max(6 * N, 3 * M)));
+  std::vector<double> cf(c.forces.const_force, c.forces.const_force + 6);
+  GDC_TRY(upload(&h->cforce, cf));
+  GDC_HIP(hipMemset(h->flags, 0, 4 * sizeof(int)));
+
+  const gdc_forces& f = c.forces;
+  if (f.steric_k > 0.0 && f.steric_cutoff > 0.0) {
+    long long ncell = 1;
+    for (int d = 0; d < 3; ++d) {
+      h->nc[d] = (int)std::floor(c.L[d] / f.steric_cutoff);
+      if (h->nc[d] < 3) {
+        set_error("the box must span at least three pair-force cells per axis");
+        return GDC_EINVAL;
+      }
+      ncell *= h->nc[d];
+    }
+    h->cell_cap = 32;
+    GDC_TRY(h->alloc(&h->cell_count, (size_t)((ncell * 4 + 15) / 16 * 4)));
+    GDC_TRY(h->alloc(&h->cell_list, (size_t)(ncell * h->cell_cap)));
+  }
+
+  const size_t nx = (size_t)h->nx;
+  GDC_TRY(h->alloc(&h->Vb, (size_t)(h->restart + 1) * nx));
+  GDC_TRY(h->alloc(&h->w, nx));
+  GDC_TRY(h->alloc(&h->z, nx));
+  GDC_TRY(h->alloc(&h->xacc, nx + 2));
+  GDC_TRY(h->alloc(&h->rhs, nx));
+  GDC_TRY(h->alloc(&h->sol, nx + 2));
+  GDC_TRY(h->alloc(&h->hdev, 5 * HCOLS));
+  GDC_TRY(h->alloc(&h->partial, (size_t)DOT_BLOCKS * HCOLS));
+  GDC_HIP(hipHostMalloc((void**)&h->hhost, 5 * HCOLS * sizeof(double), hipHostMallocDefault));
+
+  if (h->precision == GDC_FP64) {
+    GDC_TRY(init_grid_tables<double>(h));
+  } else {
+    GDC_TRY(init_grid_tables<float>(h));
+  }
+  GDC_HIP(hipDeviceSynchronize());
+  return GDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gdc_last_error(void) { return gdc::g_last_error.c_str(); }
+
+int gdc_init(const gdc_config* cfg, gdc_handle** out) {
+  if (!out) {
+    set_error("out is NULL");
+    return GDC_EINVAL;
+  }
+  *out = nullptr;
+  gdc_handle* h = new (std::nothrow) gdc_handle();
+  if (!h) {
+    set_error("host allocation failed");
+    return GDC_ENOMEM;
+  }
+  int prev = -1;
+  if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+  const int rc = init_impl(cfg, h);
+  if (rc != GDC_OK) {
+    delete h;
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return rc;
+  }
+  if (prev >= 0) (void)hipSetDevice(prev);
+  *out = h;
+  return GDC_OK;
+}
+
+void gdc_free(gdc_handle* h) {
+  if (!h) return;
+  DeviceGuard dg(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+}
+
+int gdc_mobility_apply(gdc_handle* h, int mode, const double* Y, const double* q, const double* in, double* out,
+                       int memspace) {
+  if (!h || !in || !out) {
+    set_error("handle, in and out are required");
+    return GDC_EINVAL;
+  }
+  if (mode != GDC_BLOB && mode != GDC_BODY) {
+    set_error("mode must be GDC_BLOB or GDC_BODY");
+    return GDC_EINVAL;
+  }
+  DeviceGuard dg(h->device);
+  hipStream_t s = h->stream;
+  GDC_TRY(load_state(h, Y, q, memspace));
+  GDC_TRY(blob_positions(h->bt, h->Y, h->q, h->r, s));
+  GDC_TRY(fill_zero(h->flags, 16, s));
+  GmresResult gr;
+  gr.converged = true;
+  if (mode == GDC_BLOB) {
+    GDC_TRY(copy_in(h, h->io, in, 3 * (size_t)h->M, memspace));
+    if (h->precision == GDC_FP64) {
+      GDC_TRY(apply_mobility<double>(h, h->r, h->io, h->v));
+    } else {
+      GDC_TRY(apply_mobility<float>(h, h->r, h->io, h->v));
+    }
+    GDC_TRY(check_finite(h->v, 3LL * h->M, h->flags + 1, s));
+    GDC_TRY(copy_out(h, out, h->v, 3 * (size_t)h->M, memspace));
+  } else {
+    GDC_TRY(copy_in(h, h->io, in, 6 * (size_t)h->N, memspace));
+    GDC_TRY(rhs_build(h->bt, h->q, h->Y, h->r, nullptr, h->io, 0.0, h->geom.L[1], h->rhs, s));
+    if (h->precision == GDC_FP64) {
+      GDC_TRY(gmres<double>(h, h->Y, h->q, h->r, gr));
+    } else {
+      GDC_TRY(gmres<float>(h, h->Y, h->q, h->r, gr));
+    }
+    GDC_TRY(check_finite(h->sol + 3LL * h->M, 6LL * h->N, h->flags + 1, s));
+    GDC_TRY(copy_out(h, out, h->sol + 3LL * h->M, 6 * (size_t)h->N, memspace));
+  }
+  GDC_HIP(hipMemcpyAsync(h->hhost, h->flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+  GDC_TRY(finish(h));
+  const int* fl = reinterpret_cast<const int*>(h->hhost);
+  if (fl[1]) {
+    set_error("non-finite mobility result");
+    return GDC_ENUMERIC;
+  }
+  if (!gr.converged) {
+    set_error("GMRES did not reach the tolerance (relative residual " + std::to_string(gr.relres) + ")");
+    return GDC_ENOTCONV;
+  }
+  return GDC_OK;
+}
+
+int gdc_step(gdc_handle* h, int n_steps, double* Y, double* q, int memspace, gdc_stats* st) {
+  if (!h || n_steps < 0) {
+    set_error("a handle and n_steps >= 0 are required");
+    return GDC_EINVAL;
+  }
+  DeviceGuard dg(h->device);
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = h->stream;
+  GDC_TRY(load_state(h, Y, q, memspace));
+  GDC_TRY(fill_zero(h->flags, 16, s));
+  GmresResult gr;
+  double nu = 1.0;
+  int nonpos = 0;
+  bool notconv = false;
+  for (int k = 0; k < n_steps; ++k) {
+    if (h->precision == GDC_FP64) {
+      GDC_TRY(one_step<double>(h, gr, nu));
+    } else {
+      GDC_TRY(one_step<float>(h, gr, nu));
+    }
+    if (!gr.converged) notconv = true;
+    if (!(nu > 0.0)) ++nonpos;
+  }
+  GDC_TRY(check_finite(h->Y, 3LL * h->N, h->flags + 1, s));
+  GDC_TRY(check_finite(h->q, 4LL * h->N, h->flags + 1, s));
+  GDC_TRY(copy_out(h, Y, h->Y, 3 * (size_t)h->N, memspace));
+  GDC_TRY(copy_out(h, q, h->q, 4 * (size_t)h->N, memspace));
+  GDC_HIP(hipMemcpyAsync(h->hhost, h->flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+  GDC_TRY(finish(h));
+  const int* fl = reinterpret_cast<const int*>(h->hhost);
+  const bool overflow = fl[0] != 0, nonfinite = fl[1] != 0;
+  if (st) {
+    st->steps_done = n_steps;
+    st->gmres_iterations = gr.its;
+    st->gmres_relres = gr.relres;
+    st->nu = nu;
+    st->nu_nonpositive = nonpos;
+    st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (overflow) {
+    set_error("pair-force cell list overflow");
+    return GDC_ENUMERIC;
+  }
+  if (nonfinite) {
+    set_error("non-finite positions or orientations");
+    return GDC_ENUMERIC;
+  }
+  if (notconv) {
+    set_error("GMRES did not reach the tolerance in at least one step");
+    return GDC_ENOTCONV;
+  }
+  return GDC_OK;
+}
+
+int gdc_get_step(const gdc_handle* h, uint64_t* step) {
+  if (!h || !step) {
+    set_error("handle and step are required");
+    return GDC_EINVAL;
+  }
+  *step = h->step;
+  return GDC_OK;
+}
+
+int gdc_set_step(gdc_handle* h, uint64_t step) {
+  if (!h) {
+    set_error("handle is required");
+    return GDC_EINVAL;
+  }
+  h->step = step;
+  return GDC_OK;
+}
+
+int gdc_fluct_velocity(gdc_handle* h, uint64_t step, double* u, int memspace) {
+  if (!h || !u) {
+    set_error("handle and output are required");
+    return GDC_EINVAL;
+  }
+  DeviceGuard dg(h->device);
+  const size_t n = 3 * (size_t)h->geom.G;
+  if (h->precision == GDC_FP64) {
+    GDC_TRY(make_fluct<double>(h, step));
+    GDC_TRY(copy_out(h, u, (const double*)h->grid_fl, n, memspace));
+  } else {
+    GDC_TRY(make_fluct<float>(h, step));
+    // widen into the (free) first grid buffer pair, then copy out
+    double* tmp = (double*)h->grid[1];
+    GDC_TRY(widen((const float*)h->grid_fl, tmp, (long long)n, h->stream));
+    GDC_TRY(copy_out(h, u, tmp, n, memspace));
+  }
+  return finish(h);
+}
+
+int gdc_predictor(gdc_handle* h, const double* Y, const double* q, uint64_t step, double* calV, double* d,
+                  int memspace) {
+  if (!h || !calV || !d) {
+    set_error("handle and outputs are required");
+    return GDC_EINVAL;
+  }
+  DeviceGuard dg(h->device);
+  GDC_TRY(load_state(h, Y, q, memspace));
+  if (h->precision == GDC_FP64) {
+    GDC_TRY(make_fluct<double>(h, step));
+    GDC_TRY(predictor_dev<double>(h, step));
+  } else {
+    GDC_TRY(make_fluct<float>(h, step));
+    GDC_TRY(predictor_dev<float>(h, step));
+  }
+  GDC_TRY(copy_out(h, calV, h->calV, 6 * (size_t)h->N, memspace));
+  GDC_TRY(copy_out(h, d, h->dp, (size_t)h->N, memspace));
+  return finish(h);
+}
+
+int gdc_philox_normals(gdc_handle* h, uint64_t seed, uint32_t c1, uint64_t step, uint32_t c0_begin, int count,
+                       double* out) {
+  if (!h || !out || count < 0) {
+    set_error("handle, output and count >= 0 are required");
+    return GDC_EINVAL;
+  }
+  if (count == 0) return GDC_OK;
+  DeviceGuard dg(h->device);
+  double* d = nullptr;
+  GDC_TRY(dalloc(&d, 4 * (size_t)count));
+  int rc = philox_normals_dev(seed, c1, step, c0_begin, count, d, h->stream);
+  if (rc == GDC_OK) {
+    const hipError_t e1 = hipMemcpyAsync(out, d, 4 * (size_t)count * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    const hipError_t e2 = hipStreamSynchronize(h->stream);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+      set_error("copy of the normals failed");
+      rc = GDC_EDEVICE;
+    }
+  }
+  (void)hipFree(d);
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,540 @@
+// Per-body kernels of the gDC step and of the rigid saddle-point operator
+// (Sec. 2.2, Sec. 3), FP64 throughout.
+//
+// Body-frame tables are built once per shape on the host: (K^T K)^+, the
+// projector onto null(K) (spin of a straight rod, rotation of a one-blob
+// body), and the inverse of the block preconditioner.  K, M's RPY self block
+// and the least-squares operator are covariant under rotation, so in the lab
+// frame a body only needs R(q): (K^T K)^+_lab = Q^T (K^T K)^+_body Q with
+// Q = diag(R^T, R^T), and likewise for the other tables.
+
+#include "gdc_internal.h"
+#include "noise_dev.h"
+
+namespace gdc {
+namespace {
+
+constexpr int NT = 256;
+
+inline unsigned nblk(long long n, int nt = NT) { return (unsigned)((n + nt - 1) / nt); }
+
+__device__ __forceinline__ void load3(const double* p, double* x) {
+  x[0] = p[0];
+  x[1] = p[1];
+  x[2] = p[2];
+}
+
+// y = Q^T A Q x for a body-frame 6x6 A (row-major), Q = diag(R^T, R^T).
+__device__ void rotate_6x6(const double* A, const double* R, const double* x, double* y) {
+  double xb[6], yb[6];
+  matTvec3(R, x, xb);
+  matTvec3(R, x + 3, xb + 3);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) s += A[6 * i + j] * xb[j];
+    yb[i] = s;
+  }
+  matvec3(R, yb, y);
+  matvec3(R, yb + 3, y + 3);
+}
+
+// ------------------------------------------------------------ geometry
+
+__global__ void k_blob_positions(BodyTables B, const double* __restrict__ Y, const double* __restrict__ q,
+                                 double* __restrict__ r) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B.M) return;
+  const int p = B.blob_body[i], s = B.body_shape[p];
+  double R[9], b[3], x[3];
+  rotmat(q + 4LL * p, R);
+  load3(B.shape_b + 3LL * (B.shape_boff[s] + B.blob_local[i]), b);
+  matvec3(R, b, x);
+  r[3LL * i] = Y[3LL * p] + x[0];
+  r[3LL * i + 1] = Y[3LL * p + 1] + x[1];
+  r[3LL * i + 2] = Y[3LL * p + 2] + x[2];
+}
+
+// ------------------------------------------------------------ saddle operator terms
+// out_lam_i -= U_p + Omega_p x (r_i - Y_p);  out_V_p = -K_p^T lam - Pi_p V_p.
+__global__ void k_saddle_rigid(BodyTables B, const double* __restrict__ Y, const double* __restrict__ q,
+                               const double* __restrict__ r, const double* __restrict__ lam,
+                               const double* __restrict__ V, double* __restrict__ out_lam,
+                               double* __restrict__ out_V) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= B.N) return;
+  const int s = B.body_shape[p];
+  double Vp[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) Vp[k] = V[6LL * p + k];
+  double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+  for (int i = B.body_off[p]; i < B.body_off[p + 1]; ++i) {
+    double rel[3] = {r[3LL * i] - Y[3LL * p], r[3LL * i + 1] - Y[3LL * p + 1], r[3LL * i + 2] - Y[3LL * p + 2]};
+    double w[3], l[3], t[3];
+    cross3(Vp + 3, rel, w);
+    out_lam[3LL * i] -= Vp[0] + w[0];
+    out_lam[3LL * i + 1] -= Vp[1] + w[1];
+    out_lam[3LL * i + 2] -= Vp[2] + w[2];
+    load3(lam + 3LL * i, l);
+    cross3(rel, l, t);
+    F[0] += l[0]; F[1] += l[1]; F[2] += l[2];
+    T[0] += t[0]; T[1] += t[1]; T[2] += t[2];
+  }
+  double R[9], pv[6];
+  rotmat(q + 4LL * p, R);
+  rotate_6x6(B.shape_null + 36LL * s, R, Vp, pv);
+  out_V[6LL * p] = -F[0] - pv[0];
+  out_V[6LL * p + 1] = -F[1] - pv[1];
+  out_V[6LL * p + 2] = -F[2] - pv[2];
+  out_V[6LL * p + 3] = -T[0] - pv[3];
+  out_V[6LL * p + 4] = -T[1] - pv[4];
+  out_V[6LL * p + 5] = -T[2] - pv[5];
+}
+
+// ------------------------------------------------------------ block preconditioner
+// One wavefront per body: gather (lambda_i, V_p), rotate to the body frame,
+// multiply by the shape's dense inverse (stored transposed, so lanes read
+// consecutive entries), rotate back.
+__global__ __launch_bounds__(64) void k_precond(BodyTables B, const double* __restrict__ q,
+                                                const double* __restrict__ x, double* __restrict__ y) {
+  extern __shared__ double sh[];
+  const int p = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int s = B.body_shape[p];
+  const int off = B.body_off[p], nb = B.body_off[p + 1] - off;
+  const int D = 3 * nb + 6;
+  double* xb = sh;
+  double* yb = sh + D;
+  double R[9];
+  rotmat(q + 4LL * p, R);
+  const long long Mx3 = 3LL * B.M;
+  for (int k = lane; k < nb + 2; k += 64) {
+    const double* src = k < nb ? x + 3LL * (off + k) : x + Mx3 + 6LL * p + 3 * (k - nb);
+    double v[3], w[3];
+    load3(src, v);
+    matTvec3(R, v, w);
+    xb[3 * k] = w[0];
+    xb[3 * k + 1] = w[1];
+    xb[3 * k + 2] = w[2];
+  }
+  __syncthreads();
+  const double* AT = B.shape_precT + B.shape_prec_off[s];
+  for (int i = lane; i < D; i += 64) {
+    double acc = 0.0;
+    for (int j = 0; j < D; ++j) acc += AT[(long long)j * D + i] * xb[j];
+    yb[i] = acc;
+  }
+  __syncthreads();
+  for (int k = lane; k < nb + 2; k += 64) {
+    double* dst = k < nb ? y + 3LL * (off + k) : y + Mx3 + 6LL * p + 3 * (k - nb);
+    double v[3] = {yb[3 * k], yb[3 * k + 1], yb[3 * k + 2]}, w[3];
+    matvec3(R, v, w);
+    dst[0] = w[0];
+    dst[1] = w[1];
+    dst[2] = w[2];
+  }
+}
+
+// ------------------------------------------------------------ step 3 perturbations
+// mode 0 (finite differences, eq. FD): six displacements per blob,
+//   k = 0..2: delta L_p e_k (translation), k = 3..5: (R(exp(delta e_{k-3}) . q) - R(q)) b_i.
+// mode 1 (random finite differences, eq. rfd_div): one displacement
+//   delta L_p W_U + (R(exp(delta W_Omega) . q) - R(q)) b_i with W ~ N(0,1)^6 from
+//   Philox (stage 1, c0 = body, calls 0 and 1, first six normals).
+__global__ void k_fd_displacements(BodyTables B, const double* __restrict__ q, double delta, int mode,
+                                   uint64_t seed, uint64_t step, double* __restrict__ dr,
+                                   double* __restrict__ wrfd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B.M) return;
+  const int p = B.blob_body[i], s = B.body_shape[p];
+  const double Lp = B.shape_Lp[s];
+  double b[3], R[9];
+  load3(B.shape_b + 3LL * (B.shape_boff[s] + B.blob_local[i]), b);
+  const double* qp = q + 4LL * p;
+  rotmat(qp, R);
+  if (mode == 0) {
+    double* o = dr + 18LL * i;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      o[3 * k] = k == 0 ? delta * Lp : 0.0;
+      o[3 * k + 1] = k == 1 ? delta * Lp : 0.0;
+      o[3 * k + 2] = k == 2 ? delta * Lp : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double u[3] = {0, 0, 0}, e[4], q2[4], R2[9], D[9];
+      u[a] = delta;
+      qexp(u, e);
+      qmul(e, qp, q2);
+      rotmat(q2, R2);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) D[k] = R2[k] - R[k];
+      double x[3];
+      matvec3(D, b, x);
+      o[9 + 3 * a] = x[0];
+      o[9 + 3 * a + 1] = x[1];
+      o[9 + 3 * a + 2] = x[2];
+    }
+  } else {
+    double z[8];
+    four_normals(seed, (uint32_t)p, 16u, step, z);
+    four_normals(seed, (uint32_t)p, 17u, step, z + 4);
+    double u[3] = {delta * z[3], delta * z[4], delta * z[5]}, e[4], q2[4], R2[9], D[9], x[3];
+    qexp(u, e);
+    qmul(e, qp, q2);
+    rotmat(q2, R2);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) D[k] = R2[k] - R[k];
+    matvec3(D, b, x);
+    dr[3LL * i] = delta * Lp * z[0] + x[0];
+    dr[3LL * i + 1] = delta * Lp * z[1] + x[1];
+    dr[3LL * i + 2] = delta * Lp * z[2] + x[2];
+    if (B.blob_local[i] == 0) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) wrfd[6LL * p + k] = z[k];
+    }
+  }
+}
+
+// calV = Q^T (K^T K)^+_body Q K^T v with lab-frame offsets R b_i (eq. sol_unconst).
+__device__ void lsq_body(const BodyTables& B, int p, int s, const double* R, const double* v,
+                         long long vstride, const double* vadd, long long astride, double* out) {
+  double F[6] = {0, 0, 0, 0, 0, 0};
+  const int off = B.body_off[p], nb = B.body_off[p + 1] - off;
+  for (int k = 0; k < nb; ++k) {
+    double b[3], rel[3], w[3], t[3];
+    load3(B.shape_b + 3LL * (B.shape_boff[s] + k), b);
+    matvec3(R, b, rel);
+    const double* vi = v + vstride * (off + k);
+    w[0] = vi[0];
+    w[1] = vi[1];
+    w[2] = vi[2];
+    if (vadd) {
+      const double* ai = vadd + astride * (off + k);
+      w[0] += ai[0];
+      w[1] += ai[1];
+      w[2] += ai[2];
+    }
+    cross3(rel, w, t);
+    F[0] += w[0]; F[1] += w[1]; F[2] += w[2];
+    F[3] += t[0]; F[4] += t[1]; F[5] += t[2];
+  }
+  rotate_6x6(B.shape_pinv + 36LL * s, R, F, out);
+}
+
+// Per body: calV_p and d_p (eq. FD or the term inside the expectation of
+// eq. rfd_div), so that nu = 1 + dt/2 sum_p d_p.
+__global__ void k_body_lsq_div(BodyTables B, const double* __restrict__ q, const double* __restrict__ v,
+                               const double* __restrict__ vd, const double* __restrict__ wrfd,
+                               double delta, int mode, double* __restrict__ calV, double* __restrict__ d) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= B.N) return;
+  const int s = B.body_shape[p];
+  const double Lp = B.shape_Lp[s];
+  const double* qp = q + 4LL * p;
+  double R[9], V0[6];
+  rotmat(qp, R);
+  lsq_body(B, p, s, R, v, 3, nullptr, 0, V0);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) calV[6LL * p + k] = V0[k];
+  double acc = 0.0;
+  if (mode == 0) {
+    for (int a = 0; a < 3; ++a) {  // translations: K unchanged, difference of v only
+      double dV[6];
+      lsq_body(B, p, s, R, vd + 3 * a, 18, nullptr, 0, dV);
+      acc += dV[a] / (delta * Lp);
+    }
+    for (int a = 0; a < 3; ++a) {  // rotations: K and v both change
+      double u[3] = {0, 0, 0}, e[4], q2[4], R2[9], V1[6];
+      u[a] = delta;
+      qexp(u, e);
+      qmul(e, qp, q2);
+      rotmat(q2, R2);
+      lsq_body(B, p, s, R2, v, 3, vd + 9 + 3 * a, 18, V1);
+      acc += (V1[3 + a] - V0[3 + a]) / delta;
+    }
+  } else {
+    const double* z = wrfd + 6LL * p;
+    double u[3] = {delta * z[3], delta * z[4], delta * z[5]}, e[4], q2[4], R2[9], V1[6];
+    qexp(u, e);
+    qmul(e, qp, q2);
+    rotmat(q2, R2);
+    lsq_body(B, p, s, R2, v, 3, vd, 3, V1);
+    acc = (z[0] * (V1[0] - V0[0]) + z[1] * (V1[1] - V0[1]) + z[2] * (V1[2] - V0[2])) / (delta * Lp) +
+          (z[3] * (V1[3] - V0[3]) + z[4] * (V1[4] - V0[4]) + z[5] * (V1[5] - V0[5])) / delta;
+  }
+  d[p] = acc;
+}
+
+// nu = 1 + half_dt * sum d, one block, fixed summation order.
+__global__ __launch_bounds__(1024) void k_nu_reduce(const double* __restrict__ d, int N, double half_dt,
+                                                    double* __restrict__ nu) {
+  __shared__ double sh[1024];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < N; i += 1024) s += d[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) nu[0] = 1.0 + half_dt * sh[0];
+}
+
+// Step 4: Y^m = Y + h calV_U, q^m = exp(h calV_Omega) . q.
+__global__ void k_midpoint(int N, const double* __restrict__ Y, const double* __restrict__ q,
+                           const double* __restrict__ calV, double h, double* __restrict__ Ym,
+                           double* __restrict__ qm) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const double* V = calV + 6LL * p;
+  Ym[3LL * p] = Y[3LL * p] + h * V[0];
+  Ym[3LL * p + 1] = Y[3LL * p + 1] + h * V[1];
+  Ym[3LL * p + 2] = Y[3LL * p + 2] + h * V[2];
+  double u[3] = {h * V[3], h * V[4], h * V[5]}, e[4];
+  qexp(u, e);
+  qmul(e, q + 4LL * p, qm + 4LL * p);
+}
+
+// Step 6: Y += nu dt V_U, q = exp(nu dt V_Omega) . q (nu on the device).
+__global__ void k_update(int N, double* __restrict__ Y, double* __restrict__ q, const double* __restrict__ V,
+                         const double* __restrict__ nu, double dt) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const double h = (nu ? nu[0] : 1.0) * dt;
+  const double* Vp = V + 6LL * p;
+  Y[3LL * p] += h * Vp[0];
+  Y[3LL * p + 1] += h * Vp[1];
+  Y[3LL * p + 2] += h * Vp[2];
+  double u[3] = {h * Vp[3], h * Vp[4], h * Vp[5]}, e[4], qn[4];
+  qexp(u, e);
+  qmul(e, q + 4LL * p, qn);
+  q[4LL * p] = qn[0];
+  q[4LL * p + 1] = qn[1];
+  q[4LL * p + 2] = qn[2];
+  q[4LL * p + 3] = qn[3];
+}
+
+// Right-hand side [-(v_slip + u_inf); -(I - Pi) F] of the saddle problem.
+__global__ void k_rhs_blobs(BodyTables B, const double* __restrict__ Y, const double* __restrict__ r,
+                            const double* __restrict__ vslip, double shear, double Ly, double* __restrict__ rhs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B.M) return;
+  double ux = 0.0;
+  if (shear != 0.0) {
+    const int p = B.blob_body[i];
+    const double yc = Y[3LL * p + 1];
+    const double yw = yc - Ly * floor(yc / Ly);
+    ux = shear * (yw + (r[3LL * i + 1] - yc) - 0.5 * Ly);
+  }
+  rhs[3LL * i] = -((vslip ? vslip[3LL * i] : 0.0) + ux);
+  rhs[3LL * i + 1] = -(vslip ? vslip[3LL * i + 1] : 0.0);
+  rhs[3LL * i + 2] = -(vslip ? vslip[3LL * i + 2] : 0.0);
+}
+
+__global__ void k_rhs_bodies(BodyTables B, const double* __restrict__ q, const double* __restrict__ F,
+                             double* __restrict__ rhsV) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= B.N) return;
+  double R[9], f[6], pf[6];
+  rotmat(q + 4LL * p, R);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) f[k] = F ? F[6LL * p + k] : 0.0;
+  rotate_6x6(B.shape_null + 36LL * B.body_shape[p], R, f, pf);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) rhsV[6LL * p + k] = -(f[k] - pf[k]);
+}
+
+// ------------------------------------------------------------ pair forces
+struct CellGrid {
+  int nc[3];
+  double csz[3];
+  double L[3];
+};
+
+__device__ __forceinline__ int cell_of(const CellGrid& C, const double* x, double* xw) {
+  int c[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    xw[d] = x[d] - C.L[d] * floor(x[d] / C.L[d]);
+    const double kf = xw[d] / C.csz[d];
+    int k = (kf >= 0.0 && kf < 1e9) ? (int)kf : 0;
+    c[d] = k < 0 ? 0 : (k >= C.nc[d] ? C.nc[d] - 1 : k);
+  }
+  return (c[0] * C.nc[1] + c[1]) * C.nc[2] + c[2];
+}
+
+__global__ void k_bin_blobs(CellGrid C, int M, const double* __restrict__ r, int* __restrict__ count,
+                            int* __restrict__ list, int cap, int* __restrict__ overflow) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  double xw[3];
+  const int c = cell_of(C, r + 3LL * i, xw);
+  const int slot = atomicAdd(count + c, 1);
+  if (slot < cap)
+    list[(long long)c * cap + slot] = i;
+  else
+    atomicMax(overflow, 1);
+}
+
+// Harmonic repulsion V = k/2 (r - b)^2 for r < b between blobs of different
+// bodies; each blob sums its own force (no atomics).
+__global__ void k_steric(CellGrid C, BodyTables B, const double* __restrict__ r, const int* __restrict__ count,
+                         const int* __restrict__ list, int cap, double kk, double b, double* __restrict__ f) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B.M) return;
+  double xi[3];
+  const int ci = cell_of(C, r + 3LL * i, xi);
+  int c3[3] = {ci / (C.nc[1] * C.nc[2]), (ci / C.nc[2]) % C.nc[1], ci % C.nc[2]};
+  const int bi = B.blob_body[i];
+  double fx = 0, fy = 0, fz = 0;
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int a0 = (c3[0] + dz + C.nc[0]) % C.nc[0];
+        const int a1 = (c3[1] + dy + C.nc[1]) % C.nc[1];
+        const int a2 = (c3[2] + dx + C.nc[2]) % C.nc[2];
+        const int cc = (a0 * C.nc[1] + a1) * C.nc[2] + a2;
+        const int n = min(count[cc], cap);
+        for (int s = 0; s < n; ++s) {
+          const int j = list[(long long)cc * cap + s];
+          if (j == i || B.blob_body[j] == bi) continue;
+          double d[3];
+#pragma unroll
+          for (int e = 0; e < 3; ++e) {
+            const double xj = r[3LL * j + e] - C.L[e] * floor(r[3LL * j + e] / C.L[e]);
+            double t = xi[e] - xj;
+            t -= C.L[e] * rint(t / C.L[e]);
+            d[e] = t;
+          }
+          const double dist2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+          if (dist2 < b * b && dist2 > 0.0) {
+            const double dist = sqrt(dist2);
+            const double m = kk * (b - dist) / dist;
+            fx += m * d[0];
+            fy += m * d[1];
+            fz += m * d[2];
+          }
+        }
+      }
+  f[3LL * i] = fx;
+  f[3LL * i + 1] = fy;
+  f[3LL * i + 2] = fz;
+}
+
+__global__ void k_body_forces(BodyTables B, const double* __restrict__ Y, const double* __restrict__ r,
+                              const double* __restrict__ fblob, const double* __restrict__ cf,
+                              double* __restrict__ F) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= B.N) return;
+  double acc[6] = {cf[0], cf[1], cf[2], cf[3], cf[4], cf[5]};
+  if (fblob) {
+    for (int i = B.body_off[p]; i < B.body_off[p + 1]; ++i) {
+      double rel[3] = {r[3LL * i] - Y[3LL * p], r[3LL * i + 1] - Y[3LL * p + 1], r[3LL * i + 2] - Y[3LL * p + 2]};
+      double fi[3], t[3];
+      load3(fblob + 3LL * i, fi);
+      cross3(rel, fi, t);
+      acc[0] += fi[0]; acc[1] += fi[1]; acc[2] += fi[2];
+      acc[3] += t[0]; acc[4] += t[1]; acc[5] += t[2];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) F[6LL * p + k] = acc[k];
+}
+
+__global__ void k_check_finite(const double* __restrict__ x, long long n, int* __restrict__ flag) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (long long k = i; k < n; k += stride) bad |= !isfinite(x[k]);
+  if (bad) atomicMax(flag, 1);
+}
+
+}  // namespace
+
+int blob_positions(const BodyTables& b, const double* Y, const double* q, double* r, hipStream_t s) {
+  if (b.M == 0) return GDC_OK;
+  hipLaunchKernelGGL(k_blob_positions, dim3(nblk(b.M)), dim3(NT), 0, s, b, Y, q, r);
+  return check_launch("k_blob_positions");
+}
+
+int saddle_rigid_terms(const BodyTables& b, const double* Y, const double* q, const double* r,
+                       const double* lam, const double* V, double* out_lam, double* out_V, hipStream_t s) {
+  hipLaunchKernelGGL(k_saddle_rigid, dim3(nblk(b.N, 128)), dim3(128), 0, s, b, Y, q, r, lam, V, out_lam, out_V);
+  return check_launch("k_saddle_rigid");
+}
+
+int precond_apply(const BodyTables& b, const double* q, const double* x, double* y, int maxdim, hipStream_t s) {
+  const size_t shm = 2 * (size_t)maxdim * sizeof(double);
+  hipLaunchKernelGGL(k_precond, dim3(b.N), dim3(64), shm, s, b, q, x, y);
+  return check_launch("k_precond");
+}
+
+int fd_displacements(const BodyTables& b, const double* q, double delta, int mode, uint64_t seed,
+                     uint64_t step, double* dr, double* wrfd, hipStream_t s) {
+  hipLaunchKernelGGL(k_fd_displacements, dim3(nblk(b.M)), dim3(NT), 0, s, b, q, delta, mode, seed, step, dr, wrfd);
+  return check_launch("k_fd_displacements");
+}
+
+int body_lsq_div(const BodyTables& b, const double* q, const double* v, const double* vd, const double* wrfd,
+                 double delta, int mode, double* calV, double* d, hipStream_t s) {
+  hipLaunchKernelGGL(k_body_lsq_div, dim3(nblk(b.N, 128)), dim3(128), 0, s, b, q, v, vd, wrfd, delta, mode, calV, d);
+  return check_launch("k_body_lsq_div");
+}
+
+int nu_reduce(const double* d, int N, double half_dt, double* nu, hipStream_t s) {
+  hipLaunchKernelGGL(k_nu_reduce, dim3(1), dim3(1024), 0, s, d, N, half_dt, nu);
+  return check_launch("k_nu_reduce");
+}
+
+int midpoint(const BodyTables& b, const double* Y, const double* q, const double* calV, double h, double* Ym,
+             double* qm, hipStream_t s) {
+  hipLaunchKernelGGL(k_midpoint, dim3(nblk(b.N)), dim3(NT), 0, s, b.N, Y, q, calV, h, Ym, qm);
+  return check_launch("k_midpoint");
+}
+
+int update(const BodyTables& b, double* Y, double* q, const double* V, const double* nu, double dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_update, dim3(nblk(b.N)), dim3(NT), 0, s, b.N, Y, q, V, nu, dt);
+  return check_launch("k_update");
+}
+
+int rhs_build(const BodyTables& b, const double* q, const double* Y, const double* r, const double* vslip,
+              const double* F, double shear, double Ly, double* rhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_rhs_blobs, dim3(nblk(b.M)), dim3(NT), 0, s, b, Y, r, vslip, shear, Ly, rhs);
+  GDC_TRY(check_launch("k_rhs_blobs"));
+  hipLaunchKernelGGL(k_rhs_bodies, dim3(nblk(b.N)), dim3(NT), 0, s, b, q, F, rhs + 3LL * b.M);
+  return check_launch("k_rhs_bodies");
+}
+
+int steric_forces(const BodyTables& b, const GridGeom& g, const double* r, double k, double cutoff,
+                  int* cell_count, int* cell_list, int cap, const int nc[3], int* overflow, double* fblob,
+                  hipStream_t s) {
+  CellGrid C;
+  for (int d = 0; d < 3; ++d) {
+    C.nc[d] = nc[d];
+    C.L[d] = g.L[d];
+    C.csz[d] = g.L[d] / nc[d];
+  }
+  const long long ncell = (long long)nc[0] * nc[1] * nc[2];
+  GDC_TRY(fill_zero(cell_count, ((size_t)ncell * sizeof(int) + 15) / 16 * 16, s));
+  hipLaunchKernelGGL(k_bin_blobs, dim3(nblk(b.M)), dim3(NT), 0, s, C, b.M, r, cell_count, cell_list, cap, overflow);
+  GDC_TRY(check_launch("k_bin_blobs"));
+  hipLaunchKernelGGL(k_steric, dim3(nblk(b.M)), dim3(NT), 0, s, C, b, r, cell_count, cell_list, cap, k, cutoff, fblob);
+  return check_launch("k_steric");
+}
+
+int body_forces(const BodyTables& b, const double* Y, const double* r, const double* fblob, const double* cforce,
+                double* F, hipStream_t s) {
+  hipLaunchKernelGGL(k_body_forces, dim3(nblk(b.N)), dim3(NT), 0, s, b, Y, r, fblob, cforce, F);
+  return check_launch("k_body_forces");
+}
+
+int check_finite(const double* x, long long n, int* flag, hipStream_t s) {
+  const long long want = (n + 255) / 256;
+  hipLaunchKernelGGL(k_check_finite, dim3((unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096)), dim3(256), 0, s,
+                     x, n, flag);
+  return check_launch("k_check_finite");
+}
+
+}  // namespace gdc

@@ -1,0 +1,565 @@
+// Spectral Stokes solve and fluctuating-stress field on gfx950.
+//
+// The periodic Stokes problem of Sec. 4.2 is solved in Fourier space:
+// u_hat = (I - k k^T/|k|^2) f_hat / (eta |k|^2), with the k = 0 mode and every
+// mode with an index at n_d/2 removed.  The 3-D real transforms are done as
+// five LDS-resident passes over lines, each a full read and write of the
+// field with coalesced or 128-byte-segment access, and each pass writing its
+// output transposed so that the next pass reads contiguous lines:
+//
+//   A  real [c][i0][i1][i2]   --R2C along axis 2-->  X [c][i0][k2][i1]
+//   B  X                      --FFT along axis 1-->  Y [c][k2][k1][i0]
+//   C  Y (3 components)  --FFT axis 0, project, inverse FFT axis 0-->  Y
+//   B' Y                      --iFFT along axis 1--> X
+//   A' X                      --C2R along axis 2-->  real
+//
+// Only k2 < n2/2 is stored: the Nyquist plane is zeroed by the solver, so the
+// half spectrum has exactly the real field's size and the three buffers can
+// ping-pong.  The random velocity field needs no forward transforms: pass C
+// draws the stress spectrum from Philox counters, takes its divergence and
+// projects it in place of a load (noise fused with the projection).
+//
+// Each 1-D transform is a Stockham autosort FFT with radix-4/2/3 stages,
+// fully unrolled per line length, running on several lines per workgroup in
+// LDS with twiddles e^{-2 pi i k/N} from a table computed on the host.
+
+#include "gdc_internal.h"
+#include "noise_dev.h"
+
+#include <cmath>
+
+namespace gdc {
+namespace {
+
+constexpr int NT = 256;
+
+template <typename R>
+struct Tiles {
+  // Lines per workgroup in passes A, B, B', A' (128-byte segments in the
+  // transposed accesses) and per component in pass C.
+  static constexpr int TL = sizeof(R) == 4 ? 16 : 8;
+  static constexpr int TC = sizeof(R) == 4 ? 4 : 2;
+};
+
+constexpr int next_radix(int n) {
+  return (n % 4 == 0) ? 4 : (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : 0;
+}
+
+// Radix-R DFT in registers, V[s] = sum_r v[r] w^{rs}, w = e^{-+2 pi i/R}.
+template <typename R, int RAD, bool INV>
+struct Bfly;
+
+template <typename R, bool INV>
+struct Bfly<R, 2, INV> {
+  __device__ __forceinline__ static void run(Cx<R>* v) {
+    const Cx<R> a = v[0], b = v[1];
+    v[0] = Cx<R>{a.x + b.x, a.y + b.y};
+    v[1] = Cx<R>{a.x - b.x, a.y - b.y};
+  }
+};
+
+template <typename R, bool INV>
+struct Bfly<R, 4, INV> {
+  __device__ __forceinline__ static void run(Cx<R>* v) {
+    const Cx<R> a{v[0].x + v[2].x, v[0].y + v[2].y};
+    const Cx<R> b{v[0].x - v[2].x, v[0].y - v[2].y};
+    const Cx<R> c{v[1].x + v[3].x, v[1].y + v[3].y};
+    const Cx<R> d{v[1].x - v[3].x, v[1].y - v[3].y};
+    v[0] = Cx<R>{a.x + c.x, a.y + c.y};
+    v[2] = Cx<R>{a.x - c.x, a.y - c.y};
+    if (!INV) {  // w = -i
+      v[1] = Cx<R>{b.x + d.y, b.y - d.x};
+      v[3] = Cx<R>{b.x - d.y, b.y + d.x};
+    } else {
+      v[1] = Cx<R>{b.x - d.y, b.y + d.x};
+      v[3] = Cx<R>{b.x + d.y, b.y - d.x};
+    }
+  }
+};
+
+template <typename R, bool INV>
+struct Bfly<R, 3, INV> {
+  __device__ __forceinline__ static void run(Cx<R>* v) {
+    constexpr R h = R(0.86602540378443864676);  // sqrt(3)/2
+    const Cx<R> s{v[1].x + v[2].x, v[1].y + v[2].y};
+    const Cx<R> t{v[1].x - v[2].x, v[1].y - v[2].y};
+    const Cx<R> m{v[0].x - R(0.5) * s.x, v[0].y - R(0.5) * s.y};
+    // forward: w = -i h t ; inverse: w = +i h t
+    const Cx<R> w = INV ? Cx<R>{-h * t.y, h * t.x} : Cx<R>{h * t.y, -h * t.x};
+    v[0] = Cx<R>{v[0].x + s.x, v[0].y + s.y};
+    v[1] = Cx<R>{m.x + w.x, m.y + w.y};
+    v[2] = Cx<R>{m.x - w.x, m.y - w.y};
+  }
+};
+
+// One Stockham stage on NL lines of length N (line stride LS) in LDS: the
+// sub-transforms of length NS are combined RAD at a time.  Every thread reads
+// its butterflies' inputs into registers, the block synchronises, then the
+// outputs are written in place.
+template <typename R, int N, int NL, int LS, int RAD, int NS, bool INV>
+__device__ __forceinline__ void fft_stage(Cx<R>* buf, const Cx<R>* tw) {
+  constexpr int NB = N / RAD;
+  constexpr int TOT = NL * NB;
+  constexpr int PER = (TOT + NT - 1) / NT;
+  Cx<R> v[PER][RAD];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int b = tid + m * NT;
+    if ((TOT % NT == 0) || b < TOT) {
+      const int t = b / NB, j = b - t * NB;
+      const Cx<R>* line = buf + t * LS;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[m][r] = line[j + r * NB];
+      if (NS > 1) {
+        const int k = j % NS;
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) {
+          Cx<R> w = tw[r * k * (N / (NS * RAD))];
+          if (INV) w.y = -w.y;
+          v[m][r] = cmul(v[m][r], w);
+        }
+      }
+      Bfly<R, RAD, INV>::run(v[m]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int b = tid + m * NT;
+    if ((TOT % NT == 0) || b < TOT) {
+      const int t = b / NB, j = b - t * NB;
+      const int k = j % NS;
+      Cx<R>* line = buf + t * LS;
+      const int d = (j / NS) * NS * RAD + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) line[d + r * NS] = v[m][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename R, int N, int NL, int LS, bool INV, int REM, int NS>
+struct Stages {
+  __device__ __forceinline__ static void run(Cx<R>* buf, const Cx<R>* tw) {
+    constexpr int RAD = next_radix(REM);
+    static_assert(RAD > 0, "line length must be 2^a 3^b");
+    fft_stage<R, N, NL, LS, RAD, NS, INV>(buf, tw);
+    Stages<R, N, NL, LS, INV, REM / RAD, NS * RAD>::run(buf, tw);
+  }
+};
+template <typename R, int N, int NL, int LS, bool INV, int NS>
+struct Stages<R, N, NL, LS, INV, 1, NS> {
+  __device__ __forceinline__ static void run(Cx<R>*, const Cx<R>*) {}
+};
+
+// Unnormalised forward (e^{-i}) or inverse (e^{+i}) transforms of NL lines.
+template <typename R, int N, int NL, int LS, bool INV>
+__device__ __forceinline__ void fft_lines(Cx<R>* buf, const Cx<R>* tw) {
+  Stages<R, N, NL, LS, INV, N, 1>::run(buf, tw);
+}
+
+template <typename R, int N>
+__device__ __forceinline__ void load_twiddles(Cx<R>* tw, const Cx<R>* __restrict__ twg) {
+  for (int k = threadIdx.x; k < N; k += NT) tw[k] = twg[k];
+}
+
+// ------------------------------------------------------------ pass A: R2C, axis 2
+// Two real lines packed as one complex line z = a + i b; after the FFT,
+// A(k) = (Z(k) + conj Z(N-k))/2 and B(k) = (Z(k) - conj Z(N-k))/(2i).
+template <typename R, int N2>
+__global__ __launch_bounds__(NT) void k_r2c_axis2(const R* __restrict__ in, Cx<R>* __restrict__ X,
+                                                  const Cx<R>* __restrict__ twg, int n0, int n1) {
+  constexpr int TL = Tiles<R>::TL, NLc = TL / 2, LS = N2 + 1, H = N2 / 2;
+  __shared__ Cx<R> buf[NLc * LS];
+  __shared__ Cx<R> tw[N2];
+  const int tid = threadIdx.x;
+  const int c = blockIdx.z, i0 = blockIdx.y, i1b = blockIdx.x * TL;
+  const int nl = min(TL, n1 - i1b);
+  load_twiddles<R, N2>(tw, twg);
+  const R* src = in + (((long long)c * n0 + i0) * n1 + i1b) * N2;
+  for (int e = tid; e < NLc * N2; e += NT) {
+    const int p = e / N2, x = e - p * N2;
+    const R re = (2 * p < nl) ? src[(2 * p) * N2 + x] : R(0);
+    const R im = (2 * p + 1 < nl) ? src[(2 * p + 1) * N2 + x] : R(0);
+    buf[p * LS + x] = Cx<R>{re, im};
+  }
+  __syncthreads();
+  fft_lines<R, N2, NLc, LS, false>(buf, tw);
+  Cx<R>* dst = X + ((long long)c * n0 + i0) * H * n1 + i1b;
+  for (int e = tid; e < H * TL; e += NT) {
+    const int k = e / TL, t = e - k * TL;
+    if (t < nl) {
+      const int p = t >> 1;
+      const Cx<R> z = buf[p * LS + k];
+      const Cx<R> zc = buf[p * LS + ((N2 - k) % N2)];
+      Cx<R> a;
+      if ((t & 1) == 0)
+        a = Cx<R>{R(0.5) * (z.x + zc.x), R(0.5) * (z.y - zc.y)};
+      else
+        a = Cx<R>{R(0.5) * (z.y + zc.y), R(0.5) * (zc.x - z.x)};
+      dst[(long long)k * n1 + t] = a;
+    }
+  }
+}
+
+// ------------------------------------------------------------ pass B: FFT, axis 1
+template <typename R, int N1>
+__global__ __launch_bounds__(NT) void k_fwd_axis1(const Cx<R>* __restrict__ X, Cx<R>* __restrict__ Y,
+                                                  const Cx<R>* __restrict__ twg, int n0, int H) {
+  constexpr int TL = Tiles<R>::TL, LS = N1 + 1;
+  __shared__ Cx<R> buf[TL * LS];
+  __shared__ Cx<R> tw[N1];
+  const int tid = threadIdx.x;
+  const int c = blockIdx.z, k2 = blockIdx.y, i0b = blockIdx.x * TL;
+  const int nl = min(TL, n0 - i0b);
+  load_twiddles<R, N1>(tw, twg);
+  for (int e = tid; e < TL * N1; e += NT) {
+    const int t = e / N1, x = e - t * N1;
+    buf[t * LS + x] = (t < nl) ? X[(((long long)c * n0 + i0b + t) * H + k2) * N1 + x] : Cx<R>{R(0), R(0)};
+  }
+  __syncthreads();
+  fft_lines<R, N1, TL, LS, false>(buf, tw);
+  for (int e = tid; e < N1 * TL; e += NT) {
+    const int k1 = e / TL, t = e - k1 * TL;
+    if (t < nl) Y[(((long long)c * H + k2) * N1 + k1) * n0 + i0b + t] = buf[t * LS + k1];
+  }
+}
+
+// ------------------------------------------------------------ pass B': iFFT, axis 1
+template <typename R, int N1>
+__global__ __launch_bounds__(NT) void k_inv_axis1(const Cx<R>* __restrict__ Y, Cx<R>* __restrict__ X,
+                                                  const Cx<R>* __restrict__ twg, int n0, int H) {
+  constexpr int TL = Tiles<R>::TL, LS = N1 + 1;
+  __shared__ Cx<R> buf[TL * LS];
+  __shared__ Cx<R> tw[N1];
+  const int tid = threadIdx.x;
+  const int c = blockIdx.z, k2 = blockIdx.y, i0b = blockIdx.x * TL;
+  const int nl = min(TL, n0 - i0b);
+  load_twiddles<R, N1>(tw, twg);
+  for (int e = tid; e < N1 * TL; e += NT) {
+    const int k1 = e / TL, t = e - k1 * TL;
+    buf[t * LS + k1] = (t < nl) ? Y[(((long long)c * H + k2) * N1 + k1) * n0 + i0b + t] : Cx<R>{R(0), R(0)};
+  }
+  __syncthreads();
+  fft_lines<R, N1, TL, LS, true>(buf, tw);
+  for (int e = tid; e < TL * N1; e += NT) {
+    const int t = e / N1, x = e - t * N1;
+    if (t < nl) X[(((long long)c * n0 + i0b + t) * H + k2) * N1 + x] = buf[t * LS + x];
+  }
+}
+
+// ------------------------------------------------------------ pass A': C2R, axis 2
+// Z(k) = A(k) + i B(k) with the Hermitian extension A(N-k) = conj A(k); the
+// k = 0 term keeps only real parts (as a real inverse transform does) and the
+// Nyquist term is zero.
+template <typename R, int N2>
+__global__ __launch_bounds__(NT) void k_c2r_axis2(const Cx<R>* __restrict__ X, R* __restrict__ out,
+                                                  const Cx<R>* __restrict__ twg, int n0, int n1) {
+  constexpr int TL = Tiles<R>::TL, NLc = TL / 2, LS = N2 + 1, H = N2 / 2;
+  __shared__ Cx<R> buf[NLc * LS];
+  __shared__ Cx<R> tw[N2];
+  const int tid = threadIdx.x;
+  const int c = blockIdx.z, i0 = blockIdx.y, i1b = blockIdx.x * TL;
+  const int nl = min(TL, n1 - i1b);
+  load_twiddles<R, N2>(tw, twg);
+  const Cx<R>* src = X + ((long long)c * n0 + i0) * H * n1 + i1b;
+  const Cx<R> zero{R(0), R(0)};
+  for (int e = tid; e < H * NLc; e += NT) {
+    const int k = e / NLc, p = e - k * NLc;
+    const Cx<R> a = (2 * p < nl) ? src[(long long)k * n1 + 2 * p] : zero;
+    const Cx<R> b = (2 * p + 1 < nl) ? src[(long long)k * n1 + 2 * p + 1] : zero;
+    if (k == 0) {
+      buf[p * LS] = Cx<R>{a.x, b.x};
+      buf[p * LS + H] = zero;
+    } else {
+      buf[p * LS + k] = Cx<R>{a.x - b.y, a.y + b.x};
+      buf[p * LS + N2 - k] = Cx<R>{a.x + b.y, b.x - a.y};
+    }
+  }
+  __syncthreads();
+  fft_lines<R, N2, NLc, LS, true>(buf, tw);
+  R* dst = out + (((long long)c * n0 + i0) * n1 + i1b) * N2;
+  for (int e = tid; e < NLc * N2; e += NT) {
+    const int p = e / N2, x = e - p * N2;
+    const Cx<R> z = buf[p * LS + x];
+    if (2 * p < nl) dst[(2 * p) * N2 + x] = z.x;
+    if (2 * p + 1 < nl) dst[(2 * p + 1) * N2 + x] = z.y;
+  }
+}
+
+__global__ void k_philox_normals(uint64_t seed, uint32_t c1, uint64_t step, uint32_t c0_begin,
+                                 int count, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  double z[4];
+  four_normals(seed, c0_begin + (uint32_t)i, c1, step, z);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) out[4 * (long long)i + k] = z[k];
+}
+
+// ------------------------------------------------------------ pass C
+struct ProjParams {
+  int n0, n1, n2h;
+  double kf0, kf1, kf2;    // 2 pi / L_d
+  double inv_eta;
+  double invG;
+  // noise
+  uint64_t seed, step;
+  double sdiag, soff;      // sqrt(G var / 2) of diagonal / off-diagonal components
+};
+
+__device__ __forceinline__ int signed_index(int j, int n) { return j < n / 2 ? j : j - n; }
+
+// Velocity spectrum of the stress noise at stored mode (j0, j1, j2), already
+// projected and scaled by 1/(eta |k|^2 G).  Returns false for removed modes.
+__device__ bool noise_mode(const ProjParams& P, int j0, int j1, int j2, double ur[3], double ui[3]) {
+  const int n0 = P.n0, n1 = P.n1;
+  if (j0 == n0 / 2 || j1 == n1 / 2 || (j0 == 0 && j1 == 0 && j2 == 0)) return false;
+  const int m0 = signed_index(j0, n0), m1 = signed_index(j1, n1);
+  int c0 = j0, c1 = j1;
+  bool conj = false;
+  if (j2 == 0 && !(m1 > 0 || (m1 == 0 && m0 > 0))) {
+    c0 = (n0 - j0) % n0;
+    c1 = (n1 - j1) % n1;
+    conj = true;
+  }
+  const uint32_t idx = (uint32_t)(((long long)c0 * n1 + c1) * P.n2h + j2);
+  double z[12];
+#pragma unroll
+  for (int call = 0; call < 3; ++call) four_normals(P.seed, idx, (uint32_t)call, P.step, z + 4 * call);
+  // W components xx, yy, zz, xy, xz, yz
+  double wr[6], wi[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const double sc = c < 3 ? P.sdiag : P.soff;
+    wr[c] = sc * z[2 * c];
+    wi[c] = conj ? -sc * z[2 * c + 1] : sc * z[2 * c + 1];
+  }
+  const double k[3] = {P.kf0 * m0, P.kf1 * m1, P.kf2 * j2};
+  // g_a = i sum_b k_b W_ab
+  const double sr[3] = {k[0] * wr[0] + k[1] * wr[3] + k[2] * wr[4],
+                        k[0] * wr[3] + k[1] * wr[1] + k[2] * wr[5],
+                        k[0] * wr[4] + k[1] * wr[5] + k[2] * wr[2]};
+  const double si[3] = {k[0] * wi[0] + k[1] * wi[3] + k[2] * wi[4],
+                        k[0] * wi[3] + k[1] * wi[1] + k[2] * wi[5],
+                        k[0] * wi[4] + k[1] * wi[5] + k[2] * wi[2]};
+  double gr[3], gi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    gr[a] = -si[a];
+    gi[a] = sr[a];
+  }
+  const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+  const double kgr = (k[0] * gr[0] + k[1] * gr[1] + k[2] * gr[2]) / k2;
+  const double kgi = (k[0] * gi[0] + k[1] * gi[1] + k[2] * gi[2]) / k2;
+  const double sc = P.inv_eta * P.invG / k2;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    ur[a] = sc * (gr[a] - k[a] * kgr);
+    ui[a] = sc * (gi[a] - k[a] * kgi);
+  }
+  return true;
+}
+
+template <typename R, int N0, bool NOISE>
+__global__ __launch_bounds__(NT) void k_axis0_project(Cx<R>* __restrict__ Y, const Cx<R>* __restrict__ twg,
+                                                      ProjParams P) {
+  constexpr int TC = Tiles<R>::TC, NLn = 3 * TC, LS = N0 + 1;
+  __shared__ Cx<R> buf[NLn * LS];
+  __shared__ Cx<R> tw[N0];
+  const int tid = threadIdx.x;
+  const int k2 = blockIdx.y, k1b = blockIdx.x * TC;
+  const int nl = min(TC, P.n1 - k1b);
+  const int H = P.n2h, n1 = P.n1;
+  load_twiddles<R, N0>(tw, twg);
+  if (!NOISE) {
+    for (int e = tid; e < NLn * N0; e += NT) {
+      const int l = e / N0, x = e - l * N0;
+      const int c = l / TC, t = l - c * TC;
+      buf[l * LS + x] = (t < nl) ? Y[(((long long)c * H + k2) * n1 + k1b + t) * N0 + x] : Cx<R>{R(0), R(0)};
+    }
+    __syncthreads();
+    fft_lines<R, N0, NLn, LS, false>(buf, tw);
+  } else {
+    __syncthreads();
+  }
+  for (int e = tid; e < TC * N0; e += NT) {
+    const int t = e / N0, j0 = e - t * N0;
+    const int j1 = k1b + t;
+    Cx<R> u[3] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
+    if (t < nl) {
+      if (NOISE) {
+        double ur[3], ui[3];
+        if (noise_mode(P, j0, j1, k2, ur, ui)) {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) u[a] = Cx<R>{R(ur[a]), R(ui[a])};
+        }
+      } else if (!(j0 == N0 / 2 || j1 == n1 / 2 || (j0 == 0 && j1 == 0 && k2 == 0))) {
+        const R kx = R(P.kf0) * R(signed_index(j0, N0));
+        const R ky = R(P.kf1) * R(signed_index(j1, n1));
+        const R kz = R(P.kf2) * R(k2);
+        const R kk = kx * kx + ky * ky + kz * kz;
+        const Cx<R> f0 = buf[(0 * TC + t) * LS + j0];
+        const Cx<R> f1 = buf[(1 * TC + t) * LS + j0];
+        const Cx<R> f2 = buf[(2 * TC + t) * LS + j0];
+        const R ikk = R(1) / kk;
+        const R dr = (kx * f0.x + ky * f1.x + kz * f2.x) * ikk;
+        const R di = (kx * f0.y + ky * f1.y + kz * f2.y) * ikk;
+        const R sc = R(P.inv_eta * P.invG) * ikk;
+        u[0] = Cx<R>{sc * (f0.x - kx * dr), sc * (f0.y - kx * di)};
+        u[1] = Cx<R>{sc * (f1.x - ky * dr), sc * (f1.y - ky * di)};
+        u[2] = Cx<R>{sc * (f2.x - kz * dr), sc * (f2.y - kz * di)};
+      }
+    }
+    // Each (t, j0) is read and written by the same thread only.
+#pragma unroll
+    for (int a = 0; a < 3; ++a) buf[(a * TC + t) * LS + j0] = u[a];
+  }
+  __syncthreads();
+  fft_lines<R, N0, NLn, LS, true>(buf, tw);
+  for (int e = tid; e < NLn * N0; e += NT) {
+    const int l = e / N0, x = e - l * N0;
+    const int c = l / TC, t = l - c * TC;
+    if (t < nl) Y[(((long long)c * H + k2) * n1 + k1b + t) * N0 + x] = buf[l * LS + x];
+  }
+}
+
+// ------------------------------------------------------------ dispatch
+
+#define GDC_FFT_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+
+template <typename R>
+int launch_r2c(int n2, const R* in, Cx<R>* X, const Cx<R>* tw, int n0, int n1, hipStream_t s) {
+  dim3 grid((n1 + Tiles<R>::TL - 1) / Tiles<R>::TL, n0, 3);
+  switch (n2) {
+#define X_(N) case N: hipLaunchKernelGGL((k_r2c_axis2<R, N>), grid, dim3(NT), 0, s, in, X, tw, n0, n1); break;
+    GDC_FFT_SIZES(X_)
+#undef X_
+    default: set_error("unsupported grid size"); return GDC_EINVAL;
+  }
+  return check_launch("k_r2c_axis2");
+}
+
+template <typename R>
+int launch_fwd1(int n1, const Cx<R>* X, Cx<R>* Y, const Cx<R>* tw, int n0, int H, hipStream_t s) {
+  dim3 grid((n0 + Tiles<R>::TL - 1) / Tiles<R>::TL, H, 3);
+  switch (n1) {
+#define X_(N) case N: hipLaunchKernelGGL((k_fwd_axis1<R, N>), grid, dim3(NT), 0, s, X, Y, tw, n0, H); break;
+    GDC_FFT_SIZES(X_)
+#undef X_
+    default: set_error("unsupported grid size"); return GDC_EINVAL;
+  }
+  return check_launch("k_fwd_axis1");
+}
+
+template <typename R>
+int launch_inv1(int n1, const Cx<R>* Y, Cx<R>* X, const Cx<R>* tw, int n0, int H, hipStream_t s) {
+  dim3 grid((n0 + Tiles<R>::TL - 1) / Tiles<R>::TL, H, 3);
+  switch (n1) {
+#define X_(N) case N: hipLaunchKernelGGL((k_inv_axis1<R, N>), grid, dim3(NT), 0, s, Y, X, tw, n0, H); break;
+    GDC_FFT_SIZES(X_)
+#undef X_
+    default: set_error("unsupported grid size"); return GDC_EINVAL;
+  }
+  return check_launch("k_inv_axis1");
+}
+
+template <typename R>
+int launch_c2r(int n2, const Cx<R>* X, R* out, const Cx<R>* tw, int n0, int n1, hipStream_t s) {
+  dim3 grid((n1 + Tiles<R>::TL - 1) / Tiles<R>::TL, n0, 3);
+  switch (n2) {
+#define X_(N) case N: hipLaunchKernelGGL((k_c2r_axis2<R, N>), grid, dim3(NT), 0, s, X, out, tw, n0, n1); break;
+    GDC_FFT_SIZES(X_)
+#undef X_
+    default: set_error("unsupported grid size"); return GDC_EINVAL;
+  }
+  return check_launch("k_c2r_axis2");
+}
+
+template <typename R, bool NOISE>
+int launch_proj(int n0, Cx<R>* Y, const Cx<R>* tw, const ProjParams& P, hipStream_t s) {
+  dim3 grid((P.n1 + Tiles<R>::TC - 1) / Tiles<R>::TC, P.n2h, 1);
+  switch (n0) {
+#define X_(N) case N: hipLaunchKernelGGL((k_axis0_project<R, N, NOISE>), grid, dim3(NT), 0, s, Y, tw, P); break;
+    GDC_FFT_SIZES(X_)
+#undef X_
+    default: set_error("unsupported grid size"); return GDC_EINVAL;
+  }
+  return check_launch("k_axis0_project");
+}
+
+ProjParams proj_params(const GridGeom& g) {
+  ProjParams P{};
+  P.n0 = g.n[0];
+  P.n1 = g.n[1];
+  P.n2h = g.n2h;
+  constexpr double kTwoPi = 6.283185307179586476925;
+  P.kf0 = kTwoPi / g.L[0];
+  P.kf1 = kTwoPi / g.L[1];
+  P.kf2 = kTwoPi / g.L[2];
+  P.inv_eta = 1.0 / g.eta;
+  P.invG = 1.0 / (double)g.G;
+  return P;
+}
+
+}  // namespace
+
+bool fft_size_supported(int n) {
+  switch (n) {
+#define X_(N) case N: return true;
+    GDC_FFT_SIZES(X_)
+#undef X_
+    default: return false;
+  }
+}
+
+template <typename R>
+int stokes_solve(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, Cx<R>* Y,
+                 hipStream_t s) {
+  const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], H = g.n2h;
+  GDC_TRY(launch_r2c<R>(n2, real, X, tw[2], n0, n1, s));
+  GDC_TRY(launch_fwd1<R>(n1, X, Y, tw[1], n0, H, s));
+  GDC_TRY((launch_proj<R, false>(n0, Y, tw[0], proj_params(g), s)));
+  GDC_TRY(launch_inv1<R>(n1, Y, X, tw[1], n0, H, s));
+  GDC_TRY(launch_c2r<R>(n2, X, real, tw[2], n0, n1, s));
+  return GDC_OK;
+}
+
+template <typename R>
+int fluct_field(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, Cx<R>* Y,
+                uint64_t seed, uint64_t step, double kT, double dt, hipStream_t s) {
+  const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], H = g.n2h;
+  ProjParams P = proj_params(g);
+  P.seed = seed;
+  P.step = step;
+  // real-space variances 4 kT eta/(dV dt) (diagonal) and 2 kT eta/(dV dt)
+  // (off-diagonal) of the stress at a grid point; per stored mode, real and
+  // imaginary parts each carry G var / 2.
+  const double base = kT * g.eta / (g.dV * dt);
+  P.sdiag = std::sqrt((double)g.G * 4.0 * base / 2.0);
+  P.soff = std::sqrt((double)g.G * 2.0 * base / 2.0);
+  GDC_TRY((launch_proj<R, true>(n0, Y, tw[0], P, s)));
+  GDC_TRY(launch_inv1<R>(n1, Y, X, tw[1], n0, H, s));
+  GDC_TRY(launch_c2r<R>(n2, X, real, tw[2], n0, n1, s));
+  return GDC_OK;
+}
+
+int philox_normals_dev(uint64_t seed, uint32_t c1, uint64_t step, uint32_t c0_begin, int count,
+                       double* out_dev, hipStream_t s) {
+  if (count <= 0) return GDC_OK;
+  hipLaunchKernelGGL(k_philox_normals, dim3((count + 255) / 256), dim3(256), 0, s, seed, c1, step,
+                     c0_begin, count, out_dev);
+  return check_launch("k_philox_normals");
+}
+
+template int stokes_solve<float>(const GridGeom&, const Cx<float>* const[3], float*, Cx<float>*,
+                                 Cx<float>*, hipStream_t);
+template int stokes_solve<double>(const GridGeom&, const Cx<double>* const[3], double*, Cx<double>*,
+                                  Cx<double>*, hipStream_t);
+template int fluct_field<float>(const GridGeom&, const Cx<float>* const[3], float*, Cx<float>*,
+                                Cx<float>*, uint64_t, uint64_t, double, double, hipStream_t);
+template int fluct_field<double>(const GridGeom&, const Cx<double>* const[3], double*, Cx<double>*,
+                                 Cx<double>*, uint64_t, uint64_t, double, double, hipStream_t);
+
+}  // namespace gdc

@@ -1,0 +1,215 @@
+// Internal declarations shared by the translation units of libgdc.
+// Device helpers here are header-inline; each .hip file owns its kernels and
+// exposes host launchers declared below.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gdc.h"
+
+namespace gdc {
+
+// ------------------------------------------------------------ error plumbing
+
+void set_error(const std::string& msg);
+
+struct Status {
+  int code = GDC_OK;
+  explicit operator bool() const { return code == GDC_OK; }
+};
+
+#define GDC_HIP(call)                                                           \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      ::gdc::set_error(std::string(#call) + ": " + hipGetErrorString(e_));       \
+      return GDC_EDEVICE;                                                       \
+    }                                                                           \
+  } while (0)
+
+#define GDC_TRY(expr)          \
+  do {                         \
+    int rc_ = (expr);          \
+    if (rc_ != GDC_OK) return rc_; \
+  } while (0)
+
+// Checks the launch of the kernel just issued.
+int check_launch(const char* what);
+
+// ------------------------------------------------------------ complex values
+
+template <typename R>
+struct alignas(2 * sizeof(R)) Cx {
+  R x, y;
+};
+
+template <typename R>
+__host__ __device__ inline Cx<R> cmul(Cx<R> a, Cx<R> b) {
+  return Cx<R>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// ------------------------------------------------------------ rigid-body algebra
+// Scalar-first unit quaternions and the Hamilton product (Appendix A).
+
+// R(q), row-major, eq. (quaternion_rotation_matrix).
+__host__ __device__ inline void rotmat(const double* q, double* R) {
+  const double q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+  R[0] = 1.0 - 2.0 * q2 * q2 - 2.0 * q3 * q3;
+  R[1] = 2.0 * (q1 * q2 - q3 * q0);
+  R[2] = 2.0 * (q1 * q3 + q2 * q0);
+  R[3] = 2.0 * (q1 * q2 + q3 * q0);
+  R[4] = 1.0 - 2.0 * q1 * q1 - 2.0 * q3 * q3;
+  R[5] = 2.0 * (q3 * q2 - q1 * q0);
+  R[6] = 2.0 * (q1 * q3 - q2 * q0);
+  R[7] = 2.0 * (q3 * q2 + q1 * q0);
+  R[8] = 1.0 - 2.0 * q2 * q2 - 2.0 * q1 * q1;
+}
+
+// p . q
+__host__ __device__ inline void qmul(const double* p, const double* q, double* out) {
+  const double s = p[0] * q[0] - (p[1] * q[1] + p[2] * q[2] + p[3] * q[3]);
+  const double x = p[0] * q[1] + q[0] * p[1] + (p[2] * q[3] - p[3] * q[2]);
+  const double y = p[0] * q[2] + q[0] * p[2] + (p[3] * q[1] - p[1] * q[3]);
+  const double z = p[0] * q[3] + q[0] * p[3] + (p[1] * q[2] - p[2] * q[1]);
+  out[0] = s;
+  out[1] = x;
+  out[2] = y;
+  out[3] = z;
+}
+
+// exp(u) = (cos(|u|/2), sin(|u|/2) u/|u|); below |u| = 1e-4 the factor
+// sin(t/2)/t is its Taylor series 1/2 - t^2/48 + t^4/3840.
+__host__ __device__ inline void qexp(const double* u, double* out) {
+  const double t = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  const double s = t < 1e-4 ? 0.5 - t * t / 48.0 + t * t * t * t / 3840.0 : sin(0.5 * t) / t;
+  out[0] = cos(0.5 * t);
+  out[1] = s * u[0];
+  out[2] = s * u[1];
+  out[3] = s * u[2];
+}
+
+// R x and R^T x for a row-major 3x3 R.
+__host__ __device__ inline void matvec3(const double* R, const double* x, double* y) {
+  y[0] = R[0] * x[0] + R[1] * x[1] + R[2] * x[2];
+  y[1] = R[3] * x[0] + R[4] * x[1] + R[5] * x[2];
+  y[2] = R[6] * x[0] + R[7] * x[1] + R[8] * x[2];
+}
+__host__ __device__ inline void matTvec3(const double* R, const double* x, double* y) {
+  y[0] = R[0] * x[0] + R[3] * x[1] + R[6] * x[2];
+  y[1] = R[1] * x[0] + R[4] * x[1] + R[7] * x[2];
+  y[2] = R[2] * x[0] + R[5] * x[1] + R[8] * x[2];
+}
+__host__ __device__ inline void cross3(const double* a, const double* b, double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// ------------------------------------------------------------ grid geometry
+
+// Everything a grid kernel needs about the periodic box and the envelope.
+struct GridGeom {
+  int n[3];
+  int n2h;            // n[2] / 2: stored k2 modes (the Nyquist plane is dropped)
+  long long G;        // n0 n1 n2
+  double L[3], dx[3], inv_dx[3];
+  double dV;
+  double eta;
+  double sigma, rc, rc2;
+  double inv2s2;      // 1 / (2 sigma^2)
+  double wnorm;       // (2 pi sigma^2)^(-3/2)
+  int P[3];           // stencil points per axis: floor(2 rc / dx) + 1
+};
+
+// Device tables of a suspension's bodies (see BodyHost for the meaning).
+struct BodyTables {
+  int N, M, n_shapes;
+  const int* body_shape;      // N
+  const int* body_off;        // N + 1: first blob of each body
+  const int* blob_body;       // M
+  const int* blob_local;      // M: index of the blob within its shape
+  const double* shape_b;      // sum_s n_b(s) x 3, body frame
+  const int* shape_boff;      // n_shapes + 1
+  const double* shape_pinv;   // n_shapes x 36: body-frame (K^T K)^+
+  const double* shape_null;   // n_shapes x 36: body-frame projector onto null(K)
+  const double* shape_Lp;     // n_shapes: max blob-blob distance (or a)
+  const double* shape_precT;  // concatenated transposed preconditioner inverses
+  const long long* shape_prec_off;  // n_shapes
+};
+
+// ------------------------------------------------------------ launchers
+
+// FFT / projection / noise (fft.hip).  The three grid buffers hold 3 G values
+// of R each; `real` is the real-space field (spread output in, velocity out),
+// X and Y are the two transposed half-spectrum layouts.
+template <typename R>
+int stokes_solve(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, Cx<R>* Y,
+                 hipStream_t s);
+template <typename R>
+int fluct_field(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, Cx<R>* Y,
+                uint64_t seed, uint64_t step, double kT, double dt, hipStream_t s);
+bool fft_size_supported(int n);
+int philox_normals_dev(uint64_t seed, uint32_t c1, uint64_t step, uint32_t c0_begin, int count,
+                       double* out_dev, hipStream_t s);
+
+// Grid <-> blob transfer (grid.hip).
+template <typename R>
+int spread(const GridGeom& g, const double* r, const double* lam, R* f, int M, hipStream_t s);
+template <typename R>
+int interp(const GridGeom& g, const double* r, const R* u, double* v, int M, double scale,
+           hipStream_t s);
+// v (M x 3) and the NP differences J(r + dr_k) u - J(r) u into vd (M x NP x 3),
+// dr given per blob as M x NP x 3.
+template <typename R>
+int interp_fd(const GridGeom& g, const double* r, const double* dr, int NP, const R* u,
+              double* v, double* vd, int M, hipStream_t s);
+int fill_zero(void* p, size_t bytes, hipStream_t s);
+int widen(const float* x, double* y, long long n, hipStream_t s);
+
+// Body kernels (body.hip).
+int blob_positions(const BodyTables& b, const double* Y, const double* q, double* r,
+                   hipStream_t s);
+// out_lam = J-part already written; out_lam -= K V; out_V = -K^T lam - Pi V
+int saddle_rigid_terms(const BodyTables& b, const double* Y, const double* q, const double* r,
+                       const double* lam, const double* V, double* out_lam, double* out_V,
+                       hipStream_t s);
+int precond_apply(const BodyTables& b, const double* q, const double* x, double* y, int maxdim,
+                  hipStream_t s);
+// FD / RFD perturbations: displacements of each blob (M x NP x 3) and, for
+// RFD, the Philox normals of each body (N x 6).
+int fd_displacements(const BodyTables& b, const double* q, double delta, int mode,
+                     uint64_t seed, uint64_t step, double* dr, double* wrfd, hipStream_t s);
+int body_lsq_div(const BodyTables& b, const double* q, const double* v, const double* vd,
+                 const double* wrfd, double delta, int mode, double* calV, double* d,
+                 hipStream_t s);
+int nu_reduce(const double* d, int N, double half_dt, double* nu, hipStream_t s);
+int midpoint(const BodyTables& b, const double* Y, const double* q, const double* calV,
+             double h, double* Ym, double* qm, hipStream_t s);
+int update(const BodyTables& b, double* Y, double* q, const double* V, const double* nu,
+           double dt, hipStream_t s);
+int rhs_build(const BodyTables& b, const double* q, const double* Y, const double* r,
+              const double* vslip, const double* F, double shear, double Ly, double* rhs,
+              hipStream_t s);
+int steric_forces(const BodyTables& b, const GridGeom& g, const double* r, double k,
+                  double cutoff, int* cell_count, int* cell_list, int cap, const int nc[3],
+                  int* overflow, double* fblob, hipStream_t s);
+int body_forces(const BodyTables& b, const double* Y, const double* r, const double* fblob,
+                const double* cforce, double* F, hipStream_t s);
+int check_finite(const double* x, long long n, int* flag, hipStream_t s);
+
+// Krylov vector kernels (solver.hip).
+int multi_dot(const double* V, long long ld, int k, const double* w, long long n, double* partial,
+              int nblk, double* h, hipStream_t s);
+int multi_axpy(double* w, const double* V, long long ld, int k, const double* h, double sign,
+               long long n, hipStream_t s);
+int scale_by_inv_sqrt(const double* w, const double* nrm2, double* out, long long n,
+                      hipStream_t s);
+int copy_scaled(const double* x, double a, double* y, long long n, hipStream_t s);
+int sub_from(const double* b, double* w, long long n, hipStream_t s);   // w = b - w
+
+}  // namespace gdc

@@ -241,3 +241,13 @@ def initial_state(w: Workload, min_dist=2.0 * A, max_tries=2000):
             xw = x - L * np.floor(x / L)
             bins.setdefault(key(xw), []).append(xw)
     return Y, Q
+
+
+def library_kwargs(w: Workload, **over):
+    """Keyword arguments of paper_2106_00449_amd.Suspension for a workload."""
+    kw = dict(L=w.L, n=w.n, shapes=w.shapes, body_shape=w.body_shape, a=w.a, sigma=w.sigma,
+              trunc=w.rc, eta=w.eta, kT=w.kT, dt=w.dt, precision=w.precision, seed=w.noise_seed,
+              steric_k=w.steric_k, steric_cutoff=w.steric_cutoff, const_force=w.const_force,
+              shear_rate=w.shear_rate)
+    kw.update(over)
+    return kw
