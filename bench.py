@@ -26,6 +26,21 @@ sys.path.insert(0, ROOT)
 METRIC = "blob-steps/sec of gDC step at 1e-5 rel mobility error; p50/p99 step latency"
 HBM_PEAK_GBS = 8000.0
 
+# Dominant kernel of the step (largest share of GPU time in the kernel-trace
+# summary): Gaussian spreading S lambda.  Its algorithmic traffic per launch is
+# the FP32 force field written once (3 components x 4 B per grid point) plus,
+# per blob, its sorted stencil record (32 B) and its force (3 x 8 B).
+DOMINANT = "spread"
+BYTES_PER_POINT = 12
+BYTES_PER_BLOB = 56
+
+# HBM traffic of the dominant kernel from two rocprofv3 --pmc runs of this
+# script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, averaged over the
+# spreading dispatches), each divided by the same counter's reading for the
+# 256 MiB copy that --copy-calibration adds, over 256 MiB.  None until taken
+# for the current kernel.
+TRAFFIC_BYTES = None
+
 
 def calibrate(g, wl, w, Y0, q0, target=1e-5):
     import numpy as np
@@ -72,6 +87,8 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 256 MiB device copy first (counter calibration for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -82,6 +99,13 @@ def main():
     import torch
     import paper_2106_00449_amd as g
     import workloads as wl
+
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     w = wl.rods1000("fp32")
     Y0, q0 = wl.initial_state(w)
@@ -94,6 +118,7 @@ def main():
     for _ in range(args.warmup):
         s.step(Y, q, 1)
     torch.cuda.synchronize()
+    g.probe_kernel(DOMINANT)
     lat, its, nus = [], [], []
     t_start = time.perf_counter()
     for _ in range(args.steps):
@@ -104,8 +129,18 @@ def main():
         nus.append(st["nu"])
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
+    k_ms, k_launches = g.probe_read()
+    g.probe_kernel(None)
     value = w.M * args.steps / total
     lat_ms = np.array(lat) * 1e3
+    G = int(np.prod(w.n))
+    alg_bytes = BYTES_PER_POINT * G + BYTES_PER_BLOB * w.M
+    avg_s = k_ms * 1e-3 / max(k_launches, 1)
+    achieved = alg_bytes / avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES,
+                "kernel": "k_spread_gather", "launches": k_launches, "avg_us": avg_s * 1e6,
+                "algorithmic_bytes": alg_bytes}
 
     out = {
         "metric": METRIC, "value": value, "unit": "blob-steps/s", "n_gpus": 1,
@@ -118,6 +153,7 @@ def main():
                    "gmres_iterations_mean": float(np.mean(its)),
                    "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
                    "nu_mean": float(np.mean(nus))},
+        "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, Y0, q0, tol)

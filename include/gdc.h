@@ -185,6 +185,17 @@ int gdc_predictor(gdc_handle* h, const double* Y, const double* q, uint64_t step
 int gdc_philox_normals(gdc_handle* h, uint64_t seed, uint32_t c1, uint64_t step,
                        uint32_t c0_begin, int count, double* out);
 
+/* Measurement helpers (process-wide, not tied to a handle).
+ * gdc_probe_kernel(family): from now on, every launch of the named kernel
+ * family is bracketed by HIP events on the stream it is launched on
+ * ("spread", "interp", "fft_r2c", "fft_fwd1", "fft_project", "fft_inv1",
+ * "fft_c2r", "fft_noise"; NULL or "" switches probing off; at most 8192
+ * launches are kept).  gdc_probe_read: total elapsed milliseconds and number
+ * of probed launches since the last read (waits for the last stop event),
+ * then clears the record. */
+int gdc_probe_kernel(const char* family);
+int gdc_probe_read(double* total_ms, long long* launches);
+
 #ifdef __cplusplus
 }
 #endif

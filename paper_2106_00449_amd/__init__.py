@@ -82,8 +82,11 @@ def _load():
     L.gdc_fluct_velocity.argtypes = [P, U64, P, I]
     L.gdc_predictor.argtypes = [P, P, P, U64, P, P, I]
     L.gdc_philox_normals.argtypes = [P, U64, U32, U64, U32, I, D]
+    L.gdc_probe_kernel.argtypes = [ctypes.c_char_p]
+    L.gdc_probe_read.argtypes = [D, ctypes.POINTER(ctypes.c_longlong)]
     for name in ["gdc_init", "gdc_mobility_apply", "gdc_step", "gdc_get_step", "gdc_set_step",
-                 "gdc_fluct_velocity", "gdc_predictor", "gdc_philox_normals"]:
+                 "gdc_fluct_velocity", "gdc_predictor", "gdc_philox_normals", "gdc_probe_kernel",
+                 "gdc_probe_read"]:
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -130,6 +133,19 @@ def _memspace(*args):
     if len(ms) != 1:
         raise TypeError("mix of host and device arrays in one call")
     return ms.pop()
+
+
+def probe_kernel(family):
+    """Time every later launch of one kernel family with HIP events."""
+    _check(lib.gdc_probe_kernel(family.encode() if family else None))
+
+
+def probe_read():
+    """(total ms, launches) of the probed family since the last read."""
+    ms = ctypes.c_double()
+    n = ctypes.c_longlong()
+    _check(lib.gdc_probe_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 class Suspension:

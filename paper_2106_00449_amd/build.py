@@ -1,6 +1,7 @@
 """Builds libgdc.so (the HIP library for gfx950) in this package directory.
 
-Usage: python -m paper_2106_00449_amd.build   (or build() from Python).
+Usage: python paper_2106_00449_amd/build.py   (or build() from Python; run it
+by path, since importing the package loads the library).
 Each .hip translation unit is compiled by hipcc in parallel, then linked
 into one shared library exporting the C ABI of include/gdc.h.
 """

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -22,6 +23,27 @@ thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+namespace {
+struct Probe {
+  std::string family;
+  std::vector<hipEvent_t> ev;   // pairs: start, stop
+  size_t used = 0;
+  long long dropped = 0;
+};
+Probe g_probe;
+constexpr size_t PROBE_PAIRS = 8192;
+}  // namespace
+
+void probe_record(const char* family, hipStream_t s, bool start) {
+  if (g_probe.family.empty() || g_probe.family != family) return;
+  if (start && g_probe.used + 2 > g_probe.ev.size()) {
+    ++g_probe.dropped;
+    return;
+  }
+  if (!start && (g_probe.used % 2) == 0) return;   // start was dropped
+  if (hipEventRecord(g_probe.ev[g_probe.used], s) == hipSuccess) ++g_probe.used;
+}
+
 int check_launch(const char* what) {
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
@@ -33,7 +55,6 @@ int check_launch(const char* what) {
 
 namespace {
 
-constexpr int DOT_BLOCKS = 512;
 constexpr int HCOLS = 64;       // device scratch per Hessenberg column section
 constexpr double PINV_RCOND = 1e-10;
 
@@ -266,7 +287,14 @@ struct gdc_handle {
   double *F = nullptr, *fblob = nullptr, *cforce = nullptr, *io = nullptr;
   int *cell_count = nullptr, *cell_list = nullptr, *flags = nullptr;
   double *Vb = nullptr, *w = nullptr, *z = nullptr, *xacc = nullptr, *rhs = nullptr, *sol = nullptr;
-  double *hdev = nullptr, *partial = nullptr;
+  double *hdev = nullptr, *partial = nullptr, *partial2 = nullptr;
+  unsigned int* dot_counter = nullptr;
+  TileGeom tg{};
+  int *tile_ids = nullptr, *tile_count = nullptr, *tile_off = nullptr, *tile_cursor = nullptr;
+  double* trec = nullptr;
+  int* spos = nullptr;
+  double* zsorted = nullptr;
+  bool interp_by_tiles = false;  // GDC_INTERP=tiles selects the tiled averaging
   double* hhost = nullptr;   // pinned readback
 
   ~gdc_handle() {
@@ -323,23 +351,34 @@ const Cx<R>* const* tw_of(gdc_handle* h) {
   return reinterpret_cast<const Cx<R>* const*>(h->tw);
 }
 
-// v = M_FCM lam at blob positions r (all device, FP64 at the ends).
-template <typename R>
-int apply_mobility(gdc_handle* h, const double* r, const double* lam, double* out) {
-  const GridGeom& g = h->geom;
-  R* f = (R*)h->grid[0];
-  GDC_TRY(fill_zero(f, 3 * (size_t)g.G * sizeof(R), h->stream));
-  GDC_TRY(spread<R>(g, r, lam, f, h->M, h->stream));
-  GDC_TRY(stokes_solve<R>(g, tw_of<R>(h), f, (Cx<R>*)h->grid[1], (Cx<R>*)h->grid[2], h->stream));
-  return interp<R>(g, r, f, out, h->M, g.dV, h->stream);
+// Sorts the blobs at positions r by grid tile; every spread at r needs it.
+int prepare_positions(gdc_handle* h, const double* r) {
+  return tile_sort(h->geom, h->tg, r, h->M, h->tile_ids, h->tile_count, h->tile_off, h->tile_cursor, h->trec,
+                   h->spos, h->stream);
 }
 
-// y = [[M, -K], [-K^T, -Pi]] x at (Y, q, r).
+// out = M_FCM lam at blob positions r (prepared by prepare_positions), minus
+// U_p + Omega_p x (r_i - Y_p) when V (N x 6) is given.
 template <typename R>
-int apply_saddle(gdc_handle* h, const double* Y, const double* q, const double* r, const double* x, double* y) {
+int apply_mobility(gdc_handle* h, const double* r, const double* lam, double* out, const double* Y = nullptr,
+                   const double* V = nullptr, const double* lam_sorted = nullptr) {
+  const GridGeom& g = h->geom;
+  R* f = (R*)h->grid[0];
+  GDC_TRY(spread<R>(g, h->tg, h->trec, lam, lam_sorted, h->tile_off, f, h->stream));
+  GDC_TRY(stokes_solve<R>(g, tw_of<R>(h), f, (Cx<R>*)h->grid[1], (Cx<R>*)h->grid[2], h->stream));
+  if (h->interp_by_tiles)
+    return interp_tiles<R>(g, h->tg, h->trec, h->tile_off, r, f, out, h->M, g.dV, h->bt.blob_body, Y, V,
+                           h->stream);
+  return interp<R>(g, r, f, out, h->M, g.dV, h->bt.blob_body, Y, V, h->stream);
+}
+
+// z = P^-1 x and y = A z, A = [[M, -K], [-K^T, -Pi]] at (Y, q, r).
+template <typename R>
+int apply_saddle_precond(gdc_handle* h, const double* Y, const double* q, const double* r, const double* x,
+                         double* z, double* y) {
   const long long m3 = 3LL * h->M;
-  GDC_TRY(apply_mobility<R>(h, r, x, y));
-  return saddle_rigid_terms(h->bt, Y, q, r, x, x + m3, y, y + m3, h->stream);
+  GDC_TRY(precond_apply(h->bt, q, x, z, y + m3, h->spos, h->zsorted, h->maxdim, h->stream));
+  return apply_mobility<R>(h, r, z, y, Y, z + m3, h->zsorted);
 }
 
 struct GmresResult {
@@ -358,7 +397,7 @@ int gmres(gdc_handle* h, const double* Y, const double* q, const double* r, Gmre
   hipStream_t s = h->stream;
   double* hh = h->hhost;
   // |b|
-  GDC_TRY(multi_dot(h->rhs, n, 1, h->rhs, n, h->partial, DOT_BLOCKS, h->hdev, s));
+  GDC_TRY(multi_dot(nullptr, n, 0, h->rhs, n, true, h->partial, h->dot_counter, h->hdev, s));
   GDC_HIP(hipMemcpyAsync(hh, h->hdev, sizeof(double), hipMemcpyDeviceToHost, s));
   GDC_HIP(hipStreamSynchronize(s));
   const double nb = std::sqrt(hh[0]);
@@ -379,12 +418,11 @@ int gmres(gdc_handle* h, const double* Y, const double* q, const double* r, Gmre
       GDC_TRY(copy_scaled(h->rhs, 1.0, h->w, n, s));
     } else {
       // w = b - A P^-1 xacc
-      GDC_TRY(precond_apply(h->bt, q, h->xacc, h->z, h->maxdim, s));
-      GDC_TRY(apply_saddle<R>(h, Y, q, r, h->z, h->w));
+      GDC_TRY(apply_saddle_precond<R>(h, Y, q, r, h->xacc, h->z, h->w));
       GDC_TRY(sub_from(h->rhs, h->w, n, s));
     }
     first = false;
-    GDC_TRY(multi_dot(h->w, n, 1, h->w, n, h->partial, DOT_BLOCKS, h->hdev + 2 * HCOLS, s));
+    GDC_TRY(multi_dot(nullptr, n, 0, h->w, n, true, h->partial, h->dot_counter, h->hdev + 2 * HCOLS, s));
     GDC_HIP(hipMemcpyAsync(hh, h->hdev + 2 * HCOLS, sizeof(double), hipMemcpyDeviceToHost, s));
     GDC_HIP(hipStreamSynchronize(s));
     const double beta = std::sqrt(hh[0]);
@@ -400,21 +438,18 @@ int gmres(gdc_handle* h, const double* Y, const double* q, const double* r, Gmre
     for (int k = 0; k < m; ++k) {
       double* Vk = h->Vb + n * k;
       double* Vk1 = h->Vb + n * (k + 1);
-      GDC_TRY(precond_apply(h->bt, q, Vk, h->z, h->maxdim, s));
-      GDC_TRY(apply_saddle<R>(h, Y, q, r, h->z, h->w));
+      GDC_TRY(apply_saddle_precond<R>(h, Y, q, r, Vk, h->z, h->w));
       double* h1 = h->hdev;
       double* h2 = h->hdev + HCOLS;
-      double* nr = h->hdev + 2 * HCOLS;
-      GDC_TRY(multi_dot(h->Vb, n, k + 1, h->w, n, h->partial, DOT_BLOCKS, h1, s));
-      GDC_TRY(multi_axpy(h->w, h->Vb, n, k + 1, h1, -1.0, n, s));
-      GDC_TRY(multi_dot(h->Vb, n, k + 1, h->w, n, h->partial, DOT_BLOCKS, h2, s));
-      GDC_TRY(multi_axpy(h->w, h->Vb, n, k + 1, h2, -1.0, n, s));
-      GDC_TRY(multi_dot(h->w, n, 1, h->w, n, h->partial, DOT_BLOCKS, nr, s));
-      GDC_TRY(scale_by_inv_sqrt(h->w, nr, Vk1, n, s));
-      GDC_HIP(hipMemcpyAsync(hh, h->hdev, 3 * HCOLS * sizeof(double), hipMemcpyDeviceToHost, s));
+      GDC_TRY(arnoldi_orthogonalise(h->w, h->Vb, n, k + 1, n, h->partial, h->partial2, Vk1, h1, h2, s));
+      GDC_HIP(hipMemcpyAsync(hh, h->hdev, 2 * HCOLS * sizeof(double), hipMemcpyDeviceToHost, s));
       GDC_HIP(hipStreamSynchronize(s));
-      for (int j = 0; j <= k; ++j) H[j * m + k] = hh[j] + hh[HCOLS + j];
-      H[(k + 1) * m + k] = std::sqrt(hh[2 * HCOLS]);
+      double h2sq = 0.0;
+      for (int j = 0; j <= k; ++j) {
+        H[j * m + k] = hh[j] + hh[HCOLS + j];
+        h2sq += hh[HCOLS + j] * hh[HCOLS + j];
+      }
+      H[(k + 1) * m + k] = std::sqrt(std::max(0.0, hh[HCOLS + k + 1] - h2sq));
       for (int j = 0; j < k; ++j) {
         const double t = cs[j] * H[j * m + k] + sn[j] * H[(j + 1) * m + k];
         H[(j + 1) * m + k] = -sn[j] * H[j * m + k] + cs[j] * H[(j + 1) * m + k];
@@ -447,7 +482,7 @@ int gmres(gdc_handle* h, const double* Y, const double* q, const double* r, Gmre
     }
     if (its >= h->maxit) break;
   }
-  GDC_TRY(precond_apply(h->bt, q, h->xacc, h->sol, h->maxdim, s));
+  GDC_TRY(precond_apply(h->bt, q, h->xacc, h->sol, nullptr, nullptr, nullptr, h->maxdim, s));
   res.its = its;
   res.relres = est;
   res.converged = converged;
@@ -502,7 +537,8 @@ int one_step(gdc_handle* h, GmresResult& gr, double& nu_out) {
   }
   GDC_TRY(blob_positions(h->bt, Ym, qm, h->rm, s));
   GDC_TRY(forces_at(h, Ym, h->rm));
-  GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_fl, h->v, h->M, h->geom.dV, s));
+  GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_fl, h->v, h->M, h->geom.dV, nullptr, nullptr, nullptr, s));
+  GDC_TRY(prepare_positions(h, h->rm));
   GDC_TRY(rhs_build(h->bt, qm, Ym, h->rm, h->v, h->F, h->cfg.forces.shear_rate, h->geom.L[1], h->rhs, s));
   GDC_TRY(gmres<R>(h, Ym, qm, h->rm, gr));
   const bool gdc_scheme = h->cfg.scheme == GDC_SCHEME_GDC;
@@ -615,6 +651,10 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
   if (c.gmres_tol == 0.0) c.gmres_tol = 1e-6;
   if (c.gmres_maxit == 0) c.gmres_maxit = 200;
   if (c.gmres_restart == 0) c.gmres_restart = 50;
+  {
+    const char* e = std::getenv("GDC_INTERP");
+    h->interp_by_tiles = (e && std::string(e) == "tiles");
+  }
   h->tol = c.gmres_tol;
   h->maxit = c.gmres_maxit;
   h->restart = c.gmres_restart;
@@ -781,7 +821,36 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
   GDC_TRY(h->alloc(&h->rhs, nx));
   GDC_TRY(h->alloc(&h->sol, nx + 2));
   GDC_TRY(h->alloc(&h->hdev, 5 * HCOLS));
-  GDC_TRY(h->alloc(&h->partial, (size_t)DOT_BLOCKS * HCOLS));
+  GDC_TRY(h->alloc(&h->partial, std::max((size_t)DOT_MAX_BLOCKS, (size_t)(h->nx / 1024 + 1)) * HCOLS));
+  GDC_TRY(h->alloc(&h->partial2, (size_t)(h->nx / 1024 + 1) * HCOLS));
+  GDC_TRY(h->alloc(&h->dot_counter, 4));
+  GDC_HIP(hipMemset(h->dot_counter, 0, 4 * sizeof(unsigned int)));
+  {
+    TileGeom& t = h->tg;
+    const int Tdef[3] = {8, 8, 32};
+    t.ntiles = 1;
+    for (int d = 0; d < 3; ++d) {
+      t.T[d] = std::min(Tdef[d], g.n[d]);
+      t.nt[d] = (g.n[d] + t.T[d] - 1) / t.T[d];
+      const int reach = (int)std::ceil(c.trunc / g.dx[d]) + 1;
+      t.H[d] = (reach + t.T[d] - 1) / t.T[d];
+      if (t.H[d] > 2) {
+        set_error("the envelope cutoff spans too many grid points for the spreading tiles");
+        return GDC_EINVAL;
+      }
+      t.ntiles *= t.nt[d];
+    }
+    const int cols = std::min(t.T[1], g.P[1]) * std::min(t.T[2], g.P[2]);
+    t.S = 1;
+    while (t.S < cols) t.S *= 2;
+    GDC_TRY(h->alloc(&h->tile_ids, (size_t)h->M));
+    GDC_TRY(h->alloc(&h->trec, 2 * (size_t)h->M * tile_record_bytes() / sizeof(double)));
+    GDC_TRY(h->alloc(&h->spos, (size_t)h->M));
+    GDC_TRY(h->alloc(&h->zsorted, 3 * (size_t)h->M));
+    GDC_TRY(h->alloc(&h->tile_count, (size_t)(t.ntiles + 4)));
+    GDC_TRY(h->alloc(&h->tile_off, (size_t)(t.ntiles + 1)));
+    GDC_TRY(h->alloc(&h->tile_cursor, (size_t)t.ntiles));
+  }
   GDC_HIP(hipHostMalloc((void**)&h->hhost, 5 * HCOLS * sizeof(double), hipHostMallocDefault));
 
   if (h->precision == GDC_FP64) {
@@ -849,6 +918,7 @@ int gdc_mobility_apply(gdc_handle* h, int mode, const double* Y, const double* q
   gr.converged = true;
   if (mode == GDC_BLOB) {
     GDC_TRY(copy_in(h, h->io, in, 3 * (size_t)h->M, memspace));
+    GDC_TRY(prepare_positions(h, h->r));
     if (h->precision == GDC_FP64) {
       GDC_TRY(apply_mobility<double>(h, h->r, h->io, h->v));
     } else {
@@ -859,6 +929,7 @@ int gdc_mobility_apply(gdc_handle* h, int mode, const double* Y, const double* q
   } else {
     GDC_TRY(copy_in(h, h->io, in, 6 * (size_t)h->N, memspace));
     GDC_TRY(rhs_build(h->bt, h->q, h->Y, h->r, nullptr, h->io, 0.0, h->geom.L[1], h->rhs, s));
+    GDC_TRY(prepare_positions(h, h->r));
     if (h->precision == GDC_FP64) {
       GDC_TRY(gmres<double>(h, h->Y, h->q, h->r, gr));
     } else {
@@ -932,6 +1003,36 @@ int gdc_step(gdc_handle* h, int n_steps, double* Y, double* q, int memspace, gdc
     set_error("GMRES did not reach the tolerance in at least one step");
     return GDC_ENOTCONV;
   }
+  return GDC_OK;
+}
+
+int gdc_probe_kernel(const char* family) {
+  for (hipEvent_t e : g_probe.ev) (void)hipEventDestroy(e);
+  g_probe = Probe{};
+  if (!family || !family[0]) return GDC_OK;
+  g_probe.ev.resize(2 * PROBE_PAIRS);
+  for (auto& e : g_probe.ev) GDC_HIP(hipEventCreate(&e));
+  g_probe.family = family;
+  return GDC_OK;
+}
+
+int gdc_probe_read(double* total_ms, long long* launches) {
+  if (!total_ms || !launches) {
+    set_error("outputs are required");
+    return GDC_EINVAL;
+  }
+  double tot = 0.0;
+  long long n = 0;
+  for (size_t k = 0; k + 1 < g_probe.used; k += 2) {
+    GDC_HIP(hipEventSynchronize(g_probe.ev[k + 1]));
+    float ms = 0.f;
+    GDC_HIP(hipEventElapsedTime(&ms, g_probe.ev[k], g_probe.ev[k + 1]));
+    tot += ms;
+    ++n;
+  }
+  *total_ms = tot;
+  *launches = n;
+  g_probe.used = 0;
   return GDC_OK;
 }
 

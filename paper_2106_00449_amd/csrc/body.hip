@@ -56,48 +56,17 @@ __global__ void k_blob_positions(BodyTables B, const double* __restrict__ Y, con
   r[3LL * i + 2] = Y[3LL * p + 2] + x[2];
 }
 
-// ------------------------------------------------------------ saddle operator terms
-// out_lam_i -= U_p + Omega_p x (r_i - Y_p);  out_V_p = -K_p^T lam - Pi_p V_p.
-__global__ void k_saddle_rigid(BodyTables B, const double* __restrict__ Y, const double* __restrict__ q,
-                               const double* __restrict__ r, const double* __restrict__ lam,
-                               const double* __restrict__ V, double* __restrict__ out_lam,
-                               double* __restrict__ out_V) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= B.N) return;
-  const int s = B.body_shape[p];
-  double Vp[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) Vp[k] = V[6LL * p + k];
-  double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
-  for (int i = B.body_off[p]; i < B.body_off[p + 1]; ++i) {
-    double rel[3] = {r[3LL * i] - Y[3LL * p], r[3LL * i + 1] - Y[3LL * p + 1], r[3LL * i + 2] - Y[3LL * p + 2]};
-    double w[3], l[3], t[3];
-    cross3(Vp + 3, rel, w);
-    out_lam[3LL * i] -= Vp[0] + w[0];
-    out_lam[3LL * i + 1] -= Vp[1] + w[1];
-    out_lam[3LL * i + 2] -= Vp[2] + w[2];
-    load3(lam + 3LL * i, l);
-    cross3(rel, l, t);
-    F[0] += l[0]; F[1] += l[1]; F[2] += l[2];
-    T[0] += t[0]; T[1] += t[1]; T[2] += t[2];
-  }
-  double R[9], pv[6];
-  rotmat(q + 4LL * p, R);
-  rotate_6x6(B.shape_null + 36LL * s, R, Vp, pv);
-  out_V[6LL * p] = -F[0] - pv[0];
-  out_V[6LL * p + 1] = -F[1] - pv[1];
-  out_V[6LL * p + 2] = -F[2] - pv[2];
-  out_V[6LL * p + 3] = -T[0] - pv[3];
-  out_V[6LL * p + 4] = -T[1] - pv[4];
-  out_V[6LL * p + 5] = -T[2] - pv[5];
-}
-
 // ------------------------------------------------------------ block preconditioner
-// One wavefront per body: gather (lambda_i, V_p), rotate to the body frame,
-// multiply by the shape's dense inverse (stored transposed, so lanes read
-// consecutive entries), rotate back.
+// One wavefront per body: gather (x_i for its blobs, x_V), rotate to the body
+// frame, multiply by the shape's dense inverse of [[M_RPY, -K], [-K^T, -Pi]]
+// (stored transposed, so lanes read consecutive entries), rotate back.  When
+// yV is given the same kernel also forms the body rows of the saddle operator
+// at z = P^-1 x, yV = -K^T z_lam - Pi z_V, in the body frame (K, Pi are
+// rotation covariant) before rotating them to the lab frame.
 __global__ __launch_bounds__(64) void k_precond(BodyTables B, const double* __restrict__ q,
-                                                const double* __restrict__ x, double* __restrict__ y) {
+                                                const double* __restrict__ x, double* __restrict__ z,
+                                                double* __restrict__ yV, const int* __restrict__ spos,
+                                                double* __restrict__ zs) {
   extern __shared__ double sh[];
   const int p = blockIdx.x;
   const int lane = threadIdx.x;
@@ -106,6 +75,7 @@ __global__ __launch_bounds__(64) void k_precond(BodyTables B, const double* __re
   const int D = 3 * nb + 6;
   double* xb = sh;
   double* yb = sh + D;
+  double* tb = sh + 2 * D;
   double R[9];
   rotmat(q + 4LL * p, R);
   const long long Mx3 = 3LL * B.M;
@@ -127,9 +97,43 @@ __global__ __launch_bounds__(64) void k_precond(BodyTables B, const double* __re
   }
   __syncthreads();
   for (int k = lane; k < nb + 2; k += 64) {
-    double* dst = k < nb ? y + 3LL * (off + k) : y + Mx3 + 6LL * p + 3 * (k - nb);
+    double* dst = k < nb ? z + 3LL * (off + k) : z + Mx3 + 6LL * p + 3 * (k - nb);
     double v[3] = {yb[3 * k], yb[3 * k + 1], yb[3 * k + 2]}, w[3];
     matvec3(R, v, w);
+    dst[0] = w[0];
+    dst[1] = w[1];
+    dst[2] = w[2];
+    if (zs && k < nb) {
+      double* d2 = zs + 3LL * spos[off + k];
+      d2[0] = w[0];
+      d2[1] = w[1];
+      d2[2] = w[2];
+    }
+  }
+  if (!yV) return;
+  if (lane < 6) {
+    double t = 0.0;
+    const double* bb = B.shape_b + 3LL * B.shape_boff[s];
+    for (int i = 0; i < nb; ++i) {
+      const double* zi = yb + 3 * i;
+      if (lane < 3) {
+        t += zi[lane];
+      } else {
+        const double* bi = bb + 3 * i;
+        const int c = lane - 3, c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        t += bi[c1] * zi[c2] - bi[c2] * zi[c1];
+      }
+    }
+    const double* Pi = B.shape_null + 36LL * s + 6 * lane;
+    double pz = 0.0;
+    for (int j = 0; j < 6; ++j) pz += Pi[j] * yb[3 * nb + j];
+    tb[lane] = -t - pz;
+  }
+  __syncthreads();
+  if (lane < 2) {
+    double w[3];
+    matvec3(R, tb + 3 * lane, w);
+    double* dst = yV + 6LL * p + 3 * lane;
     dst[0] = w[0];
     dst[1] = w[1];
     dst[2] = w[2];
@@ -459,15 +463,10 @@ int blob_positions(const BodyTables& b, const double* Y, const double* q, double
   return check_launch("k_blob_positions");
 }
 
-int saddle_rigid_terms(const BodyTables& b, const double* Y, const double* q, const double* r,
-                       const double* lam, const double* V, double* out_lam, double* out_V, hipStream_t s) {
-  hipLaunchKernelGGL(k_saddle_rigid, dim3(nblk(b.N, 128)), dim3(128), 0, s, b, Y, q, r, lam, V, out_lam, out_V);
-  return check_launch("k_saddle_rigid");
-}
-
-int precond_apply(const BodyTables& b, const double* q, const double* x, double* y, int maxdim, hipStream_t s) {
-  const size_t shm = 2 * (size_t)maxdim * sizeof(double);
-  hipLaunchKernelGGL(k_precond, dim3(b.N), dim3(64), shm, s, b, q, x, y);
+int precond_apply(const BodyTables& b, const double* q, const double* x, double* z, double* yV, const int* spos,
+                  double* zs, int maxdim, hipStream_t s) {
+  const size_t shm = (2 * (size_t)maxdim + 8) * sizeof(double);
+  hipLaunchKernelGGL(k_precond, dim3(b.N), dim3(64), shm, s, b, q, x, z, yV, spos, zs);
   return check_launch("k_precond");
 }
 

@@ -432,6 +432,7 @@ __global__ __launch_bounds__(NT) void k_axis0_project(Cx<R>* __restrict__ Y, con
 template <typename R>
 int launch_r2c(int n2, const R* in, Cx<R>* X, const Cx<R>* tw, int n0, int n1, hipStream_t s) {
   dim3 grid((n1 + Tiles<R>::TL - 1) / Tiles<R>::TL, n0, 3);
+  ProbeScope ps("fft_r2c", s);
   switch (n2) {
 #define X_(N) case N: hipLaunchKernelGGL((k_r2c_axis2<R, N>), grid, dim3(NT), 0, s, in, X, tw, n0, n1); break;
     GDC_FFT_SIZES(X_)
@@ -444,6 +445,7 @@ int launch_r2c(int n2, const R* in, Cx<R>* X, const Cx<R>* tw, int n0, int n1, h
 template <typename R>
 int launch_fwd1(int n1, const Cx<R>* X, Cx<R>* Y, const Cx<R>* tw, int n0, int H, hipStream_t s) {
   dim3 grid((n0 + Tiles<R>::TL - 1) / Tiles<R>::TL, H, 3);
+  ProbeScope ps("fft_fwd1", s);
   switch (n1) {
 #define X_(N) case N: hipLaunchKernelGGL((k_fwd_axis1<R, N>), grid, dim3(NT), 0, s, X, Y, tw, n0, H); break;
     GDC_FFT_SIZES(X_)
@@ -456,6 +458,7 @@ int launch_fwd1(int n1, const Cx<R>* X, Cx<R>* Y, const Cx<R>* tw, int n0, int H
 template <typename R>
 int launch_inv1(int n1, const Cx<R>* Y, Cx<R>* X, const Cx<R>* tw, int n0, int H, hipStream_t s) {
   dim3 grid((n0 + Tiles<R>::TL - 1) / Tiles<R>::TL, H, 3);
+  ProbeScope ps("fft_inv1", s);
   switch (n1) {
 #define X_(N) case N: hipLaunchKernelGGL((k_inv_axis1<R, N>), grid, dim3(NT), 0, s, Y, X, tw, n0, H); break;
     GDC_FFT_SIZES(X_)
@@ -468,6 +471,7 @@ int launch_inv1(int n1, const Cx<R>* Y, Cx<R>* X, const Cx<R>* tw, int n0, int H
 template <typename R>
 int launch_c2r(int n2, const Cx<R>* X, R* out, const Cx<R>* tw, int n0, int n1, hipStream_t s) {
   dim3 grid((n1 + Tiles<R>::TL - 1) / Tiles<R>::TL, n0, 3);
+  ProbeScope ps("fft_c2r", s);
   switch (n2) {
 #define X_(N) case N: hipLaunchKernelGGL((k_c2r_axis2<R, N>), grid, dim3(NT), 0, s, X, out, tw, n0, n1); break;
     GDC_FFT_SIZES(X_)
@@ -480,6 +484,7 @@ int launch_c2r(int n2, const Cx<R>* X, R* out, const Cx<R>* tw, int n0, int n1, 
 template <typename R, bool NOISE>
 int launch_proj(int n0, Cx<R>* Y, const Cx<R>* tw, const ProjParams& P, hipStream_t s) {
   dim3 grid((P.n1 + Tiles<R>::TC - 1) / Tiles<R>::TC, P.n2h, 1);
+  ProbeScope ps(NOISE ? "fft_noise" : "fft_project", s);
   switch (n0) {
 #define X_(N) case N: hipLaunchKernelGGL((k_axis0_project<R, N, NOISE>), grid, dim3(NT), 0, s, Y, tw, P); break;
     GDC_FFT_SIZES(X_)

@@ -41,6 +41,17 @@ struct Status {
 // Checks the launch of the kernel just issued.
 int check_launch(const char* what);
 
+// Optional timing of one kernel family with HIP events on the stream it is
+// launched on (enabled by gdc_probe_kernel): a ProbeScope around a launch
+// records a start and a stop event when the family is the probed one.
+void probe_record(const char* family, hipStream_t s, bool start);
+struct ProbeScope {
+  const char* family;
+  hipStream_t stream;
+  ProbeScope(const char* f, hipStream_t s) : family(f), stream(s) { probe_record(family, stream, true); }
+  ~ProbeScope() { probe_record(family, stream, false); }
+};
+
 // ------------------------------------------------------------ complex values
 
 template <typename R>
@@ -126,6 +137,17 @@ struct GridGeom {
   int P[3];           // stencil points per axis: floor(2 rc / dx) + 1
 };
 
+// Tiling of the grid for the spreading kernel: tiles of T[0] x T[1] x T[2]
+// points (the last tile along an axis may be partial), nt[d] tiles per axis,
+// and H[d] neighbour tiles per side whose anchored blobs can reach a tile.
+struct TileGeom {
+  int T[3];
+  int nt[3];
+  int H[3];
+  int ntiles;
+  int S;       // work-item slots per blob: a power of two >= min(T1, P1) min(T2, P2)
+};
+
 // Device tables of a suspension's bodies (see BodyHost for the meaning).
 struct BodyTables {
   int N, M, n_shapes;
@@ -158,11 +180,29 @@ int philox_normals_dev(uint64_t seed, uint32_t c1, uint64_t step, uint32_t c0_be
                        double* out_dev, hipStream_t s);
 
 // Grid <-> blob transfer (grid.hip).
+// Counting sort of blobs by the tile of their anchor point; off has
+// ntiles + 1 entries and rec (2 M records of tile_record_bytes(); the second
+// half is scratch) holds in its first half each blob's stencil origin, tile
+// by tile, in blob order within a tile.
+size_t tile_record_bytes();
+// spos[i] is blob i's position in the sorted order.
+int tile_sort(const GridGeom& g, const TileGeom& t, const double* r, int M, int* tile, int* count, int* off,
+              int* cursor, void* rec, int* spos, hipStream_t s);
+// f = S lam on every grid point (the whole field is written).  lam_sorted,
+// when given, holds lam in the sorted order (3 x M) and is read instead.
 template <typename R>
-int spread(const GridGeom& g, const double* r, const double* lam, R* f, int M, hipStream_t s);
+int spread(const GridGeom& g, const TileGeom& t, const void* rec, const double* lam, const double* lam_sorted,
+           const int* off, R* f, hipStream_t s);
+// Tiled averaging at the positions of the last tile_sort: v = scale J u,
+// minus U_p + Omega_p x (r_i - Y_p) when V (N x 6) is given.
+template <typename R>
+int interp_tiles(const GridGeom& g, const TileGeom& t, const void* rec, const int* off, const double* r,
+                 const R* u, double* v, int M, double scale, const int* blob_body, const double* Y,
+                 const double* V, hipStream_t s);
+// v = scale J u, minus U_p + Omega_p x (r_i - Y_p) when V (N x 6) is given.
 template <typename R>
 int interp(const GridGeom& g, const double* r, const R* u, double* v, int M, double scale,
-           hipStream_t s);
+           const int* blob_body, const double* Y, const double* V, hipStream_t s);
 // v (M x 3) and the NP differences J(r + dr_k) u - J(r) u into vd (M x NP x 3),
 // dr given per blob as M x NP x 3.
 template <typename R>
@@ -174,12 +214,12 @@ int widen(const float* x, double* y, long long n, hipStream_t s);
 // Body kernels (body.hip).
 int blob_positions(const BodyTables& b, const double* Y, const double* q, double* r,
                    hipStream_t s);
-// out_lam = J-part already written; out_lam -= K V; out_V = -K^T lam - Pi V
-int saddle_rigid_terms(const BodyTables& b, const double* Y, const double* q, const double* r,
-                       const double* lam, const double* V, double* out_lam, double* out_V,
-                       hipStream_t s);
-int precond_apply(const BodyTables& b, const double* q, const double* x, double* y, int maxdim,
-                  hipStream_t s);
+// z = P^-1 x (block-diagonal preconditioner, Sec. 2.2) and, when yV is
+// given, the body rows of the saddle operator at z: yV = -K^T z_lam - Pi z_V.
+// When zs is given, z_lam is also written in the spreading order:
+// zs[3 spos[i] + c] = z_lam[3 i + c].
+int precond_apply(const BodyTables& b, const double* q, const double* x, double* z, double* yV,
+                  const int* spos, double* zs, int maxdim, hipStream_t s);
 // FD / RFD perturbations: displacements of each blob (M x NP x 3) and, for
 // RFD, the Philox normals of each body (N x 6).
 int fd_displacements(const BodyTables& b, const double* q, double delta, int mode,
@@ -203,10 +243,22 @@ int body_forces(const BodyTables& b, const double* Y, const double* r, const dou
 int check_finite(const double* x, long long n, int* flag, hipStream_t s);
 
 // Krylov vector kernels (solver.hip).
-int multi_dot(const double* V, long long ld, int k, const double* w, long long n, double* partial,
-              int nblk, double* h, hipStream_t s);
+constexpr int DOT_MAX_BLOCKS = 512;
+// h[j] = V_j . w (j < k), plus h[k] = w . w when with_self; partial holds
+// (k + 1) x DOT_MAX_BLOCKS doubles, counter one zeroed unsigned int.
+int multi_dot(const double* V, long long ld, int k, const double* w, long long n, bool with_self,
+              double* partial, unsigned int* counter, double* h, hipStream_t s);
 int multi_axpy(double* w, const double* V, long long ld, int k, const double* h, double sign,
                long long n, hipStream_t s);
+// out = (w - V h2) / sqrt(h2[k] - |h2[0..k)|^2)
+int ortho_finish(const double* w, const double* V, long long ld, int k, const double* h2, double* out,
+                 long long n, hipStream_t s);
+// One Arnoldi orthogonalisation (CGS with one re-orthogonalisation) of w
+// against V_0..V_{k-1}: out = normalised remainder, h1 (k) and h2s (k + 1:
+// h2 then w.w) stored for the Hessenberg column.  partial1/2 hold
+// (k + 1) x ceil(n / 1024) doubles each.
+int arnoldi_orthogonalise(double* w, const double* V, long long ld, int k, long long n, double* partial1,
+                          double* partial2, double* out, double* h1, double* h2s, hipStream_t s);
 int scale_by_inv_sqrt(const double* w, const double* nrm2, double* out, long long n,
                       hipStream_t s);
 int copy_scaled(const double* x, double a, double* y, long long n, hipStream_t s);

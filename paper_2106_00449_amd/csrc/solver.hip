@@ -1,7 +1,16 @@
 // Krylov vector kernels for the device-resident GMRES of the saddle problem
 // (Sec. 2.2).  Vectors are FP64 and live in one basis array V[(m+1) x ld].
-// Dot products are two-stage (fixed-order partial sums per block, then one
-// block per result), so a solve is reproducible run to run.
+//
+// Each Arnoldi step orthogonalises by classical Gram-Schmidt with one
+// re-orthogonalisation in three launches over fixed chunks of the vectors:
+//   (1) partial sums of h1 = V^T w per chunk;
+//   (2) every block reduces those partials (fixed order), w -= V h1 on its
+//       chunk, and writes the chunk's partial sums of h2 = V^T w and w^T w;
+//   (3) every block reduces them, V_{k+1} = (w - V h2) / sqrt(w^T w - |h2|^2)
+// (|w - V h2|^2 = w^T w - |h2|^2 for orthonormal V, and h2 is a small
+// correction, so there is no cancellation).  No atomics: a solve is
+// reproducible run to run.  Block 0 also stores h1, h2 and w^T w for the
+// host's Hessenberg column.
 
 #include "gdc_internal.h"
 
@@ -9,7 +18,7 @@ namespace gdc {
 namespace {
 
 constexpr int NT = 256;
-constexpr int MAXK = 64;   // vectors per multi-dot launch
+constexpr int MAXK = 64;   // vectors per launch
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
 #pragma unroll
@@ -24,31 +33,141 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
-// partial[j * nblk + block] = sum over the block's slice of V_j . w, j < k.
-__global__ __launch_bounds__(NT) void k_multi_dot_partial(const double* __restrict__ V, long long ld, int k,
-                                                          const double* __restrict__ w, long long n,
-                                                          double* __restrict__ partial) {
+// h[j] = V_j . w for j < k, and h[k] = w . w when with_self.  Grid
+// (nchunk, kk): block (c, j) sums vector j over chunk c into
+// partial[j * nchunk + c]; the last block to finish (counter, zero on entry
+// and left at zero) reduces each row with one wavefront per row.
+__global__ __launch_bounds__(NT) void k_multi_dot(const double* __restrict__ V, long long ld, int k,
+                                                  const double* __restrict__ w, long long n,
+                                                  double* __restrict__ partial, unsigned int* __restrict__ counter,
+                                                  double* __restrict__ h) {
   __shared__ double sh[NT / 64];
-  const long long chunk = (n + gridDim.x - 1) / gridDim.x;
+  __shared__ bool last;
+  const int j = blockIdx.y, nchunk = gridDim.x, kk = gridDim.y;
+  const long long chunk = (n + nchunk - 1) / nchunk;
   const long long lo = chunk * blockIdx.x;
   const long long hi = min(n, lo + chunk);
-  for (int j = 0; j < k; ++j) {
-    const double* v = V + ld * j;
-    double s = 0.0;
-    for (long long e = lo + threadIdx.x; e < hi; e += NT) s += v[e] * w[e];
-    const double t = block_sum(s, sh);
-    if (threadIdx.x == 0) partial[(long long)j * gridDim.x + blockIdx.x] = t;
+  const double* v = j < k ? V + ld * j : w;
+  double s = 0.0;
+  for (long long e = lo + threadIdx.x; e < hi; e += NT) s += v[e] * w[e];
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[(long long)j * nchunk + blockIdx.x] = t;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == (unsigned)(nchunk * kk - 1);
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const volatile double* pv = partial;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int jj = wave; jj < kk; jj += NT / 64) {
+    double a = 0.0;
+    for (int c = lane; c < nchunk; c += 64) a += pv[(long long)jj * nchunk + c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if (lane == 0) h[jj] = a;
+  }
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+constexpr int CHUNK = 1024;   // vector elements per block in the Arnoldi kernels
+
+// Sum over waves of a per-wave value, one barrier; valid in thread 0.
+__device__ __forceinline__ void wave_reduce_to(double v, double* slot) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) slot[threadIdx.x >> 6] = v;
+}
+
+// partial[j * gridDim.x + c] = sum over chunk c of V_j . w, grid (nchunk, kk);
+// row j = k (when kk = k + 1) is w . w.  One vector per block keeps every
+// load of a block independent.
+__global__ __launch_bounds__(NT) void k_dot2d(const double* __restrict__ V, long long ld, int k,
+                                              const double* __restrict__ w, long long n,
+                                              double* __restrict__ partial) {
+  __shared__ double sh[NT / 64];
+  const int j = blockIdx.y;
+  const double* v = j < k ? V + ld * j : w;
+  const long long lo = (long long)blockIdx.x * CHUNK;
+  double a = 0.0;
+#pragma unroll
+  for (int m = 0; m < CHUNK / NT; ++m) {
+    const long long e = lo + threadIdx.x + m * NT;
+    if (e < n) a += v[e] * w[e];
+  }
+  wave_reduce_to(a, sh);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < NT / 64; ++q) t += sh[q];
+    partial[(long long)j * gridDim.x + blockIdx.x] = t;
   }
 }
 
-__global__ __launch_bounds__(NT) void k_multi_dot_final(const double* __restrict__ partial, int nblk,
-                                                        double* __restrict__ h) {
-  __shared__ double sh[NT / 64];
-  const int j = blockIdx.x;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += NT) s += partial[(long long)j * nblk + b];
-  const double t = block_sum(s, sh);
-  if (threadIdx.x == 0) h[j] = t;
+// Reduces rows j < k of partial (ncol columns) into hs[j], fixed order.
+__device__ __forceinline__ void reduce_rows(const double* __restrict__ partial, int k, int ncol, double* hs) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = wave; j < k; j += NT / 64) {
+    double a = 0.0;
+    for (int c = lane; c < ncol; c += 64) a += partial[(long long)j * ncol + c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if (lane == 0) hs[j] = a;
+  }
+}
+
+// w -= V h1 with h1 reduced from partial1 (k rows); block 0 stores h1.
+__global__ __launch_bounds__(NT) void k_axpy_partial(double* __restrict__ w, const double* __restrict__ V,
+                                                     long long ld, int k, const double* __restrict__ partial1,
+                                                     long long n, double* __restrict__ hout) {
+  __shared__ double hs[MAXK];
+  reduce_rows(partial1, k, gridDim.x, hs);
+  __syncthreads();
+  if (blockIdx.x == 0)
+    for (int j = threadIdx.x; j < k; j += NT) hout[j] = hs[j];
+  const long long lo = (long long)blockIdx.x * CHUNK;
+#pragma unroll
+  for (int m = 0; m < CHUNK / NT; ++m) {
+    const long long e = lo + threadIdx.x + m * NT;
+    if (e < n) {
+      double x = w[e];
+#pragma unroll 8
+      for (int j = 0; j < k; ++j) x -= hs[j] * V[ld * j + e];
+      w[e] = x;
+    }
+  }
+}
+
+// out = (w - V h2) / sqrt(s - |h2|^2) with (h2, s) reduced from partial2.
+// Block 0 stores h2 and s in hout.
+__global__ __launch_bounds__(NT) void k_ortho_finish2(const double* __restrict__ w, const double* __restrict__ V,
+                                                      long long ld, int k, const double* __restrict__ partial2,
+                                                      long long n, double* __restrict__ out, double* __restrict__ hout) {
+  __shared__ double hs[MAXK];
+  __shared__ double scale;
+  reduce_rows(partial2, k + 1, gridDim.x, hs);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double hh = 0.0;
+    for (int j = 0; j < k; ++j) hh += hs[j] * hs[j];
+    const double nrm2 = hs[k] - hh;
+    scale = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+  }
+  if (blockIdx.x == 0)
+    for (int j = threadIdx.x; j <= k; j += NT) hout[j] = hs[j];
+  __syncthreads();
+  const double a = scale;
+  const long long lo = (long long)blockIdx.x * CHUNK;
+#pragma unroll
+  for (int m = 0; m < CHUNK / NT; ++m) {
+    const long long e = lo + threadIdx.x + m * NT;
+    if (e < n) {
+      double x = w[e];
+#pragma unroll 8
+      for (int j = 0; j < k; ++j) x -= hs[j] * V[ld * j + e];
+      out[e] = a * x;
+    }
+  }
 }
 
 // w += sign * sum_j h_j V_j
@@ -63,6 +182,30 @@ __global__ __launch_bounds__(NT) void k_multi_axpy(double* __restrict__ w, const
     double acc = 0.0;
     for (int j = 0; j < k; ++j) acc += hs[j] * V[ld * j + e];
     w[e] += sign * acc;
+  }
+}
+
+// out = (w - V h) / sqrt(s - |h|^2), h = h2[0..k), s = h2[k]
+__global__ __launch_bounds__(NT) void k_ortho_finish(const double* __restrict__ w, const double* __restrict__ V,
+                                                     long long ld, int k, const double* __restrict__ h2,
+                                                     double* __restrict__ out, long long n) {
+  __shared__ double hs[MAXK];
+  __shared__ double scale;
+  for (int j = threadIdx.x; j < k; j += NT) hs[j] = h2[j];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double hh = 0.0;
+    for (int j = 0; j < k; ++j) hh += hs[j] * hs[j];
+    const double nrm2 = h2[k] - hh;
+    scale = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+  }
+  __syncthreads();
+  const double a = scale;
+  const long long stride = (long long)gridDim.x * NT;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < n; e += stride) {
+    double acc = 0.0;
+    for (int j = 0; j < k; ++j) acc += hs[j] * V[ld * j + e];
+    out[e] = a * (w[e] - acc);
   }
 }
 
@@ -85,18 +228,23 @@ __global__ void k_sub_from(const double* __restrict__ b, double* __restrict__ w,
 
 inline unsigned grid_for(long long n) {
   const long long b = (n + NT - 1) / NT;
-  return (unsigned)(b < 2048 ? (b > 0 ? b : 1) : 2048);
+  return (unsigned)(b < 1024 ? (b > 0 ? b : 1) : 1024);
 }
 
 }  // namespace
 
-int multi_dot(const double* V, long long ld, int k, const double* w, long long n, double* partial, int nblk,
-              double* h, hipStream_t s) {
-  if (k <= 0) return GDC_OK;
-  hipLaunchKernelGGL(k_multi_dot_partial, dim3(nblk), dim3(NT), 0, s, V, ld, k, w, n, partial);
-  GDC_TRY(check_launch("k_multi_dot_partial"));
-  hipLaunchKernelGGL(k_multi_dot_final, dim3(k), dim3(NT), 0, s, partial, nblk, h);
-  return check_launch("k_multi_dot_final");
+int multi_dot(const double* V, long long ld, int k, const double* w, long long n, bool with_self,
+              double* partial, unsigned int* counter, double* h, hipStream_t s) {
+  if (k + (with_self ? 1 : 0) <= 0) return GDC_OK;
+  if (k + 1 > MAXK) {
+    set_error("multi_dot: too many vectors");
+    return GDC_EINVAL;
+  }
+  const long long want = (n + 16 * NT - 1) / (16 * NT);
+  const unsigned nchunk = (unsigned)(want < DOT_MAX_BLOCKS ? (want > 0 ? want : 1) : DOT_MAX_BLOCKS);
+  const unsigned kk = (unsigned)(k + (with_self ? 1 : 0));
+  hipLaunchKernelGGL(k_multi_dot, dim3(nchunk, kk), dim3(NT), 0, s, V, ld, k, w, n, partial, counter, h);
+  return check_launch("k_multi_dot");
 }
 
 int multi_axpy(double* w, const double* V, long long ld, int k, const double* h, double sign, long long n,
@@ -108,6 +256,37 @@ int multi_axpy(double* w, const double* V, long long ld, int k, const double* h,
   }
   hipLaunchKernelGGL(k_multi_axpy, dim3(grid_for(n)), dim3(NT), 0, s, w, V, ld, k, h, sign, n);
   return check_launch("k_multi_axpy");
+}
+
+int ortho_finish(const double* w, const double* V, long long ld, int k, const double* h2, double* out, long long n,
+                 hipStream_t s) {
+  if (k >= MAXK) {
+    set_error("ortho_finish: too many vectors");
+    return GDC_EINVAL;
+  }
+  hipLaunchKernelGGL(k_ortho_finish, dim3(grid_for(n)), dim3(NT), 0, s, w, V, ld, k, h2, out, n);
+  return check_launch("k_ortho_finish");
+}
+
+int arnoldi_orthogonalise(double* w, const double* V, long long ld, int k, long long n, double* partial1,
+                          double* partial2, double* out, double* h1, double* h2s, hipStream_t s) {
+  if (k < 1 || k + 1 >= MAXK) {
+    set_error("arnoldi_orthogonalise: basis size out of range");
+    return GDC_EINVAL;
+  }
+  const unsigned nchunk = (unsigned)((n + CHUNK - 1) / CHUNK);
+  if (nchunk > (unsigned)DOT_MAX_BLOCKS * 4) {
+    set_error("arnoldi_orthogonalise: vector too long");
+    return GDC_EINVAL;
+  }
+  hipLaunchKernelGGL(k_dot2d, dim3(nchunk, k), dim3(NT), 0, s, V, ld, k, (const double*)w, n, partial1);
+  GDC_TRY(check_launch("k_dot2d"));
+  hipLaunchKernelGGL(k_axpy_partial, dim3(nchunk), dim3(NT), 0, s, w, V, ld, k, partial1, n, h1);
+  GDC_TRY(check_launch("k_axpy_partial"));
+  hipLaunchKernelGGL(k_dot2d, dim3(nchunk, k + 1), dim3(NT), 0, s, V, ld, k, (const double*)w, n, partial2);
+  GDC_TRY(check_launch("k_dot2d"));
+  hipLaunchKernelGGL(k_ortho_finish2, dim3(nchunk), dim3(NT), 0, s, w, V, ld, k, partial2, n, out, h2s);
+  return check_launch("k_ortho_finish2");
 }
 
 int scale_by_inv_sqrt(const double* w, const double* nrm2, double* out, long long n, hipStream_t s) {

@@ -18,7 +18,7 @@ def test_header_declares_boundary():
     names = _declared()
     for required in ["gdc_init", "gdc_free", "gdc_last_error", "gdc_mobility_apply", "gdc_step",
                      "gdc_get_step", "gdc_set_step", "gdc_fluct_velocity", "gdc_predictor",
-                     "gdc_philox_normals"]:
+                     "gdc_philox_normals", "gdc_probe_kernel", "gdc_probe_read"]:
         assert required in names
 
 
