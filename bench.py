@@ -139,7 +139,7 @@ def main():
     achieved = alg_bytes / avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES,
-                "kernel": "k_spread_gather", "launches": k_launches, "avg_us": avg_s * 1e6,
+                "kernel": "k_spread_sep", "launches": k_launches, "avg_us": avg_s * 1e6,
                 "algorithmic_bytes": alg_bytes}
 
     out = {

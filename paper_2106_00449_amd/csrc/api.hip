@@ -294,12 +294,17 @@ struct gdc_handle {
   double* trec = nullptr;
   int* spos = nullptr;
   double* zsorted = nullptr;
-  bool interp_by_tiles = false;  // GDC_INTERP=tiles selects the tiled averaging
   double* hhost = nullptr;   // pinned readback
+  GmresState* gm = nullptr;  // device GMRES bookkeeping
+  unsigned char* gm_host = nullptr;   // pinned: two status slots
+  hipEvent_t gm_ev[2] = {nullptr, nullptr};
 
   ~gdc_handle() {
     for (void* p : allocs) (void)hipFree(p);
     if (hhost) (void)hipHostFree(hhost);
+    if (gm_host) (void)hipHostFree(gm_host);
+    for (hipEvent_t e : gm_ev)
+      if (e) (void)hipEventDestroy(e);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 
@@ -359,26 +364,24 @@ int prepare_positions(gdc_handle* h, const double* r) {
 
 // out = M_FCM lam at blob positions r (prepared by prepare_positions), minus
 // U_p + Omega_p x (r_i - Y_p) when V (N x 6) is given.
+// Kernels launched with a non-null `skip` return at once when *skip != 0.
 template <typename R>
 int apply_mobility(gdc_handle* h, const double* r, const double* lam, double* out, const double* Y = nullptr,
-                   const double* V = nullptr, const double* lam_sorted = nullptr) {
+                   const double* V = nullptr, const double* lam_sorted = nullptr, const int* skip = nullptr) {
   const GridGeom& g = h->geom;
   R* f = (R*)h->grid[0];
-  GDC_TRY(spread<R>(g, h->tg, h->trec, lam, lam_sorted, h->tile_off, f, h->stream));
-  GDC_TRY(stokes_solve<R>(g, tw_of<R>(h), f, (Cx<R>*)h->grid[1], (Cx<R>*)h->grid[2], h->stream));
-  if (h->interp_by_tiles)
-    return interp_tiles<R>(g, h->tg, h->trec, h->tile_off, r, f, out, h->M, g.dV, h->bt.blob_body, Y, V,
-                           h->stream);
-  return interp<R>(g, r, f, out, h->M, g.dV, h->bt.blob_body, Y, V, h->stream);
+  GDC_TRY(spread<R>(g, h->tg, h->trec, lam, lam_sorted, h->tile_off, f, h->stream, skip));
+  GDC_TRY(stokes_solve<R>(g, tw_of<R>(h), f, (Cx<R>*)h->grid[1], (Cx<R>*)h->grid[2], h->stream, skip));
+  return interp<R>(g, r, f, out, h->M, g.dV, h->bt.blob_body, Y, V, h->stream, skip);
 }
 
 // z = P^-1 x and y = A z, A = [[M, -K], [-K^T, -Pi]] at (Y, q, r).
 template <typename R>
 int apply_saddle_precond(gdc_handle* h, const double* Y, const double* q, const double* r, const double* x,
-                         double* z, double* y) {
+                         double* z, double* y, const int* skip = nullptr) {
   const long long m3 = 3LL * h->M;
-  GDC_TRY(precond_apply(h->bt, q, x, z, y + m3, h->spos, h->zsorted, h->maxdim, h->stream));
-  return apply_mobility<R>(h, r, z, y, Y, z + m3, h->zsorted);
+  GDC_TRY(precond_apply(h->bt, q, x, z, y + m3, h->spos, h->zsorted, h->maxdim, h->stream, skip));
+  return apply_mobility<R>(h, r, z, y, Y, z + m3, h->zsorted, skip);
 }
 
 struct GmresResult {
@@ -387,31 +390,52 @@ struct GmresResult {
   bool converged = false;
 };
 
+// Status of the device GMRES as the host reads it.
+struct GmStatus {
+  double est;
+  int its, kdone, done, converged;
+};
+
+GmStatus read_status(const unsigned char* p) {
+  GmStatus st;
+  std::memcpy(&st.est, p, sizeof(double));
+  std::memcpy(&st.its, p + 8, 4 * sizeof(int));
+  return st;
+}
+
+// Queues a copy of the device status into pinned slot `slot` and an event
+// after it.
+int post_status(gdc_handle* h, int slot) {
+  GDC_HIP(hipMemcpyAsync(h->gm_host + 32 * slot, h->gm, GM_STATUS_BYTES, hipMemcpyDeviceToHost, h->stream));
+  GDC_HIP(hipEventRecord(h->gm_ev[slot], h->stream));
+  return GDC_OK;
+}
+
+int wait_status(gdc_handle* h, int slot, GmStatus& st) {
+  GDC_HIP(hipEventSynchronize(h->gm_ev[slot]));
+  st = read_status(h->gm_host + 32 * slot);
+  return GDC_OK;
+}
+
 // Right-preconditioned restarted GMRES (Saad & Schultz) on the saddle system
 // with classical Gram-Schmidt and one reorthogonalisation, zero initial
 // guess.  Solution (x = P^-1 u) written to h->sol.
+//
+// The Hessenberg bookkeeping runs on the device (gm_column), so the host
+// queues iteration k + 1 before it waits for the status of iteration k: the
+// GPU never idles on the host.  When iteration k ends the cycle, the kernels
+// already queued for iteration k + 1 see the device flag and return at once.
 template <typename R>
 int gmres(gdc_handle* h, const double* Y, const double* q, const double* r, GmresResult& res) {
   const long long n = h->nx;
   const int m = h->restart;
   hipStream_t s = h->stream;
-  double* hh = h->hhost;
-  // |b|
+  const int* skip = &h->gm->done;
   GDC_TRY(multi_dot(nullptr, n, 0, h->rhs, n, true, h->partial, h->dot_counter, h->hdev, s));
-  GDC_HIP(hipMemcpyAsync(hh, h->hdev, sizeof(double), hipMemcpyDeviceToHost, s));
-  GDC_HIP(hipStreamSynchronize(s));
-  const double nb = std::sqrt(hh[0]);
+  GDC_TRY(gm_init(h->gm, h->hdev, h->tol, h->maxit, s));
   GDC_TRY(fill_zero(h->xacc, (size_t)((n * 8 + 15) / 16 * 16), s));
-  if (nb == 0.0) {
-    GDC_TRY(fill_zero(h->sol, (size_t)((n * 8 + 15) / 16 * 16), s));
-    res = GmresResult{0, 0.0, true};
-    return GDC_OK;
-  }
-  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-  int its = 0;
   bool first = true;
-  double est = 1.0;
-  bool converged = false;
+  GmStatus st{};
   while (true) {
     double* V0 = h->Vb;
     if (first) {
@@ -423,69 +447,31 @@ int gmres(gdc_handle* h, const double* Y, const double* q, const double* r, Gmre
     }
     first = false;
     GDC_TRY(multi_dot(nullptr, n, 0, h->w, n, true, h->partial, h->dot_counter, h->hdev + 2 * HCOLS, s));
-    GDC_HIP(hipMemcpyAsync(hh, h->hdev + 2 * HCOLS, sizeof(double), hipMemcpyDeviceToHost, s));
-    GDC_HIP(hipStreamSynchronize(s));
-    const double beta = std::sqrt(hh[0]);
-    est = beta / nb;
-    if (est <= h->tol || its >= h->maxit) {
-      converged = est <= h->tol;
-      break;
-    }
+    GDC_TRY(gm_cycle(h->gm, h->hdev + 2 * HCOLS, s));
     GDC_TRY(scale_by_inv_sqrt(h->w, h->hdev + 2 * HCOLS, V0, n, s));
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int kdone = 0;
+    GDC_TRY(post_status(h, 0));
     for (int k = 0; k < m; ++k) {
       double* Vk = h->Vb + n * k;
       double* Vk1 = h->Vb + n * (k + 1);
-      GDC_TRY(apply_saddle_precond<R>(h, Y, q, r, Vk, h->z, h->w));
+      GDC_TRY(apply_saddle_precond<R>(h, Y, q, r, Vk, h->z, h->w, skip));
       double* h1 = h->hdev;
       double* h2 = h->hdev + HCOLS;
-      GDC_TRY(arnoldi_orthogonalise(h->w, h->Vb, n, k + 1, n, h->partial, h->partial2, Vk1, h1, h2, s));
-      GDC_HIP(hipMemcpyAsync(hh, h->hdev, 2 * HCOLS * sizeof(double), hipMemcpyDeviceToHost, s));
-      GDC_HIP(hipStreamSynchronize(s));
-      double h2sq = 0.0;
-      for (int j = 0; j <= k; ++j) {
-        H[j * m + k] = hh[j] + hh[HCOLS + j];
-        h2sq += hh[HCOLS + j] * hh[HCOLS + j];
-      }
-      H[(k + 1) * m + k] = std::sqrt(std::max(0.0, hh[HCOLS + k + 1] - h2sq));
-      for (int j = 0; j < k; ++j) {
-        const double t = cs[j] * H[j * m + k] + sn[j] * H[(j + 1) * m + k];
-        H[(j + 1) * m + k] = -sn[j] * H[j * m + k] + cs[j] * H[(j + 1) * m + k];
-        H[j * m + k] = t;
-      }
-      const double den = std::hypot(H[k * m + k], H[(k + 1) * m + k]);
-      cs[k] = den > 0 ? H[k * m + k] / den : 1.0;
-      sn[k] = den > 0 ? H[(k + 1) * m + k] / den : 0.0;
-      H[k * m + k] = den;
-      H[(k + 1) * m + k] = 0.0;
-      g[k + 1] = -sn[k] * g[k];
-      g[k] = cs[k] * g[k];
-      ++its;
-      kdone = k + 1;
-      est = std::fabs(g[k + 1]) / nb;
-      if (est <= h->tol || its >= h->maxit || H[k * m + k] == 0.0) break;
+      GDC_TRY(arnoldi_orthogonalise(h->w, h->Vb, n, k + 1, n, h->partial, h->partial2, Vk1, h1, h2, s, skip));
+      GDC_TRY(gm_column(h->gm, k, m, h1, h2, s));
+      GDC_TRY(post_status(h, (k + 1) & 1));
+      // status after iteration k - 1 (or after the cycle start)
+      GDC_TRY(wait_status(h, k & 1, st));
+      if (st.done) break;
     }
-    for (int i = kdone - 1; i >= 0; --i) {
-      double t = g[i];
-      for (int j = i + 1; j < kdone; ++j) t -= H[i * m + j] * y[j];
-      y[i] = H[i * m + i] != 0.0 ? t / H[i * m + i] : 0.0;
-    }
-    // y goes through the pinned buffer: an async copy must not read pageable memory
-    std::copy(y.begin(), y.begin() + kdone, hh + 3 * HCOLS);
-    GDC_HIP(hipMemcpyAsync(h->hdev + 3 * HCOLS, hh + 3 * HCOLS, kdone * sizeof(double), hipMemcpyHostToDevice, s));
-    GDC_TRY(multi_axpy(h->xacc, h->Vb, n, kdone, h->hdev + 3 * HCOLS, 1.0, n, s));
-    if (est <= h->tol) {
-      converged = true;
-      break;
-    }
-    if (its >= h->maxit) break;
+    GDC_TRY(gm_finish_cycle(h->gm, h->xacc, h->Vb, n, n, s));
+    GDC_TRY(post_status(h, 0));
+    GDC_TRY(wait_status(h, 0, st));
+    if (st.converged || st.its >= h->maxit) break;
   }
   GDC_TRY(precond_apply(h->bt, q, h->xacc, h->sol, nullptr, nullptr, nullptr, h->maxdim, s));
-  res.its = its;
-  res.relres = est;
-  res.converged = converged;
+  res.its = st.its;
+  res.relres = st.est;
+  res.converged = st.converged != 0;
   return GDC_OK;
 }
 
@@ -651,10 +637,6 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
   if (c.gmres_tol == 0.0) c.gmres_tol = 1e-6;
   if (c.gmres_maxit == 0) c.gmres_maxit = 200;
   if (c.gmres_restart == 0) c.gmres_restart = 50;
-  {
-    const char* e = std::getenv("GDC_INTERP");
-    h->interp_by_tiles = (e && std::string(e) == "tiles");
-  }
   h->tol = c.gmres_tol;
   h->maxit = c.gmres_maxit;
   h->restart = c.gmres_restart;
@@ -852,6 +834,9 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
     GDC_TRY(h->alloc(&h->tile_cursor, (size_t)t.ntiles));
   }
   GDC_HIP(hipHostMalloc((void**)&h->hhost, 5 * HCOLS * sizeof(double), hipHostMallocDefault));
+  GDC_TRY(h->alloc(&h->gm, 1));
+  GDC_HIP(hipHostMalloc((void**)&h->gm_host, 64, hipHostMallocDefault));
+  for (hipEvent_t& e : h->gm_ev) GDC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 
   if (h->precision == GDC_FP64) {
     GDC_TRY(init_grid_tables<double>(h));

@@ -66,7 +66,8 @@ __global__ void k_blob_positions(BodyTables B, const double* __restrict__ Y, con
 __global__ __launch_bounds__(64) void k_precond(BodyTables B, const double* __restrict__ q,
                                                 const double* __restrict__ x, double* __restrict__ z,
                                                 double* __restrict__ yV, const int* __restrict__ spos,
-                                                double* __restrict__ zs) {
+                                                double* __restrict__ zs, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   extern __shared__ double sh[];
   const int p = blockIdx.x;
   const int lane = threadIdx.x;
@@ -464,9 +465,9 @@ int blob_positions(const BodyTables& b, const double* Y, const double* q, double
 }
 
 int precond_apply(const BodyTables& b, const double* q, const double* x, double* z, double* yV, const int* spos,
-                  double* zs, int maxdim, hipStream_t s) {
+                  double* zs, int maxdim, hipStream_t s, const int* skip) {
   const size_t shm = (2 * (size_t)maxdim + 8) * sizeof(double);
-  hipLaunchKernelGGL(k_precond, dim3(b.N), dim3(64), shm, s, b, q, x, z, yV, spos, zs);
+  hipLaunchKernelGGL(k_precond, dim3(b.N), dim3(64), shm, s, b, q, x, z, yV, spos, zs, skip);
   return check_launch("k_precond");
 }
 

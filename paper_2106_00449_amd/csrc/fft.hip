@@ -169,7 +169,9 @@ __device__ __forceinline__ void load_twiddles(Cx<R>* tw, const Cx<R>* __restrict
 // A(k) = (Z(k) + conj Z(N-k))/2 and B(k) = (Z(k) - conj Z(N-k))/(2i).
 template <typename R, int N2>
 __global__ __launch_bounds__(NT) void k_r2c_axis2(const R* __restrict__ in, Cx<R>* __restrict__ X,
-                                                  const Cx<R>* __restrict__ twg, int n0, int n1) {
+                                                  const Cx<R>* __restrict__ twg, int n0, int n1,
+                                                  const int* __restrict__ skip) {
+  if (skip && *skip) return;
   constexpr int TL = Tiles<R>::TL, NLc = TL / 2, LS = N2 + 1, H = N2 / 2;
   __shared__ Cx<R> buf[NLc * LS];
   __shared__ Cx<R> tw[N2];
@@ -206,7 +208,9 @@ __global__ __launch_bounds__(NT) void k_r2c_axis2(const R* __restrict__ in, Cx<R
 // ------------------------------------------------------------ pass B: FFT, axis 1
 template <typename R, int N1>
 __global__ __launch_bounds__(NT) void k_fwd_axis1(const Cx<R>* __restrict__ X, Cx<R>* __restrict__ Y,
-                                                  const Cx<R>* __restrict__ twg, int n0, int H) {
+                                                  const Cx<R>* __restrict__ twg, int n0, int H,
+                                                  const int* __restrict__ skip) {
+  if (skip && *skip) return;
   constexpr int TL = Tiles<R>::TL, LS = N1 + 1;
   __shared__ Cx<R> buf[TL * LS];
   __shared__ Cx<R> tw[N1];
@@ -229,7 +233,9 @@ __global__ __launch_bounds__(NT) void k_fwd_axis1(const Cx<R>* __restrict__ X, C
 // ------------------------------------------------------------ pass B': iFFT, axis 1
 template <typename R, int N1>
 __global__ __launch_bounds__(NT) void k_inv_axis1(const Cx<R>* __restrict__ Y, Cx<R>* __restrict__ X,
-                                                  const Cx<R>* __restrict__ twg, int n0, int H) {
+                                                  const Cx<R>* __restrict__ twg, int n0, int H,
+                                                  const int* __restrict__ skip) {
+  if (skip && *skip) return;
   constexpr int TL = Tiles<R>::TL, LS = N1 + 1;
   __shared__ Cx<R> buf[TL * LS];
   __shared__ Cx<R> tw[N1];
@@ -255,7 +261,9 @@ __global__ __launch_bounds__(NT) void k_inv_axis1(const Cx<R>* __restrict__ Y, C
 // Nyquist term is zero.
 template <typename R, int N2>
 __global__ __launch_bounds__(NT) void k_c2r_axis2(const Cx<R>* __restrict__ X, R* __restrict__ out,
-                                                  const Cx<R>* __restrict__ twg, int n0, int n1) {
+                                                  const Cx<R>* __restrict__ twg, int n0, int n1,
+                                                  const int* __restrict__ skip) {
+  if (skip && *skip) return;
   constexpr int TL = Tiles<R>::TL, NLc = TL / 2, LS = N2 + 1, H = N2 / 2;
   __shared__ Cx<R> buf[NLc * LS];
   __shared__ Cx<R> tw[N2];
@@ -364,7 +372,8 @@ __device__ bool noise_mode(const ProjParams& P, int j0, int j1, int j2, double u
 
 template <typename R, int N0, bool NOISE>
 __global__ __launch_bounds__(NT) void k_axis0_project(Cx<R>* __restrict__ Y, const Cx<R>* __restrict__ twg,
-                                                      ProjParams P) {
+                                                      ProjParams P, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   constexpr int TC = Tiles<R>::TC, NLn = 3 * TC, LS = N0 + 1;
   __shared__ Cx<R> buf[NLn * LS];
   __shared__ Cx<R> tw[N0];
@@ -430,11 +439,11 @@ __global__ __launch_bounds__(NT) void k_axis0_project(Cx<R>* __restrict__ Y, con
 #define GDC_FFT_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
 
 template <typename R>
-int launch_r2c(int n2, const R* in, Cx<R>* X, const Cx<R>* tw, int n0, int n1, hipStream_t s) {
+int launch_r2c(int n2, const R* in, Cx<R>* X, const Cx<R>* tw, int n0, int n1, hipStream_t s, const int* skip) {
   dim3 grid((n1 + Tiles<R>::TL - 1) / Tiles<R>::TL, n0, 3);
   ProbeScope ps("fft_r2c", s);
   switch (n2) {
-#define X_(N) case N: hipLaunchKernelGGL((k_r2c_axis2<R, N>), grid, dim3(NT), 0, s, in, X, tw, n0, n1); break;
+#define X_(N) case N: hipLaunchKernelGGL((k_r2c_axis2<R, N>), grid, dim3(NT), 0, s, in, X, tw, n0, n1, skip); break;
     GDC_FFT_SIZES(X_)
 #undef X_
     default: set_error("unsupported grid size"); return GDC_EINVAL;
@@ -443,11 +452,11 @@ int launch_r2c(int n2, const R* in, Cx<R>* X, const Cx<R>* tw, int n0, int n1, h
 }
 
 template <typename R>
-int launch_fwd1(int n1, const Cx<R>* X, Cx<R>* Y, const Cx<R>* tw, int n0, int H, hipStream_t s) {
+int launch_fwd1(int n1, const Cx<R>* X, Cx<R>* Y, const Cx<R>* tw, int n0, int H, hipStream_t s, const int* skip) {
   dim3 grid((n0 + Tiles<R>::TL - 1) / Tiles<R>::TL, H, 3);
   ProbeScope ps("fft_fwd1", s);
   switch (n1) {
-#define X_(N) case N: hipLaunchKernelGGL((k_fwd_axis1<R, N>), grid, dim3(NT), 0, s, X, Y, tw, n0, H); break;
+#define X_(N) case N: hipLaunchKernelGGL((k_fwd_axis1<R, N>), grid, dim3(NT), 0, s, X, Y, tw, n0, H, skip); break;
     GDC_FFT_SIZES(X_)
 #undef X_
     default: set_error("unsupported grid size"); return GDC_EINVAL;
@@ -456,11 +465,11 @@ int launch_fwd1(int n1, const Cx<R>* X, Cx<R>* Y, const Cx<R>* tw, int n0, int H
 }
 
 template <typename R>
-int launch_inv1(int n1, const Cx<R>* Y, Cx<R>* X, const Cx<R>* tw, int n0, int H, hipStream_t s) {
+int launch_inv1(int n1, const Cx<R>* Y, Cx<R>* X, const Cx<R>* tw, int n0, int H, hipStream_t s, const int* skip) {
   dim3 grid((n0 + Tiles<R>::TL - 1) / Tiles<R>::TL, H, 3);
   ProbeScope ps("fft_inv1", s);
   switch (n1) {
-#define X_(N) case N: hipLaunchKernelGGL((k_inv_axis1<R, N>), grid, dim3(NT), 0, s, Y, X, tw, n0, H); break;
+#define X_(N) case N: hipLaunchKernelGGL((k_inv_axis1<R, N>), grid, dim3(NT), 0, s, Y, X, tw, n0, H, skip); break;
     GDC_FFT_SIZES(X_)
 #undef X_
     default: set_error("unsupported grid size"); return GDC_EINVAL;
@@ -469,11 +478,11 @@ int launch_inv1(int n1, const Cx<R>* Y, Cx<R>* X, const Cx<R>* tw, int n0, int H
 }
 
 template <typename R>
-int launch_c2r(int n2, const Cx<R>* X, R* out, const Cx<R>* tw, int n0, int n1, hipStream_t s) {
+int launch_c2r(int n2, const Cx<R>* X, R* out, const Cx<R>* tw, int n0, int n1, hipStream_t s, const int* skip) {
   dim3 grid((n1 + Tiles<R>::TL - 1) / Tiles<R>::TL, n0, 3);
   ProbeScope ps("fft_c2r", s);
   switch (n2) {
-#define X_(N) case N: hipLaunchKernelGGL((k_c2r_axis2<R, N>), grid, dim3(NT), 0, s, X, out, tw, n0, n1); break;
+#define X_(N) case N: hipLaunchKernelGGL((k_c2r_axis2<R, N>), grid, dim3(NT), 0, s, X, out, tw, n0, n1, skip); break;
     GDC_FFT_SIZES(X_)
 #undef X_
     default: set_error("unsupported grid size"); return GDC_EINVAL;
@@ -482,11 +491,11 @@ int launch_c2r(int n2, const Cx<R>* X, R* out, const Cx<R>* tw, int n0, int n1, 
 }
 
 template <typename R, bool NOISE>
-int launch_proj(int n0, Cx<R>* Y, const Cx<R>* tw, const ProjParams& P, hipStream_t s) {
+int launch_proj(int n0, Cx<R>* Y, const Cx<R>* tw, const ProjParams& P, hipStream_t s, const int* skip) {
   dim3 grid((P.n1 + Tiles<R>::TC - 1) / Tiles<R>::TC, P.n2h, 1);
   ProbeScope ps(NOISE ? "fft_noise" : "fft_project", s);
   switch (n0) {
-#define X_(N) case N: hipLaunchKernelGGL((k_axis0_project<R, N, NOISE>), grid, dim3(NT), 0, s, Y, tw, P); break;
+#define X_(N) case N: hipLaunchKernelGGL((k_axis0_project<R, N, NOISE>), grid, dim3(NT), 0, s, Y, tw, P, skip); break;
     GDC_FFT_SIZES(X_)
 #undef X_
     default: set_error("unsupported grid size"); return GDC_EINVAL;
@@ -521,13 +530,13 @@ bool fft_size_supported(int n) {
 
 template <typename R>
 int stokes_solve(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, Cx<R>* Y,
-                 hipStream_t s) {
+                 hipStream_t s, const int* skip) {
   const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], H = g.n2h;
-  GDC_TRY(launch_r2c<R>(n2, real, X, tw[2], n0, n1, s));
-  GDC_TRY(launch_fwd1<R>(n1, X, Y, tw[1], n0, H, s));
-  GDC_TRY((launch_proj<R, false>(n0, Y, tw[0], proj_params(g), s)));
-  GDC_TRY(launch_inv1<R>(n1, Y, X, tw[1], n0, H, s));
-  GDC_TRY(launch_c2r<R>(n2, X, real, tw[2], n0, n1, s));
+  GDC_TRY(launch_r2c<R>(n2, real, X, tw[2], n0, n1, s, skip));
+  GDC_TRY(launch_fwd1<R>(n1, X, Y, tw[1], n0, H, s, skip));
+  GDC_TRY((launch_proj<R, false>(n0, Y, tw[0], proj_params(g), s, skip)));
+  GDC_TRY(launch_inv1<R>(n1, Y, X, tw[1], n0, H, s, skip));
+  GDC_TRY(launch_c2r<R>(n2, X, real, tw[2], n0, n1, s, skip));
   return GDC_OK;
 }
 
@@ -544,9 +553,9 @@ int fluct_field(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, 
   const double base = kT * g.eta / (g.dV * dt);
   P.sdiag = std::sqrt((double)g.G * 4.0 * base / 2.0);
   P.soff = std::sqrt((double)g.G * 2.0 * base / 2.0);
-  GDC_TRY((launch_proj<R, true>(n0, Y, tw[0], P, s)));
-  GDC_TRY(launch_inv1<R>(n1, Y, X, tw[1], n0, H, s));
-  GDC_TRY(launch_c2r<R>(n2, X, real, tw[2], n0, n1, s));
+  GDC_TRY((launch_proj<R, true>(n0, Y, tw[0], P, s, nullptr)));
+  GDC_TRY(launch_inv1<R>(n1, Y, X, tw[1], n0, H, s, nullptr));
+  GDC_TRY(launch_c2r<R>(n2, X, real, tw[2], n0, n1, s, nullptr));
   return GDC_OK;
 }
 
@@ -559,9 +568,9 @@ int philox_normals_dev(uint64_t seed, uint32_t c1, uint64_t step, uint32_t c0_be
 }
 
 template int stokes_solve<float>(const GridGeom&, const Cx<float>* const[3], float*, Cx<float>*,
-                                 Cx<float>*, hipStream_t);
+                                   Cx<float>*, hipStream_t, const int*);
 template int stokes_solve<double>(const GridGeom&, const Cx<double>* const[3], double*, Cx<double>*,
-                                  Cx<double>*, hipStream_t);
+                                   Cx<double>*, hipStream_t, const int*);
 template int fluct_field<float>(const GridGeom&, const Cx<float>* const[3], float*, Cx<float>*,
                                 Cx<float>*, uint64_t, uint64_t, double, double, hipStream_t);
 template int fluct_field<double>(const GridGeom&, const Cx<double>* const[3], double*, Cx<double>*,

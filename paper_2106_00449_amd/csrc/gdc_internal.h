@@ -169,9 +169,11 @@ struct BodyTables {
 // FFT / projection / noise (fft.hip).  The three grid buffers hold 3 G values
 // of R each; `real` is the real-space field (spread output in, velocity out),
 // X and Y are the two transposed half-spectrum layouts.
+// Kernels given `skip` (a device int) return at once when *skip != 0: the
+// GMRES loop queues iterations ahead and stops them this way once converged.
 template <typename R>
 int stokes_solve(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, Cx<R>* Y,
-                 hipStream_t s);
+                 hipStream_t s, const int* skip = nullptr);
 template <typename R>
 int fluct_field(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, Cx<R>* Y,
                 uint64_t seed, uint64_t step, double kT, double dt, hipStream_t s);
@@ -192,17 +194,12 @@ int tile_sort(const GridGeom& g, const TileGeom& t, const double* r, int M, int*
 // when given, holds lam in the sorted order (3 x M) and is read instead.
 template <typename R>
 int spread(const GridGeom& g, const TileGeom& t, const void* rec, const double* lam, const double* lam_sorted,
-           const int* off, R* f, hipStream_t s);
-// Tiled averaging at the positions of the last tile_sort: v = scale J u,
-// minus U_p + Omega_p x (r_i - Y_p) when V (N x 6) is given.
-template <typename R>
-int interp_tiles(const GridGeom& g, const TileGeom& t, const void* rec, const int* off, const double* r,
-                 const R* u, double* v, int M, double scale, const int* blob_body, const double* Y,
-                 const double* V, hipStream_t s);
+           const int* off, R* f, hipStream_t s, const int* skip = nullptr);
 // v = scale J u, minus U_p + Omega_p x (r_i - Y_p) when V (N x 6) is given.
 template <typename R>
 int interp(const GridGeom& g, const double* r, const R* u, double* v, int M, double scale,
-           const int* blob_body, const double* Y, const double* V, hipStream_t s);
+           const int* blob_body, const double* Y, const double* V, hipStream_t s,
+           const int* skip = nullptr);
 // v (M x 3) and the NP differences J(r + dr_k) u - J(r) u into vd (M x NP x 3),
 // dr given per blob as M x NP x 3.
 template <typename R>
@@ -219,7 +216,7 @@ int blob_positions(const BodyTables& b, const double* Y, const double* q, double
 // When zs is given, z_lam is also written in the spreading order:
 // zs[3 spos[i] + c] = z_lam[3 i + c].
 int precond_apply(const BodyTables& b, const double* q, const double* x, double* z, double* yV,
-                  const int* spos, double* zs, int maxdim, hipStream_t s);
+                  const int* spos, double* zs, int maxdim, hipStream_t s, const int* skip = nullptr);
 // FD / RFD perturbations: displacements of each blob (M x NP x 3) and, for
 // RFD, the Philox normals of each body (N x 6).
 int fd_displacements(const BodyTables& b, const double* q, double delta, int mode,
@@ -258,7 +255,30 @@ int ortho_finish(const double* w, const double* V, long long ld, int k, const do
 // h2 then w.w) stored for the Hessenberg column.  partial1/2 hold
 // (k + 1) x ceil(n / 1024) doubles each.
 int arnoldi_orthogonalise(double* w, const double* V, long long ld, int k, long long n, double* partial1,
-                          double* partial2, double* out, double* h1, double* h2s, hipStream_t s);
+                          double* partial2, double* out, double* h1, double* h2s, hipStream_t s,
+                          const int* skip = nullptr);
+
+// Device-resident GMRES bookkeeping (restart length <= GM_MAXR).  The first
+// GM_STATUS_BYTES hold what the host polls: est, its, kdone, done, converged.
+constexpr int GM_MAXR = 64;
+struct GmresState {
+  double est;        // relative residual estimate
+  int its;           // iterations so far (all cycles)
+  int kdone;         // columns of the current cycle
+  int done;          // the current cycle is over
+  int converged;
+  double nb;         // |b|
+  double tol;
+  int maxit, pad;
+  double g[GM_MAXR + 1], cs[GM_MAXR], sn[GM_MAXR], y[GM_MAXR];
+  double H[(GM_MAXR + 1) * GM_MAXR];   // H[j * GM_MAXR + k]
+};
+constexpr size_t GM_STATUS_BYTES = 24;
+int gm_init(GmresState* st, const double* nb2, double tol, int maxit, hipStream_t s);
+int gm_cycle(GmresState* st, const double* beta2, hipStream_t s);
+int gm_column(GmresState* st, int k, int m, const double* h1, const double* h2, hipStream_t s);
+// y = H^-1 g over the cycle, then x += V y.
+int gm_finish_cycle(GmresState* st, double* x, const double* V, long long ld, long long n, hipStream_t s);
 int scale_by_inv_sqrt(const double* w, const double* nrm2, double* out, long long n,
                       hipStream_t s);
 int copy_scaled(const double* x, double a, double* y, long long n, hipStream_t s);

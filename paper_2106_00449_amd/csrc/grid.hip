@@ -5,7 +5,7 @@
 // beyond the cutoff radius rc (minimum-image distance, no renormalisation), so
 // J = dV S^T exactly.  Averaging: one 64-wide wavefront per blob walks the
 // blob's stencil.  Spreading: one workgroup per grid tile gathers the blobs
-// that reach it (see k_spread_tiles).  Positions arrive in FP64; each blob's offset to
+// that reach it (k_spread_sep).  Positions arrive in FP64; each blob's offset to
 // the first stencil point is formed in FP64 before any rounding to the grid
 // precision, so an FP32 grid does not lose the position to the box size.
 //
@@ -98,7 +98,8 @@ struct RigidTerm {
 template <typename R>
 __global__ __launch_bounds__(NT) void k_interp(GridGeom G, const double* __restrict__ r,
                                                const R* __restrict__ u, double* __restrict__ v, int M,
-                                               double scale, RigidTerm K) {
+                                               double scale, RigidTerm K, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int blob = blockIdx.x * WAVES + threadIdx.x / 64;
   const int lane = threadIdx.x & 63;
   if (blob >= M) return;
@@ -382,22 +383,78 @@ __device__ __forceinline__ Ranges axis_ranges(int g, int tstart, int Teff, int n
   return R;
 }
 
-// Spreading by gathering: one workgroup per tile of 8 x 8 x 32 points; thread
-// (j0, j1, b) owns the 8 points (j0, j1, 8b..8b+7) and keeps their three
-// force components in registers.  The blobs that reach the tile are collected
-// in LDS in candidate order (tiles are sorted by blob index), then every
-// thread adds each blob's Gaussian to its points: no atomics, one coalesced
-// write of the tile, and a fixed summation order.
+// Per-axis factor table of a spreading tile for hits h < nr: for tile offset
+// j < W along axis D, the stencil offset a = (ts + j - g) mod n; inside the
+// stencil (a < P, j < te) the factor exp(-d^2 / 2 sigma^2) (axis 0 also
+// carries wnorm) and d^2, else 0 and `big`.  Thread -> (hit, j) by shifts.
+template <typename R, int D, int W>
+__device__ __forceinline__ void table_axis(const GridGeom& G, int ts, int te, int nr, const double (*he)[3],
+                                           const int* hg, R (*tf)[W], R (*tsq)[W], R big) {
+  constexpr int LW = W == 8 ? 3 : 5;
+  static_assert(W == 8 || W == 32, "table width");
+  const int n = G.n[D], P = G.P[D];
+  const double dx = G.dx[D], i2 = G.inv2s2, wn = G.wnorm;
+  for (int e = threadIdx.x; e < nr * W; e += NT) {
+    const int h = e >> LW, j = e & (W - 1);
+    const int gb = (hg[h] >> (10 * D)) & 1023;
+    int a = ts + j - gb;
+    a += (a < 0) ? n : 0;
+    R fv = R(0), sv = big;
+    if (j < te && a < P) {
+      const double dd = he[h][D] + a * dx;
+      const double s2 = dd * dd;
+      sv = R(s2);
+      fv = gexp<R>(R(-s2 * i2));
+      if (D == 0) fv *= R(wn);
+    }
+    tf[h][j] = fv;
+    tsq[h][j] = sv;
+  }
+}
+
+// Spreading by gathering, one workgroup per tile of (up to) 8 x 8 x 32 grid
+// points.
+//  1. The blobs whose stencil box meets the tile are collected from the
+//     neighbouring tiles' sorted records into an LDS hit list, in a fixed
+//     order (tiles in neighbour order, blobs by index within a tile).
+//  2. The truncated Gaussian is separable, w = wnorm e0(d0) e1(d1) e2(d2) with
+//     the cut d0^2 + d1^2 + d2^2 <= rc^2, so each hit gets per-axis tables over
+//     the tile's coordinates (factor and squared distance; zero and a large
+//     value off the stencil), HR hits at a time.
+//  3. Wave w owns z-chunk w (8 consecutive axis-2 points), lane = (axis-1
+//     offset, point of the chunk), and keeps the 8 axis-0 planes of its
+//     point in registers.  Per hit it skips, wave-uniformly, a chunk the hit
+//     misses and the axis-0 planes outside the hit's stencil; a point costs a
+//     product, a compare and three multiply-adds.
+//  4. The tile goes through LDS and out with 16-byte stores, whole 128-byte
+//     rows at a time.
+// No atomics and a fixed summation order: results repeat bit for bit.
 template <typename R>
-__global__ __launch_bounds__(NT) void k_spread_gather(GridGeom G, TileGeom T, const SRec* __restrict__ rec,
-                                                      const int* __restrict__ off, const double* __restrict__ lam,
-                                                      const double* __restrict__ lam_sorted, R* __restrict__ f) {
-  constexpr int HMAX = 2 * NT;
+__global__ __launch_bounds__(NT) void k_spread_sep(GridGeom G, TileGeom T, const SRec* __restrict__ rec,
+                                                   const int* __restrict__ off, const double* __restrict__ lam,
+                                                   const double* __restrict__ lam_sorted, R* __restrict__ f,
+                                                   const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  constexpr int HMAX = NT;              // hits collected per scan
+  constexpr int HR = 64;                // hits per table round
+  constexpr int TX = 8, TZ = 32;        // tile shape the lane map assumes
+  constexpr int TAB = HR * (4 * TX + 2 * TZ);   // table entries per round
+  constexpr int TZP = sizeof(R) == 4 ? TZ + 1 : TZ;   // staged row stride (FP32: padded against bank conflicts)
+  constexpr int STAGE = 3 * TX * TX * TZP;     // staged tile
+  constexpr int SH = TAB > STAGE ? TAB : STAGE;
   __shared__ int nb_base[125], nb_pref[126];
-  __shared__ double hit_e[HMAX][3];
-  __shared__ R hit_l[HMAX][3];
-  __shared__ int hit_g[HMAX];
-  __shared__ int wave_cnt[2 * WAVES];
+  __shared__ double h_e[HMAX][3];       // stencil origin offsets of each hit
+  __shared__ int h_g[HMAX];             // packed stencil origin
+  __shared__ int h_mask[HMAX];          // bits 0-3: z-chunks the hit reaches; bits 8-15: axis-0 planes
+  __shared__ R h_l[HMAX][3];
+  __shared__ R sh[SH];                  // tables during accumulation, then the staged tile
+  __shared__ int wave_cnt[WAVES];
+  R (*t_f0)[TX] = reinterpret_cast<R (*)[TX]>(sh);                      // e0 (x wnorm)
+  R (*t_s0)[TX] = reinterpret_cast<R (*)[TX]>(sh + HR * TX);            // d0^2 (large off the stencil)
+  R (*t_f1)[TX] = reinterpret_cast<R (*)[TX]>(sh + 2 * HR * TX);
+  R (*t_s1)[TX] = reinterpret_cast<R (*)[TX]>(sh + 3 * HR * TX);
+  R (*t_fz)[TZ] = reinterpret_cast<R (*)[TZ]>(sh + 4 * HR * TX);
+  R (*t_sz)[TZ] = reinterpret_cast<R (*)[TZ]>(sh + HR * (4 * TX + TZ));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tl = blockIdx.x;
   const int t2 = tl % T.nt[2], t1 = (tl / T.nt[2]) % T.nt[1], t0 = tl / (T.nt[1] * T.nt[2]);
@@ -427,334 +484,124 @@ __global__ __launch_bounds__(NT) void k_spread_gather(GridGeom G, TileGeom T, co
   }
   __syncthreads();
   const int total = nb_pref[nnb];
-  // this thread's points
-  const int j0 = tid >> 5, j1 = (tid >> 2) & 7, zb = tid & 3;
-  const bool live = j0 < te[0] && j1 < te[1] && zb * 8 < te[2];
-  const R wn = R(G.wnorm), i2 = R(G.inv2s2);
-  R acc[8][3];
+  const R big = R(1e30);
+  const R rc2 = R(G.rc2);
+  const int j1 = lane >> 3, zl = lane & 7, z = wave * 8 + zl;
+  const bool live = j1 < te[1] && z < te[2];
+  R acc[TX][3];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) acc[k][0] = acc[k][1] = acc[k][2] = R(0);
-  for (int base = 0; base < total; base += HMAX) {
-    // compact the hits of this round in candidate order
-    int hslot[2];
-    bool hflag[2];
-    SRec hx[2];
-    double hl[2][3];
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      const int ci = base + half * NT + tid;
-      hflag[half] = false;
-      if (ci < total) {
-        int k = 0;
-        while (nb_pref[k + 1] <= ci) ++k;
-        const int pos = nb_base[k] + (ci - nb_pref[k]);
-        hx[half] = rec[pos];
-        const SRec& x = hx[half];
-        if (lam_sorted) {
-          hl[half][0] = lam_sorted[3LL * pos];
-          hl[half][1] = lam_sorted[3LL * pos + 1];
-          hl[half][2] = lam_sorted[3LL * pos + 2];
-        } else {
-          hl[half][0] = lam[3LL * x.blob];
-          hl[half][1] = lam[3LL * x.blob + 1];
-          hl[half][2] = lam[3LL * x.blob + 2];
-        }
-        const int gb[3] = {x.g & 1023, (x.g >> 10) & 1023, (x.g >> 20) & 1023};
-        bool hit = true;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          const Ranges Rg = axis_ranges(gb[d], ts[d], te[d], G.n[d], G.P[d]);
-          hit = hit && (Rg.l1 + Rg.l2 > 0);
-        }
-        hflag[half] = hit;
+  for (int k = 0; k < TX; ++k) acc[k][0] = acc[k][1] = acc[k][2] = R(0);
+  for (int cbase = 0; cbase < total; cbase += NT) {
+    // 1. candidates cbase .. cbase + NT, one per thread
+    bool hit = false;
+    int pos = 0, hmask = 0;
+    SRec x;
+    if (cbase + tid < total) {
+      const int ci = cbase + tid;
+      int lo = 0, hi = nnb;   // neighbour tile k with nb_pref[k] <= ci < nb_pref[k + 1]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (nb_pref[mid] <= ci) lo = mid; else hi = mid;
       }
-      const unsigned long long m = __ballot(hflag[half]);
-      hslot[half] = __popcll(m & ((1ull << lane) - 1ull));
-      if (lane == 0) wave_cnt[half * WAVES + wave] = __popcll(m);
-    }
-    __syncthreads();
-    int nh = 0;
+      pos = nb_base[lo] + (ci - nb_pref[lo]);
+      x = rec[pos];
+      const int gb[3] = {x.g & 1023, (x.g >> 10) & 1023, (x.g >> 20) & 1023};
+      hit = true;
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      int before = nh;
-      for (int w = 0; w < WAVES; ++w) {
-        if (w < wave) before += wave_cnt[half * WAVES + w];
-        nh += wave_cnt[half * WAVES + w];
-      }
-      if (hflag[half]) {
-        const int slot = before + hslot[half];
-        hit_e[slot][0] = hx[half].e[0];
-        hit_e[slot][1] = hx[half].e[1];
-        hit_e[slot][2] = hx[half].e[2];
-        hit_g[slot] = hx[half].g;
-        hit_l[slot][0] = R(hl[half][0]);
-        hit_l[slot][1] = R(hl[half][1]);
-        hit_l[slot][2] = R(hl[half][2]);
+      for (int d = 0; d < 3; ++d) {
+        const Ranges Rg = axis_ranges(gb[d], ts[d], te[d], G.n[d], G.P[d]);
+        hit = hit && (Rg.l1 + Rg.l2 > 0);
+        if (d == 0) {
+          // axis-0 planes [s1, s1 + l1) and [s2, s2 + l2) of the tile
+          const int m1 = Rg.l1 > 0 ? ((1 << Rg.l1) - 1) << Rg.s1 : 0;
+          const int m2 = Rg.l2 > 0 ? ((1 << Rg.l2) - 1) << Rg.s2 : 0;
+          hmask |= (m1 | m2) << 8;
+        } else if (d == 2) {
+          // z-chunks covered by [s1, s1 + l1) and [s2, s2 + l2)
+          if (Rg.l1 > 0)
+            for (int q = Rg.s1 >> 3; q <= (Rg.s1 + Rg.l1 - 1) >> 3; ++q) hmask |= 1 << q;
+          if (Rg.l2 > 0)
+            for (int q = Rg.s2 >> 3; q <= (Rg.s2 + Rg.l2 - 1) >> 3; ++q) hmask |= 1 << q;
+        }
       }
     }
+    const unsigned long long m = __ballot(hit);
+    if (lane == 0) wave_cnt[wave] = __popcll(m);
     __syncthreads();
-    if (live) {
-      for (int h = 0; h < nh; ++h) {
-        const int g = hit_g[h];
-        int a0 = ts[0] + j0 - (g & 1023);
-        a0 += (a0 < 0) ? G.n[0] : 0;
-        int a1 = ts[1] + j1 - ((g >> 10) & 1023);
-        a1 += (a1 < 0) ? G.n[1] : 0;
-        if (a0 >= G.P[0] || a1 >= G.P[1]) continue;
-        const double d0 = hit_e[h][0] + a0 * G.dx[0];
-        const double d1 = hit_e[h][1] + a1 * G.dx[1];
-        const double d01 = d0 * d0 + d1 * d1;
-        if (d01 > G.rc2) continue;
-        int a2 = ts[2] + zb * 8 - ((g >> 20) & 1023);
-        a2 += (a2 < 0) ? G.n[2] : 0;
-        const double e2 = hit_e[h][2];
-        const R l0 = hit_l[h][0], l1 = hit_l[h][1], l2 = hit_l[h][2];
+    int before = 0, nh = 0;
+    for (int w = 0; w < WAVES; ++w) {
+      if (w < wave) before += wave_cnt[w];
+      nh += wave_cnt[w];
+    }
+    if (hit) {
+      const int slot = before + __popcll(m & ((1ull << lane) - 1ull));
+      h_e[slot][0] = x.e[0];
+      h_e[slot][1] = x.e[1];
+      h_e[slot][2] = x.e[2];
+      h_g[slot] = x.g;
+      h_mask[slot] = hmask;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const int ak = (a2 + k >= G.n[2]) ? a2 + k - G.n[2] : a2 + k;
-          const double dz = e2 + ak * G.dx[2];
-          const double dd = d01 + dz * dz;
-          if (ak < G.P[2] && dd <= G.rc2) {
-            const R w = wn * gexp<R>(-R(dd) * i2);
+      for (int q = 0; q < 3; ++q) h_l[slot][q] = R(lam_sorted ? lam_sorted[3LL * pos + q] : lam[3LL * x.blob + q]);
+    }
+    __syncthreads();
+    for (int hb = 0; hb < nh; hb += HR) {
+      const int nr = min(HR, nh - hb);
+      // 2. per-axis tables; the axis is a compile-time constant in each loop
+      //    (a runtime index into the kernel-argument struct would be a
+      //    memory load per entry)
+      table_axis<R, 0, TX>(G, ts[0], te[0], nr, h_e + hb, h_g + hb, t_f0, t_s0, big);
+      table_axis<R, 1, TX>(G, ts[1], te[1], nr, h_e + hb, h_g + hb, t_f1, t_s1, big);
+      table_axis<R, 2, TZ>(G, ts[2], te[2], nr, h_e + hb, h_g + hb, t_fz, t_sz, big);
+      __syncthreads();
+      // 3. accumulate
+      if (live) {
+        for (int h = 0; h < nr; ++h) {
+          const int hm = h_mask[hb + h];
+          if (!((hm >> wave) & 1)) continue;
+          const R s12 = t_s1[h][j1] + t_sz[h][z];
+          if (s12 > rc2) continue;
+          const R f12 = t_f1[h][j1] * t_fz[h][z];
+          const R l0 = h_l[hb + h][0], l1 = h_l[hb + h][1], l2 = h_l[hb + h][2];
+#pragma unroll
+          for (int k = 0; k < TX; ++k) {
+            if (!((hm >> (8 + k)) & 1)) continue;
+            const R w = (t_s0[h][k] + s12 <= rc2) ? f12 * t_f0[h][k] : R(0);
             acc[k][0] += w * l0;
             acc[k][1] += w * l1;
             acc[k][2] += w * l2;
           }
         }
       }
-    }
-    __syncthreads();
-  }
-  if (live) {
-    const long long Gs = G.G;
-    const long long row = ((long long)(ts[0] + j0) * G.n[1] + (ts[1] + j1)) * G.n[2] + ts[2] + zb * 8;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      if (zb * 8 + k < te[2]) {
-        f[row + k] = acc[k][0];
-        f[Gs + row + k] = acc[k][1];
-        f[2 * Gs + row + k] = acc[k][2];
-      }
-    }
-  }
-}
-
-// One workgroup per tile.  MODE 0 (spreading): the tile's field starts at
-// zero in LDS, every blob that reaches the tile adds its Gaussian with LDS
-// atomics, and the tile is written once.  MODE 1 (averaging): the tile's field
-// is read once into LDS with coalesced loads, every blob that reaches the tile
-// forms its partial sum over the tile from LDS, and the partial sums are added
-// to the blob velocities with one FP64 global atomic per blob, tile and
-// component.  LDS rows are padded by one element so that lanes walking a
-// stencil cross-section hit distinct banks.
-template <typename R, int MODE>
-__global__ __launch_bounds__(NT) void k_tile_op(GridGeom G, TileGeom T, const SRec* __restrict__ rec,
-                                                const int* __restrict__ off, const double* __restrict__ lam,
-                                                const double* __restrict__ lam_sorted, R* __restrict__ f,
-                                                const R* __restrict__ u, double* __restrict__ v, double scale) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  R* acc = reinterpret_cast<R*>(smem);
-  const int RS = T.T[2] + 1, PS = T.T[1] * RS, CS = T.T[0] * PS;
-  const int TP = T.T[0] * T.T[1] * T.T[2];
-  __shared__ int nb_base[125], nb_pref[126];
-  constexpr int HMAX = 2 * NT;   // candidates tested per round
-  __shared__ double hit_e[HMAX][3];
-  __shared__ double hit_l[HMAX][3];
-  __shared__ int hit_g[HMAX];
-  __shared__ int hit_b[HMAX];
-  __shared__ int nhit;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tl = blockIdx.x;
-  const int t2 = tl % T.nt[2], t1 = (tl / T.nt[2]) % T.nt[1], t0 = tl / (T.nt[1] * T.nt[2]);
-  const int tt[3] = {t0, t1, t2};
-  const int ts[3] = {t0 * T.T[0], t1 * T.T[1], t2 * T.T[2]};
-  const int te[3] = {min(T.T[0], G.n[0] - ts[0]), min(T.T[1], G.n[1] - ts[1]), min(T.T[2], G.n[2] - ts[2])};
-  const long long Gs = G.G;
-  int c[3], st[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    c[d] = min(2 * T.H[d] + 1, T.nt[d]);
-    st[d] = (c[d] == T.nt[d]) ? 0 : tt[d] - T.H[d];
-  }
-  const int nnb = c[0] * c[1] * c[2];
-  for (int p = tid; p < TP; p += NT) {
-    const int j2 = p % T.T[2], j1 = (p / T.T[2]) % T.T[1], j0 = p / (T.T[1] * T.T[2]);
-    const int q = j0 * PS + j1 * RS + j2;
-    if (MODE == 0) {
-      acc[q] = R(0);
-      acc[CS + q] = R(0);
-      acc[2 * CS + q] = R(0);
-    } else {
-      R x0 = 0, x1 = 0, x2 = 0;
-      if (j0 < te[0] && j1 < te[1] && j2 < te[2]) {
-        const long long idx = ((long long)(ts[0] + j0) * G.n[1] + (ts[1] + j1)) * G.n[2] + ts[2] + j2;
-        x0 = u[idx];
-        x1 = u[Gs + idx];
-        x2 = u[2 * Gs + idx];
-      }
-      acc[q] = x0;
-      acc[CS + q] = x1;
-      acc[2 * CS + q] = x2;
-    }
-  }
-  if (tid < nnb) {
-    const int i2 = tid % c[2], i1 = (tid / c[2]) % c[1], i0 = tid / (c[1] * c[2]);
-    const int a0 = ((st[0] + i0) % T.nt[0] + T.nt[0]) % T.nt[0];
-    const int a1 = ((st[1] + i1) % T.nt[1] + T.nt[1]) % T.nt[1];
-    const int a2 = ((st[2] + i2) % T.nt[2] + T.nt[2]) % T.nt[2];
-    const int nt = (a0 * T.nt[1] + a1) * T.nt[2] + a2;
-    nb_base[tid] = off[nt];
-    nb_pref[tid + 1] = off[nt + 1] - off[nt];
-  }
-  __syncthreads();
-  if (tid == 0) {
-    nb_pref[0] = 0;
-    for (int k = 1; k <= nnb; ++k) nb_pref[k] += nb_pref[k - 1];
-  }
-  __syncthreads();
-  const int total = nb_pref[nnb];
-  const R wn = R(G.wnorm), i2 = R(G.inv2s2);
-  for (int base = 0; base < total; base += HMAX) {
-    if (tid == 0) nhit = 0;
-    __syncthreads();
-    // each thread tests two candidates; a hit's record (and forces) go to LDS
-#pragma unroll
-    for (int half = 0; half < HMAX / NT; ++half) {
-      const int ci = base + half * NT + tid;
-      if (ci < total) {
-        int k = 0;
-        while (nb_pref[k + 1] <= ci) ++k;
-        const int pos = nb_base[k] + (ci - nb_pref[k]);
-        const SRec x = rec[pos];
-        double la = 0, lb = 0, lc = 0;
-        if (MODE == 0) {
-          if (lam_sorted) {
-            la = lam_sorted[3LL * pos];
-            lb = lam_sorted[3LL * pos + 1];
-            lc = lam_sorted[3LL * pos + 2];
-          } else {
-            la = lam[3LL * x.blob];
-            lb = lam[3LL * x.blob + 1];
-            lc = lam[3LL * x.blob + 2];
-          }
-        }
-        const int gb[3] = {x.g & 1023, (x.g >> 10) & 1023, (x.g >> 20) & 1023};
-        bool hit = true;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          const Ranges Rg = axis_ranges(gb[d], ts[d], te[d], G.n[d], G.P[d]);
-          hit = hit && (Rg.l1 + Rg.l2 > 0);
-        }
-        if (hit) {
-          const int slot = atomicAdd(&nhit, 1);
-          hit_e[slot][0] = x.e[0];
-          hit_e[slot][1] = x.e[1];
-          hit_e[slot][2] = x.e[2];
-          hit_g[slot] = x.g;
-          hit_b[slot] = x.blob;
-          hit_l[slot][0] = la;
-          hit_l[slot][1] = lb;
-          hit_l[slot][2] = lc;
-        }
-      }
-    }
-    __syncthreads();
-    // work items (hit, stencil column): item = hit * S + pair, pair < c1 c2,
-    // spread over all threads of the block
-    const int nh = nhit;
-    const int S = T.S;
-    for (int it = tid; it < nh * S; it += NT) {
-      const int h = it / S, pr = it - h * S;
-      const int g = hit_g[h];
-      const int gb1 = (g >> 10) & 1023, gb2 = (g >> 20) & 1023;
-      const Ranges R1 = axis_ranges(gb1, ts[1], te[1], G.n[1], G.P[1]);
-      const Ranges R2 = axis_ranges(gb2, ts[2], te[2], G.n[2], G.P[2]);
-      const int c1 = R1.l1 + R1.l2, c2 = R2.l1 + R2.l2;
-      if (pr >= c1 * c2) continue;
-      const int gb0 = g & 1023;
-      const Ranges R0 = axis_ranges(gb0, ts[0], te[0], G.n[0], G.P[0]);
-      const int c0 = R0.l1 + R0.l2;
-      const int i1 = pr / c2, i2c = pr - i1 * c2;
-      const int j1 = i1 < R1.l1 ? R1.s1 + i1 : R1.s2 + (i1 - R1.l1);
-      const int j2 = i2c < R2.l1 ? R2.s1 + i2c : R2.s2 + (i2c - R2.l1);
-      int a1 = ts[1] + j1 - gb1;
-      a1 += (a1 < 0) ? G.n[1] : 0;
-      int a2 = ts[2] + j2 - gb2;
-      a2 += (a2 < 0) ? G.n[2] : 0;
-      const double d1 = hit_e[h][1] + a1 * G.dx[1], d2 = hit_e[h][2] + a2 * G.dx[2];
-      const double d12 = d1 * d1 + d2 * d2;
-      if (d12 > G.rc2) continue;
-      const double e0 = hit_e[h][0];
-      R s0 = 0, s1 = 0, s2 = 0;
-      const R l0 = R(hit_l[h][0]), l1 = R(hit_l[h][1]), l2 = R(hit_l[h][2]);
-      for (int i0 = 0; i0 < c0; ++i0) {
-        const int j0 = i0 < R0.l1 ? R0.s1 + i0 : R0.s2 + (i0 - R0.l1);
-        int a0 = ts[0] + j0 - gb0;
-        a0 += (a0 < 0) ? G.n[0] : 0;
-        const double d0 = e0 + a0 * G.dx[0];
-        const double dd = d0 * d0 + d12;
-        if (dd <= G.rc2) {
-          const R w = wn * gexp<R>(-R(dd) * i2);
-          const int q = j0 * PS + j1 * RS + j2;
-          if (MODE == 0) {
-            atomicAdd(acc + q, w * l0);
-            atomicAdd(acc + CS + q, w * l1);
-            atomicAdd(acc + 2 * CS + q, w * l2);
-          } else {
-            s0 += w * acc[q];
-            s1 += w * acc[CS + q];
-            s2 += w * acc[2 * CS + q];
-          }
-        }
-      }
-      if (MODE == 1) {
-        atomicAdd(&hit_l[h][0], (double)s0);
-        atomicAdd(&hit_l[h][1], (double)s1);
-        atomicAdd(&hit_l[h][2], (double)s2);
-      }
-    }
-    if (MODE == 1) {
       __syncthreads();
-      for (int h = tid; h < nh; h += NT) {
-        const int b = hit_b[h];
-        atomicAdd(v + 3LL * b, scale * hit_l[h][0]);
-        atomicAdd(v + 3LL * b + 1, scale * hit_l[h][1]);
-        atomicAdd(v + 3LL * b + 2, scale * hit_l[h][2]);
-      }
-    }
-    __syncthreads();
-  }
-  if (MODE == 0) {
-    for (int p = tid; p < TP; p += NT) {
-      const int j2 = p % T.T[2], j1 = (p / T.T[2]) % T.T[1], j0 = p / (T.T[1] * T.T[2]);
-      if (j0 < te[0] && j1 < te[1] && j2 < te[2]) {
-        const long long idx = ((long long)(ts[0] + j0) * G.n[1] + (ts[1] + j1)) * G.n[2] + ts[2] + j2;
-        const int q = j0 * PS + j1 * RS + j2;
-        f[idx] = acc[q];
-        f[Gs + idx] = acc[CS + q];
-        f[2 * Gs + idx] = acc[2 * CS + q];
-      }
     }
   }
-}
-
-// v_i = -(U_p + Omega_p x (r_i - Y_p)) (rigid term of the saddle operator),
-// or 0; the tiled averaging then adds dV J u.
-__global__ void k_interp_init(const double* __restrict__ r, int M, RigidTerm K, double* __restrict__ v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M) return;
-  double o[3] = {0.0, 0.0, 0.0};
-  if (K.V) {
-    const int p = K.blob_body[i];
-    const double* Vp = K.V + 6LL * p;
-    const double rel[3] = {r[3LL * i] - K.Y[3LL * p], r[3LL * i + 1] - K.Y[3LL * p + 1], r[3LL * i + 2] - K.Y[3LL * p + 2]};
-    o[0] = -(Vp[0] + (Vp[4] * rel[2] - Vp[5] * rel[1]));
-    o[1] = -(Vp[1] + (Vp[5] * rel[0] - Vp[3] * rel[2]));
-    o[2] = -(Vp[2] + (Vp[3] * rel[1] - Vp[4] * rel[0]));
+  // 4. stage [c][axis-0][axis-1][z] and write rows with 16-byte stores
+#pragma unroll
+  for (int k = 0; k < TX; ++k) {
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) sh[(cc * TX * TX + k * TX + j1) * TZP + z] = acc[k][cc];
   }
-  v[3LL * i] = o[0];
-  v[3LL * i + 1] = o[1];
-  v[3LL * i + 2] = o[2];
+  __syncthreads();
+  constexpr int VW = 16 / sizeof(R);   // values per 16-byte store
+  constexpr int NV = TZ / VW;          // stores per row
+  const long long Gs = G.G;
+  for (int p = tid; p < 3 * TX * TX * NV; p += NT) {
+    const int cc = p / (TX * TX * NV), rem = p - cc * (TX * TX * NV);
+    const int col = rem / NV, zv = (rem - col * NV) * VW;
+    const int c0 = col >> 3, c1 = col & 7;
+    if (c0 >= te[0] || c1 >= te[1] || zv >= te[2]) continue;
+    const long long idx = cc * Gs + ((long long)(ts[0] + c0) * G.n[1] + (ts[1] + c1)) * G.n[2] + ts[2] + zv;
+    const R* src = sh + (cc * TX * TX + col) * TZP + zv;
+    if (zv + VW <= te[2]) {
+      if constexpr (sizeof(R) == 4) {
+        *reinterpret_cast<float4*>(f + idx) = make_float4(src[0], src[1], src[2], src[3]);
+      } else {
+        *reinterpret_cast<double2*>(f + idx) = make_double2(src[0], src[1]);
+      }
+    } else {
+      for (int v = 0; zv + v < te[2]; ++v) f[idx + v] = src[v];
+    }
+  }
 }
 
 __global__ void k_fill_zero(uint4* __restrict__ p, long long n16) {
@@ -815,43 +662,25 @@ int tile_sort(const GridGeom& g, const TileGeom& t, const double* r, int M, int*
 }
 
 template <typename R>
-size_t tile_lds_bytes(const TileGeom& t) {
-  return 3 * (size_t)t.T[0] * t.T[1] * (t.T[2] + 1) * sizeof(R);
-}
-
-template <typename R>
 int spread(const GridGeom& g, const TileGeom& t, const void* rec, const double* lam, const double* lam_sorted,
-           const int* off, R* f, hipStream_t s) {
+           const int* off, R* f, hipStream_t s, const int* skip) {
   if (t.T[0] > 8 || t.T[1] > 8 || t.T[2] > 32) {
     set_error("spread: tiles larger than 8 x 8 x 32");
     return GDC_EINVAL;
   }
   ProbeScope ps("spread", s);
-  hipLaunchKernelGGL((k_spread_gather<R>), dim3(t.ntiles), dim3(NT), 0, s, g, t, (const SRec*)rec, off, lam,
-                     lam_sorted, f);
-  return check_launch("k_spread_gather");
-}
-
-template <typename R>
-int interp_tiles(const GridGeom& g, const TileGeom& t, const void* rec, const int* off, const double* r,
-                 const R* u, double* v, int M, double scale, const int* blob_body, const double* Y,
-                 const double* V, hipStream_t s) {
-  if (M <= 0) return GDC_OK;
-  RigidTerm K{blob_body, Y, V};
-  hipLaunchKernelGGL(k_interp_init, dim3((M + 255) / 256), dim3(256), 0, s, r, M, K, v);
-  GDC_TRY(check_launch("k_interp_init"));
-  hipLaunchKernelGGL((k_tile_op<R, 1>), dim3(t.ntiles), dim3(NT), tile_lds_bytes<R>(t), s, g, t, (const SRec*)rec,
-                     off, (const double*)nullptr, (const double*)nullptr, (R*)nullptr, u, v, scale);
-  return check_launch("k_tile_op<interp>");
+  hipLaunchKernelGGL((k_spread_sep<R>), dim3(t.ntiles), dim3(NT), 0, s, g, t, (const SRec*)rec, off, lam,
+                     lam_sorted, f, skip);
+  return check_launch("k_spread_sep");
 }
 
 template <typename R>
 int interp(const GridGeom& g, const double* r, const R* u, double* v, int M, double scale,
-           const int* blob_body, const double* Y, const double* V, hipStream_t s) {
+           const int* blob_body, const double* Y, const double* V, hipStream_t s, const int* skip) {
   if (M <= 0) return GDC_OK;
   RigidTerm K{blob_body, Y, V};
   ProbeScope ps("interp", s);
-  hipLaunchKernelGGL((k_interp<R>), dim3(blocks_for(M)), dim3(NT), 0, s, g, r, u, v, M, scale, K);
+  hipLaunchKernelGGL((k_interp<R>), dim3(blocks_for(M)), dim3(NT), 0, s, g, r, u, v, M, scale, K, skip);
   return check_launch("k_interp");
 }
 
@@ -874,19 +703,13 @@ int interp_fd(const GridGeom& g, const double* r, const double* dr, int NP, cons
 }
 
 template int spread<float>(const GridGeom&, const TileGeom&, const void*, const double*, const double*, const int*,
-                           float*, hipStream_t);
+                           float*, hipStream_t, const int*);
 template int spread<double>(const GridGeom&, const TileGeom&, const void*, const double*, const double*, const int*,
-                            double*, hipStream_t);
+                            double*, hipStream_t, const int*);
 template int interp<float>(const GridGeom&, const double*, const float*, double*, int, double, const int*,
-                           const double*, const double*, hipStream_t);
-template int interp_tiles<float>(const GridGeom&, const TileGeom&, const void*, const int*, const double*,
-                                 const float*, double*, int, double, const int*, const double*, const double*,
-                                 hipStream_t);
-template int interp_tiles<double>(const GridGeom&, const TileGeom&, const void*, const int*, const double*,
-                                  const double*, double*, int, double, const int*, const double*, const double*,
-                                  hipStream_t);
+                           const double*, const double*, hipStream_t, const int*);
 template int interp<double>(const GridGeom&, const double*, const double*, double*, int, double, const int*,
-                            const double*, const double*, hipStream_t);
+                            const double*, const double*, hipStream_t, const int*);
 template int interp_fd<float>(const GridGeom&, const double*, const double*, int, const float*, double*,
                               double*, int, hipStream_t);
 template int interp_fd<double>(const GridGeom&, const double*, const double*, int, const double*, double*,

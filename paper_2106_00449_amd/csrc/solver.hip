@@ -84,7 +84,8 @@ __device__ __forceinline__ void wave_reduce_to(double v, double* slot) {
 // load of a block independent.
 __global__ __launch_bounds__(NT) void k_dot2d(const double* __restrict__ V, long long ld, int k,
                                               const double* __restrict__ w, long long n,
-                                              double* __restrict__ partial) {
+                                              double* __restrict__ partial, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double sh[NT / 64];
   const int j = blockIdx.y;
   const double* v = j < k ? V + ld * j : w;
@@ -119,7 +120,9 @@ __device__ __forceinline__ void reduce_rows(const double* __restrict__ partial, 
 // w -= V h1 with h1 reduced from partial1 (k rows); block 0 stores h1.
 __global__ __launch_bounds__(NT) void k_axpy_partial(double* __restrict__ w, const double* __restrict__ V,
                                                      long long ld, int k, const double* __restrict__ partial1,
-                                                     long long n, double* __restrict__ hout) {
+                                                     long long n, double* __restrict__ hout,
+                                                     const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double hs[MAXK];
   reduce_rows(partial1, k, gridDim.x, hs);
   __syncthreads();
@@ -142,7 +145,9 @@ __global__ __launch_bounds__(NT) void k_axpy_partial(double* __restrict__ w, con
 // Block 0 stores h2 and s in hout.
 __global__ __launch_bounds__(NT) void k_ortho_finish2(const double* __restrict__ w, const double* __restrict__ V,
                                                       long long ld, int k, const double* __restrict__ partial2,
-                                                      long long n, double* __restrict__ out, double* __restrict__ hout) {
+                                                      long long n, double* __restrict__ out, double* __restrict__ hout,
+                                                      const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double hs[MAXK];
   __shared__ double scale;
   reduce_rows(partial2, k + 1, gridDim.x, hs);
@@ -226,6 +231,113 @@ __global__ void k_sub_from(const double* __restrict__ b, double* __restrict__ w,
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) w[e] = b[e] - w[e];
 }
 
+// ------------------------------------------------------------ GMRES bookkeeping
+// The Hessenberg matrix, its Givens rotations and the residual estimate live
+// on the device (GmresState), updated by one single-thread kernel per
+// iteration, so the host can queue iterations ahead of the GPU; `done` ends a
+// restart cycle and makes the queued kernels of later iterations return.
+
+__global__ void k_gm_init(GmresState* st, const double* __restrict__ nb2, double tol, int maxit) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double nb = sqrt(fmax(nb2[0], 0.0));
+  st->nb = nb;
+  st->tol = tol;
+  st->maxit = maxit;
+  st->its = 0;
+  st->kdone = 0;
+  st->converged = nb == 0.0 ? 1 : 0;
+  st->done = st->converged;
+  st->est = nb == 0.0 ? 0.0 : 1.0;
+}
+
+// Start of a restart cycle with residual norm^2 beta2: g = (beta, 0, ...).
+__global__ void k_gm_cycle(GmresState* st, const double* __restrict__ beta2) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st->kdone = 0;
+  if (st->converged) {
+    st->done = 1;
+    return;
+  }
+  const double beta = sqrt(fmax(beta2[0], 0.0));
+  st->est = beta / st->nb;
+  st->g[0] = beta;
+  if (st->est <= st->tol) {
+    st->converged = 1;
+    st->done = 1;
+  } else {
+    st->done = st->its >= st->maxit ? 1 : 0;
+  }
+}
+
+// Column k of the Hessenberg matrix from the Gram-Schmidt coefficients:
+// H[j][k] = h1[j] + h2[j] (j <= k), H[k+1][k] = sqrt(w.w - |h2|^2) with
+// w.w = h2[k+1]; then the previous rotations, a new one, and the residual
+// estimate |g[k+1]| / |b|.
+__global__ void k_gm_column(GmresState* st, int k, int m, const double* __restrict__ h1,
+                            const double* __restrict__ h2) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (st->done) return;
+  double* H = st->H;
+  double h2sq = 0.0;
+  for (int j = 0; j <= k; ++j) {
+    H[j * GM_MAXR + k] = h1[j] + h2[j];
+    h2sq += h2[j] * h2[j];
+  }
+  H[(k + 1) * GM_MAXR + k] = sqrt(fmax(0.0, h2[k + 1] - h2sq));
+  for (int j = 0; j < k; ++j) {
+    const double a = H[j * GM_MAXR + k], b = H[(j + 1) * GM_MAXR + k];
+    H[j * GM_MAXR + k] = st->cs[j] * a + st->sn[j] * b;
+    H[(j + 1) * GM_MAXR + k] = -st->sn[j] * a + st->cs[j] * b;
+  }
+  const double a = H[k * GM_MAXR + k], b = H[(k + 1) * GM_MAXR + k];
+  const double den = hypot(a, b);
+  st->cs[k] = den > 0.0 ? a / den : 1.0;
+  st->sn[k] = den > 0.0 ? b / den : 0.0;
+  H[k * GM_MAXR + k] = den;
+  H[(k + 1) * GM_MAXR + k] = 0.0;
+  const double gk = st->g[k];
+  st->g[k + 1] = -st->sn[k] * gk;
+  st->g[k] = st->cs[k] * gk;
+  st->its += 1;
+  st->kdone = k + 1;
+  st->est = fabs(st->g[k + 1]) / st->nb;
+  if (st->est <= st->tol) {
+    st->converged = 1;
+    st->done = 1;
+  } else if (st->its >= st->maxit || den == 0.0 || k + 1 >= m) {
+    st->done = 1;
+  }
+}
+
+// y = H^-1 g over the cycle's kdone columns (back substitution).
+__global__ void k_gm_solve(GmresState* st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int kd = st->kdone;
+  const double* H = st->H;
+  for (int i = kd - 1; i >= 0; --i) {
+    double t = st->g[i];
+    for (int j = i + 1; j < kd; ++j) t -= H[i * GM_MAXR + j] * st->y[j];
+    const double d = H[i * GM_MAXR + i];
+    st->y[i] = d != 0.0 ? t / d : 0.0;
+  }
+}
+
+// x += sum_{j < st->kdone} y_j V_j
+__global__ __launch_bounds__(NT) void k_gm_update(double* __restrict__ x, const double* __restrict__ V,
+                                                  long long ld, const GmresState* __restrict__ st,
+                                                  long long n) {
+  __shared__ double ys[GM_MAXR];
+  const int k = st->kdone;
+  for (int j = threadIdx.x; j < k; j += NT) ys[j] = st->y[j];
+  __syncthreads();
+  const long long stride = (long long)gridDim.x * NT;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < n; e += stride) {
+    double acc = 0.0;
+    for (int j = 0; j < k; ++j) acc += ys[j] * V[ld * j + e];
+    x[e] += acc;
+  }
+}
+
 inline unsigned grid_for(long long n) {
   const long long b = (n + NT - 1) / NT;
   return (unsigned)(b < 1024 ? (b > 0 ? b : 1) : 1024);
@@ -269,7 +381,8 @@ int ortho_finish(const double* w, const double* V, long long ld, int k, const do
 }
 
 int arnoldi_orthogonalise(double* w, const double* V, long long ld, int k, long long n, double* partial1,
-                          double* partial2, double* out, double* h1, double* h2s, hipStream_t s) {
+                          double* partial2, double* out, double* h1, double* h2s, hipStream_t s,
+                          const int* skip) {
   if (k < 1 || k + 1 >= MAXK) {
     set_error("arnoldi_orthogonalise: basis size out of range");
     return GDC_EINVAL;
@@ -279,14 +392,40 @@ int arnoldi_orthogonalise(double* w, const double* V, long long ld, int k, long 
     set_error("arnoldi_orthogonalise: vector too long");
     return GDC_EINVAL;
   }
-  hipLaunchKernelGGL(k_dot2d, dim3(nchunk, k), dim3(NT), 0, s, V, ld, k, (const double*)w, n, partial1);
+  hipLaunchKernelGGL(k_dot2d, dim3(nchunk, k), dim3(NT), 0, s, V, ld, k, (const double*)w, n, partial1, skip);
   GDC_TRY(check_launch("k_dot2d"));
-  hipLaunchKernelGGL(k_axpy_partial, dim3(nchunk), dim3(NT), 0, s, w, V, ld, k, partial1, n, h1);
+  hipLaunchKernelGGL(k_axpy_partial, dim3(nchunk), dim3(NT), 0, s, w, V, ld, k, partial1, n, h1, skip);
   GDC_TRY(check_launch("k_axpy_partial"));
-  hipLaunchKernelGGL(k_dot2d, dim3(nchunk, k + 1), dim3(NT), 0, s, V, ld, k, (const double*)w, n, partial2);
+  hipLaunchKernelGGL(k_dot2d, dim3(nchunk, k + 1), dim3(NT), 0, s, V, ld, k, (const double*)w, n, partial2, skip);
   GDC_TRY(check_launch("k_dot2d"));
-  hipLaunchKernelGGL(k_ortho_finish2, dim3(nchunk), dim3(NT), 0, s, w, V, ld, k, partial2, n, out, h2s);
+  hipLaunchKernelGGL(k_ortho_finish2, dim3(nchunk), dim3(NT), 0, s, w, V, ld, k, partial2, n, out, h2s, skip);
   return check_launch("k_ortho_finish2");
+}
+
+int gm_init(GmresState* st, const double* nb2, double tol, int maxit, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(64), 0, s, st, nb2, tol, maxit);
+  return check_launch("k_gm_init");
+}
+
+int gm_cycle(GmresState* st, const double* beta2, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_cycle, dim3(1), dim3(64), 0, s, st, beta2);
+  return check_launch("k_gm_cycle");
+}
+
+int gm_column(GmresState* st, int k, int m, const double* h1, const double* h2, hipStream_t s) {
+  if (k < 0 || k >= m || m > GM_MAXR) {
+    set_error("gm_column: column out of range");
+    return GDC_EINVAL;
+  }
+  hipLaunchKernelGGL(k_gm_column, dim3(1), dim3(64), 0, s, st, k, m, h1, h2);
+  return check_launch("k_gm_column");
+}
+
+int gm_finish_cycle(GmresState* st, double* x, const double* V, long long ld, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(64), 0, s, st);
+  GDC_TRY(check_launch("k_gm_solve"));
+  hipLaunchKernelGGL(k_gm_update, dim3(grid_for(n)), dim3(NT), 0, s, x, V, ld, (const GmresState*)st, n);
+  return check_launch("k_gm_update");
 }
 
 int scale_by_inv_sqrt(const double* w, const double* nrm2, double* out, long long n, hipStream_t s) {
