@@ -297,6 +297,7 @@ struct gdc_handle {
   double* hhost = nullptr;   // pinned readback
   GmresState* gm = nullptr;  // device GMRES bookkeeping
   unsigned char* gm_host = nullptr;   // pinned: two status slots
+  unsigned char* gm_host_dev = nullptr;   // the same memory as the device sees it
   hipEvent_t gm_ev[2] = {nullptr, nullptr};
 
   ~gdc_handle() {
@@ -421,7 +422,8 @@ int wait_status(gdc_handle* h, int slot, GmStatus& st) {
 // with classical Gram-Schmidt and one reorthogonalisation, zero initial
 // guess.  Solution (x = P^-1 u) written to h->sol.
 //
-// The Hessenberg bookkeeping runs on the device (gm_column), so the host
+// The Hessenberg bookkeeping runs on the device (in the last Arnoldi kernel,
+// which also writes the status to pinned host memory), so the host
 // queues iteration k + 1 before it waits for the status of iteration k: the
 // GPU never idles on the host.  When iteration k ends the cycle, the kernels
 // already queued for iteration k + 1 see the device flag and return at once.
@@ -456,9 +458,10 @@ int gmres(gdc_handle* h, const double* Y, const double* q, const double* r, Gmre
       GDC_TRY(apply_saddle_precond<R>(h, Y, q, r, Vk, h->z, h->w, skip));
       double* h1 = h->hdev;
       double* h2 = h->hdev + HCOLS;
-      GDC_TRY(arnoldi_orthogonalise(h->w, h->Vb, n, k + 1, n, h->partial, h->partial2, Vk1, h1, h2, s, skip));
-      GDC_TRY(gm_column(h->gm, k, m, h1, h2, s));
-      GDC_TRY(post_status(h, (k + 1) & 1));
+      const int slot = (k + 1) & 1;
+      GDC_TRY(arnoldi_orthogonalise(h->w, h->Vb, n, k + 1, n, h->partial, h->partial2, Vk1, h1, h2, s, skip, h->gm,
+                                    m, h->gm_host_dev + 32 * slot));
+      GDC_HIP(hipEventRecord(h->gm_ev[slot], s));
       // status after iteration k - 1 (or after the cycle start)
       GDC_TRY(wait_status(h, k & 1, st));
       if (st.done) break;
@@ -835,7 +838,8 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
   }
   GDC_HIP(hipHostMalloc((void**)&h->hhost, 5 * HCOLS * sizeof(double), hipHostMallocDefault));
   GDC_TRY(h->alloc(&h->gm, 1));
-  GDC_HIP(hipHostMalloc((void**)&h->gm_host, 64, hipHostMallocDefault));
+  GDC_HIP(hipHostMalloc((void**)&h->gm_host, 64, hipHostMallocMapped | hipHostMallocCoherent));
+  GDC_HIP(hipHostGetDevicePointer((void**)&h->gm_host_dev, h->gm_host, 0));
   for (hipEvent_t& e : h->gm_ev) GDC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 
   if (h->precision == GDC_FP64) {

@@ -92,76 +92,129 @@ struct Bfly<R, 3, INV> {
   }
 };
 
-// One Stockham stage on NL lines of length N (line stride LS) in LDS: the
-// sub-transforms of length NS are combined RAD at a time.  Every thread reads
-// its butterflies' inputs into registers, the block synchronises, then the
-// outputs are written in place.
-template <typename R, int N, int NL, int LS, int RAD, int NS, bool INV>
-__device__ __forceinline__ void fft_stage(Cx<R>* buf, const Cx<R>* tw) {
-  constexpr int NB = N / RAD;
-  constexpr int TOT = NL * NB;
-  constexpr int PER = (TOT + NT - 1) / NT;
-  Cx<R> v[PER][RAD];
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int m = 0; m < PER; ++m) {
-    const int b = tid + m * NT;
-    if ((TOT % NT == 0) || b < TOT) {
-      const int t = b / NB, j = b - t * NB;
-      const Cx<R>* line = buf + t * LS;
-#pragma unroll
-      for (int r = 0; r < RAD; ++r) v[m][r] = line[j + r * NB];
-      if (NS > 1) {
-        const int k = j % NS;
-#pragma unroll
-        for (int r = 1; r < RAD; ++r) {
-          Cx<R> w = tw[r * k * (N / (NS * RAD))];
-          if (INV) w.y = -w.y;
-          v[m][r] = cmul(v[m][r], w);
-        }
-      }
-      Bfly<R, RAD, INV>::run(v[m]);
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < PER; ++m) {
-    const int b = tid + m * NT;
-    if ((TOT % NT == 0) || b < TOT) {
-      const int t = b / NB, j = b - t * NB;
-      const int k = j % NS;
-      Cx<R>* line = buf + t * LS;
-      const int d = (j / NS) * NS * RAD + k;
-#pragma unroll
-      for (int r = 0; r < RAD; ++r) line[d + r * NS] = v[m][r];
-    }
-  }
-  __syncthreads();
+// ------------------------------------------------------------ line transforms
+// A length-N line transform runs as the four-step factorisation N = A B:
+//   step 1: for each b < B, an A-point DFT of x[b + B a] (a < A) in
+//           registers, times w_N^{b k1}, written back to the same places;
+//   step 2: for each k1 < A, a B-point DFT of the B consecutive values
+//           y[B k1 + b] in registers, giving X[k1 + A k2].
+// Step 1 is in place per thread; step 2 reads everything before any write.
+// Three barriers per transform.  Threads take tasks line-fastest, so lanes
+// walk across lines whose padded stride spreads them over the LDS banks.
+// Small DFTs in registers recurse on radix 4/2/3 with twiddles read from the
+// line's table (w_A^e = w_N^{e N/A}).
+
+template <typename R, bool INV>
+__device__ __forceinline__ Cx<R> twiddle(const Cx<R>* tw, int e) {
+  Cx<R> w = tw[e];
+  if (INV) w.y = -w.y;
+  return w;
 }
 
-template <typename R, int N, int NL, int LS, bool INV, int REM, int NS>
-struct Stages {
-  __device__ __forceinline__ static void run(Cx<R>* buf, const Cx<R>* tw) {
-    constexpr int RAD = next_radix(REM);
-    static_assert(RAD > 0, "line length must be 2^a 3^b");
-    fft_stage<R, N, NL, LS, RAD, NS, INV>(buf, tw);
-    Stages<R, N, NL, LS, INV, REM / RAD, NS * RAD>::run(buf, tw);
+// In-register DFT of A values v[j] (natural order in and out); tw is the
+// e^{-2 pi i k/N} table of the full line length N (A divides N).
+template <typename R, int A, int N, bool INV>
+struct RegDFT {
+  static constexpr int RAD = next_radix(A), S = A / RAD;
+  __device__ __forceinline__ static void run(Cx<R>* v, const Cx<R>* tw) {
+    Cx<R> sub[RAD][S];
+#pragma unroll
+    for (int p = 0; p < RAD; ++p)
+#pragma unroll
+      for (int j = 0; j < S; ++j) sub[p][j] = v[j * RAD + p];
+#pragma unroll
+    for (int p = 0; p < RAD; ++p) RegDFT<R, S, N, INV>::run(sub[p], tw);
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      Cx<R> t[RAD];
+#pragma unroll
+      for (int p = 0; p < RAD; ++p)
+        t[p] = (p * k == 0) ? sub[p][k] : cmul(sub[p][k], twiddle<R, INV>(tw, (p * k * (N / A)) % N));
+      Bfly<R, RAD, INV>::run(t);
+#pragma unroll
+      for (int q = 0; q < RAD; ++q) v[k + S * q] = t[q];
+    }
   }
 };
-template <typename R, int N, int NL, int LS, bool INV, int NS>
-struct Stages<R, N, NL, LS, INV, 1, NS> {
+template <typename R, int N, bool INV>
+struct RegDFT<R, 1, N, INV> {
   __device__ __forceinline__ static void run(Cx<R>*, const Cx<R>*) {}
 };
+template <typename R, int N, bool INV>
+struct RegDFT<R, 2, N, INV> {
+  __device__ __forceinline__ static void run(Cx<R>* v, const Cx<R>*) { Bfly<R, 2, INV>::run(v); }
+};
+template <typename R, int N, bool INV>
+struct RegDFT<R, 3, N, INV> {
+  __device__ __forceinline__ static void run(Cx<R>* v, const Cx<R>*) { Bfly<R, 3, INV>::run(v); }
+};
+template <typename R, int N, bool INV>
+struct RegDFT<R, 4, N, INV> {
+  __device__ __forceinline__ static void run(Cx<R>* v, const Cx<R>*) { Bfly<R, 4, INV>::run(v); }
+};
 
-// Unnormalised forward (e^{-i}) or inverse (e^{+i}) transforms of NL lines.
-template <typename R, int N, int NL, int LS, bool INV>
-__device__ __forceinline__ void fft_lines(Cx<R>* buf, const Cx<R>* tw) {
-  Stages<R, N, NL, LS, INV, N, 1>::run(buf, tw);
+// N = A B with A the largest divisor of N not above 16.
+constexpr int split_a(int n) {
+  int a = 1;
+  for (int d = 1; d <= 16; ++d)
+    if (n % d == 0) a = d;
+  return a;
 }
 
-template <typename R, int N>
+// Unnormalised forward (e^{-i}) or inverse (e^{+i}) transforms of NL lines
+// of length N (line stride LS) in LDS by a workgroup of NTH threads.
+template <typename R, int N, int NL, int LS, bool INV, int NTH = NT>
+__device__ __forceinline__ void fft_lines(Cx<R>* buf, const Cx<R>* tw) {
+  constexpr int A = split_a(N), B = N / A;
+  static_assert(A * B == N, "line length");
+  const int tid = threadIdx.x;
+  // step 1
+  for (int task = tid; task < NL * B; task += NTH) {
+    const int t = task % NL, b = task / NL;
+    Cx<R>* line = buf + t * LS;
+    Cx<R> v[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) v[a] = line[b + B * a];
+    RegDFT<R, A, N, INV>::run(v, tw);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      const Cx<R> w = (B > 1 && k1 > 0 && b > 0) ? cmul(v[k1], twiddle<R, INV>(tw, (b * k1) % N)) : v[k1];
+      line[b + B * k1] = w;
+    }
+  }
+  __syncthreads();
+  if (B > 1) {
+    constexpr int TOT = NL * A, PER = (TOT + NTH - 1) / NTH;
+    Cx<R> u[PER][B];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int task = tid + m * NTH;
+      if ((TOT % NTH == 0) || task < TOT) {
+        const int t = task % NL, k1 = task / NL;
+        const Cx<R>* line = buf + t * LS;
+#pragma unroll
+        for (int b = 0; b < B; ++b) u[m][b] = line[B * k1 + b];
+        RegDFT<R, B, N, INV>::run(u[m], tw);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int task = tid + m * NTH;
+      if ((TOT % NTH == 0) || task < TOT) {
+        const int t = task % NL, k1 = task / NL;
+        Cx<R>* line = buf + t * LS;
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) line[k1 + A * k2] = u[m][k2];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename R, int N, int NTH = NT>
 __device__ __forceinline__ void load_twiddles(Cx<R>* tw, const Cx<R>* __restrict__ twg) {
-  for (int k = threadIdx.x; k < N; k += NT) tw[k] = twg[k];
+  for (int k = threadIdx.x; k < N; k += NTH) tw[k] = twg[k];
 }
 
 // ------------------------------------------------------------ pass A: R2C, axis 2
@@ -434,6 +487,216 @@ __global__ __launch_bounds__(NT) void k_axis0_project(Cx<R>* __restrict__ Y, con
   }
 }
 
+
+// ------------------------------------------------------------ three-pass layout
+// For FP32 grids with n1 = n2 <= 128 a whole (component, axis-0) plane of
+// the half spectrum fits in LDS (n1 x n2/2 complex values, 66 KB at 128), so
+// the two passes on each side of pass C merge into one:
+//
+//   P  real [c][i0][i1][i2]  --R2C axis 2, FFT axis 1-->   Z [c][i0][k2][k1]
+//   C  Z (3 components)  --FFT axis 0, project, inverse FFT axis 0-->  Z
+//   P' Z                     --iFFT axis 1, C2R axis 2-->   real
+//
+// P and P' read and write whole planes contiguously; pass C reads 16
+// consecutive k1 of each (c, i0, k2) line, one 128-byte segment.
+
+constexpr int NTP = 512;   // threads of a plane workgroup
+
+template <int N1, int N2>
+struct PlaneLds {
+  static constexpr int LA = N2 + 1, LB = N1 + 1;    // padded line strides
+  static constexpr int H = N2 / 2;
+  static constexpr int A = (N1 / 2) * LA, B = H * LB;
+  static constexpr int SIZE = A > B ? A : B;
+};
+
+// Two real rows (2p, 2p+1) of length N2 as one complex line; after its FFT
+// Z, row 2p has A(k) = (Z(k) + conj Z(N2-k))/2 and row 2p+1 has
+// B(k) = (Z(k) - conj Z(N2-k))/(2i), k < N2/2.  Then FFT along axis 1.
+template <typename R, int N1, int N2>
+__global__ __launch_bounds__(NTP) void k_plane_fwd(const R* __restrict__ in, Cx<R>* __restrict__ Z,
+                                                   const Cx<R>* __restrict__ tw1g, const Cx<R>* __restrict__ tw2g,
+                                                   int n0, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  using L = PlaneLds<N1, N2>;
+  constexpr int H = L::H, NP = N1 / 2;
+  __shared__ Cx<R> buf[L::SIZE];
+  __shared__ Cx<R> tw1[N1], tw2[N2];
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.x, c = blockIdx.y;
+  load_twiddles<R, N1, NTP>(tw1, tw1g);
+  load_twiddles<R, N2, NTP>(tw2, tw2g);
+  const R* src = in + ((long long)c * n0 + i0) * N1 * N2;
+  for (int e = tid; e < NP * N2; e += NTP) {
+    const int p = e / N2, x = e - p * N2;
+    buf[p * L::LA + x] = Cx<R>{src[(2 * p) * N2 + x], src[(2 * p + 1) * N2 + x]};
+  }
+  __syncthreads();
+  fft_lines<R, N2, NP, L::LA, false, NTP>(buf, tw2);
+  // unpack into lines k2 (length N1, index i1)
+  constexpr int ITEMS = NP * H, PER = (ITEMS + NTP - 1) / NTP;
+  Cx<R> ra[PER], rb[PER];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int e = tid + m * NTP;
+    if (e < ITEMS) {
+      const int p = e / H, k = e - p * H;
+      const Cx<R> z = buf[p * L::LA + k];
+      const Cx<R> zc = buf[p * L::LA + ((N2 - k) % N2)];
+      ra[m] = Cx<R>{R(0.5) * (z.x + zc.x), R(0.5) * (z.y - zc.y)};
+      rb[m] = Cx<R>{R(0.5) * (z.y + zc.y), R(0.5) * (zc.x - z.x)};
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int e = tid + m * NTP;
+    if (e < ITEMS) {
+      const int p = e / H, k = e - p * H;
+      buf[k * L::LB + 2 * p] = ra[m];
+      buf[k * L::LB + 2 * p + 1] = rb[m];
+    }
+  }
+  __syncthreads();
+  fft_lines<R, N1, H, L::LB, false, NTP>(buf, tw1);
+  Cx<R>* dst = Z + ((long long)c * n0 + i0) * H * N1;
+  for (int e = tid; e < H * N1; e += NTP) {
+    const int k = e / N1, x = e - k * N1;
+    dst[e] = buf[k * L::LB + x];
+  }
+}
+
+// Inverse of k_plane_fwd: iFFT along axis 1, then rows (2p, 2p+1) rebuilt as
+// one complex line Z(k) = A(k) + i B(k) with the Hermitian extensions (the
+// k = 0 term keeps real parts, the Nyquist term is zero) and inverse FFT.
+template <typename R, int N1, int N2>
+__global__ __launch_bounds__(NTP) void k_plane_inv(const Cx<R>* __restrict__ Z, R* __restrict__ out,
+                                                   const Cx<R>* __restrict__ tw1g, const Cx<R>* __restrict__ tw2g,
+                                                   int n0, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  using L = PlaneLds<N1, N2>;
+  constexpr int H = L::H, NP = N1 / 2;
+  __shared__ Cx<R> buf[L::SIZE];
+  __shared__ Cx<R> tw1[N1], tw2[N2];
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.x, c = blockIdx.y;
+  load_twiddles<R, N1, NTP>(tw1, tw1g);
+  load_twiddles<R, N2, NTP>(tw2, tw2g);
+  const Cx<R>* src = Z + ((long long)c * n0 + i0) * H * N1;
+  for (int e = tid; e < H * N1; e += NTP) {
+    const int k = e / N1, x = e - k * N1;
+    buf[k * L::LB + x] = src[e];
+  }
+  __syncthreads();
+  fft_lines<R, N1, H, L::LB, true, NTP>(buf, tw1);
+  constexpr int ITEMS = NP * H, PER = (ITEMS + NTP - 1) / NTP;
+  Cx<R> ra[PER], rb[PER];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int e = tid + m * NTP;
+    if (e < ITEMS) {
+      const int p = e / H, k = e - p * H;
+      ra[m] = buf[k * L::LB + 2 * p];
+      rb[m] = buf[k * L::LB + 2 * p + 1];
+    }
+  }
+  __syncthreads();
+  const Cx<R> zero{R(0), R(0)};
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int e = tid + m * NTP;
+    if (e < ITEMS) {
+      const int p = e / H, k = e - p * H;
+      const Cx<R> a = ra[m], b = rb[m];
+      if (k == 0) {
+        buf[p * L::LA] = Cx<R>{a.x, b.x};
+        buf[p * L::LA + H] = zero;
+      } else {
+        buf[p * L::LA + k] = Cx<R>{a.x - b.y, a.y + b.x};
+        buf[p * L::LA + N2 - k] = Cx<R>{a.x + b.y, b.x - a.y};
+      }
+    }
+  }
+  __syncthreads();
+  fft_lines<R, N2, NP, L::LA, true, NTP>(buf, tw2);
+  R* dst = out + ((long long)c * n0 + i0) * N1 * N2;
+  for (int e = tid; e < NP * N2; e += NTP) {
+    const int p = e / N2, x = e - p * N2;
+    const Cx<R> z = buf[p * L::LA + x];
+    dst[(2 * p) * N2 + x] = z.x;
+    dst[(2 * p + 1) * N2 + x] = z.y;
+  }
+}
+
+// Pass C on the plane layout Z[c][i0][k2][k1]: TCP consecutive k1 lines of
+// each component per workgroup.
+constexpr int TCP = 16;
+
+template <typename R, int N0, bool NOISE>
+__global__ __launch_bounds__(NT) void k_axis0_plane(Cx<R>* __restrict__ Z, const Cx<R>* __restrict__ twg,
+                                                    ProjParams P, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  constexpr int NLn = 3 * TCP, LS = N0 + 1;
+  __shared__ Cx<R> buf[NLn * LS];
+  __shared__ Cx<R> tw[N0];
+  const int tid = threadIdx.x;
+  const int k2 = blockIdx.y, k1b = blockIdx.x * TCP;
+  const int nl = min(TCP, P.n1 - k1b);
+  const int H = P.n2h, n1 = P.n1;
+  load_twiddles<R, N0>(tw, twg);
+  if (!NOISE) {
+    for (int e = tid; e < NLn * N0; e += NT) {
+      const int t = e % TCP, rest = e / TCP;
+      const int x = rest % N0, c = rest / N0;
+      buf[(c * TCP + t) * LS + x] =
+          (t < nl) ? Z[(((long long)c * N0 + x) * H + k2) * n1 + k1b + t] : Cx<R>{R(0), R(0)};
+    }
+    __syncthreads();
+    fft_lines<R, N0, NLn, LS, false>(buf, tw);
+  } else {
+    __syncthreads();
+  }
+  for (int e = tid; e < TCP * N0; e += NT) {
+    const int t = e / N0, j0 = e - t * N0;
+    const int j1 = k1b + t;
+    Cx<R> u[3] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
+    if (t < nl) {
+      if (NOISE) {
+        double ur[3], ui[3];
+        if (noise_mode(P, j0, j1, k2, ur, ui)) {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) u[a] = Cx<R>{R(ur[a]), R(ui[a])};
+        }
+      } else if (!(j0 == N0 / 2 || j1 == n1 / 2 || (j0 == 0 && j1 == 0 && k2 == 0))) {
+        const R kx = R(P.kf0) * R(signed_index(j0, N0));
+        const R ky = R(P.kf1) * R(signed_index(j1, n1));
+        const R kz = R(P.kf2) * R(k2);
+        const R kk = kx * kx + ky * ky + kz * kz;
+        const Cx<R> f0 = buf[(0 * TCP + t) * LS + j0];
+        const Cx<R> f1 = buf[(1 * TCP + t) * LS + j0];
+        const Cx<R> f2 = buf[(2 * TCP + t) * LS + j0];
+        const R ikk = R(1) / kk;
+        const R dr = (kx * f0.x + ky * f1.x + kz * f2.x) * ikk;
+        const R di = (kx * f0.y + ky * f1.y + kz * f2.y) * ikk;
+        const R sc = R(P.inv_eta * P.invG) * ikk;
+        u[0] = Cx<R>{sc * (f0.x - kx * dr), sc * (f0.y - kx * di)};
+        u[1] = Cx<R>{sc * (f1.x - ky * dr), sc * (f1.y - ky * di)};
+        u[2] = Cx<R>{sc * (f2.x - kz * dr), sc * (f2.y - kz * di)};
+      }
+    }
+    // Each (t, j0) is read and written by the same thread only.
+#pragma unroll
+    for (int a = 0; a < 3; ++a) buf[(a * TCP + t) * LS + j0] = u[a];
+  }
+  __syncthreads();
+  fft_lines<R, N0, NLn, LS, true>(buf, tw);
+  for (int e = tid; e < NLn * N0; e += NT) {
+    const int t = e % TCP, rest = e / TCP;
+    const int x = rest % N0, c = rest / N0;
+    if (t < nl) Z[(((long long)c * N0 + x) * H + k2) * n1 + k1b + t] = buf[(c * TCP + t) * LS + x];
+  }
+}
+
 // ------------------------------------------------------------ dispatch
 
 #define GDC_FFT_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
@@ -503,6 +766,70 @@ int launch_proj(int n0, Cx<R>* Y, const Cx<R>* tw, const ProjParams& P, hipStrea
   return check_launch("k_axis0_project");
 }
 
+
+// Plane sizes: n1 = n2 and n0 in this list (FP32 only).
+#define GDC_PLANE_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128)
+
+bool plane_size(int n) {
+  switch (n) {
+#define X_(N) case N: return true;
+    GDC_PLANE_SIZES(X_)
+#undef X_
+    default: return false;
+  }
+}
+
+template <typename R>
+bool plane_path(const GridGeom& g) {
+  return sizeof(R) == 4 && g.n[1] == g.n[2] && plane_size(g.n[1]) && plane_size(g.n[0]);
+}
+
+template <typename R>
+int launch_plane(bool inverse, int n, const void* in, void* out, const Cx<R>* tw1, const Cx<R>* tw2, int n0,
+                 hipStream_t s, const int* skip) {
+  dim3 grid(n0, 3);
+  ProbeScope ps(inverse ? "fft_plane_inv" : "fft_plane_fwd", s);
+  if constexpr (sizeof(R) != 4) {
+    set_error("plane transforms are FP32 only");
+    return GDC_EINVAL;
+  } else {
+  if (!inverse) {
+    switch (n) {
+#define X_(N) case N: hipLaunchKernelGGL((k_plane_fwd<R, N, N>), grid, dim3(NTP), 0, s, (const R*)in, (Cx<R>*)out, tw1, tw2, n0, skip); break;
+      GDC_PLANE_SIZES(X_)
+#undef X_
+      default: set_error("unsupported plane size"); return GDC_EINVAL;
+    }
+    return check_launch("k_plane_fwd");
+  }
+  switch (n) {
+#define X_(N) case N: hipLaunchKernelGGL((k_plane_inv<R, N, N>), grid, dim3(NTP), 0, s, (const Cx<R>*)in, (R*)out, tw1, tw2, n0, skip); break;
+    GDC_PLANE_SIZES(X_)
+#undef X_
+    default: set_error("unsupported plane size"); return GDC_EINVAL;
+  }
+  return check_launch("k_plane_inv");
+  }
+}
+
+template <typename R, bool NOISE>
+int launch_proj_plane(int n0, Cx<R>* Z, const Cx<R>* tw, const ProjParams& P, hipStream_t s, const int* skip) {
+  dim3 grid((P.n1 + TCP - 1) / TCP, P.n2h, 1);
+  ProbeScope ps(NOISE ? "fft_noise" : "fft_project", s);
+  if constexpr (sizeof(R) != 4) {
+    set_error("plane transforms are FP32 only");
+    return GDC_EINVAL;
+  } else {
+    switch (n0) {
+#define X_(N) case N: hipLaunchKernelGGL((k_axis0_plane<R, N, NOISE>), grid, dim3(NT), 0, s, Z, tw, P, skip); break;
+      GDC_PLANE_SIZES(X_)
+#undef X_
+      default: set_error("unsupported grid size"); return GDC_EINVAL;
+    }
+    return check_launch("k_axis0_plane");
+  }
+}
+
 ProjParams proj_params(const GridGeom& g) {
   ProjParams P{};
   P.n0 = g.n[0];
@@ -532,6 +859,11 @@ template <typename R>
 int stokes_solve(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, Cx<R>* Y,
                  hipStream_t s, const int* skip) {
   const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], H = g.n2h;
+  if (plane_path<R>(g)) {
+    GDC_TRY(launch_plane<R>(false, n1, real, X, tw[1], tw[2], n0, s, skip));
+    GDC_TRY((launch_proj_plane<R, false>(n0, X, tw[0], proj_params(g), s, skip)));
+    return launch_plane<R>(true, n1, X, real, tw[1], tw[2], n0, s, skip);
+  }
   GDC_TRY(launch_r2c<R>(n2, real, X, tw[2], n0, n1, s, skip));
   GDC_TRY(launch_fwd1<R>(n1, X, Y, tw[1], n0, H, s, skip));
   GDC_TRY((launch_proj<R, false>(n0, Y, tw[0], proj_params(g), s, skip)));
@@ -553,6 +885,10 @@ int fluct_field(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, 
   const double base = kT * g.eta / (g.dV * dt);
   P.sdiag = std::sqrt((double)g.G * 4.0 * base / 2.0);
   P.soff = std::sqrt((double)g.G * 2.0 * base / 2.0);
+  if (plane_path<R>(g)) {
+    GDC_TRY((launch_proj_plane<R, true>(n0, X, tw[0], P, s, nullptr)));
+    return launch_plane<R>(true, n1, X, real, tw[1], tw[2], n0, s, nullptr);
+  }
   GDC_TRY((launch_proj<R, true>(n0, Y, tw[0], P, s, nullptr)));
   GDC_TRY(launch_inv1<R>(n1, Y, X, tw[1], n0, H, s, nullptr));
   GDC_TRY(launch_c2r<R>(n2, X, real, tw[2], n0, n1, s, nullptr));

@@ -250,14 +250,6 @@ int multi_axpy(double* w, const double* V, long long ld, int k, const double* h,
 // out = (w - V h2) / sqrt(h2[k] - |h2[0..k)|^2)
 int ortho_finish(const double* w, const double* V, long long ld, int k, const double* h2, double* out,
                  long long n, hipStream_t s);
-// One Arnoldi orthogonalisation (CGS with one re-orthogonalisation) of w
-// against V_0..V_{k-1}: out = normalised remainder, h1 (k) and h2s (k + 1:
-// h2 then w.w) stored for the Hessenberg column.  partial1/2 hold
-// (k + 1) x ceil(n / 1024) doubles each.
-int arnoldi_orthogonalise(double* w, const double* V, long long ld, int k, long long n, double* partial1,
-                          double* partial2, double* out, double* h1, double* h2s, hipStream_t s,
-                          const int* skip = nullptr);
-
 // Device-resident GMRES bookkeeping (restart length <= GM_MAXR).  The first
 // GM_STATUS_BYTES hold what the host polls: est, its, kdone, done, converged.
 constexpr int GM_MAXR = 64;
@@ -274,9 +266,18 @@ struct GmresState {
   double H[(GM_MAXR + 1) * GM_MAXR];   // H[j * GM_MAXR + k]
 };
 constexpr size_t GM_STATUS_BYTES = 24;
+// One Arnoldi orthogonalisation (CGS with one re-orthogonalisation) of w
+// against V_0..V_{k-1}: out = normalised remainder, h1 (k) and h2s (k + 1:
+// h2 then w.w) stored for the Hessenberg column.  With st, the last kernel
+// also updates Hessenberg column k - 1 of a restart of length m and writes
+// the status to hstat (device-visible pinned host memory, or null).  partial1/2 hold
+// (k + 1) x ceil(n / 1024) doubles each.
+int arnoldi_orthogonalise(double* w, const double* V, long long ld, int k, long long n, double* partial1,
+                          double* partial2, double* out, double* h1, double* h2s, hipStream_t s,
+                          const int* skip, GmresState* st, int m, unsigned char* hstat);
+
 int gm_init(GmresState* st, const double* nb2, double tol, int maxit, hipStream_t s);
 int gm_cycle(GmresState* st, const double* beta2, hipStream_t s);
-int gm_column(GmresState* st, int k, int m, const double* h1, const double* h2, hipStream_t s);
 // y = H^-1 g over the cycle, then x += V y.
 int gm_finish_cycle(GmresState* st, double* x, const double* V, long long ld, long long n, hipStream_t s);
 int scale_by_inv_sqrt(const double* w, const double* nrm2, double* out, long long n,

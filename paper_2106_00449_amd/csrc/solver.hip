@@ -141,13 +141,98 @@ __global__ __launch_bounds__(NT) void k_axpy_partial(double* __restrict__ w, con
   }
 }
 
+// Column k of the Hessenberg matrix from the Gram-Schmidt coefficients, by
+// one workgroup: H[j][k] = h1[j] + h2[j] (j <= k), H[k+1][k] =
+// sqrt(w.w - |h2|^2) with w.w = h2[k+1]; then the previous rotations, a new
+// one, and the residual estimate |g[k+1]| / |b|; done (and converged) are set
+// when the cycle ends.  The rotations are staged in LDS first so that thread
+// 0 works without global-memory round trips; the status fields (est, its,
+// kdone, done, converged) then go to `out` (pinned host memory) when given.
+// Must be called by every thread of the block.
+__device__ void gm_column_block(GmresState* st, int k, int m, const double* __restrict__ h1,
+                                const double* h2, unsigned char* out) {
+  __shared__ double cs[GM_MAXR], sn[GM_MAXR], col[GM_MAXR + 1], h1s[GM_MAXR];
+  __shared__ double g_k, nb, tol, est;
+  __shared__ int done, its, maxit, conv;
+  const int tid = threadIdx.x;
+  for (int j = tid; j < k; j += NT) {
+    cs[j] = st->cs[j];
+    sn[j] = st->sn[j];
+  }
+  for (int j = tid; j <= k; j += NT) h1s[j] = h1[j];
+  if (tid == 0) {
+    done = st->done;
+    its = st->its;
+    maxit = st->maxit;
+    g_k = st->g[k];
+    nb = st->nb;
+    tol = st->tol;
+    est = st->est;
+    conv = st->converged;
+  }
+  __syncthreads();
+  const bool update = !done;
+  if (update && tid == 0) {
+    double h2sq = 0.0;
+    for (int j = 0; j <= k; ++j) {
+      col[j] = h1s[j] + h2[j];
+      h2sq += h2[j] * h2[j];
+    }
+    col[k + 1] = sqrt(fmax(0.0, h2[k + 1] - h2sq));
+    for (int j = 0; j < k; ++j) {
+      const double a = col[j], b = col[j + 1];
+      col[j] = cs[j] * a + sn[j] * b;
+      col[j + 1] = -sn[j] * a + cs[j] * b;
+    }
+    const double a = col[k], b = col[k + 1];
+    const double den = hypot(a, b);
+    const double c = den > 0.0 ? a / den : 1.0, sv = den > 0.0 ? b / den : 0.0;
+    col[k] = den;
+    col[k + 1] = 0.0;
+    st->cs[k] = c;
+    st->sn[k] = sv;
+    st->g[k + 1] = -sv * g_k;
+    st->g[k] = c * g_k;
+    its += 1;
+    est = fabs(sv * g_k) / nb;
+    if (est <= tol) {
+      conv = 1;
+      done = 1;
+    } else if (its >= maxit || den == 0.0 || k + 1 >= m) {
+      done = 1;
+    }
+    st->its = its;
+    st->kdone = k + 1;
+    st->est = est;
+    st->done = done;
+    st->converged = conv;
+  }
+  __syncthreads();
+  if (update)
+    for (int j = tid; j <= k + 1; j += NT) st->H[j * GM_MAXR + k] = col[j];
+  if (out && tid == 0) {
+    volatile double* d = reinterpret_cast<volatile double*>(out);
+    volatile int* i = reinterpret_cast<volatile int*>(out + 8);
+    d[0] = est;
+    i[0] = its;
+    i[1] = update ? k + 1 : st->kdone;
+    i[2] = done;
+    i[3] = conv;
+  }
+}
+
 // out = (w - V h2) / sqrt(s - |h2|^2) with (h2, s) reduced from partial2.
-// Block 0 stores h2 and s in hout.
+// Block 0 stores h2 and s in hout and, when st is given and its cycle is
+// not over, updates Hessenberg column k - 1 from h1 and h2 and writes the
+// status to hstat (pinned host memory; visible to the host once the kernel
+// has completed).  No skip flag: block 0 reads `done` before it may set it,
+// and an iteration past the end of a cycle only writes a basis vector that
+// is never used.
 __global__ __launch_bounds__(NT) void k_ortho_finish2(const double* __restrict__ w, const double* __restrict__ V,
                                                       long long ld, int k, const double* __restrict__ partial2,
                                                       long long n, double* __restrict__ out, double* __restrict__ hout,
-                                                      const int* __restrict__ skip) {
-  if (skip && *skip) return;
+                                                      GmresState* st, int m, const double* __restrict__ h1,
+                                                      unsigned char* hstat) {
   __shared__ double hs[MAXK];
   __shared__ double scale;
   reduce_rows(partial2, k + 1, gridDim.x, hs);
@@ -158,8 +243,10 @@ __global__ __launch_bounds__(NT) void k_ortho_finish2(const double* __restrict__
     const double nrm2 = hs[k] - hh;
     scale = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
   }
-  if (blockIdx.x == 0)
+  if (blockIdx.x == 0) {
     for (int j = threadIdx.x; j <= k; j += NT) hout[j] = hs[j];
+    if (st) gm_column_block(st, k - 1, m, h1, hs, hstat);
+  }
   __syncthreads();
   const double a = scale;
   const long long lo = (long long)blockIdx.x * CHUNK;
@@ -269,46 +356,6 @@ __global__ void k_gm_cycle(GmresState* st, const double* __restrict__ beta2) {
   }
 }
 
-// Column k of the Hessenberg matrix from the Gram-Schmidt coefficients:
-// H[j][k] = h1[j] + h2[j] (j <= k), H[k+1][k] = sqrt(w.w - |h2|^2) with
-// w.w = h2[k+1]; then the previous rotations, a new one, and the residual
-// estimate |g[k+1]| / |b|.
-__global__ void k_gm_column(GmresState* st, int k, int m, const double* __restrict__ h1,
-                            const double* __restrict__ h2) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (st->done) return;
-  double* H = st->H;
-  double h2sq = 0.0;
-  for (int j = 0; j <= k; ++j) {
-    H[j * GM_MAXR + k] = h1[j] + h2[j];
-    h2sq += h2[j] * h2[j];
-  }
-  H[(k + 1) * GM_MAXR + k] = sqrt(fmax(0.0, h2[k + 1] - h2sq));
-  for (int j = 0; j < k; ++j) {
-    const double a = H[j * GM_MAXR + k], b = H[(j + 1) * GM_MAXR + k];
-    H[j * GM_MAXR + k] = st->cs[j] * a + st->sn[j] * b;
-    H[(j + 1) * GM_MAXR + k] = -st->sn[j] * a + st->cs[j] * b;
-  }
-  const double a = H[k * GM_MAXR + k], b = H[(k + 1) * GM_MAXR + k];
-  const double den = hypot(a, b);
-  st->cs[k] = den > 0.0 ? a / den : 1.0;
-  st->sn[k] = den > 0.0 ? b / den : 0.0;
-  H[k * GM_MAXR + k] = den;
-  H[(k + 1) * GM_MAXR + k] = 0.0;
-  const double gk = st->g[k];
-  st->g[k + 1] = -st->sn[k] * gk;
-  st->g[k] = st->cs[k] * gk;
-  st->its += 1;
-  st->kdone = k + 1;
-  st->est = fabs(st->g[k + 1]) / st->nb;
-  if (st->est <= st->tol) {
-    st->converged = 1;
-    st->done = 1;
-  } else if (st->its >= st->maxit || den == 0.0 || k + 1 >= m) {
-    st->done = 1;
-  }
-}
-
 // y = H^-1 g over the cycle's kdone columns (back substitution).
 __global__ void k_gm_solve(GmresState* st) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -382,7 +429,7 @@ int ortho_finish(const double* w, const double* V, long long ld, int k, const do
 
 int arnoldi_orthogonalise(double* w, const double* V, long long ld, int k, long long n, double* partial1,
                           double* partial2, double* out, double* h1, double* h2s, hipStream_t s,
-                          const int* skip) {
+                          const int* skip, GmresState* st, int m, unsigned char* hstat) {
   if (k < 1 || k + 1 >= MAXK) {
     set_error("arnoldi_orthogonalise: basis size out of range");
     return GDC_EINVAL;
@@ -398,7 +445,12 @@ int arnoldi_orthogonalise(double* w, const double* V, long long ld, int k, long 
   GDC_TRY(check_launch("k_axpy_partial"));
   hipLaunchKernelGGL(k_dot2d, dim3(nchunk, k + 1), dim3(NT), 0, s, V, ld, k, (const double*)w, n, partial2, skip);
   GDC_TRY(check_launch("k_dot2d"));
-  hipLaunchKernelGGL(k_ortho_finish2, dim3(nchunk), dim3(NT), 0, s, w, V, ld, k, partial2, n, out, h2s, skip);
+  if (st && (k > m || m > GM_MAXR)) {
+    set_error("arnoldi_orthogonalise: column out of range");
+    return GDC_EINVAL;
+  }
+  hipLaunchKernelGGL(k_ortho_finish2, dim3(nchunk), dim3(NT), 0, s, w, V, ld, k, partial2, n, out, h2s, st, m,
+                     (const double*)h1, hstat);
   return check_launch("k_ortho_finish2");
 }
 
@@ -410,15 +462,6 @@ int gm_init(GmresState* st, const double* nb2, double tol, int maxit, hipStream_
 int gm_cycle(GmresState* st, const double* beta2, hipStream_t s) {
   hipLaunchKernelGGL(k_gm_cycle, dim3(1), dim3(64), 0, s, st, beta2);
   return check_launch("k_gm_cycle");
-}
-
-int gm_column(GmresState* st, int k, int m, const double* h1, const double* h2, hipStream_t s) {
-  if (k < 0 || k >= m || m > GM_MAXR) {
-    set_error("gm_column: column out of range");
-    return GDC_EINVAL;
-  }
-  hipLaunchKernelGGL(k_gm_column, dim3(1), dim3(64), 0, s, st, k, m, h1, h2);
-  return check_launch("k_gm_column");
 }
 
 int gm_finish_cycle(GmresState* st, double* x, const double* V, long long ld, long long n, hipStream_t s) {

@@ -53,8 +53,12 @@ def test_philox_normals_bit_identical(lib):
         assert np.array_equal(g, o), np.abs(g - o).max()
 
 
+# FP32 grids with n1 = n2 <= 128 (and n0 <= 128) take the three-pass plane
+# transforms, other grids the five-pass ones: both are covered.
 @pytest.mark.parametrize("prec,n,L", [("fp64", (16, 12, 24), (16.0, 12.0, 24.0)),
                                       ("fp32", (16, 12, 24), (16.0, 12.0, 24.0)),
+                                      ("fp32", (24, 32, 32), (20.0, 26.0, 26.0)),
+                                      ("fp32", (48, 48, 48), (32.0, 32.0, 32.0)),
                                       ("fp64", (48, 48, 48), (32.0, 32.0, 32.0))])
 def test_fluct_velocity_field(lib, prec, n, L):
     w = wl.small_case(n=n, L=L, precision=prec, seed=11)
@@ -74,6 +78,7 @@ CASES = [
     ("small8", 8, 8.0, [wl.rod(2), np.zeros((1, 3))]),
     ("ragged24", (24, 16, 12), (20.0, 15.0, 13.0), [wl.tetrahedron(), wl.rod(3)]),
     ("rods48", 48, 32.0, [wl.rod(5)]),
+    ("slab16x32", (16, 32, 32), (13.0, 24.0, 24.0), [wl.rod(4), wl.boomerang()]),
     ("mixed64", 64, 48.0, [wl.rod(10), wl.boomerang(), wl.tetrahedron()]),
 ]
 
