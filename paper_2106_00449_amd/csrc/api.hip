@@ -294,6 +294,9 @@ struct gdc_handle {
   double* trec = nullptr;
   int* spos = nullptr;
   double* zsorted = nullptr;
+  void* tabs = nullptr;          // spreading tables of the current configuration
+  int *tab_start = nullptr, *tab_count = nullptr;
+  unsigned int* tab_claimed = nullptr;
   double* hhost = nullptr;   // pinned readback
   GmresState* gm = nullptr;  // device GMRES bookkeeping
   unsigned char* gm_host = nullptr;   // pinned: two status slots
@@ -357,10 +360,16 @@ const Cx<R>* const* tw_of(gdc_handle* h) {
   return reinterpret_cast<const Cx<R>* const*>(h->tw);
 }
 
-// Sorts the blobs at positions r by grid tile; every spread at r needs it.
+// Sorts the blobs at positions r by grid tile and builds the spreading
+// tables; every spread at r needs them.
 int prepare_positions(gdc_handle* h, const double* r) {
-  return tile_sort(h->geom, h->tg, r, h->M, h->tile_ids, h->tile_count, h->tile_off, h->tile_cursor, h->trec,
-                   h->spos, h->stream);
+  GDC_TRY(tile_sort(h->geom, h->tg, r, h->M, h->tile_ids, h->tile_count, h->tile_off, h->tile_cursor, h->trec,
+                    h->spos, h->stream));
+  if (h->precision == GDC_FP64)
+    return spread_prepare<double>(h->geom, h->tg, h->trec, h->tile_off, h->tabs, h->tab_start, h->tab_count,
+                                  h->tab_claimed, h->stream);
+  return spread_prepare<float>(h->geom, h->tg, h->trec, h->tile_off, h->tabs, h->tab_start, h->tab_count,
+                               h->tab_claimed, h->stream);
 }
 
 // out = M_FCM lam at blob positions r (prepared by prepare_positions), minus
@@ -371,7 +380,7 @@ int apply_mobility(gdc_handle* h, const double* r, const double* lam, double* ou
                    const double* V = nullptr, const double* lam_sorted = nullptr, const int* skip = nullptr) {
   const GridGeom& g = h->geom;
   R* f = (R*)h->grid[0];
-  GDC_TRY(spread<R>(g, h->tg, h->trec, lam, lam_sorted, h->tile_off, f, h->stream, skip));
+  GDC_TRY(spread<R>(g, h->tg, h->tabs, h->tab_start, h->tab_count, lam, lam_sorted, f, h->stream, skip));
   GDC_TRY(stokes_solve<R>(g, tw_of<R>(h), f, (Cx<R>*)h->grid[1], (Cx<R>*)h->grid[2], h->stream, skip));
   return interp<R>(g, r, f, out, h->M, g.dV, h->bt.blob_body, Y, V, h->stream, skip);
 }
@@ -835,6 +844,14 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
     GDC_TRY(h->alloc(&h->tile_count, (size_t)(t.ntiles + 4)));
     GDC_TRY(h->alloc(&h->tile_off, (size_t)(t.ntiles + 1)));
     GDC_TRY(h->alloc(&h->tile_cursor, (size_t)t.ntiles));
+    {
+      double* tabs = nullptr;
+      GDC_TRY(h->alloc(&tabs, (spread_table_bytes(g, t, h->M, h->precision) + 7) / 8));
+      h->tabs = tabs;
+    }
+    GDC_TRY(h->alloc(&h->tab_start, (size_t)t.ntiles));
+    GDC_TRY(h->alloc(&h->tab_count, (size_t)t.ntiles));
+    GDC_TRY(h->alloc(&h->tab_claimed, 4));
   }
   GDC_HIP(hipHostMalloc((void**)&h->hhost, 5 * HCOLS * sizeof(double), hipHostMallocDefault));
   GDC_TRY(h->alloc(&h->gm, 1));

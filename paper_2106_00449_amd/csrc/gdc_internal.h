@@ -190,11 +190,21 @@ size_t tile_record_bytes();
 // spos[i] is blob i's position in the sorted order.
 int tile_sort(const GridGeom& g, const TileGeom& t, const double* r, int M, int* tile, int* count, int* off,
               int* cursor, void* rec, int* spos, hipStream_t s);
-// f = S lam on every grid point (the whole field is written).  lam_sorted,
-// when given, holds lam in the sorted order (3 x M) and is read instead.
+// Spreading tables: per tile, the blobs whose stencil reaches it and their
+// per-axis Gaussian factors at the tile's coordinates, built once per
+// configuration (after tile_sort) into `tabs` (spread_table_bytes bytes);
+// tab_start / tab_count (ntiles each) locate each tile's entries, `claimed`
+// is 16 bytes of scratch.
+size_t spread_table_bytes(const GridGeom& g, const TileGeom& t, int M, int precision);
 template <typename R>
-int spread(const GridGeom& g, const TileGeom& t, const void* rec, const double* lam, const double* lam_sorted,
-           const int* off, R* f, hipStream_t s, const int* skip = nullptr);
+int spread_prepare(const GridGeom& g, const TileGeom& t, const void* rec, const int* off, void* tabs,
+                   int* tab_start, int* tab_count, unsigned int* claimed, hipStream_t s);
+// f = S lam on every grid point (the whole field is written) from the
+// tables of the last spread_prepare.  lam_sorted, when given, holds lam in
+// the sorted order (3 x M) and is read instead.
+template <typename R>
+int spread(const GridGeom& g, const TileGeom& t, const void* tabs, const int* tab_start, const int* tab_count,
+           const double* lam, const double* lam_sorted, R* f, hipStream_t s, const int* skip = nullptr);
 // v = scale J u, minus U_p + Omega_p x (r_i - Y_p) when V (N x 6) is given.
 template <typename R>
 int interp(const GridGeom& g, const double* r, const R* u, double* v, int M, double scale,

@@ -18,6 +18,8 @@
 
 #include "gdc_internal.h"
 
+#include <algorithm>
+
 namespace gdc {
 namespace {
 
@@ -383,92 +385,51 @@ __device__ __forceinline__ Ranges axis_ranges(int g, int tstart, int Teff, int n
   return R;
 }
 
-// Per-axis factor table of a spreading tile for hits h < nr: for tile offset
-// j < W along axis D, the stencil offset a = (ts + j - g) mod n; inside the
-// stencil (a < P, j < te) the factor exp(-d^2 / 2 sigma^2) (axis 0 also
-// carries wnorm) and d^2, else 0 and `big`.  Thread -> (hit, j) by shifts.
-template <typename R, int D, int W>
-__device__ __forceinline__ void table_axis(const GridGeom& G, int ts, int te, int nr, const double (*he)[3],
-                                           const int* hg, R (*tf)[W], R (*tsq)[W], R big) {
-  constexpr int LW = W == 8 ? 3 : 5;
-  static_assert(W == 8 || W == 32, "table width");
-  const int n = G.n[D], P = G.P[D];
-  const double dx = G.dx[D], i2 = G.inv2s2, wn = G.wnorm;
-  for (int e = threadIdx.x; e < nr * W; e += NT) {
-    const int h = e >> LW, j = e & (W - 1);
-    const int gb = (hg[h] >> (10 * D)) & 1023;
-    int a = ts + j - gb;
-    a += (a < 0) ? n : 0;
-    R fv = R(0), sv = big;
-    if (j < te && a < P) {
-      const double dd = he[h][D] + a * dx;
-      const double s2 = dd * dd;
-      sv = R(s2);
-      fv = gexp<R>(R(-s2 * i2));
-      if (D == 0) fv *= R(wn);
-    }
-    tf[h][j] = fv;
-    tsq[h][j] = sv;
-  }
-}
+// ------------------------------------------------------------ spreading
+// The blobs whose stencil box meets a grid tile (8 x 8 x 32 points) are its
+// "hits".  The truncated Gaussian is separable, w = wnorm e0(d0) e1(d1)
+// e2(d2) with the cut d0^2 + d1^2 + d2^2 <= rc^2, so each hit carries
+// per-axis tables over the tile's coordinates: factor and squared distance,
+// zero and a large value off the stencil.  The tables depend on positions
+// only, so k_spread_prep builds them once per configuration and every
+// spread S lambda at that configuration (one per GMRES iteration) reads
+// them back: gather the forces, accumulate, write the tile.
 
-// Spreading by gathering, one workgroup per tile of (up to) 8 x 8 x 32 grid
-// points.
-//  1. The blobs whose stencil box meets the tile are collected from the
-//     neighbouring tiles' sorted records into an LDS hit list, in a fixed
-//     order (tiles in neighbour order, blobs by index within a tile).
-//  2. The truncated Gaussian is separable, w = wnorm e0(d0) e1(d1) e2(d2) with
-//     the cut d0^2 + d1^2 + d2^2 <= rc^2, so each hit gets per-axis tables over
-//     the tile's coordinates (factor and squared distance; zero and a large
-//     value off the stencil), HR hits at a time.
-//  3. Wave w owns z-chunk w (8 consecutive axis-2 points), lane = (axis-1
-//     offset, point of the chunk), and keeps the 8 axis-0 planes of its
-//     point in registers.  Per hit it skips, wave-uniformly, a chunk the hit
-//     misses and the axis-0 planes outside the hit's stencil; a point costs a
-//     product, a compare and three multiply-adds.
-//  4. The tile goes through LDS and out with 16-byte stores, whole 128-byte
-//     rows at a time.
-// No atomics and a fixed summation order: results repeat bit for bit.
 template <typename R>
-__global__ __launch_bounds__(NT) void k_spread_sep(GridGeom G, TileGeom T, const SRec* __restrict__ rec,
-                                                   const int* __restrict__ off, const double* __restrict__ lam,
-                                                   const double* __restrict__ lam_sorted, R* __restrict__ f,
-                                                   const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  constexpr int HMAX = NT;              // hits collected per scan
-  constexpr int HR = 64;                // hits per table round
-  constexpr int TX = 8, TZ = 32;        // tile shape the lane map assumes
-  constexpr int TAB = HR * (4 * TX + 2 * TZ);   // table entries per round
-  constexpr int TZP = sizeof(R) == 4 ? TZ + 1 : TZ;   // staged row stride (FP32: padded against bank conflicts)
-  constexpr int STAGE = 3 * TX * TX * TZP;     // staged tile
-  constexpr int SH = TAB > STAGE ? TAB : STAGE;
-  __shared__ int nb_base[125], nb_pref[126];
-  __shared__ double h_e[HMAX][3];       // stencil origin offsets of each hit
-  __shared__ int h_g[HMAX];             // packed stencil origin
-  __shared__ int h_mask[HMAX];          // bits 0-3: z-chunks the hit reaches; bits 8-15: axis-0 planes
-  __shared__ R h_l[HMAX][3];
-  __shared__ R sh[SH];                  // tables during accumulation, then the staged tile
-  __shared__ int wave_cnt[WAVES];
-  R (*t_f0)[TX] = reinterpret_cast<R (*)[TX]>(sh);                      // e0 (x wnorm)
-  R (*t_s0)[TX] = reinterpret_cast<R (*)[TX]>(sh + HR * TX);            // d0^2 (large off the stencil)
-  R (*t_f1)[TX] = reinterpret_cast<R (*)[TX]>(sh + 2 * HR * TX);
-  R (*t_s1)[TX] = reinterpret_cast<R (*)[TX]>(sh + 3 * HR * TX);
-  R (*t_fz)[TZ] = reinterpret_cast<R (*)[TZ]>(sh + 4 * HR * TX);
-  R (*t_sz)[TZ] = reinterpret_cast<R (*)[TZ]>(sh + HR * (4 * TX + TZ));
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tl = blockIdx.x;
+struct HitTab {
+  R f0[8], s0[8];      // axis 0 (f0 carries wnorm)
+  R f1[8], s1[8];      // axis 1
+  R fz[32], sz[32];    // axis 2
+  int mask;            // bits 0-3: z-chunks the hit reaches; bits 8-15: axis-0 planes
+  int pos;             // record position (index into the sorted order)
+  int blob;
+  int pad;
+};
+static_assert(sizeof(HitTab<float>) % 16 == 0 && sizeof(HitTab<double>) % 16 == 0, "16-byte rows");
+
+// Candidates of a tile: the records of the (up to 5 x 5 x 5) neighbour tiles
+// whose anchored blobs can reach it, in neighbour order.
+struct TileFrame {
+  int ts[3], te[3];
+  int nnb;
+};
+
+__device__ __forceinline__ TileFrame tile_frame(const GridGeom& G, const TileGeom& T, int tl, const int* off,
+                                                int* nb_base, int* nb_pref) {
+  TileFrame F;
   const int t2 = tl % T.nt[2], t1 = (tl / T.nt[2]) % T.nt[1], t0 = tl / (T.nt[1] * T.nt[2]);
   const int tt[3] = {t0, t1, t2};
-  const int ts[3] = {t0 * T.T[0], t1 * T.T[1], t2 * T.T[2]};
-  const int te[3] = {min(T.T[0], G.n[0] - ts[0]), min(T.T[1], G.n[1] - ts[1]), min(T.T[2], G.n[2] - ts[2])};
   int c[3], st[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
+    F.ts[d] = tt[d] * T.T[d];
+    F.te[d] = min(T.T[d], G.n[d] - F.ts[d]);
     c[d] = min(2 * T.H[d] + 1, T.nt[d]);
     st[d] = (c[d] == T.nt[d]) ? 0 : tt[d] - T.H[d];
   }
-  const int nnb = c[0] * c[1] * c[2];
-  if (tid < nnb) {
+  F.nnb = c[0] * c[1] * c[2];
+  const int tid = threadIdx.x;
+  if (tid < F.nnb) {
     const int i2 = tid % c[2], i1 = (tid / c[2]) % c[1], i0 = tid / (c[1] * c[2]);
     const int a0 = ((st[0] + i0) % T.nt[0] + T.nt[0]) % T.nt[0];
     const int a1 = ((st[1] + i1) % T.nt[1] + T.nt[1]) % T.nt[1];
@@ -480,51 +441,128 @@ __global__ __launch_bounds__(NT) void k_spread_sep(GridGeom G, TileGeom T, const
   __syncthreads();
   if (tid == 0) {
     nb_pref[0] = 0;
-    for (int k = 1; k <= nnb; ++k) nb_pref[k] += nb_pref[k - 1];
+    for (int k = 1; k <= F.nnb; ++k) nb_pref[k] += nb_pref[k - 1];
   }
   __syncthreads();
-  const int total = nb_pref[nnb];
-  const R big = R(1e30);
-  const R rc2 = R(G.rc2);
-  const int j1 = lane >> 3, zl = lane & 7, z = wave * 8 + zl;
-  const bool live = j1 < te[1] && z < te[2];
-  R acc[TX][3];
+  return F;
+}
+
+// Candidate ci: its record position, and whether its stencil box meets the
+// tile (with the z-chunk / axis-0-plane mask).
+__device__ __forceinline__ bool tile_candidate(const GridGeom& G, const TileFrame& F, const SRec* __restrict__ rec,
+                                               const int* nb_base, const int* nb_pref, int ci, int& pos, int& mask,
+                                               SRec& x) {
+  int lo = 0, hi = F.nnb;   // neighbour tile with nb_pref[lo] <= ci < nb_pref[lo + 1]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (nb_pref[mid] <= ci) lo = mid; else hi = mid;
+  }
+  pos = nb_base[lo] + (ci - nb_pref[lo]);
+  x = rec[pos];
+  const int gb[3] = {x.g & 1023, (x.g >> 10) & 1023, (x.g >> 20) & 1023};
+  bool hit = true;
+  mask = 0;
 #pragma unroll
-  for (int k = 0; k < TX; ++k) acc[k][0] = acc[k][1] = acc[k][2] = R(0);
-  for (int cbase = 0; cbase < total; cbase += NT) {
-    // 1. candidates cbase .. cbase + NT, one per thread
-    bool hit = false;
-    int pos = 0, hmask = 0;
-    SRec x;
-    if (cbase + tid < total) {
-      const int ci = cbase + tid;
-      int lo = 0, hi = nnb;   // neighbour tile k with nb_pref[k] <= ci < nb_pref[k + 1]
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (nb_pref[mid] <= ci) lo = mid; else hi = mid;
-      }
-      pos = nb_base[lo] + (ci - nb_pref[lo]);
-      x = rec[pos];
-      const int gb[3] = {x.g & 1023, (x.g >> 10) & 1023, (x.g >> 20) & 1023};
-      hit = true;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const Ranges Rg = axis_ranges(gb[d], ts[d], te[d], G.n[d], G.P[d]);
-        hit = hit && (Rg.l1 + Rg.l2 > 0);
-        if (d == 0) {
-          // axis-0 planes [s1, s1 + l1) and [s2, s2 + l2) of the tile
-          const int m1 = Rg.l1 > 0 ? ((1 << Rg.l1) - 1) << Rg.s1 : 0;
-          const int m2 = Rg.l2 > 0 ? ((1 << Rg.l2) - 1) << Rg.s2 : 0;
-          hmask |= (m1 | m2) << 8;
-        } else if (d == 2) {
-          // z-chunks covered by [s1, s1 + l1) and [s2, s2 + l2)
-          if (Rg.l1 > 0)
-            for (int q = Rg.s1 >> 3; q <= (Rg.s1 + Rg.l1 - 1) >> 3; ++q) hmask |= 1 << q;
-          if (Rg.l2 > 0)
-            for (int q = Rg.s2 >> 3; q <= (Rg.s2 + Rg.l2 - 1) >> 3; ++q) hmask |= 1 << q;
-        }
-      }
+  for (int d = 0; d < 3; ++d) {
+    const Ranges Rg = axis_ranges(gb[d], F.ts[d], F.te[d], G.n[d], G.P[d]);
+    hit = hit && (Rg.l1 + Rg.l2 > 0);
+    if (d == 0) {
+      // axis-0 planes [s1, s1 + l1) and [s2, s2 + l2) of the tile
+      const int m1 = Rg.l1 > 0 ? ((1 << Rg.l1) - 1) << Rg.s1 : 0;
+      const int m2 = Rg.l2 > 0 ? ((1 << Rg.l2) - 1) << Rg.s2 : 0;
+      mask |= (m1 | m2) << 8;
+    } else if (d == 2) {
+      // z-chunks covered by [s1, s1 + l1) and [s2, s2 + l2)
+      if (Rg.l1 > 0)
+        for (int q = Rg.s1 >> 3; q <= (Rg.s1 + Rg.l1 - 1) >> 3; ++q) mask |= 1 << q;
+      if (Rg.l2 > 0)
+        for (int q = Rg.s2 >> 3; q <= (Rg.s2 + Rg.l2 - 1) >> 3; ++q) mask |= 1 << q;
     }
+  }
+  return hit;
+}
+
+// One axis of the tables of hits [0, nr) (origin offsets he, packed origins
+// hg) into out[h]: for tile offset j < W along axis D, the stencil offset
+// a = (ts + j - g) mod n; inside the stencil (a < P, j < te) the factor
+// exp(-d^2 / 2 sigma^2) (axis 0 also carries wnorm) and d^2, else 0 and
+// `big`.  The axis is a compile-time constant (a runtime index into the
+// kernel-argument struct would be a memory load per entry).
+template <typename R, int D>
+__device__ __forceinline__ void table_axis(const GridGeom& G, const TileFrame& F, int nr, const double (*he)[3],
+                                           const int* hg, HitTab<R>* out, R big) {
+  constexpr int W = D == 2 ? 32 : 8, LW = D == 2 ? 5 : 3;
+  const int n = G.n[D], P = G.P[D];
+  const double dx = G.dx[D], i2 = G.inv2s2, wn = G.wnorm;
+  for (int e = threadIdx.x; e < nr * W; e += NT) {
+    const int h = e >> LW, j = e & (W - 1);
+    const int gb = (hg[h] >> (10 * D)) & 1023;
+    int a = F.ts[D] + j - gb;
+    a += (a < 0) ? n : 0;
+    R fv = R(0), sv = big;
+    if (j < F.te[D] && a < P) {
+      const double dd = he[h][D] + a * dx;
+      const double s2 = dd * dd;
+      sv = R(s2);
+      fv = gexp<R>(R(-s2 * i2));
+      if (D == 0) fv *= R(wn);
+    }
+    if (D == 0) {
+      out[h].f0[j] = fv;
+      out[h].s0[j] = sv;
+    } else if (D == 1) {
+      out[h].f1[j] = fv;
+      out[h].s1[j] = sv;
+    } else {
+      out[h].fz[j] = fv;
+      out[h].sz[j] = sv;
+    }
+  }
+}
+
+// Per tile: count its hits, claim room for them in `tabs` (tab_start,
+// tab_count), and write their tables in candidate order.  The order fixes
+// every later summation; the room's place does not matter.
+template <typename R>
+__global__ __launch_bounds__(NT) void k_spread_prep(GridGeom G, TileGeom T, const SRec* __restrict__ rec,
+                                                    const int* __restrict__ off, HitTab<R>* __restrict__ tabs,
+                                                    int* __restrict__ tab_start, int* __restrict__ tab_count,
+                                                    unsigned int* __restrict__ claimed) {
+  constexpr int HMAX = NT;
+  __shared__ int nb_base[125], nb_pref[126];
+  __shared__ double h_e[HMAX][3];
+  __shared__ int h_g[HMAX];
+  __shared__ int wave_cnt[WAVES];
+  __shared__ int base_s;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const TileFrame F = tile_frame(G, T, blockIdx.x, off, nb_base, nb_pref);
+  const int total = nb_pref[F.nnb];
+  // 1. count the hits
+  int mine = 0;
+  for (int ci = tid; ci < total; ci += NT) {
+    int pos, mask;
+    SRec x;
+    mine += tile_candidate(G, F, rec, nb_base, nb_pref, ci, pos, mask, x) ? 1 : 0;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o, 64);
+  if (lane == 0) wave_cnt[wave] = mine;
+  __syncthreads();
+  if (tid == 0) {
+    int nh = 0;
+    for (int w = 0; w < WAVES; ++w) nh += wave_cnt[w];
+    base_s = (int)atomicAdd(claimed, (unsigned)nh);
+    tab_start[blockIdx.x] = base_s;
+    tab_count[blockIdx.x] = nh;
+  }
+  __syncthreads();
+  const R big = R(1e30);
+  int running = base_s;
+  // 2. candidates again, NT at a time: compact the hits, then their tables
+  for (int cbase = 0; cbase < total; cbase += NT) {
+    int pos = 0, mask = 0;
+    SRec x;
+    const bool hit = (cbase + tid < total) && tile_candidate(G, F, rec, nb_base, nb_pref, cbase + tid, pos, mask, x);
     const unsigned long long m = __ballot(hit);
     if (lane == 0) wave_cnt[wave] = __popcll(m);
     __syncthreads();
@@ -539,43 +577,92 @@ __global__ __launch_bounds__(NT) void k_spread_sep(GridGeom G, TileGeom T, const
       h_e[slot][1] = x.e[1];
       h_e[slot][2] = x.e[2];
       h_g[slot] = x.g;
-      h_mask[slot] = hmask;
-#pragma unroll
-      for (int q = 0; q < 3; ++q) h_l[slot][q] = R(lam_sorted ? lam_sorted[3LL * pos + q] : lam[3LL * x.blob + q]);
+      HitTab<R>& t = tabs[running + slot];
+      t.mask = mask;
+      t.pos = pos;
+      t.blob = x.blob;
+      t.pad = 0;
     }
     __syncthreads();
-    for (int hb = 0; hb < nh; hb += HR) {
-      const int nr = min(HR, nh - hb);
-      // 2. per-axis tables; the axis is a compile-time constant in each loop
-      //    (a runtime index into the kernel-argument struct would be a
-      //    memory load per entry)
-      table_axis<R, 0, TX>(G, ts[0], te[0], nr, h_e + hb, h_g + hb, t_f0, t_s0, big);
-      table_axis<R, 1, TX>(G, ts[1], te[1], nr, h_e + hb, h_g + hb, t_f1, t_s1, big);
-      table_axis<R, 2, TZ>(G, ts[2], te[2], nr, h_e + hb, h_g + hb, t_fz, t_sz, big);
-      __syncthreads();
-      // 3. accumulate
-      if (live) {
-        for (int h = 0; h < nr; ++h) {
-          const int hm = h_mask[hb + h];
-          if (!((hm >> wave) & 1)) continue;
-          const R s12 = t_s1[h][j1] + t_sz[h][z];
-          if (s12 > rc2) continue;
-          const R f12 = t_f1[h][j1] * t_fz[h][z];
-          const R l0 = h_l[hb + h][0], l1 = h_l[hb + h][1], l2 = h_l[hb + h][2];
+    table_axis<R, 0>(G, F, nh, h_e, h_g, tabs + running, big);
+    table_axis<R, 1>(G, F, nh, h_e, h_g, tabs + running, big);
+    table_axis<R, 2>(G, F, nh, h_e, h_g, tabs + running, big);
+    running += nh;
+    __syncthreads();
+  }
+}
+
+// Spreading f = S lambda, one workgroup per tile, from the tables of
+// k_spread_prep.  Wave w owns z-chunk w (8 consecutive axis-2 points), lane =
+// (axis-1 offset, point of the chunk), with the 8 axis-0 planes of its point
+// in registers.  Per hit it skips, wave-uniformly, a chunk the hit misses and
+// the axis-0 planes outside the hit's stencil; a point costs a product, a
+// compare and three multiply-adds.  The tile then goes through LDS and out
+// with 16-byte stores, whole 128-byte rows at a time.  No atomics and a fixed
+// summation order: results repeat bit for bit.
+template <typename R>
+__global__ __launch_bounds__(NT) void k_spread_tab(GridGeom G, TileGeom T, const HitTab<R>* __restrict__ tabs,
+                                                   const int* __restrict__ tab_start,
+                                                   const int* __restrict__ tab_count, const double* __restrict__ lam,
+                                                   const double* __restrict__ lam_sorted, R* __restrict__ f,
+                                                   const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  constexpr int HR = 64;                // hits per round
+  constexpr int TX = 8, TZ = 32;
+  constexpr int TZP = sizeof(R) == 4 ? TZ + 1 : TZ;   // staged row stride (FP32: padded against bank conflicts)
+  constexpr int STAGE = 3 * TX * TX * TZP;
+  constexpr int TABR = HR * (int)(sizeof(HitTab<R>) / sizeof(R));
+  constexpr int SH = TABR > STAGE ? TABR : STAGE;
+  __shared__ __align__(16) R sh[SH];    // a round of tables, then the staged tile
+  __shared__ R h_l[HR][3];
+  HitTab<R>* tab = reinterpret_cast<HitTab<R>*>(sh);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tl = blockIdx.x;
+  const int t2 = tl % T.nt[2], t1 = (tl / T.nt[2]) % T.nt[1], t0 = tl / (T.nt[1] * T.nt[2]);
+  const int ts[3] = {t0 * T.T[0], t1 * T.T[1], t2 * T.T[2]};
+  const int te[3] = {min(T.T[0], G.n[0] - ts[0]), min(T.T[1], G.n[1] - ts[1]), min(T.T[2], G.n[2] - ts[2])};
+  const int start = tab_start[tl], cnt = tab_count[tl];
+  const R rc2 = R(G.rc2);
+  const int j1 = lane >> 3, zl = lane & 7, z = wave * 8 + zl;
+  const bool live = j1 < te[1] && z < te[2];
+  R acc[TX][3];
 #pragma unroll
-          for (int k = 0; k < TX; ++k) {
-            if (!((hm >> (8 + k)) & 1)) continue;
-            const R w = (t_s0[h][k] + s12 <= rc2) ? f12 * t_f0[h][k] : R(0);
-            acc[k][0] += w * l0;
-            acc[k][1] += w * l1;
-            acc[k][2] += w * l2;
-          }
+  for (int k = 0; k < TX; ++k) acc[k][0] = acc[k][1] = acc[k][2] = R(0);
+  constexpr int V16 = (int)(sizeof(HitTab<R>) / 16);
+  for (int hb = 0; hb < cnt; hb += HR) {
+    const int nr = min(HR, cnt - hb);
+    const uint4* src = reinterpret_cast<const uint4*>(tabs + start + hb);
+    uint4* dstv = reinterpret_cast<uint4*>(sh);
+    for (int v = tid; v < nr * V16; v += NT) dstv[v] = src[v];
+    __syncthreads();
+    if (tid < nr) {
+      const int p = tab[tid].pos, b = tab[tid].blob;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) h_l[tid][q] = R(lam_sorted ? lam_sorted[3LL * p + q] : lam[3LL * b + q]);
+    }
+    __syncthreads();
+    if (live) {
+      for (int h = 0; h < nr; ++h) {
+        const HitTab<R>& t = tab[h];
+        const int hm = t.mask;
+        if (!((hm >> wave) & 1)) continue;
+        const R s12 = t.s1[j1] + t.sz[z];
+        if (s12 > rc2) continue;
+        const R f12 = t.f1[j1] * t.fz[z];
+        const R l0 = h_l[h][0], l1 = h_l[h][1], l2 = h_l[h][2];
+#pragma unroll
+        for (int k = 0; k < TX; ++k) {
+          if (!((hm >> (8 + k)) & 1)) continue;
+          const R w = (t.s0[k] + s12 <= rc2) ? f12 * t.f0[k] : R(0);
+          acc[k][0] += w * l0;
+          acc[k][1] += w * l1;
+          acc[k][2] += w * l2;
         }
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
-  // 4. stage [c][axis-0][axis-1][z] and write rows with 16-byte stores
+  // stage [c][axis-0][axis-1][z] and write rows with 16-byte stores
 #pragma unroll
   for (int k = 0; k < TX; ++k) {
 #pragma unroll
@@ -591,15 +678,15 @@ __global__ __launch_bounds__(NT) void k_spread_sep(GridGeom G, TileGeom T, const
     const int c0 = col >> 3, c1 = col & 7;
     if (c0 >= te[0] || c1 >= te[1] || zv >= te[2]) continue;
     const long long idx = cc * Gs + ((long long)(ts[0] + c0) * G.n[1] + (ts[1] + c1)) * G.n[2] + ts[2] + zv;
-    const R* src = sh + (cc * TX * TX + col) * TZP + zv;
+    const R* srcv = sh + (cc * TX * TX + col) * TZP + zv;
     if (zv + VW <= te[2]) {
       if constexpr (sizeof(R) == 4) {
-        *reinterpret_cast<float4*>(f + idx) = make_float4(src[0], src[1], src[2], src[3]);
+        *reinterpret_cast<float4*>(f + idx) = make_float4(srcv[0], srcv[1], srcv[2], srcv[3]);
       } else {
-        *reinterpret_cast<double2*>(f + idx) = make_double2(src[0], src[1]);
+        *reinterpret_cast<double2*>(f + idx) = make_double2(srcv[0], srcv[1]);
       }
     } else {
-      for (int v = 0; zv + v < te[2]; ++v) f[idx + v] = src[v];
+      for (int v = 0; zv + v < te[2]; ++v) f[idx + v] = srcv[v];
     }
   }
 }
@@ -661,17 +748,42 @@ int tile_sort(const GridGeom& g, const TileGeom& t, const double* r, int M, int*
   return GDC_OK;
 }
 
+size_t spread_table_bytes(const GridGeom& g, const TileGeom& t, int M, int precision) {
+  // a stencil of P points meets at most ceil((P - 1) / T) + 2 tiles of an
+  // axis (a partial last tile can add one), and never more than nt
+  size_t per = 1;
+  for (int d = 0; d < 3; ++d) {
+    const int k = (g.P[d] - 1 + t.T[d] - 1) / t.T[d] + 2;
+    per *= (size_t)std::min(k, t.nt[d]);
+  }
+  const size_t rec = precision == GDC_FP64 ? sizeof(HitTab<double>) : sizeof(HitTab<float>);
+  return per * (size_t)(M > 0 ? M : 1) * rec;
+}
+
 template <typename R>
-int spread(const GridGeom& g, const TileGeom& t, const void* rec, const double* lam, const double* lam_sorted,
-           const int* off, R* f, hipStream_t s, const int* skip) {
-  if (t.T[0] > 8 || t.T[1] > 8 || t.T[2] > 32) {
-    set_error("spread: tiles larger than 8 x 8 x 32");
+int spread_prepare(const GridGeom& g, const TileGeom& t, const void* rec, const int* off, void* tabs,
+                   int* tab_start, int* tab_count, unsigned int* claimed, hipStream_t s) {
+  if (t.T[0] != 8 || t.T[1] != 8 || t.T[2] > 32) {
+    set_error("spread: tiles must be 8 x 8 x (up to 32)");
+    return GDC_EINVAL;
+  }
+  GDC_TRY(fill_zero(claimed, 16, s));
+  hipLaunchKernelGGL((k_spread_prep<R>), dim3(t.ntiles), dim3(NT), 0, s, g, t, (const SRec*)rec, off,
+                     (HitTab<R>*)tabs, tab_start, tab_count, claimed);
+  return check_launch("k_spread_prep");
+}
+
+template <typename R>
+int spread(const GridGeom& g, const TileGeom& t, const void* tabs, const int* tab_start, const int* tab_count,
+           const double* lam, const double* lam_sorted, R* f, hipStream_t s, const int* skip) {
+  if (t.T[0] != 8 || t.T[1] != 8 || t.T[2] > 32) {
+    set_error("spread: tiles must be 8 x 8 x (up to 32)");
     return GDC_EINVAL;
   }
   ProbeScope ps("spread", s);
-  hipLaunchKernelGGL((k_spread_sep<R>), dim3(t.ntiles), dim3(NT), 0, s, g, t, (const SRec*)rec, off, lam,
-                     lam_sorted, f, skip);
-  return check_launch("k_spread_sep");
+  hipLaunchKernelGGL((k_spread_tab<R>), dim3(t.ntiles), dim3(NT), 0, s, g, t, (const HitTab<R>*)tabs, tab_start,
+                     tab_count, lam, lam_sorted, f, skip);
+  return check_launch("k_spread_tab");
 }
 
 template <typename R>
@@ -702,10 +814,14 @@ int interp_fd(const GridGeom& g, const double* r, const double* dr, int NP, cons
   return check_launch("k_interp_fd");
 }
 
-template int spread<float>(const GridGeom&, const TileGeom&, const void*, const double*, const double*, const int*,
-                           float*, hipStream_t, const int*);
-template int spread<double>(const GridGeom&, const TileGeom&, const void*, const double*, const double*, const int*,
-                            double*, hipStream_t, const int*);
+template int spread_prepare<float>(const GridGeom&, const TileGeom&, const void*, const int*, void*, int*, int*,
+                                   unsigned int*, hipStream_t);
+template int spread_prepare<double>(const GridGeom&, const TileGeom&, const void*, const int*, void*, int*, int*,
+                                    unsigned int*, hipStream_t);
+template int spread<float>(const GridGeom&, const TileGeom&, const void*, const int*, const int*, const double*,
+                           const double*, float*, hipStream_t, const int*);
+template int spread<double>(const GridGeom&, const TileGeom&, const void*, const int*, const int*, const double*,
+                            const double*, double*, hipStream_t, const int*);
 template int interp<float>(const GridGeom&, const double*, const float*, double*, int, double, const int*,
                            const double*, const double*, hipStream_t, const int*);
 template int interp<double>(const GridGeom&, const double*, const double*, double*, int, double, const int*,
