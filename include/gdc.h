@@ -35,6 +35,7 @@
 #ifndef GDC_H
 #define GDC_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -55,6 +56,7 @@ enum { GDC_HOST = 0, GDC_DEVICE = 1 };        /* memspace */
 enum { GDC_BLOB = 0, GDC_BODY = 1 };          /* gdc_mobility_apply mode */
 enum { GDC_SCHEME_GDC = 0, GDC_SCHEME_EM = 1 };
 enum { GDC_DIV_FD = 0, GDC_DIV_RFD = 1 };
+enum { GDC_UNTIL_ALL = 0, GDC_UNTIL_ANY = 1 };  /* gdc_batch_step return condition */
 
 /* A rigid body shape: n_blobs body-frame blob offsets b_i (n_blobs x 3);
  * a body with reference point Y and orientation q has blobs at
@@ -111,14 +113,17 @@ typedef struct {
   void* stream;
 } gdc_config;
 
-/* Per-call statistics of gdc_step (values of the last step taken). */
+/* Per-call statistics of gdc_step and gdc_batch_step (values of the last
+ * step completed in the call). */
 typedef struct {
-  int steps_done;
+  int steps_done;            /* steps completed in this call */
   int gmres_iterations;      /* preconditioned GMRES iterations, last step */
   double gmres_relres;       /* final relative residual, last step */
   double nu;                 /* drift factor nu of the last step (Sec. 3, step 3) */
   int nu_nonpositive;        /* steps of this call whose nu was <= 0 */
-  double ms;                 /* wall time of the call */
+  double ms;                 /* gdc_step: wall time of the call; gdc_batch_step:
+                                time from the call's start to this handle's
+                                last completed step (0 if none) */
 } gdc_stats;
 
 typedef struct gdc_handle gdc_handle;
@@ -158,6 +163,52 @@ int gdc_mobility_apply(gdc_handle* h, int mode, const double* Y, const double* q
  * Errors: GDC_EINVAL, GDC_ENOTCONV (the step is still taken), GDC_ENUMERIC,
  * GDC_EDEVICE. */
 int gdc_step(gdc_handle* h, int n_steps, double* Y, double* q, int memspace, gdc_stats* st);
+
+/* Resident state for gdc_batch_step (Sec. 3: the state of a suspension is
+ * (Y, q)).  gdc_set_state copies Y (N x 3) and q (N x 4, unit norm within
+ * 1e-6, host arrays checked) into the handle; gdc_get_state copies the
+ * current state out.  gdc_step also leaves its result resident.  Both wait
+ * for the handle's stream.  Errors: GDC_EINVAL (no state yet, a step in
+ * flight, bad quaternion), GDC_EDEVICE. */
+int gdc_set_state(gdc_handle* h, const double* Y, const double* q, int memspace);
+int gdc_get_state(gdc_handle* h, double* Y, double* q, int memspace);
+
+/* Advance several independent resident suspensions together (the steps of
+ * Sec. 3 for each).  One host thread keeps every handle's step in flight:
+ * each handle's kernels go to its own stream, so the work of different
+ * suspensions overlaps on the device, and each handle's GMRES status is
+ * polled without blocking the others.  The result of each handle is the
+ * same as gdc_step on it alone (same kernels, same order, same noise).
+ *   hs[nh]: distinct handles holding a state (gdc_set_state / gdc_step),
+ *     each on its own stream (handles sharing a stream are serialised, still
+ *     correct).
+ *   steps[nh] (in/out): steps still to take per handle; each completed step
+ *     decrements it.
+ *   until: GDC_UNTIL_ALL returns when every entry of steps is 0;
+ *     GDC_UNTIL_ANY as soon as one handle that had steps left at entry has
+ *     none.  max_ms > 0 also returns once that much wall time has passed
+ *     (0: no limit).  A handle left in the middle of a step keeps its place:
+ *     its queued kernels continue on the device, and the next
+ *     gdc_batch_step call resumes it; every other call on that handle except
+ *     gdc_free returns GDC_EINVAL until the step is finished.
+ *   st[nh] (optional): per-handle statistics of this call.
+ * Errors: GDC_EINVAL; GDC_ENOTCONV / GDC_ENUMERIC (as gdc_step, for the
+ * first handle that hit one; the steps are still taken); GDC_EDEVICE. */
+int gdc_batch_step(gdc_handle* const* hs, int nh, int* steps, int until, double max_ms, gdc_stats* st);
+
+/* Completion times of the handle's steps, in milliseconds of the host's
+ * monotonic clock (CLOCK_MONOTONIC), oldest first: the time of the last
+ * gdc_set_state, then one entry per completed step.  Copies up to cap
+ * entries into t_ms, sets *count, and drops them from the handle's log
+ * except the newest, from which the next step's latency is measured. */
+int gdc_step_log(gdc_handle* h, double* t_ms, int cap, int* count);
+
+/* Device memory a handle for cfg would hold, in bytes, without allocating
+ * or touching a device (admission control by HBM footprint).  gdc_device_bytes
+ * gives the same figure for an existing handle.  Errors: as gdc_init's
+ * validation. */
+int gdc_footprint(const gdc_config* cfg, size_t* bytes);
+int gdc_device_bytes(const gdc_handle* h, size_t* bytes);
 
 /* Internal step counter (checkpoint / resume: with the same state and
  * counter a resumed run repeats an uninterrupted one exactly). */

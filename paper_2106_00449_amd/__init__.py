@@ -14,7 +14,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Suspension", "GdcError", "LIB_PATH", "lib",
+__all__ = ["Suspension", "GdcError", "LIB_PATH", "lib", "batch_step", "footprint",
            "GDC_FP32", "GDC_FP64", "GDC_BLOB", "GDC_BODY",
            "GDC_SCHEME_GDC", "GDC_SCHEME_EM", "GDC_DIV_FD", "GDC_DIV_RFD"]
 
@@ -26,6 +26,7 @@ GDC_HOST, GDC_DEVICE = 0, 1
 GDC_BLOB, GDC_BODY = 0, 1
 GDC_SCHEME_GDC, GDC_SCHEME_EM = 0, 1
 GDC_DIV_FD, GDC_DIV_RFD = 0, 1
+GDC_UNTIL_ALL, GDC_UNTIL_ANY = 0, 1
 
 _NAMES = {GDC_EINVAL: "GDC_EINVAL", GDC_ENOMEM: "GDC_ENOMEM", GDC_ENOTCONV: "GDC_ENOTCONV",
           GDC_ENUMERIC: "GDC_ENUMERIC", GDC_EDEVICE: "GDC_EDEVICE"}
@@ -84,9 +85,17 @@ def _load():
     L.gdc_philox_normals.argtypes = [P, U64, U32, U64, U32, I, D]
     L.gdc_probe_kernel.argtypes = [ctypes.c_char_p]
     L.gdc_probe_read.argtypes = [D, ctypes.POINTER(ctypes.c_longlong)]
+    L.gdc_set_state.argtypes = [P, P, P, I]
+    L.gdc_get_state.argtypes = [P, P, P, I]
+    L.gdc_batch_step.argtypes = [ctypes.POINTER(P), I, ctypes.POINTER(I), I, ctypes.c_double,
+                                 ctypes.POINTER(_Stats)]
+    L.gdc_step_log.argtypes = [P, D, I, ctypes.POINTER(I)]
+    L.gdc_footprint.argtypes = [ctypes.POINTER(_Config), ctypes.POINTER(ctypes.c_size_t)]
+    L.gdc_device_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
     for name in ["gdc_init", "gdc_mobility_apply", "gdc_step", "gdc_get_step", "gdc_set_step",
                  "gdc_fluct_velocity", "gdc_predictor", "gdc_philox_normals", "gdc_probe_kernel",
-                 "gdc_probe_read"]:
+                 "gdc_probe_read", "gdc_set_state", "gdc_get_state", "gdc_batch_step", "gdc_step_log",
+                 "gdc_footprint", "gdc_device_bytes"]:
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -148,52 +157,88 @@ def probe_read():
     return ms.value, n.value
 
 
+def _make_config(L, n, shapes, body_shape, *, a=1.0, sigma=0.0, trunc=0.0,
+                 eta=1.0 / (6.0 * np.pi), kT=1.0, dt=0.01, fd_delta=0.0, gmres_tol=0.0,
+                 gmres_maxit=0, gmres_restart=0, precision="fp32", scheme="gdc",
+                 divergence="fd", seed=0, steric_k=0.0, steric_cutoff=0.0,
+                 const_force=(0, 0, 0, 0, 0, 0), shear_rate=0.0, device=0, stream=None):
+    """A gdc_config and the arrays it points into (kept alive by the caller)."""
+    shape_arrays = [np.ascontiguousarray(np.asarray(s, dtype=np.float64).reshape(-1, 3)) for s in shapes]
+    bshape = np.ascontiguousarray(np.asarray(body_shape, dtype=np.int32))
+    sh = (_Shape * len(shapes))()
+    for i, s in enumerate(shape_arrays):
+        sh[i].n_blobs = s.shape[0]
+        sh[i].b = s.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    c = _Config()
+    Ls = np.broadcast_to(np.asarray(L, dtype=np.float64), (3,))
+    ns = np.broadcast_to(np.asarray(n, dtype=np.int64), (3,))
+    for d in range(3):
+        c.L[d] = float(Ls[d])
+        c.n[d] = int(ns[d])
+    c.a, c.sigma, c.trunc, c.eta, c.kT, c.dt = a, sigma, trunc, eta, kT, dt
+    c.fd_delta, c.gmres_tol, c.gmres_maxit, c.gmres_restart = fd_delta, gmres_tol, gmres_maxit, gmres_restart
+    c.precision = {"fp32": GDC_FP32, "fp64": GDC_FP64}[precision]
+    c.scheme = {"gdc": GDC_SCHEME_GDC, "em": GDC_SCHEME_EM}[scheme]
+    c.divergence = {"fd": GDC_DIV_FD, "rfd": GDC_DIV_RFD}[divergence]
+    c.seed = int(seed)
+    c.n_shapes = len(shapes)
+    c.shapes = ctypes.cast(sh, ctypes.POINTER(_Shape))
+    c.n_bodies = int(bshape.size)
+    c.body_shape = bshape.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    c.forces.steric_k, c.forces.steric_cutoff = steric_k, steric_cutoff
+    for k in range(6):
+        c.forces.const_force[k] = float(const_force[k])
+    c.forces.shear_rate = shear_rate
+    c.device = int(device)
+    c.stream = stream
+    keep = {"shapes": shape_arrays, "body_shape": bshape, "shapes_c": sh, "N": int(bshape.size),
+            "M": int(sum(shape_arrays[s].shape[0] for s in bshape)), "n": tuple(int(x) for x in ns)}
+    return c, keep
+
+
+def footprint(L, n, shapes, body_shape, **kw):
+    """Device bytes a Suspension with these arguments would hold (no device
+    is touched)."""
+    c, keep = _make_config(L, n, shapes, body_shape, **kw)
+    b = ctypes.c_size_t()
+    _check(lib.gdc_footprint(ctypes.byref(c), ctypes.byref(b)))
+    return int(b.value)
+
+
+def batch_step(susps, steps, until="all", max_ms=0.0):
+    """Advance resident suspensions together (gdc_batch_step).
+
+    steps: steps still to take per suspension.  Returns (steps left,
+    per-suspension statistics, return code); GDC_ENOTCONV is returned, not
+    raised, other errors raise."""
+    nh = len(susps)
+    hs = (ctypes.c_void_p * max(nh, 1))(*[s._h for s in susps])
+    st_in = (ctypes.c_int * max(nh, 1))(*[int(x) for x in steps])
+    stats = (_Stats * max(nh, 1))()
+    rc = lib.gdc_batch_step(hs, nh, st_in, {"all": GDC_UNTIL_ALL, "any": GDC_UNTIL_ANY}[until],
+                            float(max_ms), stats)
+    if rc not in (GDC_OK, GDC_ENOTCONV):
+        _check(rc)
+    out = [{"steps_done": x.steps_done, "gmres_iterations": x.gmres_iterations,
+            "gmres_relres": x.gmres_relres, "nu": x.nu, "nu_nonpositive": x.nu_nonpositive,
+            "ms": x.ms} for x in stats[:nh]]
+    return [int(x) for x in st_in[:nh]], out, rc
+
+
 class Suspension:
     """A suspension of rigid multiblob bodies in a periodic box on one GPU.
 
     shapes: list of (n_b, 3) body-frame blob offsets; body_shape: (N,) ints.
     Remaining keyword arguments follow gdc_config (include/gdc.h)."""
 
-    def __init__(self, L, n, shapes, body_shape, *, a=1.0, sigma=0.0, trunc=0.0,
-                 eta=1.0 / (6.0 * np.pi), kT=1.0, dt=0.01, fd_delta=0.0, gmres_tol=0.0,
-                 gmres_maxit=0, gmres_restart=0, precision="fp32", scheme="gdc",
-                 divergence="fd", seed=0, steric_k=0.0, steric_cutoff=0.0,
-                 const_force=(0, 0, 0, 0, 0, 0), shear_rate=0.0, device=0, stream=None):
-        self._shape_arrays = [np.ascontiguousarray(np.asarray(s, dtype=np.float64).reshape(-1, 3))
-                              for s in shapes]
-        self._body_shape = np.ascontiguousarray(np.asarray(body_shape, dtype=np.int32))
-        sh = (_Shape * len(shapes))()
-        for i, s in enumerate(self._shape_arrays):
-            sh[i].n_blobs = s.shape[0]
-            sh[i].b = s.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        self._shapes_c = sh
-        c = _Config()
-        Ls = np.broadcast_to(np.asarray(L, dtype=np.float64), (3,))
-        ns = np.broadcast_to(np.asarray(n, dtype=np.int64), (3,))
-        for d in range(3):
-            c.L[d] = float(Ls[d])
-            c.n[d] = int(ns[d])
-        c.a, c.sigma, c.trunc, c.eta, c.kT, c.dt = a, sigma, trunc, eta, kT, dt
-        c.fd_delta, c.gmres_tol, c.gmres_maxit, c.gmres_restart = fd_delta, gmres_tol, gmres_maxit, gmres_restart
-        c.precision = {"fp32": GDC_FP32, "fp64": GDC_FP64}[precision]
-        c.scheme = {"gdc": GDC_SCHEME_GDC, "em": GDC_SCHEME_EM}[scheme]
-        c.divergence = {"fd": GDC_DIV_FD, "rfd": GDC_DIV_RFD}[divergence]
-        c.seed = int(seed)
-        c.n_shapes = len(shapes)
-        c.shapes = ctypes.cast(sh, ctypes.POINTER(_Shape))
-        c.n_bodies = int(self._body_shape.size)
-        c.body_shape = self._body_shape.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
-        c.forces.steric_k, c.forces.steric_cutoff = steric_k, steric_cutoff
-        for k in range(6):
-            c.forces.const_force[k] = float(const_force[k])
-        c.forces.shear_rate = shear_rate
-        c.device = int(device)
-        c.stream = stream
+    def __init__(self, L, n, shapes, body_shape, **kw):
+        c, keep = _make_config(L, n, shapes, body_shape, **kw)
+        self._keep = keep
         self._cfg = c
-        self.N = int(self._body_shape.size)
-        self.M = int(sum(self._shape_arrays[s].shape[0] for s in self._body_shape))
-        self.n = tuple(int(x) for x in ns)
-        self.precision = precision
+        self.N = keep["N"]
+        self.M = keep["M"]
+        self.n = keep["n"]
+        self.precision = kw.get("precision", "fp32")
         h = ctypes.c_void_p()
         _check(lib.gdc_init(ctypes.byref(c), ctypes.byref(h)))
         self._h = h
@@ -250,6 +295,35 @@ class Suspension:
         if rc != GDC_ENOTCONV:
             _check(rc)
         return stats
+
+    def set_state(self, Y, q):
+        """Make (Y, q) the resident state (for batch_step)."""
+        aY, aq = _Arg(Y, (self.N, 3)), _Arg(q, (self.N, 4))
+        _check(lib.gdc_set_state(self._h, aY.ptr, aq.ptr, _memspace(aY, aq)))
+
+    def get_state(self):
+        """The resident state (Y (N x 3), q (N x 4)) as host arrays."""
+        Y = np.empty((self.N, 3))
+        q = np.empty((self.N, 4))
+        _check(lib.gdc_get_state(self._h, Y.ctypes.data_as(ctypes.c_void_p), q.ctypes.data_as(ctypes.c_void_p),
+                                 GDC_HOST))
+        return Y, q
+
+    def step_log(self, cap=1 << 16):
+        """Completion times (ms, monotonic clock) logged since the last read;
+        the first entry is the previous read's last one (or the set_state
+        time)."""
+        buf = np.empty(cap)
+        cnt = ctypes.c_int()
+        _check(lib.gdc_step_log(self._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cap,
+                                ctypes.byref(cnt)))
+        return buf[:cnt.value].copy()
+
+    @property
+    def device_bytes(self):
+        b = ctypes.c_size_t()
+        _check(lib.gdc_device_bytes(self._h, ctypes.byref(b)))
+        return int(b.value)
 
     @property
     def step_counter(self):

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <thread>
 
 namespace gdc {
 
@@ -253,6 +254,49 @@ int dalloc(T** p, size_t count) {
   return GDC_OK;
 }
 
+struct GmresResult {
+  int its = 0;
+  double relres = 0.0;
+  bool converged = false;
+};
+
+// Status of the device GMRES as the host reads it.
+struct GmStatus {
+  double est;
+  int its, kdone, done, converged;
+};
+
+// Host side of a GMRES solve in progress (the device side is GmresState).
+// A solve advances by one enqueue or one status read at a time, so that one
+// host thread can keep the solves of many handles in flight at once.
+struct SolveRun {
+  enum Phase { IDLE, CYCLE, ITER, FINISH, FINISH_WAIT, DONE };
+  Phase phase = IDLE;
+  const double *Y = nullptr, *q = nullptr, *r = nullptr;
+  bool first = true;    // first cycle: the residual is the right-hand side
+  int k = 0;            // Arnoldi column of the current cycle
+  bool queued = false;  // iteration k is on the stream
+  GmStatus st{};
+  GmresResult res{};
+};
+
+// Host side of a time step in progress: the pre-solve kernels are queued
+// on entry to SOLVE; POST_WAIT waits for the update and the readback of nu
+// and the error flags.
+struct StepRun {
+  enum Phase { IDLE, SOLVE, POST_WAIT };
+  Phase phase = IDLE;
+  GmresResult gr{};
+  double nu = 1.0;
+};
+
+// Outcome of one advance of a solve or a step.
+enum Advance { ADV_BLOCKED = 0, ADV_PROGRESS = 1, ADV_DONE = 2 };
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 }  // namespace
 }  // namespace gdc
 
@@ -302,6 +346,16 @@ struct gdc_handle {
   unsigned char* gm_host = nullptr;   // pinned: two status slots
   unsigned char* gm_host_dev = nullptr;   // the same memory as the device sees it
   hipEvent_t gm_ev[2] = {nullptr, nullptr};
+  hipEvent_t step_ev = nullptr;   // end of a step's update and readback
+
+  bool dry = false;               // footprint query: count device bytes, touch no device
+  size_t dev_bytes = 0;           // device memory held by the handle
+  bool has_state = false;         // Y, q hold a state (gdc_set_state or gdc_step)
+  SolveRun sv;
+  StepRun sr;
+  std::vector<double> step_log;   // completion times of steps (ms, monotonic clock)
+  // error counts of the steps completed since the last gdc_step / gdc_batch_step entry
+  int n_overflow = 0, n_nonfinite = 0, n_notconv = 0, n_nonpos = 0;
 
   ~gdc_handle() {
     for (void* p : allocs) (void)hipFree(p);
@@ -309,11 +363,17 @@ struct gdc_handle {
     if (gm_host) (void)hipHostFree(gm_host);
     for (hipEvent_t e : gm_ev)
       if (e) (void)hipEventDestroy(e);
+    if (step_ev) (void)hipEventDestroy(step_ev);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 
   template <typename T>
   int alloc(T** p, size_t count) {
+    dev_bytes += std::max<size_t>(count, 1) * sizeof(T);
+    if (dry) {
+      *p = nullptr;
+      return GDC_OK;
+    }
     GDC_TRY(dalloc(p, count));
     allocs.push_back((void*)*p);
     return GDC_OK;
@@ -394,18 +454,6 @@ int apply_saddle_precond(gdc_handle* h, const double* Y, const double* q, const 
   return apply_mobility<R>(h, r, z, y, Y, z + m3, h->zsorted, skip);
 }
 
-struct GmresResult {
-  int its = 0;
-  double relres = 0.0;
-  bool converged = false;
-};
-
-// Status of the device GMRES as the host reads it.
-struct GmStatus {
-  double est;
-  int its, kdone, done, converged;
-};
-
 GmStatus read_status(const unsigned char* p) {
   GmStatus st;
   std::memcpy(&st.est, p, sizeof(double));
@@ -421,9 +469,30 @@ int post_status(gdc_handle* h, int slot) {
   return GDC_OK;
 }
 
-int wait_status(gdc_handle* h, int slot, GmStatus& st) {
-  GDC_HIP(hipEventSynchronize(h->gm_ev[slot]));
-  st = read_status(h->gm_host + 32 * slot);
+// ready = whether event e has completed; waits for it when block is set.
+int event_done(hipEvent_t e, bool block, bool& ready) {
+  if (block) {
+    GDC_HIP(hipEventSynchronize(e));
+    ready = true;
+    return GDC_OK;
+  }
+  const hipError_t q = hipEventQuery(e);
+  if (q == hipErrorNotReady) {
+    (void)hipGetLastError();   // "not ready" is an answer, not an error to carry
+    ready = false;
+    return GDC_OK;
+  }
+  if (q != hipSuccess) {
+    set_error(std::string("hipEventQuery: ") + hipGetErrorString(q));
+    return GDC_EDEVICE;
+  }
+  ready = true;
+  return GDC_OK;
+}
+
+int poll_status(gdc_handle* h, int slot, bool block, bool& ready, GmStatus& st) {
+  GDC_TRY(event_done(h->gm_ev[slot], block, ready));
+  if (ready) st = read_status(h->gm_host + 32 * slot);
   return GDC_OK;
 }
 
@@ -433,57 +502,124 @@ int wait_status(gdc_handle* h, int slot, GmStatus& st) {
 //
 // The Hessenberg bookkeeping runs on the device (in the last Arnoldi kernel,
 // which also writes the status to pinned host memory), so the host
-// queues iteration k + 1 before it waits for the status of iteration k: the
+// queues iteration k + 1 before it reads the status of iteration k: the
 // GPU never idles on the host.  When iteration k ends the cycle, the kernels
 // already queued for iteration k + 1 see the device flag and return at once.
+//
+// solve_begin queues the set-up; each solve_advance queues the next piece of
+// work or reads the next status (waiting for it when block is set, else
+// reporting ADV_BLOCKED while it is not there yet) and reports ADV_DONE once
+// h->sol is queued.
 template <typename R>
-int gmres(gdc_handle* h, const double* Y, const double* q, const double* r, GmresResult& res) {
+int solve_begin(gdc_handle* h, const double* Y, const double* q, const double* r) {
   const long long n = h->nx;
-  const int m = h->restart;
   hipStream_t s = h->stream;
-  const int* skip = &h->gm->done;
   GDC_TRY(multi_dot(nullptr, n, 0, h->rhs, n, true, h->partial, h->dot_counter, h->hdev, s));
   GDC_TRY(gm_init(h->gm, h->hdev, h->tol, h->maxit, s));
   GDC_TRY(fill_zero(h->xacc, (size_t)((n * 8 + 15) / 16 * 16), s));
-  bool first = true;
-  GmStatus st{};
-  while (true) {
-    double* V0 = h->Vb;
-    if (first) {
-      GDC_TRY(copy_scaled(h->rhs, 1.0, h->w, n, s));
-    } else {
-      // w = b - A P^-1 xacc
-      GDC_TRY(apply_saddle_precond<R>(h, Y, q, r, h->xacc, h->z, h->w));
-      GDC_TRY(sub_from(h->rhs, h->w, n, s));
+  h->sv = SolveRun{};
+  h->sv.Y = Y;
+  h->sv.q = q;
+  h->sv.r = r;
+  h->sv.phase = SolveRun::CYCLE;
+  return GDC_OK;
+}
+
+template <typename R>
+int solve_advance(gdc_handle* h, bool block, int& adv) {
+  SolveRun& sv = h->sv;
+  const long long n = h->nx;
+  const int m = h->restart;
+  hipStream_t s = h->stream;
+  adv = ADV_PROGRESS;
+  switch (sv.phase) {
+    case SolveRun::CYCLE: {
+      if (sv.first) {
+        GDC_TRY(copy_scaled(h->rhs, 1.0, h->w, n, s));
+      } else {
+        // w = b - A P^-1 xacc
+        GDC_TRY(apply_saddle_precond<R>(h, sv.Y, sv.q, sv.r, h->xacc, h->z, h->w));
+        GDC_TRY(sub_from(h->rhs, h->w, n, s));
+      }
+      sv.first = false;
+      GDC_TRY(multi_dot(nullptr, n, 0, h->w, n, true, h->partial, h->dot_counter, h->hdev + 2 * HCOLS, s));
+      GDC_TRY(gm_cycle(h->gm, h->hdev + 2 * HCOLS, s));
+      GDC_TRY(scale_by_inv_sqrt(h->w, h->hdev + 2 * HCOLS, h->Vb, n, s));
+      GDC_TRY(post_status(h, 0));
+      sv.k = 0;
+      sv.queued = false;
+      sv.phase = SolveRun::ITER;
+      return GDC_OK;
     }
-    first = false;
-    GDC_TRY(multi_dot(nullptr, n, 0, h->w, n, true, h->partial, h->dot_counter, h->hdev + 2 * HCOLS, s));
-    GDC_TRY(gm_cycle(h->gm, h->hdev + 2 * HCOLS, s));
-    GDC_TRY(scale_by_inv_sqrt(h->w, h->hdev + 2 * HCOLS, V0, n, s));
-    GDC_TRY(post_status(h, 0));
-    for (int k = 0; k < m; ++k) {
-      double* Vk = h->Vb + n * k;
-      double* Vk1 = h->Vb + n * (k + 1);
-      GDC_TRY(apply_saddle_precond<R>(h, Y, q, r, Vk, h->z, h->w, skip));
-      double* h1 = h->hdev;
-      double* h2 = h->hdev + HCOLS;
-      const int slot = (k + 1) & 1;
-      GDC_TRY(arnoldi_orthogonalise(h->w, h->Vb, n, k + 1, n, h->partial, h->partial2, Vk1, h1, h2, s, skip, h->gm,
-                                    m, h->gm_host_dev + 32 * slot));
-      GDC_HIP(hipEventRecord(h->gm_ev[slot], s));
+    case SolveRun::ITER: {
+      const int k = sv.k;
+      bool enq = false;
+      if (!sv.queued) {
+        double* Vk = h->Vb + n * k;
+        double* Vk1 = h->Vb + n * (k + 1);
+        GDC_TRY(apply_saddle_precond<R>(h, sv.Y, sv.q, sv.r, Vk, h->z, h->w, &h->gm->done));
+        const int slot = (k + 1) & 1;
+        GDC_TRY(arnoldi_orthogonalise(h->w, h->Vb, n, k + 1, n, h->partial, h->partial2, Vk1, h->hdev,
+                                      h->hdev + HCOLS, s, &h->gm->done, h->gm, m, h->gm_host_dev + 32 * slot));
+        GDC_HIP(hipEventRecord(h->gm_ev[slot], s));
+        sv.queued = enq = true;
+      }
       // status after iteration k - 1 (or after the cycle start)
-      GDC_TRY(wait_status(h, k & 1, st));
-      if (st.done) break;
+      bool ready = false;
+      GDC_TRY(poll_status(h, k & 1, block, ready, sv.st));
+      if (!ready) {
+        adv = enq ? ADV_PROGRESS : ADV_BLOCKED;
+        return GDC_OK;
+      }
+      if (sv.st.done || k + 1 >= m) {
+        sv.phase = SolveRun::FINISH;
+      } else {
+        sv.k = k + 1;
+        sv.queued = false;
+      }
+      return GDC_OK;
     }
-    GDC_TRY(gm_finish_cycle(h->gm, h->xacc, h->Vb, n, n, s));
-    GDC_TRY(post_status(h, 0));
-    GDC_TRY(wait_status(h, 0, st));
-    if (st.converged || st.its >= h->maxit) break;
+    case SolveRun::FINISH:
+      GDC_TRY(gm_finish_cycle(h->gm, h->xacc, h->Vb, n, n, s));
+      GDC_TRY(post_status(h, 0));
+      sv.phase = SolveRun::FINISH_WAIT;
+      return GDC_OK;
+    case SolveRun::FINISH_WAIT: {
+      bool ready = false;
+      GDC_TRY(poll_status(h, 0, block, ready, sv.st));
+      if (!ready) {
+        adv = ADV_BLOCKED;
+        return GDC_OK;
+      }
+      if (sv.st.converged || sv.st.its >= h->maxit) {
+        GDC_TRY(precond_apply(h->bt, sv.q, h->xacc, h->sol, nullptr, nullptr, nullptr, h->maxdim, s));
+        sv.res.its = sv.st.its;
+        sv.res.relres = sv.st.est;
+        sv.res.converged = sv.st.converged != 0;
+        sv.phase = SolveRun::DONE;
+        adv = ADV_DONE;
+      } else {
+        sv.phase = SolveRun::CYCLE;
+      }
+      return GDC_OK;
+    }
+    case SolveRun::DONE:
+      adv = ADV_DONE;
+      return GDC_OK;
+    default:
+      set_error("no solve in progress");
+      return GDC_EINVAL;
   }
-  GDC_TRY(precond_apply(h->bt, q, h->xacc, h->sol, nullptr, nullptr, nullptr, h->maxdim, s));
-  res.its = st.its;
-  res.relres = st.est;
-  res.converged = st.converged != 0;
+}
+
+// The whole solve, waiting for each status.
+template <typename R>
+int gmres(gdc_handle* h, const double* Y, const double* q, const double* r, GmresResult& res) {
+  GDC_TRY(solve_begin<R>(h, Y, q, r));
+  int adv = ADV_PROGRESS;
+  while (adv != ADV_DONE) GDC_TRY(solve_advance<R>(h, true, adv));
+  res = h->sv.res;
+  h->sv.phase = SolveRun::IDLE;
   return GDC_OK;
 }
 
@@ -520,35 +656,108 @@ int predictor_dev(gdc_handle* h, uint64_t step) {
   return nu_reduce(h->dp, h->N, 0.5 * h->cfg.dt, h->nu, s);
 }
 
+// One time step of the resident state (h->Y, h->q) as a resumable run:
+// IDLE queues the noise, steps 2-4, the forces and the right-hand side and
+// starts the solve; SOLVE advances it; once it is done the update (step 6)
+// and the readback of nu and the error flags are queued, and POST_WAIT
+// reports ADV_DONE when they have landed.
 template <typename R>
-int one_step(gdc_handle* h, GmresResult& gr, double& nu_out) {
+int step_advance(gdc_handle* h, bool block, int& adv) {
   hipStream_t s = h->stream;
-  const uint64_t step = h->step;
-  GDC_TRY(make_fluct<R>(h, step));
-  const double* Ym = h->Y;
-  const double* qm = h->q;
-  if (h->cfg.scheme == GDC_SCHEME_GDC) {
-    GDC_TRY(predictor_dev<R>(h, step));
-    GDC_TRY(midpoint(h->bt, h->Y, h->q, h->calV, 0.5 * h->cfg.dt, h->Ym, h->qm, s));
-    Ym = h->Ym;
-    qm = h->qm;
-  }
-  GDC_TRY(blob_positions(h->bt, Ym, qm, h->rm, s));
-  GDC_TRY(forces_at(h, Ym, h->rm));
-  GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_fl, h->v, h->M, h->geom.dV, nullptr, nullptr, nullptr, s));
-  GDC_TRY(prepare_positions(h, h->rm));
-  GDC_TRY(rhs_build(h->bt, qm, Ym, h->rm, h->v, h->F, h->cfg.forces.shear_rate, h->geom.L[1], h->rhs, s));
-  GDC_TRY(gmres<R>(h, Ym, qm, h->rm, gr));
+  StepRun& sr = h->sr;
   const bool gdc_scheme = h->cfg.scheme == GDC_SCHEME_GDC;
-  GDC_TRY(update(h->bt, h->Y, h->q, h->sol + 3LL * h->M, gdc_scheme ? h->nu : nullptr, h->cfg.dt, s));
-  if (gdc_scheme) {
-    GDC_HIP(hipMemcpyAsync(h->hhost + 4 * HCOLS, h->nu, sizeof(double), hipMemcpyDeviceToHost, s));
-    GDC_HIP(hipStreamSynchronize(s));
-    nu_out = h->hhost[4 * HCOLS];
-  } else {
-    nu_out = 1.0;
+  adv = ADV_PROGRESS;
+  switch (sr.phase) {
+    case StepRun::IDLE: {
+      const uint64_t step = h->step;
+      GDC_TRY(fill_zero(h->flags, 16, s));
+      GDC_TRY(make_fluct<R>(h, step));
+      const double* Ym = h->Y;
+      const double* qm = h->q;
+      if (gdc_scheme) {
+        GDC_TRY(predictor_dev<R>(h, step));
+        GDC_TRY(midpoint(h->bt, h->Y, h->q, h->calV, 0.5 * h->cfg.dt, h->Ym, h->qm, s));
+        Ym = h->Ym;
+        qm = h->qm;
+      }
+      GDC_TRY(blob_positions(h->bt, Ym, qm, h->rm, s));
+      GDC_TRY(forces_at(h, Ym, h->rm));
+      GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_fl, h->v, h->M, h->geom.dV, nullptr, nullptr, nullptr, s));
+      GDC_TRY(prepare_positions(h, h->rm));
+      GDC_TRY(rhs_build(h->bt, qm, Ym, h->rm, h->v, h->F, h->cfg.forces.shear_rate, h->geom.L[1], h->rhs, s));
+      GDC_TRY(solve_begin<R>(h, Ym, qm, h->rm));
+      sr.phase = StepRun::SOLVE;
+      return GDC_OK;
+    }
+    case StepRun::SOLVE: {
+      int a = ADV_PROGRESS;
+      GDC_TRY(solve_advance<R>(h, block, a));
+      if (a != ADV_DONE) {
+        adv = a;
+        return GDC_OK;
+      }
+      sr.gr = h->sv.res;
+      h->sv.phase = SolveRun::IDLE;
+      GDC_TRY(update(h->bt, h->Y, h->q, h->sol + 3LL * h->M, gdc_scheme ? h->nu : nullptr, h->cfg.dt,
+                     h->flags + 1, s));
+      GDC_HIP(hipMemcpyAsync(h->hhost + 4 * HCOLS, h->nu, sizeof(double), hipMemcpyDeviceToHost, s));
+      GDC_HIP(hipMemcpyAsync(h->hhost + 4 * HCOLS + 1, h->flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+      GDC_HIP(hipEventRecord(h->step_ev, s));
+      sr.phase = StepRun::POST_WAIT;
+      return GDC_OK;
+    }
+    case StepRun::POST_WAIT: {
+      bool ready = false;
+      GDC_TRY(event_done(h->step_ev, block, ready));
+      if (!ready) {
+        adv = ADV_BLOCKED;
+        return GDC_OK;
+      }
+      h->step_log.push_back(now_ms());
+      sr.nu = gdc_scheme ? h->hhost[4 * HCOLS] : 1.0;
+      const int* fl = reinterpret_cast<const int*>(h->hhost + 4 * HCOLS + 1);
+      if (fl[0]) ++h->n_overflow;
+      if (fl[1]) ++h->n_nonfinite;
+      if (!sr.gr.converged) ++h->n_notconv;
+      if (!(sr.nu > 0.0)) ++h->n_nonpos;
+      h->step += 1;
+      sr.phase = StepRun::IDLE;
+      adv = ADV_DONE;
+      return GDC_OK;
+    }
   }
-  h->step += 1;
+  set_error("corrupt step state");
+  return GDC_EINVAL;
+}
+
+int step_advance_any(gdc_handle* h, bool block, int& adv) {
+  return h->precision == GDC_FP64 ? step_advance<double>(h, block, adv) : step_advance<float>(h, block, adv);
+}
+
+// Return code for the errors counted since the last reset_errors.
+int step_errors(const gdc_handle* h) {
+  if (h->n_overflow) {
+    set_error("pair-force cell list overflow");
+    return GDC_ENUMERIC;
+  }
+  if (h->n_nonfinite) {
+    set_error("non-finite positions or orientations");
+    return GDC_ENUMERIC;
+  }
+  if (h->n_notconv) {
+    set_error("GMRES did not reach the tolerance in at least one step");
+    return GDC_ENOTCONV;
+  }
+  return GDC_OK;
+}
+
+void reset_errors(gdc_handle* h) { h->n_overflow = h->n_nonfinite = h->n_notconv = h->n_nonpos = 0; }
+
+int require_idle(const gdc_handle* h) {
+  if (h->sr.phase != StepRun::IDLE || h->sv.phase != SolveRun::IDLE) {
+    set_error("the handle has a step in flight: finish it with gdc_batch_step first");
+    return GDC_EINVAL;
+  }
   return GDC_OK;
 }
 
@@ -623,7 +832,10 @@ int init_grid_tables(gdc_handle* h) {
     }
     Cx<R>* dptr = nullptr;
     GDC_TRY(h->alloc(&dptr, n));
-    GDC_HIP(hipMemcpy(dptr, t.data(), n * sizeof(Cx<R>), hipMemcpyHostToDevice));
+    if (!h->dry) {
+      GDC_HIP(hipMemcpyAsync(dptr, t.data(), n * sizeof(Cx<R>), hipMemcpyHostToDevice, h->stream));
+      GDC_HIP(hipStreamSynchronize(h->stream));
+    }
     h->tw[d] = dptr;
   }
   // The three work fields are one allocation, so grid[1] and grid[2] together
@@ -716,26 +928,31 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
     }
   h->nx = 3LL * h->M + 6LL * h->N;
 
-  // device
-  int ndev = 0;
-  GDC_HIP(hipGetDeviceCount(&ndev));
-  if (c.device < 0 || c.device >= ndev) {
-    set_error("device ordinal out of range");
-    return GDC_EINVAL;
-  }
-  GDC_HIP(hipSetDevice(c.device));
-  if (c.stream) {
-    h->stream = (hipStream_t)c.stream;
-  } else {
-    GDC_HIP(hipStreamCreate(&h->stream));
-    h->own_stream = true;
+  // device (a footprint query touches none)
+  if (!h->dry) {
+    int ndev = 0;
+    GDC_HIP(hipGetDeviceCount(&ndev));
+    if (c.device < 0 || c.device >= ndev) {
+      set_error("device ordinal out of range");
+      return GDC_EINVAL;
+    }
+    GDC_HIP(hipSetDevice(c.device));
+    if (c.stream) {
+      h->stream = (hipStream_t)c.stream;
+    } else {
+      // non-blocking: work of other handles and the legacy stream does not
+      // serialise with this handle's
+      GDC_HIP(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+      h->own_stream = true;
+    }
   }
 
   auto upload = [&](auto** dst, const auto& vec) -> int {
     using T = typename std::remove_reference<decltype(vec)>::type::value_type;
     T* p = nullptr;
     GDC_TRY(h->alloc(&p, vec.size()));
-    GDC_HIP(hipMemcpy(p, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice));
+    if (!h->dry && !vec.empty())
+      GDC_HIP(hipMemcpyAsync(p, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
     *dst = p;
     return GDC_OK;
   };
@@ -789,7 +1006,7 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
   GDC_TRY(h->alloc(&h->io, std::max(6 * N, 3 * M)));
   std::vector<double> cf(c.forces.const_force, c.forces.const_force + 6);
   GDC_TRY(upload(&h->cforce, cf));
-  GDC_HIP(hipMemset(h->flags, 0, 4 * sizeof(int)));
+  if (!h->dry) GDC_HIP(hipMemsetAsync(h->flags, 0, 4 * sizeof(int), h->stream));
 
   const gdc_forces& f = c.forces;
   if (f.steric_k > 0.0 && f.steric_cutoff > 0.0) {
@@ -818,7 +1035,7 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
   GDC_TRY(h->alloc(&h->partial, std::max((size_t)DOT_MAX_BLOCKS, (size_t)(h->nx / 1024 + 1)) * HCOLS));
   GDC_TRY(h->alloc(&h->partial2, (size_t)(h->nx / 1024 + 1) * HCOLS));
   GDC_TRY(h->alloc(&h->dot_counter, 4));
-  GDC_HIP(hipMemset(h->dot_counter, 0, 4 * sizeof(unsigned int)));
+  if (!h->dry) GDC_HIP(hipMemsetAsync(h->dot_counter, 0, 4 * sizeof(unsigned int), h->stream));
   {
     TileGeom& t = h->tg;
     const int Tdef[3] = {8, 8, 32};
@@ -853,18 +1070,22 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
     GDC_TRY(h->alloc(&h->tab_count, (size_t)t.ntiles));
     GDC_TRY(h->alloc(&h->tab_claimed, 4));
   }
-  GDC_HIP(hipHostMalloc((void**)&h->hhost, 5 * HCOLS * sizeof(double), hipHostMallocDefault));
   GDC_TRY(h->alloc(&h->gm, 1));
-  GDC_HIP(hipHostMalloc((void**)&h->gm_host, 64, hipHostMallocMapped | hipHostMallocCoherent));
-  GDC_HIP(hipHostGetDevicePointer((void**)&h->gm_host_dev, h->gm_host, 0));
-  for (hipEvent_t& e : h->gm_ev) GDC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  if (!h->dry) {
+    GDC_HIP(hipHostMalloc((void**)&h->hhost, 5 * HCOLS * sizeof(double), hipHostMallocDefault));
+    GDC_HIP(hipHostMalloc((void**)&h->gm_host, 64, hipHostMallocMapped | hipHostMallocCoherent));
+    GDC_HIP(hipHostGetDevicePointer((void**)&h->gm_host_dev, h->gm_host, 0));
+    for (hipEvent_t& e : h->gm_ev) GDC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    GDC_HIP(hipEventCreateWithFlags(&h->step_ev, hipEventDisableTiming));
+  }
 
   if (h->precision == GDC_FP64) {
     GDC_TRY(init_grid_tables<double>(h));
   } else {
     GDC_TRY(init_grid_tables<float>(h));
   }
-  GDC_HIP(hipDeviceSynchronize());
+  // the host vectors of the uploads above go out of scope on return
+  if (!h->dry) GDC_HIP(hipStreamSynchronize(h->stream));
   return GDC_OK;
 }
 
@@ -917,6 +1138,7 @@ int gdc_mobility_apply(gdc_handle* h, int mode, const double* Y, const double* q
   }
   DeviceGuard dg(h->device);
   hipStream_t s = h->stream;
+  GDC_TRY(require_idle(h));
   GDC_TRY(load_state(h, Y, q, memspace));
   GDC_TRY(blob_positions(h->bt, h->Y, h->q, h->r, s));
   GDC_TRY(fill_zero(h->flags, 16, s));
@@ -964,51 +1186,205 @@ int gdc_step(gdc_handle* h, int n_steps, double* Y, double* q, int memspace, gdc
     return GDC_EINVAL;
   }
   DeviceGuard dg(h->device);
+  GDC_TRY(require_idle(h));
   const auto t0 = std::chrono::steady_clock::now();
-  hipStream_t s = h->stream;
   GDC_TRY(load_state(h, Y, q, memspace));
-  GDC_TRY(fill_zero(h->flags, 16, s));
-  GmresResult gr;
-  double nu = 1.0;
-  int nonpos = 0;
-  bool notconv = false;
+  h->has_state = true;
+  reset_errors(h);
   for (int k = 0; k < n_steps; ++k) {
-    if (h->precision == GDC_FP64) {
-      GDC_TRY(one_step<double>(h, gr, nu));
-    } else {
-      GDC_TRY(one_step<float>(h, gr, nu));
-    }
-    if (!gr.converged) notconv = true;
-    if (!(nu > 0.0)) ++nonpos;
+    int adv = ADV_PROGRESS;
+    while (adv != ADV_DONE) GDC_TRY(step_advance_any(h, true, adv));
   }
-  GDC_TRY(check_finite(h->Y, 3LL * h->N, h->flags + 1, s));
-  GDC_TRY(check_finite(h->q, 4LL * h->N, h->flags + 1, s));
   GDC_TRY(copy_out(h, Y, h->Y, 3 * (size_t)h->N, memspace));
   GDC_TRY(copy_out(h, q, h->q, 4 * (size_t)h->N, memspace));
-  GDC_HIP(hipMemcpyAsync(h->hhost, h->flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
   GDC_TRY(finish(h));
-  const int* fl = reinterpret_cast<const int*>(h->hhost);
-  const bool overflow = fl[0] != 0, nonfinite = fl[1] != 0;
   if (st) {
     st->steps_done = n_steps;
-    st->gmres_iterations = gr.its;
-    st->gmres_relres = gr.relres;
-    st->nu = nu;
-    st->nu_nonpositive = nonpos;
+    st->gmres_iterations = h->sr.gr.its;
+    st->gmres_relres = h->sr.gr.relres;
+    st->nu = h->sr.nu;
+    st->nu_nonpositive = h->n_nonpos;
     st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
-  if (overflow) {
-    set_error("pair-force cell list overflow");
-    return GDC_ENUMERIC;
+  return step_errors(h);
+}
+
+int gdc_set_state(gdc_handle* h, const double* Y, const double* q, int memspace) {
+  if (!h) {
+    set_error("handle is required");
+    return GDC_EINVAL;
   }
-  if (nonfinite) {
-    set_error("non-finite positions or orientations");
-    return GDC_ENUMERIC;
+  DeviceGuard dg(h->device);
+  GDC_TRY(require_idle(h));
+  GDC_TRY(load_state(h, Y, q, memspace));
+  GDC_TRY(finish(h));
+  h->has_state = true;
+  h->step_log.clear();
+  h->step_log.push_back(now_ms());
+  return GDC_OK;
+}
+
+int gdc_get_state(gdc_handle* h, double* Y, double* q, int memspace) {
+  if (!h || !Y || !q || (memspace != GDC_HOST && memspace != GDC_DEVICE)) {
+    set_error("handle, Y, q and a valid memspace are required");
+    return GDC_EINVAL;
   }
-  if (notconv) {
-    set_error("GMRES did not reach the tolerance in at least one step");
-    return GDC_ENOTCONV;
+  DeviceGuard dg(h->device);
+  GDC_TRY(require_idle(h));
+  if (!h->has_state) {
+    set_error("the handle holds no state: call gdc_set_state or gdc_step first");
+    return GDC_EINVAL;
   }
+  GDC_TRY(copy_out(h, Y, h->Y, 3 * (size_t)h->N, memspace));
+  GDC_TRY(copy_out(h, q, h->q, 4 * (size_t)h->N, memspace));
+  return finish(h);
+}
+
+int gdc_batch_step(gdc_handle* const* hs, int nh, int* steps, int until, double max_ms, gdc_stats* st) {
+  if (nh < 0 || (nh > 0 && (!hs || !steps)) || (until != GDC_UNTIL_ALL && until != GDC_UNTIL_ANY) ||
+      !(max_ms >= 0.0)) {
+    set_error("gdc_batch_step: bad arguments");
+    return GDC_EINVAL;
+  }
+  for (int i = 0; i < nh; ++i) {
+    if (!hs[i] || steps[i] < 0) {
+      set_error("gdc_batch_step: handle " + std::to_string(i) + " is NULL or has a negative step count");
+      return GDC_EINVAL;
+    }
+    if (!hs[i]->has_state) {
+      set_error("gdc_batch_step: handle " + std::to_string(i) + " holds no state (gdc_set_state)");
+      return GDC_EINVAL;
+    }
+    if (steps[i] == 0 && hs[i]->sr.phase != StepRun::IDLE) {
+      set_error("gdc_batch_step: handle " + std::to_string(i) + " has a step in flight but no steps left");
+      return GDC_EINVAL;
+    }
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) {
+        set_error("gdc_batch_step: a handle appears twice");
+        return GDC_EINVAL;
+      }
+  }
+  int prev_dev = -1;
+  if (hipGetDevice(&prev_dev) != hipSuccess) prev_dev = -1;
+  const double t0 = now_ms();
+  std::vector<int> watched(nh, 0), done_here(nh, 0);
+  std::vector<double> t_last(nh, 0.0);
+  bool any_watched = false;
+  for (int i = 0; i < nh; ++i) {
+    watched[i] = steps[i] > 0;
+    any_watched = any_watched || watched[i];
+    reset_errors(hs[i]);
+  }
+  int rc = GDC_OK;
+  int cur_dev = -1;
+  while (any_watched) {
+    bool progressed = false;
+    for (int i = 0; i < nh && rc == GDC_OK; ++i) {
+      gdc_handle* h = hs[i];
+      if (steps[i] == 0) continue;
+      if (h->device != cur_dev) {
+        if (hipSetDevice(h->device) != hipSuccess) {
+          set_error("hipSetDevice failed");
+          rc = GDC_EDEVICE;
+          break;
+        }
+        cur_dev = h->device;
+      }
+      // queue all the work this handle can take before it must wait
+      while (steps[i] > 0) {
+        int adv = ADV_BLOCKED;
+        const int r = step_advance_any(h, false, adv);
+        if (r != GDC_OK) {
+          set_error("gdc_batch_step: handle " + std::to_string(i) + ": " + gdc_last_error());
+          rc = r;
+          break;
+        }
+        if (adv == ADV_BLOCKED) break;
+        progressed = true;
+        if (adv == ADV_DONE) {
+          --steps[i];
+          ++done_here[i];
+          t_last[i] = h->step_log.back() - t0;
+        }
+      }
+    }
+    if (rc != GDC_OK) break;
+    bool all_zero = true, any_hit = false;
+    for (int i = 0; i < nh; ++i) {
+      all_zero = all_zero && steps[i] == 0;
+      any_hit = any_hit || (watched[i] && steps[i] == 0);
+    }
+    if (all_zero || (until == GDC_UNTIL_ANY && any_hit)) break;
+    if (max_ms > 0.0 && now_ms() - t0 >= max_ms) break;
+    if (!progressed) std::this_thread::yield();
+  }
+  if (prev_dev >= 0) (void)hipSetDevice(prev_dev);
+  int first_err = GDC_OK;
+  for (int i = 0; i < nh; ++i) {
+    gdc_handle* h = hs[i];
+    if (st) {
+      st[i].steps_done = done_here[i];
+      st[i].gmres_iterations = h->sr.gr.its;
+      st[i].gmres_relres = h->sr.gr.relres;
+      st[i].nu = h->sr.nu;
+      st[i].nu_nonpositive = h->n_nonpos;
+      st[i].ms = t_last[i];
+    }
+    if (rc == GDC_OK && first_err == GDC_OK) {
+      const int e = step_errors(h);
+      if (e != GDC_OK) {
+        set_error("handle " + std::to_string(i) + ": " + gdc_last_error());
+        first_err = e;
+      }
+    }
+  }
+  return rc != GDC_OK ? rc : first_err;
+}
+
+int gdc_step_log(gdc_handle* h, double* t_ms, int cap, int* count) {
+  if (!h || !count || cap < 0 || (cap > 0 && !t_ms)) {
+    set_error("handle, count and a buffer of cap entries are required");
+    return GDC_EINVAL;
+  }
+  const int n = (int)std::min<size_t>((size_t)cap, h->step_log.size());
+  if (n > 0) std::memcpy(t_ms, h->step_log.data(), n * sizeof(double));
+  *count = n;
+  // the last entry stays: the next step's latency is measured from it
+  if (!h->step_log.empty()) {
+    const double last = h->step_log.back();
+    if ((size_t)n == h->step_log.size()) {
+      h->step_log.assign(1, last);
+    } else {
+      h->step_log.erase(h->step_log.begin(), h->step_log.begin() + n);
+    }
+  }
+  return GDC_OK;
+}
+
+int gdc_footprint(const gdc_config* cfg, size_t* bytes) {
+  if (!bytes) {
+    set_error("bytes is NULL");
+    return GDC_EINVAL;
+  }
+  *bytes = 0;
+  std::unique_ptr<gdc_handle> h(new (std::nothrow) gdc_handle());
+  if (!h) {
+    set_error("host allocation failed");
+    return GDC_ENOMEM;
+  }
+  h->dry = true;
+  GDC_TRY(init_impl(cfg, h.get()));
+  *bytes = h->dev_bytes;
+  return GDC_OK;
+}
+
+int gdc_device_bytes(const gdc_handle* h, size_t* bytes) {
+  if (!h || !bytes) {
+    set_error("handle and bytes are required");
+    return GDC_EINVAL;
+  }
+  *bytes = h->dev_bytes;
   return GDC_OK;
 }
 
@@ -1056,6 +1432,7 @@ int gdc_set_step(gdc_handle* h, uint64_t step) {
     set_error("handle is required");
     return GDC_EINVAL;
   }
+  GDC_TRY(require_idle(h));
   h->step = step;
   return GDC_OK;
 }
@@ -1066,6 +1443,7 @@ int gdc_fluct_velocity(gdc_handle* h, uint64_t step, double* u, int memspace) {
     return GDC_EINVAL;
   }
   DeviceGuard dg(h->device);
+  GDC_TRY(require_idle(h));
   const size_t n = 3 * (size_t)h->geom.G;
   if (h->precision == GDC_FP64) {
     GDC_TRY(make_fluct<double>(h, step));
@@ -1087,6 +1465,7 @@ int gdc_predictor(gdc_handle* h, const double* Y, const double* q, uint64_t step
     return GDC_EINVAL;
   }
   DeviceGuard dg(h->device);
+  GDC_TRY(require_idle(h));
   GDC_TRY(load_state(h, Y, q, memspace));
   if (h->precision == GDC_FP64) {
     GDC_TRY(make_fluct<double>(h, step));

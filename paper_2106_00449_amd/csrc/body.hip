@@ -304,7 +304,7 @@ __global__ void k_midpoint(int N, const double* __restrict__ Y, const double* __
 
 // Step 6: Y += nu dt V_U, q = exp(nu dt V_Omega) . q (nu on the device).
 __global__ void k_update(int N, double* __restrict__ Y, double* __restrict__ q, const double* __restrict__ V,
-                         const double* __restrict__ nu, double dt) {
+                         const double* __restrict__ nu, double dt, int* __restrict__ nonfinite) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= N) return;
   const double h = (nu ? nu[0] : 1.0) * dt;
@@ -319,6 +319,11 @@ __global__ void k_update(int N, double* __restrict__ Y, double* __restrict__ q, 
   q[4LL * p + 1] = qn[1];
   q[4LL * p + 2] = qn[2];
   q[4LL * p + 3] = qn[3];
+  if (nonfinite) {
+    bool ok = isfinite(qn[0]) && isfinite(qn[1]) && isfinite(qn[2]) && isfinite(qn[3]);
+    for (int c = 0; c < 3; ++c) ok = ok && isfinite(Y[3LL * p + c]);
+    if (!ok) atomicMax(nonfinite, 1);
+  }
 }
 
 // Right-hand side [-(v_slip + u_inf); -(I - Pi) F] of the saddle problem.
@@ -494,8 +499,9 @@ int midpoint(const BodyTables& b, const double* Y, const double* q, const double
   return check_launch("k_midpoint");
 }
 
-int update(const BodyTables& b, double* Y, double* q, const double* V, const double* nu, double dt, hipStream_t s) {
-  hipLaunchKernelGGL(k_update, dim3(nblk(b.N)), dim3(NT), 0, s, b.N, Y, q, V, nu, dt);
+int update(const BodyTables& b, double* Y, double* q, const double* V, const double* nu, double dt, int* nonfinite,
+           hipStream_t s) {
+  hipLaunchKernelGGL(k_update, dim3(nblk(b.N)), dim3(NT), 0, s, b.N, Y, q, V, nu, dt, nonfinite);
   return check_launch("k_update");
 }
 

@@ -237,8 +237,9 @@ int body_lsq_div(const BodyTables& b, const double* q, const double* v, const do
 int nu_reduce(const double* d, int N, double half_dt, double* nu, hipStream_t s);
 int midpoint(const BodyTables& b, const double* Y, const double* q, const double* calV,
              double h, double* Ym, double* qm, hipStream_t s);
+// Step 6; sets *nonfinite (when given) if a new position or quaternion is not finite.
 int update(const BodyTables& b, double* Y, double* q, const double* V, const double* nu,
-           double dt, hipStream_t s);
+           double dt, int* nonfinite, hipStream_t s);
 int rhs_build(const BodyTables& b, const double* q, const double* Y, const double* r,
               const double* vslip, const double* F, double shear, double Ly, double* rhs,
               hipStream_t s);

@@ -1,0 +1,145 @@
+"""Batched stepping and serving on the GPU, through the C ABI.
+
+gdc_batch_step advances several resident suspensions with overlapped work;
+each suspension must end where gdc_step takes it alone (same kernels, same
+order, same Philox noise: the results are compared exactly where no
+pair-force cell list is built, and to the FP32 step tolerance 1e-5 of the
+increment otherwise).  The served run must give each request the result it
+gets alone.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from tests._common import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2106_00449_amd as g
+    return g
+
+
+def _mix():
+    return [
+        wl.small_case("b_rods", n_bodies=12, n=32, L=24.0, shapes=[wl.rod(5)], precision="fp32", seed=21,
+                      dt=0.005),
+        wl.small_case("b_mixed", n_bodies=9, n=(24, 32, 48), L=(20.0, 24.0, 36.0),
+                      shapes=[wl.rod(4), wl.boomerang(), wl.tetrahedron()], precision="fp32", seed=22,
+                      dt=0.005, const_force=(0.0, 0.0, 1.0, 0.0, 0.0, 0.0)),
+        wl.small_case("b_fp64", n_bodies=6, n=24, L=20.0, shapes=[wl.rod(3)], precision="fp64", seed=23,
+                      dt=0.005),
+        wl.small_case("b_steric", n_bodies=16, n=48, L=32.0, shapes=[wl.rod(5)], precision="fp32", seed=24,
+                      dt=0.005, steric_k=40.0 / 2.2, steric_cutoff=2.2),
+    ]
+
+
+def _alone(lib, w, n_steps):
+    Y, q = wl.initial_state(w)
+    Y0 = Y.copy()
+    s = lib.Suspension(**wl.library_kwargs(w, gmres_tol=1e-6))
+    s.step(Y, q, n_steps)
+    s.close()
+    return Y0, Y, q
+
+
+def _close(a, b, Y0, exact):
+    if exact:
+        return np.array_equal(a, b)
+    return rel_l2(a - Y0, b - Y0) < 1e-5
+
+
+def test_footprint_matches_allocation(lib):
+    for w in _mix():
+        kw = wl.library_kwargs(w)
+        s = lib.Suspension(**kw)
+        assert s.device_bytes == lib.footprint(**kw)
+        s.close()
+
+
+@pytest.mark.parametrize("until", ["all", "any"])
+def test_batch_step_equals_each_alone(lib, until):
+    ws = _mix()
+    n_steps = [3, 2, 4, 3]
+    ref = [_alone(lib, w, k) for w, k in zip(ws, n_steps)]
+    _say("batch", until)
+    ss = []
+    for w in ws:
+        s = lib.Suspension(**wl.library_kwargs(w, gmres_tol=1e-6))
+        Y, q = wl.initial_state(w)
+        s.set_state(Y, q)
+        ss.append(s)
+    left = list(n_steps)
+    calls = 0
+    while any(left):
+        left, stats, rc = lib.batch_step(ss, left, until=until)
+        assert rc == 0
+        calls += 1
+        assert calls <= sum(n_steps)
+    for s, w, (Y0, Yr, qr), k in zip(ss, ws, ref, n_steps):
+        Y, q = s.get_state()
+        exact = w.steric_k == 0.0
+        assert _close(Y, Yr, Y0, exact), w.name
+        assert _close(q, qr, 0.0 * qr, exact), w.name
+        assert s.step_counter == k
+        log = s.step_log()
+        assert len(log) == k + 1 and np.all(np.diff(log) > 0)
+        s.close()
+
+
+def test_batch_step_resumes_a_step_left_in_flight(lib):
+    ws = _mix()[:3]
+    ref = [_alone(lib, w, 2) for w in ws]
+    _say("resume")
+    ss = []
+    for w in ws:
+        s = lib.Suspension(**wl.library_kwargs(w, gmres_tol=1e-6))
+        s.set_state(*wl.initial_state(w))
+        ss.append(s)
+    # a wall-clock limit far below one step returns with steps in flight
+    left, _, rc = lib.batch_step(ss, [2, 2, 2], until="all", max_ms=0.001)
+    assert rc == 0
+    with pytest.raises(lib.GdcError):
+        ss[0].get_state()
+    while any(left):
+        left, _, rc = lib.batch_step(ss, left, until="all")
+        assert rc == 0
+    for s, (Y0, Yr, qr) in zip(ss, ref):
+        Y, q = s.get_state()
+        assert np.array_equal(Y, Yr) and np.array_equal(q, qr)
+        s.close()
+
+
+def test_served_results_equal_alone(lib):
+    from paper_2106_00449_amd.serving import Request, Server, summarise
+    ws = _mix()
+    n_steps = [6, 4, 5, 6]
+    reqs = []
+    for i, (w, k) in enumerate(zip(ws, n_steps)):
+        Y, q = wl.initial_state(w)
+        reqs.append(Request(i, wl.library_kwargs(w, gmres_tol=1e-6), Y, q, k, arrival=0.002 * i, blobs=w.M))
+    _say("serve mix")
+    # a budget that holds three of the four at once, so admission binds
+    fps = sorted(lib.footprint(**r.kwargs) for r in reqs)
+    srv = Server(hbm_budget=sum(fps[1:]), max_slots=8)
+    res = srv.run(reqs)
+    summ = summarise(res)
+    assert summ["completed"] == 4, summ
+    assert srv.peak_bytes <= srv.budget
+    for r, w in zip(reqs, ws):
+        Y0, Yr, qr = _alone(lib, w, r.n_steps)
+        out = res[r.rid]
+        exact = w.steric_k == 0.0
+        assert _close(out.Y, Yr, Y0, exact), w.name
+        assert _close(out.q, qr, 0.0 * qr, exact), w.name
+        assert len(out.step_times) == r.n_steps + 1
+    assert summ["step_latency_p99_ms"] >= summ["step_latency_p50_ms"] > 0

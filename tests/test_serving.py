@@ -1,0 +1,125 @@
+"""Host logic of the continuous-batching server (no GPU): admission by
+footprint and slots, FIFO order, rejection of oversize requests, admission of
+arrivals while other suspensions are in flight, and the latency bookkeeping.
+A simulated executor stands in for the library: each suspension's step takes
+a fixed simulated time, and suspensions in flight run concurrently."""
+import numpy as np
+
+from paper_2106_00449_amd.serving import Request, Server, summarise
+
+
+class SimClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 0.0)
+
+
+class SimExecutor:
+    """Suspension state = Y0 + (steps taken); step time per suspension =
+    kwargs["step_s"]; footprint = kwargs["bytes"]."""
+
+    def __init__(self, clock):
+        self.clock = clock
+        self.calls = []
+        self.live = set()
+
+    def footprint(self, req):
+        return req.kwargs["bytes"]
+
+    def open(self, req):
+        h = {"req": req, "done": 0, "next": self.clock() + req.kwargs["step_s"], "log": [self.clock() * 1e3]}
+        self.live.add(id(h))
+        return h
+
+    def step(self, handles, steps, until, max_ms):
+        assert until == "any"
+        self.calls.append(len(handles))
+        left = list(steps)
+        deadline = self.clock() + max_ms / 1e3 if max_ms > 0 else float("inf")
+        while True:
+            i = min(range(len(handles)), key=lambda k: handles[k]["next"] if left[k] > 0 else float("inf"))
+            t_next = handles[i]["next"]
+            if t_next > deadline:
+                self.clock.t = deadline
+                return left, 0
+            self.clock.t = t_next
+            h = handles[i]
+            h["done"] += 1
+            h["log"].append(t_next * 1e3)
+            left[i] -= 1
+            h["next"] = t_next + h["req"].kwargs["step_s"]
+            if left[i] == 0:
+                return left, 0
+
+    def close(self, h):
+        self.live.discard(id(h))
+        r = h["req"]
+        return r.Y0 + h["done"], r.q0.copy(), h["log"]
+
+
+def _req(rid, arrival, n_steps, step_s, nbytes):
+    return Request(rid, {"step_s": step_s, "bytes": nbytes}, np.full((2, 3), float(rid)),
+                   np.tile([1.0, 0, 0, 0], (2, 1)), n_steps, arrival, blobs=20)
+
+
+def _serve(reqs, budget, slots):
+    clk = SimClock()
+    ex = SimExecutor(clk)
+    srv = Server(hbm_budget=budget, max_slots=slots, executor=ex, clock=clk, sleep=clk.sleep)
+    return srv, ex, srv.run(reqs)
+
+
+def test_every_request_completes_with_its_own_result():
+    reqs = [_req(i, 0.01 * i, 5 + i % 3, 0.001 * (1 + i % 4), 100) for i in range(20)]
+    srv, ex, res = _serve(reqs, budget=1000, slots=4)
+    assert len(res) == 20 and not ex.live
+    for r in reqs:
+        out = res[r.rid]
+        assert not out.error
+        assert np.array_equal(out.Y, r.Y0 + r.n_steps)
+        assert len(out.step_times) == r.n_steps + 1
+        assert np.all(out.latencies > 0)
+        assert out.admitted >= r.arrival and out.finished >= out.admitted
+
+
+def test_budget_and_slots_bind():
+    reqs = [_req(i, 0.0, 4, 0.002, 300) for i in range(10)]
+    srv, _, res = _serve(reqs, budget=1000, slots=8)
+    assert srv.peak_bytes <= 1000 and srv.peak_slots == 3   # 3 x 300 fit, 4 do not
+    srv, _, res = _serve(reqs, budget=10_000, slots=2)
+    assert srv.peak_slots == 2
+
+
+def test_fifo_admission_and_oversize_rejection():
+    reqs = [_req(0, 0.0, 3, 0.001, 600), _req(1, 0.0001, 3, 0.001, 5000), _req(2, 0.0002, 3, 0.001, 600),
+            _req(3, 0.0003, 3, 0.001, 300)]
+    _, _, res = _serve(reqs, budget=1000, slots=8)
+    assert res[1].error and not res[0].error and not res[2].error
+    # request 3 fits beside 0 but must not overtake 2, which does not
+    assert res[3].admitted >= res[2].admitted
+    order = sorted([r for r in res.values() if not r.error], key=lambda r: r.arrival)
+    assert all(a.admitted <= b.admitted for a, b in zip(order, order[1:]))
+
+
+def test_arrivals_are_admitted_while_others_run():
+    # a long suspension is in flight when a short one arrives: the short one
+    # must be admitted at its arrival and finish long before the long one
+    reqs = [_req(0, 0.0, 100, 0.01, 100), _req(1, 0.05, 5, 0.001, 100)]
+    _, ex, res = _serve(reqs, budget=1000, slots=4)
+    assert abs(res[1].admitted - 0.05) < 1e-9
+    assert res[1].finished < res[0].finished
+    assert max(ex.calls) == 2
+
+
+def test_summary_figures():
+    reqs = [_req(i, 0.0, 4, 0.001, 100) for i in range(4)]
+    _, _, res = _serve(reqs, budget=1000, slots=4)
+    s = summarise(res)
+    assert s["completed"] == 4 and s["rejected"] == 0
+    assert abs(s["step_latency_p50_ms"] - 1.0) < 1e-9
+    assert abs(s["blob_steps_per_s"] - 4 * 20 * 4 / 0.004) < 1e-6
