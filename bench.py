@@ -12,7 +12,20 @@ solve stays within 1e-5 (relative L2) of the library's FP64 solve (itself
 parity-tested against the FP64 oracle), on the first state with a probe force
 F ~ N(0,1) per body.
 
+Beside the headline figure the JSON line carries:
+  roofline      the dominant kernel (Gaussian spreading) against HBM peak;
+  kernels       achieved bandwidth of spreading, averaging and each FFT pass;
+  fp64_single   the same suspension on the plain FP64 path;
+  serving       256 independent suspensions (N log-uniform in [8, 2048] rods,
+                grids 32^3..128^3, 50 steps each) served with continuous
+                batching: saturation throughput (all requests queued at
+                once), a Poisson stream at that rate with p50/p99 step
+                latency, and the same requests stepped one at a time on the
+                plain FP64 and FP32 paths (a sample of 16);
+  cpu_baseline  the FP64 oracle on one step of the headline suspension.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--no-serving] [--serving-requests R]
 """
 import argparse
 import json
@@ -41,6 +54,13 @@ BYTES_PER_BLOB = 56
 # for the current kernel.
 TRAFFIC_BYTES = None
 
+SERVING_BUDGET = 8 << 30
+SERVING_SLOTS = 16
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
 
 def calibrate(g, wl, w, Y0, q0, target=1e-5):
     import numpy as np
@@ -63,6 +83,20 @@ def calibrate(g, wl, w, Y0, q0, target=1e-5):
     return chosen
 
 
+def mobility_error(g, wl, w, Y0, q0, tol, precision="fp32"):
+    """Relative L2 error of the body mobility at GMRES tolerance tol against
+    the library's FP64 solve at 1e-12."""
+    import numpy as np
+    F = np.random.default_rng(1234).standard_normal((w.N, 6))
+    ref = g.Suspension(**wl.library_kwargs(w, precision="fp64", gmres_tol=1e-12, gmres_maxit=1000))
+    Vref = ref.mobility_apply("body", Y0, q0, F)
+    ref.close()
+    s = g.Suspension(**wl.library_kwargs(w, precision=precision, gmres_tol=tol, gmres_maxit=500))
+    V = s.mobility_apply("body", Y0, q0, F, allow_notconv=True)
+    s.close()
+    return float(np.linalg.norm(V - Vref) / np.linalg.norm(Vref))
+
+
 def cpu_baseline(w, Y0, q0, tol):
     """The FP64 oracle, as it stands, on one step of the same workload."""
     import numpy as np
@@ -81,12 +115,153 @@ def cpu_baseline(w, Y0, q0, tol):
                       f"GMRES tol {tol:g}, {dt:.1f} s"}
 
 
+def grid_coverage(w, Y, q):
+    """Fraction of grid points within the envelope cutoff of some blob (the
+    part of the field an averaging pass must read)."""
+    import numpy as np
+    from workloads import _rodrigues_many
+    n = np.asarray(w.n)
+    L = np.asarray(w.L)
+    dx = L / n
+    ang = 2.0 * np.arccos(np.clip(q[:, 0], -1.0, 1.0))
+    s = np.sin(ang / 2)
+    axis = np.where(s[:, None] > 1e-15, q[:, 1:] / np.where(s[:, None] > 1e-15, s[:, None], 1.0),
+                    np.array([0.0, 0.0, 1.0]))
+    r = np.concatenate([Y[p] + _rodrigues_many(axis[p:p + 1], ang[p:p + 1],
+                                               np.asarray(w.shapes[w.body_shape[p]]))[0]
+                        for p in range(w.N)])
+    mark = np.zeros(tuple(n), bool)
+    P = np.ceil(w.rc / dx).astype(int)
+    offs = np.stack(np.meshgrid(*[np.arange(-P[d], P[d] + 1) for d in range(3)], indexing="ij"), -1).reshape(-1, 3)
+    base = np.floor(r / dx).astype(np.int64)
+    for k in range(0, len(r), 2000):
+        g = base[k:k + 2000, None, :] + offs[None, :, :]
+        d = g * dx - r[k:k + 2000, None, :]
+        inside = (d * d).sum(-1) <= w.rc * w.rc
+        gi = np.mod(g[inside], n)
+        mark[gi[:, 0], gi[:, 1], gi[:, 2]] = True
+    return float(mark.mean())
+
+
+def timed_steps(g, s, Y, q, steps, warmup):
+    import numpy as np
+    import torch
+    for _ in range(warmup):
+        s.step(Y, q, 1)
+    torch.cuda.synchronize()
+    lat, its, nus = [], [], []
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        st = s.step(Y, q, 1)
+        lat.append(time.perf_counter() - t0)
+        its.append(st["gmres_iterations"])
+        nus.append(st["nu"])
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    return total, np.array(lat) * 1e3, its, nus
+
+
+def kernel_bandwidth(g, s, Y, q, w, cov):
+    """Average duration and achieved algorithmic bandwidth of each grid
+    kernel family over 4 steps (HIP events on the launch stream)."""
+    G = int(w.G)
+    fams = {
+        "spread": ("k_spread_tab", BYTES_PER_POINT * G + BYTES_PER_BLOB * w.M),
+        "interp": ("k_interp", int(12 * cov * G) + 48 * w.M),
+        "fft_plane_fwd": ("k_plane_fwd", 24 * G),
+        "fft_project": ("k_axis0_plane", 24 * G),
+        "fft_plane_inv": ("k_plane_inv", 24 * G),
+    }
+    out = {}
+    for fam, (kname, nbytes) in fams.items():
+        g.probe_kernel(fam)
+        for _ in range(4):
+            s.step(Y, q, 1)
+        ms, n = g.probe_read()
+        g.probe_kernel(None)
+        if n == 0:
+            continue
+        avg = ms * 1e-3 / n
+        gbs = nbytes / avg / 1e9
+        out[fam] = {"kernel": kname, "launches": n, "avg_us": avg * 1e6, "algorithmic_bytes": nbytes,
+                    "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+    return out
+
+
+def serving_bench(g, wl, reqs, states, tol, budget, slots):
+    import numpy as np
+    from paper_2106_00449_amd.serving import Request, Server, summarise
+
+    def requests(rate):
+        out = []
+        for i, (w, (Y, q)) in enumerate(zip(reqs, states)):
+            arr = w.extra["arrival"] / rate if rate else 0.0
+            out.append(Request(i, wl.library_kwargs(w, gmres_tol=tol, gmres_maxit=500), Y, q, w.steps, arr,
+                               blobs=w.M))
+        return out
+
+    # the tolerance checked on the smallest and the largest request
+    order = np.argsort([w.M for w in reqs])
+    errs = [mobility_error(g, wl, reqs[i], *states[i], tol) for i in (order[0], order[-1])]
+
+    progress("serving: saturation run")
+    srv = Server(hbm_budget=budget, max_slots=slots)
+    t0 = time.perf_counter()
+    res = srv.run(requests(None))
+    sat = summarise(res, makespan=time.perf_counter() - t0)
+    sat.update(peak_bytes=srv.peak_bytes, peak_slots=srv.peak_slots)
+    rate = len(reqs) / sat["makespan_s"]
+    progress(f"serving: Poisson run at {rate:.1f} requests/s")
+    srv = Server(hbm_budget=budget, max_slots=slots)
+    res = srv.run(requests(rate))
+    poisson = summarise(res)
+    poisson.update(arrival_rate_per_s=rate, peak_bytes=srv.peak_bytes, peak_slots=srv.peak_slots)
+
+    # one at a time on the plain paths, same requests (a sample)
+    sample = order[:: max(1, len(order) // 16)][:16]
+    seq = {}
+    for prec in ["fp64", "fp32"]:
+        progress(f"serving: sequential {prec} sample")
+        blob_steps, t_tot, lat = 0, 0.0, []
+        for i in sample:
+            w = reqs[i]
+            Y, q = (x.copy() for x in states[i])
+            s = g.Suspension(**wl.library_kwargs(w, precision=prec, gmres_tol=tol, gmres_maxit=500))
+            s.step(Y, q, 1)
+            t0 = time.perf_counter()
+            for _ in range(w.steps):
+                t1 = time.perf_counter()
+                s.step(Y, q, 1)
+                lat.append(time.perf_counter() - t1)
+            t_tot += time.perf_counter() - t0
+            blob_steps += w.M * w.steps
+            s.close()
+        lat = np.array(lat) * 1e3
+        seq[prec] = {"blob_steps_per_s": blob_steps / t_tot, "requests": len(sample),
+                     "step_latency_p50_ms": float(np.percentile(lat, 50)),
+                     "step_latency_p99_ms": float(np.percentile(lat, 99))}
+    return {
+        "workload": f"{len(reqs)} suspensions of N rods x 10 blobs, N log-uniform in [8, 2048] "
+                    f"({sum(w.M for w in reqs):,} blobs), 5% blob volume fraction, grids "
+                    f"{min(w.n[0] for w in reqs)}^3..{max(w.n[0] for w in reqs)}^3, 50 gDC steps each, FP32",
+        "gmres_tol": tol, "mobility_rel_err_smallest_largest": errs,
+        "hbm_budget_bytes": budget, "max_slots": slots,
+        "saturation": sat, "poisson_at_saturation_rate": poisson,
+        "sequential_fp64_sample": seq["fp64"], "sequential_fp32_sample": seq["fp32"],
+        "served_over_sequential_fp64": sat["blob_steps_per_s"] / seq["fp64"]["blob_steps_per_s"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--serving-slots", type=int, default=SERVING_SLOTS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device copy first (counter calibration for profiling)")
     args = ap.parse_args()
@@ -96,9 +271,18 @@ def main():
         sys.exit(2)
 
     import numpy as np
+    import workloads as wl
+
+    # initial states first, in worker processes, before anything touches the GPU
+    w = wl.rods1000("fp32")
+    Y0, q0 = wl.initial_state(w)
+    reqs, states = [], []
+    if not args.no_serving:
+        reqs = wl.serving_requests(args.serving_requests)
+        states = wl.initial_states(reqs)
+
     import torch
     import paper_2106_00449_amd as g
-    import workloads as wl
 
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -107,9 +291,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    w = wl.rods1000("fp32")
-    Y0, q0 = wl.initial_state(w)
+    progress("calibrating the GMRES tolerance")
     tol, err = calibrate(g, wl, w, Y0, q0)
+    progress(f"tolerance {tol:g} (mobility error {err:.2e}); timing {args.steps} steps")
 
     stream = torch.cuda.current_stream()
     s = g.Suspension(**wl.library_kwargs(w, gmres_tol=tol, gmres_maxit=500, stream=stream.cuda_stream))
@@ -119,28 +303,35 @@ def main():
         s.step(Y, q, 1)
     torch.cuda.synchronize()
     g.probe_kernel(DOMINANT)
-    lat, its, nus = [], [], []
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        t0 = time.perf_counter()
-        st = s.step(Y, q, 1)
-        lat.append(time.perf_counter() - t0)
-        its.append(st["gmres_iterations"])
-        nus.append(st["nu"])
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
+    total, lat_ms, its, nus = timed_steps(g, s, Y, q, args.steps, 0)
     k_ms, k_launches = g.probe_read()
     g.probe_kernel(None)
     value = w.M * args.steps / total
-    lat_ms = np.array(lat) * 1e3
     G = int(np.prod(w.n))
     alg_bytes = BYTES_PER_POINT * G + BYTES_PER_BLOB * w.M
     avg_s = k_ms * 1e-3 / max(k_launches, 1)
     achieved = alg_bytes / avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES,
-                "kernel": "k_spread_sep", "launches": k_launches, "avg_us": avg_s * 1e6,
+                "kernel": "k_spread_tab", "launches": k_launches, "avg_us": avg_s * 1e6,
                 "algorithmic_bytes": alg_bytes}
+    progress("kernel bandwidths")
+    cov = grid_coverage(w, Y0, q0)
+    kernels = kernel_bandwidth(g, s, Y, q, w, cov)
+    s.close()
+
+    progress("plain FP64 path")
+    # the plain FP64 path on the same suspension, same tolerance
+    s64 = g.Suspension(**wl.library_kwargs(w, precision="fp64", gmres_tol=tol, gmres_maxit=500,
+                                           stream=stream.cuda_stream))
+    Y64 = torch.tensor(Y0, dtype=torch.float64, device="cuda")
+    q64 = torch.tensor(q0, dtype=torch.float64, device="cuda")
+    t64, lat64, its64, _ = timed_steps(g, s64, Y64, q64, max(5, args.steps // 3), 2)
+    s64.close()
+    fp64 = {"blob_steps_per_s": w.M * max(5, args.steps // 3) / t64,
+            "ms_per_step": t64 * 1e3 / max(5, args.steps // 3),
+            "gmres_iterations_mean": float(np.mean(its64)),
+            "mobility_rel_err": mobility_error(g, wl, w, Y0, q0, tol, precision="fp64")}
 
     out = {
         "metric": METRIC, "value": value, "unit": "blob-steps/s", "n_gpus": 1,
@@ -152,10 +343,16 @@ def main():
                    "gmres_tol": tol, "mobility_rel_err": err,
                    "gmres_iterations_mean": float(np.mean(its)),
                    "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
-                   "nu_mean": float(np.mean(nus))},
+                   "nu_mean": float(np.mean(nus)), "interp_grid_coverage": cov},
         "roofline": roofline,
+        "kernels": kernels,
+        "fp64_single": fp64,
     }
+    if reqs:
+        progress(f"serving {len(reqs)} requests")
+        out["serving"] = serving_bench(g, wl, reqs, states, tol, SERVING_BUDGET, args.serving_slots)
     if not args.no_cpu_baseline:
+        progress("oracle on the host")
         out["cpu_baseline"] = cpu_baseline(w, Y0, q0, tol)
     print(json.dumps(out))
 

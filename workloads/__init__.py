@@ -82,6 +82,7 @@ class Workload:
     const_force: tuple = (0.0, 0.0, 0.0, 0.0, 0.0, 0.0)
     shear_rate: float = 0.0
     nematic_cap_deg: float = 0.0     # 0: orientations uniform on S^3
+    placement: str = "sequential"    # or "batch" (see initial_state)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -119,14 +120,14 @@ def mixed4096():
     return Workload("mixed4096", (256.0,) * 3, (256,) * 3,
                     [rod(10), boomerang(), tetrahedron()], body_shape,
                     dt=0.005, steps=100, noise_seed=3, placement_seed=1003,
-                    const_force=(0.0, 0.0, 1.0, 0.0, 0.0, 0.0))
+                    const_force=(0.0, 0.0, 1.0, 0.0, 0.0, 0.0), placement="batch")
 
 
 def rods32768(steric=True):
     kw = _steric() if steric else {}
     return Workload("rods32768", (384.0,) * 3, (384,) * 3, [rod(10)],
                     np.zeros(32768, np.int64), dt=0.005, steps=10000, noise_seed=5,
-                    placement_seed=1005, shear_rate=0.1, nematic_cap_deg=15.0, **kw)
+                    placement_seed=1005, shear_rate=0.1, nematic_cap_deg=15.0, placement="batch", **kw)
 
 
 def small_case(name="tiny", n_bodies=4, n=16, L=16.0, shapes=None, body_shape=None,
@@ -156,7 +157,7 @@ def serving_requests(n_requests=256, seed=4):
         n = next(g for g in grids if g >= L / A)
         t += rng.exponential(1.0)
         w = Workload(f"req{r}", (L,) * 3, (n,) * 3, [rod(10)], np.zeros(N, np.int64),
-                     dt=0.005, steps=50, noise_seed=r, placement_seed=10000 + r)
+                     dt=0.005, steps=50, noise_seed=r, placement_seed=10000 + r, placement="batch")
         w.extra["arrival"] = t
         out.append(w)
     return out
@@ -197,9 +198,16 @@ def _random_orientation(rng, cap_deg):
 
 
 def initial_state(w: Workload, min_dist=2.0 * A, max_tries=2000):
-    """Centres uniform in the box, orientations as described, rejecting any
-    placement that puts a blob within min_dist (minimum image) of a blob of
-    another body.  Returns Y (N, 3) and q (N, 4), FP64."""
+    """Centres uniform in the box, orientations as described, no blob within
+    min_dist (minimum image) of a blob of another body.  Returns Y (N, 3) and
+    q (N, 4), FP64.
+
+    placement "sequential": bodies are placed one after the other, each
+    redrawn until it clears every body placed before it.  "batch": all bodies
+    are drawn at once, then every body that overlaps a lower-numbered one is
+    redrawn, until none overlaps (vectorised; for the large suspensions)."""
+    if w.placement == "batch":
+        return _batch_placement(w, min_dist, max_tries)
     rng = np.random.default_rng(w.placement_seed)
     L = np.asarray(w.L, dtype=np.float64)
     cell = max(min_dist, 1e-9)
@@ -241,6 +249,119 @@ def initial_state(w: Workload, min_dist=2.0 * A, max_tries=2000):
             xw = x - L * np.floor(x / L)
             bins.setdefault(key(xw), []).append(xw)
     return Y, Q
+
+
+def _draw_bodies(rng, k, L, cap_deg):
+    """k centres uniform in the box and k orientations: quaternions (k, 4)
+    and the matching (axis, angle) pairs."""
+    c = rng.uniform(0.0, 1.0, (k, 3)) * L
+    if cap_deg <= 0.0:
+        q = rng.standard_normal((k, 4))
+        q /= np.linalg.norm(q, axis=1, keepdims=True)
+        q[q[:, 0] < 0] *= -1.0
+        angle = 2.0 * np.arccos(np.minimum(1.0, q[:, 0]))
+        nv = np.linalg.norm(q[:, 1:], axis=1, keepdims=True)
+        axis = np.where(nv > 0, q[:, 1:] / np.where(nv > 0, nv, 1.0), np.array([0.0, 0.0, 1.0]))
+    else:
+        cmin = math.cos(math.radians(cap_deg))
+        ct = rng.uniform(cmin, 1.0, k)
+        phi = rng.uniform(0.0, 2.0 * math.pi, k)
+        st = np.sqrt(1.0 - ct * ct)
+        e = np.stack([st * np.cos(phi), st * np.sin(phi), ct], axis=1)
+        axis = np.cross(np.array([0.0, 0.0, 1.0]), e)
+        na = np.linalg.norm(axis, axis=1, keepdims=True)
+        angle = np.arccos(ct)
+        axis = np.where(na > 1e-15, axis / np.where(na > 1e-15, na, 1.0), np.array([1.0, 0.0, 0.0]))
+        q = np.concatenate([np.cos(angle / 2)[:, None], np.sin(angle / 2)[:, None] * axis], axis=1)
+    return c, q, axis, angle
+
+
+def _rodrigues_many(axis, angle, b):
+    """Rotate the body-frame offsets b (nb, 3) of k bodies: (k, nb, 3)."""
+    c = np.cos(angle)[:, None, None]
+    s = np.sin(angle)[:, None, None]
+    ax = axis[:, None, :]
+    v = b[None, :, :]
+    return v * c + np.cross(ax, v) * s + (v @ axis[:, :, None]) * ax * (1.0 - c)
+
+
+def _close_pairs(p, ref, L, nc, min_dist):
+    """Index pairs (i, j) with p[i] within min_dist of ref[j] (minimum image),
+    found through a cell list of ref (cells of at least min_dist)."""
+    def cells(x):
+        w = x - L * np.floor(x / L)
+        c = np.minimum((w / (L / nc)).astype(np.int64), nc - 1)
+        return w, c
+    pw, pc = cells(p)
+    rw, rc = cells(ref)
+    rid = (rc[:, 0] * nc[1] + rc[:, 1]) * nc[2] + rc[:, 2]
+    order = np.argsort(rid, kind="stable")
+    srid = rid[order]
+    out_i, out_j = [], []
+    for d in np.ndindex(3, 3, 3):
+        nb = (pc + np.array(d) - 1) % nc
+        nid = (nb[:, 0] * nc[1] + nb[:, 1]) * nc[2] + nb[:, 2]
+        lo = np.searchsorted(srid, nid, "left")
+        hi = np.searchsorted(srid, nid, "right")
+        k = lo[:, None] + np.arange(max(int((hi - lo).max(initial=0)), 1))[None, :]
+        ok = k < hi[:, None]
+        cj = order[np.minimum(np.where(ok, k, 0), len(order) - 1)]
+        dv = pw[:, None, :] - rw[cj]
+        dv -= L * np.round(dv / L)
+        close = ok & (np.einsum("ijk,ijk->ij", dv, dv) < min_dist * min_dist)
+        i, jj = np.nonzero(close)
+        out_i.append(i)
+        out_j.append(cj[i, jj])
+    return np.concatenate(out_i), np.concatenate(out_j)
+
+
+def _batch_placement(w, min_dist, max_rounds):
+    rng = np.random.default_rng(w.placement_seed)
+    L = np.asarray(w.L, dtype=np.float64)
+    N = w.N
+    nc = np.maximum((L // max(min_dist, 1e-9)).astype(int), 1)
+    if np.any(nc < 3):
+        raise ValueError("batch placement needs a box of at least three cells per axis")
+    bshape = np.asarray(w.body_shape)
+    nbs = np.array([len(w.shapes[s]) for s in bshape])
+    off = np.concatenate([[0], np.cumsum(nbs)])
+    blob_body = np.repeat(np.arange(N), nbs)
+    Y = np.zeros((N, 3))
+    Q = np.zeros((N, 4))
+    pos = np.zeros((int(off[-1]), 3))
+    todo = np.arange(N)
+    for _ in range(max_rounds):
+        for s in np.unique(bshape[todo]):
+            grp = todo[bshape[todo] == s]
+            nb = len(w.shapes[s])
+            c, q, axis, angle = _draw_bodies(rng, len(grp), L, w.nematic_cap_deg)
+            Y[grp], Q[grp] = c, q
+            idx = off[grp][:, None] + np.arange(nb)[None, :]
+            pos[idx.ravel()] = (c[:, None, :] + _rodrigues_many(axis, angle, np.asarray(w.shapes[s]))).reshape(-1, 3)
+        # a drawn body that overlaps a kept body, or a lower-numbered drawn
+        # body, is drawn again (kept bodies never move)
+        drawn = np.zeros(N, bool)
+        drawn[todo] = True
+        rows = np.nonzero(drawn[blob_body])[0]
+        i, j = _close_pairs(pos[rows], pos, L, nc, min_dist)
+        bi, bj = blob_body[rows[i]], blob_body[j]
+        hit = (bi != bj) & (~drawn[bj] | (bj < bi))
+        todo = np.unique(bi[hit])
+        if todo.size == 0:
+            return Y, Q
+    raise RuntimeError(f"could not place the bodies of {w.name}")
+
+
+def initial_states(ws, processes=None):
+    """initial_state of each workload, computed in worker processes (fork;
+    call it before the process touches a GPU)."""
+    import multiprocessing as mp
+    import os
+    n = processes or min(16, len(os.sched_getaffinity(0)))
+    if n <= 1 or len(ws) <= 1:
+        return [initial_state(w) for w in ws]
+    with mp.get_context("fork").Pool(n) as pool:
+        return pool.map(initial_state, ws, chunksize=1)
 
 
 def library_kwargs(w: Workload, **over):
