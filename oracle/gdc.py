@@ -162,8 +162,8 @@ def rfd_divergence(cfg: Config, Y, q, ufl, calV, step):
     """Random finite difference (eq. rfd_div): W~ ~ N(0,1)^{6N} from Philox
     (stage 1, counter c0 = body, two calls of which the first six normals are
     used), translations scaled by L_p; returns per-body terms d_p whose sum
-    has the divergence as its expectation.  Parity unpinned beyond the
-    statistical law E[sum d_p] = d_x . calV."""
+    has the divergence as its expectation (pinned by that law against the
+    forward-difference divergence)."""
     b = cfg.susp.bodies
     Y = np.asarray(Y, dtype=np.float64).reshape(-1, 3)
     q = np.asarray(q, dtype=np.float64).reshape(-1, 4)

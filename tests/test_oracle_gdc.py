@@ -132,3 +132,22 @@ def test_background_shear_profile():
     u = gdc.background_flow(cfg, Y, r)
     assert np.allclose(u[:, 0], 0.1 * (9.0 + (r[:, 1] - Y[0, 1]) - 6.0))
     assert np.all(u[:, 1:] == 0)
+
+
+def test_rfd_mean_is_the_fd_divergence():
+    # eq. rfd_div: with W~ ~ N(0, I) the random difference quotient of each
+    # body has that body's divergence as its mean.  W~ is keyed by the step
+    # counter while the field is passed in, so averaging over counters with
+    # the field held fixed samples W~ alone; the mean must match the
+    # forward-difference divergence (pinned above) within its standard error.
+    cfg = _cfg([wl.boomerang(), wl.rod(3)], [0, 1])
+    Y, q = _state(cfg, 4)
+    ufl = gdc.fluct_field(cfg, 0)
+    calV, d_fd = gdc.predictor(cfg, Y, q, ufl)
+    K = 3000
+    smp = np.array([gdc.rfd_divergence(cfg, Y, q, ufl, calV, s) for s in range(K)])
+    mean = smp.mean(0)
+    se = smp.std(0, ddof=1) / math.sqrt(K)
+    assert np.all(np.abs(mean - d_fd) < 5.0 * se), (mean, d_fd, se)
+    # the test resolves the divergence: it is many standard errors from 0
+    assert np.all(np.abs(d_fd) > 5.0 * se), (d_fd, se)
