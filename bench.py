@@ -189,6 +189,23 @@ def kernel_bandwidth(g, s, Y, q, w, cov):
     return out
 
 
+def fp64_single(g, wl, w, Y0, q0, tol, stream, steps):
+    """The plain FP64 path on the same suspension at the same tolerance."""
+    import numpy as np
+    import torch
+    progress("plain FP64 path")
+    k = max(5, steps // 3)
+    s64 = g.Suspension(**wl.library_kwargs(w, precision="fp64", gmres_tol=tol, gmres_maxit=500,
+                                           stream=stream.cuda_stream))
+    Y64 = torch.tensor(Y0, dtype=torch.float64, device="cuda")
+    q64 = torch.tensor(q0, dtype=torch.float64, device="cuda")
+    t64, _, its64, _ = timed_steps(g, s64, Y64, q64, k, 2)
+    s64.close()
+    return {"blob_steps_per_s": w.M * k / t64, "ms_per_step": t64 * 1e3 / k,
+            "gmres_iterations_mean": float(np.mean(its64)),
+            "mobility_rel_err": mobility_error(g, wl, w, Y0, q0, tol, precision="fp64")}
+
+
 def serving_bench(g, wl, reqs, states, tol, budget, slots):
     import numpy as np
     from paper_2106_00449_amd.serving import Request, Server, summarise
@@ -262,6 +279,10 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-slots", type=int, default=SERVING_SLOTS)
+    ap.add_argument("--gmres-tol", type=float, default=0.0,
+                    help="use this GMRES tolerance instead of calibrating one (profiling runs)")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time the headline suspension only (no kernel table, FP64 path or serving)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device copy first (counter calibration for profiling)")
     args = ap.parse_args()
@@ -277,7 +298,7 @@ def main():
     w = wl.rods1000("fp32")
     Y0, q0 = wl.initial_state(w)
     reqs, states = [], []
-    if not args.no_serving:
+    if not (args.no_serving or args.only_headline):
         reqs = wl.serving_requests(args.serving_requests)
         states = wl.initial_states(reqs)
 
@@ -291,9 +312,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    progress("calibrating the GMRES tolerance")
-    tol, err = calibrate(g, wl, w, Y0, q0)
-    progress(f"tolerance {tol:g} (mobility error {err:.2e}); timing {args.steps} steps")
+    if args.gmres_tol > 0.0:
+        tol, err = args.gmres_tol, None
+    else:
+        progress("calibrating the GMRES tolerance")
+        tol, err = calibrate(g, wl, w, Y0, q0)
+    progress(f"tolerance {tol:g}; timing {args.steps} steps")
 
     stream = torch.cuda.current_stream()
     s = g.Suspension(**wl.library_kwargs(w, gmres_tol=tol, gmres_maxit=500, stream=stream.cuda_stream))
@@ -315,24 +339,15 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES,
                 "kernel": "k_spread_tab", "launches": k_launches, "avg_us": avg_s * 1e6,
                 "algorithmic_bytes": alg_bytes}
-    progress("kernel bandwidths")
     cov = grid_coverage(w, Y0, q0)
-    kernels = kernel_bandwidth(g, s, Y, q, w, cov)
+    kernels, fp64 = {}, {}
+    if not args.only_headline:
+        progress("kernel bandwidths")
+        kernels = kernel_bandwidth(g, s, Y, q, w, cov)
     s.close()
 
-    progress("plain FP64 path")
-    # the plain FP64 path on the same suspension, same tolerance
-    s64 = g.Suspension(**wl.library_kwargs(w, precision="fp64", gmres_tol=tol, gmres_maxit=500,
-                                           stream=stream.cuda_stream))
-    Y64 = torch.tensor(Y0, dtype=torch.float64, device="cuda")
-    q64 = torch.tensor(q0, dtype=torch.float64, device="cuda")
-    t64, lat64, its64, _ = timed_steps(g, s64, Y64, q64, max(5, args.steps // 3), 2)
-    s64.close()
-    fp64 = {"blob_steps_per_s": w.M * max(5, args.steps // 3) / t64,
-            "ms_per_step": t64 * 1e3 / max(5, args.steps // 3),
-            "gmres_iterations_mean": float(np.mean(its64)),
-            "mobility_rel_err": mobility_error(g, wl, w, Y0, q0, tol, precision="fp64")}
-
+    if not args.only_headline:
+        fp64 = fp64_single(g, wl, w, Y0, q0, tol, stream, args.steps)
     out = {
         "metric": METRIC, "value": value, "unit": "blob-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": total * 1e3 / args.steps,

@@ -889,6 +889,7 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
   g.rc2 = c.trunc * c.trunc;
   g.inv2s2 = 1.0 / (2.0 * c.sigma * c.sigma);
   g.wnorm = std::pow(2.0 * 3.14159265358979323846 * c.sigma * c.sigma, -1.5);
+  g.tiled = (g.n[0] % 8 == 0 && g.n[1] % 8 == 0 && g.n[2] % 32 == 0) ? 1 : 0;
 
   // shapes and bodies
   h->N = cfg->n_bodies;
@@ -1447,12 +1448,19 @@ int gdc_fluct_velocity(gdc_handle* h, uint64_t step, double* u, int memspace) {
   const size_t n = 3 * (size_t)h->geom.G;
   if (h->precision == GDC_FP64) {
     GDC_TRY(make_fluct<double>(h, step));
-    GDC_TRY(copy_out(h, u, (const double*)h->grid_fl, n, memspace));
+    if (h->geom.tiled) {
+      // row-major copy in the (free) first two work fields, then out
+      double* tmp = (double*)h->grid[1];
+      GDC_TRY(field_to_rowmajor(h->geom, (const double*)h->grid_fl, tmp, h->stream));
+      GDC_TRY(copy_out(h, u, tmp, n, memspace));
+    } else {
+      GDC_TRY(copy_out(h, u, (const double*)h->grid_fl, n, memspace));
+    }
   } else {
     GDC_TRY(make_fluct<float>(h, step));
-    // widen into the (free) first grid buffer pair, then copy out
+    // widen into the (free) first grid buffer pair, row-major, then copy out
     double* tmp = (double*)h->grid[1];
-    GDC_TRY(widen((const float*)h->grid_fl, tmp, (long long)n, h->stream));
+    GDC_TRY(field_to_rowmajor(h->geom, (const float*)h->grid_fl, tmp, h->stream));
     GDC_TRY(copy_out(h, u, tmp, n, memspace));
   }
   return finish(h);

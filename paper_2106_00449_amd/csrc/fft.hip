@@ -222,7 +222,7 @@ __device__ __forceinline__ void load_twiddles(Cx<R>* tw, const Cx<R>* __restrict
 // A(k) = (Z(k) + conj Z(N-k))/2 and B(k) = (Z(k) - conj Z(N-k))/(2i).
 template <typename R, int N2>
 __global__ __launch_bounds__(NT) void k_r2c_axis2(const R* __restrict__ in, Cx<R>* __restrict__ X,
-                                                  const Cx<R>* __restrict__ twg, int n0, int n1,
+                                                  const Cx<R>* __restrict__ twg, int n0, int n1, int tiled,
                                                   const int* __restrict__ skip) {
   if (skip && *skip) return;
   constexpr int TL = Tiles<R>::TL, NLc = TL / 2, LS = N2 + 1, H = N2 / 2;
@@ -232,11 +232,11 @@ __global__ __launch_bounds__(NT) void k_r2c_axis2(const R* __restrict__ in, Cx<R
   const int c = blockIdx.z, i0 = blockIdx.y, i1b = blockIdx.x * TL;
   const int nl = min(TL, n1 - i1b);
   load_twiddles<R, N2>(tw, twg);
-  const R* src = in + (((long long)c * n0 + i0) * n1 + i1b) * N2;
+  const R* src = in + (long long)c * n0 * n1 * N2 + field_plane_off(tiled, n1, N2, i0);
   for (int e = tid; e < NLc * N2; e += NT) {
     const int p = e / N2, x = e - p * N2;
-    const R re = (2 * p < nl) ? src[(2 * p) * N2 + x] : R(0);
-    const R im = (2 * p + 1 < nl) ? src[(2 * p + 1) * N2 + x] : R(0);
+    const R re = (2 * p < nl) ? src[field_col_off(tiled, N2, i1b + 2 * p, x)] : R(0);
+    const R im = (2 * p + 1 < nl) ? src[field_col_off(tiled, N2, i1b + 2 * p + 1, x)] : R(0);
     buf[p * LS + x] = Cx<R>{re, im};
   }
   __syncthreads();
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(NT) void k_inv_axis1(const Cx<R>* __restrict__ Y, C
 // Nyquist term is zero.
 template <typename R, int N2>
 __global__ __launch_bounds__(NT) void k_c2r_axis2(const Cx<R>* __restrict__ X, R* __restrict__ out,
-                                                  const Cx<R>* __restrict__ twg, int n0, int n1,
+                                                  const Cx<R>* __restrict__ twg, int n0, int n1, int tiled,
                                                   const int* __restrict__ skip) {
   if (skip && *skip) return;
   constexpr int TL = Tiles<R>::TL, NLc = TL / 2, LS = N2 + 1, H = N2 / 2;
@@ -340,12 +340,12 @@ __global__ __launch_bounds__(NT) void k_c2r_axis2(const Cx<R>* __restrict__ X, R
   }
   __syncthreads();
   fft_lines<R, N2, NLc, LS, true>(buf, tw);
-  R* dst = out + (((long long)c * n0 + i0) * n1 + i1b) * N2;
+  R* dst = out + (long long)c * n0 * n1 * N2 + field_plane_off(tiled, n1, N2, i0);
   for (int e = tid; e < NLc * N2; e += NT) {
     const int p = e / N2, x = e - p * N2;
     const Cx<R> z = buf[p * LS + x];
-    if (2 * p < nl) dst[(2 * p) * N2 + x] = z.x;
-    if (2 * p + 1 < nl) dst[(2 * p + 1) * N2 + x] = z.y;
+    if (2 * p < nl) dst[field_col_off(tiled, N2, i1b + 2 * p, x)] = z.x;
+    if (2 * p + 1 < nl) dst[field_col_off(tiled, N2, i1b + 2 * p + 1, x)] = z.y;
   }
 }
 
@@ -516,7 +516,7 @@ struct PlaneLds {
 template <typename R, int N1, int N2>
 __global__ __launch_bounds__(NTP) void k_plane_fwd(const R* __restrict__ in, Cx<R>* __restrict__ Z,
                                                    const Cx<R>* __restrict__ tw1g, const Cx<R>* __restrict__ tw2g,
-                                                   int n0, const int* __restrict__ skip) {
+                                                   int n0, int tiled, const int* __restrict__ skip) {
   if (skip && *skip) return;
   using L = PlaneLds<N1, N2>;
   constexpr int H = L::H, NP = N1 / 2;
@@ -526,10 +526,10 @@ __global__ __launch_bounds__(NTP) void k_plane_fwd(const R* __restrict__ in, Cx<
   const int i0 = blockIdx.x, c = blockIdx.y;
   load_twiddles<R, N1, NTP>(tw1, tw1g);
   load_twiddles<R, N2, NTP>(tw2, tw2g);
-  const R* src = in + ((long long)c * n0 + i0) * N1 * N2;
+  const R* src = in + (long long)c * n0 * N1 * N2 + field_plane_off(tiled, N1, N2, i0);
   for (int e = tid; e < NP * N2; e += NTP) {
     const int p = e / N2, x = e - p * N2;
-    buf[p * L::LA + x] = Cx<R>{src[(2 * p) * N2 + x], src[(2 * p + 1) * N2 + x]};
+    buf[p * L::LA + x] = Cx<R>{src[field_col_off(tiled, N2, 2 * p, x)], src[field_col_off(tiled, N2, 2 * p + 1, x)]};
   }
   __syncthreads();
   fft_lines<R, N2, NP, L::LA, false, NTP>(buf, tw2);
@@ -572,7 +572,7 @@ __global__ __launch_bounds__(NTP) void k_plane_fwd(const R* __restrict__ in, Cx<
 template <typename R, int N1, int N2>
 __global__ __launch_bounds__(NTP) void k_plane_inv(const Cx<R>* __restrict__ Z, R* __restrict__ out,
                                                    const Cx<R>* __restrict__ tw1g, const Cx<R>* __restrict__ tw2g,
-                                                   int n0, const int* __restrict__ skip) {
+                                                   int n0, int tiled, const int* __restrict__ skip) {
   if (skip && *skip) return;
   using L = PlaneLds<N1, N2>;
   constexpr int H = L::H, NP = N1 / 2;
@@ -619,12 +619,12 @@ __global__ __launch_bounds__(NTP) void k_plane_inv(const Cx<R>* __restrict__ Z, 
   }
   __syncthreads();
   fft_lines<R, N2, NP, L::LA, true, NTP>(buf, tw2);
-  R* dst = out + ((long long)c * n0 + i0) * N1 * N2;
+  R* dst = out + (long long)c * n0 * N1 * N2 + field_plane_off(tiled, N1, N2, i0);
   for (int e = tid; e < NP * N2; e += NTP) {
     const int p = e / N2, x = e - p * N2;
     const Cx<R> z = buf[p * L::LA + x];
-    dst[(2 * p) * N2 + x] = z.x;
-    dst[(2 * p + 1) * N2 + x] = z.y;
+    dst[field_col_off(tiled, N2, 2 * p, x)] = z.x;
+    dst[field_col_off(tiled, N2, 2 * p + 1, x)] = z.y;
   }
 }
 
@@ -702,11 +702,12 @@ __global__ __launch_bounds__(NT) void k_axis0_plane(Cx<R>* __restrict__ Z, const
 #define GDC_FFT_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
 
 template <typename R>
-int launch_r2c(int n2, const R* in, Cx<R>* X, const Cx<R>* tw, int n0, int n1, hipStream_t s, const int* skip) {
+int launch_r2c(int n2, const R* in, Cx<R>* X, const Cx<R>* tw, int n0, int n1, int tiled, hipStream_t s,
+               const int* skip) {
   dim3 grid((n1 + Tiles<R>::TL - 1) / Tiles<R>::TL, n0, 3);
   ProbeScope ps("fft_r2c", s);
   switch (n2) {
-#define X_(N) case N: hipLaunchKernelGGL((k_r2c_axis2<R, N>), grid, dim3(NT), 0, s, in, X, tw, n0, n1, skip); break;
+#define X_(N) case N: hipLaunchKernelGGL((k_r2c_axis2<R, N>), grid, dim3(NT), 0, s, in, X, tw, n0, n1, tiled, skip); break;
     GDC_FFT_SIZES(X_)
 #undef X_
     default: set_error("unsupported grid size"); return GDC_EINVAL;
@@ -741,11 +742,12 @@ int launch_inv1(int n1, const Cx<R>* Y, Cx<R>* X, const Cx<R>* tw, int n0, int H
 }
 
 template <typename R>
-int launch_c2r(int n2, const Cx<R>* X, R* out, const Cx<R>* tw, int n0, int n1, hipStream_t s, const int* skip) {
+int launch_c2r(int n2, const Cx<R>* X, R* out, const Cx<R>* tw, int n0, int n1, int tiled, hipStream_t s,
+               const int* skip) {
   dim3 grid((n1 + Tiles<R>::TL - 1) / Tiles<R>::TL, n0, 3);
   ProbeScope ps("fft_c2r", s);
   switch (n2) {
-#define X_(N) case N: hipLaunchKernelGGL((k_c2r_axis2<R, N>), grid, dim3(NT), 0, s, X, out, tw, n0, n1, skip); break;
+#define X_(N) case N: hipLaunchKernelGGL((k_c2r_axis2<R, N>), grid, dim3(NT), 0, s, X, out, tw, n0, n1, tiled, skip); break;
     GDC_FFT_SIZES(X_)
 #undef X_
     default: set_error("unsupported grid size"); return GDC_EINVAL;
@@ -786,7 +788,7 @@ bool plane_path(const GridGeom& g) {
 
 template <typename R>
 int launch_plane(bool inverse, int n, const void* in, void* out, const Cx<R>* tw1, const Cx<R>* tw2, int n0,
-                 hipStream_t s, const int* skip) {
+                 int tiled, hipStream_t s, const int* skip) {
   dim3 grid(n0, 3);
   ProbeScope ps(inverse ? "fft_plane_inv" : "fft_plane_fwd", s);
   if constexpr (sizeof(R) != 4) {
@@ -795,7 +797,7 @@ int launch_plane(bool inverse, int n, const void* in, void* out, const Cx<R>* tw
   } else {
   if (!inverse) {
     switch (n) {
-#define X_(N) case N: hipLaunchKernelGGL((k_plane_fwd<R, N, N>), grid, dim3(NTP), 0, s, (const R*)in, (Cx<R>*)out, tw1, tw2, n0, skip); break;
+#define X_(N) case N: hipLaunchKernelGGL((k_plane_fwd<R, N, N>), grid, dim3(NTP), 0, s, (const R*)in, (Cx<R>*)out, tw1, tw2, n0, tiled, skip); break;
       GDC_PLANE_SIZES(X_)
 #undef X_
       default: set_error("unsupported plane size"); return GDC_EINVAL;
@@ -803,7 +805,7 @@ int launch_plane(bool inverse, int n, const void* in, void* out, const Cx<R>* tw
     return check_launch("k_plane_fwd");
   }
   switch (n) {
-#define X_(N) case N: hipLaunchKernelGGL((k_plane_inv<R, N, N>), grid, dim3(NTP), 0, s, (const Cx<R>*)in, (R*)out, tw1, tw2, n0, skip); break;
+#define X_(N) case N: hipLaunchKernelGGL((k_plane_inv<R, N, N>), grid, dim3(NTP), 0, s, (const Cx<R>*)in, (R*)out, tw1, tw2, n0, tiled, skip); break;
     GDC_PLANE_SIZES(X_)
 #undef X_
     default: set_error("unsupported plane size"); return GDC_EINVAL;
@@ -860,15 +862,15 @@ int stokes_solve(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X,
                  hipStream_t s, const int* skip) {
   const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], H = g.n2h;
   if (plane_path<R>(g)) {
-    GDC_TRY(launch_plane<R>(false, n1, real, X, tw[1], tw[2], n0, s, skip));
+    GDC_TRY(launch_plane<R>(false, n1, real, X, tw[1], tw[2], n0, g.tiled, s, skip));
     GDC_TRY((launch_proj_plane<R, false>(n0, X, tw[0], proj_params(g), s, skip)));
-    return launch_plane<R>(true, n1, X, real, tw[1], tw[2], n0, s, skip);
+    return launch_plane<R>(true, n1, X, real, tw[1], tw[2], n0, g.tiled, s, skip);
   }
-  GDC_TRY(launch_r2c<R>(n2, real, X, tw[2], n0, n1, s, skip));
+  GDC_TRY(launch_r2c<R>(n2, real, X, tw[2], n0, n1, g.tiled, s, skip));
   GDC_TRY(launch_fwd1<R>(n1, X, Y, tw[1], n0, H, s, skip));
   GDC_TRY((launch_proj<R, false>(n0, Y, tw[0], proj_params(g), s, skip)));
   GDC_TRY(launch_inv1<R>(n1, Y, X, tw[1], n0, H, s, skip));
-  GDC_TRY(launch_c2r<R>(n2, X, real, tw[2], n0, n1, s, skip));
+  GDC_TRY(launch_c2r<R>(n2, X, real, tw[2], n0, n1, g.tiled, s, skip));
   return GDC_OK;
 }
 
@@ -887,11 +889,11 @@ int fluct_field(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, 
   P.soff = std::sqrt((double)g.G * 2.0 * base / 2.0);
   if (plane_path<R>(g)) {
     GDC_TRY((launch_proj_plane<R, true>(n0, X, tw[0], P, s, nullptr)));
-    return launch_plane<R>(true, n1, X, real, tw[1], tw[2], n0, s, nullptr);
+    return launch_plane<R>(true, n1, X, real, tw[1], tw[2], n0, g.tiled, s, nullptr);
   }
   GDC_TRY((launch_proj<R, true>(n0, Y, tw[0], P, s, nullptr)));
   GDC_TRY(launch_inv1<R>(n1, Y, X, tw[1], n0, H, s, nullptr));
-  GDC_TRY(launch_c2r<R>(n2, X, real, tw[2], n0, n1, s, nullptr));
+  GDC_TRY(launch_c2r<R>(n2, X, real, tw[2], n0, n1, g.tiled, s, nullptr));
   return GDC_OK;
 }
 

@@ -135,7 +135,23 @@ struct GridGeom {
   double inv2s2;      // 1 / (2 sigma^2)
   double wnorm;       // (2 pi sigma^2)^(-3/2)
   int P[3];           // stencil points per axis: floor(2 rc / dx) + 1
+  // Layout of each component of a real-space field: row-major [i0][i1][i2]
+  // (tiled = 0) or tile-major (tiled = 1, when 8 | n0, 8 | n1, 32 | n2):
+  // tiles of 8 x 8 x 32 points in row-major tile order, each tile stored
+  // contiguously as [i0 % 8][i1 % 8][i2 % 32].  A spreading workgroup then
+  // writes its tile as one contiguous block.
+  int tiled;
 };
+
+// Offset of grid point (i0, i1, i2) within one component of a real-space
+// field: field_plane_off(i0) + field_col_off(i1, i2).
+__host__ __device__ inline long long field_plane_off(int tiled, int n1, int n2, int i0) {
+  return tiled ? (((long long)(i0 >> 3) * n1 * n2) << 3) + ((i0 & 7) << 8) : (long long)i0 * n1 * n2;
+}
+__host__ __device__ inline long long field_col_off(int tiled, int n2, int i1, int i2) {
+  return tiled ? ((long long)((i1 >> 3) * (n2 >> 5) + (i2 >> 5)) << 11) + ((i1 & 7) << 5) + (i2 & 31)
+               : (long long)i1 * n2 + i2;
+}
 
 // Tiling of the grid for the spreading kernel: tiles of T[0] x T[1] x T[2]
 // points (the last tile along an axis may be partial), nt[d] tiles per axis,
@@ -216,7 +232,9 @@ template <typename R>
 int interp_fd(const GridGeom& g, const double* r, const double* dr, int NP, const R* u,
               double* v, double* vd, int M, hipStream_t s);
 int fill_zero(void* p, size_t bytes, hipStream_t s);
-int widen(const float* x, double* y, long long n, hipStream_t s);
+// y (3 x n0 x n1 x n2, row-major, FP64) = the real-space field x in the layout of g.
+template <typename R>
+int field_to_rowmajor(const GridGeom& g, const R* x, double* y, hipStream_t s);
 
 // Body kernels (body.hip).
 int blob_positions(const BodyTables& b, const double* Y, const double* q, double* r,

@@ -116,8 +116,7 @@ __global__ __launch_bounds__(NT) void k_interp(GridGeom G, const double* __restr
     const double d1 = B.e[1] + a1 * G.dx[1], d2 = B.e[2] + a2 * G.dx[2];
     const double d12 = d1 * d1 + d2 * d2;
     if (d12 > G.rc2) continue;
-    const long long col = (long long)wrap(B.g[1] + a1, n1) * n2 + wrap(B.g[2] + a2, n2);
-    const long long plane = (long long)n1 * n2;
+    const long long col = field_col_off(G.tiled, n2, wrap(B.g[1] + a1, n1), wrap(B.g[2] + a2, n2));
     // four points of the column per round, all loads issued before use
     for (int a0 = 0; a0 < P0; a0 += 4) {
       R wv[4];
@@ -130,7 +129,7 @@ __global__ __launch_bounds__(NT) void k_interp(GridGeom G, const double* __restr
         const double dd = d0 * d0 + d12;
         const bool ok = (aa < P0) && (dd <= G.rc2);
         wv[q] = ok ? wn * gexp<R>(-R(dd) * i2) : R(0);
-        ix[q] = (long long)(ok ? gg : B.g[0]) * plane + col;
+        ix[q] = field_plane_off(G.tiled, n1, n2, ok ? gg : B.g[0]) + col;
       }
       R x0[4], x1[4], x2[4];
 #pragma unroll
@@ -202,14 +201,14 @@ __global__ __launch_bounds__(NT) void k_interp_fd(GridGeom G, const double* __re
     const double d1 = B.e[1] + a1 * G.dx[1], d2 = B.e[2] + a2 * G.dx[2];
     const double d12 = d1 * d1 + d2 * d2;
     if (d12 > reach2) continue;
-    const long long col = (long long)wrap(B.g[1] + a1, n1) * n2 + wrap(B.g[2] + a2, n2);
+    const long long col = field_col_off(G.tiled, n2, wrap(B.g[1] + a1, n1), wrap(B.g[2] + a2, n2));
     int g0 = B.g[0];
     for (int a0 = 0; a0 < P0; ++a0, g0 = (g0 + 1 == n0) ? 0 : g0 + 1) {
       const double d0 = B.e[0] + a0 * G.dx[0];
       const double dd = d0 * d0 + d12;
       if (dd > reach2) continue;
       const bool in0 = dd <= G.rc2;
-      const long long idx = (long long)g0 * n1 * n2 + col;
+      const long long idx = field_plane_off(G.tiled, n1, n2, g0) + col;
       const R u0 = u[idx], u1 = u[Gs + idx], u2 = u[2 * Gs + idx];
       const R w = in0 ? wn * gexp<R>(-R(dd) * i2) : R(0);
       s[0] += w * u0;
@@ -672,6 +671,21 @@ __global__ __launch_bounds__(NT) void k_spread_tab(GridGeom G, TileGeom T, const
   constexpr int VW = 16 / sizeof(R);   // values per 16-byte store
   constexpr int NV = TZ / VW;          // stores per row
   const long long Gs = G.G;
+  if (G.tiled) {
+    // tile-major field: the tile (all tiles full) is one contiguous block per component
+    for (int p = tid; p < 3 * TX * TX * NV; p += NT) {
+      const int cc = p / (TX * TX * NV), rem = p - cc * (TX * TX * NV);
+      const int col = rem / NV, zv = (rem - col * NV) * VW;
+      const R* srcv = sh + (cc * TX * TX + col) * TZP + zv;
+      R* dst = f + cc * Gs + (long long)tl * (TX * TX * TZ) + col * TZ + zv;
+      if constexpr (sizeof(R) == 4) {
+        *reinterpret_cast<float4*>(dst) = make_float4(srcv[0], srcv[1], srcv[2], srcv[3]);
+      } else {
+        *reinterpret_cast<double2*>(dst) = make_double2(srcv[0], srcv[1]);
+      }
+    }
+    return;
+  }
   for (int p = tid; p < 3 * TX * TX * NV; p += NT) {
     const int cc = p / (TX * TX * NV), rem = p - cc * (TX * TX * NV);
     const int col = rem / NV, zv = (rem - col * NV) * VW;
@@ -697,9 +711,18 @@ __global__ void k_fill_zero(uint4* __restrict__ p, long long n16) {
   for (long long k = i; k < n16; k += stride) p[k] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-__global__ void k_widen(const float* __restrict__ x, double* __restrict__ y, long long n) {
+template <typename R>
+__global__ void k_to_rowmajor(GridGeom G, const R* __restrict__ x, double* __restrict__ y) {
+  const long long n = 3 * G.G;
   const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) y[e] = (double)x[e];
+  const int n1 = G.n[1], n2 = G.n[2];
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+    const long long c = e / G.G, rem = e - c * G.G;
+    const int i2 = (int)(rem % n2);
+    const long long r01 = rem / n2;
+    const int i1 = (int)(r01 % n1), i0 = (int)(r01 / n1);
+    y[e] = (double)x[c * G.G + field_plane_off(G.tiled, n1, n2, i0) + field_col_off(G.tiled, n2, i1, i2)];
+  }
 }
 
 inline unsigned blocks_for(int M) { return (unsigned)((M + WAVES - 1) / WAVES); }
@@ -721,11 +744,15 @@ int fill_zero(void* p, size_t bytes, hipStream_t s) {
   return check_launch("k_fill_zero");
 }
 
-int widen(const float* x, double* y, long long n, hipStream_t s) {
-  const long long want = (n + 255) / 256;
-  hipLaunchKernelGGL(k_widen, dim3((unsigned)(want < 8192 ? (want > 0 ? want : 1) : 8192)), dim3(256), 0, s, x, y, n);
-  return check_launch("k_widen");
+template <typename R>
+int field_to_rowmajor(const GridGeom& g, const R* x, double* y, hipStream_t s) {
+  const long long want = (3 * g.G + 255) / 256;
+  hipLaunchKernelGGL((k_to_rowmajor<R>), dim3((unsigned)(want < 8192 ? (want > 0 ? want : 1) : 8192)), dim3(256),
+                     0, s, g, x, y);
+  return check_launch("k_to_rowmajor");
 }
+template int field_to_rowmajor<float>(const GridGeom&, const float*, double*, hipStream_t);
+template int field_to_rowmajor<double>(const GridGeom&, const double*, double*, hipStream_t);
 
 int tile_sort(const GridGeom& g, const TileGeom& t, const double* r, int M, int* tile, int* count, int* off,
               int* cursor, void* rec, int* spos, hipStream_t s) {
