@@ -78,6 +78,17 @@ __device__ __forceinline__ BlobBase blob_base(const GridGeom& G, const double* r
   return b;
 }
 
+// Workgroups are handed to the 8 XCDs (each with its own L2) round-robin by
+// block index.  The averaging kernels remap the block index so that XCD x
+// takes a contiguous run of blobs (whole bodies: blobs are numbered body by
+// body), which keeps the overlapping stencils of a body's blobs in one L2.
+// The grid is padded to a multiple of 8 blocks; blocks past the end return.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_block(int nb_padded) {
+  const int per = nb_padded / NXCD;
+  return (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
+}
+
 // Index of stencil point g + a (g in [0, n), 0 <= a <= n + 1).
 __device__ __forceinline__ int wrap(int g, int n) {
   g -= (g >= n) ? n : 0;
@@ -102,7 +113,7 @@ __global__ __launch_bounds__(NT) void k_interp(GridGeom G, const double* __restr
                                                const R* __restrict__ u, double* __restrict__ v, int M,
                                                double scale, RigidTerm K, const int* __restrict__ skip) {
   if (skip && *skip) return;
-  const int blob = blockIdx.x * WAVES + threadIdx.x / 64;
+  const int blob = xcd_block(gridDim.x) * WAVES + threadIdx.x / 64;
   const int lane = threadIdx.x & 63;
   if (blob >= M) return;
   const BlobBase B = blob_base(G, r + 3LL * blob, 0);
@@ -170,7 +181,7 @@ template <typename R, int NP>
 __global__ __launch_bounds__(NT) void k_interp_fd(GridGeom G, const double* __restrict__ r,
                                                   const double* __restrict__ dr, const R* __restrict__ u,
                                                   double* __restrict__ v, double* __restrict__ vd, int M) {
-  const int blob = blockIdx.x * WAVES + threadIdx.x / 64;
+  const int blob = xcd_block(gridDim.x) * WAVES + threadIdx.x / 64;
   const int lane = threadIdx.x & 63;
   if (blob >= M) return;
   const BlobBase B = blob_base(G, r + 3LL * blob, 1);
@@ -591,16 +602,21 @@ __global__ __launch_bounds__(NT) void k_spread_prep(GridGeom G, TileGeom T, cons
   }
 }
 
-// Spreading f = S lambda, one workgroup per tile, from the tables of
-// k_spread_prep.  Wave w owns z-chunk w (8 consecutive axis-2 points), lane =
-// (axis-1 offset, point of the chunk), with the 8 axis-0 planes of its point
-// in registers.  Per hit it skips, wave-uniformly, a chunk the hit misses and
-// the axis-0 planes outside the hit's stencil; a point costs a product, a
-// compare and three multiply-adds.  The tile then goes through LDS and out
-// with 16-byte stores, whole 128-byte rows at a time.  No atomics and a fixed
-// summation order: results repeat bit for bit.
+// Spreading f = S lambda, one workgroup of 512 threads per tile, from the
+// tables of k_spread_prep.  Wave w owns z-chunk w % 4 (8 consecutive axis-2
+// points) and the hits of parity w / 4; lane = (axis-1 offset, point of the
+// chunk), with the 8 axis-0 planes of its point in registers.  Per hit it
+// skips, wave-uniformly, a chunk the hit misses and the axis-0 planes outside
+// the hit's stencil; a point costs a product, a compare and three
+// multiply-adds.  Splitting the hits between two waves per chunk halves the
+// longest workgroup (the kernel lasts as long as its busiest tile); the odd
+// half is added to the even one through LDS in a fixed order.  The tile then
+// goes out with 16-byte stores, whole 128-byte rows at a time.  No atomics and
+// a fixed summation order: results repeat bit for bit.
+constexpr int NTS = 512;   // threads of a spreading workgroup
+
 template <typename R>
-__global__ __launch_bounds__(NT) void k_spread_tab(GridGeom G, TileGeom T, const HitTab<R>* __restrict__ tabs,
+__global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, const HitTab<R>* __restrict__ tabs,
                                                    const int* __restrict__ tab_start,
                                                    const int* __restrict__ tab_count, const double* __restrict__ lam,
                                                    const double* __restrict__ lam_sorted, R* __restrict__ f,
@@ -615,7 +631,7 @@ __global__ __launch_bounds__(NT) void k_spread_tab(GridGeom G, TileGeom T, const
   __shared__ __align__(16) R sh[SH];    // a round of tables, then the staged tile
   __shared__ R h_l[HR][3];
   HitTab<R>* tab = reinterpret_cast<HitTab<R>*>(sh);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = (tid >> 6) & 3, half = tid >> 8;
   const int tl = blockIdx.x;
   const int t2 = tl % T.nt[2], t1 = (tl / T.nt[2]) % T.nt[1], t0 = tl / (T.nt[1] * T.nt[2]);
   const int ts[3] = {t0 * T.T[0], t1 * T.T[1], t2 * T.T[2]};
@@ -632,7 +648,7 @@ __global__ __launch_bounds__(NT) void k_spread_tab(GridGeom G, TileGeom T, const
     const int nr = min(HR, cnt - hb);
     const uint4* src = reinterpret_cast<const uint4*>(tabs + start + hb);
     uint4* dstv = reinterpret_cast<uint4*>(sh);
-    for (int v = tid; v < nr * V16; v += NT) dstv[v] = src[v];
+    for (int v = tid; v < nr * V16; v += NTS) dstv[v] = src[v];
     __syncthreads();
     if (tid < nr) {
       const int p = tab[tid].pos, b = tab[tid].blob;
@@ -641,7 +657,7 @@ __global__ __launch_bounds__(NT) void k_spread_tab(GridGeom G, TileGeom T, const
     }
     __syncthreads();
     if (live) {
-      for (int h = 0; h < nr; ++h) {
+      for (int h = half; h < nr; h += 2) {
         const HitTab<R>& t = tab[h];
         const int hm = t.mask;
         if (!((hm >> wave) & 1)) continue;
@@ -661,11 +677,25 @@ __global__ __launch_bounds__(NT) void k_spread_tab(GridGeom G, TileGeom T, const
     }
     __syncthreads();
   }
-  // stage [c][axis-0][axis-1][z] and write rows with 16-byte stores
+  // stage [c][axis-0][axis-1][z]: the odd-hit half first, then the even
+  // half adds its sums, and write rows with 16-byte stores
+  if (half == 1) {
 #pragma unroll
-  for (int k = 0; k < TX; ++k) {
+    for (int k = 0; k < TX; ++k) {
 #pragma unroll
-    for (int cc = 0; cc < 3; ++cc) sh[(cc * TX * TX + k * TX + j1) * TZP + z] = acc[k][cc];
+      for (int cc = 0; cc < 3; ++cc) sh[(cc * TX * TX + k * TX + j1) * TZP + z] = acc[k][cc];
+    }
+  }
+  __syncthreads();
+  if (half == 0) {
+#pragma unroll
+    for (int k = 0; k < TX; ++k) {
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        const int a = (cc * TX * TX + k * TX + j1) * TZP + z;
+        sh[a] = acc[k][cc] + sh[a];
+      }
+    }
   }
   __syncthreads();
   constexpr int VW = 16 / sizeof(R);   // values per 16-byte store
@@ -673,7 +703,7 @@ __global__ __launch_bounds__(NT) void k_spread_tab(GridGeom G, TileGeom T, const
   const long long Gs = G.G;
   if (G.tiled) {
     // tile-major field: the tile (all tiles full) is one contiguous block per component
-    for (int p = tid; p < 3 * TX * TX * NV; p += NT) {
+    for (int p = tid; p < 3 * TX * TX * NV; p += NTS) {
       const int cc = p / (TX * TX * NV), rem = p - cc * (TX * TX * NV);
       const int col = rem / NV, zv = (rem - col * NV) * VW;
       const R* srcv = sh + (cc * TX * TX + col) * TZP + zv;
@@ -686,7 +716,7 @@ __global__ __launch_bounds__(NT) void k_spread_tab(GridGeom G, TileGeom T, const
     }
     return;
   }
-  for (int p = tid; p < 3 * TX * TX * NV; p += NT) {
+  for (int p = tid; p < 3 * TX * TX * NV; p += NTS) {
     const int cc = p / (TX * TX * NV), rem = p - cc * (TX * TX * NV);
     const int col = rem / NV, zv = (rem - col * NV) * VW;
     const int c0 = col >> 3, c1 = col & 7;
@@ -725,7 +755,10 @@ __global__ void k_to_rowmajor(GridGeom G, const R* __restrict__ x, double* __res
   }
 }
 
-inline unsigned blocks_for(int M) { return (unsigned)((M + WAVES - 1) / WAVES); }
+inline unsigned blocks_for(int M) {
+  const unsigned nb = (unsigned)((M + WAVES - 1) / WAVES);
+  return (nb + NXCD - 1) / NXCD * NXCD;
+}
 
 }  // namespace
 
@@ -808,7 +841,7 @@ int spread(const GridGeom& g, const TileGeom& t, const void* tabs, const int* ta
     return GDC_EINVAL;
   }
   ProbeScope ps("spread", s);
-  hipLaunchKernelGGL((k_spread_tab<R>), dim3(t.ntiles), dim3(NT), 0, s, g, t, (const HitTab<R>*)tabs, tab_start,
+  hipLaunchKernelGGL((k_spread_tab<R>), dim3(t.ntiles), dim3(NTS), 0, s, g, t, (const HitTab<R>*)tabs, tab_start,
                      tab_count, lam, lam_sorted, f, skip);
   return check_launch("k_spread_tab");
 }
