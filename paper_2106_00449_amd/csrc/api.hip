@@ -442,7 +442,7 @@ int apply_mobility(gdc_handle* h, const double* r, const double* lam, double* ou
   R* f = (R*)h->grid[0];
   GDC_TRY(spread<R>(g, h->tg, h->tabs, h->tab_start, h->tab_count, lam, lam_sorted, f, h->stream, skip));
   GDC_TRY(stokes_solve<R>(g, tw_of<R>(h), f, (Cx<R>*)h->grid[1], (Cx<R>*)h->grid[2], h->stream, skip));
-  return interp<R>(g, r, f, out, h->M, g.dV, h->bt.blob_body, Y, V, h->stream, skip);
+  return interp<R>(g, r, f, out, h->M, g.dV, h->bt.blob_body, Y, V, h->stream, skip, h->trec);
 }
 
 // z = P^-1 x and y = A z, A = [[M, -K], [-K^T, -Pi]] at (Y, q, r).
@@ -682,8 +682,9 @@ int step_advance(gdc_handle* h, bool block, int& adv) {
       }
       GDC_TRY(blob_positions(h->bt, Ym, qm, h->rm, s));
       GDC_TRY(forces_at(h, Ym, h->rm));
-      GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_fl, h->v, h->M, h->geom.dV, nullptr, nullptr, nullptr, s));
       GDC_TRY(prepare_positions(h, h->rm));
+      GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_fl, h->v, h->M, h->geom.dV, nullptr, nullptr, nullptr, s,
+                        nullptr, h->trec));
       GDC_TRY(rhs_build(h->bt, qm, Ym, h->rm, h->v, h->F, h->cfg.forces.shear_rate, h->geom.L[1], h->rhs, s));
       GDC_TRY(solve_begin<R>(h, Ym, qm, h->rm));
       sr.phase = StepRun::SOLVE;

@@ -222,10 +222,12 @@ template <typename R>
 int spread(const GridGeom& g, const TileGeom& t, const void* tabs, const int* tab_start, const int* tab_count,
            const double* lam, const double* lam_sorted, R* f, hipStream_t s, const int* skip = nullptr);
 // v = scale J u, minus U_p + Omega_p x (r_i - Y_p) when V (N x 6) is given.
+// sorted, when given, is the record array of tile_sort for the same
+// positions r: blobs are then visited in the sorted order (same results).
 template <typename R>
 int interp(const GridGeom& g, const double* r, const R* u, double* v, int M, double scale,
            const int* blob_body, const double* Y, const double* V, hipStream_t s,
-           const int* skip = nullptr);
+           const int* skip = nullptr, const void* sorted = nullptr);
 // v (M x 3) and the NP differences J(r + dr_k) u - J(r) u into vd (M x NP x 3),
 // dr given per blob as M x NP x 3.
 template <typename R>

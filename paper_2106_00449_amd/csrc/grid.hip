@@ -100,6 +100,15 @@ __device__ __forceinline__ int wrap(int g, int n) {
 // the P1 x P2 cross-section and loops over a0, so consecutive lanes read
 // consecutive grid points along axis 2 and no division happens in the loop.
 
+// A blob's record in the tile-sorted order: the FP64 offsets and grid index
+// (10 bits per axis) of its first stencil point, as blob_base gives them, and
+// the blob index.
+struct SRec {
+  double e[3];
+  int g;
+  int blob;
+};
+
 // Rigid-body term subtracted by the averaging epilogue of the saddle operator:
 // U_p + Omega_p x (r_i - Y_p) for blob i of body p.
 struct RigidTerm {
@@ -108,15 +117,33 @@ struct RigidTerm {
   const double* V;        // N x 6 (U, Omega); null: no rigid term
 };
 
+// With rec (the tile-sorted records of the same positions), wave p takes the
+// blob at sorted place p, so that each XCD's run of blobs is a compact region
+// of the box and the stencils it reads stay in that XCD's L2; the arithmetic
+// of each blob is unchanged.
 template <typename R>
 __global__ __launch_bounds__(NT) void k_interp(GridGeom G, const double* __restrict__ r,
                                                const R* __restrict__ u, double* __restrict__ v, int M,
-                                               double scale, RigidTerm K, const int* __restrict__ skip) {
+                                               double scale, RigidTerm K, const int* __restrict__ skip,
+                                               const SRec* __restrict__ rec) {
   if (skip && *skip) return;
-  const int blob = xcd_block(gridDim.x) * WAVES + threadIdx.x / 64;
+  const int place = xcd_block(gridDim.x) * WAVES + threadIdx.x / 64;
   const int lane = threadIdx.x & 63;
-  if (blob >= M) return;
-  const BlobBase B = blob_base(G, r + 3LL * blob, 0);
+  if (place >= M) return;
+  int blob;
+  BlobBase B;
+  if (rec) {
+    const SRec x = rec[place];
+    blob = x.blob;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      B.e[d] = x.e[d];
+      B.g[d] = (x.g >> (10 * d)) & 1023;
+    }
+  } else {
+    blob = place;
+    B = blob_base(G, r + 3LL * blob, 0);
+  }
   const int P0 = G.P[0], P1 = G.P[1], P2 = G.P[2];
   const long long Gs = G.G;
   const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
@@ -320,12 +347,6 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const int* __restrict__ coun
 
 // Sorted blob record: offset of the first stencil point (FP64), its wrapped
 // grid index packed 10 bits per axis, and the blob's index.
-struct SRec {
-  double e[3];
-  int g;
-  int blob;
-};
-
 __global__ void k_tile_scatter(GridGeom G, const double* __restrict__ r, const int* __restrict__ tile, int M,
                                int* __restrict__ cursor, SRec* __restrict__ rec) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -848,11 +869,13 @@ int spread(const GridGeom& g, const TileGeom& t, const void* tabs, const int* ta
 
 template <typename R>
 int interp(const GridGeom& g, const double* r, const R* u, double* v, int M, double scale,
-           const int* blob_body, const double* Y, const double* V, hipStream_t s, const int* skip) {
+           const int* blob_body, const double* Y, const double* V, hipStream_t s, const int* skip,
+           const void* sorted) {
   if (M <= 0) return GDC_OK;
   RigidTerm K{blob_body, Y, V};
   ProbeScope ps("interp", s);
-  hipLaunchKernelGGL((k_interp<R>), dim3(blocks_for(M)), dim3(NT), 0, s, g, r, u, v, M, scale, K, skip);
+  hipLaunchKernelGGL((k_interp<R>), dim3(blocks_for(M)), dim3(NT), 0, s, g, r, u, v, M, scale, K, skip,
+                     (const SRec*)sorted);
   return check_launch("k_interp");
 }
 
@@ -883,9 +906,9 @@ template int spread<float>(const GridGeom&, const TileGeom&, const void*, const 
 template int spread<double>(const GridGeom&, const TileGeom&, const void*, const int*, const int*, const double*,
                             const double*, double*, hipStream_t, const int*);
 template int interp<float>(const GridGeom&, const double*, const float*, double*, int, double, const int*,
-                           const double*, const double*, hipStream_t, const int*);
+                           const double*, const double*, hipStream_t, const int*, const void*);
 template int interp<double>(const GridGeom&, const double*, const double*, double*, int, double, const int*,
-                            const double*, const double*, hipStream_t, const int*);
+                            const double*, const double*, hipStream_t, const int*, const void*);
 template int interp_fd<float>(const GridGeom&, const double*, const double*, int, const float*, double*,
                               double*, int, hipStream_t);
 template int interp_fd<double>(const GridGeom&, const double*, const double*, int, const double*, double*,
