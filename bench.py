@@ -54,6 +54,15 @@ BYTES_PER_BLOB = 56
 # for the current kernel.
 TRAFFIC_BYTES = None
 
+WORKLOAD_TEXT = {
+    "rods1000": "rods1000: 1,000 rods x 10 blobs (10,000 blobs), L=128a, grid 128^3, FP32 grid / FP64 bodies "
+                "and Krylov, harmonic pair repulsion 2.2a, dt=0.005",
+    "mixed4096": "mixed4096: 1,366 rods(10) + 1,365 boomerangs(15) + 1,365 tetrahedra(4) (39,595 blobs), "
+                 "L=256a, grid 256^3, FP32 grid / FP64 bodies, force e_z on every body, dt=0.005",
+    "rods32768": "rods32768: 32,768 rods x 10 blobs (327,680 blobs), L=384a, grid 384^3, axes within 15 deg "
+                 "of z, shear 0.1 + harmonic pair repulsion, FP32 grid / FP64 bodies, dt=0.005",
+}
+
 SERVING_BUDGET = 8 << 30
 SERVING_SLOTS = 16
 
@@ -169,10 +178,14 @@ def kernel_bandwidth(g, s, Y, q, w, cov):
     fams = {
         "spread": ("k_spread_tab", BYTES_PER_POINT * G + BYTES_PER_BLOB * w.M),
         "interp": ("k_interp", int(12 * cov * G) + 48 * w.M),
-        "fft_plane_fwd": ("k_plane_fwd", 24 * G),
-        "fft_project": ("k_axis0_plane", 24 * G),
-        "fft_plane_inv": ("k_plane_inv", 24 * G),
     }
+    if max(w.n) <= 128:   # three-pass plane transforms
+        fams.update({"fft_plane_fwd": ("k_plane_fwd", 24 * G), "fft_project": ("k_axis0_plane", 24 * G),
+                     "fft_plane_inv": ("k_plane_inv", 24 * G)})
+    else:                 # five-pass line transforms
+        fams.update({"fft_r2c": ("k_r2c_axis2", 24 * G), "fft_fwd1": ("k_fwd_axis1", 24 * G),
+                     "fft_project": ("k_axis0_project", 24 * G), "fft_inv1": ("k_inv_axis1", 24 * G),
+                     "fft_c2r": ("k_c2r_axis2", 24 * G)})
     out = {}
     for fam, (kname, nbytes) in fams.items():
         g.probe_kernel(fam)
@@ -283,6 +296,8 @@ def main():
                     help="use this GMRES tolerance instead of calibrating one (profiling runs)")
     ap.add_argument("--only-headline", action="store_true",
                     help="time the headline suspension only (no kernel table, FP64 path or serving)")
+    ap.add_argument("--workload", default="rods1000", choices=["rods1000", "mixed4096", "rods32768"],
+                    help="suspension to time (the headline figure is quoted on rods1000)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device copy first (counter calibration for profiling)")
     args = ap.parse_args()
@@ -295,7 +310,8 @@ def main():
     import workloads as wl
 
     # initial states first, in worker processes, before anything touches the GPU
-    w = wl.rods1000("fp32")
+    w = {"rods1000": lambda: wl.rods1000("fp32"), "mixed4096": wl.mixed4096,
+         "rods32768": wl.rods32768}[args.workload]()
     Y0, q0 = wl.initial_state(w)
     reqs, states = [], []
     if not (args.no_serving or args.only_headline):
@@ -353,8 +369,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": total * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "rods1000: 1,000 rods x 10 blobs (10,000 blobs), L=128a, grid 128^3, "
-                               "FP32 grid / FP64 bodies and Krylov, harmonic pair repulsion 2.2a, dt=0.005",
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "gmres_tol": tol, "mobility_rel_err": err,
                    "gmres_iterations_mean": float(np.mean(its)),
                    "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),

@@ -2,7 +2,8 @@
 // (Sec. 2.2).  Vectors are FP64 and live in one basis array V[(m+1) x ld].
 //
 // Each Arnoldi step orthogonalises by classical Gram-Schmidt with one
-// re-orthogonalisation in three launches over fixed chunks of the vectors:
+// re-orthogonalisation in three launches over fixed chunks of the vectors
+// (k_dot2d, k_axpy_dot, k_ortho_finish2):
 //   (1) partial sums of h1 = V^T w per chunk;
 //   (2) every block reduces those partials (fixed order), w -= V h1 on its
 //       chunk, and writes the chunk's partial sums of h2 = V^T w and w^T w;
@@ -118,26 +119,52 @@ __device__ __forceinline__ void reduce_rows(const double* __restrict__ partial, 
 }
 
 // w -= V h1 with h1 reduced from partial1 (k rows); block 0 stores h1.
-__global__ __launch_bounds__(NT) void k_axpy_partial(double* __restrict__ w, const double* __restrict__ V,
-                                                     long long ld, int k, const double* __restrict__ partial1,
-                                                     long long n, double* __restrict__ hout,
-                                                     const int* __restrict__ skip) {
+// Then, from the updated chunk, partial2[j * gridDim.x + c] = chunk sums of
+// V_j . w (j < k) and w . w (row k), each reduced within waves by shuffles
+// and across the block's waves in a fixed order.
+__global__ __launch_bounds__(NT) void k_axpy_dot(double* __restrict__ w, const double* __restrict__ V,
+                                                 long long ld, int k, const double* __restrict__ partial1,
+                                                 long long n, double* __restrict__ hout,
+                                                 double* __restrict__ partial2, const int* __restrict__ skip) {
   if (skip && *skip) return;
   __shared__ double hs[MAXK];
+  __shared__ double wp[MAXK][NT / 64];
   reduce_rows(partial1, k, gridDim.x, hs);
   __syncthreads();
   if (blockIdx.x == 0)
     for (int j = threadIdx.x; j < k; j += NT) hout[j] = hs[j];
   const long long lo = (long long)blockIdx.x * CHUNK;
+  double xw[CHUNK / NT];
 #pragma unroll
   for (int m = 0; m < CHUNK / NT; ++m) {
     const long long e = lo + threadIdx.x + m * NT;
+    double x = 0.0;
     if (e < n) {
-      double x = w[e];
+      x = w[e];
 #pragma unroll 8
       for (int j = 0; j < k; ++j) x -= hs[j] * V[ld * j + e];
       w[e] = x;
     }
+    xw[m] = x;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = 0; j <= k; ++j) {
+    double a = 0.0;
+#pragma unroll
+    for (int m = 0; m < CHUNK / NT; ++m) {
+      const long long e = lo + threadIdx.x + m * NT;
+      const double vj = j < k ? (e < n ? V[ld * j + e] : 0.0) : xw[m];
+      a += vj * xw[m];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if (lane == 0) wp[j][wave] = a;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j <= k; j += NT) {
+    double t = 0.0;
+    for (int q = 0; q < NT / 64; ++q) t += wp[j][q];
+    partial2[(long long)j * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -441,10 +468,8 @@ int arnoldi_orthogonalise(double* w, const double* V, long long ld, int k, long 
   }
   hipLaunchKernelGGL(k_dot2d, dim3(nchunk, k), dim3(NT), 0, s, V, ld, k, (const double*)w, n, partial1, skip);
   GDC_TRY(check_launch("k_dot2d"));
-  hipLaunchKernelGGL(k_axpy_partial, dim3(nchunk), dim3(NT), 0, s, w, V, ld, k, partial1, n, h1, skip);
-  GDC_TRY(check_launch("k_axpy_partial"));
-  hipLaunchKernelGGL(k_dot2d, dim3(nchunk, k + 1), dim3(NT), 0, s, V, ld, k, (const double*)w, n, partial2, skip);
-  GDC_TRY(check_launch("k_dot2d"));
+  hipLaunchKernelGGL(k_axpy_dot, dim3(nchunk), dim3(NT), 0, s, w, V, ld, k, partial1, n, h1, partial2, skip);
+  GDC_TRY(check_launch("k_axpy_dot"));
   if (st && (k > m || m > GM_MAXR)) {
     set_error("arnoldi_orthogonalise: column out of range");
     return GDC_EINVAL;
