@@ -248,13 +248,14 @@ __device__ void gm_column_block(GmresState* st, int k, int m, const double* __re
   }
 }
 
-// out = (w - V h2) / sqrt(s - |h2|^2) with (h2, s) reduced from partial2.
-// Block 0 stores h2 and s in hout and, when st is given and its cycle is
-// not over, updates Hessenberg column k - 1 from h1 and h2 and writes the
-// status to hstat (pinned host memory; visible to the host once the kernel
-// has completed).  No skip flag: block 0 reads `done` before it may set it,
-// and an iteration past the end of a cycle only writes a basis vector that
-// is never used.
+// out = (w - V h2) / sqrt(s - |h2|^2) with (h2, s) reduced from partial2,
+// by blocks 0 .. nchunk - 1.  The extra last block (nchunk) stores h2 and s
+// in hout and, when st is given and its cycle is not over, updates
+// Hessenberg column k - 1 from h1 and h2 and writes the status to hstat
+// (pinned host memory; visible to the host once the kernel has completed),
+// in parallel with the chunk work.  No skip flag: the last block reads
+// `done` before it may set it, and an iteration past the end of a cycle only
+// writes a basis vector that is never used.
 __global__ __launch_bounds__(NT) void k_ortho_finish2(const double* __restrict__ w, const double* __restrict__ V,
                                                       long long ld, int k, const double* __restrict__ partial2,
                                                       long long n, double* __restrict__ out, double* __restrict__ hout,
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(NT) void k_ortho_finish2(const double* __restrict__
                                                       unsigned char* hstat) {
   __shared__ double hs[MAXK];
   __shared__ double scale;
-  reduce_rows(partial2, k + 1, gridDim.x, hs);
+  reduce_rows(partial2, k + 1, gridDim.x - 1, hs);
   __syncthreads();
   if (threadIdx.x == 0) {
     double hh = 0.0;
@@ -270,9 +271,11 @@ __global__ __launch_bounds__(NT) void k_ortho_finish2(const double* __restrict__
     const double nrm2 = hs[k] - hh;
     scale = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
   }
-  if (blockIdx.x == 0) {
+  const int nchunk = gridDim.x - 1;
+  if (blockIdx.x == nchunk) {
     for (int j = threadIdx.x; j <= k; j += NT) hout[j] = hs[j];
     if (st) gm_column_block(st, k - 1, m, h1, hs, hstat);
+    return;
   }
   __syncthreads();
   const double a = scale;
@@ -474,7 +477,7 @@ int arnoldi_orthogonalise(double* w, const double* V, long long ld, int k, long 
     set_error("arnoldi_orthogonalise: column out of range");
     return GDC_EINVAL;
   }
-  hipLaunchKernelGGL(k_ortho_finish2, dim3(nchunk), dim3(NT), 0, s, w, V, ld, k, partial2, n, out, h2s, st, m,
+  hipLaunchKernelGGL(k_ortho_finish2, dim3(nchunk + 1), dim3(NT), 0, s, w, V, ld, k, partial2, n, out, h2s, st, m,
                      (const double*)h1, hstat);
   return check_launch("k_ortho_finish2");
 }
