@@ -39,6 +39,9 @@ struct Tiles {
   // transposed accesses) and per component in pass C.
   static constexpr int TL = sizeof(R) == 4 ? 16 : 8;
   static constexpr int TC = sizeof(R) == 4 ? 4 : 2;
+  // Threads of an axis-1 pass workgroup (measured: 512 beats 256 for FP32;
+  // FP64 needs more registers per thread and keeps 256).
+  static constexpr int NTH = sizeof(R) == 4 ? 512 : 256;
 };
 
 constexpr int next_radix(int n) {
@@ -231,7 +234,7 @@ __global__ __launch_bounds__(NT) void k_r2c_axis2(const R* __restrict__ in, Cx<R
   const int tid = threadIdx.x;
   const int c = blockIdx.z, i0 = blockIdx.y, i1b = blockIdx.x * TL;
   const int nl = min(TL, n1 - i1b);
-  load_twiddles<R, N2>(tw, twg);
+  load_twiddles<R, N2, NT>(tw, twg);
   const R* src = in + (long long)c * n0 * n1 * N2 + field_plane_off(tiled, n1, N2, i0);
   for (int e = tid; e < NLc * N2; e += NT) {
     const int p = e / N2, x = e - p * N2;
@@ -240,7 +243,7 @@ __global__ __launch_bounds__(NT) void k_r2c_axis2(const R* __restrict__ in, Cx<R
     buf[p * LS + x] = Cx<R>{re, im};
   }
   __syncthreads();
-  fft_lines<R, N2, NLc, LS, false>(buf, tw);
+  fft_lines<R, N2, NLc, LS, false, NT>(buf, tw);
   Cx<R>* dst = X + ((long long)c * n0 + i0) * H * n1 + i1b;
   for (int e = tid; e < H * TL; e += NT) {
     const int k = e / TL, t = e - k * TL;
@@ -260,7 +263,7 @@ __global__ __launch_bounds__(NT) void k_r2c_axis2(const R* __restrict__ in, Cx<R
 
 // ------------------------------------------------------------ pass B: FFT, axis 1
 template <typename R, int N1>
-__global__ __launch_bounds__(NT) void k_fwd_axis1(const Cx<R>* __restrict__ X, Cx<R>* __restrict__ Y,
+__global__ __launch_bounds__(Tiles<R>::NTH) void k_fwd_axis1(const Cx<R>* __restrict__ X, Cx<R>* __restrict__ Y,
                                                   const Cx<R>* __restrict__ twg, int n0, int H,
                                                   const int* __restrict__ skip) {
   if (skip && *skip) return;
@@ -270,14 +273,14 @@ __global__ __launch_bounds__(NT) void k_fwd_axis1(const Cx<R>* __restrict__ X, C
   const int tid = threadIdx.x;
   const int c = blockIdx.z, k2 = blockIdx.y, i0b = blockIdx.x * TL;
   const int nl = min(TL, n0 - i0b);
-  load_twiddles<R, N1>(tw, twg);
-  for (int e = tid; e < TL * N1; e += NT) {
+  load_twiddles<R, N1, Tiles<R>::NTH>(tw, twg);
+  for (int e = tid; e < TL * N1; e += Tiles<R>::NTH) {
     const int t = e / N1, x = e - t * N1;
     buf[t * LS + x] = (t < nl) ? X[(((long long)c * n0 + i0b + t) * H + k2) * N1 + x] : Cx<R>{R(0), R(0)};
   }
   __syncthreads();
-  fft_lines<R, N1, TL, LS, false>(buf, tw);
-  for (int e = tid; e < N1 * TL; e += NT) {
+  fft_lines<R, N1, TL, LS, false, Tiles<R>::NTH>(buf, tw);
+  for (int e = tid; e < N1 * TL; e += Tiles<R>::NTH) {
     const int k1 = e / TL, t = e - k1 * TL;
     if (t < nl) Y[(((long long)c * H + k2) * N1 + k1) * n0 + i0b + t] = buf[t * LS + k1];
   }
@@ -285,7 +288,7 @@ __global__ __launch_bounds__(NT) void k_fwd_axis1(const Cx<R>* __restrict__ X, C
 
 // ------------------------------------------------------------ pass B': iFFT, axis 1
 template <typename R, int N1>
-__global__ __launch_bounds__(NT) void k_inv_axis1(const Cx<R>* __restrict__ Y, Cx<R>* __restrict__ X,
+__global__ __launch_bounds__(Tiles<R>::NTH) void k_inv_axis1(const Cx<R>* __restrict__ Y, Cx<R>* __restrict__ X,
                                                   const Cx<R>* __restrict__ twg, int n0, int H,
                                                   const int* __restrict__ skip) {
   if (skip && *skip) return;
@@ -295,14 +298,14 @@ __global__ __launch_bounds__(NT) void k_inv_axis1(const Cx<R>* __restrict__ Y, C
   const int tid = threadIdx.x;
   const int c = blockIdx.z, k2 = blockIdx.y, i0b = blockIdx.x * TL;
   const int nl = min(TL, n0 - i0b);
-  load_twiddles<R, N1>(tw, twg);
-  for (int e = tid; e < N1 * TL; e += NT) {
+  load_twiddles<R, N1, Tiles<R>::NTH>(tw, twg);
+  for (int e = tid; e < N1 * TL; e += Tiles<R>::NTH) {
     const int k1 = e / TL, t = e - k1 * TL;
     buf[t * LS + k1] = (t < nl) ? Y[(((long long)c * H + k2) * N1 + k1) * n0 + i0b + t] : Cx<R>{R(0), R(0)};
   }
   __syncthreads();
-  fft_lines<R, N1, TL, LS, true>(buf, tw);
-  for (int e = tid; e < TL * N1; e += NT) {
+  fft_lines<R, N1, TL, LS, true, Tiles<R>::NTH>(buf, tw);
+  for (int e = tid; e < TL * N1; e += Tiles<R>::NTH) {
     const int t = e / N1, x = e - t * N1;
     if (t < nl) X[(((long long)c * n0 + i0b + t) * H + k2) * N1 + x] = buf[t * LS + x];
   }
@@ -323,7 +326,7 @@ __global__ __launch_bounds__(NT) void k_c2r_axis2(const Cx<R>* __restrict__ X, R
   const int tid = threadIdx.x;
   const int c = blockIdx.z, i0 = blockIdx.y, i1b = blockIdx.x * TL;
   const int nl = min(TL, n1 - i1b);
-  load_twiddles<R, N2>(tw, twg);
+  load_twiddles<R, N2, NT>(tw, twg);
   const Cx<R>* src = X + ((long long)c * n0 + i0) * H * n1 + i1b;
   const Cx<R> zero{R(0), R(0)};
   for (int e = tid; e < H * NLc; e += NT) {
@@ -339,7 +342,7 @@ __global__ __launch_bounds__(NT) void k_c2r_axis2(const Cx<R>* __restrict__ X, R
     }
   }
   __syncthreads();
-  fft_lines<R, N2, NLc, LS, true>(buf, tw);
+  fft_lines<R, N2, NLc, LS, true, NT>(buf, tw);
   R* dst = out + (long long)c * n0 * n1 * N2 + field_plane_off(tiled, n1, N2, i0);
   for (int e = tid; e < NLc * N2; e += NT) {
     const int p = e / N2, x = e - p * N2;
@@ -434,7 +437,7 @@ __global__ __launch_bounds__(NT) void k_axis0_project(Cx<R>* __restrict__ Y, con
   const int k2 = blockIdx.y, k1b = blockIdx.x * TC;
   const int nl = min(TC, P.n1 - k1b);
   const int H = P.n2h, n1 = P.n1;
-  load_twiddles<R, N0>(tw, twg);
+  load_twiddles<R, N0, NT>(tw, twg);
   if (!NOISE) {
     for (int e = tid; e < NLn * N0; e += NT) {
       const int l = e / N0, x = e - l * N0;
@@ -442,7 +445,7 @@ __global__ __launch_bounds__(NT) void k_axis0_project(Cx<R>* __restrict__ Y, con
       buf[l * LS + x] = (t < nl) ? Y[(((long long)c * H + k2) * n1 + k1b + t) * N0 + x] : Cx<R>{R(0), R(0)};
     }
     __syncthreads();
-    fft_lines<R, N0, NLn, LS, false>(buf, tw);
+    fft_lines<R, N0, NLn, LS, false, NT>(buf, tw);
   } else {
     __syncthreads();
   }
@@ -479,7 +482,7 @@ __global__ __launch_bounds__(NT) void k_axis0_project(Cx<R>* __restrict__ Y, con
     for (int a = 0; a < 3; ++a) buf[(a * TC + t) * LS + j0] = u[a];
   }
   __syncthreads();
-  fft_lines<R, N0, NLn, LS, true>(buf, tw);
+  fft_lines<R, N0, NLn, LS, true, NT>(buf, tw);
   for (int e = tid; e < NLn * N0; e += NT) {
     const int l = e / N0, x = e - l * N0;
     const int c = l / TC, t = l - c * TC;
@@ -631,9 +634,10 @@ __global__ __launch_bounds__(NTP) void k_plane_inv(const Cx<R>* __restrict__ Z, 
 // Pass C on the plane layout Z[c][i0][k2][k1]: TCP consecutive k1 lines of
 // each component per workgroup.
 constexpr int TCP = 16;
+constexpr int NTA = 512;   // threads of a pass-C workgroup (two per CU)
 
 template <typename R, int N0, bool NOISE>
-__global__ __launch_bounds__(NT) void k_axis0_plane(Cx<R>* __restrict__ Z, const Cx<R>* __restrict__ twg,
+__global__ __launch_bounds__(NTA) void k_axis0_plane(Cx<R>* __restrict__ Z, const Cx<R>* __restrict__ twg,
                                                     ProjParams P, const int* __restrict__ skip) {
   if (skip && *skip) return;
   constexpr int NLn = 3 * TCP, LS = N0 + 1;
@@ -643,20 +647,20 @@ __global__ __launch_bounds__(NT) void k_axis0_plane(Cx<R>* __restrict__ Z, const
   const int k2 = blockIdx.y, k1b = blockIdx.x * TCP;
   const int nl = min(TCP, P.n1 - k1b);
   const int H = P.n2h, n1 = P.n1;
-  load_twiddles<R, N0>(tw, twg);
+  load_twiddles<R, N0, NTA>(tw, twg);
   if (!NOISE) {
-    for (int e = tid; e < NLn * N0; e += NT) {
+    for (int e = tid; e < NLn * N0; e += NTA) {
       const int t = e % TCP, rest = e / TCP;
       const int x = rest % N0, c = rest / N0;
       buf[(c * TCP + t) * LS + x] =
           (t < nl) ? Z[(((long long)c * N0 + x) * H + k2) * n1 + k1b + t] : Cx<R>{R(0), R(0)};
     }
     __syncthreads();
-    fft_lines<R, N0, NLn, LS, false>(buf, tw);
+    fft_lines<R, N0, NLn, LS, false, NTA>(buf, tw);
   } else {
     __syncthreads();
   }
-  for (int e = tid; e < TCP * N0; e += NT) {
+  for (int e = tid; e < TCP * N0; e += NTA) {
     const int t = e / N0, j0 = e - t * N0;
     const int j1 = k1b + t;
     Cx<R> u[3] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
@@ -689,8 +693,8 @@ __global__ __launch_bounds__(NT) void k_axis0_plane(Cx<R>* __restrict__ Z, const
     for (int a = 0; a < 3; ++a) buf[(a * TCP + t) * LS + j0] = u[a];
   }
   __syncthreads();
-  fft_lines<R, N0, NLn, LS, true>(buf, tw);
-  for (int e = tid; e < NLn * N0; e += NT) {
+  fft_lines<R, N0, NLn, LS, true, NTA>(buf, tw);
+  for (int e = tid; e < NLn * N0; e += NTA) {
     const int t = e % TCP, rest = e / TCP;
     const int x = rest % N0, c = rest / N0;
     if (t < nl) Z[(((long long)c * N0 + x) * H + k2) * n1 + k1b + t] = buf[(c * TCP + t) * LS + x];
@@ -720,7 +724,7 @@ int launch_fwd1(int n1, const Cx<R>* X, Cx<R>* Y, const Cx<R>* tw, int n0, int H
   dim3 grid((n0 + Tiles<R>::TL - 1) / Tiles<R>::TL, H, 3);
   ProbeScope ps("fft_fwd1", s);
   switch (n1) {
-#define X_(N) case N: hipLaunchKernelGGL((k_fwd_axis1<R, N>), grid, dim3(NT), 0, s, X, Y, tw, n0, H, skip); break;
+#define X_(N) case N: hipLaunchKernelGGL((k_fwd_axis1<R, N>), grid, dim3(Tiles<R>::NTH), 0, s, X, Y, tw, n0, H, skip); break;
     GDC_FFT_SIZES(X_)
 #undef X_
     default: set_error("unsupported grid size"); return GDC_EINVAL;
@@ -733,7 +737,7 @@ int launch_inv1(int n1, const Cx<R>* Y, Cx<R>* X, const Cx<R>* tw, int n0, int H
   dim3 grid((n0 + Tiles<R>::TL - 1) / Tiles<R>::TL, H, 3);
   ProbeScope ps("fft_inv1", s);
   switch (n1) {
-#define X_(N) case N: hipLaunchKernelGGL((k_inv_axis1<R, N>), grid, dim3(NT), 0, s, Y, X, tw, n0, H, skip); break;
+#define X_(N) case N: hipLaunchKernelGGL((k_inv_axis1<R, N>), grid, dim3(Tiles<R>::NTH), 0, s, Y, X, tw, n0, H, skip); break;
     GDC_FFT_SIZES(X_)
 #undef X_
     default: set_error("unsupported grid size"); return GDC_EINVAL;
@@ -823,7 +827,7 @@ int launch_proj_plane(int n0, Cx<R>* Z, const Cx<R>* tw, const ProjParams& P, hi
     return GDC_EINVAL;
   } else {
     switch (n0) {
-#define X_(N) case N: hipLaunchKernelGGL((k_axis0_plane<R, N, NOISE>), grid, dim3(NT), 0, s, Z, tw, P, skip); break;
+#define X_(N) case N: hipLaunchKernelGGL((k_axis0_plane<R, N, NOISE>), grid, dim3(NTA), 0, s, Z, tw, P, skip); break;
       GDC_PLANE_SIZES(X_)
 #undef X_
       default: set_error("unsupported grid size"); return GDC_EINVAL;
