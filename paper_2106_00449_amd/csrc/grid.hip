@@ -5,7 +5,7 @@
 // beyond the cutoff radius rc (minimum-image distance, no renormalisation), so
 // J = dV S^T exactly.  Averaging: one 64-wide wavefront per blob walks the
 // blob's stencil.  Spreading: one workgroup per grid tile gathers the blobs
-// that reach it (k_spread_sep).  Positions arrive in FP64; each blob's offset to
+// that reach it (k_spread_tab).  Positions arrive in FP64; each blob's offset to
 // the first stencil point is formed in FP64 before any rounding to the grid
 // precision, so an FP32 grid does not lose the position to the box size.
 //
