@@ -221,3 +221,33 @@ def em_step(cfg: Config, Y, q, step, tol=1e-12, dense=None):
     ufl = fluct_field(cfg, step)
     V, info = corrector_solve(cfg, Y, q, ufl, tol=tol, dense=dense)
     return Y + cfg.dt * V[:, :3], qmul(qexp(cfg.dt * V[:, 3:]), q), {"V": V, **info}
+
+
+def mobility_divergence(cfg: Config, Y, q, h=1e-4):
+    """kT-free drift of the overdamped dynamics: (d_x . N)_i = sum_j dN_ij/dx_j
+    over the 6N generalised coordinates (Sec. 3: the term the drift
+    correction captures, so that E[x^{n+1} - x^n] = dt (N F + kT d_x . N)
+    + O(dt^2)).  Translations perturb Y_p; rotations perturb q_p <-
+    exp(h e) q_p, the Lie-algebra coordinates reset to 0 at x^n.  Central
+    differences of the dense body mobility (small systems only)."""
+    b = cfg.susp.bodies
+    Y = np.asarray(Y, dtype=np.float64).reshape(-1, 3)
+    q = np.asarray(q, dtype=np.float64).reshape(-1, 4)
+
+    def N_at(Yx, qx):
+        return rigid.body_mobility(cfg.susp, Yx, rigid.blob_positions(b, Yx, qx))
+
+    div = np.zeros(6 * b.N)
+    for j in range(6 * b.N):
+        p, c = divmod(j, 6)
+        Yp, Ym, qp, qm = Y.copy(), Y.copy(), q.copy(), q.copy()
+        if c < 3:
+            Yp[p, c] += h
+            Ym[p, c] -= h
+        else:
+            e = np.zeros((1, 3))
+            e[0, c - 3] = h
+            qp[p] = qmul(qexp(e), q[p:p + 1])[0]
+            qm[p] = qmul(qexp(-e), q[p:p + 1])[0]
+        div += (N_at(Yp, qp)[:, j] - N_at(Ym, qm)[:, j]) / (2.0 * h)
+    return div

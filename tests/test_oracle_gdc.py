@@ -151,3 +151,43 @@ def test_rfd_mean_is_the_fd_divergence():
     assert np.all(np.abs(mean - d_fd) < 5.0 * se), (mean, d_fd, se)
     # the test resolves the divergence: it is many standard errors from 0
     assert np.all(np.abs(d_fd) > 5.0 * se), (d_fd, se)
+
+
+def _pair_cfg(shape, L=16.0, n=16):
+    return _cfg([shape], [0, 0], L=L, n=n)
+
+
+def test_mobility_divergence_pins():
+    # (a) one body in a periodic box on a fine grid (sigma/dx = 2.3, aliasing
+    # ~1e-40): N does not depend on the body's position, so the derivatives
+    # along translations vanish and the divergence is its rotational part
+    # alone (on the dx = a grids of the workloads the sampled envelope makes
+    # N vary with the sub-grid position at the 1e-3 level, so there they do
+    # not vanish); (b) second-order convergence in h; (c) swapping two
+    # bodies of the same shape swaps the blocks of the divergence.
+    one = _cfg([wl.tetrahedron()], [0], L=8.0, n=32)
+    Y1 = np.array([[4.13, 3.76, 4.21]])
+    q1 = np.array([[0.8, 0.2, -0.4, 0.4]]) / np.linalg.norm([0.8, 0.2, -0.4, 0.4])
+    d1 = gdc.mobility_divergence(one, Y1, q1)
+    N1 = rigid.body_mobility(one.susp, Y1, rigid.blob_positions(one.susp.bodies, Y1, q1))
+    rot = np.zeros(6)
+    for j in range(3, 6):
+        e = np.zeros((1, 3))
+        e[0, j - 3] = 1e-4
+        Np = rigid.body_mobility(one.susp, Y1, rigid.blob_positions(one.susp.bodies, Y1, qmul(qexp(e), q1)))
+        Nm = rigid.body_mobility(one.susp, Y1, rigid.blob_positions(one.susp.bodies, Y1, qmul(qexp(-e), q1)))
+        rot += (Np[:, j] - Nm[:, j]) / 2e-4
+    # (cut-off sphere crossings and round-off leave ~1e-6; the rotational
+    # terms are ~1e-2)
+    assert np.abs(d1 - rot).max() < 1e-5 * np.abs(N1).max()
+    assert np.abs(rot).max() > 1e-3 * np.abs(N1).max()
+    cfg = _pair_cfg(wl.rod(3))
+    Y = np.array([[6.5, 8.0, 8.3], [9.5, 8.4, 8.0]])
+    q = np.array([[0.9, 0.3, 0.2, 0.1], [0.7, -0.2, 0.5, 0.3]])
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    d_a = gdc.mobility_divergence(cfg, Y, q, h=1e-3)
+    d_b = gdc.mobility_divergence(cfg, Y, q, h=1e-4)
+    assert np.abs(d_a - d_b).max() < 1e-4 * np.abs(d_b).max()
+    assert np.abs(d_b).max() > 1e-2            # the pair has a drift to see
+    d_s = gdc.mobility_divergence(cfg, Y[::-1].copy(), q[::-1].copy(), h=1e-4)
+    assert np.abs(d_s - np.concatenate([d_b[6:], d_b[:6]])).max() < 1e-9 * np.abs(d_b).max()
