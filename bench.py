@@ -356,6 +356,7 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES,
                 "kernel": "k_spread_tab", "launches": k_launches, "avg_us": avg_s * 1e6,
                 "algorithmic_bytes": alg_bytes}
+    launch = s.launch_config
     cov = grid_coverage(w, Y0, q0)
     kernels, fp64 = {}, {}
     if not args.only_headline:
@@ -374,7 +375,8 @@ def main():
                    "gmres_tol": tol, "mobility_rel_err": err,
                    "gmres_iterations_mean": float(np.mean(its)),
                    "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
-                   "nu_mean": float(np.mean(nus)), "interp_grid_coverage": cov},
+                   "nu_mean": float(np.mean(nus)), "interp_grid_coverage": cov,
+                   "fft_workgroup_sizes": launch},
         "roofline": roofline,
         "kernels": kernels,
         "fp64_single": fp64,

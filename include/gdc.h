@@ -210,6 +210,18 @@ int gdc_step_log(gdc_handle* h, double* t_ms, int cap, int* count);
 int gdc_footprint(const gdc_config* cfg, size_t* bytes);
 int gdc_device_bytes(const gdc_handle* h, size_t* bytes);
 
+/* Workgroup sizes (threads) of the FFT passes of the handle's grid, in the
+ * order: three-pass path (plane forward, projection, plane inverse), then
+ * five-pass path (R2C, axis-1 forward, projection, axis-1 inverse, C2R):
+ * GDC_FFT_PASSES values.  gdc_init times every size of every pass on the
+ * handle's grid and keeps the fastest (cached per grid and precision for the
+ * process); gdc_set_launch_config overrides them (plane passes: 256, 512 or
+ * 1024; others: 256 or 512).  Every size gives the same results bit for bit.
+ * Errors: GDC_EINVAL (NULL, n < GDC_FFT_PASSES, a size not allowed). */
+enum { GDC_FFT_PASSES = 8 };
+int gdc_get_launch_config(const gdc_handle* h, int* threads, int n);
+int gdc_set_launch_config(gdc_handle* h, const int* threads, int n);
+
 /* Internal step counter (checkpoint / resume: with the same state and
  * counter a resumed run repeats an uninterrupted one exactly). */
 int gdc_get_step(const gdc_handle* h, uint64_t* step);

@@ -92,10 +92,13 @@ def _load():
     L.gdc_step_log.argtypes = [P, D, I, ctypes.POINTER(I)]
     L.gdc_footprint.argtypes = [ctypes.POINTER(_Config), ctypes.POINTER(ctypes.c_size_t)]
     L.gdc_device_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+    L.gdc_get_launch_config.argtypes = [P, ctypes.POINTER(I), I]
+    L.gdc_set_launch_config.argtypes = [P, ctypes.POINTER(I), I]
     for name in ["gdc_init", "gdc_mobility_apply", "gdc_step", "gdc_get_step", "gdc_set_step",
                  "gdc_fluct_velocity", "gdc_predictor", "gdc_philox_normals", "gdc_probe_kernel",
                  "gdc_probe_read", "gdc_set_state", "gdc_get_state", "gdc_batch_step", "gdc_step_log",
-                 "gdc_footprint", "gdc_device_bytes"]:
+                 "gdc_footprint", "gdc_device_bytes",
+                 "gdc_get_launch_config", "gdc_set_launch_config"]:
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -318,6 +321,22 @@ class Suspension:
         _check(lib.gdc_step_log(self._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cap,
                                 ctypes.byref(cnt)))
         return buf[:cnt.value].copy()
+
+    FFT_PASSES = ("plane_fwd", "proj_plane", "plane_inv", "r2c", "fwd1", "proj", "inv1", "c2r")
+
+    @property
+    def launch_config(self):
+        """Workgroup sizes of the FFT passes (dict), as tuned at set-up."""
+        buf = (ctypes.c_int * 8)()
+        _check(lib.gdc_get_launch_config(self._h, buf, 8))
+        return dict(zip(self.FFT_PASSES, list(buf)))
+
+    @launch_config.setter
+    def launch_config(self, cfg):
+        cur = self.launch_config
+        cur.update(cfg)
+        buf = (ctypes.c_int * 8)(*[int(cur[k]) for k in self.FFT_PASSES])
+        _check(lib.gdc_set_launch_config(self._h, buf, 8))
 
     @property
     def device_bytes(self):

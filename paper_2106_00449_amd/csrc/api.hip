@@ -1088,6 +1088,16 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
   }
   // the host vectors of the uploads above go out of scope on return
   if (!h->dry) GDC_HIP(hipStreamSynchronize(h->stream));
+  if (!h->dry) {
+    if (h->precision == GDC_FP64) {
+      GDC_TRY(fft_autotune<double>(h->geom, tw_of<double>(h), (double*)h->grid[0], (Cx<double>*)h->grid[1],
+                                   (Cx<double>*)h->grid[2], h->stream));
+    } else {
+      GDC_TRY(fft_autotune<float>(h->geom, tw_of<float>(h), (float*)h->grid[0], (Cx<float>*)h->grid[1],
+                                  (Cx<float>*)h->grid[2], h->stream));
+    }
+    GDC_HIP(hipStreamSynchronize(h->stream));
+  }
   return GDC_OK;
 }
 
@@ -1417,6 +1427,43 @@ int gdc_probe_read(double* total_ms, long long* launches) {
   *total_ms = tot;
   *launches = n;
   g_probe.used = 0;
+  return GDC_OK;
+}
+
+int gdc_get_launch_config(const gdc_handle* h, int* threads, int n) {
+  if (!h || !threads || n < GDC_FFT_PASSES) {
+    set_error("handle and GDC_FFT_PASSES outputs are required");
+    return GDC_EINVAL;
+  }
+  const FftShape& f = h->geom.fft;
+  const int v[GDC_FFT_PASSES] = {f.plane_fwd, f.proj_plane, f.plane_inv, f.r2c, f.fwd1, f.proj, f.inv1, f.c2r};
+  for (int k = 0; k < GDC_FFT_PASSES; ++k) threads[k] = v[k];
+  return GDC_OK;
+}
+
+int gdc_set_launch_config(gdc_handle* h, const int* threads, int n) {
+  if (!h || !threads || n < GDC_FFT_PASSES) {
+    set_error("handle and GDC_FFT_PASSES sizes are required");
+    return GDC_EINVAL;
+  }
+  GDC_TRY(require_idle(h));
+  for (int k = 0; k < GDC_FFT_PASSES; ++k) {
+    const int t = threads[k];
+    const bool plane = k == 0 || k == 2;
+    if (!(t == 256 || t == 512 || (plane && t == 1024))) {
+      set_error("FFT workgroup size " + std::to_string(t) + " not allowed for pass " + std::to_string(k));
+      return GDC_EINVAL;
+    }
+  }
+  FftShape& f = h->geom.fft;
+  f.plane_fwd = threads[0];
+  f.proj_plane = threads[1];
+  f.plane_inv = threads[2];
+  f.r2c = threads[3];
+  f.fwd1 = threads[4];
+  f.proj = threads[5];
+  f.inv1 = threads[6];
+  f.c2r = threads[7];
   return GDC_OK;
 }
 

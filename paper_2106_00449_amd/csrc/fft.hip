@@ -26,7 +26,16 @@
 #include "gdc_internal.h"
 #include "noise_dev.h"
 
+// No automatic multiply-add contraction in this file: every instantiation of
+// a pass (each workgroup size the autotuner may pick) then performs the same
+// roundings, and the transforms give the same bits whatever the launch shape.
+#pragma clang fp contract(off)
+
+#include <array>
 #include <cmath>
+#include <initializer_list>
+#include <map>
+#include <mutex>
 
 namespace gdc {
 namespace {
@@ -39,9 +48,6 @@ struct Tiles {
   // transposed accesses) and per component in pass C.
   static constexpr int TL = sizeof(R) == 4 ? 16 : 8;
   static constexpr int TC = sizeof(R) == 4 ? 4 : 2;
-  // Threads of an axis-1 pass workgroup (measured: 512 beats 256 for FP32;
-  // FP64 needs more registers per thread and keeps 256).
-  static constexpr int NTH = sizeof(R) == 4 ? 512 : 256;
 };
 
 constexpr int next_radix(int n) {
@@ -223,8 +229,8 @@ __device__ __forceinline__ void load_twiddles(Cx<R>* tw, const Cx<R>* __restrict
 // ------------------------------------------------------------ pass A: R2C, axis 2
 // Two real lines packed as one complex line z = a + i b; after the FFT,
 // A(k) = (Z(k) + conj Z(N-k))/2 and B(k) = (Z(k) - conj Z(N-k))/(2i).
-template <typename R, int N2>
-__global__ __launch_bounds__(NT) void k_r2c_axis2(const R* __restrict__ in, Cx<R>* __restrict__ X,
+template <typename R, int N2, int NTH>
+__global__ __launch_bounds__(NTH) void k_r2c_axis2(const R* __restrict__ in, Cx<R>* __restrict__ X,
                                                   const Cx<R>* __restrict__ twg, int n0, int n1, int tiled,
                                                   const int* __restrict__ skip) {
   if (skip && *skip) return;
@@ -234,18 +240,18 @@ __global__ __launch_bounds__(NT) void k_r2c_axis2(const R* __restrict__ in, Cx<R
   const int tid = threadIdx.x;
   const int c = blockIdx.z, i0 = blockIdx.y, i1b = blockIdx.x * TL;
   const int nl = min(TL, n1 - i1b);
-  load_twiddles<R, N2, NT>(tw, twg);
+  load_twiddles<R, N2, NTH>(tw, twg);
   const R* src = in + (long long)c * n0 * n1 * N2 + field_plane_off(tiled, n1, N2, i0);
-  for (int e = tid; e < NLc * N2; e += NT) {
+  for (int e = tid; e < NLc * N2; e += NTH) {
     const int p = e / N2, x = e - p * N2;
     const R re = (2 * p < nl) ? src[field_col_off(tiled, N2, i1b + 2 * p, x)] : R(0);
     const R im = (2 * p + 1 < nl) ? src[field_col_off(tiled, N2, i1b + 2 * p + 1, x)] : R(0);
     buf[p * LS + x] = Cx<R>{re, im};
   }
   __syncthreads();
-  fft_lines<R, N2, NLc, LS, false, NT>(buf, tw);
+  fft_lines<R, N2, NLc, LS, false, NTH>(buf, tw);
   Cx<R>* dst = X + ((long long)c * n0 + i0) * H * n1 + i1b;
-  for (int e = tid; e < H * TL; e += NT) {
+  for (int e = tid; e < H * TL; e += NTH) {
     const int k = e / TL, t = e - k * TL;
     if (t < nl) {
       const int p = t >> 1;
@@ -262,8 +268,8 @@ __global__ __launch_bounds__(NT) void k_r2c_axis2(const R* __restrict__ in, Cx<R
 }
 
 // ------------------------------------------------------------ pass B: FFT, axis 1
-template <typename R, int N1>
-__global__ __launch_bounds__(Tiles<R>::NTH) void k_fwd_axis1(const Cx<R>* __restrict__ X, Cx<R>* __restrict__ Y,
+template <typename R, int N1, int NTH>
+__global__ __launch_bounds__(NTH) void k_fwd_axis1(const Cx<R>* __restrict__ X, Cx<R>* __restrict__ Y,
                                                   const Cx<R>* __restrict__ twg, int n0, int H,
                                                   const int* __restrict__ skip) {
   if (skip && *skip) return;
@@ -273,22 +279,22 @@ __global__ __launch_bounds__(Tiles<R>::NTH) void k_fwd_axis1(const Cx<R>* __rest
   const int tid = threadIdx.x;
   const int c = blockIdx.z, k2 = blockIdx.y, i0b = blockIdx.x * TL;
   const int nl = min(TL, n0 - i0b);
-  load_twiddles<R, N1, Tiles<R>::NTH>(tw, twg);
-  for (int e = tid; e < TL * N1; e += Tiles<R>::NTH) {
+  load_twiddles<R, N1, NTH>(tw, twg);
+  for (int e = tid; e < TL * N1; e += NTH) {
     const int t = e / N1, x = e - t * N1;
     buf[t * LS + x] = (t < nl) ? X[(((long long)c * n0 + i0b + t) * H + k2) * N1 + x] : Cx<R>{R(0), R(0)};
   }
   __syncthreads();
-  fft_lines<R, N1, TL, LS, false, Tiles<R>::NTH>(buf, tw);
-  for (int e = tid; e < N1 * TL; e += Tiles<R>::NTH) {
+  fft_lines<R, N1, TL, LS, false, NTH>(buf, tw);
+  for (int e = tid; e < N1 * TL; e += NTH) {
     const int k1 = e / TL, t = e - k1 * TL;
     if (t < nl) Y[(((long long)c * H + k2) * N1 + k1) * n0 + i0b + t] = buf[t * LS + k1];
   }
 }
 
 // ------------------------------------------------------------ pass B': iFFT, axis 1
-template <typename R, int N1>
-__global__ __launch_bounds__(Tiles<R>::NTH) void k_inv_axis1(const Cx<R>* __restrict__ Y, Cx<R>* __restrict__ X,
+template <typename R, int N1, int NTH>
+__global__ __launch_bounds__(NTH) void k_inv_axis1(const Cx<R>* __restrict__ Y, Cx<R>* __restrict__ X,
                                                   const Cx<R>* __restrict__ twg, int n0, int H,
                                                   const int* __restrict__ skip) {
   if (skip && *skip) return;
@@ -298,14 +304,14 @@ __global__ __launch_bounds__(Tiles<R>::NTH) void k_inv_axis1(const Cx<R>* __rest
   const int tid = threadIdx.x;
   const int c = blockIdx.z, k2 = blockIdx.y, i0b = blockIdx.x * TL;
   const int nl = min(TL, n0 - i0b);
-  load_twiddles<R, N1, Tiles<R>::NTH>(tw, twg);
-  for (int e = tid; e < N1 * TL; e += Tiles<R>::NTH) {
+  load_twiddles<R, N1, NTH>(tw, twg);
+  for (int e = tid; e < N1 * TL; e += NTH) {
     const int k1 = e / TL, t = e - k1 * TL;
     buf[t * LS + k1] = (t < nl) ? Y[(((long long)c * H + k2) * N1 + k1) * n0 + i0b + t] : Cx<R>{R(0), R(0)};
   }
   __syncthreads();
-  fft_lines<R, N1, TL, LS, true, Tiles<R>::NTH>(buf, tw);
-  for (int e = tid; e < TL * N1; e += Tiles<R>::NTH) {
+  fft_lines<R, N1, TL, LS, true, NTH>(buf, tw);
+  for (int e = tid; e < TL * N1; e += NTH) {
     const int t = e / N1, x = e - t * N1;
     if (t < nl) X[(((long long)c * n0 + i0b + t) * H + k2) * N1 + x] = buf[t * LS + x];
   }
@@ -315,8 +321,8 @@ __global__ __launch_bounds__(Tiles<R>::NTH) void k_inv_axis1(const Cx<R>* __rest
 // Z(k) = A(k) + i B(k) with the Hermitian extension A(N-k) = conj A(k); the
 // k = 0 term keeps only real parts (as a real inverse transform does) and the
 // Nyquist term is zero.
-template <typename R, int N2>
-__global__ __launch_bounds__(NT) void k_c2r_axis2(const Cx<R>* __restrict__ X, R* __restrict__ out,
+template <typename R, int N2, int NTH>
+__global__ __launch_bounds__(NTH) void k_c2r_axis2(const Cx<R>* __restrict__ X, R* __restrict__ out,
                                                   const Cx<R>* __restrict__ twg, int n0, int n1, int tiled,
                                                   const int* __restrict__ skip) {
   if (skip && *skip) return;
@@ -326,10 +332,10 @@ __global__ __launch_bounds__(NT) void k_c2r_axis2(const Cx<R>* __restrict__ X, R
   const int tid = threadIdx.x;
   const int c = blockIdx.z, i0 = blockIdx.y, i1b = blockIdx.x * TL;
   const int nl = min(TL, n1 - i1b);
-  load_twiddles<R, N2, NT>(tw, twg);
+  load_twiddles<R, N2, NTH>(tw, twg);
   const Cx<R>* src = X + ((long long)c * n0 + i0) * H * n1 + i1b;
   const Cx<R> zero{R(0), R(0)};
-  for (int e = tid; e < H * NLc; e += NT) {
+  for (int e = tid; e < H * NLc; e += NTH) {
     const int k = e / NLc, p = e - k * NLc;
     const Cx<R> a = (2 * p < nl) ? src[(long long)k * n1 + 2 * p] : zero;
     const Cx<R> b = (2 * p + 1 < nl) ? src[(long long)k * n1 + 2 * p + 1] : zero;
@@ -342,9 +348,9 @@ __global__ __launch_bounds__(NT) void k_c2r_axis2(const Cx<R>* __restrict__ X, R
     }
   }
   __syncthreads();
-  fft_lines<R, N2, NLc, LS, true, NT>(buf, tw);
+  fft_lines<R, N2, NLc, LS, true, NTH>(buf, tw);
   R* dst = out + (long long)c * n0 * n1 * N2 + field_plane_off(tiled, n1, N2, i0);
-  for (int e = tid; e < NLc * N2; e += NT) {
+  for (int e = tid; e < NLc * N2; e += NTH) {
     const int p = e / N2, x = e - p * N2;
     const Cx<R> z = buf[p * LS + x];
     if (2 * p < nl) dst[field_col_off(tiled, N2, i1b + 2 * p, x)] = z.x;
@@ -426,8 +432,8 @@ __device__ bool noise_mode(const ProjParams& P, int j0, int j1, int j2, double u
   return true;
 }
 
-template <typename R, int N0, bool NOISE>
-__global__ __launch_bounds__(NT) void k_axis0_project(Cx<R>* __restrict__ Y, const Cx<R>* __restrict__ twg,
+template <typename R, int N0, bool NOISE, int NTH>
+__global__ __launch_bounds__(NTH) void k_axis0_project(Cx<R>* __restrict__ Y, const Cx<R>* __restrict__ twg,
                                                       ProjParams P, const int* __restrict__ skip) {
   if (skip && *skip) return;
   constexpr int TC = Tiles<R>::TC, NLn = 3 * TC, LS = N0 + 1;
@@ -437,19 +443,19 @@ __global__ __launch_bounds__(NT) void k_axis0_project(Cx<R>* __restrict__ Y, con
   const int k2 = blockIdx.y, k1b = blockIdx.x * TC;
   const int nl = min(TC, P.n1 - k1b);
   const int H = P.n2h, n1 = P.n1;
-  load_twiddles<R, N0, NT>(tw, twg);
+  load_twiddles<R, N0, NTH>(tw, twg);
   if (!NOISE) {
-    for (int e = tid; e < NLn * N0; e += NT) {
+    for (int e = tid; e < NLn * N0; e += NTH) {
       const int l = e / N0, x = e - l * N0;
       const int c = l / TC, t = l - c * TC;
       buf[l * LS + x] = (t < nl) ? Y[(((long long)c * H + k2) * n1 + k1b + t) * N0 + x] : Cx<R>{R(0), R(0)};
     }
     __syncthreads();
-    fft_lines<R, N0, NLn, LS, false, NT>(buf, tw);
+    fft_lines<R, N0, NLn, LS, false, NTH>(buf, tw);
   } else {
     __syncthreads();
   }
-  for (int e = tid; e < TC * N0; e += NT) {
+  for (int e = tid; e < TC * N0; e += NTH) {
     const int t = e / N0, j0 = e - t * N0;
     const int j1 = k1b + t;
     Cx<R> u[3] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
@@ -482,8 +488,8 @@ __global__ __launch_bounds__(NT) void k_axis0_project(Cx<R>* __restrict__ Y, con
     for (int a = 0; a < 3; ++a) buf[(a * TC + t) * LS + j0] = u[a];
   }
   __syncthreads();
-  fft_lines<R, N0, NLn, LS, true, NT>(buf, tw);
-  for (int e = tid; e < NLn * N0; e += NT) {
+  fft_lines<R, N0, NLn, LS, true, NTH>(buf, tw);
+  for (int e = tid; e < NLn * N0; e += NTH) {
     const int l = e / N0, x = e - l * N0;
     const int c = l / TC, t = l - c * TC;
     if (t < nl) Y[(((long long)c * H + k2) * n1 + k1b + t) * N0 + x] = buf[l * LS + x];
@@ -503,7 +509,6 @@ __global__ __launch_bounds__(NT) void k_axis0_project(Cx<R>* __restrict__ Y, con
 // P and P' read and write whole planes contiguously; pass C reads 16
 // consecutive k1 of each (c, i0, k2) line, one 128-byte segment.
 
-constexpr int NTP = 512;   // threads of a plane workgroup
 
 template <int N1, int N2>
 struct PlaneLds {
@@ -516,8 +521,8 @@ struct PlaneLds {
 // Two real rows (2p, 2p+1) of length N2 as one complex line; after its FFT
 // Z, row 2p has A(k) = (Z(k) + conj Z(N2-k))/2 and row 2p+1 has
 // B(k) = (Z(k) - conj Z(N2-k))/(2i), k < N2/2.  Then FFT along axis 1.
-template <typename R, int N1, int N2>
-__global__ __launch_bounds__(NTP) void k_plane_fwd(const R* __restrict__ in, Cx<R>* __restrict__ Z,
+template <typename R, int N1, int N2, int NTH>
+__global__ __launch_bounds__(NTH) void k_plane_fwd(const R* __restrict__ in, Cx<R>* __restrict__ Z,
                                                    const Cx<R>* __restrict__ tw1g, const Cx<R>* __restrict__ tw2g,
                                                    int n0, int tiled, const int* __restrict__ skip) {
   if (skip && *skip) return;
@@ -527,21 +532,21 @@ __global__ __launch_bounds__(NTP) void k_plane_fwd(const R* __restrict__ in, Cx<
   __shared__ Cx<R> tw1[N1], tw2[N2];
   const int tid = threadIdx.x;
   const int i0 = blockIdx.x, c = blockIdx.y;
-  load_twiddles<R, N1, NTP>(tw1, tw1g);
-  load_twiddles<R, N2, NTP>(tw2, tw2g);
+  load_twiddles<R, N1, NTH>(tw1, tw1g);
+  load_twiddles<R, N2, NTH>(tw2, tw2g);
   const R* src = in + (long long)c * n0 * N1 * N2 + field_plane_off(tiled, N1, N2, i0);
-  for (int e = tid; e < NP * N2; e += NTP) {
+  for (int e = tid; e < NP * N2; e += NTH) {
     const int p = e / N2, x = e - p * N2;
     buf[p * L::LA + x] = Cx<R>{src[field_col_off(tiled, N2, 2 * p, x)], src[field_col_off(tiled, N2, 2 * p + 1, x)]};
   }
   __syncthreads();
-  fft_lines<R, N2, NP, L::LA, false, NTP>(buf, tw2);
+  fft_lines<R, N2, NP, L::LA, false, NTH>(buf, tw2);
   // unpack into lines k2 (length N1, index i1)
-  constexpr int ITEMS = NP * H, PER = (ITEMS + NTP - 1) / NTP;
+  constexpr int ITEMS = NP * H, PER = (ITEMS + NTH - 1) / NTH;
   Cx<R> ra[PER], rb[PER];
 #pragma unroll
   for (int m = 0; m < PER; ++m) {
-    const int e = tid + m * NTP;
+    const int e = tid + m * NTH;
     if (e < ITEMS) {
       const int p = e / H, k = e - p * H;
       const Cx<R> z = buf[p * L::LA + k];
@@ -553,7 +558,7 @@ __global__ __launch_bounds__(NTP) void k_plane_fwd(const R* __restrict__ in, Cx<
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < PER; ++m) {
-    const int e = tid + m * NTP;
+    const int e = tid + m * NTH;
     if (e < ITEMS) {
       const int p = e / H, k = e - p * H;
       buf[k * L::LB + 2 * p] = ra[m];
@@ -561,9 +566,9 @@ __global__ __launch_bounds__(NTP) void k_plane_fwd(const R* __restrict__ in, Cx<
     }
   }
   __syncthreads();
-  fft_lines<R, N1, H, L::LB, false, NTP>(buf, tw1);
+  fft_lines<R, N1, H, L::LB, false, NTH>(buf, tw1);
   Cx<R>* dst = Z + ((long long)c * n0 + i0) * H * N1;
-  for (int e = tid; e < H * N1; e += NTP) {
+  for (int e = tid; e < H * N1; e += NTH) {
     const int k = e / N1, x = e - k * N1;
     dst[e] = buf[k * L::LB + x];
   }
@@ -572,8 +577,8 @@ __global__ __launch_bounds__(NTP) void k_plane_fwd(const R* __restrict__ in, Cx<
 // Inverse of k_plane_fwd: iFFT along axis 1, then rows (2p, 2p+1) rebuilt as
 // one complex line Z(k) = A(k) + i B(k) with the Hermitian extensions (the
 // k = 0 term keeps real parts, the Nyquist term is zero) and inverse FFT.
-template <typename R, int N1, int N2>
-__global__ __launch_bounds__(NTP) void k_plane_inv(const Cx<R>* __restrict__ Z, R* __restrict__ out,
+template <typename R, int N1, int N2, int NTH>
+__global__ __launch_bounds__(NTH) void k_plane_inv(const Cx<R>* __restrict__ Z, R* __restrict__ out,
                                                    const Cx<R>* __restrict__ tw1g, const Cx<R>* __restrict__ tw2g,
                                                    int n0, int tiled, const int* __restrict__ skip) {
   if (skip && *skip) return;
@@ -583,20 +588,20 @@ __global__ __launch_bounds__(NTP) void k_plane_inv(const Cx<R>* __restrict__ Z, 
   __shared__ Cx<R> tw1[N1], tw2[N2];
   const int tid = threadIdx.x;
   const int i0 = blockIdx.x, c = blockIdx.y;
-  load_twiddles<R, N1, NTP>(tw1, tw1g);
-  load_twiddles<R, N2, NTP>(tw2, tw2g);
+  load_twiddles<R, N1, NTH>(tw1, tw1g);
+  load_twiddles<R, N2, NTH>(tw2, tw2g);
   const Cx<R>* src = Z + ((long long)c * n0 + i0) * H * N1;
-  for (int e = tid; e < H * N1; e += NTP) {
+  for (int e = tid; e < H * N1; e += NTH) {
     const int k = e / N1, x = e - k * N1;
     buf[k * L::LB + x] = src[e];
   }
   __syncthreads();
-  fft_lines<R, N1, H, L::LB, true, NTP>(buf, tw1);
-  constexpr int ITEMS = NP * H, PER = (ITEMS + NTP - 1) / NTP;
+  fft_lines<R, N1, H, L::LB, true, NTH>(buf, tw1);
+  constexpr int ITEMS = NP * H, PER = (ITEMS + NTH - 1) / NTH;
   Cx<R> ra[PER], rb[PER];
 #pragma unroll
   for (int m = 0; m < PER; ++m) {
-    const int e = tid + m * NTP;
+    const int e = tid + m * NTH;
     if (e < ITEMS) {
       const int p = e / H, k = e - p * H;
       ra[m] = buf[k * L::LB + 2 * p];
@@ -607,7 +612,7 @@ __global__ __launch_bounds__(NTP) void k_plane_inv(const Cx<R>* __restrict__ Z, 
   const Cx<R> zero{R(0), R(0)};
 #pragma unroll
   for (int m = 0; m < PER; ++m) {
-    const int e = tid + m * NTP;
+    const int e = tid + m * NTH;
     if (e < ITEMS) {
       const int p = e / H, k = e - p * H;
       const Cx<R> a = ra[m], b = rb[m];
@@ -621,9 +626,9 @@ __global__ __launch_bounds__(NTP) void k_plane_inv(const Cx<R>* __restrict__ Z, 
     }
   }
   __syncthreads();
-  fft_lines<R, N2, NP, L::LA, true, NTP>(buf, tw2);
+  fft_lines<R, N2, NP, L::LA, true, NTH>(buf, tw2);
   R* dst = out + (long long)c * n0 * N1 * N2 + field_plane_off(tiled, N1, N2, i0);
-  for (int e = tid; e < NP * N2; e += NTP) {
+  for (int e = tid; e < NP * N2; e += NTH) {
     const int p = e / N2, x = e - p * N2;
     const Cx<R> z = buf[p * L::LA + x];
     dst[field_col_off(tiled, N2, 2 * p, x)] = z.x;
@@ -634,10 +639,9 @@ __global__ __launch_bounds__(NTP) void k_plane_inv(const Cx<R>* __restrict__ Z, 
 // Pass C on the plane layout Z[c][i0][k2][k1]: TCP consecutive k1 lines of
 // each component per workgroup.
 constexpr int TCP = 16;
-constexpr int NTA = 512;   // threads of a pass-C workgroup (two per CU)
 
-template <typename R, int N0, bool NOISE>
-__global__ __launch_bounds__(NTA) void k_axis0_plane(Cx<R>* __restrict__ Z, const Cx<R>* __restrict__ twg,
+template <typename R, int N0, bool NOISE, int NTH>
+__global__ __launch_bounds__(NTH) void k_axis0_plane(Cx<R>* __restrict__ Z, const Cx<R>* __restrict__ twg,
                                                     ProjParams P, const int* __restrict__ skip) {
   if (skip && *skip) return;
   constexpr int NLn = 3 * TCP, LS = N0 + 1;
@@ -647,20 +651,20 @@ __global__ __launch_bounds__(NTA) void k_axis0_plane(Cx<R>* __restrict__ Z, cons
   const int k2 = blockIdx.y, k1b = blockIdx.x * TCP;
   const int nl = min(TCP, P.n1 - k1b);
   const int H = P.n2h, n1 = P.n1;
-  load_twiddles<R, N0, NTA>(tw, twg);
+  load_twiddles<R, N0, NTH>(tw, twg);
   if (!NOISE) {
-    for (int e = tid; e < NLn * N0; e += NTA) {
+    for (int e = tid; e < NLn * N0; e += NTH) {
       const int t = e % TCP, rest = e / TCP;
       const int x = rest % N0, c = rest / N0;
       buf[(c * TCP + t) * LS + x] =
           (t < nl) ? Z[(((long long)c * N0 + x) * H + k2) * n1 + k1b + t] : Cx<R>{R(0), R(0)};
     }
     __syncthreads();
-    fft_lines<R, N0, NLn, LS, false, NTA>(buf, tw);
+    fft_lines<R, N0, NLn, LS, false, NTH>(buf, tw);
   } else {
     __syncthreads();
   }
-  for (int e = tid; e < TCP * N0; e += NTA) {
+  for (int e = tid; e < TCP * N0; e += NTH) {
     const int t = e / N0, j0 = e - t * N0;
     const int j1 = k1b + t;
     Cx<R> u[3] = {{R(0), R(0)}, {R(0), R(0)}, {R(0), R(0)}};
@@ -693,8 +697,8 @@ __global__ __launch_bounds__(NTA) void k_axis0_plane(Cx<R>* __restrict__ Z, cons
     for (int a = 0; a < 3; ++a) buf[(a * TCP + t) * LS + j0] = u[a];
   }
   __syncthreads();
-  fft_lines<R, N0, NLn, LS, true, NTA>(buf, tw);
-  for (int e = tid; e < NLn * N0; e += NTA) {
+  fft_lines<R, N0, NLn, LS, true, NTH>(buf, tw);
+  for (int e = tid; e < NLn * N0; e += NTH) {
     const int t = e % TCP, rest = e / TCP;
     const int x = rest % N0, c = rest / N0;
     if (t < nl) Z[(((long long)c * N0 + x) * H + k2) * n1 + k1b + t] = buf[(c * TCP + t) * LS + x];
@@ -705,70 +709,97 @@ __global__ __launch_bounds__(NTA) void k_axis0_plane(Cx<R>* __restrict__ Z, cons
 
 #define GDC_FFT_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
 
+// Every pass takes its workgroup size (threads) at run time from the grid's
+// FftShape; the instantiated sizes are 256 and 512 (and 1024 for the plane
+// passes).  The size only changes how the same line transforms are shared
+// out, so every choice gives the same results bit for bit.
+bool nth_ok(int nth, bool allow_1024) {
+  if (nth == 256 || nth == 512 || (allow_1024 && nth == 1024)) return true;
+  set_error("unsupported FFT workgroup size");
+  return false;
+}
+
 template <typename R>
-int launch_r2c(int n2, const R* in, Cx<R>* X, const Cx<R>* tw, int n0, int n1, int tiled, hipStream_t s,
+int launch_r2c(int n2, const R* in, Cx<R>* X, const Cx<R>* tw, int n0, int n1, int tiled, int nth, hipStream_t s,
                const int* skip) {
+  if (!nth_ok(nth, false)) return GDC_EINVAL;
   dim3 grid((n1 + Tiles<R>::TL - 1) / Tiles<R>::TL, n0, 3);
   ProbeScope ps("fft_r2c", s);
+#define L_(N, T) hipLaunchKernelGGL((k_r2c_axis2<R, N, T>), grid, dim3(T), 0, s, in, X, tw, n0, n1, tiled, skip)
   switch (n2) {
-#define X_(N) case N: hipLaunchKernelGGL((k_r2c_axis2<R, N>), grid, dim3(NT), 0, s, in, X, tw, n0, n1, tiled, skip); break;
+#define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
     GDC_FFT_SIZES(X_)
 #undef X_
     default: set_error("unsupported grid size"); return GDC_EINVAL;
   }
+#undef L_
   return check_launch("k_r2c_axis2");
 }
 
 template <typename R>
-int launch_fwd1(int n1, const Cx<R>* X, Cx<R>* Y, const Cx<R>* tw, int n0, int H, hipStream_t s, const int* skip) {
+int launch_fwd1(int n1, const Cx<R>* X, Cx<R>* Y, const Cx<R>* tw, int n0, int H, int nth, hipStream_t s,
+                const int* skip) {
+  if (!nth_ok(nth, false)) return GDC_EINVAL;
   dim3 grid((n0 + Tiles<R>::TL - 1) / Tiles<R>::TL, H, 3);
   ProbeScope ps("fft_fwd1", s);
+#define L_(N, T) hipLaunchKernelGGL((k_fwd_axis1<R, N, T>), grid, dim3(T), 0, s, X, Y, tw, n0, H, skip)
   switch (n1) {
-#define X_(N) case N: hipLaunchKernelGGL((k_fwd_axis1<R, N>), grid, dim3(Tiles<R>::NTH), 0, s, X, Y, tw, n0, H, skip); break;
+#define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
     GDC_FFT_SIZES(X_)
 #undef X_
     default: set_error("unsupported grid size"); return GDC_EINVAL;
   }
+#undef L_
   return check_launch("k_fwd_axis1");
 }
 
 template <typename R>
-int launch_inv1(int n1, const Cx<R>* Y, Cx<R>* X, const Cx<R>* tw, int n0, int H, hipStream_t s, const int* skip) {
+int launch_inv1(int n1, const Cx<R>* Y, Cx<R>* X, const Cx<R>* tw, int n0, int H, int nth, hipStream_t s,
+                const int* skip) {
+  if (!nth_ok(nth, false)) return GDC_EINVAL;
   dim3 grid((n0 + Tiles<R>::TL - 1) / Tiles<R>::TL, H, 3);
   ProbeScope ps("fft_inv1", s);
+#define L_(N, T) hipLaunchKernelGGL((k_inv_axis1<R, N, T>), grid, dim3(T), 0, s, Y, X, tw, n0, H, skip)
   switch (n1) {
-#define X_(N) case N: hipLaunchKernelGGL((k_inv_axis1<R, N>), grid, dim3(Tiles<R>::NTH), 0, s, Y, X, tw, n0, H, skip); break;
+#define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
     GDC_FFT_SIZES(X_)
 #undef X_
     default: set_error("unsupported grid size"); return GDC_EINVAL;
   }
+#undef L_
   return check_launch("k_inv_axis1");
 }
 
 template <typename R>
-int launch_c2r(int n2, const Cx<R>* X, R* out, const Cx<R>* tw, int n0, int n1, int tiled, hipStream_t s,
+int launch_c2r(int n2, const Cx<R>* X, R* out, const Cx<R>* tw, int n0, int n1, int tiled, int nth, hipStream_t s,
                const int* skip) {
+  if (!nth_ok(nth, false)) return GDC_EINVAL;
   dim3 grid((n1 + Tiles<R>::TL - 1) / Tiles<R>::TL, n0, 3);
   ProbeScope ps("fft_c2r", s);
+#define L_(N, T) hipLaunchKernelGGL((k_c2r_axis2<R, N, T>), grid, dim3(T), 0, s, X, out, tw, n0, n1, tiled, skip)
   switch (n2) {
-#define X_(N) case N: hipLaunchKernelGGL((k_c2r_axis2<R, N>), grid, dim3(NT), 0, s, X, out, tw, n0, n1, tiled, skip); break;
+#define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
     GDC_FFT_SIZES(X_)
 #undef X_
     default: set_error("unsupported grid size"); return GDC_EINVAL;
   }
+#undef L_
   return check_launch("k_c2r_axis2");
 }
 
 template <typename R, bool NOISE>
-int launch_proj(int n0, Cx<R>* Y, const Cx<R>* tw, const ProjParams& P, hipStream_t s, const int* skip) {
+int launch_proj(int n0, Cx<R>* Y, const Cx<R>* tw, const ProjParams& P, int nth, hipStream_t s, const int* skip) {
+  if (!nth_ok(nth, false)) return GDC_EINVAL;
   dim3 grid((P.n1 + Tiles<R>::TC - 1) / Tiles<R>::TC, P.n2h, 1);
   ProbeScope ps(NOISE ? "fft_noise" : "fft_project", s);
+#define L_(N, T) hipLaunchKernelGGL((k_axis0_project<R, N, NOISE, T>), grid, dim3(T), 0, s, Y, tw, P, skip)
   switch (n0) {
-#define X_(N) case N: hipLaunchKernelGGL((k_axis0_project<R, N, NOISE>), grid, dim3(NT), 0, s, Y, tw, P, skip); break;
+#define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
     GDC_FFT_SIZES(X_)
 #undef X_
     default: set_error("unsupported grid size"); return GDC_EINVAL;
   }
+#undef L_
   return check_launch("k_axis0_project");
 }
 
@@ -792,46 +823,55 @@ bool plane_path(const GridGeom& g) {
 
 template <typename R>
 int launch_plane(bool inverse, int n, const void* in, void* out, const Cx<R>* tw1, const Cx<R>* tw2, int n0,
-                 int tiled, hipStream_t s, const int* skip) {
+                 int tiled, int nth, hipStream_t s, const int* skip) {
+  if (!nth_ok(nth, true)) return GDC_EINVAL;
   dim3 grid(n0, 3);
   ProbeScope ps(inverse ? "fft_plane_inv" : "fft_plane_fwd", s);
   if constexpr (sizeof(R) != 4) {
     set_error("plane transforms are FP32 only");
     return GDC_EINVAL;
   } else {
-  if (!inverse) {
+    if (!inverse) {
+#define L_(N, T) hipLaunchKernelGGL((k_plane_fwd<R, N, N, T>), grid, dim3(T), 0, s, (const R*)in, (Cx<R>*)out, tw1, tw2, n0, tiled, skip)
+      switch (n) {
+#define X_(N) case N: if (nth == 1024) L_(N, 1024); else if (nth == 512) L_(N, 512); else L_(N, 256); break;
+        GDC_PLANE_SIZES(X_)
+#undef X_
+        default: set_error("unsupported plane size"); return GDC_EINVAL;
+      }
+#undef L_
+      return check_launch("k_plane_fwd");
+    }
+#define L_(N, T) hipLaunchKernelGGL((k_plane_inv<R, N, N, T>), grid, dim3(T), 0, s, (const Cx<R>*)in, (R*)out, tw1, tw2, n0, tiled, skip)
     switch (n) {
-#define X_(N) case N: hipLaunchKernelGGL((k_plane_fwd<R, N, N>), grid, dim3(NTP), 0, s, (const R*)in, (Cx<R>*)out, tw1, tw2, n0, tiled, skip); break;
+#define X_(N) case N: if (nth == 1024) L_(N, 1024); else if (nth == 512) L_(N, 512); else L_(N, 256); break;
       GDC_PLANE_SIZES(X_)
 #undef X_
       default: set_error("unsupported plane size"); return GDC_EINVAL;
     }
-    return check_launch("k_plane_fwd");
-  }
-  switch (n) {
-#define X_(N) case N: hipLaunchKernelGGL((k_plane_inv<R, N, N>), grid, dim3(NTP), 0, s, (const Cx<R>*)in, (R*)out, tw1, tw2, n0, tiled, skip); break;
-    GDC_PLANE_SIZES(X_)
-#undef X_
-    default: set_error("unsupported plane size"); return GDC_EINVAL;
-  }
-  return check_launch("k_plane_inv");
+#undef L_
+    return check_launch("k_plane_inv");
   }
 }
 
 template <typename R, bool NOISE>
-int launch_proj_plane(int n0, Cx<R>* Z, const Cx<R>* tw, const ProjParams& P, hipStream_t s, const int* skip) {
+int launch_proj_plane(int n0, Cx<R>* Z, const Cx<R>* tw, const ProjParams& P, int nth, hipStream_t s,
+                      const int* skip) {
+  if (!nth_ok(nth, false)) return GDC_EINVAL;
   dim3 grid((P.n1 + TCP - 1) / TCP, P.n2h, 1);
   ProbeScope ps(NOISE ? "fft_noise" : "fft_project", s);
   if constexpr (sizeof(R) != 4) {
     set_error("plane transforms are FP32 only");
     return GDC_EINVAL;
   } else {
+#define L_(N, T) hipLaunchKernelGGL((k_axis0_plane<R, N, NOISE, T>), grid, dim3(T), 0, s, Z, tw, P, skip)
     switch (n0) {
-#define X_(N) case N: hipLaunchKernelGGL((k_axis0_plane<R, N, NOISE>), grid, dim3(NTA), 0, s, Z, tw, P, skip); break;
+#define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
       GDC_PLANE_SIZES(X_)
 #undef X_
       default: set_error("unsupported grid size"); return GDC_EINVAL;
     }
+#undef L_
     return check_launch("k_axis0_plane");
   }
 }
@@ -865,16 +905,17 @@ template <typename R>
 int stokes_solve(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, Cx<R>* Y,
                  hipStream_t s, const int* skip) {
   const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], H = g.n2h;
+  const FftShape& f = g.fft;
   if (plane_path<R>(g)) {
-    GDC_TRY(launch_plane<R>(false, n1, real, X, tw[1], tw[2], n0, g.tiled, s, skip));
-    GDC_TRY((launch_proj_plane<R, false>(n0, X, tw[0], proj_params(g), s, skip)));
-    return launch_plane<R>(true, n1, X, real, tw[1], tw[2], n0, g.tiled, s, skip);
+    GDC_TRY(launch_plane<R>(false, n1, real, X, tw[1], tw[2], n0, g.tiled, f.plane_fwd, s, skip));
+    GDC_TRY((launch_proj_plane<R, false>(n0, X, tw[0], proj_params(g), f.proj_plane, s, skip)));
+    return launch_plane<R>(true, n1, X, real, tw[1], tw[2], n0, g.tiled, f.plane_inv, s, skip);
   }
-  GDC_TRY(launch_r2c<R>(n2, real, X, tw[2], n0, n1, g.tiled, s, skip));
-  GDC_TRY(launch_fwd1<R>(n1, X, Y, tw[1], n0, H, s, skip));
-  GDC_TRY((launch_proj<R, false>(n0, Y, tw[0], proj_params(g), s, skip)));
-  GDC_TRY(launch_inv1<R>(n1, Y, X, tw[1], n0, H, s, skip));
-  GDC_TRY(launch_c2r<R>(n2, X, real, tw[2], n0, n1, g.tiled, s, skip));
+  GDC_TRY(launch_r2c<R>(n2, real, X, tw[2], n0, n1, g.tiled, f.r2c, s, skip));
+  GDC_TRY(launch_fwd1<R>(n1, X, Y, tw[1], n0, H, f.fwd1, s, skip));
+  GDC_TRY((launch_proj<R, false>(n0, Y, tw[0], proj_params(g), f.proj, s, skip)));
+  GDC_TRY(launch_inv1<R>(n1, Y, X, tw[1], n0, H, f.inv1, s, skip));
+  GDC_TRY(launch_c2r<R>(n2, X, real, tw[2], n0, n1, g.tiled, f.c2r, s, skip));
   return GDC_OK;
 }
 
@@ -882,6 +923,7 @@ template <typename R>
 int fluct_field(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, Cx<R>* Y,
                 uint64_t seed, uint64_t step, double kT, double dt, hipStream_t s) {
   const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], H = g.n2h;
+  const FftShape& f = g.fft;
   ProjParams P = proj_params(g);
   P.seed = seed;
   P.step = step;
@@ -892,12 +934,97 @@ int fluct_field(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, 
   P.sdiag = std::sqrt((double)g.G * 4.0 * base / 2.0);
   P.soff = std::sqrt((double)g.G * 2.0 * base / 2.0);
   if (plane_path<R>(g)) {
-    GDC_TRY((launch_proj_plane<R, true>(n0, X, tw[0], P, s, nullptr)));
-    return launch_plane<R>(true, n1, X, real, tw[1], tw[2], n0, g.tiled, s, nullptr);
+    GDC_TRY((launch_proj_plane<R, true>(n0, X, tw[0], P, f.proj_plane, s, nullptr)));
+    return launch_plane<R>(true, n1, X, real, tw[1], tw[2], n0, g.tiled, f.plane_inv, s, nullptr);
   }
-  GDC_TRY((launch_proj<R, true>(n0, Y, tw[0], P, s, nullptr)));
-  GDC_TRY(launch_inv1<R>(n1, Y, X, tw[1], n0, H, s, nullptr));
-  GDC_TRY(launch_c2r<R>(n2, X, real, tw[2], n0, n1, g.tiled, s, nullptr));
+  GDC_TRY((launch_proj<R, true>(n0, Y, tw[0], P, f.proj, s, nullptr)));
+  GDC_TRY(launch_inv1<R>(n1, Y, X, tw[1], n0, H, f.inv1, s, nullptr));
+  GDC_TRY(launch_c2r<R>(n2, X, real, tw[2], n0, n1, g.tiled, f.c2r, s, nullptr));
+  return GDC_OK;
+}
+
+// Autotuner: for every pass of this grid's transform, time each workgroup
+// size (one warm-up launch, then the mean of three) on the handle's own
+// buffers and keep the fastest.  The buffers are zeroed first; the choice is
+// cached per (grid, precision) for the process.
+namespace {
+template <typename F>
+int time_launches(hipStream_t s, F launch, float& us) {
+  hipEvent_t a = nullptr, b = nullptr;
+  GDC_HIP(hipEventCreate(&a));
+  GDC_HIP(hipEventCreate(&b));
+  int rc = launch();
+  if (rc == GDC_OK && hipEventRecord(a, s) != hipSuccess) rc = GDC_EDEVICE;
+  for (int k = 0; k < 3 && rc == GDC_OK; ++k) rc = launch();
+  if (rc == GDC_OK && hipEventRecord(b, s) != hipSuccess) rc = GDC_EDEVICE;
+  float ms = 0.f;
+  if (rc == GDC_OK && (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess))
+    rc = GDC_EDEVICE;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc == GDC_EDEVICE) set_error("autotuner timing failed");
+  us = ms * 1e3f / 3.f;
+  return rc;
+}
+
+template <typename F>
+int pick(hipStream_t s, std::initializer_list<int> sizes, F launch_with, int& best) {
+  float best_us = 0.f;
+  best = 0;
+  for (int nth : sizes) {
+    float us = 0.f;
+    GDC_TRY(time_launches(s, [&] { return launch_with(nth); }, us));
+    if (best == 0 || us < best_us) {
+      best = nth;
+      best_us = us;
+    }
+  }
+  return GDC_OK;
+}
+
+std::mutex g_tune_mutex;
+std::map<std::array<int, 4>, FftShape> g_tuned;
+}  // namespace
+
+template <typename R>
+int fft_autotune(GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, Cx<R>* Y, hipStream_t s) {
+  const std::array<int, 4> key{g.n[0], g.n[1], g.n[2], (int)sizeof(R)};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mutex);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      g.fft = it->second;
+      return GDC_OK;
+    }
+  }
+  const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], H = g.n2h;
+  GDC_TRY(fill_zero(real, 3 * (size_t)g.G * sizeof(R), s));
+  GDC_TRY(fill_zero(X, 3 * (size_t)g.G * sizeof(R), s));
+  GDC_TRY(fill_zero(Y, 3 * (size_t)g.G * sizeof(R), s));
+  FftShape f = g.fft;
+  const ProjParams P = proj_params(g);
+  if (plane_path<R>(g)) {
+    GDC_TRY(pick(s, {256, 512, 1024}, [&](int t) {
+      return launch_plane<R>(false, n1, real, X, tw[1], tw[2], n0, g.tiled, t, s, nullptr); }, f.plane_fwd));
+    GDC_TRY(pick(s, {256, 512}, [&](int t) {
+      return launch_proj_plane<R, false>(n0, X, tw[0], P, t, s, nullptr); }, f.proj_plane));
+    GDC_TRY(pick(s, {256, 512, 1024}, [&](int t) {
+      return launch_plane<R>(true, n1, X, real, tw[1], tw[2], n0, g.tiled, t, s, nullptr); }, f.plane_inv));
+  } else {
+    GDC_TRY(pick(s, {256, 512}, [&](int t) {
+      return launch_r2c<R>(n2, real, X, tw[2], n0, n1, g.tiled, t, s, nullptr); }, f.r2c));
+    GDC_TRY(pick(s, {256, 512}, [&](int t) { return launch_fwd1<R>(n1, X, Y, tw[1], n0, H, t, s, nullptr); },
+                 f.fwd1));
+    GDC_TRY(pick(s, {256, 512}, [&](int t) {
+      return launch_proj<R, false>(n0, Y, tw[0], P, t, s, nullptr); }, f.proj));
+    GDC_TRY(pick(s, {256, 512}, [&](int t) { return launch_inv1<R>(n1, Y, X, tw[1], n0, H, t, s, nullptr); },
+                 f.inv1));
+    GDC_TRY(pick(s, {256, 512}, [&](int t) {
+      return launch_c2r<R>(n2, X, real, tw[2], n0, n1, g.tiled, t, s, nullptr); }, f.c2r));
+  }
+  g.fft = f;
+  std::lock_guard<std::mutex> lk(g_tune_mutex);
+  g_tuned[key] = f;
   return GDC_OK;
 }
 
@@ -917,5 +1044,9 @@ template int fluct_field<float>(const GridGeom&, const Cx<float>* const[3], floa
                                 Cx<float>*, uint64_t, uint64_t, double, double, hipStream_t);
 template int fluct_field<double>(const GridGeom&, const Cx<double>* const[3], double*, Cx<double>*,
                                  Cx<double>*, uint64_t, uint64_t, double, double, hipStream_t);
+template int fft_autotune<float>(GridGeom&, const Cx<float>* const[3], float*, Cx<float>*, Cx<float>*,
+                                 hipStream_t);
+template int fft_autotune<double>(GridGeom&, const Cx<double>* const[3], double*, Cx<double>*, Cx<double>*,
+                                  hipStream_t);
 
 }  // namespace gdc

@@ -59,9 +59,15 @@ struct alignas(2 * sizeof(R)) Cx {
   R x, y;
 };
 
+// Explicit fused multiply-adds, so that the product rounds the same way in
+// every kernel instantiation (the transform file turns automatic contraction
+// off).
+__host__ __device__ inline float fused_ma(float a, float b, float c) { return fmaf(a, b, c); }
+__host__ __device__ inline double fused_ma(double a, double b, double c) { return fma(a, b, c); }
+
 template <typename R>
 __host__ __device__ inline Cx<R> cmul(Cx<R> a, Cx<R> b) {
-  return Cx<R>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+  return Cx<R>{fused_ma(a.x, b.x, -(a.y * b.y)), fused_ma(a.x, b.y, a.y * b.x)};
 }
 
 // ------------------------------------------------------------ rigid-body algebra
@@ -123,6 +129,13 @@ __host__ __device__ inline void cross3(const double* a, const double* b, double*
 
 // ------------------------------------------------------------ grid geometry
 
+// Workgroup sizes (threads) of the FFT passes of a grid, chosen at set-up by
+// fft_autotune; every choice gives the same results.
+struct FftShape {
+  int plane_fwd = 512, proj_plane = 512, plane_inv = 512;        // three-pass path
+  int r2c = 256, fwd1 = 256, proj = 256, inv1 = 256, c2r = 256;   // five-pass path
+};
+
 // Everything a grid kernel needs about the periodic box and the envelope.
 struct GridGeom {
   int n[3];
@@ -141,6 +154,7 @@ struct GridGeom {
   // contiguously as [i0 % 8][i1 % 8][i2 % 32].  A spreading workgroup then
   // writes its tile as one contiguous block.
   int tiled;
+  FftShape fft;       // host side: launch shapes of the transform passes
 };
 
 // Offset of grid point (i0, i1, i2) within one component of a real-space
@@ -194,6 +208,11 @@ template <typename R>
 int fluct_field(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, Cx<R>* Y,
                 uint64_t seed, uint64_t step, double kT, double dt, hipStream_t s);
 bool fft_size_supported(int n);
+// Times every workgroup size of each pass of g's transform on the given
+// buffers (zeroed first) and stores the fastest in g.fft; cached per grid and
+// precision for the process.
+template <typename R>
+int fft_autotune(GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, Cx<R>* Y, hipStream_t s);
 int philox_normals_dev(uint64_t seed, uint32_t c1, uint64_t step, uint32_t c0_begin, int count,
                        double* out_dev, hipStream_t s);
 

@@ -143,3 +143,26 @@ def test_served_results_equal_alone(lib):
         assert _close(out.q, qr, 0.0 * qr, exact), w.name
         assert len(out.step_times) == r.n_steps + 1
     assert summ["step_latency_p99_ms"] >= summ["step_latency_p50_ms"] > 0
+
+
+@pytest.mark.parametrize("prec,n,L", [("fp32", 32, 24.0), ("fp32", (24, 32, 48), (20.0, 24.0, 36.0)),
+                                      ("fp64", 32, 24.0)])
+def test_every_fft_launch_shape_gives_identical_results(lib, prec, n, L):
+    # the autotuner only chooses among workgroup sizes that distribute the
+    # same arithmetic: forcing each size must give the same mobility bit for bit
+    w = wl.small_case("shapes", n_bodies=6, n=n, L=L, shapes=[wl.rod(4), wl.boomerang()], precision=prec, seed=17)
+    Y, q = wl.initial_state(w)
+    lam = np.random.default_rng(5).standard_normal((w.M, 3))
+    s = lib.Suspension(**wl.library_kwargs(w))
+    tuned = s.launch_config
+    _say("shapes", prec, n, tuned)
+    ref = s.mobility_apply("blob", Y, q, lam)
+    for t in [256, 512, 1024]:
+        cfg = {k: (t if k in ("plane_fwd", "plane_inv") else min(t, 512)) for k in s.FFT_PASSES}
+        s.launch_config = cfg
+        assert s.launch_config == cfg
+        v = s.mobility_apply("blob", Y, q, lam)
+        assert np.array_equal(v, ref), t
+    with pytest.raises(lib.GdcError):
+        s.launch_config = {"r2c": 1024}
+    s.close()
