@@ -987,6 +987,31 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
   B.shape_Lp = d_Lp;
   B.shape_precT = d_prec;
   B.shape_prec_off = d_poff;
+  {
+    // bodies grouped by shape, PREC_GROUP per group, for the matrix-core preconditioner
+    std::vector<int> gbody, gfirst, gcount, gshape;
+    for (int sh = 0; sh < cfg->n_shapes; ++sh) {
+      const int first = (int)gbody.size();
+      for (int p = 0; p < h->N; ++p)
+        if (h->body_shape[p] == sh) gbody.push_back(p);
+      for (int k = first; k < (int)gbody.size(); k += PREC_GROUP) {
+        gfirst.push_back(k);
+        gcount.push_back(std::min(PREC_GROUP, (int)gbody.size() - k));
+        gshape.push_back(sh);
+      }
+    }
+    int *d_gb, *d_gf, *d_gc, *d_gs;
+    GDC_TRY(upload(&d_gb, gbody));
+    GDC_TRY(upload(&d_gf, gfirst));
+    GDC_TRY(upload(&d_gc, gcount));
+    GDC_TRY(upload(&d_gs, gshape));
+    B.n_groups = (int)gfirst.size();
+    B.group_body = d_gb;
+    B.group_first = d_gf;
+    B.group_count = d_gc;
+    B.group_shape = d_gs;
+    B.mfma = h->maxdim <= PREC_MFMA_MAXDIM ? 1 : 0;
+  }
 
   const size_t N = h->N, M = h->M;
   GDC_TRY(h->alloc(&h->Y, 3 * N));

@@ -63,6 +63,123 @@ __global__ void k_blob_positions(BodyTables B, const double* __restrict__ Y, con
 // yV is given the same kernel also forms the body rows of the saddle operator
 // at z = P^-1 x, yV = -K^T z_lam - Pi z_V, in the body frame (K, Pi are
 // rotation covariant) before rotating them to the lab frame.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// The same preconditioner on the matrix cores: one workgroup (4 waves) per
+// group of up to 16 bodies of one shape, each wave one 16-row block.  The body-frame vectors x_b = Q^T x of the group
+// are the columns of X (D x 16, LDS); Y = P_s^-1 X by FP64 MFMA
+// (v_mfma_f64_16x16x4f64: 16-row blocks of P_s^-1, K in steps of 4; lane l
+// passes A[16 rb + l % 16][4 t + l / 16] and X[4 t + l / 16][l % 16] and gets
+// Y[16 rb + l / 16 + 4 r][l % 16], r < 4); then rotated back and scattered
+// exactly as k_precond does.  D = 3 n_b + 6 <= PREC_MFMA_MAXDIM.
+__global__ __launch_bounds__(256) void k_precond_mfma(BodyTables B, const double* __restrict__ q,
+                                                     const double* __restrict__ x, double* __restrict__ z,
+                                                     double* __restrict__ yV, const int* __restrict__ spos,
+                                                     double* __restrict__ zs, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  constexpr int DP = PREC_MFMA_MAXDIM;
+  __shared__ double X[DP][16];
+  __shared__ double Yl[DP][16];
+  __shared__ double As[DP * DP];   // the shape's block, staged once
+  __shared__ double Rm[16][9];
+  __shared__ double Tb[16][6];
+  __shared__ int pb[16];
+  const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int s = B.group_shape[g], first = B.group_first[g], cnt = B.group_count[g];
+  const int off_s = B.shape_boff[s], nb = B.shape_boff[s + 1] - off_s;
+  const int D = 3 * nb + 6, nv = nb + 2;
+  const long long Mx3 = 3LL * B.M;
+  if (tid < 16) {
+    const int p = tid < cnt ? B.group_body[first + tid] : -1;
+    pb[tid] = p;
+    if (p >= 0) rotmat(q + 4LL * p, &Rm[tid][0]);
+  }
+  __syncthreads();
+  for (int t = tid; t < nv * 16; t += 256) {
+    const int v = t >> 4, j = t & 15;
+    const int p = pb[j];
+    double w[3] = {0.0, 0.0, 0.0};
+    if (p >= 0) {
+      const double* src = v < nb ? x + 3LL * (B.body_off[p] + v) : x + Mx3 + 6LL * p + 3 * (v - nb);
+      double xv[3];
+      load3(src, xv);
+      matTvec3(&Rm[j][0], xv, w);
+    }
+    X[3 * v][j] = w[0];
+    X[3 * v + 1][j] = w[1];
+    X[3 * v + 2][j] = w[2];
+  }
+  for (int t = tid; t < (DP - D) * 16; t += 256) X[D + (t >> 4)][t & 15] = 0.0;
+  const double* AT = B.shape_precT + B.shape_prec_off[s];   // AT[k D + i] = (P_s^-1)[i][k]
+  for (int e = tid; e < D * D; e += 256) As[e] = AT[e];
+  __syncthreads();
+  const int il = lane & 15, kq = lane >> 4;
+  const int nrb = (D + 15) / 16, nk = (D + 3) / 4;
+  for (int rb = wave; rb < nrb; rb += 4) {   // one 16-row block per wave
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    const int i = 16 * rb + il;
+    for (int t = 0; t < nk; ++t) {
+      const int k = 4 * t + kq;
+      const double a = (i < D && k < D) ? As[k * D + i] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, X[k][il], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Yl[16 * rb + kq + 4 * r][il] = acc[r];
+  }
+  __syncthreads();
+  for (int t = tid; t < nv * 16; t += 256) {
+    const int v = t >> 4, j = t & 15;
+    const int p = pb[j];
+    if (p < 0) continue;
+    const double yv[3] = {Yl[3 * v][j], Yl[3 * v + 1][j], Yl[3 * v + 2][j]};
+    double w[3];
+    matvec3(&Rm[j][0], yv, w);
+    const int off = B.body_off[p];
+    double* dst = v < nb ? z + 3LL * (off + v) : z + Mx3 + 6LL * p + 3 * (v - nb);
+    dst[0] = w[0];
+    dst[1] = w[1];
+    dst[2] = w[2];
+    if (zs && v < nb) {
+      double* d2 = zs + 3LL * spos[off + v];
+      d2[0] = w[0];
+      d2[1] = w[1];
+      d2[2] = w[2];
+    }
+  }
+  if (!yV) return;
+  const double* bb = B.shape_b + 3LL * off_s;
+  for (int t = tid; t < 16 * 6; t += 256) {
+    const int j = t / 6, c = t % 6;
+    if (pb[j] < 0) continue;
+    double acc = 0.0;
+    for (int i = 0; i < nb; ++i) {
+      if (c < 3) {
+        acc += Yl[3 * i + c][j];
+      } else {
+        const int cc = c - 3, c1 = (cc + 1) % 3, c2 = (cc + 2) % 3;
+        acc += bb[3 * i + c1] * Yl[3 * i + c2][j] - bb[3 * i + c2] * Yl[3 * i + c1][j];
+      }
+    }
+    const double* Pi = B.shape_null + 36LL * s + 6 * c;
+    double pz = 0.0;
+    for (int m = 0; m < 6; ++m) pz += Pi[m] * Yl[3 * nb + m][j];
+    Tb[j][c] = -acc - pz;
+  }
+  __syncthreads();
+  if (tid < 32) {
+    const int j = tid >> 1, half = tid & 1;
+    const int p = pb[j];
+    if (p >= 0) {
+      double w[3];
+      matvec3(&Rm[j][0], &Tb[j][3 * half], w);
+      double* dst = yV + 6LL * p + 3 * half;
+      dst[0] = w[0];
+      dst[1] = w[1];
+      dst[2] = w[2];
+    }
+  }
+}
+
 __global__ __launch_bounds__(64) void k_precond(BodyTables B, const double* __restrict__ q,
                                                 const double* __restrict__ x, double* __restrict__ z,
                                                 double* __restrict__ yV, const int* __restrict__ spos,
@@ -471,6 +588,10 @@ int blob_positions(const BodyTables& b, const double* Y, const double* q, double
 
 int precond_apply(const BodyTables& b, const double* q, const double* x, double* z, double* yV, const int* spos,
                   double* zs, int maxdim, hipStream_t s, const int* skip) {
+  if (b.mfma && maxdim <= PREC_MFMA_MAXDIM) {
+    hipLaunchKernelGGL(k_precond_mfma, dim3(b.n_groups), dim3(256), 0, s, b, q, x, z, yV, spos, zs, skip);
+    return check_launch("k_precond_mfma");
+  }
   const size_t shm = (2 * (size_t)maxdim + 8) * sizeof(double);
   hipLaunchKernelGGL(k_precond, dim3(b.N), dim3(64), shm, s, b, q, x, z, yV, spos, zs, skip);
   return check_launch("k_precond");

@@ -192,6 +192,15 @@ struct BodyTables {
   const double* shape_Lp;     // n_shapes: max blob-blob distance (or a)
   const double* shape_precT;  // concatenated transposed preconditioner inverses
   const long long* shape_prec_off;  // n_shapes
+  // Groups of up to PREC_GROUP bodies of one shape for the matrix-core
+  // preconditioner: group g covers bodies group_body[group_first[g] ..
+  // group_first[g] + group_count[g]) of shape group_shape[g].
+  int n_groups;
+  const int* group_body;
+  const int* group_first;
+  const int* group_count;
+  const int* group_shape;
+  int mfma;                   // every block fits the matrix-core kernel
 };
 
 // ------------------------------------------------------------ launchers
@@ -260,6 +269,12 @@ int field_to_rowmajor(const GridGeom& g, const R* x, double* y, hipStream_t s);
 // Body kernels (body.hip).
 int blob_positions(const BodyTables& b, const double* Y, const double* q, double* r,
                    hipStream_t s);
+// Largest preconditioner block (3 n_b + 6) the matrix-core kernel takes.
+constexpr int PREC_MFMA_MAXDIM = 64;
+// Bodies per workgroup of the matrix-core preconditioner (<= 16, the
+// columns of one MFMA tile): fewer bodies give more workgroups to hide the
+// gather and scatter latency.
+constexpr int PREC_GROUP = 4;
 // z = P^-1 x (block-diagonal preconditioner, Sec. 2.2) and, when yV is
 // given, the body rows of the saddle operator at z: yV = -K^T z_lam - Pi z_V.
 // When zs is given, z_lam is also written in the spreading order:

@@ -80,6 +80,9 @@ CASES = [
     ("rods48", 48, 32.0, [wl.rod(5)]),
     ("slab16x32", (16, 32, 32), (13.0, 24.0, 24.0), [wl.rod(4), wl.boomerang()]),
     ("mixed64", 64, 48.0, [wl.rod(10), wl.boomerang(), wl.tetrahedron()]),
+    # a 20-blob shape: preconditioner block of 66, above the matrix-core
+    # kernel's limit, so the per-body kernel runs
+    ("rod20", 48, 48.0, [wl.rod(20), wl.tetrahedron()]),
 ]
 
 
