@@ -16,6 +16,7 @@ Beside the headline figure the JSON line carries:
   roofline      the dominant kernel (Gaussian spreading) against HBM peak;
   kernels       achieved bandwidth of spreading, averaging and each FFT pass;
   fp64_single   the same suspension on the plain FP64 path;
+  rheology      effective viscosity of 500 rods under the sinusoidal forcing;
   serving       256 independent suspensions (N log-uniform in [8, 2048] rods,
                 grids 32^3..128^3, 50 steps each) served with continuous
                 batching: saturation throughput (all requests queued at
@@ -220,6 +221,40 @@ def fp64_single(g, wl, w, Y0, q0, tol, stream, steps):
             "mobility_rel_err": mobility_error(g, wl, w, Y0, q0, tol, precision="fp64")}
 
 
+def rheology_bench(g, wl, tol, stream, steps=100):
+    """Effective viscosity under the sinusoidal forcing f0 sin(k y) e_x:
+    eta_eff = f0 / (k^2 v_x), v_x the per-step sine amplitude of the fluid
+    x-velocity averaged over the run (Sec. 6.3)."""
+    import numpy as np
+    import torch
+    progress("rheology")
+    w = wl.rheology500()
+    Y0, q0 = wl.initial_state(w)
+    s = g.Suspension(**wl.library_kwargs(w, gmres_tol=tol, gmres_maxit=500, stream=stream.cuda_stream))
+    Y = torch.tensor(Y0, dtype=torch.float64, device="cuda")
+    q = torch.tensor(q0, dtype=torch.float64, device="cuda")
+    s.step(Y, q, 5)
+    torch.cuda.synchronize()
+    vx = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        vx.append(s.step(Y, q, 1)["sine_vx"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s.close()
+    vx = np.array(vx)
+    k = 2.0 * np.pi / w.L[1]
+    ratio = w.sine_force / (k * k * vx.mean()) / w.eta
+    se = vx.std(ddof=1) / np.sqrt(len(vx)) / vx.mean() * ratio
+    return {"workload": "rheology500: 500 rods x 10 blobs (5,000 blobs, 8% volume fraction), L=64a, grid 64^3, "
+                        f"f0={w.sine_force:g}, k=2pi/L, dt={w.dt:g}, pair repulsion, FP32",
+            "steps": steps, "blob_steps_per_s": w.M * steps / dt,
+            "v_x_mean": float(vx.mean()), "eta_eff_over_eta": float(ratio), "eta_eff_over_eta_se": float(se),
+            "shear_rate": float(k * vx.mean()),
+            "note": "v_x from each step's midpoint solve; a short run from a random start, not a converged "
+                    "rheology measurement"}
+
+
 def serving_bench(g, wl, reqs, states, tol, budget, slots):
     import numpy as np
     from paper_2106_00449_amd.serving import Request, Server, summarise
@@ -364,8 +399,10 @@ def main():
         kernels = kernel_bandwidth(g, s, Y, q, w, cov)
     s.close()
 
+    rheo = {}
     if not args.only_headline:
         fp64 = fp64_single(g, wl, w, Y0, q0, tol, stream, args.steps)
+        rheo = rheology_bench(g, wl, tol, stream)
     out = {
         "metric": METRIC, "value": value, "unit": "blob-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": total * 1e3 / args.steps,
@@ -380,6 +417,7 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "fp64_single": fp64,
+        "rheology": rheo,
     }
     if reqs:
         progress(f"serving {len(reqs)} requests")

@@ -72,12 +72,18 @@ typedef struct {
  *     Sec. 6.3 applied to blob pairs); 0 disables it.
  *   const_force: force and torque added to every body.
  *   shear_rate: background flow u(r) = rate (y - L1/2) e_x at each blob, y
- *     measured from the body's wrapped reference point (not Lees-Edwards). */
+ *     measured from the body's wrapped reference point (not Lees-Edwards).
+ *   sine_force: f0 of the periodic force density f0 sin(k y) e_x on the
+ *     fluid, k = 2 pi / L1 (the rheology forcing of Sec. 6.3); its flow
+ *     f0/(eta k^2) sin(k y) e_x, averaged at each blob, enters the step-5
+ *     slip, and each step reports the sine amplitude v_x of the fluid's
+ *     x-velocity (gdc_stats.sine_vx), so that eta_eff = f0 / (k^2 v_x). */
 typedef struct {
   double steric_k;
   double steric_cutoff;
   double const_force[6];
   double shear_rate;
+  double sine_force;
 } gdc_forces;
 
 /* Suspension and solver parameters (Sec. 2-4, Sec. 6.1).
@@ -124,6 +130,10 @@ typedef struct {
   double ms;                 /* gdc_step: wall time of the call; gdc_batch_step:
                                 time from the call's start to this handle's
                                 last completed step (0 if none) */
+  double sine_vx;            /* with sine forcing: mean over the call's steps of
+                                the sin(k y) amplitude of the fluid x-velocity,
+                                (f0 + (2/V) sum_i lambda_ix J[sin(k y)](r_i)) /
+                                (eta k^2) at the midpoint solve; else 0 */
 } gdc_stats;
 
 typedef struct gdc_handle gdc_handle;

@@ -40,11 +40,14 @@ class Forces:
     const_force: (6,) force and torque applied to every body;
     shear_rate: imposed background flow u_inf = rate (y - L_y/2) e_x, with y
       measured from the body's wrapped centre so the flow is continuous
-      across each body (not Lees-Edwards)."""
+      across each body (not Lees-Edwards);
+    sine_force: f0 of the periodic force density f0 sin(k y) e_x on the
+      fluid, k = 2 pi / L_y (Sec. 6.3, rheology)."""
     steric_k: float = 0.0
     steric_cutoff: float = 0.0
     const_force: np.ndarray = field(default_factory=lambda: np.zeros(6))
     shear_rate: float = 0.0
+    sine_force: float = 0.0
 
 
 @dataclass
@@ -102,9 +105,45 @@ def body_forces(cfg: Config, Y, r):
     return F + np.asarray(cfg.forces.const_force, dtype=np.float64)[None, :]
 
 
+def sine_average(cfg: Config, r):
+    """s_i = J[sin(k y)](r_i): the averaged sine profile at each blob (the
+    trapezoidal average of eq. averaging), k = 2 pi / L_y."""
+    p = cfg.susp.fcm
+    grid = p.grid
+    k = 2.0 * np.pi / grid.L[1]
+    field = np.zeros((3,) + grid.n)
+    field[0] = np.sin(k * grid.dx[1] * np.arange(grid.n[1]))[None, :, None]
+    W = fcm.weight_matrix(r, grid, p.sigma, p.rc)
+    return fcm.interp(W, field, grid)[:, 0]
+
+
+def sine_flow_scale(cfg: Config):
+    """f0 / (eta k^2): the fluid velocity amplitude the forcing f0 sin(k y) e_x
+    drives alone.  The single Fourier mode is unchanged by the projection, so
+    on the grid L^-1 f = f0/(eta k^2) sin(k y_g) e_x exactly."""
+    k = 2.0 * np.pi / cfg.susp.fcm.grid.L[1]
+    return cfg.forces.sine_force / (cfg.susp.fcm.eta * k * k)
+
+
+def sine_amplitude(cfg: Config, r, lam):
+    """v_x, the sin(k y) amplitude of the x-velocity of the fluid at a solved
+    configuration: the sine mode of L^-1 (S lambda + f0 sin(k y) e_x), i.e.
+    (f0 + (2/V) sum_i lambda_ix s_i) / (eta k^2) with s_i = J[sin(k y)](r_i)
+    (the blob forces seen by the grid's sine mode; V the box volume).  The
+    effective viscosity is eta_eff = f0 / (k^2 v_x)."""
+    grid = cfg.susp.fcm.grid
+    k = 2.0 * np.pi / grid.L[1]
+    V = float(np.prod(grid.L))
+    s_i = sine_average(cfg, r)
+    return (cfg.forces.sine_force + (2.0 / V) * float(lam[:, 0] @ s_i)) / (cfg.susp.fcm.eta * k * k)
+
+
 def background_flow(cfg: Config, Y, r):
-    """u_inf at every blob (zero unless a shear rate is set)."""
+    """u_inf at every blob: the shear profile and the averaged flow of the
+    sine forcing (zero when neither is set)."""
     out = np.zeros_like(r)
+    if cfg.forces.sine_force != 0.0:
+        out[:, 0] += sine_flow_scale(cfg) * sine_average(cfg, r)
     g = cfg.forces.shear_rate
     if g == 0.0:
         return out
@@ -112,7 +151,7 @@ def background_flow(cfg: Config, Y, r):
     b = cfg.susp.bodies
     Yb = np.asarray(Y).reshape(-1, 3)[b.body_of_blob()]
     ywrap = (Yb[:, 1] - Ly * np.floor(Yb[:, 1] / Ly)) + (r[:, 1] - Yb[:, 1])
-    out[:, 0] = g * (ywrap - 0.5 * Ly)
+    out[:, 0] += g * (ywrap - 0.5 * Ly)
     return out
 
 
@@ -194,6 +233,8 @@ def corrector_solve(cfg: Config, Ym, qm, ufl, tol=1e-12, dense=None):
     slip = averaged(cfg, rm, ufl) + background_flow(cfg, Ym, rm)
     F = body_forces(cfg, Ym, rm)
     lam, V, info = rigid.solve_saddle(cfg.susp, Ym, rm, slip, F, tol=tol, dense=dense)
+    if cfg.forces.sine_force != 0.0:
+        info["sine_vx"] = sine_amplitude(cfg, rm, lam)
     return V, info
 
 

@@ -44,7 +44,8 @@ class _Shape(ctypes.Structure):
 
 class _Forces(ctypes.Structure):
     _fields_ = [("steric_k", ctypes.c_double), ("steric_cutoff", ctypes.c_double),
-                ("const_force", ctypes.c_double * 6), ("shear_rate", ctypes.c_double)]
+                ("const_force", ctypes.c_double * 6), ("shear_rate", ctypes.c_double),
+                ("sine_force", ctypes.c_double)]
 
 
 class _Config(ctypes.Structure):
@@ -63,7 +64,8 @@ class _Config(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("steps_done", ctypes.c_int), ("gmres_iterations", ctypes.c_int),
                 ("gmres_relres", ctypes.c_double), ("nu", ctypes.c_double),
-                ("nu_nonpositive", ctypes.c_int), ("ms", ctypes.c_double)]
+                ("nu_nonpositive", ctypes.c_int), ("ms", ctypes.c_double),
+                ("sine_vx", ctypes.c_double)]
 
 
 def _load():
@@ -164,7 +166,7 @@ def _make_config(L, n, shapes, body_shape, *, a=1.0, sigma=0.0, trunc=0.0,
                  eta=1.0 / (6.0 * np.pi), kT=1.0, dt=0.01, fd_delta=0.0, gmres_tol=0.0,
                  gmres_maxit=0, gmres_restart=0, precision="fp32", scheme="gdc",
                  divergence="fd", seed=0, steric_k=0.0, steric_cutoff=0.0,
-                 const_force=(0, 0, 0, 0, 0, 0), shear_rate=0.0, device=0, stream=None):
+                 const_force=(0, 0, 0, 0, 0, 0), shear_rate=0.0, sine_force=0.0, device=0, stream=None):
     """A gdc_config and the arrays it points into (kept alive by the caller)."""
     shape_arrays = [np.ascontiguousarray(np.asarray(s, dtype=np.float64).reshape(-1, 3)) for s in shapes]
     bshape = np.ascontiguousarray(np.asarray(body_shape, dtype=np.int32))
@@ -192,6 +194,7 @@ def _make_config(L, n, shapes, body_shape, *, a=1.0, sigma=0.0, trunc=0.0,
     for k in range(6):
         c.forces.const_force[k] = float(const_force[k])
     c.forces.shear_rate = shear_rate
+    c.forces.sine_force = sine_force
     c.device = int(device)
     c.stream = stream
     keep = {"shapes": shape_arrays, "body_shape": bshape, "shapes_c": sh, "N": int(bshape.size),
@@ -224,7 +227,7 @@ def batch_step(susps, steps, until="all", max_ms=0.0):
         _check(rc)
     out = [{"steps_done": x.steps_done, "gmres_iterations": x.gmres_iterations,
             "gmres_relres": x.gmres_relres, "nu": x.nu, "nu_nonpositive": x.nu_nonpositive,
-            "ms": x.ms} for x in stats[:nh]]
+            "ms": x.ms, "sine_vx": x.sine_vx} for x in stats[:nh]]
     return [int(x) for x in st_in[:nh]], out, rc
 
 
@@ -294,7 +297,7 @@ class Suspension:
         rc = lib.gdc_step(self._h, int(n_steps), aY.ptr, aq.ptr, ms, ctypes.byref(st))
         stats = {"steps_done": st.steps_done, "gmres_iterations": st.gmres_iterations,
                  "gmres_relres": st.gmres_relres, "nu": st.nu, "nu_nonpositive": st.nu_nonpositive,
-                 "ms": st.ms, "rc": rc}
+                 "ms": st.ms, "sine_vx": st.sine_vx, "rc": rc}
         if rc != GDC_ENOTCONV:
             _check(rc)
         return stats

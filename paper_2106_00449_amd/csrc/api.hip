@@ -356,6 +356,12 @@ struct gdc_handle {
   std::vector<double> step_log;   // completion times of steps (ms, monotonic clock)
   // error counts of the steps completed since the last gdc_step / gdc_batch_step entry
   int n_overflow = 0, n_nonfinite = 0, n_notconv = 0, n_nonpos = 0;
+  // sine forcing: the field (sin(k y), 0, 0) on the grid, its average at
+  // each blob, f0/(eta k^2), and the amplitudes v_x of this call's steps
+  void* grid_sine = nullptr;
+  double* vbg = nullptr;
+  double sine_scale = 0.0, sine_sum_coef = 0.0, sine_acc = 0.0;
+  int sine_n = 0;
 
   ~gdc_handle() {
     for (void* p : allocs) (void)hipFree(p);
@@ -685,7 +691,11 @@ int step_advance(gdc_handle* h, bool block, int& adv) {
       GDC_TRY(prepare_positions(h, h->rm));
       GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_fl, h->v, h->M, h->geom.dV, nullptr, nullptr, nullptr, s,
                         nullptr, h->trec));
-      GDC_TRY(rhs_build(h->bt, qm, Ym, h->rm, h->v, h->F, h->cfg.forces.shear_rate, h->geom.L[1], h->rhs, s));
+      if (h->vbg)
+        GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_sine, h->vbg, h->M, h->geom.dV, nullptr, nullptr,
+                          nullptr, s, nullptr, h->trec));
+      GDC_TRY(rhs_build(h->bt, qm, Ym, h->rm, h->v, h->vbg, h->sine_scale, h->F, h->cfg.forces.shear_rate,
+                        h->geom.L[1], h->rhs, s));
       GDC_TRY(solve_begin<R>(h, Ym, qm, h->rm));
       sr.phase = StepRun::SOLVE;
       return GDC_OK;
@@ -699,6 +709,11 @@ int step_advance(gdc_handle* h, bool block, int& adv) {
       }
       sr.gr = h->sv.res;
       h->sv.phase = SolveRun::IDLE;
+      if (h->vbg) {
+        // sum_i lambda_ix J[sin(k y)](r_i) of the midpoint solve, for v_x
+        GDC_TRY(blob_dot_x(h->sol, h->vbg, h->M, h->nu + 1, s));
+        GDC_HIP(hipMemcpyAsync(h->hhost + 4 * HCOLS + 3, h->nu + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+      }
       GDC_TRY(update(h->bt, h->Y, h->q, h->sol + 3LL * h->M, gdc_scheme ? h->nu : nullptr, h->cfg.dt,
                      h->flags + 1, s));
       GDC_HIP(hipMemcpyAsync(h->hhost + 4 * HCOLS, h->nu, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -721,6 +736,10 @@ int step_advance(gdc_handle* h, bool block, int& adv) {
       if (fl[1]) ++h->n_nonfinite;
       if (!sr.gr.converged) ++h->n_notconv;
       if (!(sr.nu > 0.0)) ++h->n_nonpos;
+      if (h->vbg) {
+        h->sine_acc += h->sine_scale + h->sine_sum_coef * h->hhost[4 * HCOLS + 3];
+        ++h->sine_n;
+      }
       h->step += 1;
       sr.phase = StepRun::IDLE;
       adv = ADV_DONE;
@@ -752,7 +771,13 @@ int step_errors(const gdc_handle* h) {
   return GDC_OK;
 }
 
-void reset_errors(gdc_handle* h) { h->n_overflow = h->n_nonfinite = h->n_notconv = h->n_nonpos = 0; }
+void reset_errors(gdc_handle* h) {
+  h->n_overflow = h->n_nonfinite = h->n_notconv = h->n_nonpos = 0;
+  h->sine_acc = 0.0;
+  h->sine_n = 0;
+}
+
+double sine_mean(const gdc_handle* h) { return h->sine_n ? h->sine_acc / h->sine_n : 0.0; }
 
 int require_idle(const gdc_handle* h) {
   if (h->sr.phase != StepRun::IDLE || h->sv.phase != SolveRun::IDLE) {
@@ -1111,6 +1136,23 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
   } else {
     GDC_TRY(init_grid_tables<float>(h));
   }
+  if (c.forces.sine_force != 0.0) {
+    const double k = 2.0 * 3.14159265358979323846 / g.L[1];
+    h->sine_scale = c.forces.sine_force / (c.eta * k * k);
+    h->sine_sum_coef = 2.0 / (g.L[0] * g.L[1] * g.L[2]) / (c.eta * k * k);
+    GDC_TRY(h->alloc(&h->vbg, 3 * (size_t)h->M));
+    if (h->precision == GDC_FP64) {
+      double* f = nullptr;
+      GDC_TRY(h->alloc(&f, 3 * (size_t)g.G));
+      if (!h->dry) GDC_TRY(fill_sine_field<double>(g, f, h->stream));
+      h->grid_sine = f;
+    } else {
+      float* f = nullptr;
+      GDC_TRY(h->alloc(&f, 3 * (size_t)g.G));
+      if (!h->dry) GDC_TRY(fill_sine_field<float>(g, f, h->stream));
+      h->grid_sine = f;
+    }
+  }
   // the host vectors of the uploads above go out of scope on return
   if (!h->dry) GDC_HIP(hipStreamSynchronize(h->stream));
   if (!h->dry) {
@@ -1193,7 +1235,7 @@ int gdc_mobility_apply(gdc_handle* h, int mode, const double* Y, const double* q
     GDC_TRY(copy_out(h, out, h->v, 3 * (size_t)h->M, memspace));
   } else {
     GDC_TRY(copy_in(h, h->io, in, 6 * (size_t)h->N, memspace));
-    GDC_TRY(rhs_build(h->bt, h->q, h->Y, h->r, nullptr, h->io, 0.0, h->geom.L[1], h->rhs, s));
+    GDC_TRY(rhs_build(h->bt, h->q, h->Y, h->r, nullptr, nullptr, 0.0, h->io, 0.0, h->geom.L[1], h->rhs, s));
     GDC_TRY(prepare_positions(h, h->r));
     if (h->precision == GDC_FP64) {
       GDC_TRY(gmres<double>(h, h->Y, h->q, h->r, gr));
@@ -1242,6 +1284,7 @@ int gdc_step(gdc_handle* h, int n_steps, double* Y, double* q, int memspace, gdc
     st->nu = h->sr.nu;
     st->nu_nonpositive = h->n_nonpos;
     st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    st->sine_vx = sine_mean(h);
   }
   return step_errors(h);
 }
@@ -1367,6 +1410,7 @@ int gdc_batch_step(gdc_handle* const* hs, int nh, int* steps, int until, double 
       st[i].nu = h->sr.nu;
       st[i].nu_nonpositive = h->n_nonpos;
       st[i].ms = t_last[i];
+      st[i].sine_vx = sine_mean(h);
     }
     if (rc == GDC_OK && first_err == GDC_OK) {
       const int e = step_errors(h);

@@ -445,15 +445,16 @@ __global__ void k_update(int N, double* __restrict__ Y, double* __restrict__ q, 
 
 // Right-hand side [-(v_slip + u_inf); -(I - Pi) F] of the saddle problem.
 __global__ void k_rhs_blobs(BodyTables B, const double* __restrict__ Y, const double* __restrict__ r,
-                            const double* __restrict__ vslip, double shear, double Ly, double* __restrict__ rhs) {
+                            const double* __restrict__ vslip, const double* __restrict__ vbg, double cbg,
+                            double shear, double Ly, double* __restrict__ rhs) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= B.M) return;
-  double ux = 0.0;
+  double ux = vbg ? cbg * vbg[3LL * i] : 0.0;
   if (shear != 0.0) {
     const int p = B.blob_body[i];
     const double yc = Y[3LL * p + 1];
     const double yw = yc - Ly * floor(yc / Ly);
-    ux = shear * (yw + (r[3LL * i + 1] - yc) - 0.5 * Ly);
+    ux += shear * (yw + (r[3LL * i + 1] - yc) - 0.5 * Ly);
   }
   rhs[3LL * i] = -((vslip ? vslip[3LL * i] : 0.0) + ux);
   rhs[3LL * i + 1] = -(vslip ? vslip[3LL * i + 1] : 0.0);
@@ -627,8 +628,9 @@ int update(const BodyTables& b, double* Y, double* q, const double* V, const dou
 }
 
 int rhs_build(const BodyTables& b, const double* q, const double* Y, const double* r, const double* vslip,
-              const double* F, double shear, double Ly, double* rhs, hipStream_t s) {
-  hipLaunchKernelGGL(k_rhs_blobs, dim3(nblk(b.M)), dim3(NT), 0, s, b, Y, r, vslip, shear, Ly, rhs);
+              const double* vbg, double cbg, const double* F, double shear, double Ly, double* rhs,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_rhs_blobs, dim3(nblk(b.M)), dim3(NT), 0, s, b, Y, r, vslip, vbg, cbg, shear, Ly, rhs);
   GDC_TRY(check_launch("k_rhs_blobs"));
   hipLaunchKernelGGL(k_rhs_bodies, dim3(nblk(b.N)), dim3(NT), 0, s, b, q, F, rhs + 3LL * b.M);
   return check_launch("k_rhs_bodies");

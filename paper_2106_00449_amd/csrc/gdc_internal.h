@@ -265,6 +265,11 @@ int fill_zero(void* p, size_t bytes, hipStream_t s);
 // y (3 x n0 x n1 x n2, row-major, FP64) = the real-space field x in the layout of g.
 template <typename R>
 int field_to_rowmajor(const GridGeom& g, const R* x, double* y, hipStream_t s);
+// f = (sin(k y_g), 0, 0) on the grid in its layout, k = 2 pi / L1.
+template <typename R>
+int fill_sine_field(const GridGeom& g, R* f, hipStream_t s);
+// *out = sum_i a[3 i] b[3 i] over M blobs, in a fixed order (one workgroup).
+int blob_dot_x(const double* a, const double* b, int M, double* out, hipStream_t s);
 
 // Body kernels (body.hip).
 int blob_positions(const BodyTables& b, const double* Y, const double* q, double* r,
@@ -294,9 +299,11 @@ int midpoint(const BodyTables& b, const double* Y, const double* q, const double
 // Step 6; sets *nonfinite (when given) if a new position or quaternion is not finite.
 int update(const BodyTables& b, double* Y, double* q, const double* V, const double* nu,
            double dt, int* nonfinite, hipStream_t s);
+// rhs = [-(vslip + cbg vbg_x e_x + shear flow); -(I - Pi) F]; vslip, vbg
+// (M x 3, only the x components of vbg are used) may be null.
 int rhs_build(const BodyTables& b, const double* q, const double* Y, const double* r,
-              const double* vslip, const double* F, double shear, double Ly, double* rhs,
-              hipStream_t s);
+              const double* vslip, const double* vbg, double cbg, const double* F, double shear,
+              double Ly, double* rhs, hipStream_t s);
 int steric_forces(const BodyTables& b, const GridGeom& g, const double* r, double k,
                   double cutoff, int* cell_count, int* cell_list, int cap, const int nc[3],
                   int* overflow, double* fblob, hipStream_t s);

@@ -799,6 +799,37 @@ int fill_zero(void* p, size_t bytes, hipStream_t s) {
 }
 
 template <typename R>
+__global__ void k_fill_sine(GridGeom G, R* __restrict__ f, double k) {
+  const long long n = 3 * G.G;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const int n1 = G.n[1], n2 = G.n[2];
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+    const long long c = e / G.G, rem = e - c * G.G;
+    const int i2 = (int)(rem % n2);
+    const long long r01 = rem / n2;
+    const int i1 = (int)(r01 % n1), i0 = (int)(r01 / n1);
+    f[c * G.G + field_plane_off(G.tiled, n1, n2, i0) + field_col_off(G.tiled, n2, i1, i2)] =
+        c == 0 ? R(sin(k * (i1 * G.dx[1]))) : R(0);
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_blob_dot_x(const double* __restrict__ a, const double* __restrict__ b,
+                                                     int M, double* __restrict__ out) {
+  __shared__ double sh[16];
+  double t = 0.0;
+  for (int i = threadIdx.x; i < M; i += 1024) t += a[3LL * i] * b[3LL * i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double u = 0.0;
+    for (int w = 0; w < 16; ++w) u += sh[w];
+    *out = u;
+  }
+}
+
+template <typename R>
 int field_to_rowmajor(const GridGeom& g, const R* x, double* y, hipStream_t s) {
   const long long want = (3 * g.G + 255) / 256;
   hipLaunchKernelGGL((k_to_rowmajor<R>), dim3((unsigned)(want < 8192 ? (want > 0 ? want : 1) : 8192)), dim3(256),
@@ -806,6 +837,22 @@ int field_to_rowmajor(const GridGeom& g, const R* x, double* y, hipStream_t s) {
   return check_launch("k_to_rowmajor");
 }
 template int field_to_rowmajor<float>(const GridGeom&, const float*, double*, hipStream_t);
+
+template <typename R>
+int fill_sine_field(const GridGeom& g, R* f, hipStream_t s) {
+  const long long want = (3 * g.G + 255) / 256;
+  const double k = 2.0 * 3.14159265358979323846 / g.L[1];
+  hipLaunchKernelGGL((k_fill_sine<R>), dim3((unsigned)(want < 8192 ? (want > 0 ? want : 1) : 8192)), dim3(256), 0,
+                     s, g, f, k);
+  return check_launch("k_fill_sine");
+}
+template int fill_sine_field<float>(const GridGeom&, float*, hipStream_t);
+template int fill_sine_field<double>(const GridGeom&, double*, hipStream_t);
+
+int blob_dot_x(const double* a, const double* b, int M, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_blob_dot_x, dim3(1), dim3(1024), 0, s, a, b, M, out);
+  return check_launch("k_blob_dot_x");
+}
 template int field_to_rowmajor<double>(const GridGeom&, const double*, double*, hipStream_t);
 
 int tile_sort(const GridGeom& g, const TileGeom& t, const double* r, int M, int* tile, int* count, int* off,

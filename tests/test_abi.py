@@ -18,7 +18,9 @@ def test_header_declares_boundary():
     names = _declared()
     for required in ["gdc_init", "gdc_free", "gdc_last_error", "gdc_mobility_apply", "gdc_step",
                      "gdc_get_step", "gdc_set_step", "gdc_fluct_velocity", "gdc_predictor",
-                     "gdc_philox_normals", "gdc_probe_kernel", "gdc_probe_read"]:
+                     "gdc_philox_normals", "gdc_probe_kernel", "gdc_probe_read", "gdc_set_state",
+                     "gdc_get_state", "gdc_batch_step", "gdc_step_log", "gdc_footprint", "gdc_device_bytes",
+                     "gdc_get_launch_config", "gdc_set_launch_config"]:
         assert required in names
 
 
@@ -46,7 +48,7 @@ def test_python_binding_marshals_config_layout():
     import paper_2106_00449_amd as g
     c = g._Config
     assert c.L.offset == 0 and c.n.offset == 24
-    assert ctypes.sizeof(g._Forces) == 8 * 9
+    assert ctypes.sizeof(g._Forces) == 8 * 10
     off = c.forces.offset
     assert off % 8 == 0 and c.device.offset == off + ctypes.sizeof(g._Forces)
 

@@ -234,3 +234,26 @@ def test_error_paths(lib):
     with pytest.raises(lib.GdcError) as e:
         s.step(Yn, qn, 1)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("prec,kT", [("fp64", 0.0), ("fp32", 0.0), ("fp32", 1.0)])
+def test_sine_forcing_step(lib, prec, kT):
+    # the rheology forcing f0 sin(k y) e_x: one step's increment and the
+    # measured amplitude v_x against the oracle (kT = 0 isolates the
+    # deterministic forcing response, nu = 1)
+    w = wl.small_case("sine", n_bodies=9, n=(32, 32, 48), L=(24.0, 24.0, 36.0),
+                      shapes=[wl.rod(4), wl.boomerang(), wl.tetrahedron()], precision=prec, seed=19,
+                      dt=0.005, kT=kT, sine_force=2.0)
+    Y0, q0 = wl.initial_state(w)
+    _say("sine", prec, kT)
+    s = lib.Suspension(**wl.library_kwargs(w, gmres_tol=1e-13 if prec == "fp64" else 1e-7, gmres_maxit=500))
+    Y, q = Y0.copy(), q0.copy()
+    st = s.step(Y, q, 1)
+    s.close()
+    o = oracle_config(w)
+    Yr, qr, info = gdc.gdc_step(o, Y0, q0, 0, tol=1e-13)
+    dx = np.concatenate([(Y - Y0).ravel(), (q - q0).ravel()])
+    dr = np.concatenate([(Yr - Y0).ravel(), (qr - q0).ravel()])
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert rel_l2(dx, dr) < tol
+    assert abs(st["sine_vx"] - info["sine_vx"]) < tol * abs(info["sine_vx"])

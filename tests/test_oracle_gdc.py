@@ -191,3 +191,49 @@ def test_mobility_divergence_pins():
     assert np.abs(d_b).max() > 1e-2            # the pair has a drift to see
     d_s = gdc.mobility_divergence(cfg, Y[::-1].copy(), q[::-1].copy(), h=1e-4)
     assert np.abs(d_s - np.concatenate([d_b[6:], d_b[:6]])).max() < 1e-9 * np.abs(d_b).max()
+
+
+def test_sine_average_closed_form():
+    # J[sin(k y)](r) is the Gaussian average of sin(k y): exp(-k^2 sigma^2 / 2)
+    # sin(k r_y) in the continuum; on a grid with sigma/dx = 1.13 the
+    # trapezoidal average matches it to the cut-off and aliasing errors (<1e-5)
+    cfg = _cfg([np.zeros((1, 3))], [0, 0, 0], L=16.0, n=32)
+    r = np.array([[1.3, 2.2, 3.9], [7.4, 11.05, 5.1], [14.9, 15.7, 0.4]])
+    k = 2.0 * math.pi / 16.0
+    s = gdc.sine_average(cfg, r)
+    ref = math.exp(-0.5 * (k / math.sqrt(math.pi)) ** 2) * np.sin(k * r[:, 1])
+    assert np.abs(s - ref).max() < 1e-5
+
+
+def test_sine_forcing_force_free_blobs_follow_the_flow():
+    # single-blob bodies without forces carry no constraint force (K^T lambda
+    # = 0 gives lambda = 0): they move with the averaged forcing flow, and the
+    # measured amplitude is the unhindered f0 / (eta k^2), so eta_eff = eta
+    cfg = _cfg([np.zeros((1, 3))], [0, 0, 0], kT=0.0, L=12.0, n=12, sine_force=0.7)
+    Y = np.array([[1.3, 2.2, 3.9], [7.4, 8.05, 5.1], [10.9, 5.7, 0.4]])
+    q = np.tile([1.0, 0.0, 0.0, 0.0], (3, 1))
+    Y1, _, info = gdc.gdc_step(cfg, Y, q, step=0, dense=True)
+    k = 2.0 * math.pi / 12.0
+    scale = 0.7 / (ETA * k * k)
+    r = rigid.blob_positions(cfg.susp.bodies, Y, q)
+    u = scale * gdc.sine_average(cfg, r)
+    assert np.abs((Y1 - Y)[:, 0] - cfg.dt * u).max() < 1e-12 * abs(scale) * cfg.dt
+    assert np.abs((Y1 - Y)[:, 1:]).max() < 1e-15
+    assert abs(info["sine_vx"] - scale) < 1e-12 * scale
+
+
+def test_sine_forcing_rigid_bodies_raise_the_viscosity():
+    # rigid bodies resist the imposed flow: the response to the same force
+    # density is weaker, so eta_eff = f0 / (k^2 v_x) > eta, and the amplitude
+    # is linear in f0
+    cfg = _cfg([wl.rod(4), wl.boomerang()], [0, 1, 0], kT=0.0, L=12.0, n=12, sine_force=1.0)
+    Y = np.array([[2.0, 3.0, 4.0], [7.5, 8.0, 6.5], [4.0, 9.0, 10.0]])
+    q = np.array([[0.9, 0.3, 0.2, 0.1], [0.7, -0.2, 0.5, 0.3], [0.5, 0.5, 0.5, 0.5]])
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    _, _, info = gdc.gdc_step(cfg, Y, q, step=0, dense=True)
+    k = 2.0 * math.pi / 12.0
+    eta_eff = 1.0 / (k * k * info["sine_vx"])
+    assert eta_eff > ETA * (1.0 + 1e-3), eta_eff / ETA
+    cfg.forces.sine_force = 2.0
+    _, _, info2 = gdc.gdc_step(cfg, Y, q, step=0, dense=True)
+    assert abs(info2["sine_vx"] - 2.0 * info["sine_vx"]) < 1e-10 * abs(info["sine_vx"])

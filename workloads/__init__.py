@@ -17,6 +17,8 @@ Workloads (sizes of the five suspensions the paper's method is exercised on):
                box at 5% blob volume fraction, grid from {32,48,64,96,128}
   rods32768    32,768 rods x 10 blobs, L = 384a, grid 384^3, axes within 15
                degrees of z, shear rate 0.1 plus the pair repulsion
+  rheology500  500 rods x 10 blobs, L = 64a, grid 64^3, sinusoidal forcing
+               f0 sin(2 pi y / L) e_x of the fluid (effective viscosity)
 Common: a = 1, eta = 1/(6 pi), kT = 1, sigma = a/sqrt(pi), cutoff 3a.
 """
 
@@ -81,6 +83,7 @@ class Workload:
     steric_cutoff: float = 0.0
     const_force: tuple = (0.0, 0.0, 0.0, 0.0, 0.0, 0.0)
     shear_rate: float = 0.0
+    sine_force: float = 0.0          # f0 of the rheology forcing f0 sin(2 pi y / L_y) e_x
     nematic_cap_deg: float = 0.0     # 0: orientations uniform on S^3
     placement: str = "sequential"    # or "batch" (see initial_state)
     extra: dict = field(default_factory=dict)
@@ -128,6 +131,16 @@ def rods32768(steric=True):
     return Workload("rods32768", (384.0,) * 3, (384,) * 3, [rod(10)],
                     np.zeros(32768, np.int64), dt=0.005, steps=10000, noise_seed=5,
                     placement_seed=1005, shear_rate=0.1, nematic_cap_deg=15.0, placement="batch", **kw)
+
+
+def rheology500(sine_force=0.002):
+    """Sinusoidal-forcing rheology: 500 rods x 10 blobs (8% blob volume
+    fraction), L = 64a, grid 64^3, fluid forced by f0 sin(2 pi y / L) e_x;
+    the paper's suspension (Sec. 6.3) is the same forcing on a denser box of
+    19-blob particles whose geometry the text does not give."""
+    return Workload("rheology500", (64.0,) * 3, (64,) * 3, [rod(10)], np.zeros(500, np.int64),
+                    dt=0.005, steps=200, noise_seed=6, placement_seed=1006, sine_force=sine_force,
+                    placement="batch", **_steric())
 
 
 def small_case(name="tiny", n_bodies=4, n=16, L=16.0, shapes=None, body_shape=None,
@@ -369,6 +382,6 @@ def library_kwargs(w: Workload, **over):
     kw = dict(L=w.L, n=w.n, shapes=w.shapes, body_shape=w.body_shape, a=w.a, sigma=w.sigma,
               trunc=w.rc, eta=w.eta, kT=w.kT, dt=w.dt, precision=w.precision, seed=w.noise_seed,
               steric_k=w.steric_k, steric_cutoff=w.steric_cutoff, const_force=w.const_force,
-              shear_rate=w.shear_rate)
+              shear_rate=w.shear_rate, sine_force=w.sine_force)
     kw.update(over)
     return kw
