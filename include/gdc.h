@@ -119,8 +119,8 @@ typedef struct {
   void* stream;
 } gdc_config;
 
-/* Per-call statistics of gdc_step and gdc_batch_step (values of the last
- * step completed in the call). */
+/* Per-call statistics of gdc_step and gdc_batch_step: values of the last
+ * step completed in the call, and means over the steps completed in it. */
 typedef struct {
   int steps_done;            /* steps completed in this call */
   int gmres_iterations;      /* preconditioned GMRES iterations, last step */
@@ -134,6 +134,8 @@ typedef struct {
                                 the sin(k y) amplitude of the fluid x-velocity,
                                 (f0 + (2/V) sum_i lambda_ix J[sin(k y)](r_i)) /
                                 (eta k^2) at the midpoint solve; else 0 */
+  double gmres_iterations_mean; /* mean GMRES iterations over the call's steps */
+  double nu_mean;            /* mean nu over the call's steps (1 for EM) */
 } gdc_stats;
 
 typedef struct gdc_handle gdc_handle;

@@ -65,7 +65,8 @@ class _Stats(ctypes.Structure):
     _fields_ = [("steps_done", ctypes.c_int), ("gmres_iterations", ctypes.c_int),
                 ("gmres_relres", ctypes.c_double), ("nu", ctypes.c_double),
                 ("nu_nonpositive", ctypes.c_int), ("ms", ctypes.c_double),
-                ("sine_vx", ctypes.c_double)]
+                ("sine_vx", ctypes.c_double), ("gmres_iterations_mean", ctypes.c_double),
+                ("nu_mean", ctypes.c_double)]
 
 
 def _load():
@@ -227,7 +228,8 @@ def batch_step(susps, steps, until="all", max_ms=0.0):
         _check(rc)
     out = [{"steps_done": x.steps_done, "gmres_iterations": x.gmres_iterations,
             "gmres_relres": x.gmres_relres, "nu": x.nu, "nu_nonpositive": x.nu_nonpositive,
-            "ms": x.ms, "sine_vx": x.sine_vx} for x in stats[:nh]]
+            "ms": x.ms, "sine_vx": x.sine_vx, "gmres_iterations_mean": x.gmres_iterations_mean,
+            "nu_mean": x.nu_mean} for x in stats[:nh]]
     return [int(x) for x in st_in[:nh]], out, rc
 
 
@@ -297,7 +299,8 @@ class Suspension:
         rc = lib.gdc_step(self._h, int(n_steps), aY.ptr, aq.ptr, ms, ctypes.byref(st))
         stats = {"steps_done": st.steps_done, "gmres_iterations": st.gmres_iterations,
                  "gmres_relres": st.gmres_relres, "nu": st.nu, "nu_nonpositive": st.nu_nonpositive,
-                 "ms": st.ms, "sine_vx": st.sine_vx, "rc": rc}
+                 "ms": st.ms, "sine_vx": st.sine_vx, "gmres_iterations_mean": st.gmres_iterations_mean,
+                 "nu_mean": st.nu_mean, "rc": rc}
         if rc != GDC_ENOTCONV:
             _check(rc)
         return stats

@@ -280,14 +280,21 @@ struct SolveRun {
   GmresResult res{};
 };
 
-// Host side of a time step in progress: the pre-solve kernels are queued
-// on entry to SOLVE; POST_WAIT waits for the update and the readback of nu
-// and the error flags.
+// Host side of the time steps in progress: the pre-solve kernels are queued
+// on entry to SOLVE, the update and the readback when the solve is done.
+// Steps are pipelined: once a step's update is queued, the next step's
+// work is queued at once, and the step's readback (nu, error flags, sine
+// amplitude) is read from one of two pinned slots when it has landed, so the
+// GPU does not idle between steps while the host reads and enqueues.
 struct StepRun {
-  enum Phase { IDLE, SOLVE, POST_WAIT };
+  enum Phase { IDLE, SOLVE };
   Phase phase = IDLE;
-  GmresResult gr{};
-  double nu = 1.0;
+  int to_start = 0;          // steps the driver still wants started
+  int pend = 0;              // queued steps whose readback is outstanding (<= 2)
+  int head = 0;              // slot of the oldest outstanding readback
+  GmresResult slot_gr[2]{};  // solve statistics of the step in each slot
+  GmresResult gr{};          // of the last completed step
+  double nu = 1.0;           // of the last completed step
 };
 
 // Outcome of one advance of a solve or a step.
@@ -346,7 +353,7 @@ struct gdc_handle {
   unsigned char* gm_host = nullptr;   // pinned: two status slots
   unsigned char* gm_host_dev = nullptr;   // the same memory as the device sees it
   hipEvent_t gm_ev[2] = {nullptr, nullptr};
-  hipEvent_t step_ev = nullptr;   // end of a step's update and readback
+  hipEvent_t step_ev[2] = {nullptr, nullptr};   // end of a step's update and readback, per slot
 
   bool dry = false;               // footprint query: count device bytes, touch no device
   size_t dev_bytes = 0;           // device memory held by the handle
@@ -362,6 +369,9 @@ struct gdc_handle {
   double* vbg = nullptr;
   double sine_scale = 0.0, sine_sum_coef = 0.0, sine_acc = 0.0;
   int sine_n = 0;
+  // sums over the steps completed since reset_errors, for the call's means
+  double its_acc = 0.0, nu_acc = 0.0;
+  int done_n = 0;
 
   ~gdc_handle() {
     for (void* p : allocs) (void)hipFree(p);
@@ -369,7 +379,8 @@ struct gdc_handle {
     if (gm_host) (void)hipHostFree(gm_host);
     for (hipEvent_t e : gm_ev)
       if (e) (void)hipEventDestroy(e);
-    if (step_ev) (void)hipEventDestroy(step_ev);
+    for (hipEvent_t e : step_ev)
+      if (e) (void)hipEventDestroy(e);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 
@@ -662,92 +673,122 @@ int predictor_dev(gdc_handle* h, uint64_t step) {
   return nu_reduce(h->dp, h->N, 0.5 * h->cfg.dt, h->nu, s);
 }
 
-// One time step of the resident state (h->Y, h->q) as a resumable run:
-// IDLE queues the noise, steps 2-4, the forces and the right-hand side and
-// starts the solve; SOLVE advances it; once it is done the update (step 6)
-// and the readback of nu and the error flags are queued, and POST_WAIT
-// reports ADV_DONE when they have landed.
+// Readback slot k of the pinned buffer: nu, the 4 error flags (2 doubles),
+// the sine sum.
+inline double* readback(gdc_handle* h, int k) { return h->hhost + 4 * HCOLS + 8 * k; }
+
+// Takes in the readback of the oldest queued step: statistics, error counts,
+// the step log.
+void retire_step(gdc_handle* h, bool gdc_scheme) {
+  StepRun& sr = h->sr;
+  const double* rb = readback(h, sr.head);
+  h->step_log.push_back(now_ms());
+  sr.gr = sr.slot_gr[sr.head];
+  sr.nu = gdc_scheme ? rb[0] : 1.0;
+  const int* fl = reinterpret_cast<const int*>(rb + 1);
+  if (fl[0]) ++h->n_overflow;
+  if (fl[1]) ++h->n_nonfinite;
+  if (!sr.gr.converged) ++h->n_notconv;
+  if (!(sr.nu > 0.0)) ++h->n_nonpos;
+  h->its_acc += sr.gr.its;
+  h->nu_acc += sr.nu;
+  ++h->done_n;
+  if (h->vbg) {
+    h->sine_acc += h->sine_scale + h->sine_sum_coef * rb[3];
+    ++h->sine_n;
+  }
+  sr.head ^= 1;
+  --sr.pend;
+}
+
+// Time steps of the resident state (h->Y, h->q) as a resumable, pipelined
+// run.  Each advance does one thing:
+//   - retires the oldest queued step whose readback has landed (ADV_DONE);
+//   - IDLE, with steps left to start: queues the noise, steps 2-4, the
+//     forces and the right-hand side and starts the solve;
+//   - SOLVE: advances the solve; when it is done, queues the update (step 6)
+//     and the readback into the next free slot and returns to IDLE, so the
+//     following step is queued behind it at once.
+// With block set and nothing else to do it waits for the oldest readback
+// or for the solve's next status.
 template <typename R>
 int step_advance(gdc_handle* h, bool block, int& adv) {
   hipStream_t s = h->stream;
   StepRun& sr = h->sr;
   const bool gdc_scheme = h->cfg.scheme == GDC_SCHEME_GDC;
   adv = ADV_PROGRESS;
-  switch (sr.phase) {
-    case StepRun::IDLE: {
-      const uint64_t step = h->step;
-      GDC_TRY(fill_zero(h->flags, 16, s));
-      GDC_TRY(make_fluct<R>(h, step));
-      const double* Ym = h->Y;
-      const double* qm = h->q;
-      if (gdc_scheme) {
-        GDC_TRY(predictor_dev<R>(h, step));
-        GDC_TRY(midpoint(h->bt, h->Y, h->q, h->calV, 0.5 * h->cfg.dt, h->Ym, h->qm, s));
-        Ym = h->Ym;
-        qm = h->qm;
-      }
-      GDC_TRY(blob_positions(h->bt, Ym, qm, h->rm, s));
-      GDC_TRY(forces_at(h, Ym, h->rm));
-      GDC_TRY(prepare_positions(h, h->rm));
-      GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_fl, h->v, h->M, h->geom.dV, nullptr, nullptr, nullptr, s,
-                        nullptr, h->trec));
-      if (h->vbg)
-        GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_sine, h->vbg, h->M, h->geom.dV, nullptr, nullptr,
-                          nullptr, s, nullptr, h->trec));
-      GDC_TRY(rhs_build(h->bt, qm, Ym, h->rm, h->v, h->vbg, h->sine_scale, h->F, h->cfg.forces.shear_rate,
-                        h->geom.L[1], h->rhs, s));
-      GDC_TRY(solve_begin<R>(h, Ym, qm, h->rm));
-      sr.phase = StepRun::SOLVE;
-      return GDC_OK;
-    }
-    case StepRun::SOLVE: {
-      int a = ADV_PROGRESS;
-      GDC_TRY(solve_advance<R>(h, block, a));
-      if (a != ADV_DONE) {
-        adv = a;
-        return GDC_OK;
-      }
-      sr.gr = h->sv.res;
-      h->sv.phase = SolveRun::IDLE;
-      if (h->vbg) {
-        // sum_i lambda_ix J[sin(k y)](r_i) of the midpoint solve, for v_x
-        GDC_TRY(blob_dot_x(h->sol, h->vbg, h->M, h->nu + 1, s));
-        GDC_HIP(hipMemcpyAsync(h->hhost + 4 * HCOLS + 3, h->nu + 1, sizeof(double), hipMemcpyDeviceToHost, s));
-      }
-      GDC_TRY(update(h->bt, h->Y, h->q, h->sol + 3LL * h->M, gdc_scheme ? h->nu : nullptr, h->cfg.dt,
-                     h->flags + 1, s));
-      GDC_HIP(hipMemcpyAsync(h->hhost + 4 * HCOLS, h->nu, sizeof(double), hipMemcpyDeviceToHost, s));
-      GDC_HIP(hipMemcpyAsync(h->hhost + 4 * HCOLS + 1, h->flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-      GDC_HIP(hipEventRecord(h->step_ev, s));
-      sr.phase = StepRun::POST_WAIT;
-      return GDC_OK;
-    }
-    case StepRun::POST_WAIT: {
-      bool ready = false;
-      GDC_TRY(event_done(h->step_ev, block, ready));
-      if (!ready) {
-        adv = ADV_BLOCKED;
-        return GDC_OK;
-      }
-      h->step_log.push_back(now_ms());
-      sr.nu = gdc_scheme ? h->hhost[4 * HCOLS] : 1.0;
-      const int* fl = reinterpret_cast<const int*>(h->hhost + 4 * HCOLS + 1);
-      if (fl[0]) ++h->n_overflow;
-      if (fl[1]) ++h->n_nonfinite;
-      if (!sr.gr.converged) ++h->n_notconv;
-      if (!(sr.nu > 0.0)) ++h->n_nonpos;
-      if (h->vbg) {
-        h->sine_acc += h->sine_scale + h->sine_sum_coef * h->hhost[4 * HCOLS + 3];
-        ++h->sine_n;
-      }
-      h->step += 1;
-      sr.phase = StepRun::IDLE;
+  if (sr.pend > 0) {
+    bool ready = false;
+    GDC_TRY(event_done(h->step_ev[sr.head], false, ready));
+    if (ready) {
+      retire_step(h, gdc_scheme);
       adv = ADV_DONE;
       return GDC_OK;
     }
   }
-  set_error("corrupt step state");
-  return GDC_EINVAL;
+  if (sr.phase == StepRun::IDLE && sr.to_start > 0 && sr.pend < 2) {
+    const uint64_t step = h->step;
+    GDC_TRY(fill_zero(h->flags, 16, s));
+    GDC_TRY(make_fluct<R>(h, step));
+    const double* Ym = h->Y;
+    const double* qm = h->q;
+    if (gdc_scheme) {
+      GDC_TRY(predictor_dev<R>(h, step));
+      GDC_TRY(midpoint(h->bt, h->Y, h->q, h->calV, 0.5 * h->cfg.dt, h->Ym, h->qm, s));
+      Ym = h->Ym;
+      qm = h->qm;
+    }
+    GDC_TRY(blob_positions(h->bt, Ym, qm, h->rm, s));
+    GDC_TRY(forces_at(h, Ym, h->rm));
+    GDC_TRY(prepare_positions(h, h->rm));
+    GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_fl, h->v, h->M, h->geom.dV, nullptr, nullptr, nullptr, s,
+                      nullptr, h->trec));
+    if (h->vbg)
+      GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_sine, h->vbg, h->M, h->geom.dV, nullptr, nullptr,
+                        nullptr, s, nullptr, h->trec));
+    GDC_TRY(rhs_build(h->bt, qm, Ym, h->rm, h->v, h->vbg, h->sine_scale, h->F, h->cfg.forces.shear_rate,
+                      h->geom.L[1], h->rhs, s));
+    GDC_TRY(solve_begin<R>(h, Ym, qm, h->rm));
+    --sr.to_start;
+    sr.phase = StepRun::SOLVE;
+    return GDC_OK;
+  }
+  if (sr.phase == StepRun::SOLVE) {
+    int a = ADV_PROGRESS;
+    // the oldest readback lands before any status of this solve, so a
+    // blocking wait goes to it first
+    GDC_TRY(solve_advance<R>(h, block && sr.pend == 0, a));
+    if (a == ADV_DONE) {
+      const int k = (sr.head + sr.pend) & 1;
+      double* rb = readback(h, k);
+      sr.slot_gr[k] = h->sv.res;
+      h->sv.phase = SolveRun::IDLE;
+      if (h->vbg) {
+        // sum_i lambda_ix J[sin(k y)](r_i) of the midpoint solve, for v_x
+        GDC_TRY(blob_dot_x(h->sol, h->vbg, h->M, h->nu + 1, s));
+        GDC_HIP(hipMemcpyAsync(rb + 3, h->nu + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+      }
+      GDC_TRY(update(h->bt, h->Y, h->q, h->sol + 3LL * h->M, gdc_scheme ? h->nu : nullptr, h->cfg.dt,
+                     h->flags + 1, s));
+      GDC_HIP(hipMemcpyAsync(rb, h->nu, sizeof(double), hipMemcpyDeviceToHost, s));
+      GDC_HIP(hipMemcpyAsync(rb + 1, h->flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+      GDC_HIP(hipEventRecord(h->step_ev[k], s));
+      ++sr.pend;
+      h->step += 1;   // the next step draws the next noise
+      sr.phase = StepRun::IDLE;
+      return GDC_OK;
+    }
+    if (a == ADV_PROGRESS) return GDC_OK;
+  }
+  if (block && sr.pend > 0) {
+    bool ready = false;
+    GDC_TRY(event_done(h->step_ev[sr.head], true, ready));
+    retire_step(h, gdc_scheme);
+    adv = ADV_DONE;
+    return GDC_OK;
+  }
+  adv = ADV_BLOCKED;
+  return GDC_OK;
 }
 
 int step_advance_any(gdc_handle* h, bool block, int& adv) {
@@ -775,12 +816,26 @@ void reset_errors(gdc_handle* h) {
   h->n_overflow = h->n_nonfinite = h->n_notconv = h->n_nonpos = 0;
   h->sine_acc = 0.0;
   h->sine_n = 0;
+  h->its_acc = h->nu_acc = 0.0;
+  h->done_n = 0;
 }
 
 double sine_mean(const gdc_handle* h) { return h->sine_n ? h->sine_acc / h->sine_n : 0.0; }
 
+// Statistics of the steps completed since reset_errors (the last step's
+// solve, the call's means).
+void fill_stats(const gdc_handle* h, gdc_stats* st) {
+  st->gmres_iterations = h->sr.gr.its;
+  st->gmres_relres = h->sr.gr.relres;
+  st->nu = h->sr.nu;
+  st->nu_nonpositive = h->n_nonpos;
+  st->sine_vx = sine_mean(h);
+  st->gmres_iterations_mean = h->done_n ? h->its_acc / h->done_n : 0.0;
+  st->nu_mean = h->done_n ? h->nu_acc / h->done_n : 0.0;
+}
+
 int require_idle(const gdc_handle* h) {
-  if (h->sr.phase != StepRun::IDLE || h->sv.phase != SolveRun::IDLE) {
+  if (h->sr.phase != StepRun::IDLE || h->sv.phase != SolveRun::IDLE || h->sr.pend != 0) {
     set_error("the handle has a step in flight: finish it with gdc_batch_step first");
     return GDC_EINVAL;
   }
@@ -1128,7 +1183,7 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
     GDC_HIP(hipHostMalloc((void**)&h->gm_host, 64, hipHostMallocMapped | hipHostMallocCoherent));
     GDC_HIP(hipHostGetDevicePointer((void**)&h->gm_host_dev, h->gm_host, 0));
     for (hipEvent_t& e : h->gm_ev) GDC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    GDC_HIP(hipEventCreateWithFlags(&h->step_ev, hipEventDisableTiming));
+    for (hipEvent_t& e : h->step_ev) GDC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
 
   if (h->precision == GDC_FP64) {
@@ -1270,21 +1325,23 @@ int gdc_step(gdc_handle* h, int n_steps, double* Y, double* q, int memspace, gdc
   GDC_TRY(load_state(h, Y, q, memspace));
   h->has_state = true;
   reset_errors(h);
-  for (int k = 0; k < n_steps; ++k) {
+  h->sr.to_start = n_steps;
+  for (int done = 0; done < n_steps;) {
     int adv = ADV_PROGRESS;
-    while (adv != ADV_DONE) GDC_TRY(step_advance_any(h, true, adv));
+    GDC_TRY(step_advance_any(h, true, adv));
+    if (adv == ADV_DONE) ++done;
+    if (adv == ADV_BLOCKED) {
+      set_error("step pipeline stalled");
+      return GDC_EINVAL;
+    }
   }
   GDC_TRY(copy_out(h, Y, h->Y, 3 * (size_t)h->N, memspace));
   GDC_TRY(copy_out(h, q, h->q, 4 * (size_t)h->N, memspace));
   GDC_TRY(finish(h));
   if (st) {
     st->steps_done = n_steps;
-    st->gmres_iterations = h->sr.gr.its;
-    st->gmres_relres = h->sr.gr.relres;
-    st->nu = h->sr.nu;
-    st->nu_nonpositive = h->n_nonpos;
+    fill_stats(h, st);
     st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    st->sine_vx = sine_mean(h);
   }
   return step_errors(h);
 }
@@ -1335,8 +1392,11 @@ int gdc_batch_step(gdc_handle* const* hs, int nh, int* steps, int until, double 
       set_error("gdc_batch_step: handle " + std::to_string(i) + " holds no state (gdc_set_state)");
       return GDC_EINVAL;
     }
-    if (steps[i] == 0 && hs[i]->sr.phase != StepRun::IDLE) {
-      set_error("gdc_batch_step: handle " + std::to_string(i) + " has a step in flight but no steps left");
+    // steps already queued by an earlier call count towards steps[i]
+    const int inflight = (hs[i]->sr.phase == StepRun::SOLVE ? 1 : 0) + hs[i]->sr.pend;
+    if (steps[i] < inflight) {
+      set_error("gdc_batch_step: handle " + std::to_string(i) + " has " + std::to_string(inflight) +
+                " steps in flight but only " + std::to_string(steps[i]) + " left");
       return GDC_EINVAL;
     }
     for (int j = 0; j < i; ++j)
@@ -1354,6 +1414,7 @@ int gdc_batch_step(gdc_handle* const* hs, int nh, int* steps, int until, double 
   for (int i = 0; i < nh; ++i) {
     watched[i] = steps[i] > 0;
     any_watched = any_watched || watched[i];
+    hs[i]->sr.to_start = steps[i] - (hs[i]->sr.phase == StepRun::SOLVE ? 1 : 0) - hs[i]->sr.pend;
     reset_errors(hs[i]);
   }
   int rc = GDC_OK;
@@ -1405,12 +1466,8 @@ int gdc_batch_step(gdc_handle* const* hs, int nh, int* steps, int until, double 
     gdc_handle* h = hs[i];
     if (st) {
       st[i].steps_done = done_here[i];
-      st[i].gmres_iterations = h->sr.gr.its;
-      st[i].gmres_relres = h->sr.gr.relres;
-      st[i].nu = h->sr.nu;
-      st[i].nu_nonpositive = h->n_nonpos;
+      fill_stats(h, &st[i]);
       st[i].ms = t_last[i];
-      st[i].sine_vx = sine_mean(h);
     }
     if (rc == GDC_OK && first_err == GDC_OK) {
       const int e = step_errors(h);

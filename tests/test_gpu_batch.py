@@ -96,6 +96,31 @@ def test_batch_step_equals_each_alone(lib, until):
         s.close()
 
 
+@pytest.mark.parametrize("k", [0, 2])
+def test_pipelined_steps_equal_single_steps(lib, k):
+    # one call of 5 steps queues each step behind the previous one's update
+    # and reads nu and the flags back later: the result, the means and the
+    # step log must be those of 5 calls of one step
+    w = _mix()[k]
+    Y0, q0 = wl.initial_state(w)
+    _say("pipeline", w.name)
+    s = lib.Suspension(**wl.library_kwargs(w, gmres_tol=1e-6))
+    Y1, q1 = Y0.copy(), q0.copy()
+    singles = [s.step(Y1, q1, 1) for _ in range(5)]
+    s.step_counter = 0
+    s.step_log()
+    Y5, q5 = Y0.copy(), q0.copy()
+    st = s.step(Y5, q5, 5)
+    log = s.step_log()
+    s.close()
+    assert np.array_equal(Y5, Y1) and np.array_equal(q5, q1)
+    assert st["steps_done"] == 5 and len(log) == 6 and np.all(np.diff(log) > 0)
+    assert st["gmres_iterations"] == singles[-1]["gmres_iterations"]
+    assert st["nu"] == singles[-1]["nu"]
+    assert st["gmres_iterations_mean"] == pytest.approx(np.mean([x["gmres_iterations"] for x in singles]))
+    assert st["nu_mean"] == pytest.approx(np.mean([x["nu"] for x in singles]))
+
+
 def test_batch_step_resumes_a_step_left_in_flight(lib):
     ws = _mix()[:3]
     ref = [_alone(lib, w, 2) for w in ws]
