@@ -1140,7 +1140,7 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
   GDC_TRY(h->alloc(&h->sol, nx + 2));
   GDC_TRY(h->alloc(&h->hdev, 5 * HCOLS));
   GDC_TRY(h->alloc(&h->partial, std::max((size_t)DOT_MAX_BLOCKS, (size_t)(h->nx / 1024 + 1)) * HCOLS));
-  GDC_TRY(h->alloc(&h->partial2, (size_t)(h->nx / 1024 + 1) * HCOLS));
+  GDC_TRY(h->alloc(&h->partial2, std::max((size_t)DOT_MAX_BLOCKS, (size_t)(h->nx / 1024 + 1)) * HCOLS));
   GDC_TRY(h->alloc(&h->dot_counter, 4));
   if (!h->dry) GDC_HIP(hipMemsetAsync(h->dot_counter, 0, 4 * sizeof(unsigned int), h->stream));
   {

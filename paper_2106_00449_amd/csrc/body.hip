@@ -346,47 +346,70 @@ __device__ void lsq_body(const BodyTables& B, int p, int s, const double* R, con
 }
 
 // Per body: calV_p and d_p (eq. FD or the term inside the expectation of
-// eq. rfd_div), so that nu = 1 + dt/2 sum_p d_p.
-__global__ void k_body_lsq_div(BodyTables B, const double* __restrict__ q, const double* __restrict__ v,
-                               const double* __restrict__ vd, const double* __restrict__ wrfd,
-                               double delta, int mode, double* __restrict__ calV, double* __restrict__ d) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= B.N) return;
+// eq. rfd_div), so that nu = 1 + dt/2 sum_p d_p.  A body takes 8 lanes: lane
+// 0 solves at the unperturbed state; with forward differences lanes 1-3
+// solve with the translated velocities and lanes 4-6 at the rotated
+// orientations, with RFD lane 1 at the random displacement.  Lane 0 adds the
+// quotients in the order translations, then rotations.
+constexpr int LSQ_LANES = 8;
+
+__global__ __launch_bounds__(64) void k_body_lsq_div(BodyTables B, const double* __restrict__ q,
+                                                     const double* __restrict__ v, const double* __restrict__ vd,
+                                                     const double* __restrict__ wrfd, double delta, int mode,
+                                                     double* __restrict__ calV, double* __restrict__ d) {
+  const int p = (blockIdx.x * blockDim.x + threadIdx.x) / LSQ_LANES;
+  const int j = threadIdx.x % LSQ_LANES;
+  if (p >= B.N) return;   // a body's lanes leave together
   const int s = B.body_shape[p];
   const double Lp = B.shape_Lp[s];
   const double* qp = q + 4LL * p;
-  double R[9], V0[6];
+  double R[9], V[6] = {0, 0, 0, 0, 0, 0};
   rotmat(qp, R);
-  lsq_body(B, p, s, R, v, 3, nullptr, 0, V0);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) calV[6LL * p + k] = V0[k];
-  double acc = 0.0;
-  if (mode == 0) {
-    for (int a = 0; a < 3; ++a) {  // translations: K unchanged, difference of v only
-      double dV[6];
-      lsq_body(B, p, s, R, vd + 3 * a, 18, nullptr, 0, dV);
-      acc += dV[a] / (delta * Lp);
+  if (j == 0) {
+    lsq_body(B, p, s, R, v, 3, nullptr, 0, V);
+  } else if (mode == 0 && j <= 3) {   // translation: K unchanged, difference of v only
+    lsq_body(B, p, s, R, vd + 3 * (j - 1), 18, nullptr, 0, V);
+  } else if ((mode == 0 && j <= 6) || (mode != 0 && j == 1)) {   // rotation: K and v both change
+    double u[3] = {0, 0, 0}, e[4], q2[4], R2[9];
+    if (mode == 0) {
+      u[j - 4] = delta;
+    } else {
+      const double* z = wrfd + 6LL * p;
+      u[0] = delta * z[3];
+      u[1] = delta * z[4];
+      u[2] = delta * z[5];
     }
-    for (int a = 0; a < 3; ++a) {  // rotations: K and v both change
-      double u[3] = {0, 0, 0}, e[4], q2[4], R2[9], V1[6];
-      u[a] = delta;
-      qexp(u, e);
-      qmul(e, qp, q2);
-      rotmat(q2, R2);
-      lsq_body(B, p, s, R2, v, 3, vd + 9 + 3 * a, 18, V1);
-      acc += (V1[3 + a] - V0[3 + a]) / delta;
-    }
-  } else {
-    const double* z = wrfd + 6LL * p;
-    double u[3] = {delta * z[3], delta * z[4], delta * z[5]}, e[4], q2[4], R2[9], V1[6];
     qexp(u, e);
     qmul(e, qp, q2);
     rotmat(q2, R2);
-    lsq_body(B, p, s, R2, v, 3, vd, 3, V1);
-    acc = (z[0] * (V1[0] - V0[0]) + z[1] * (V1[1] - V0[1]) + z[2] * (V1[2] - V0[2])) / (delta * Lp) +
-          (z[3] * (V1[3] - V0[3]) + z[4] * (V1[4] - V0[4]) + z[5] * (V1[5] - V0[5])) / delta;
+    lsq_body(B, p, s, R2, v, 3, mode == 0 ? vd + 9 + 3 * (j - 4) : vd, mode == 0 ? 18 : 3, V);
   }
-  d[p] = acc;
+  double V0[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) V0[k] = __shfl(V[k], 0, LSQ_LANES);
+  if (j == 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) calV[6LL * p + k] = V0[k];
+  }
+  if (mode == 0) {
+    double c = 0.0;
+    if (j >= 1 && j <= 3) {
+      const double dv = j == 1 ? V[0] : j == 2 ? V[1] : V[2];
+      c = dv / (delta * Lp);
+    } else if (j >= 4 && j <= 6) {
+      const double v1 = j == 4 ? V[3] : j == 5 ? V[4] : V[5];
+      const double v0 = j == 4 ? V0[3] : j == 5 ? V0[4] : V0[5];
+      c = (v1 - v0) / delta;
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 1; t <= 6; ++t) acc += __shfl(c, t, LSQ_LANES);
+    if (j == 0) d[p] = acc;
+  } else if (j == 1) {
+    const double* z = wrfd + 6LL * p;
+    d[p] = (z[0] * (V[0] - V0[0]) + z[1] * (V[1] - V0[1]) + z[2] * (V[2] - V0[2])) / (delta * Lp) +
+           (z[3] * (V[3] - V0[3]) + z[4] * (V[4] - V0[4]) + z[5] * (V[5] - V0[5])) / delta;
+  }
 }
 
 // nu = 1 + half_dt * sum d, one block, fixed summation order.
@@ -507,48 +530,60 @@ __global__ void k_bin_blobs(CellGrid C, int M, const double* __restrict__ r, int
 }
 
 // Harmonic repulsion V = k/2 (r - b)^2 for r < b between blobs of different
-// bodies; each blob sums its own force (no atomics).
-__global__ void k_steric(CellGrid C, BodyTables B, const double* __restrict__ r, const int* __restrict__ count,
-                         const int* __restrict__ list, int cap, double kk, double b, double* __restrict__ f) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= B.M) return;
+// bodies; each blob sums its own force (no atomics).  A blob takes 32 lanes,
+// lane c < 27 scanning neighbour cell c of its 3 x 3 x 3 block, and the
+// lanes' partial forces are added across the half wave.
+constexpr int STERIC_LANES = 32;
+
+__global__ __launch_bounds__(NT) void k_steric(CellGrid C, BodyTables B, const double* __restrict__ r,
+                                               const int* __restrict__ count, const int* __restrict__ list, int cap,
+                                               double kk, double b, double* __restrict__ f) {
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) / STERIC_LANES;
+  const int lane = threadIdx.x % STERIC_LANES;
+  if (i >= B.M) return;   // whole half waves leave together
   double xi[3];
   const int ci = cell_of(C, r + 3LL * i, xi);
-  int c3[3] = {ci / (C.nc[1] * C.nc[2]), (ci / C.nc[2]) % C.nc[1], ci % C.nc[2]};
-  const int bi = B.blob_body[i];
   double fx = 0, fy = 0, fz = 0;
-  for (int dz = -1; dz <= 1; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int a0 = (c3[0] + dz + C.nc[0]) % C.nc[0];
-        const int a1 = (c3[1] + dy + C.nc[1]) % C.nc[1];
-        const int a2 = (c3[2] + dx + C.nc[2]) % C.nc[2];
-        const int cc = (a0 * C.nc[1] + a1) * C.nc[2] + a2;
-        const int n = min(count[cc], cap);
-        for (int s = 0; s < n; ++s) {
-          const int j = list[(long long)cc * cap + s];
-          if (j == i || B.blob_body[j] == bi) continue;
-          double d[3];
+  if (lane < 27) {
+    const int c3[3] = {ci / (C.nc[1] * C.nc[2]), (ci / C.nc[2]) % C.nc[1], ci % C.nc[2]};
+    const int a0 = (c3[0] + lane / 9 - 1 + C.nc[0]) % C.nc[0];
+    const int a1 = (c3[1] + (lane / 3) % 3 - 1 + C.nc[1]) % C.nc[1];
+    const int a2 = (c3[2] + lane % 3 - 1 + C.nc[2]) % C.nc[2];
+    const int cc = (a0 * C.nc[1] + a1) * C.nc[2] + a2;
+    const int n = min(count[cc], cap);
+    const int bi = B.blob_body[i];
+    for (int s = 0; s < n; ++s) {
+      const int j = list[(long long)cc * cap + s];
+      if (j == i || B.blob_body[j] == bi) continue;
+      double d[3];
 #pragma unroll
-          for (int e = 0; e < 3; ++e) {
-            const double xj = r[3LL * j + e] - C.L[e] * floor(r[3LL * j + e] / C.L[e]);
-            double t = xi[e] - xj;
-            t -= C.L[e] * rint(t / C.L[e]);
-            d[e] = t;
-          }
-          const double dist2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-          if (dist2 < b * b && dist2 > 0.0) {
-            const double dist = sqrt(dist2);
-            const double m = kk * (b - dist) / dist;
-            fx += m * d[0];
-            fy += m * d[1];
-            fz += m * d[2];
-          }
-        }
+      for (int e = 0; e < 3; ++e) {
+        const double xj = r[3LL * j + e] - C.L[e] * floor(r[3LL * j + e] / C.L[e]);
+        double t = xi[e] - xj;
+        t -= C.L[e] * rint(t / C.L[e]);
+        d[e] = t;
       }
-  f[3LL * i] = fx;
-  f[3LL * i + 1] = fy;
-  f[3LL * i + 2] = fz;
+      const double dist2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      if (dist2 < b * b && dist2 > 0.0) {
+        const double dist = sqrt(dist2);
+        const double m = kk * (b - dist) / dist;
+        fx += m * d[0];
+        fy += m * d[1];
+        fz += m * d[2];
+      }
+    }
+  }
+#pragma unroll
+  for (int o = STERIC_LANES / 2; o > 0; o >>= 1) {
+    fx += __shfl_xor(fx, o, STERIC_LANES);
+    fy += __shfl_xor(fy, o, STERIC_LANES);
+    fz += __shfl_xor(fz, o, STERIC_LANES);
+  }
+  if (lane == 0) {
+    f[3LL * i] = fx;
+    f[3LL * i + 1] = fy;
+    f[3LL * i + 2] = fz;
+  }
 }
 
 __global__ void k_body_forces(BodyTables B, const double* __restrict__ Y, const double* __restrict__ r,
@@ -606,7 +641,8 @@ int fd_displacements(const BodyTables& b, const double* q, double delta, int mod
 
 int body_lsq_div(const BodyTables& b, const double* q, const double* v, const double* vd, const double* wrfd,
                  double delta, int mode, double* calV, double* d, hipStream_t s) {
-  hipLaunchKernelGGL(k_body_lsq_div, dim3(nblk(b.N, 128)), dim3(128), 0, s, b, q, v, vd, wrfd, delta, mode, calV, d);
+  hipLaunchKernelGGL(k_body_lsq_div, dim3(nblk((long long)b.N * LSQ_LANES, 64)), dim3(64), 0, s, b, q, v, vd, wrfd,
+                     delta, mode, calV, d);
   return check_launch("k_body_lsq_div");
 }
 
@@ -649,7 +685,8 @@ int steric_forces(const BodyTables& b, const GridGeom& g, const double* r, doubl
   GDC_TRY(fill_zero(cell_count, ((size_t)ncell * sizeof(int) + 15) / 16 * 16, s));
   hipLaunchKernelGGL(k_bin_blobs, dim3(nblk(b.M)), dim3(NT), 0, s, C, b.M, r, cell_count, cell_list, cap, overflow);
   GDC_TRY(check_launch("k_bin_blobs"));
-  hipLaunchKernelGGL(k_steric, dim3(nblk(b.M)), dim3(NT), 0, s, C, b, r, cell_count, cell_list, cap, k, cutoff, fblob);
+  hipLaunchKernelGGL(k_steric, dim3(nblk((long long)b.M * STERIC_LANES)), dim3(NT), 0, s, C, b, r, cell_count,
+                     cell_list, cap, k, cutoff, fblob);
   return check_launch("k_steric");
 }
 

@@ -226,6 +226,32 @@ __device__ __forceinline__ void load_twiddles(Cx<R>* tw, const Cx<R>* __restrict
   for (int k = threadIdx.x; k < N; k += NTH) tw[k] = twg[k];
 }
 
+// Moves ITEMS items e = tid, tid + NTH, ... from ld(e) to st(e, value) with
+// the loads of a chunk issued before any of its stores, so that a thread has
+// up to 128 bytes of global loads in flight instead of one at a time.
+template <int ITEMS, int NTH, typename Ld, typename St>
+__device__ __forceinline__ void staged_copy(Ld ld, St st) {
+  using T = decltype(ld(0));
+  constexpr int PER = (ITEMS + NTH - 1) / NTH;
+  constexpr int CH0 = 128 / (int)sizeof(T) > 0 ? 128 / (int)sizeof(T) : 1;
+  constexpr int CH = CH0 < PER ? CH0 : PER;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int m0 = 0; m0 < PER; m0 += CH) {
+    T v[CH];
+#pragma unroll
+    for (int m = 0; m < CH; ++m) {
+      const int e = tid + (m0 + m) * NTH;
+      if (m0 + m < PER && (ITEMS % NTH == 0 || e < ITEMS)) v[m] = ld(e);
+    }
+#pragma unroll
+    for (int m = 0; m < CH; ++m) {
+      const int e = tid + (m0 + m) * NTH;
+      if (m0 + m < PER && (ITEMS % NTH == 0 || e < ITEMS)) st(e, v[m]);
+    }
+  }
+}
+
 // ------------------------------------------------------------ pass A: R2C, axis 2
 // Two real lines packed as one complex line z = a + i b; after the FFT,
 // A(k) = (Z(k) + conj Z(N-k))/2 and B(k) = (Z(k) - conj Z(N-k))/(2i).
@@ -242,12 +268,17 @@ __global__ __launch_bounds__(NTH) void k_r2c_axis2(const R* __restrict__ in, Cx<
   const int nl = min(TL, n1 - i1b);
   load_twiddles<R, N2, NTH>(tw, twg);
   const R* src = in + (long long)c * n0 * n1 * N2 + field_plane_off(tiled, n1, N2, i0);
-  for (int e = tid; e < NLc * N2; e += NTH) {
-    const int p = e / N2, x = e - p * N2;
-    const R re = (2 * p < nl) ? src[field_col_off(tiled, N2, i1b + 2 * p, x)] : R(0);
-    const R im = (2 * p + 1 < nl) ? src[field_col_off(tiled, N2, i1b + 2 * p + 1, x)] : R(0);
-    buf[p * LS + x] = Cx<R>{re, im};
-  }
+  staged_copy<NLc * N2, NTH>(
+      [&](int e) {
+        const int p = e / N2, x = e - p * N2;
+        const R re = (2 * p < nl) ? src[field_col_off(tiled, N2, i1b + 2 * p, x)] : R(0);
+        const R im = (2 * p + 1 < nl) ? src[field_col_off(tiled, N2, i1b + 2 * p + 1, x)] : R(0);
+        return Cx<R>{re, im};
+      },
+      [&](int e, Cx<R> z) {
+        const int p = e / N2, x = e - p * N2;
+        buf[p * LS + x] = z;
+      });
   __syncthreads();
   fft_lines<R, N2, NLc, LS, false, NTH>(buf, tw);
   Cx<R>* dst = X + ((long long)c * n0 + i0) * H * n1 + i1b;
@@ -280,10 +311,15 @@ __global__ __launch_bounds__(NTH) void k_fwd_axis1(const Cx<R>* __restrict__ X, 
   const int c = blockIdx.z, k2 = blockIdx.y, i0b = blockIdx.x * TL;
   const int nl = min(TL, n0 - i0b);
   load_twiddles<R, N1, NTH>(tw, twg);
-  for (int e = tid; e < TL * N1; e += NTH) {
-    const int t = e / N1, x = e - t * N1;
-    buf[t * LS + x] = (t < nl) ? X[(((long long)c * n0 + i0b + t) * H + k2) * N1 + x] : Cx<R>{R(0), R(0)};
-  }
+  staged_copy<TL * N1, NTH>(
+      [&](int e) {
+        const int t = e / N1, x = e - t * N1;
+        return (t < nl) ? X[(((long long)c * n0 + i0b + t) * H + k2) * N1 + x] : Cx<R>{R(0), R(0)};
+      },
+      [&](int e, Cx<R> z) {
+        const int t = e / N1, x = e - t * N1;
+        buf[t * LS + x] = z;
+      });
   __syncthreads();
   fft_lines<R, N1, TL, LS, false, NTH>(buf, tw);
   for (int e = tid; e < N1 * TL; e += NTH) {
@@ -305,10 +341,15 @@ __global__ __launch_bounds__(NTH) void k_inv_axis1(const Cx<R>* __restrict__ Y, 
   const int c = blockIdx.z, k2 = blockIdx.y, i0b = blockIdx.x * TL;
   const int nl = min(TL, n0 - i0b);
   load_twiddles<R, N1, NTH>(tw, twg);
-  for (int e = tid; e < N1 * TL; e += NTH) {
-    const int k1 = e / TL, t = e - k1 * TL;
-    buf[t * LS + k1] = (t < nl) ? Y[(((long long)c * H + k2) * N1 + k1) * n0 + i0b + t] : Cx<R>{R(0), R(0)};
-  }
+  staged_copy<N1 * TL, NTH>(
+      [&](int e) {
+        const int k1 = e / TL, t = e - k1 * TL;
+        return (t < nl) ? Y[(((long long)c * H + k2) * N1 + k1) * n0 + i0b + t] : Cx<R>{R(0), R(0)};
+      },
+      [&](int e, Cx<R> z) {
+        const int k1 = e / TL, t = e - k1 * TL;
+        buf[t * LS + k1] = z;
+      });
   __syncthreads();
   fft_lines<R, N1, TL, LS, true, NTH>(buf, tw);
   for (int e = tid; e < TL * N1; e += NTH) {
@@ -335,18 +376,26 @@ __global__ __launch_bounds__(NTH) void k_c2r_axis2(const Cx<R>* __restrict__ X, 
   load_twiddles<R, N2, NTH>(tw, twg);
   const Cx<R>* src = X + ((long long)c * n0 + i0) * H * n1 + i1b;
   const Cx<R> zero{R(0), R(0)};
-  for (int e = tid; e < H * NLc; e += NTH) {
-    const int k = e / NLc, p = e - k * NLc;
-    const Cx<R> a = (2 * p < nl) ? src[(long long)k * n1 + 2 * p] : zero;
-    const Cx<R> b = (2 * p + 1 < nl) ? src[(long long)k * n1 + 2 * p + 1] : zero;
-    if (k == 0) {
-      buf[p * LS] = Cx<R>{a.x, b.x};
-      buf[p * LS + H] = zero;
-    } else {
-      buf[p * LS + k] = Cx<R>{a.x - b.y, a.y + b.x};
-      buf[p * LS + N2 - k] = Cx<R>{a.x + b.y, b.x - a.y};
-    }
-  }
+  struct Pair {
+    Cx<R> a, b;
+  };
+  staged_copy<H * NLc, NTH>(
+      [&](int e) {
+        const int k = e / NLc, p = e - k * NLc;
+        return Pair{(2 * p < nl) ? src[(long long)k * n1 + 2 * p] : zero,
+                    (2 * p + 1 < nl) ? src[(long long)k * n1 + 2 * p + 1] : zero};
+      },
+      [&](int e, Pair v) {
+        const int k = e / NLc, p = e - k * NLc;
+        const Cx<R> a = v.a, b = v.b;
+        if (k == 0) {
+          buf[p * LS] = Cx<R>{a.x, b.x};
+          buf[p * LS + H] = zero;
+        } else {
+          buf[p * LS + k] = Cx<R>{a.x - b.y, a.y + b.x};
+          buf[p * LS + N2 - k] = Cx<R>{a.x + b.y, b.x - a.y};
+        }
+      });
   __syncthreads();
   fft_lines<R, N2, NLc, LS, true, NTH>(buf, tw);
   R* dst = out + (long long)c * n0 * n1 * N2 + field_plane_off(tiled, n1, N2, i0);
@@ -445,11 +494,16 @@ __global__ __launch_bounds__(NTH) void k_axis0_project(Cx<R>* __restrict__ Y, co
   const int H = P.n2h, n1 = P.n1;
   load_twiddles<R, N0, NTH>(tw, twg);
   if (!NOISE) {
-    for (int e = tid; e < NLn * N0; e += NTH) {
-      const int l = e / N0, x = e - l * N0;
-      const int c = l / TC, t = l - c * TC;
-      buf[l * LS + x] = (t < nl) ? Y[(((long long)c * H + k2) * n1 + k1b + t) * N0 + x] : Cx<R>{R(0), R(0)};
-    }
+    staged_copy<NLn * N0, NTH>(
+        [&](int e) {
+          const int l = e / N0, x = e - l * N0;
+          const int c = l / TC, t = l - c * TC;
+          return (t < nl) ? Y[(((long long)c * H + k2) * n1 + k1b + t) * N0 + x] : Cx<R>{R(0), R(0)};
+        },
+        [&](int e, Cx<R> z) {
+          const int l = e / N0, x = e - l * N0;
+          buf[l * LS + x] = z;
+        });
     __syncthreads();
     fft_lines<R, N0, NLn, LS, false, NTH>(buf, tw);
   } else {
@@ -535,10 +589,15 @@ __global__ __launch_bounds__(NTH) void k_plane_fwd(const R* __restrict__ in, Cx<
   load_twiddles<R, N1, NTH>(tw1, tw1g);
   load_twiddles<R, N2, NTH>(tw2, tw2g);
   const R* src = in + (long long)c * n0 * N1 * N2 + field_plane_off(tiled, N1, N2, i0);
-  for (int e = tid; e < NP * N2; e += NTH) {
-    const int p = e / N2, x = e - p * N2;
-    buf[p * L::LA + x] = Cx<R>{src[field_col_off(tiled, N2, 2 * p, x)], src[field_col_off(tiled, N2, 2 * p + 1, x)]};
-  }
+  staged_copy<NP * N2, NTH>(
+      [&](int e) {
+        const int p = e / N2, x = e - p * N2;
+        return Cx<R>{src[field_col_off(tiled, N2, 2 * p, x)], src[field_col_off(tiled, N2, 2 * p + 1, x)]};
+      },
+      [&](int e, Cx<R> z) {
+        const int p = e / N2, x = e - p * N2;
+        buf[p * L::LA + x] = z;
+      });
   __syncthreads();
   fft_lines<R, N2, NP, L::LA, false, NTH>(buf, tw2);
   // unpack into lines k2 (length N1, index i1)
@@ -568,10 +627,12 @@ __global__ __launch_bounds__(NTH) void k_plane_fwd(const R* __restrict__ in, Cx<
   __syncthreads();
   fft_lines<R, N1, H, L::LB, false, NTH>(buf, tw1);
   Cx<R>* dst = Z + ((long long)c * n0 + i0) * H * N1;
-  for (int e = tid; e < H * N1; e += NTH) {
-    const int k = e / N1, x = e - k * N1;
-    dst[e] = buf[k * L::LB + x];
-  }
+  staged_copy<H * N1, NTH>(
+      [&](int e) {
+        const int k = e / N1, x = e - k * N1;
+        return buf[k * L::LB + x];
+      },
+      [&](int e, Cx<R> z) { dst[e] = z; });
 }
 
 // Inverse of k_plane_fwd: iFFT along axis 1, then rows (2p, 2p+1) rebuilt as
@@ -591,10 +652,11 @@ __global__ __launch_bounds__(NTH) void k_plane_inv(const Cx<R>* __restrict__ Z, 
   load_twiddles<R, N1, NTH>(tw1, tw1g);
   load_twiddles<R, N2, NTH>(tw2, tw2g);
   const Cx<R>* src = Z + ((long long)c * n0 + i0) * H * N1;
-  for (int e = tid; e < H * N1; e += NTH) {
-    const int k = e / N1, x = e - k * N1;
-    buf[k * L::LB + x] = src[e];
-  }
+  staged_copy<H * N1, NTH>([&](int e) { return src[e]; },
+                           [&](int e, Cx<R> z) {
+                             const int k = e / N1, x = e - k * N1;
+                             buf[k * L::LB + x] = z;
+                           });
   __syncthreads();
   fft_lines<R, N1, H, L::LB, true, NTH>(buf, tw1);
   constexpr int ITEMS = NP * H, PER = (ITEMS + NTH - 1) / NTH;
@@ -628,12 +690,16 @@ __global__ __launch_bounds__(NTH) void k_plane_inv(const Cx<R>* __restrict__ Z, 
   __syncthreads();
   fft_lines<R, N2, NP, L::LA, true, NTH>(buf, tw2);
   R* dst = out + (long long)c * n0 * N1 * N2 + field_plane_off(tiled, N1, N2, i0);
-  for (int e = tid; e < NP * N2; e += NTH) {
-    const int p = e / N2, x = e - p * N2;
-    const Cx<R> z = buf[p * L::LA + x];
-    dst[field_col_off(tiled, N2, 2 * p, x)] = z.x;
-    dst[field_col_off(tiled, N2, 2 * p + 1, x)] = z.y;
-  }
+  staged_copy<NP * N2, NTH>(
+      [&](int e) {
+        const int p = e / N2, x = e - p * N2;
+        return buf[p * L::LA + x];
+      },
+      [&](int e, Cx<R> z) {
+        const int p = e / N2, x = e - p * N2;
+        dst[field_col_off(tiled, N2, 2 * p, x)] = z.x;
+        dst[field_col_off(tiled, N2, 2 * p + 1, x)] = z.y;
+      });
 }
 
 // Pass C on the plane layout Z[c][i0][k2][k1]: TCP consecutive k1 lines of
@@ -653,12 +719,17 @@ __global__ __launch_bounds__(NTH) void k_axis0_plane(Cx<R>* __restrict__ Z, cons
   const int H = P.n2h, n1 = P.n1;
   load_twiddles<R, N0, NTH>(tw, twg);
   if (!NOISE) {
-    for (int e = tid; e < NLn * N0; e += NTH) {
-      const int t = e % TCP, rest = e / TCP;
-      const int x = rest % N0, c = rest / N0;
-      buf[(c * TCP + t) * LS + x] =
-          (t < nl) ? Z[(((long long)c * N0 + x) * H + k2) * n1 + k1b + t] : Cx<R>{R(0), R(0)};
-    }
+    staged_copy<NLn * N0, NTH>(
+        [&](int e) {
+          const int t = e % TCP, rest = e / TCP;
+          const int x = rest % N0, c = rest / N0;
+          return (t < nl) ? Z[(((long long)c * N0 + x) * H + k2) * n1 + k1b + t] : Cx<R>{R(0), R(0)};
+        },
+        [&](int e, Cx<R> z) {
+          const int t = e % TCP, rest = e / TCP;
+          const int x = rest % N0, c = rest / N0;
+          buf[(c * TCP + t) * LS + x] = z;
+        });
     __syncthreads();
     fft_lines<R, N0, NLn, LS, false, NTH>(buf, tw);
   } else {
@@ -698,11 +769,17 @@ __global__ __launch_bounds__(NTH) void k_axis0_plane(Cx<R>* __restrict__ Z, cons
   }
   __syncthreads();
   fft_lines<R, N0, NLn, LS, true, NTH>(buf, tw);
-  for (int e = tid; e < NLn * N0; e += NTH) {
-    const int t = e % TCP, rest = e / TCP;
-    const int x = rest % N0, c = rest / N0;
-    if (t < nl) Z[(((long long)c * N0 + x) * H + k2) * n1 + k1b + t] = buf[(c * TCP + t) * LS + x];
-  }
+  staged_copy<NLn * N0, NTH>(
+      [&](int e) {
+        const int t = e % TCP, rest = e / TCP;
+        const int x = rest % N0, c = rest / N0;
+        return buf[(c * TCP + t) * LS + x];
+      },
+      [&](int e, Cx<R> z) {
+        const int t = e % TCP, rest = e / TCP;
+        const int x = rest % N0, c = rest / N0;
+        if (t < nl) Z[(((long long)c * N0 + x) * H + k2) * n1 + k1b + t] = z;
+      });
 }
 
 // ------------------------------------------------------------ dispatch

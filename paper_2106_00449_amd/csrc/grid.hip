@@ -636,6 +636,26 @@ __global__ __launch_bounds__(NT) void k_spread_prep(GridGeom G, TileGeom T, cons
 // a fixed summation order: results repeat bit for bit.
 constexpr int NTS = 512;   // threads of a spreading workgroup
 
+// Marks values as needed here: the compiler keeps their loads ahead of this
+// point instead of moving each into the branch that uses it.
+template <typename R>
+__device__ __forceinline__ void pin_values(R (&a)[8], R (&b)[8], R c, R d, R e, R f) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) asm volatile("" ::"v"(a[k]), "v"(b[k]));
+  asm volatile("" ::"v"(c), "v"(d), "v"(e), "v"(f));
+}
+
+// Value of v in lane l (l wave-uniform), without LDS.
+__device__ __forceinline__ float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <typename R>
 __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, const HitTab<R>* __restrict__ tabs,
                                                    const int* __restrict__ tab_start,
@@ -645,7 +665,9 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
   if (skip && *skip) return;
   constexpr int HR = 64;                // hits per round
   constexpr int TX = 8, TZ = 32;
-  constexpr int TZP = sizeof(R) == 4 ? TZ + 1 : TZ;   // staged row stride (FP32: padded against bank conflicts)
+  // staged row stride: the 8 rows (axis 1) a wave writes for one plane start
+  // 40 words apart, 8 distinct bank groups (FP32); FP64 rows are 2 words per value
+  constexpr int TZP = sizeof(R) == 4 ? TZ + 8 : TZ;
   constexpr int STAGE = 3 * TX * TX * TZP;
   constexpr int TABR = HR * (int)(sizeof(HitTab<R>) / sizeof(R));
   constexpr int SH = TABR > STAGE ? TABR : STAGE;
@@ -665,35 +687,70 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
 #pragma unroll
   for (int k = 0; k < TX; ++k) acc[k][0] = acc[k][1] = acc[k][2] = R(0);
   constexpr int V16 = (int)(sizeof(HitTab<R>) / 16);
+  constexpr int LPT = (HR * V16 + NTS - 1) / NTS;   // 16-byte table loads per thread and round
   for (int hb = 0; hb < cnt; hb += HR) {
     const int nr = min(HR, cnt - hb);
+    // the round's table loads and the forces of its hits (record position,
+    // then force) are all in flight before the first LDS store
     const uint4* src = reinterpret_cast<const uint4*>(tabs + start + hb);
     uint4* dstv = reinterpret_cast<uint4*>(sh);
-    for (int v = tid; v < nr * V16; v += NTS) dstv[v] = src[v];
-    __syncthreads();
-    if (tid < nr) {
-      const int p = tab[tid].pos, b = tab[tid].blob;
+    uint4 tv[LPT];
 #pragma unroll
-      for (int q = 0; q < 3; ++q) h_l[tid][q] = R(lam_sorted ? lam_sorted[3LL * p + q] : lam[3LL * b + q]);
+    for (int m = 0; m < LPT; ++m) {
+      const int v = tid + m * NTS;
+      if (v < nr * V16) tv[m] = src[v];
+    }
+    double lv[3] = {0.0, 0.0, 0.0};
+    if (tid < nr) {
+      const HitTab<R>& g = tabs[start + hb + tid];
+      const long long base = lam_sorted ? 3LL * g.pos : 3LL * g.blob;
+      const double* ls = lam_sorted ? lam_sorted : lam;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) lv[q] = ls[base + q];
+    }
+#pragma unroll
+    for (int m = 0; m < LPT; ++m) {
+      const int v = tid + m * NTS;
+      if (v < nr * V16) dstv[v] = tv[m];
+    }
+    if (tid < nr) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) h_l[tid][q] = R(lv[q]);
     }
     __syncthreads();
-    if (live) {
-      for (int h = half; h < nr; h += 2) {
-        const HitTab<R>& t = tab[h];
-        const int hm = t.mask;
-        if (!((hm >> wave) & 1)) continue;
-        const R s12 = t.s1[j1] + t.sz[z];
-        if (s12 > rc2) continue;
-        const R f12 = t.f1[j1] * t.fz[z];
-        const R l0 = h_l[h][0], l1 = h_l[h][1], l2 = h_l[h][2];
+    // lane h of every wave holds hit h's mask and force for the round; the
+    // hit loop takes them with readlane (no LDS round trip per hit)
+    const int hr = lane < nr ? lane : 0;
+    const int hmask = lane < nr ? tab[hr].mask : 0;
+    const R hl0 = h_l[hr][0], hl1 = h_l[hr][1], hl2 = h_l[hr][2];
+    // the loop runs with every lane of the wave active up to the per-lane
+    // test below, so each readlane sees values all lanes hold
+    for (int h = half; h < nr; h += 2) {
+      const int hm = __builtin_amdgcn_readlane(hmask, h);
+      if (!((hm >> wave) & 1)) continue;
+      const R l0 = read_lane(hl0, h), l1 = read_lane(hl1, h), l2 = read_lane(hl2, h);
+      const HitTab<R>& t = tab[h];
+      // every table value of the hit in registers before any test, so that
+      // one LDS wait serves the hit (a load left under a test would cost a
+      // round trip per plane)
+      R f0v[TX], s0v[TX];
 #pragma unroll
-        for (int k = 0; k < TX; ++k) {
-          if (!((hm >> (8 + k)) & 1)) continue;
-          const R w = (t.s0[k] + s12 <= rc2) ? f12 * t.f0[k] : R(0);
-          acc[k][0] += w * l0;
-          acc[k][1] += w * l1;
-          acc[k][2] += w * l2;
-        }
+      for (int k = 0; k < TX; ++k) {
+        f0v[k] = t.f0[k];
+        s0v[k] = t.s0[k];
+      }
+      const R s1v = t.s1[j1], szv = t.sz[z], f1v = t.f1[j1], fzv = t.fz[z];
+      pin_values(f0v, s0v, s1v, szv, f1v, fzv);
+      const R s12 = s1v + szv;
+      if (!live || s12 > rc2) continue;
+      const R f12 = f1v * fzv;
+#pragma unroll
+      for (int k = 0; k < TX; ++k) {
+        if (!((hm >> (8 + k)) & 1)) continue;
+        const R w = (s0v[k] + s12 <= rc2) ? f12 * f0v[k] : R(0);
+        acc[k][0] += w * l0;
+        acc[k][1] += w * l1;
+        acc[k][2] += w * l2;
       }
     }
     __syncthreads();

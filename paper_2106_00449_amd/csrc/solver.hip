@@ -71,7 +71,10 @@ __global__ __launch_bounds__(NT) void k_multi_dot(const double* __restrict__ V, 
   if (threadIdx.x == 0) *counter = 0u;
 }
 
-constexpr int CHUNK = 1024;   // vector elements per block in the Arnoldi kernels
+// Vector elements per block in the Arnoldi kernels: EPT elements per thread,
+// 1 for vectors of up to DOT_MAX_BLOCKS * NT elements (more blocks, shorter
+// dependency chains), else 4.
+constexpr int EPT_LONG = 4;
 
 // Sum over waves of a per-wave value, one barrier; valid in thread 0.
 __device__ __forceinline__ void wave_reduce_to(double v, double* slot) {
@@ -83,6 +86,7 @@ __device__ __forceinline__ void wave_reduce_to(double v, double* slot) {
 // partial[j * gridDim.x + c] = sum over chunk c of V_j . w, grid (nchunk, kk);
 // row j = k (when kk = k + 1) is w . w.  One vector per block keeps every
 // load of a block independent.
+template <int EPT>
 __global__ __launch_bounds__(NT) void k_dot2d(const double* __restrict__ V, long long ld, int k,
                                               const double* __restrict__ w, long long n,
                                               double* __restrict__ partial, const int* __restrict__ skip) {
@@ -90,10 +94,10 @@ __global__ __launch_bounds__(NT) void k_dot2d(const double* __restrict__ V, long
   __shared__ double sh[NT / 64];
   const int j = blockIdx.y;
   const double* v = j < k ? V + ld * j : w;
-  const long long lo = (long long)blockIdx.x * CHUNK;
+  const long long lo = (long long)blockIdx.x * (EPT * NT);
   double a = 0.0;
 #pragma unroll
-  for (int m = 0; m < CHUNK / NT; ++m) {
+  for (int m = 0; m < EPT; ++m) {
     const long long e = lo + threadIdx.x + m * NT;
     if (e < n) a += v[e] * w[e];
   }
@@ -106,37 +110,64 @@ __global__ __launch_bounds__(NT) void k_dot2d(const double* __restrict__ V, long
   }
 }
 
-// Reduces rows j < k of partial (ncol columns) into hs[j], fixed order.
+// Reduces rows j < k of partial (ncol columns) into hs[j]: wave w takes
+// rows w, w + 4, ..., lane l columns l, l + 64, ... summed in that order,
+// then across the wave by shuffles.  Four rows' loads per wave, up to 512
+// columns each, are in flight together.
 __device__ __forceinline__ void reduce_rows(const double* __restrict__ partial, int k, int ncol, double* hs) {
+  constexpr int QMAX = 8, RB = 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int j = wave; j < k; j += NT / 64) {
-    double a = 0.0;
-    for (int c = lane; c < ncol; c += 64) a += partial[(long long)j * ncol + c];
+  for (int j0 = wave; j0 < k; j0 += RB * (NT / 64)) {
+    double a[RB];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-    if (lane == 0) hs[j] = a;
+    for (int r = 0; r < RB; ++r) a[r] = 0.0;
+    for (int c0 = 0; c0 < ncol; c0 += 64 * QMAX) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int j = j0 + r * (NT / 64);
+        double x[QMAX];
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q) {
+          const int c = c0 + lane + 64 * q;
+          x[q] = (j < k && c < ncol) ? partial[(long long)j * ncol + c] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q) a[r] += x[q];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      double v = a[r];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      const int j = j0 + r * (NT / 64);
+      if (lane == 0 && j < k) hs[j] = v;
+    }
   }
 }
 
 // w -= V h1 with h1 reduced from partial1 (k rows); block 0 stores h1.
 // Then, from the updated chunk, partial2[j * gridDim.x + c] = chunk sums of
 // V_j . w (j < k) and w . w (row k), each reduced within waves by shuffles
-// and across the block's waves in a fixed order.
+// and across the block's waves in a fixed order.  The dot rows go eight at a
+// time so that their loads are in flight together.
+template <int EPT>
 __global__ __launch_bounds__(NT) void k_axpy_dot(double* __restrict__ w, const double* __restrict__ V,
                                                  long long ld, int k, const double* __restrict__ partial1,
                                                  long long n, double* __restrict__ hout,
                                                  double* __restrict__ partial2, const int* __restrict__ skip) {
   if (skip && *skip) return;
+  constexpr int JB = 8;
   __shared__ double hs[MAXK];
   __shared__ double wp[MAXK][NT / 64];
   reduce_rows(partial1, k, gridDim.x, hs);
   __syncthreads();
   if (blockIdx.x == 0)
     for (int j = threadIdx.x; j < k; j += NT) hout[j] = hs[j];
-  const long long lo = (long long)blockIdx.x * CHUNK;
-  double xw[CHUNK / NT];
+  const long long lo = (long long)blockIdx.x * (EPT * NT);
+  double xw[EPT];
 #pragma unroll
-  for (int m = 0; m < CHUNK / NT; ++m) {
+  for (int m = 0; m < EPT; ++m) {
     const long long e = lo + threadIdx.x + m * NT;
     double x = 0.0;
     if (e < n) {
@@ -148,17 +179,26 @@ __global__ __launch_bounds__(NT) void k_axpy_dot(double* __restrict__ w, const d
     xw[m] = x;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int j = 0; j <= k; ++j) {
-    double a = 0.0;
+  for (int j0 = 0; j0 <= k; j0 += JB) {
+    double a[JB];
 #pragma unroll
-    for (int m = 0; m < CHUNK / NT; ++m) {
-      const long long e = lo + threadIdx.x + m * NT;
-      const double vj = j < k ? (e < n ? V[ld * j + e] : 0.0) : xw[m];
-      a += vj * xw[m];
+    for (int u = 0; u < JB; ++u) {
+      const int j = j0 + u;
+      a[u] = 0.0;
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) {
+        const long long e = lo + threadIdx.x + m * NT;
+        const double vj = j < k ? (e < n ? V[ld * j + e] : 0.0) : (j == k ? xw[m] : 0.0);
+        a[u] += vj * xw[m];
+      }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-    if (lane == 0) wp[j][wave] = a;
+    for (int u = 0; u < JB; ++u) {
+      double v = a[u];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (lane == 0 && j0 + u <= k) wp[j0 + u][wave] = v;
+    }
   }
   __syncthreads();
   for (int j = threadIdx.x; j <= k; j += NT) {
@@ -248,22 +288,23 @@ __device__ void gm_column_block(GmresState* st, int k, int m, const double* __re
   }
 }
 
-// out = (w - V h2) / sqrt(s - |h2|^2) with (h2, s) reduced from partial2,
-// by blocks 0 .. nchunk - 1.  The extra last block (nchunk) stores h2 and s
+// out = (w - V h2) / sqrt(s - |h2|^2) with (h2, s) reduced from partial2
+// (ncol columns), by blocks 0 .. nchunk - 1 of EPT * NT elements.  The extra last block (nchunk) stores h2 and s
 // in hout and, when st is given and its cycle is not over, updates
 // Hessenberg column k - 1 from h1 and h2 and writes the status to hstat
 // (pinned host memory; visible to the host once the kernel has completed),
 // in parallel with the chunk work.  No skip flag: the last block reads
 // `done` before it may set it, and an iteration past the end of a cycle only
 // writes a basis vector that is never used.
+template <int EPT>
 __global__ __launch_bounds__(NT) void k_ortho_finish2(const double* __restrict__ w, const double* __restrict__ V,
                                                       long long ld, int k, const double* __restrict__ partial2,
-                                                      long long n, double* __restrict__ out, double* __restrict__ hout,
-                                                      GmresState* st, int m, const double* __restrict__ h1,
-                                                      unsigned char* hstat) {
+                                                      int ncol, long long n, double* __restrict__ out,
+                                                      double* __restrict__ hout, GmresState* st, int m,
+                                                      const double* __restrict__ h1, unsigned char* hstat) {
   __shared__ double hs[MAXK];
   __shared__ double scale;
-  reduce_rows(partial2, k + 1, gridDim.x - 1, hs);
+  reduce_rows(partial2, k + 1, ncol, hs);
   __syncthreads();
   if (threadIdx.x == 0) {
     double hh = 0.0;
@@ -279,9 +320,9 @@ __global__ __launch_bounds__(NT) void k_ortho_finish2(const double* __restrict__
   }
   __syncthreads();
   const double a = scale;
-  const long long lo = (long long)blockIdx.x * CHUNK;
+  const long long lo = (long long)blockIdx.x * (EPT * NT);
 #pragma unroll
-  for (int m = 0; m < CHUNK / NT; ++m) {
+  for (int m = 0; m < EPT; ++m) {
     const long long e = lo + threadIdx.x + m * NT;
     if (e < n) {
       double x = w[e];
@@ -464,21 +505,37 @@ int arnoldi_orthogonalise(double* w, const double* V, long long ld, int k, long 
     set_error("arnoldi_orthogonalise: basis size out of range");
     return GDC_EINVAL;
   }
-  const unsigned nchunk = (unsigned)((n + CHUNK - 1) / CHUNK);
+  const bool shortv = n <= (long long)DOT_MAX_BLOCKS * NT;
+  const long long per = shortv ? NT : (long long)EPT_LONG * NT;
+  const unsigned nchunk = (unsigned)((n + per - 1) / per);
   if (nchunk > (unsigned)DOT_MAX_BLOCKS * 4) {
     set_error("arnoldi_orthogonalise: vector too long");
     return GDC_EINVAL;
   }
-  hipLaunchKernelGGL(k_dot2d, dim3(nchunk, k), dim3(NT), 0, s, V, ld, k, (const double*)w, n, partial1, skip);
-  GDC_TRY(check_launch("k_dot2d"));
-  hipLaunchKernelGGL(k_axpy_dot, dim3(nchunk), dim3(NT), 0, s, w, V, ld, k, partial1, n, h1, partial2, skip);
-  GDC_TRY(check_launch("k_axpy_dot"));
   if (st && (k > m || m > GM_MAXR)) {
     set_error("arnoldi_orthogonalise: column out of range");
     return GDC_EINVAL;
   }
-  hipLaunchKernelGGL(k_ortho_finish2, dim3(nchunk + 1), dim3(NT), 0, s, w, V, ld, k, partial2, n, out, h2s, st, m,
-                     (const double*)h1, hstat);
+  if (shortv) {
+    hipLaunchKernelGGL(k_dot2d<1>, dim3(nchunk, k), dim3(NT), 0, s, V, ld, k, (const double*)w, n, partial1, skip);
+    GDC_TRY(check_launch("k_dot2d"));
+    hipLaunchKernelGGL(k_axpy_dot<1>, dim3(nchunk), dim3(NT), 0, s, w, V, ld, k, partial1, n, h1, partial2, skip);
+    GDC_TRY(check_launch("k_axpy_dot"));
+    // the finishing pass is a plain scaled update: longer chunks, fewer
+    // blocks reducing the partial sums
+    const unsigned nfin = (unsigned)((n + EPT_LONG * NT - 1) / (EPT_LONG * NT));
+    hipLaunchKernelGGL(k_ortho_finish2<EPT_LONG>, dim3(nfin + 1), dim3(NT), 0, s, w, V, ld, k, partial2, (int)nchunk,
+                       n, out, h2s, st, m, (const double*)h1, hstat);
+  } else {
+    hipLaunchKernelGGL(k_dot2d<EPT_LONG>, dim3(nchunk, k), dim3(NT), 0, s, V, ld, k, (const double*)w, n, partial1,
+                       skip);
+    GDC_TRY(check_launch("k_dot2d"));
+    hipLaunchKernelGGL(k_axpy_dot<EPT_LONG>, dim3(nchunk), dim3(NT), 0, s, w, V, ld, k, partial1, n, h1, partial2,
+                       skip);
+    GDC_TRY(check_launch("k_axpy_dot"));
+    hipLaunchKernelGGL(k_ortho_finish2<EPT_LONG>, dim3(nchunk + 1), dim3(NT), 0, s, w, V, ld, k, partial2,
+                       (int)nchunk, n, out, h2s, st, m, (const double*)h1, hstat);
+  }
   return check_launch("k_ortho_finish2");
 }
 
