@@ -262,10 +262,12 @@ int gdc_philox_normals(gdc_handle* h, uint64_t seed, uint32_t c1, uint64_t step,
 
 /* Measurement helpers (process-wide, not tied to a handle).
  * gdc_probe_kernel(family): from now on, every launch of the named kernel
- * family is bracketed by HIP events on the stream it is launched on
- * ("spread", "interp", "fft_r2c", "fft_fwd1", "fft_project", "fft_inv1",
- * "fft_c2r", "fft_noise"; NULL or "" switches probing off; at most 8192
- * launches are kept).  gdc_probe_read: total elapsed milliseconds and number
+ * family carries a start and a stop HIP event that the dispatch itself
+ * stamps (hipExtLaunchKernel on the stream it is launched on), so the
+ * elapsed time is the kernel's own duration ("spread", "interp", "fft_r2c",
+ * "fft_fwd1", "fft_project", "fft_inv1", "fft_c2r", "fft_plane_fwd",
+ * "fft_plane_inv", "fft_noise"; NULL or "" switches probing off; at most
+ * 8192 launches are kept).  gdc_probe_read: total elapsed milliseconds and number
  * of probed launches since the last read (waits for the last stop event),
  * then clears the record. */
 int gdc_probe_kernel(const char* family);

@@ -35,14 +35,17 @@ Probe g_probe;
 constexpr size_t PROBE_PAIRS = 8192;
 }  // namespace
 
-void probe_record(const char* family, hipStream_t s, bool start) {
-  if (g_probe.family.empty() || g_probe.family != family) return;
-  if (start && g_probe.used + 2 > g_probe.ev.size()) {
+ProbeEvents probe_claim(const char* family) {
+  ProbeEvents pe;
+  if (g_probe.family.empty() || g_probe.family != family) return pe;
+  if (g_probe.used + 2 > g_probe.ev.size()) {
     ++g_probe.dropped;
-    return;
+    return pe;
   }
-  if (!start && (g_probe.used % 2) == 0) return;   // start was dropped
-  if (hipEventRecord(g_probe.ev[g_probe.used], s) == hipSuccess) ++g_probe.used;
+  pe.start = g_probe.ev[g_probe.used];
+  pe.stop = g_probe.ev[g_probe.used + 1];
+  g_probe.used += 2;
+  return pe;
 }
 
 int check_launch(const char* what) {

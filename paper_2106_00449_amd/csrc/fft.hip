@@ -23,6 +23,8 @@
 // fully unrolled per line length, running on several lines per workgroup in
 // LDS with twiddles e^{-2 pi i k/N} from a table computed on the host.
 
+#include <hip/hip_ext.h>
+
 #include "gdc_internal.h"
 #include "noise_dev.h"
 
@@ -376,18 +378,19 @@ __global__ __launch_bounds__(NTH) void k_c2r_axis2(const Cx<R>* __restrict__ X, 
   load_twiddles<R, N2, NTH>(tw, twg);
   const Cx<R>* src = X + ((long long)c * n0 + i0) * H * n1 + i1b;
   const Cx<R> zero{R(0), R(0)};
-  struct Pair {
-    Cx<R> a, b;
-  };
+  // the two values of an item as one native 4-vector (kept in registers)
+  typedef R R4 __attribute__((ext_vector_type(4)));
   staged_copy<H * NLc, NTH>(
       [&](int e) {
         const int k = e / NLc, p = e - k * NLc;
-        return Pair{(2 * p < nl) ? src[(long long)k * n1 + 2 * p] : zero,
-                    (2 * p + 1 < nl) ? src[(long long)k * n1 + 2 * p + 1] : zero};
+        // select values, not references (a reference to `zero` would put it in scratch memory)
+        const Cx<R> a = (2 * p < nl) ? Cx<R>(src[(long long)k * n1 + 2 * p]) : Cx<R>{R(0), R(0)};
+        const Cx<R> b = (2 * p + 1 < nl) ? Cx<R>(src[(long long)k * n1 + 2 * p + 1]) : Cx<R>{R(0), R(0)};
+        return R4{a.x, a.y, b.x, b.y};
       },
-      [&](int e, Pair v) {
+      [&](int e, R4 v) {
         const int k = e / NLc, p = e - k * NLc;
-        const Cx<R> a = v.a, b = v.b;
+        const Cx<R> a{v.x, v.y}, b{v.z, v.w};
         if (k == 0) {
           buf[p * LS] = Cx<R>{a.x, b.x};
           buf[p * LS + H] = zero;
@@ -801,8 +804,8 @@ int launch_r2c(int n2, const R* in, Cx<R>* X, const Cx<R>* tw, int n0, int n1, i
                const int* skip) {
   if (!nth_ok(nth, false)) return GDC_EINVAL;
   dim3 grid((n1 + Tiles<R>::TL - 1) / Tiles<R>::TL, n0, 3);
-  ProbeScope ps("fft_r2c", s);
-#define L_(N, T) hipLaunchKernelGGL((k_r2c_axis2<R, N, T>), grid, dim3(T), 0, s, in, X, tw, n0, n1, tiled, skip)
+  const ProbeEvents pe = probe_claim("fft_r2c");
+#define L_(N, T) hipExtLaunchKernelGGL((k_r2c_axis2<R, N, T>), grid, dim3(T), 0, s, pe.start, pe.stop, 0, in, X, tw, n0, n1, tiled, skip)
   switch (n2) {
 #define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
     GDC_FFT_SIZES(X_)
@@ -818,8 +821,8 @@ int launch_fwd1(int n1, const Cx<R>* X, Cx<R>* Y, const Cx<R>* tw, int n0, int H
                 const int* skip) {
   if (!nth_ok(nth, false)) return GDC_EINVAL;
   dim3 grid((n0 + Tiles<R>::TL - 1) / Tiles<R>::TL, H, 3);
-  ProbeScope ps("fft_fwd1", s);
-#define L_(N, T) hipLaunchKernelGGL((k_fwd_axis1<R, N, T>), grid, dim3(T), 0, s, X, Y, tw, n0, H, skip)
+  const ProbeEvents pe = probe_claim("fft_fwd1");
+#define L_(N, T) hipExtLaunchKernelGGL((k_fwd_axis1<R, N, T>), grid, dim3(T), 0, s, pe.start, pe.stop, 0, X, Y, tw, n0, H, skip)
   switch (n1) {
 #define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
     GDC_FFT_SIZES(X_)
@@ -835,8 +838,8 @@ int launch_inv1(int n1, const Cx<R>* Y, Cx<R>* X, const Cx<R>* tw, int n0, int H
                 const int* skip) {
   if (!nth_ok(nth, false)) return GDC_EINVAL;
   dim3 grid((n0 + Tiles<R>::TL - 1) / Tiles<R>::TL, H, 3);
-  ProbeScope ps("fft_inv1", s);
-#define L_(N, T) hipLaunchKernelGGL((k_inv_axis1<R, N, T>), grid, dim3(T), 0, s, Y, X, tw, n0, H, skip)
+  const ProbeEvents pe = probe_claim("fft_inv1");
+#define L_(N, T) hipExtLaunchKernelGGL((k_inv_axis1<R, N, T>), grid, dim3(T), 0, s, pe.start, pe.stop, 0, Y, X, tw, n0, H, skip)
   switch (n1) {
 #define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
     GDC_FFT_SIZES(X_)
@@ -852,8 +855,8 @@ int launch_c2r(int n2, const Cx<R>* X, R* out, const Cx<R>* tw, int n0, int n1, 
                const int* skip) {
   if (!nth_ok(nth, false)) return GDC_EINVAL;
   dim3 grid((n1 + Tiles<R>::TL - 1) / Tiles<R>::TL, n0, 3);
-  ProbeScope ps("fft_c2r", s);
-#define L_(N, T) hipLaunchKernelGGL((k_c2r_axis2<R, N, T>), grid, dim3(T), 0, s, X, out, tw, n0, n1, tiled, skip)
+  const ProbeEvents pe = probe_claim("fft_c2r");
+#define L_(N, T) hipExtLaunchKernelGGL((k_c2r_axis2<R, N, T>), grid, dim3(T), 0, s, pe.start, pe.stop, 0, X, out, tw, n0, n1, tiled, skip)
   switch (n2) {
 #define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
     GDC_FFT_SIZES(X_)
@@ -868,8 +871,8 @@ template <typename R, bool NOISE>
 int launch_proj(int n0, Cx<R>* Y, const Cx<R>* tw, const ProjParams& P, int nth, hipStream_t s, const int* skip) {
   if (!nth_ok(nth, false)) return GDC_EINVAL;
   dim3 grid((P.n1 + Tiles<R>::TC - 1) / Tiles<R>::TC, P.n2h, 1);
-  ProbeScope ps(NOISE ? "fft_noise" : "fft_project", s);
-#define L_(N, T) hipLaunchKernelGGL((k_axis0_project<R, N, NOISE, T>), grid, dim3(T), 0, s, Y, tw, P, skip)
+  const ProbeEvents pe = probe_claim(NOISE ? "fft_noise" : "fft_project");
+#define L_(N, T) hipExtLaunchKernelGGL((k_axis0_project<R, N, NOISE, T>), grid, dim3(T), 0, s, pe.start, pe.stop, 0, Y, tw, P, skip)
   switch (n0) {
 #define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
     GDC_FFT_SIZES(X_)
@@ -903,13 +906,13 @@ int launch_plane(bool inverse, int n, const void* in, void* out, const Cx<R>* tw
                  int tiled, int nth, hipStream_t s, const int* skip) {
   if (!nth_ok(nth, true)) return GDC_EINVAL;
   dim3 grid(n0, 3);
-  ProbeScope ps(inverse ? "fft_plane_inv" : "fft_plane_fwd", s);
+  const ProbeEvents pe = probe_claim(inverse ? "fft_plane_inv" : "fft_plane_fwd");
   if constexpr (sizeof(R) != 4) {
     set_error("plane transforms are FP32 only");
     return GDC_EINVAL;
   } else {
     if (!inverse) {
-#define L_(N, T) hipLaunchKernelGGL((k_plane_fwd<R, N, N, T>), grid, dim3(T), 0, s, (const R*)in, (Cx<R>*)out, tw1, tw2, n0, tiled, skip)
+#define L_(N, T) hipExtLaunchKernelGGL((k_plane_fwd<R, N, N, T>), grid, dim3(T), 0, s, pe.start, pe.stop, 0, (const R*)in, (Cx<R>*)out, tw1, tw2, n0, tiled, skip)
       switch (n) {
 #define X_(N) case N: if (nth == 1024) L_(N, 1024); else if (nth == 512) L_(N, 512); else L_(N, 256); break;
         GDC_PLANE_SIZES(X_)
@@ -919,7 +922,7 @@ int launch_plane(bool inverse, int n, const void* in, void* out, const Cx<R>* tw
 #undef L_
       return check_launch("k_plane_fwd");
     }
-#define L_(N, T) hipLaunchKernelGGL((k_plane_inv<R, N, N, T>), grid, dim3(T), 0, s, (const Cx<R>*)in, (R*)out, tw1, tw2, n0, tiled, skip)
+#define L_(N, T) hipExtLaunchKernelGGL((k_plane_inv<R, N, N, T>), grid, dim3(T), 0, s, pe.start, pe.stop, 0, (const Cx<R>*)in, (R*)out, tw1, tw2, n0, tiled, skip)
     switch (n) {
 #define X_(N) case N: if (nth == 1024) L_(N, 1024); else if (nth == 512) L_(N, 512); else L_(N, 256); break;
       GDC_PLANE_SIZES(X_)
@@ -936,12 +939,12 @@ int launch_proj_plane(int n0, Cx<R>* Z, const Cx<R>* tw, const ProjParams& P, in
                       const int* skip) {
   if (!nth_ok(nth, false)) return GDC_EINVAL;
   dim3 grid((P.n1 + TCP - 1) / TCP, P.n2h, 1);
-  ProbeScope ps(NOISE ? "fft_noise" : "fft_project", s);
+  const ProbeEvents pe = probe_claim(NOISE ? "fft_noise" : "fft_project");
   if constexpr (sizeof(R) != 4) {
     set_error("plane transforms are FP32 only");
     return GDC_EINVAL;
   } else {
-#define L_(N, T) hipLaunchKernelGGL((k_axis0_plane<R, N, NOISE, T>), grid, dim3(T), 0, s, Z, tw, P, skip)
+#define L_(N, T) hipExtLaunchKernelGGL((k_axis0_plane<R, N, NOISE, T>), grid, dim3(T), 0, s, pe.start, pe.stop, 0, Z, tw, P, skip)
     switch (n0) {
 #define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
       GDC_PLANE_SIZES(X_)

@@ -42,15 +42,14 @@ struct Status {
 int check_launch(const char* what);
 
 // Optional timing of one kernel family with HIP events on the stream it is
-// launched on (enabled by gdc_probe_kernel): a ProbeScope around a launch
-// records a start and a stop event when the family is the probed one.
-void probe_record(const char* family, hipStream_t s, bool start);
-struct ProbeScope {
-  const char* family;
-  hipStream_t stream;
-  ProbeScope(const char* f, hipStream_t s) : family(f), stream(s) { probe_record(family, stream, true); }
-  ~ProbeScope() { probe_record(family, stream, false); }
+// launched on (enabled by gdc_probe_kernel).  Start and stop events for the next launch of `family` when
+// gdc_probe_kernel watches it, else nulls: the launch passes them to
+// hipExtLaunchKernelGGL, which stamps them from the dispatch itself, so a
+// probed launch runs exactly as an unprobed one.
+struct ProbeEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
 };
+ProbeEvents probe_claim(const char* family);
 
 // ------------------------------------------------------------ complex values
 

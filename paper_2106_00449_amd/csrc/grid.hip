@@ -16,6 +16,8 @@
 // directly from weight differences w' - w = w expm1((2 dr.d - |dr|^2)/2 sigma^2)
 // (d = x_g - r), with the cutoff applied to both positions.
 
+#include <hip/hip_ext.h>
+
 #include "gdc_internal.h"
 
 #include <algorithm>
@@ -692,9 +694,11 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
     const int nr = min(HR, cnt - hb);
     // the round's table loads and the forces of its hits (record position,
     // then force) are all in flight before the first LDS store
-    const uint4* src = reinterpret_cast<const uint4*>(tabs + start + hb);
-    uint4* dstv = reinterpret_cast<uint4*>(sh);
-    uint4 tv[LPT];
+    // native 4-word vectors: an array of them stays in registers
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4* src = reinterpret_cast<const u32x4*>(tabs + start + hb);
+    u32x4* dstv = reinterpret_cast<u32x4*>(sh);
+    u32x4 tv[LPT];
 #pragma unroll
     for (int m = 0; m < LPT; ++m) {
       const int v = tid + m * NTS;
@@ -965,8 +969,8 @@ int spread(const GridGeom& g, const TileGeom& t, const void* tabs, const int* ta
     set_error("spread: tiles must be 8 x 8 x (up to 32)");
     return GDC_EINVAL;
   }
-  ProbeScope ps("spread", s);
-  hipLaunchKernelGGL((k_spread_tab<R>), dim3(t.ntiles), dim3(NTS), 0, s, g, t, (const HitTab<R>*)tabs, tab_start,
+  const ProbeEvents pe = probe_claim("spread");
+  hipExtLaunchKernelGGL((k_spread_tab<R>), dim3(t.ntiles), dim3(NTS), 0, s, pe.start, pe.stop, 0, g, t, (const HitTab<R>*)tabs, tab_start,
                      tab_count, lam, lam_sorted, f, skip);
   return check_launch("k_spread_tab");
 }
@@ -977,8 +981,8 @@ int interp(const GridGeom& g, const double* r, const R* u, double* v, int M, dou
            const void* sorted) {
   if (M <= 0) return GDC_OK;
   RigidTerm K{blob_body, Y, V};
-  ProbeScope ps("interp", s);
-  hipLaunchKernelGGL((k_interp<R>), dim3(blocks_for(M)), dim3(NT), 0, s, g, r, u, v, M, scale, K, skip,
+  const ProbeEvents pe = probe_claim("interp");
+  hipExtLaunchKernelGGL((k_interp<R>), dim3(blocks_for(M)), dim3(NT), 0, s, pe.start, pe.stop, 0, g, r, u, v, M, scale, K, skip,
                      (const SRec*)sorted);
   return check_launch("k_interp");
 }
