@@ -335,6 +335,8 @@ def main():
                     help="time the headline suspension only (no kernel table, FP64 path or serving)")
     ap.add_argument("--workload", default="rods1000", choices=["rods1000", "mixed4096", "rods32768"],
                     help="suspension to time (the headline figure is quoted on rods1000)")
+    ap.add_argument("--kernel-table", action="store_true",
+                    help="with --only-headline, still measure the per-kernel bandwidth table")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device copy first (counter calibration for profiling)")
     args = ap.parse_args()
@@ -395,7 +397,7 @@ def main():
     launch = s.launch_config
     cov = grid_coverage(w, Y0, q0)
     kernels, fp64 = {}, {}
-    if not args.only_headline:
+    if not args.only_headline or args.kernel_table:
         progress("kernel bandwidths")
         kernels = kernel_bandwidth(g, s, Y, q, w, cov)
     s.close()

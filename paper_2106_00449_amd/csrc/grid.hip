@@ -658,7 +658,7 @@ __device__ __forceinline__ double read_lane(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <typename R>
+template <typename R, bool HOIST>
 __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, const HitTab<R>* __restrict__ tabs,
                                                    const int* __restrict__ tab_start,
                                                    const int* __restrict__ tab_count, const double* __restrict__ lam,
@@ -698,11 +698,16 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
     const u32x4* src = reinterpret_cast<const u32x4*>(tabs + start + hb);
     u32x4* dstv = reinterpret_cast<u32x4*>(sh);
-    u32x4 tv[LPT];
+    // (the register variant copies one vector at a time: the staged
+    // vectors would be live beside the accumulators)
+    constexpr int LPS = HOIST ? LPT : 1;
+    u32x4 tv[LPS];
+    if constexpr (!HOIST)
+      for (int v = tid; v < nr * V16; v += NTS) dstv[v] = src[v];
 #pragma unroll
-    for (int m = 0; m < LPT; ++m) {
+    for (int m = 0; m < LPS; ++m) {
       const int v = tid + m * NTS;
-      if (v < nr * V16) tv[m] = src[v];
+      if (HOIST && v < nr * V16) tv[m] = src[v];
     }
     double lv[3] = {0.0, 0.0, 0.0};
     if (tid < nr) {
@@ -713,9 +718,9 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
       for (int q = 0; q < 3; ++q) lv[q] = ls[base + q];
     }
 #pragma unroll
-    for (int m = 0; m < LPT; ++m) {
+    for (int m = 0; m < LPS; ++m) {
       const int v = tid + m * NTS;
-      if (v < nr * V16) dstv[v] = tv[m];
+      if (HOIST && v < nr * V16) dstv[v] = tv[m];
     }
     if (tid < nr) {
 #pragma unroll
@@ -734,27 +739,44 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
       if (!((hm >> wave) & 1)) continue;
       const R l0 = read_lane(hl0, h), l1 = read_lane(hl1, h), l2 = read_lane(hl2, h);
       const HitTab<R>& t = tab[h];
-      // every table value of the hit in registers before any test, so that
-      // one LDS wait serves the hit (a load left under a test would cost a
-      // round trip per plane)
-      R f0v[TX], s0v[TX];
+      if constexpr (HOIST) {
+        // every table value of the hit in registers before any test, so
+        // that one LDS wait serves the hit (a load left under a test costs
+        // a round trip per plane); 16 more registers per lane
+        R f0v[TX], s0v[TX];
 #pragma unroll
-      for (int k = 0; k < TX; ++k) {
-        f0v[k] = t.f0[k];
-        s0v[k] = t.s0[k];
-      }
-      const R s1v = t.s1[j1], szv = t.sz[z], f1v = t.f1[j1], fzv = t.fz[z];
-      pin_values(f0v, s0v, s1v, szv, f1v, fzv);
-      const R s12 = s1v + szv;
-      if (!live || s12 > rc2) continue;
-      const R f12 = f1v * fzv;
+        for (int k = 0; k < TX; ++k) {
+          f0v[k] = t.f0[k];
+          s0v[k] = t.s0[k];
+        }
+        const R s1v = t.s1[j1], szv = t.sz[z], f1v = t.f1[j1], fzv = t.fz[z];
+        pin_values(f0v, s0v, s1v, szv, f1v, fzv);
+        const R s12 = s1v + szv;
+        if (!live || s12 > rc2) continue;
+        const R f12 = f1v * fzv;
 #pragma unroll
-      for (int k = 0; k < TX; ++k) {
-        if (!((hm >> (8 + k)) & 1)) continue;
-        const R w = (s0v[k] + s12 <= rc2) ? f12 * f0v[k] : R(0);
-        acc[k][0] += w * l0;
-        acc[k][1] += w * l1;
-        acc[k][2] += w * l2;
+        for (int k = 0; k < TX; ++k) {
+          if (!((hm >> (8 + k)) & 1)) continue;
+          const R w = (s0v[k] + s12 <= rc2) ? f12 * f0v[k] : R(0);
+          acc[k][0] += w * l0;
+          acc[k][1] += w * l1;
+          acc[k][2] += w * l2;
+        }
+      } else {
+        // plane factors read where they are used: fewer registers, more
+        // workgroups per CU when the tiles run in many rounds
+        if (!live) continue;
+        const R s12 = t.s1[j1] + t.sz[z];
+        if (s12 > rc2) continue;
+        const R f12 = t.f1[j1] * t.fz[z];
+#pragma unroll
+        for (int k = 0; k < TX; ++k) {
+          if (!((hm >> (8 + k)) & 1)) continue;
+          const R w = (t.s0[k] + s12 <= rc2) ? f12 * t.f0[k] : R(0);
+          acc[k][0] += w * l0;
+          acc[k][1] += w * l1;
+          acc[k][2] += w * l2;
+        }
       }
     }
     __syncthreads();
@@ -970,8 +992,14 @@ int spread(const GridGeom& g, const TileGeom& t, const void* tabs, const int* ta
     return GDC_EINVAL;
   }
   const ProbeEvents pe = probe_claim("spread");
-  hipExtLaunchKernelGGL((k_spread_tab<R>), dim3(t.ntiles), dim3(NTS), 0, s, pe.start, pe.stop, 0, g, t, (const HitTab<R>*)tabs, tab_start,
-                     tab_count, lam, lam_sorted, f, skip);
+  // both variants add the same terms in the same order: identical results.
+  // FP64 tables would need 150 registers a lane hoisted: always the lean one
+  if (t.one_round && sizeof(R) == 4)
+    hipExtLaunchKernelGGL((k_spread_tab<R, true>), dim3(t.ntiles), dim3(NTS), 0, s, pe.start, pe.stop, 0, g, t,
+                          (const HitTab<R>*)tabs, tab_start, tab_count, lam, lam_sorted, f, skip);
+  else
+    hipExtLaunchKernelGGL((k_spread_tab<R, false>), dim3(t.ntiles), dim3(NTS), 0, s, pe.start, pe.stop, 0, g, t,
+                          (const HitTab<R>*)tabs, tab_start, tab_count, lam, lam_sorted, f, skip);
   return check_launch("k_spread_tab");
 }
 
