@@ -129,7 +129,9 @@ __global__ __launch_bounds__(NT) void k_interp(GridGeom G, const double* __restr
                                                double scale, RigidTerm K, const int* __restrict__ skip,
                                                const SRec* __restrict__ rec) {
   if (skip && *skip) return;
-  const int place = xcd_block(gridDim.x) * WAVES + threadIdx.x / 64;
+  // wave-uniform by construction; readfirstlane tells the compiler, so the
+  // blob's record and body data come through scalar loads
+  const int place = xcd_block(gridDim.x) * WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (place >= M) return;
   int blob;
@@ -145,6 +147,18 @@ __global__ __launch_bounds__(NT) void k_interp(GridGeom G, const double* __restr
   } else {
     blob = place;
     B = blob_base(G, r + 3LL * blob, 0);
+  }
+  // the rigid velocity of the blob's body at the blob (K V), loaded here,
+  // uniform per wave, so the loads overlap the gather instead of following it
+  double kvel[3] = {0.0, 0.0, 0.0};
+  if (K.V) {
+    const int p = K.blob_body[blob];
+    const double* Vp = K.V + 6LL * p;
+    const double rel[3] = {r[3LL * blob] - K.Y[3LL * p], r[3LL * blob + 1] - K.Y[3LL * p + 1],
+                           r[3LL * blob + 2] - K.Y[3LL * p + 2]};
+    kvel[0] = Vp[0] + (Vp[4] * rel[2] - Vp[5] * rel[1]);
+    kvel[1] = Vp[1] + (Vp[5] * rel[0] - Vp[3] * rel[2]);
+    kvel[2] = Vp[2] + (Vp[3] * rel[1] - Vp[4] * rel[0]);
   }
   const int P0 = G.P[0], P1 = G.P[1], P2 = G.P[2];
   const long long Gs = G.G;
@@ -192,13 +206,9 @@ __global__ __launch_bounds__(NT) void k_interp(GridGeom G, const double* __restr
   if (lane == 0) {
     double o[3] = {scale * (double)s0, scale * (double)s1, scale * (double)s2};
     if (K.V) {
-      const int p = K.blob_body[blob];
-      const double* Vp = K.V + 6LL * p;
-      const double rel[3] = {r[3LL * blob] - K.Y[3LL * p], r[3LL * blob + 1] - K.Y[3LL * p + 1],
-                             r[3LL * blob + 2] - K.Y[3LL * p + 2]};
-      o[0] -= Vp[0] + (Vp[4] * rel[2] - Vp[5] * rel[1]);
-      o[1] -= Vp[1] + (Vp[5] * rel[0] - Vp[3] * rel[2]);
-      o[2] -= Vp[2] + (Vp[3] * rel[1] - Vp[4] * rel[0]);
+      o[0] -= kvel[0];
+      o[1] -= kvel[1];
+      o[2] -= kvel[2];
     }
     v[3LL * blob] = o[0];
     v[3LL * blob + 1] = o[1];
