@@ -220,7 +220,7 @@ template <typename R, int NP>
 __global__ __launch_bounds__(NT) void k_interp_fd(GridGeom G, const double* __restrict__ r,
                                                   const double* __restrict__ dr, const R* __restrict__ u,
                                                   double* __restrict__ v, double* __restrict__ vd, int M) {
-  const int blob = xcd_block(gridDim.x) * WAVES + threadIdx.x / 64;
+  const int blob = xcd_block(gridDim.x) * WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (blob >= M) return;
   const BlobBase B = blob_base(G, r + 3LL * blob, 1);
@@ -686,7 +686,9 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
   __shared__ __align__(16) R sh[SH];    // a round of tables, then the staged tile
   __shared__ R h_l[HR][3];
   HitTab<R>* tab = reinterpret_cast<HitTab<R>*>(sh);
-  const int tid = threadIdx.x, lane = tid & 63, wave = (tid >> 6) & 3, half = tid >> 8;
+  // wave and half are wave-uniform; readfirstlane makes the per-hit tests scalar branches
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((tid >> 6) & 3), half = __builtin_amdgcn_readfirstlane(tid >> 8);
   const int tl = blockIdx.x;
   const int t2 = tl % T.nt[2], t1 = (tl / T.nt[2]) % T.nt[1], t0 = tl / (T.nt[1] * T.nt[2]);
   const int ts[3] = {t0 * T.T[0], t1 * T.T[1], t2 * T.T[2]};
