@@ -555,16 +555,19 @@ int solve_advance(gdc_handle* h, bool block, int& adv) {
   switch (sv.phase) {
     case SolveRun::CYCLE: {
       if (sv.first) {
-        GDC_TRY(copy_scaled(h->rhs, 1.0, h->w, n, s));
+        // zero initial guess: the residual is b, whose |b|^2 solve_begin
+        // left in hdev[0]; V_0 = b / |b|
+        GDC_TRY(gm_cycle(h->gm, h->hdev, s));
+        GDC_TRY(scale_by_inv_sqrt(h->rhs, h->hdev, h->Vb, n, s));
       } else {
         // w = b - A P^-1 xacc
         GDC_TRY(apply_saddle_precond<R>(h, sv.Y, sv.q, sv.r, h->xacc, h->z, h->w));
         GDC_TRY(sub_from(h->rhs, h->w, n, s));
+        GDC_TRY(multi_dot(nullptr, n, 0, h->w, n, true, h->partial, h->dot_counter, h->hdev + 2 * HCOLS, s));
+        GDC_TRY(gm_cycle(h->gm, h->hdev + 2 * HCOLS, s));
+        GDC_TRY(scale_by_inv_sqrt(h->w, h->hdev + 2 * HCOLS, h->Vb, n, s));
       }
       sv.first = false;
-      GDC_TRY(multi_dot(nullptr, n, 0, h->w, n, true, h->partial, h->dot_counter, h->hdev + 2 * HCOLS, s));
-      GDC_TRY(gm_cycle(h->gm, h->hdev + 2 * HCOLS, s));
-      GDC_TRY(scale_by_inv_sqrt(h->w, h->hdev + 2 * HCOLS, h->Vb, n, s));
       GDC_TRY(post_status(h, 0));
       sv.k = 0;
       sv.queued = false;
@@ -669,8 +672,7 @@ template <typename R>
 int predictor_dev(gdc_handle* h, uint64_t step) {
   hipStream_t s = h->stream;
   const int mode = h->cfg.divergence == GDC_DIV_RFD ? 1 : 0;
-  GDC_TRY(blob_positions(h->bt, h->Y, h->q, h->r, s));
-  GDC_TRY(fd_displacements(h->bt, h->q, h->cfg.fd_delta, mode, h->cfg.seed, step, h->dr, h->wrfd, s));
+  GDC_TRY(fd_displacements(h->bt, h->q, h->cfg.fd_delta, mode, h->cfg.seed, step, h->dr, h->wrfd, s, h->Y, h->r));
   GDC_TRY(interp_fd<R>(h->geom, h->r, h->dr, mode == 1 ? 1 : 6, (const R*)h->grid_fl, h->v, h->vd, h->M, s));
   GDC_TRY(body_lsq_div(h->bt, h->q, h->v, h->vd, h->wrfd, h->cfg.fd_delta, mode, h->calV, h->dp, s));
   return nu_reduce(h->dp, h->N, 0.5 * h->cfg.dt, h->nu, s);
@@ -737,11 +739,12 @@ int step_advance(gdc_handle* h, bool block, int& adv) {
     const double* qm = h->q;
     if (gdc_scheme) {
       GDC_TRY(predictor_dev<R>(h, step));
-      GDC_TRY(midpoint(h->bt, h->Y, h->q, h->calV, 0.5 * h->cfg.dt, h->Ym, h->qm, s));
+      GDC_TRY(midpoint_positions(h->bt, h->Y, h->q, h->calV, 0.5 * h->cfg.dt, h->Ym, h->qm, h->rm, s));
       Ym = h->Ym;
       qm = h->qm;
+    } else {
+      GDC_TRY(blob_positions(h->bt, Ym, qm, h->rm, s));
     }
-    GDC_TRY(blob_positions(h->bt, Ym, qm, h->rm, s));
     GDC_TRY(forces_at(h, Ym, h->rm));
     GDC_TRY(prepare_positions(h, h->rm));
     GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_fl, h->v, h->M, h->geom.dV, nullptr, nullptr, nullptr, s,

@@ -264,9 +264,12 @@ __global__ __launch_bounds__(64) void k_precond(BodyTables B, const double* __re
 // mode 1 (random finite differences, eq. rfd_div): one displacement
 //   delta L_p W_U + (R(exp(delta W_Omega) . q) - R(q)) b_i with W ~ N(0,1)^6 from
 //   Philox (stage 1, c0 = body, calls 0 and 1, first six normals).
+// With Y given, the blob positions r_i = Y_p + R(q_p) b_i are written too
+// (the rotation is at hand).
 __global__ void k_fd_displacements(BodyTables B, const double* __restrict__ q, double delta, int mode,
                                    uint64_t seed, uint64_t step, double* __restrict__ dr,
-                                   double* __restrict__ wrfd) {
+                                   double* __restrict__ wrfd, const double* __restrict__ Y,
+                                   double* __restrict__ r) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= B.M) return;
   const int p = B.blob_body[i], s = B.body_shape[p];
@@ -275,6 +278,13 @@ __global__ void k_fd_displacements(BodyTables B, const double* __restrict__ q, d
   load3(B.shape_b + 3LL * (B.shape_boff[s] + B.blob_local[i]), b);
   const double* qp = q + 4LL * p;
   rotmat(qp, R);
+  if (Y) {
+    double x[3];
+    matvec3(R, b, x);
+    r[3LL * i] = Y[3LL * p] + x[0];
+    r[3LL * i + 1] = Y[3LL * p + 1] + x[1];
+    r[3LL * i + 2] = Y[3LL * p + 2] + x[2];
+  }
   if (mode == 0) {
     double* o = dr + 18LL * i;
 #pragma unroll
@@ -427,19 +437,34 @@ __global__ __launch_bounds__(1024) void k_nu_reduce(const double* __restrict__ d
   if (threadIdx.x == 0) nu[0] = 1.0 + half_dt * sh[0];
 }
 
-// Step 4: Y^m = Y + h calV_U, q^m = exp(h calV_Omega) . q.
-__global__ void k_midpoint(int N, const double* __restrict__ Y, const double* __restrict__ q,
-                           const double* __restrict__ calV, double h, double* __restrict__ Ym,
-                           double* __restrict__ qm) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= N) return;
+// Step 4 and the midpoint blob positions in one pass, one thread per blob:
+// each blob forms its body's Y^m, q^m (the body's first blob stores them)
+// and r^m_i = Y^m + R(q^m) b_i.
+__global__ void k_midpoint_blobs(BodyTables B, const double* __restrict__ Y, const double* __restrict__ q,
+                                 const double* __restrict__ calV, double h, double* __restrict__ Ym,
+                                 double* __restrict__ qm, double* __restrict__ rm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B.M) return;
+  const int p = B.blob_body[i], s = B.body_shape[p];
   const double* V = calV + 6LL * p;
-  Ym[3LL * p] = Y[3LL * p] + h * V[0];
-  Ym[3LL * p + 1] = Y[3LL * p + 1] + h * V[1];
-  Ym[3LL * p + 2] = Y[3LL * p + 2] + h * V[2];
-  double u[3] = {h * V[3], h * V[4], h * V[5]}, e[4];
+  const double y[3] = {Y[3LL * p] + h * V[0], Y[3LL * p + 1] + h * V[1], Y[3LL * p + 2] + h * V[2]};
+  double u[3] = {h * V[3], h * V[4], h * V[5]}, e[4], qq[4];
   qexp(u, e);
-  qmul(e, q + 4LL * p, qm + 4LL * p);
+  qmul(e, q + 4LL * p, qq);
+  if (B.blob_local[i] == 0) {
+    Ym[3LL * p] = y[0];
+    Ym[3LL * p + 1] = y[1];
+    Ym[3LL * p + 2] = y[2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qm[4LL * p + k] = qq[k];
+  }
+  double R[9], b[3], x[3];
+  rotmat(qq, R);
+  load3(B.shape_b + 3LL * (B.shape_boff[s] + B.blob_local[i]), b);
+  matvec3(R, b, x);
+  rm[3LL * i] = y[0] + x[0];
+  rm[3LL * i + 1] = y[1] + x[1];
+  rm[3LL * i + 2] = y[2] + x[2];
 }
 
 // Step 6: Y += nu dt V_U, q = exp(nu dt V_Omega) . q (nu on the device).
@@ -467,11 +492,10 @@ __global__ void k_update(int N, double* __restrict__ Y, double* __restrict__ q, 
 }
 
 // Right-hand side [-(v_slip + u_inf); -(I - Pi) F] of the saddle problem.
-__global__ void k_rhs_blobs(BodyTables B, const double* __restrict__ Y, const double* __restrict__ r,
-                            const double* __restrict__ vslip, const double* __restrict__ vbg, double cbg,
-                            double shear, double Ly, double* __restrict__ rhs) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= B.M) return;
+__device__ __forceinline__ void rhs_blob(const BodyTables& B, int i, const double* __restrict__ Y,
+                                         const double* __restrict__ r, const double* __restrict__ vslip,
+                                         const double* __restrict__ vbg, double cbg, double shear, double Ly,
+                                         double* __restrict__ rhs) {
   double ux = vbg ? cbg * vbg[3LL * i] : 0.0;
   if (shear != 0.0) {
     const int p = B.blob_body[i];
@@ -484,10 +508,8 @@ __global__ void k_rhs_blobs(BodyTables B, const double* __restrict__ Y, const do
   rhs[3LL * i + 2] = -(vslip ? vslip[3LL * i + 2] : 0.0);
 }
 
-__global__ void k_rhs_bodies(BodyTables B, const double* __restrict__ q, const double* __restrict__ F,
-                             double* __restrict__ rhsV) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= B.N) return;
+__device__ __forceinline__ void rhs_body(const BodyTables& B, int p, const double* __restrict__ q,
+                                         const double* __restrict__ F, double* __restrict__ rhsV) {
   double R[9], f[6], pf[6];
   rotmat(q + 4LL * p, R);
 #pragma unroll
@@ -495,6 +517,19 @@ __global__ void k_rhs_bodies(BodyTables B, const double* __restrict__ q, const d
   rotate_6x6(B.shape_null + 36LL * B.body_shape[p], R, f, pf);
 #pragma unroll
   for (int k = 0; k < 6; ++k) rhsV[6LL * p + k] = -(f[k] - pf[k]);
+}
+
+// Both parts of the right-hand side in one launch: threads [0, M) the blob
+// rows, threads [M, M + N) the body rows.
+__global__ void k_rhs(BodyTables B, const double* __restrict__ Y, const double* __restrict__ r,
+                      const double* __restrict__ vslip, const double* __restrict__ vbg, double cbg, double shear,
+                      double Ly, const double* __restrict__ q, const double* __restrict__ F,
+                      double* __restrict__ rhs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < B.M)
+    rhs_blob(B, i, Y, r, vslip, vbg, cbg, shear, Ly, rhs);
+  else if (i < B.M + B.N)
+    rhs_body(B, i - B.M, q, F, rhs + 3LL * B.M);
 }
 
 // ------------------------------------------------------------ pair forces
@@ -634,8 +669,9 @@ int precond_apply(const BodyTables& b, const double* q, const double* x, double*
 }
 
 int fd_displacements(const BodyTables& b, const double* q, double delta, int mode, uint64_t seed,
-                     uint64_t step, double* dr, double* wrfd, hipStream_t s) {
-  hipLaunchKernelGGL(k_fd_displacements, dim3(nblk(b.M)), dim3(NT), 0, s, b, q, delta, mode, seed, step, dr, wrfd);
+                     uint64_t step, double* dr, double* wrfd, hipStream_t s, const double* Y, double* r) {
+  hipLaunchKernelGGL(k_fd_displacements, dim3(nblk(b.M)), dim3(NT), 0, s, b, q, delta, mode, seed, step, dr, wrfd,
+                     Y, r);
   return check_launch("k_fd_displacements");
 }
 
@@ -651,10 +687,10 @@ int nu_reduce(const double* d, int N, double half_dt, double* nu, hipStream_t s)
   return check_launch("k_nu_reduce");
 }
 
-int midpoint(const BodyTables& b, const double* Y, const double* q, const double* calV, double h, double* Ym,
-             double* qm, hipStream_t s) {
-  hipLaunchKernelGGL(k_midpoint, dim3(nblk(b.N)), dim3(NT), 0, s, b.N, Y, q, calV, h, Ym, qm);
-  return check_launch("k_midpoint");
+int midpoint_positions(const BodyTables& b, const double* Y, const double* q, const double* calV, double h,
+                       double* Ym, double* qm, double* rm, hipStream_t s) {
+  hipLaunchKernelGGL(k_midpoint_blobs, dim3(nblk(b.M)), dim3(NT), 0, s, b, Y, q, calV, h, Ym, qm, rm);
+  return check_launch("k_midpoint_blobs");
 }
 
 int update(const BodyTables& b, double* Y, double* q, const double* V, const double* nu, double dt, int* nonfinite,
@@ -666,10 +702,9 @@ int update(const BodyTables& b, double* Y, double* q, const double* V, const dou
 int rhs_build(const BodyTables& b, const double* q, const double* Y, const double* r, const double* vslip,
               const double* vbg, double cbg, const double* F, double shear, double Ly, double* rhs,
               hipStream_t s) {
-  hipLaunchKernelGGL(k_rhs_blobs, dim3(nblk(b.M)), dim3(NT), 0, s, b, Y, r, vslip, vbg, cbg, shear, Ly, rhs);
-  GDC_TRY(check_launch("k_rhs_blobs"));
-  hipLaunchKernelGGL(k_rhs_bodies, dim3(nblk(b.N)), dim3(NT), 0, s, b, q, F, rhs + 3LL * b.M);
-  return check_launch("k_rhs_bodies");
+  hipLaunchKernelGGL(k_rhs, dim3(nblk((long long)b.M + b.N)), dim3(NT), 0, s, b, Y, r, vslip, vbg, cbg, shear, Ly, q,
+                     F, rhs);
+  return check_launch("k_rhs");
 }
 
 int steric_forces(const BodyTables& b, const GridGeom& g, const double* r, double k, double cutoff,

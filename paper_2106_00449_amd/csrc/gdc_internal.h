@@ -289,13 +289,15 @@ int precond_apply(const BodyTables& b, const double* q, const double* x, double*
 // FD / RFD perturbations: displacements of each blob (M x NP x 3) and, for
 // RFD, the Philox normals of each body (N x 6).
 int fd_displacements(const BodyTables& b, const double* q, double delta, int mode,
-                     uint64_t seed, uint64_t step, double* dr, double* wrfd, hipStream_t s);
+                     uint64_t seed, uint64_t step, double* dr, double* wrfd, hipStream_t s,
+                     const double* Y = nullptr, double* r = nullptr);
 int body_lsq_div(const BodyTables& b, const double* q, const double* v, const double* vd,
                  const double* wrfd, double delta, int mode, double* calV, double* d,
                  hipStream_t s);
 int nu_reduce(const double* d, int N, double half_dt, double* nu, hipStream_t s);
-int midpoint(const BodyTables& b, const double* Y, const double* q, const double* calV,
-             double h, double* Ym, double* qm, hipStream_t s);
+// Step 4 with the midpoint blob positions rm in the same launch.
+int midpoint_positions(const BodyTables& b, const double* Y, const double* q, const double* calV, double h,
+                       double* Ym, double* qm, double* rm, hipStream_t s);
 // Step 6; sets *nonfinite (when given) if a new position or quaternion is not finite.
 int update(const BodyTables& b, double* Y, double* q, const double* V, const double* nu,
            double dt, int* nonfinite, hipStream_t s);

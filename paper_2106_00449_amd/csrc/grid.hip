@@ -381,10 +381,31 @@ __global__ __launch_bounds__(256) void k_tile_rank(const int* __restrict__ off, 
                                                    const SRec* __restrict__ in, SRec* __restrict__ out,
                                                    int* __restrict__ spos) {
   __shared__ int idx[4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int t = blockIdx.x * 4 + w;
   if (t >= ntiles) return;   // whole wave leaves together; no block barrier below
   const int lo = off[t], hi = off[t + 1];
+  if (hi - lo <= 64) {
+    // the usual case: the tile's records fit one wave, ranked from the
+    // blob indices the lanes already hold
+    const int i = lo + lane;
+    SRec x;
+    int b = 0x7fffffff;
+    if (i < hi) {
+      x = in[i];
+      b = x.blob;
+    }
+    idx[w][lane] = b;
+    __builtin_amdgcn_wave_barrier();
+    int rank = 0;
+    const int cnt = hi - lo;
+    for (int k = 0; k < cnt; ++k) rank += idx[w][k] < b;
+    if (i < hi) {
+      out[lo + rank] = x;
+      spos[b] = lo + rank;
+    }
+    return;
+  }
   for (int i0 = lo; i0 < hi; i0 += 64) {
     const int i = i0 + lane;
     SRec x;
