@@ -83,6 +83,9 @@ CASES = [
     # a 20-blob shape: preconditioner block of 66, above the matrix-core
     # kernel's limit, so the per-body kernel runs
     ("rod20", 48, 48.0, [wl.rod(20), wl.tetrahedron()]),
+    # one 8x8x8 tile holding 80 blobs: the spreading hit loop takes two
+    # rounds of 64 and the tile sort ranks more records than a wave
+    ("dense8", 8, 12.0, [wl.rod(5)]),
 ]
 
 
@@ -90,7 +93,7 @@ CASES = [
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_blob_mobility(lib, prec, case):
     name, n, L, shapes = case
-    nb = 3 if name == "small8" else 12
+    nb = {"small8": 3, "dense8": 16}.get(name, 12)
     w = wl.small_case(name, n_bodies=nb, n=n, L=L, shapes=shapes, precision=prec, seed=3)
     Y, q, lam, _ = _rand_blobs(w, 1)
     _say("blob", name, prec, w.M)
