@@ -89,6 +89,22 @@ __global__ __launch_bounds__(256) void k_precond_mfma(BodyTables B, const double
   const int off_s = B.shape_boff[s], nb = B.shape_boff[s + 1] - off_s;
   const int D = 3 * nb + 6, nv = nb + 2;
   const long long Mx3 = 3LL * B.M;
+  // the shape's block first: its loads do not depend on the bodies, so they
+  // are in flight while the body indices, orientations and vectors arrive
+  const double* AT = B.shape_precT + B.shape_prec_off[s];   // AT[k D + i] = (P_s^-1)[i][k]
+  for (int e0 = 0; e0 < D * D; e0 += 8 * 256) {   // eight loads per thread in flight
+    double v[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int e = e0 + tid + 256 * m;
+      v[m] = e < D * D ? AT[e] : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int e = e0 + tid + 256 * m;
+      if (e < D * D) As[e] = v[m];
+    }
+  }
   if (tid < 16) {
     const int p = tid < cnt ? B.group_body[first + tid] : -1;
     pb[tid] = p;
@@ -110,8 +126,6 @@ __global__ __launch_bounds__(256) void k_precond_mfma(BodyTables B, const double
     X[3 * v + 2][j] = w[2];
   }
   for (int t = tid; t < (DP - D) * 16; t += 256) X[D + (t >> 4)][t & 15] = 0.0;
-  const double* AT = B.shape_precT + B.shape_prec_off[s];   // AT[k D + i] = (P_s^-1)[i][k]
-  for (int e = tid; e < D * D; e += 256) As[e] = AT[e];
   __syncthreads();
   const int il = lane & 15, kq = lane >> 4;
   const int nrb = (D + 15) / 16, nk = (D + 3) / 4;
