@@ -428,26 +428,33 @@ __global__ void k_gm_cycle(GmresState* st, const double* __restrict__ beta2) {
 }
 
 // y = H^-1 g over the cycle's kdone columns (back substitution).
-__global__ void k_gm_solve(GmresState* st) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int kd = st->kdone;
-  const double* H = st->H;
-  for (int i = kd - 1; i >= 0; --i) {
-    double t = st->g[i];
-    for (int j = i + 1; j < kd; ++j) t -= H[i * GM_MAXR + j] * st->y[j];
-    const double d = H[i * GM_MAXR + i];
-    st->y[i] = d != 0.0 ? t / d : 0.0;
-  }
-}
-
-// x += sum_{j < st->kdone} y_j V_j
+// End of a restart cycle: y = H^-1 g by back-substitution over the cycle's
+// kdone columns, then x += sum_j y_j V_j.  Every block stages H's upper
+// triangle and g in LDS and solves the small system itself (thread 0, the
+// same arithmetic in every block, so all blocks hold the same y); block 0
+// also stores y in the state.
 __global__ __launch_bounds__(NT) void k_gm_update(double* __restrict__ x, const double* __restrict__ V,
-                                                  long long ld, const GmresState* __restrict__ st,
-                                                  long long n) {
-  __shared__ double ys[GM_MAXR];
+                                                  long long ld, GmresState* __restrict__ st, long long n) {
+  __shared__ double Hs[GM_MAXR * GM_MAXR];
+  __shared__ double gs[GM_MAXR], ys[GM_MAXR];
   const int k = st->kdone;
-  for (int j = threadIdx.x; j < k; j += NT) ys[j] = st->y[j];
+  for (int e = threadIdx.x; e < k * k; e += NT) {
+    const int i = e / k, j = e - i * k;
+    Hs[i * GM_MAXR + j] = j >= i ? st->H[i * GM_MAXR + j] : 0.0;
+  }
+  for (int j = threadIdx.x; j < k; j += NT) gs[j] = st->g[j];
   __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = k - 1; i >= 0; --i) {
+      double t = gs[i];
+      for (int j = i + 1; j < k; ++j) t -= Hs[i * GM_MAXR + j] * ys[j];
+      const double d = Hs[i * GM_MAXR + i];
+      ys[i] = d != 0.0 ? t / d : 0.0;
+    }
+  }
+  __syncthreads();
+  if (blockIdx.x == 0)
+    for (int j = threadIdx.x; j < k; j += NT) st->y[j] = ys[j];
   const long long stride = (long long)gridDim.x * NT;
   for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < n; e += stride) {
     double acc = 0.0;
@@ -550,9 +557,7 @@ int gm_cycle(GmresState* st, const double* beta2, hipStream_t s) {
 }
 
 int gm_finish_cycle(GmresState* st, double* x, const double* V, long long ld, long long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(64), 0, s, st);
-  GDC_TRY(check_launch("k_gm_solve"));
-  hipLaunchKernelGGL(k_gm_update, dim3(grid_for(n)), dim3(NT), 0, s, x, V, ld, (const GmresState*)st, n);
+  hipLaunchKernelGGL(k_gm_update, dim3(grid_for(n)), dim3(NT), 0, s, x, V, ld, st, n);
   return check_launch("k_gm_update");
 }
 
