@@ -175,7 +175,7 @@ struct TileGeom {
   int H[3];
   int ntiles;
   int S;       // work-item slots per blob: a power of two >= min(T1, P1) min(T2, P2)
-  int one_round;   // every spreading workgroup resident at once (tiles <= 4 per CU)
+  int one_round;   // at most 4 tiles per CU: spreading is bound by each tile's latency, not occupancy
 };
 
 // Device tables of a suspension's bodies (see BodyHost for the meaning).
