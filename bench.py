@@ -156,8 +156,8 @@ def grid_coverage(w, Y, q):
 
 def timed_steps(g, s, Y, q, steps, warmup):
     """Time `steps` steps as one library call (the steps are pipelined on the
-    stream); per-step latencies are the gaps between the completion times in
-    the handle's step log."""
+    stream); per-step latencies are the gaps between consecutive completion
+    times in the handle's step log within that call (steps - 1 of them)."""
     import numpy as np
     import torch
     if warmup:
@@ -169,9 +169,12 @@ def timed_steps(g, s, Y, q, steps, warmup):
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
     log = np.asarray(s.step_log())
-    lat = np.diff(log)
-    if len(lat) != steps:
-        raise RuntimeError(f"step log holds {len(lat)} latencies for {steps} steps")
+    # gaps between consecutive completions inside the timed call; the first
+    # entry is the warm-up call's last completion, so the first gap would
+    # also hold the host's time between the two calls
+    lat = np.diff(log)[1:]
+    if len(lat) != steps - 1:
+        raise RuntimeError(f"step log holds {len(lat) + 1} latencies for {steps} steps")
     return total, lat, st["gmres_iterations_mean"], st["nu_mean"]
 
 
@@ -383,6 +386,8 @@ def main():
     torch.cuda.synchronize()
     g.probe_kernel(DOMINANT)
     total, lat_ms, its, nus = timed_steps(g, s, Y, q, args.steps, 0)
+    if len(lat_ms) == 0:   # one timed step: its latency is the call's time
+        lat_ms = np.array([total * 1e3])
     k_ms, k_launches = g.probe_read()
     g.probe_kernel(None)
     value = w.M * args.steps / total
