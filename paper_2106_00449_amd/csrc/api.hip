@@ -534,9 +534,10 @@ template <typename R>
 int solve_begin(gdc_handle* h, const double* Y, const double* q, const double* r) {
   const long long n = h->nx;
   hipStream_t s = h->stream;
-  GDC_TRY(multi_dot(nullptr, n, 0, h->rhs, n, true, h->partial, h->dot_counter, h->hdev, s));
-  GDC_TRY(gm_init(h->gm, h->hdev, h->tol, h->maxit, s));
-  GDC_TRY(fill_zero(h->xacc, (size_t)((n * 8 + 15) / 16 * 16), s));
+  // |b|^2 and, in the same launch, the GMRES state; the solution
+  // accumulator is cleared by the first cycle's start
+  GDC_TRY(multi_dot(nullptr, n, 0, h->rhs, n, true, h->partial, h->dot_counter, h->hdev, s, h->gm, h->tol,
+                    h->maxit));
   h->sv = SolveRun{};
   h->sv.Y = Y;
   h->sv.q = q;
@@ -557,15 +558,13 @@ int solve_advance(gdc_handle* h, bool block, int& adv) {
       if (sv.first) {
         // zero initial guess: the residual is b, whose |b|^2 solve_begin
         // left in hdev[0]; V_0 = b / |b|
-        GDC_TRY(gm_cycle(h->gm, h->hdev, s));
-        GDC_TRY(scale_by_inv_sqrt(h->rhs, h->hdev, h->Vb, n, s));
+        GDC_TRY(scale_by_inv_sqrt(h->rhs, h->hdev, h->Vb, n, s, h->gm, h->xacc, n));
       } else {
         // w = b - A P^-1 xacc
         GDC_TRY(apply_saddle_precond<R>(h, sv.Y, sv.q, sv.r, h->xacc, h->z, h->w));
         GDC_TRY(sub_from(h->rhs, h->w, n, s));
         GDC_TRY(multi_dot(nullptr, n, 0, h->w, n, true, h->partial, h->dot_counter, h->hdev + 2 * HCOLS, s));
-        GDC_TRY(gm_cycle(h->gm, h->hdev + 2 * HCOLS, s));
-        GDC_TRY(scale_by_inv_sqrt(h->w, h->hdev + 2 * HCOLS, h->Vb, n, s));
+        GDC_TRY(scale_by_inv_sqrt(h->w, h->hdev + 2 * HCOLS, h->Vb, n, s, h->gm));
       }
       sv.first = false;
       GDC_TRY(post_status(h, 0));
@@ -674,8 +673,8 @@ int predictor_dev(gdc_handle* h, uint64_t step) {
   const int mode = h->cfg.divergence == GDC_DIV_RFD ? 1 : 0;
   GDC_TRY(fd_displacements(h->bt, h->q, h->cfg.fd_delta, mode, h->cfg.seed, step, h->dr, h->wrfd, s, h->Y, h->r));
   GDC_TRY(interp_fd<R>(h->geom, h->r, h->dr, mode == 1 ? 1 : 6, (const R*)h->grid_fl, h->v, h->vd, h->M, s));
-  GDC_TRY(body_lsq_div(h->bt, h->q, h->v, h->vd, h->wrfd, h->cfg.fd_delta, mode, h->calV, h->dp, s));
-  return nu_reduce(h->dp, h->N, 0.5 * h->cfg.dt, h->nu, s);
+  return body_lsq_div(h->bt, h->q, h->v, h->vd, h->wrfd, h->cfg.fd_delta, mode, h->calV, h->dp,
+                      h->dot_counter + 1, 0.5 * h->cfg.dt, h->nu, s);
 }
 
 // Readback slot k of the pinned buffer: nu, the 4 error flags (2 doubles),

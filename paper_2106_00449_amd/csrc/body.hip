@@ -377,13 +377,10 @@ __device__ void lsq_body(const BodyTables& B, int p, int s, const double* R, con
 // quotients in the order translations, then rotations.
 constexpr int LSQ_LANES = 8;
 
-__global__ __launch_bounds__(64) void k_body_lsq_div(BodyTables B, const double* __restrict__ q,
-                                                     const double* __restrict__ v, const double* __restrict__ vd,
-                                                     const double* __restrict__ wrfd, double delta, int mode,
-                                                     double* __restrict__ calV, double* __restrict__ d) {
-  const int p = (blockIdx.x * blockDim.x + threadIdx.x) / LSQ_LANES;
-  const int j = threadIdx.x % LSQ_LANES;
-  if (p >= B.N) return;   // a body's lanes leave together
+__device__ void lsq_div_body(const BodyTables& B, int p, int j, const double* __restrict__ q,
+                             const double* __restrict__ v, const double* __restrict__ vd,
+                             const double* __restrict__ wrfd, double delta, int mode, double* __restrict__ calV,
+                             double* __restrict__ d) {
   const int s = B.body_shape[p];
   const double Lp = B.shape_Lp[s];
   const double* qp = q + 4LL * p;
@@ -436,20 +433,37 @@ __global__ __launch_bounds__(64) void k_body_lsq_div(BodyTables B, const double*
   }
 }
 
-// nu = 1 + half_dt * sum d, one block, fixed summation order.
-__global__ __launch_bounds__(1024) void k_nu_reduce(const double* __restrict__ d, int N, double half_dt,
-                                                    double* __restrict__ nu) {
-  __shared__ double sh[1024];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < N; i += 1024) s += d[i];
-  sh[threadIdx.x] = s;
+// The per-body work above, then nu = 1 + half_dt sum_p d_p by the last block
+// to finish (counter zero on entry and left at zero): thread t adds d_t,
+// d_{t+64}, ... in order, then the wave adds across lanes.  Fixed order, no
+// atomics on the data.
+__global__ __launch_bounds__(64) void k_body_lsq_div(BodyTables B, const double* __restrict__ q,
+                                                     const double* __restrict__ v, const double* __restrict__ vd,
+                                                     const double* __restrict__ wrfd, double delta, int mode,
+                                                     double* __restrict__ calV, double* __restrict__ d,
+                                                     unsigned int* __restrict__ counter, double half_dt,
+                                                     double* __restrict__ nu) {
+  __shared__ bool last;
+  const int p = (blockIdx.x * blockDim.x + threadIdx.x) / LSQ_LANES;
+  const int j = threadIdx.x % LSQ_LANES;
+  if (p < B.N) lsq_div_body(B, p, j, q, v, vd, wrfd, delta, mode, calV, d);   // a body's 8 lanes together
+  __threadfence();
   __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const volatile double* dv = d;
+  double sum = 0.0;
+  for (int i = threadIdx.x; i < B.N; i += 64) sum += dv[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  if (threadIdx.x == 0) {
+    nu[0] = 1.0 + half_dt * sum;
+    *counter = 0u;
   }
-  if (threadIdx.x == 0) nu[0] = 1.0 + half_dt * sh[0];
 }
+
 
 // Step 4 and the midpoint blob positions in one pass, one thread per blob:
 // each blob forms its body's Y^m, q^m (the body's first blob stores them)
@@ -690,16 +704,13 @@ int fd_displacements(const BodyTables& b, const double* q, double delta, int mod
 }
 
 int body_lsq_div(const BodyTables& b, const double* q, const double* v, const double* vd, const double* wrfd,
-                 double delta, int mode, double* calV, double* d, hipStream_t s) {
+                 double delta, int mode, double* calV, double* d, unsigned int* counter, double half_dt, double* nu,
+                 hipStream_t s) {
   hipLaunchKernelGGL(k_body_lsq_div, dim3(nblk((long long)b.N * LSQ_LANES, 64)), dim3(64), 0, s, b, q, v, vd, wrfd,
-                     delta, mode, calV, d);
+                     delta, mode, calV, d, counter, half_dt, nu);
   return check_launch("k_body_lsq_div");
 }
 
-int nu_reduce(const double* d, int N, double half_dt, double* nu, hipStream_t s) {
-  hipLaunchKernelGGL(k_nu_reduce, dim3(1), dim3(1024), 0, s, d, N, half_dt, nu);
-  return check_launch("k_nu_reduce");
-}
 
 int midpoint_positions(const BodyTables& b, const double* Y, const double* q, const double* calV, double h,
                        double* Ym, double* qm, double* rm, hipStream_t s) {

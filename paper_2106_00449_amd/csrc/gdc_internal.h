@@ -291,10 +291,11 @@ int precond_apply(const BodyTables& b, const double* q, const double* x, double*
 int fd_displacements(const BodyTables& b, const double* q, double delta, int mode,
                      uint64_t seed, uint64_t step, double* dr, double* wrfd, hipStream_t s,
                      const double* Y = nullptr, double* r = nullptr);
+// calV, d_p and (same launch) nu = 1 + half_dt sum_p d_p; counter: one
+// zeroed unsigned int, left at zero.
 int body_lsq_div(const BodyTables& b, const double* q, const double* v, const double* vd,
                  const double* wrfd, double delta, int mode, double* calV, double* d,
-                 hipStream_t s);
-int nu_reduce(const double* d, int N, double half_dt, double* nu, hipStream_t s);
+                 unsigned int* counter, double half_dt, double* nu, hipStream_t s);
 // Step 4 with the midpoint blob positions rm in the same launch.
 int midpoint_positions(const BodyTables& b, const double* Y, const double* q, const double* calV, double h,
                        double* Ym, double* qm, double* rm, hipStream_t s);
@@ -316,9 +317,13 @@ int check_finite(const double* x, long long n, int* flag, hipStream_t s);
 // Krylov vector kernels (solver.hip).
 constexpr int DOT_MAX_BLOCKS = 512;
 // h[j] = V_j . w (j < k), plus h[k] = w . w when with_self; partial holds
-// (k + 1) x DOT_MAX_BLOCKS doubles, counter one zeroed unsigned int.
+// (k + 1) x DOT_MAX_BLOCKS doubles, counter one zeroed unsigned int.  With
+// init (k = 0, with_self: h[0] = |b|^2), the reduction's last block also sets
+// up the GMRES state (tolerance, iteration limit, |b|).
+struct GmresState;
 int multi_dot(const double* V, long long ld, int k, const double* w, long long n, bool with_self,
-              double* partial, unsigned int* counter, double* h, hipStream_t s);
+              double* partial, unsigned int* counter, double* h, hipStream_t s, GmresState* init = nullptr,
+              double tol = 0.0, int maxit = 0);
 int multi_axpy(double* w, const double* V, long long ld, int k, const double* h, double sign,
                long long n, hipStream_t s);
 // out = (w - V h2) / sqrt(h2[k] - |h2[0..k)|^2)
@@ -350,12 +355,13 @@ int arnoldi_orthogonalise(double* w, const double* V, long long ld, int k, long 
                           double* partial2, double* out, double* h1, double* h2s, hipStream_t s,
                           const int* skip, GmresState* st, int m, unsigned char* hstat);
 
-int gm_init(GmresState* st, const double* nb2, double tol, int maxit, hipStream_t s);
-int gm_cycle(GmresState* st, const double* beta2, hipStream_t s);
 // y = H^-1 g over the cycle, then x += V y.
 int gm_finish_cycle(GmresState* st, double* x, const double* V, long long ld, long long n, hipStream_t s);
+// out = w / sqrt(nrm2[0]); with cycle, also starts a GMRES restart cycle
+// from beta^2 = nrm2[0]; with zero, also clears zero[0, nzero).
 int scale_by_inv_sqrt(const double* w, const double* nrm2, double* out, long long n,
-                      hipStream_t s);
+                      hipStream_t s, GmresState* cycle = nullptr, double* zero = nullptr,
+                      long long nzero = 0);
 int copy_scaled(const double* x, double a, double* y, long long n, hipStream_t s);
 int sub_from(const double* b, double* w, long long n, hipStream_t s);   // w = b - w
 

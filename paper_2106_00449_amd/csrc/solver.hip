@@ -38,10 +38,13 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // (nchunk, kk): block (c, j) sums vector j over chunk c into
 // partial[j * nchunk + c]; the last block to finish (counter, zero on entry
 // and left at zero) reduces each row with one wavefront per row.
+__device__ void gm_init_dev(GmresState* st, double nb2, double tol, int maxit);
+__device__ void gm_cycle_dev(GmresState* st, const double* __restrict__ beta2);
+
 __global__ __launch_bounds__(NT) void k_multi_dot(const double* __restrict__ V, long long ld, int k,
                                                   const double* __restrict__ w, long long n,
                                                   double* __restrict__ partial, unsigned int* __restrict__ counter,
-                                                  double* __restrict__ h) {
+                                                  double* __restrict__ h, GmresState* ist, double tol, int maxit) {
   __shared__ double sh[NT / 64];
   __shared__ bool last;
   const int j = blockIdx.y, nchunk = gridDim.x, kk = gridDim.y;
@@ -67,6 +70,8 @@ __global__ __launch_bounds__(NT) void k_multi_dot(const double* __restrict__ V, 
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
     if (lane == 0) h[jj] = a;
+    // a solve's set-up: the GMRES state from |b|^2 (row 0, this thread's own sum)
+    if (ist && jj == 0 && lane == 0) gm_init_dev(ist, a, tol, maxit);
   }
   if (threadIdx.x == 0) *counter = 0u;
 }
@@ -372,11 +377,17 @@ __global__ __launch_bounds__(NT) void k_ortho_finish(const double* __restrict__ 
   }
 }
 
+// out = w / sqrt(nrm2); with cst, block 0 also starts the GMRES cycle from
+// nrm2 = beta^2; with zero, the kernel also clears zero[0, nzero).
 __global__ void k_scale_inv_sqrt(const double* __restrict__ w, const double* __restrict__ nrm2,
-                                 double* __restrict__ out, long long n) {
+                                 double* __restrict__ out, long long n, GmresState* cst,
+                                 double* __restrict__ zero, long long nzero) {
+  if (cst && blockIdx.x == 0 && threadIdx.x == 0) gm_cycle_dev(cst, nrm2);
   const double a = nrm2[0] > 0.0 ? 1.0 / sqrt(nrm2[0]) : 0.0;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) out[e] = a * w[e];
+  if (zero)
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nzero; e += stride) zero[e] = 0.0;
 }
 
 __global__ void k_copy_scaled(const double* __restrict__ x, double a, double* __restrict__ y, long long n) {
@@ -391,13 +402,14 @@ __global__ void k_sub_from(const double* __restrict__ b, double* __restrict__ w,
 
 // ------------------------------------------------------------ GMRES bookkeeping
 // The Hessenberg matrix, its Givens rotations and the residual estimate live
-// on the device (GmresState), updated by one single-thread kernel per
-// iteration, so the host can queue iterations ahead of the GPU; `done` ends a
-// restart cycle and makes the queued kernels of later iterations return.
+// on the device (GmresState), updated by the extra block of each iteration's
+// last Arnoldi kernel, so the host can queue iterations ahead of the GPU;
+// `done` ends a restart cycle and makes the queued kernels of later
+// iterations return.  The set-up runs in the last block of the |b|^2
+// reduction, a cycle's start in the kernel that scales V_0.
 
-__global__ void k_gm_init(GmresState* st, const double* __restrict__ nb2, double tol, int maxit) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double nb = sqrt(fmax(nb2[0], 0.0));
+__device__ void gm_init_dev(GmresState* st, double nb2, double tol, int maxit) {
+  const double nb = sqrt(fmax(nb2, 0.0));
   st->nb = nb;
   st->tol = tol;
   st->maxit = maxit;
@@ -409,8 +421,7 @@ __global__ void k_gm_init(GmresState* st, const double* __restrict__ nb2, double
 }
 
 // Start of a restart cycle with residual norm^2 beta2: g = (beta, 0, ...).
-__global__ void k_gm_cycle(GmresState* st, const double* __restrict__ beta2) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void gm_cycle_dev(GmresState* st, const double* __restrict__ beta2) {
   st->kdone = 0;
   if (st->converged) {
     st->done = 1;
@@ -471,7 +482,8 @@ inline unsigned grid_for(long long n) {
 }  // namespace
 
 int multi_dot(const double* V, long long ld, int k, const double* w, long long n, bool with_self,
-              double* partial, unsigned int* counter, double* h, hipStream_t s) {
+              double* partial, unsigned int* counter, double* h, hipStream_t s, GmresState* init, double tol,
+              int maxit) {
   if (k + (with_self ? 1 : 0) <= 0) return GDC_OK;
   if (k + 1 > MAXK) {
     set_error("multi_dot: too many vectors");
@@ -480,7 +492,12 @@ int multi_dot(const double* V, long long ld, int k, const double* w, long long n
   const long long want = (n + 16 * NT - 1) / (16 * NT);
   const unsigned nchunk = (unsigned)(want < DOT_MAX_BLOCKS ? (want > 0 ? want : 1) : DOT_MAX_BLOCKS);
   const unsigned kk = (unsigned)(k + (with_self ? 1 : 0));
-  hipLaunchKernelGGL(k_multi_dot, dim3(nchunk, kk), dim3(NT), 0, s, V, ld, k, w, n, partial, counter, h);
+  if (init && !(k == 0 && with_self)) {
+    set_error("multi_dot: the GMRES set-up needs exactly |w|^2");
+    return GDC_EINVAL;
+  }
+  hipLaunchKernelGGL(k_multi_dot, dim3(nchunk, kk), dim3(NT), 0, s, V, ld, k, w, n, partial, counter, h, init, tol,
+                     maxit);
   return check_launch("k_multi_dot");
 }
 
@@ -546,23 +563,16 @@ int arnoldi_orthogonalise(double* w, const double* V, long long ld, int k, long 
   return check_launch("k_ortho_finish2");
 }
 
-int gm_init(GmresState* st, const double* nb2, double tol, int maxit, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(64), 0, s, st, nb2, tol, maxit);
-  return check_launch("k_gm_init");
-}
-
-int gm_cycle(GmresState* st, const double* beta2, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_cycle, dim3(1), dim3(64), 0, s, st, beta2);
-  return check_launch("k_gm_cycle");
-}
 
 int gm_finish_cycle(GmresState* st, double* x, const double* V, long long ld, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_gm_update, dim3(grid_for(n)), dim3(NT), 0, s, x, V, ld, st, n);
   return check_launch("k_gm_update");
 }
 
-int scale_by_inv_sqrt(const double* w, const double* nrm2, double* out, long long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_inv_sqrt, dim3(grid_for(n)), dim3(NT), 0, s, w, nrm2, out, n);
+int scale_by_inv_sqrt(const double* w, const double* nrm2, double* out, long long n, hipStream_t s,
+                      GmresState* cycle, double* zero, long long nzero) {
+  hipLaunchKernelGGL(k_scale_inv_sqrt, dim3(grid_for(n > nzero ? n : nzero)), dim3(NT), 0, s, w, nrm2, out, n, cycle,
+                     zero, nzero);
   return check_launch("k_scale_inv_sqrt");
 }
 
