@@ -442,14 +442,16 @@ const Cx<R>* const* tw_of(gdc_handle* h) {
 
 // Sorts the blobs at positions r by grid tile and builds the spreading
 // tables; every spread at r needs them.
-int prepare_positions(gdc_handle* h, const double* r) {
+// zeroed: the tile counts and the table claim counter were cleared already
+// (by the step's opening clear).
+int prepare_positions(gdc_handle* h, const double* r, bool zeroed = false) {
   GDC_TRY(tile_sort(h->geom, h->tg, r, h->M, h->tile_ids, h->tile_count, h->tile_off, h->tile_cursor, h->trec,
-                    h->spos, h->stream));
+                    h->spos, h->stream, zeroed));
   if (h->precision == GDC_FP64)
     return spread_prepare<double>(h->geom, h->tg, h->trec, h->tile_off, h->tabs, h->tab_start, h->tab_count,
-                                  h->tab_claimed, h->stream);
+                                  h->tab_claimed, h->stream, zeroed);
   return spread_prepare<float>(h->geom, h->tg, h->trec, h->tile_off, h->tabs, h->tab_start, h->tab_count,
-                               h->tab_claimed, h->stream);
+                               h->tab_claimed, h->stream, zeroed);
 }
 
 // out = M_FCM lam at blob positions r (prepared by prepare_positions), minus
@@ -646,12 +648,17 @@ int gmres(gdc_handle* h, const double* Y, const double* q, const double* r, Gmre
 }
 
 // Blob forces and body forces/torques at (Y, q, r) into h->F.
-int forces_at(gdc_handle* h, const double* Y, const double* r) {
+bool steric_on(const gdc_handle* h) {
+  return h->cfg.forces.steric_k > 0.0 && h->cfg.forces.steric_cutoff > 0.0;
+}
+
+// zeroed: the pair-force cell counts were cleared already.
+int forces_at(gdc_handle* h, const double* Y, const double* r, bool zeroed = false) {
   const gdc_forces& f = h->cfg.forces;
   const double* fb = nullptr;
-  if (f.steric_k > 0.0 && f.steric_cutoff > 0.0) {
+  if (steric_on(h)) {
     GDC_TRY(steric_forces(h->bt, h->geom, r, f.steric_k, f.steric_cutoff, h->cell_count, h->cell_list,
-                          h->cell_cap, h->nc, h->flags, h->fblob, h->stream));
+                          h->cell_cap, h->nc, h->flags, h->fblob, h->stream, zeroed));
     fb = h->fblob;
   }
   return body_forces(h->bt, Y, r, fb, h->cforce, h->F, h->stream);
@@ -732,7 +739,14 @@ int step_advance(gdc_handle* h, bool block, int& adv) {
   }
   if (sr.phase == StepRun::IDLE && sr.to_start > 0 && sr.pend < 2) {
     const uint64_t step = h->step;
-    GDC_TRY(fill_zero(h->flags, 16, s));
+    // the step's counters in one launch: error flags, pair-force cell
+    // counts, tile counts, spreading-table claim (none is read again before
+    // this step uses it)
+    {
+      void* zp[4] = {h->flags, h->tile_count, h->tab_claimed, h->cell_count};
+      const size_t zb[4] = {16, tile_count_bytes(h->tg), 16, steric_on(h) ? cell_count_bytes(h->nc) : 0};
+      GDC_TRY(fill_zero_many(zp, zb, 4, s));
+    }
     GDC_TRY(make_fluct<R>(h, step));
     const double* Ym = h->Y;
     const double* qm = h->q;
@@ -744,8 +758,8 @@ int step_advance(gdc_handle* h, bool block, int& adv) {
     } else {
       GDC_TRY(blob_positions(h->bt, Ym, qm, h->rm, s));
     }
-    GDC_TRY(forces_at(h, Ym, h->rm));
-    GDC_TRY(prepare_positions(h, h->rm));
+    GDC_TRY(forces_at(h, Ym, h->rm, true));
+    GDC_TRY(prepare_positions(h, h->rm, true));
     GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_fl, h->v, h->M, h->geom.dV, nullptr, nullptr, nullptr, s,
                       nullptr, h->trec));
     if (h->vbg)

@@ -734,15 +734,14 @@ int rhs_build(const BodyTables& b, const double* q, const double* Y, const doubl
 
 int steric_forces(const BodyTables& b, const GridGeom& g, const double* r, double k, double cutoff,
                   int* cell_count, int* cell_list, int cap, const int nc[3], int* overflow, double* fblob,
-                  hipStream_t s) {
+                  hipStream_t s, bool zeroed) {
   CellGrid C;
   for (int d = 0; d < 3; ++d) {
     C.nc[d] = nc[d];
     C.L[d] = g.L[d];
     C.csz[d] = g.L[d] / nc[d];
   }
-  const long long ncell = (long long)nc[0] * nc[1] * nc[2];
-  GDC_TRY(fill_zero(cell_count, ((size_t)ncell * sizeof(int) + 15) / 16 * 16, s));
+  if (!zeroed) GDC_TRY(fill_zero(cell_count, cell_count_bytes(nc), s));
   hipLaunchKernelGGL(k_bin_blobs, dim3(nblk(b.M)), dim3(NT), 0, s, C, b.M, r, cell_count, cell_list, cap, overflow);
   GDC_TRY(check_launch("k_bin_blobs"));
   hipLaunchKernelGGL(k_steric, dim3(nblk((long long)b.M * STERIC_LANES)), dim3(NT), 0, s, C, b, r, cell_count,

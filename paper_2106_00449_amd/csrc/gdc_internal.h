@@ -232,8 +232,10 @@ int philox_normals_dev(uint64_t seed, uint32_t c1, uint64_t step, uint32_t c0_be
 // by tile, in blob order within a tile.
 size_t tile_record_bytes();
 // spos[i] is blob i's position in the sorted order.
+// zeroed: count (tile_count_bytes) was already cleared on the stream.
 int tile_sort(const GridGeom& g, const TileGeom& t, const double* r, int M, int* tile, int* count, int* off,
-              int* cursor, void* rec, int* spos, hipStream_t s);
+              int* cursor, void* rec, int* spos, hipStream_t s, bool zeroed = false);
+inline size_t tile_count_bytes(const TileGeom& t) { return ((size_t)t.ntiles * sizeof(int) + 15) / 16 * 16; }
 // Spreading tables: per tile, the blobs whose stencil reaches it and their
 // per-axis Gaussian factors at the tile's coordinates, built once per
 // configuration (after tile_sort) into `tabs` (spread_table_bytes bytes);
@@ -242,7 +244,7 @@ int tile_sort(const GridGeom& g, const TileGeom& t, const double* r, int M, int*
 size_t spread_table_bytes(const GridGeom& g, const TileGeom& t, int M, int precision);
 template <typename R>
 int spread_prepare(const GridGeom& g, const TileGeom& t, const void* rec, const int* off, void* tabs,
-                   int* tab_start, int* tab_count, unsigned int* claimed, hipStream_t s);
+                   int* tab_start, int* tab_count, unsigned int* claimed, hipStream_t s, bool zeroed = false);
 // f = S lam on every grid point (the whole field is written) from the
 // tables of the last spread_prepare.  lam_sorted, when given, holds lam in
 // the sorted order (3 x M) and is read instead.
@@ -262,6 +264,8 @@ template <typename R>
 int interp_fd(const GridGeom& g, const double* r, const double* dr, int NP, const R* u,
               double* v, double* vd, int M, hipStream_t s);
 int fill_zero(void* p, size_t bytes, hipStream_t s);
+// Clears n <= 4 buffers (16-byte aligned sizes and addresses) in one launch.
+int fill_zero_many(void* const* ptrs, const size_t* bytes, int n, hipStream_t s);
 // y (3 x n0 x n1 x n2, row-major, FP64) = the real-space field x in the layout of g.
 template <typename R>
 int field_to_rowmajor(const GridGeom& g, const R* x, double* y, hipStream_t s);
@@ -307,9 +311,13 @@ int update(const BodyTables& b, double* Y, double* q, const double* V, const dou
 int rhs_build(const BodyTables& b, const double* q, const double* Y, const double* r,
               const double* vslip, const double* vbg, double cbg, const double* F, double shear,
               double Ly, double* rhs, hipStream_t s);
+// zeroed: cell_count (cell_count_bytes) was already cleared on the stream.
 int steric_forces(const BodyTables& b, const GridGeom& g, const double* r, double k,
                   double cutoff, int* cell_count, int* cell_list, int cap, const int nc[3],
-                  int* overflow, double* fblob, hipStream_t s);
+                  int* overflow, double* fblob, hipStream_t s, bool zeroed = false);
+inline size_t cell_count_bytes(const int nc[3]) {
+  return ((size_t)nc[0] * nc[1] * nc[2] * sizeof(int) + 15) / 16 * 16;
+}
 int body_forces(const BodyTables& b, const double* Y, const double* r, const double* fblob,
                 const double* cforce, double* F, hipStream_t s);
 int check_finite(const double* x, long long n, int* flag, hipStream_t s);

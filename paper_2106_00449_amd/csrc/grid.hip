@@ -901,6 +901,46 @@ inline unsigned blocks_for(int M) {
 
 size_t tile_record_bytes() { return sizeof(SRec); }
 
+// Up to four buffers cleared by one launch (the segments are walked in turn).
+struct ZeroList {
+  uint4* p[4];
+  long long n16[4];
+  int n;
+};
+
+__global__ void k_fill_zero_many(ZeroList z) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int k = 0; k < z.n; ++k)
+    for (long long i = i0; i < z.n16[k]; i += stride) z.p[k][i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+int fill_zero_many(void* const* ptrs, const size_t* bytes, int n, hipStream_t s) {
+  if (n < 0 || n > 4) {
+    set_error("fill_zero_many: at most four buffers");
+    return GDC_EINVAL;
+  }
+  ZeroList z{};
+  long long most = 0;
+  int m = 0;
+  for (int k = 0; k < n; ++k) {
+    if (bytes[k] == 0) continue;
+    if ((bytes[k] & 15) || (reinterpret_cast<uintptr_t>(ptrs[k]) & 15)) {
+      set_error("fill_zero_many: sizes and addresses must be 16-byte aligned");
+      return GDC_EINVAL;
+    }
+    z.p[m] = reinterpret_cast<uint4*>(ptrs[k]);
+    z.n16[m] = (long long)(bytes[k] / 16);
+    most = std::max(most, z.n16[m]);
+    ++m;
+  }
+  z.n = m;
+  if (m == 0) return GDC_OK;
+  const long long blocks = std::min<long long>((most + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_fill_zero_many, dim3((unsigned)blocks), dim3(256), 0, s, z);
+  return check_launch("k_fill_zero_many");
+}
+
 int fill_zero(void* p, size_t bytes, hipStream_t s) {
   if (bytes == 0) return GDC_OK;
   if (bytes % 16 != 0 || (reinterpret_cast<uintptr_t>(p) & 15) != 0) {
@@ -972,8 +1012,8 @@ int blob_dot_x(const double* a, const double* b, int M, double* out, hipStream_t
 template int field_to_rowmajor<double>(const GridGeom&, const double*, double*, hipStream_t);
 
 int tile_sort(const GridGeom& g, const TileGeom& t, const double* r, int M, int* tile, int* count, int* off,
-              int* cursor, void* rec, int* spos, hipStream_t s) {
-  GDC_TRY(fill_zero(count, ((size_t)t.ntiles * sizeof(int) + 15) / 16 * 16, s));
+              int* cursor, void* rec, int* spos, hipStream_t s, bool zeroed) {
+  if (!zeroed) GDC_TRY(fill_zero(count, tile_count_bytes(t), s));
   if (M > 0) {
     hipLaunchKernelGGL(k_tile_count, dim3((M + 255) / 256), dim3(256), 0, s, g, t, r, M, tile, count);
     GDC_TRY(check_launch("k_tile_count"));
@@ -1006,12 +1046,12 @@ size_t spread_table_bytes(const GridGeom& g, const TileGeom& t, int M, int preci
 
 template <typename R>
 int spread_prepare(const GridGeom& g, const TileGeom& t, const void* rec, const int* off, void* tabs,
-                   int* tab_start, int* tab_count, unsigned int* claimed, hipStream_t s) {
+                   int* tab_start, int* tab_count, unsigned int* claimed, hipStream_t s, bool zeroed) {
   if (t.T[0] != 8 || t.T[1] != 8 || t.T[2] > 32) {
     set_error("spread: tiles must be 8 x 8 x (up to 32)");
     return GDC_EINVAL;
   }
-  GDC_TRY(fill_zero(claimed, 16, s));
+  if (!zeroed) GDC_TRY(fill_zero(claimed, 16, s));
   hipLaunchKernelGGL((k_spread_prep<R>), dim3(t.ntiles), dim3(NT), 0, s, g, t, (const SRec*)rec, off,
                      (HitTab<R>*)tabs, tab_start, tab_count, claimed);
   return check_launch("k_spread_prep");
@@ -1067,9 +1107,9 @@ int interp_fd(const GridGeom& g, const double* r, const double* dr, int NP, cons
 }
 
 template int spread_prepare<float>(const GridGeom&, const TileGeom&, const void*, const int*, void*, int*, int*,
-                                   unsigned int*, hipStream_t);
+                                   unsigned int*, hipStream_t, bool);
 template int spread_prepare<double>(const GridGeom&, const TileGeom&, const void*, const int*, void*, int*, int*,
-                                    unsigned int*, hipStream_t);
+                                    unsigned int*, hipStream_t, bool);
 template int spread<float>(const GridGeom&, const TileGeom&, const void*, const int*, const int*, const double*,
                            const double*, float*, hipStream_t, const int*);
 template int spread<double>(const GridGeom&, const TileGeom&, const void*, const int*, const int*, const double*,
