@@ -65,7 +65,7 @@ WORKLOAD_TEXT = {
                  "of z, shear 0.1 + harmonic pair repulsion, FP32 grid / FP64 bodies, dt=0.005",
 }
 
-SERVING_BUDGET = 8 << 30
+SERVING_BUDGET = 32 << 30
 SERVING_SLOTS = 16
 
 
@@ -109,7 +109,7 @@ def mobility_error(g, wl, w, Y0, q0, tol, precision="fp32"):
 
 
 def cpu_baseline(w, Y0, q0, tol):
-    """The FP64 oracle, as it stands, on one step of the same workload."""
+    """The FP64 oracle, as it stands, on the first steps of the same workload."""
     import numpy as np
     from oracle import fcm, gdc, rigid
     cores = len(os.sched_getaffinity(0))
@@ -118,11 +118,14 @@ def cpu_baseline(w, Y0, q0, tol):
     cfg = gdc.Config(rigid.Suspension(p, rigid.Bodies(w.shapes, w.body_shape), w.a), w.kT, w.dt,
                      w.noise_seed, gdc.Forces(w.steric_k, w.steric_cutoff,
                                               np.asarray(w.const_force, dtype=np.float64), w.shear_rate))
+    n_steps = 2
     t0 = time.perf_counter()
-    gdc.gdc_step(cfg, Y0, q0, 0, tol=tol)
+    Y, q = Y0, q0
+    for k in range(n_steps):
+        Y, q, _ = gdc.gdc_step(cfg, Y, q, k, tol=tol)
     dt = time.perf_counter() - t0
-    return {"value": w.M / dt, "unit": "blob-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"one gDC step of the same 1,000-rod suspension from the same state, "
+    return {"value": w.M * n_steps / dt, "unit": "blob-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"the first {n_steps} gDC steps of the same 1,000-rod suspension from the same state, "
                       f"GMRES tol {tol:g}, {dt:.1f} s"}
 
 
@@ -175,7 +178,7 @@ def timed_steps(g, s, Y, q, steps, warmup):
     lat = np.diff(log)[1:]
     if len(lat) != steps - 1:
         raise RuntimeError(f"step log holds {len(lat) + 1} latencies for {steps} steps")
-    return total, lat, st["gmres_iterations_mean"], st["nu_mean"]
+    return total, lat, st["gmres_iterations_mean"], st
 
 
 def kernel_bandwidth(g, s, Y, q, w, cov):
@@ -282,11 +285,16 @@ def serving_bench(g, wl, reqs, states, tol, budget, slots):
     sat = summarise(res, makespan=time.perf_counter() - t0)
     sat.update(peak_bytes=srv.peak_bytes, peak_slots=srv.peak_slots)
     rate = len(reqs) / sat["makespan_s"]
-    progress(f"serving: Poisson run at {rate:.1f} requests/s")
-    srv = Server(hbm_budget=budget, max_slots=slots)
-    res = srv.run(requests(rate))
-    poisson = summarise(res)
-    poisson.update(arrival_rate_per_s=rate, peak_bytes=srv.peak_bytes, peak_slots=srv.peak_slots)
+    # Poisson arrivals at 0.5x, 1x and 2x the saturation request rate
+    sweep = {}
+    for f in (0.5, 1.0, 2.0):
+        progress(f"serving: Poisson run at {f * rate:.1f} requests/s ({f:g}x saturation)")
+        srv = Server(hbm_budget=budget, max_slots=slots)
+        res = srv.run(requests(f * rate))
+        summ = summarise(res)
+        summ.update(arrival_rate_per_s=f * rate, peak_bytes=srv.peak_bytes, peak_slots=srv.peak_slots)
+        sweep[f"{f:g}x"] = summ
+    poisson = sweep["1x"]
 
     # one at a time on the plain paths, same requests (a sample)
     sample = order[:: max(1, len(order) // 16)][:16]
@@ -317,7 +325,7 @@ def serving_bench(g, wl, reqs, states, tol, budget, slots):
                     f"{min(w.n[0] for w in reqs)}^3..{max(w.n[0] for w in reqs)}^3, 50 gDC steps each, FP32",
         "gmres_tol": tol, "mobility_rel_err_smallest_largest": errs,
         "hbm_budget_bytes": budget, "max_slots": slots,
-        "saturation": sat, "poisson_at_saturation_rate": poisson,
+        "saturation": sat, "poisson_at_saturation_rate": poisson, "poisson_rate_sweep": sweep,
         "sequential_fp64_sample": seq["fp64"], "sequential_fp32_sample": seq["fp32"],
         "served_over_sequential_fp64": sat["blob_steps_per_s"] / seq["fp64"]["blob_steps_per_s"],
     }
@@ -385,7 +393,7 @@ def main():
         s.step(Y, q, args.warmup)
     torch.cuda.synchronize()
     g.probe_kernel(DOMINANT)
-    total, lat_ms, its, nus = timed_steps(g, s, Y, q, args.steps, 0)
+    total, lat_ms, its, nust = timed_steps(g, s, Y, q, args.steps, 0)
     if len(lat_ms) == 0:   # one timed step: its latency is the call's time
         lat_ms = np.array([total * 1e3])
     k_ms, k_launches = g.probe_read()
@@ -399,6 +407,14 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES,
                 "kernel": "k_spread_tab", "launches": k_launches, "avg_us": avg_s * 1e6,
                 "algorithmic_bytes": alg_bytes}
+    # the whole step against the byte model of the method's grid traffic:
+    # G (60 + 72 k) bytes per FP32 step with k operator applies (GMRES
+    # iterations), each 3D transform counted once read and once written
+    step_bytes = G * (60.0 + 72.0 * float(its))
+    step_gbs = step_bytes / (total / args.steps) / 1e9
+    step_roofline = {"model": "G (60 + 72 k) bytes per step, k = mean GMRES iterations",
+                     "bytes_per_step": step_bytes, "achieved": step_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": step_gbs / HBM_PEAK_GBS}
     launch = s.launch_config
     cov = grid_coverage(w, Y0, q0)
     kernels, fp64 = {}, {}
@@ -420,9 +436,12 @@ def main():
                    "gmres_tol": tol, "mobility_rel_err": err,
                    "gmres_iterations_mean": float(its),
                    "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
-                   "nu_mean": float(nus), "interp_grid_coverage": cov,
+                   "nu_mean": nust["nu_mean"], "nu_std": nust["nu_std"], "nu_min": nust["nu_min"],
+                   "nu_max": nust["nu_max"], "interp_grid_coverage": cov,
+                   "fft_passes": 3 if (max(w.n) <= 128 and w.n[1] == w.n[2]) else 5,
                    "fft_workgroup_sizes": launch},
         "roofline": roofline,
+        "step_roofline": step_roofline,
         "kernels": kernels,
         "fp64_single": fp64,
         "rheology": rheo,

@@ -136,6 +136,8 @@ typedef struct {
                                 (eta k^2) at the midpoint solve; else 0 */
   double gmres_iterations_mean; /* mean GMRES iterations over the call's steps */
   double nu_mean;            /* mean nu over the call's steps (1 for EM) */
+  double nu_std;             /* standard deviation of nu over the call's steps */
+  double nu_min, nu_max;     /* extremes of nu over the call's steps */
 } gdc_stats;
 
 typedef struct gdc_handle gdc_handle;

@@ -66,7 +66,8 @@ class _Stats(ctypes.Structure):
                 ("gmres_relres", ctypes.c_double), ("nu", ctypes.c_double),
                 ("nu_nonpositive", ctypes.c_int), ("ms", ctypes.c_double),
                 ("sine_vx", ctypes.c_double), ("gmres_iterations_mean", ctypes.c_double),
-                ("nu_mean", ctypes.c_double)]
+                ("nu_mean", ctypes.c_double), ("nu_std", ctypes.c_double), ("nu_min", ctypes.c_double),
+                ("nu_max", ctypes.c_double)]
 
 
 def _load():
@@ -229,7 +230,8 @@ def batch_step(susps, steps, until="all", max_ms=0.0):
     out = [{"steps_done": x.steps_done, "gmres_iterations": x.gmres_iterations,
             "gmres_relres": x.gmres_relres, "nu": x.nu, "nu_nonpositive": x.nu_nonpositive,
             "ms": x.ms, "sine_vx": x.sine_vx, "gmres_iterations_mean": x.gmres_iterations_mean,
-            "nu_mean": x.nu_mean} for x in stats[:nh]]
+            "nu_mean": x.nu_mean, "nu_std": x.nu_std, "nu_min": x.nu_min, "nu_max": x.nu_max}
+           for x in stats[:nh]]
     return [int(x) for x in st_in[:nh]], out, rc
 
 
@@ -300,7 +302,8 @@ class Suspension:
         stats = {"steps_done": st.steps_done, "gmres_iterations": st.gmres_iterations,
                  "gmres_relres": st.gmres_relres, "nu": st.nu, "nu_nonpositive": st.nu_nonpositive,
                  "ms": st.ms, "sine_vx": st.sine_vx, "gmres_iterations_mean": st.gmres_iterations_mean,
-                 "nu_mean": st.nu_mean, "rc": rc}
+                 "nu_mean": st.nu_mean, "nu_std": st.nu_std, "nu_min": st.nu_min, "nu_max": st.nu_max,
+                 "rc": rc}
         if rc != GDC_ENOTCONV:
             _check(rc)
         return stats

@@ -373,7 +373,7 @@ struct gdc_handle {
   double sine_scale = 0.0, sine_sum_coef = 0.0, sine_acc = 0.0;
   int sine_n = 0;
   // sums over the steps completed since reset_errors, for the call's means
-  double its_acc = 0.0, nu_acc = 0.0;
+  double its_acc = 0.0, nu_acc = 0.0, nu_acc2 = 0.0, nu_lo = 0.0, nu_hi = 0.0;
   int done_n = 0;
 
   ~gdc_handle() {
@@ -703,6 +703,9 @@ void retire_step(gdc_handle* h, bool gdc_scheme) {
   if (!(sr.nu > 0.0)) ++h->n_nonpos;
   h->its_acc += sr.gr.its;
   h->nu_acc += sr.nu;
+  h->nu_acc2 += sr.nu * sr.nu;
+  h->nu_lo = h->done_n ? std::min(h->nu_lo, sr.nu) : sr.nu;
+  h->nu_hi = h->done_n ? std::max(h->nu_hi, sr.nu) : sr.nu;
   ++h->done_n;
   if (h->vbg) {
     h->sine_acc += h->sine_scale + h->sine_sum_coef * rb[3];
@@ -835,7 +838,7 @@ void reset_errors(gdc_handle* h) {
   h->n_overflow = h->n_nonfinite = h->n_notconv = h->n_nonpos = 0;
   h->sine_acc = 0.0;
   h->sine_n = 0;
-  h->its_acc = h->nu_acc = 0.0;
+  h->its_acc = h->nu_acc = h->nu_acc2 = h->nu_lo = h->nu_hi = 0.0;
   h->done_n = 0;
 }
 
@@ -851,6 +854,9 @@ void fill_stats(const gdc_handle* h, gdc_stats* st) {
   st->sine_vx = sine_mean(h);
   st->gmres_iterations_mean = h->done_n ? h->its_acc / h->done_n : 0.0;
   st->nu_mean = h->done_n ? h->nu_acc / h->done_n : 0.0;
+  st->nu_std = h->done_n ? std::sqrt(std::max(0.0, h->nu_acc2 / h->done_n - st->nu_mean * st->nu_mean)) : 0.0;
+  st->nu_min = h->nu_lo;
+  st->nu_max = h->nu_hi;
 }
 
 int require_idle(const gdc_handle* h) {
