@@ -118,7 +118,10 @@ def test_pipelined_steps_equal_single_steps(lib, k):
     assert st["gmres_iterations"] == singles[-1]["gmres_iterations"]
     assert st["nu"] == singles[-1]["nu"]
     assert st["gmres_iterations_mean"] == pytest.approx(np.mean([x["gmres_iterations"] for x in singles]))
-    assert st["nu_mean"] == pytest.approx(np.mean([x["nu"] for x in singles]))
+    nus = np.array([x["nu"] for x in singles])
+    assert st["nu_mean"] == pytest.approx(nus.mean())
+    assert st["nu_min"] == nus.min() and st["nu_max"] == nus.max()
+    assert st["nu_std"] == pytest.approx(nus.std(), rel=1e-9, abs=1e-12)
 
 
 def test_batch_step_resumes_a_step_left_in_flight(lib):
