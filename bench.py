@@ -129,6 +129,53 @@ def cpu_baseline(w, Y0, q0, tol):
                       f"GMRES tol {tol:g}, {dt:.1f} s"}
 
 
+def oracle_timings(wl, tol):
+    """The oracle, as it stands, on the measurement configurations: seconds per
+    step and blob-steps/s with all host threads, and with one thread for the
+    two smallest.  1,000-rod and 4,096-body suspensions: first 3 steps; 8-rod
+    suspension: 100 steps (10 on one thread); serving: the first 3 steps of 8
+    requests (the smallest, the largest, 6 evenly spaced).  The 32,768-rod
+    suspension is left out: at about 10 oracle minutes per step its first 10
+    steps do not fit a bounded run."""
+    import numpy as np
+    from oracle import fcm, gdc, rigid
+    cores = len(os.sched_getaffinity(0))
+
+    def run(w, n_steps, workers, tol_w):
+        fcm.DEFAULT_WORKERS = workers
+        p = fcm.FcmParams(fcm.Grid(w.L, w.n), w.eta, w.sigma, w.rc)
+        cfg = gdc.Config(rigid.Suspension(p, rigid.Bodies(w.shapes, w.body_shape), w.a), w.kT, w.dt,
+                         w.noise_seed, gdc.Forces(w.steric_k, w.steric_cutoff,
+                                                  np.asarray(w.const_force, dtype=np.float64), w.shear_rate,
+                                                  w.sine_force))
+        Y, q = wl.initial_state(w)
+        t0 = time.perf_counter()
+        for k in range(n_steps):
+            Y, q, _ = gdc.gdc_step(cfg, Y, q, k, tol=tol_w)
+        dt = time.perf_counter() - t0
+        progress(f"oracle {w.name}: {n_steps} steps on {workers} threads, {dt:.1f} s")
+        return {"steps": n_steps, "threads": workers, "s_per_step": dt / n_steps, "blob_steps_per_s": w.M * n_steps / dt}
+
+    out = {"host_threads": cores, "gmres_tol": tol}
+    c1 = wl.rods8()
+    out["rods8"] = run(c1, 100, cores, tol)
+    out["rods8_one_thread"] = run(c1, 10, 1, tol)
+    c2 = wl.rods1000("fp64")
+    out["rods1000"] = run(c2, 3, cores, tol)
+    out["rods1000_one_thread"] = run(c2, 1, 1, tol)
+    out["mixed4096"] = run(wl.mixed4096(), 3, cores, tol)
+    reqs = wl.serving_requests(256)
+    order = np.argsort([w.M for w in reqs])
+    pick = sorted(set([int(order[0]), int(order[-1])] + [int(order[i]) for i in np.linspace(0, len(order) - 1, 8)[1:-1].astype(int)]))[:8]
+    blob_steps, secs = 0, 0.0
+    for i in pick:
+        r = run(reqs[i], 3, cores, tol)
+        blob_steps += reqs[i].M * 3
+        secs += r["s_per_step"] * 3
+    out["serving_sample"] = {"requests": len(pick), "steps_each": 3, "blob_steps_per_s": blob_steps / secs}
+    return out
+
+
 def grid_coverage(w, Y, q):
     """Fraction of grid points within the envelope cutoff of some blob (the
     part of the field an averaging pass must read)."""
@@ -346,6 +393,9 @@ def main():
                     help="time the headline suspension only (no kernel table, FP64 path or serving)")
     ap.add_argument("--workload", default="rods1000", choices=["rods1000", "mixed4096", "rods32768"],
                     help="suspension to time (the headline figure is quoted on rods1000)")
+    ap.add_argument("--oracle-timings", action="store_true",
+                    help="time the oracle on every measurement configuration instead (host only, ~20 min; "
+                         "no GPU work)")
     ap.add_argument("--kernel-table", action="store_true",
                     help="with --only-headline, still measure the per-kernel bandwidth table")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -358,6 +408,11 @@ def main():
 
     import numpy as np
     import workloads as wl
+
+    if args.oracle_timings:
+        tol = args.gmres_tol if args.gmres_tol > 0.0 else 1e-5
+        print(json.dumps({"oracle_timings": oracle_timings(wl, tol)}))
+        return
 
     # initial states first, in worker processes, before anything touches the GPU
     w = {"rods1000": lambda: wl.rods1000("fp32"), "mixed4096": wl.mixed4096,
