@@ -667,6 +667,12 @@ __global__ __launch_bounds__(NT) void k_spread_prep(GridGeom G, TileGeom T, cons
 // half is added to the even one through LDS in a fixed order.  The tile then
 // goes out with 16-byte stores, whole 128-byte rows at a time.  No atomics and
 // a fixed summation order: results repeat bit for bit.
+// Each round of up to 64 hits is staged in LDS; every wave keeps the round's
+// hit masks and forces in its lanes and takes them with readlane.  HOIST
+// reads all of a hit's table values into registers before its tests (one
+// LDS wait per hit, more registers: for few tiles per CU); without it the
+// plane factors are read where used (fewer registers, more workgroups per
+// CU: for many tiles per CU).  Both add the same terms in the same order.
 constexpr int NTS = 512;   // threads of a spreading workgroup
 
 // Marks values as needed here: the compiler keeps their loads ahead of this
