@@ -459,17 +459,30 @@ __device__ __forceinline__ Ranges axis_ranges(int g, int tstart, int Teff, int n
 // spread S lambda at that configuration (one per GMRES iteration) reads
 // them back: gather the forces, accumulate, write the tile.
 
-template <typename R>
+// Axis 2 keeps a window of WZ entries from tile offset zlo: WZ = 8 when a
+// stencil spans at most 8 points and a tile never holds both ends of the
+// axis (then the hit's points along axis 2 are one run of at most 8), else
+// the whole 32-point tile (zlo = 0).
+template <typename R, int WZ>
 struct HitTab {
   R f0[8], s0[8];      // axis 0 (f0 carries wnorm)
   R f1[8], s1[8];      // axis 1
-  R fz[32], sz[32];    // axis 2
+  R fz[WZ], sz[WZ];    // axis 2, tile offsets zlo .. zlo + WZ - 1
   int mask;            // bits 0-3: z-chunks the hit reaches; bits 8-15: axis-0 planes
   int pos;             // record position (index into the sorted order)
   int blob;
-  int pad;
+  int zlo;
 };
-static_assert(sizeof(HitTab<float>) % 16 == 0 && sizeof(HitTab<double>) % 16 == 0, "16-byte rows");
+static_assert(sizeof(HitTab<float, 8>) % 16 == 0 && sizeof(HitTab<double, 8>) % 16 == 0 &&
+              sizeof(HitTab<float, 32>) % 16 == 0 && sizeof(HitTab<double, 32>) % 16 == 0, "16-byte rows");
+
+// First tile offset along axis 2 of a hit's stencil run (origin g2 of an
+// n2-point axis, tile start ts2, stencil of P2 points).
+__device__ __forceinline__ int hit_zlo(int g2, int ts2, int n2, int P2) {
+  int u = ts2 - g2;
+  u += (u < 0) ? n2 : 0;
+  return u < P2 ? 0 : n2 - u;
+}
 
 // Candidates of a tile: the records of the (up to 5 x 5 x 5) neighbour tiles
 // whose anchored blobs can reach it, in neighbour order.
@@ -552,17 +565,19 @@ __device__ __forceinline__ bool tile_candidate(const GridGeom& G, const TileFram
 // exp(-d^2 / 2 sigma^2) (axis 0 also carries wnorm) and d^2, else 0 and
 // `big`.  The axis is a compile-time constant (a runtime index into the
 // kernel-argument struct would be a memory load per entry).
-template <typename R, int D>
+template <typename R, int D, int WZ>
 __device__ __forceinline__ void table_axis(const GridGeom& G, const TileFrame& F, int nr, const double (*he)[3],
-                                           const int* hg, HitTab<R>* out, R big) {
-  constexpr int W = D == 2 ? 32 : 8, LW = D == 2 ? 5 : 3;
+                                           const int* hg, HitTab<R, WZ>* out, R big) {
+  constexpr int W = D == 2 ? WZ : 8, LW = D == 2 ? (WZ == 32 ? 5 : 3) : 3;
   const int n = G.n[D], P = G.P[D];
   const double dx = G.dx[D], i2 = G.inv2s2, wn = G.wnorm;
   for (int e = threadIdx.x; e < nr * W; e += NT) {
-    const int h = e >> LW, j = e & (W - 1);
+    const int h = e >> LW, jw = e & (W - 1);
     const int gb = (hg[h] >> (10 * D)) & 1023;
+    const int j = (D == 2 && WZ != 32) ? hit_zlo(gb, F.ts[2], n, P) + jw : jw;   // tile offset
     int a = F.ts[D] + j - gb;
     a += (a < 0) ? n : 0;
+    a -= (a >= n) ? n : 0;
     R fv = R(0), sv = big;
     if (j < F.te[D] && a < P) {
       const double dd = he[h][D] + a * dx;
@@ -572,14 +587,14 @@ __device__ __forceinline__ void table_axis(const GridGeom& G, const TileFrame& F
       if (D == 0) fv *= R(wn);
     }
     if (D == 0) {
-      out[h].f0[j] = fv;
-      out[h].s0[j] = sv;
+      out[h].f0[jw] = fv;
+      out[h].s0[jw] = sv;
     } else if (D == 1) {
-      out[h].f1[j] = fv;
-      out[h].s1[j] = sv;
+      out[h].f1[jw] = fv;
+      out[h].s1[jw] = sv;
     } else {
-      out[h].fz[j] = fv;
-      out[h].sz[j] = sv;
+      out[h].fz[jw] = fv;
+      out[h].sz[jw] = sv;
     }
   }
 }
@@ -587,9 +602,9 @@ __device__ __forceinline__ void table_axis(const GridGeom& G, const TileFrame& F
 // Per tile: count its hits, claim room for them in `tabs` (tab_start,
 // tab_count), and write their tables in candidate order.  The order fixes
 // every later summation; the room's place does not matter.
-template <typename R>
+template <typename R, int WZ>
 __global__ __launch_bounds__(NT) void k_spread_prep(GridGeom G, TileGeom T, const SRec* __restrict__ rec,
-                                                    const int* __restrict__ off, HitTab<R>* __restrict__ tabs,
+                                                    const int* __restrict__ off, HitTab<R, WZ>* __restrict__ tabs,
                                                     int* __restrict__ tab_start, int* __restrict__ tab_count,
                                                     unsigned int* __restrict__ claimed) {
   constexpr int HMAX = NT;
@@ -641,16 +656,16 @@ __global__ __launch_bounds__(NT) void k_spread_prep(GridGeom G, TileGeom T, cons
       h_e[slot][1] = x.e[1];
       h_e[slot][2] = x.e[2];
       h_g[slot] = x.g;
-      HitTab<R>& t = tabs[running + slot];
+      HitTab<R, WZ>& t = tabs[running + slot];
       t.mask = mask;
       t.pos = pos;
       t.blob = x.blob;
-      t.pad = 0;
+      t.zlo = WZ == 32 ? 0 : hit_zlo((x.g >> 20) & 1023, F.ts[2], G.n[2], G.P[2]);
     }
     __syncthreads();
-    table_axis<R, 0>(G, F, nh, h_e, h_g, tabs + running, big);
-    table_axis<R, 1>(G, F, nh, h_e, h_g, tabs + running, big);
-    table_axis<R, 2>(G, F, nh, h_e, h_g, tabs + running, big);
+    table_axis<R, 0, WZ>(G, F, nh, h_e, h_g, tabs + running, big);
+    table_axis<R, 1, WZ>(G, F, nh, h_e, h_g, tabs + running, big);
+    table_axis<R, 2, WZ>(G, F, nh, h_e, h_g, tabs + running, big);
     running += nh;
     __syncthreads();
   }
@@ -695,8 +710,8 @@ __device__ __forceinline__ double read_lane(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <typename R, bool HOIST>
-__global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, const HitTab<R>* __restrict__ tabs,
+template <typename R, bool HOIST, int WZ>
+__global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, const HitTab<R, WZ>* __restrict__ tabs,
                                                    const int* __restrict__ tab_start,
                                                    const int* __restrict__ tab_count, const double* __restrict__ lam,
                                                    const double* __restrict__ lam_sorted, R* __restrict__ f,
@@ -708,11 +723,11 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
   // 40 words apart, 8 distinct bank groups (FP32); FP64 rows are 2 words per value
   constexpr int TZP = sizeof(R) == 4 ? TZ + 8 : TZ;
   constexpr int STAGE = 3 * TX * TX * TZP;
-  constexpr int TABR = HR * (int)(sizeof(HitTab<R>) / sizeof(R));
+  constexpr int TABR = HR * (int)(sizeof(HitTab<R, WZ>) / sizeof(R));
   constexpr int SH = TABR > STAGE ? TABR : STAGE;
   __shared__ __align__(16) R sh[SH];    // a round of tables, then the staged tile
   __shared__ R h_l[HR][3];
-  HitTab<R>* tab = reinterpret_cast<HitTab<R>*>(sh);
+  HitTab<R, WZ>* tab = reinterpret_cast<HitTab<R, WZ>*>(sh);
   // wave and half are wave-uniform; readfirstlane makes the per-hit tests scalar branches
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane((tid >> 6) & 3), half = __builtin_amdgcn_readfirstlane(tid >> 8);
@@ -727,7 +742,7 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
   R acc[TX][3];
 #pragma unroll
   for (int k = 0; k < TX; ++k) acc[k][0] = acc[k][1] = acc[k][2] = R(0);
-  constexpr int V16 = (int)(sizeof(HitTab<R>) / 16);
+  constexpr int V16 = (int)(sizeof(HitTab<R, WZ>) / 16);
   constexpr int LPT = (HR * V16 + NTS - 1) / NTS;   // 16-byte table loads per thread and round
   for (int hb = 0; hb < cnt; hb += HR) {
     const int nr = min(HR, cnt - hb);
@@ -750,7 +765,7 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
     }
     double lv[3] = {0.0, 0.0, 0.0};
     if (tid < nr) {
-      const HitTab<R>& g = tabs[start + hb + tid];
+      const HitTab<R, WZ>& g = tabs[start + hb + tid];
       const long long base = lam_sorted ? 3LL * g.pos : 3LL * g.blob;
       const double* ls = lam_sorted ? lam_sorted : lam;
 #pragma unroll
@@ -770,6 +785,7 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
     // hit loop takes them with readlane (no LDS round trip per hit)
     const int hr = lane < nr ? lane : 0;
     const int hmask = lane < nr ? tab[hr].mask : 0;
+    const int hzlo = lane < nr ? tab[hr].zlo : 0;
     const R hl0 = h_l[hr][0], hl1 = h_l[hr][1], hl2 = h_l[hr][2];
     // the loop runs with every lane of the wave active up to the per-lane
     // test below, so each readlane sees values all lanes hold
@@ -777,7 +793,11 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
       const int hm = __builtin_amdgcn_readlane(hmask, h);
       if (!((hm >> wave) & 1)) continue;
       const R l0 = read_lane(hl0, h), l1 = read_lane(hl1, h), l2 = read_lane(hl2, h);
-      const HitTab<R>& t = tab[h];
+      const HitTab<R, WZ>& t = tab[h];
+      // this lane's entry of the hit's axis-2 window (outside it: no weight)
+      const int zz = z - (WZ == 32 ? 0 : __builtin_amdgcn_readlane(hzlo, h));
+      const bool zin = (unsigned)zz < (unsigned)WZ;
+      const int zi = zin ? zz : 0;
       if constexpr (HOIST) {
         // every table value of the hit in registers before any test, so
         // that one LDS wait serves the hit (a load left under a test costs
@@ -788,7 +808,7 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
           f0v[k] = t.f0[k];
           s0v[k] = t.s0[k];
         }
-        const R s1v = t.s1[j1], szv = t.sz[z], f1v = t.f1[j1], fzv = t.fz[z];
+        const R s1v = t.s1[j1], szv = zin ? t.sz[zi] : R(1e30), f1v = t.f1[j1], fzv = t.fz[zi];
         pin_values(f0v, s0v, s1v, szv, f1v, fzv);
         const R s12 = s1v + szv;
         if (!live || s12 > rc2) continue;
@@ -804,10 +824,10 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
       } else {
         // plane factors read where they are used: fewer registers, more
         // workgroups per CU when the tiles run in many rounds
-        if (!live) continue;
-        const R s12 = t.s1[j1] + t.sz[z];
+        if (!live || !zin) continue;
+        const R s12 = t.s1[j1] + t.sz[zi];
         if (s12 > rc2) continue;
-        const R f12 = t.f1[j1] * t.fz[z];
+        const R f12 = t.f1[j1] * t.fz[zi];
 #pragma unroll
         for (int k = 0; k < TX; ++k) {
           if (!((hm >> (8 + k)) & 1)) continue;
@@ -1046,7 +1066,9 @@ size_t spread_table_bytes(const GridGeom& g, const TileGeom& t, int M, int preci
     const int k = (g.P[d] - 1 + t.T[d] - 1) / t.T[d] + 2;
     per *= (size_t)std::min(k, t.nt[d]);
   }
-  const size_t rec = precision == GDC_FP64 ? sizeof(HitTab<double>) : sizeof(HitTab<float>);
+  const size_t rec = precision == GDC_FP64
+                         ? (t.wz8 ? sizeof(HitTab<double, 8>) : sizeof(HitTab<double, 32>))
+                         : (t.wz8 ? sizeof(HitTab<float, 8>) : sizeof(HitTab<float, 32>));
   return per * (size_t)(M > 0 ? M : 1) * rec;
 }
 
@@ -1058,8 +1080,12 @@ int spread_prepare(const GridGeom& g, const TileGeom& t, const void* rec, const 
     return GDC_EINVAL;
   }
   if (!zeroed) GDC_TRY(fill_zero(claimed, 16, s));
-  hipLaunchKernelGGL((k_spread_prep<R>), dim3(t.ntiles), dim3(NT), 0, s, g, t, (const SRec*)rec, off,
-                     (HitTab<R>*)tabs, tab_start, tab_count, claimed);
+  if (t.wz8)
+    hipLaunchKernelGGL((k_spread_prep<R, 8>), dim3(t.ntiles), dim3(NT), 0, s, g, t, (const SRec*)rec, off,
+                       (HitTab<R, 8>*)tabs, tab_start, tab_count, claimed);
+  else
+    hipLaunchKernelGGL((k_spread_prep<R, 32>), dim3(t.ntiles), dim3(NT), 0, s, g, t, (const SRec*)rec, off,
+                       (HitTab<R, 32>*)tabs, tab_start, tab_count, claimed);
   return check_launch("k_spread_prep");
 }
 
@@ -1073,12 +1099,16 @@ int spread(const GridGeom& g, const TileGeom& t, const void* tabs, const int* ta
   const ProbeEvents pe = probe_claim("spread");
   // both variants add the same terms in the same order: identical results.
   // FP64 tables would need 150 registers a lane hoisted: always the lean one
-  if (t.one_round && sizeof(R) == 4)
-    hipExtLaunchKernelGGL((k_spread_tab<R, true>), dim3(t.ntiles), dim3(NTS), 0, s, pe.start, pe.stop, 0, g, t,
-                          (const HitTab<R>*)tabs, tab_start, tab_count, lam, lam_sorted, f, skip);
-  else
-    hipExtLaunchKernelGGL((k_spread_tab<R, false>), dim3(t.ntiles), dim3(NTS), 0, s, pe.start, pe.stop, 0, g, t,
-                          (const HitTab<R>*)tabs, tab_start, tab_count, lam, lam_sorted, f, skip);
+  const bool hoist = t.one_round && sizeof(R) == 4;
+#define GDC_SPREAD_(H, W)                                                                                     \
+  hipExtLaunchKernelGGL((k_spread_tab<R, H, W>), dim3(t.ntiles), dim3(NTS), 0, s, pe.start, pe.stop, 0, g, t, \
+                        (const HitTab<R, W>*)tabs, tab_start, tab_count, lam, lam_sorted, f, skip)
+  if (t.wz8) {
+    if (hoist) GDC_SPREAD_(true, 8); else GDC_SPREAD_(false, 8);
+  } else {
+    if (hoist) GDC_SPREAD_(true, 32); else GDC_SPREAD_(false, 32);
+  }
+#undef GDC_SPREAD_
   return check_launch("k_spread_tab");
 }
 
