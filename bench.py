@@ -135,7 +135,7 @@ def oracle_timings(wl, tol):
     two smallest.  1,000-rod and 4,096-body suspensions: first 3 steps; 8-rod
     suspension: 100 steps (10 on one thread); serving: the first 3 steps of 8
     requests (the smallest, the largest, 6 evenly spaced).  The 32,768-rod
-    suspension is left out: at about 10 oracle minutes per step its first 10
+    suspension is left out: at over 20 oracle minutes per step its first
     steps do not fit a bounded run."""
     import numpy as np
     from oracle import fcm, gdc, rigid
