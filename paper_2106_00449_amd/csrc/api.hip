@@ -349,7 +349,7 @@ struct gdc_handle {
   int* spos = nullptr;
   double* zsorted = nullptr;
   void* tabs = nullptr;          // spreading tables of the current configuration
-  int *tab_start = nullptr, *tab_count = nullptr;
+  int *tab_start = nullptr, *tab_count = nullptr, *tab_order = nullptr;
   unsigned int* tab_claimed = nullptr;
   double* hhost = nullptr;   // pinned readback
   GmresState* gm = nullptr;  // device GMRES bookkeeping
@@ -449,9 +449,9 @@ int prepare_positions(gdc_handle* h, const double* r, bool zeroed = false) {
                     h->spos, h->stream, zeroed));
   if (h->precision == GDC_FP64)
     return spread_prepare<double>(h->geom, h->tg, h->trec, h->tile_off, h->tabs, h->tab_start, h->tab_count,
-                                  h->tab_claimed, h->stream, zeroed);
+                                  h->tab_order, h->tab_claimed, h->stream, zeroed);
   return spread_prepare<float>(h->geom, h->tg, h->trec, h->tile_off, h->tabs, h->tab_start, h->tab_count,
-                               h->tab_claimed, h->stream, zeroed);
+                               h->tab_order, h->tab_claimed, h->stream, zeroed);
 }
 
 // out = M_FCM lam at blob positions r (prepared by prepare_positions), minus
@@ -462,7 +462,7 @@ int apply_mobility(gdc_handle* h, const double* r, const double* lam, double* ou
                    const double* V = nullptr, const double* lam_sorted = nullptr, const int* skip = nullptr) {
   const GridGeom& g = h->geom;
   R* f = (R*)h->grid[0];
-  GDC_TRY(spread<R>(g, h->tg, h->tabs, h->tab_start, h->tab_count, lam, lam_sorted, f, h->stream, skip));
+  GDC_TRY(spread<R>(g, h->tg, h->tabs, h->tab_order, lam, lam_sorted, f, h->stream, skip));
   GDC_TRY(stokes_solve<R>(g, tw_of<R>(h), f, (Cx<R>*)h->grid[1], (Cx<R>*)h->grid[2], h->stream, skip));
   return interp<R>(g, r, f, out, h->M, g.dV, h->bt.blob_body, Y, V, h->stream, skip, h->trec);
 }
@@ -747,7 +747,8 @@ int step_advance(gdc_handle* h, bool block, int& adv) {
     // this step uses it)
     {
       void* zp[4] = {h->flags, h->tile_count, h->tab_claimed, h->cell_count};
-      const size_t zb[4] = {16, tile_count_bytes(h->tg), 16, steric_on(h) ? cell_count_bytes(h->nc) : 0};
+      const size_t zb[4] = {16, tile_count_bytes(h->tg), spread_claim_bytes(),
+                            steric_on(h) ? cell_count_bytes(h->nc) : 0};
       GDC_TRY(fill_zero_many(zp, zb, 4, s));
     }
     GDC_TRY(make_fluct<R>(h, step));
@@ -1205,7 +1206,8 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
     }
     GDC_TRY(h->alloc(&h->tab_start, (size_t)t.ntiles));
     GDC_TRY(h->alloc(&h->tab_count, (size_t)t.ntiles));
-    GDC_TRY(h->alloc(&h->tab_claimed, 4));
+    GDC_TRY(h->alloc(&h->tab_order, 4 * (size_t)t.ntiles));
+    GDC_TRY(h->alloc(&h->tab_claimed, spread_claim_bytes() / sizeof(unsigned int)));
   }
   GDC_TRY(h->alloc(&h->gm, 1));
   if (!h->dry) {

@@ -240,18 +240,23 @@ inline size_t tile_count_bytes(const TileGeom& t) { return ((size_t)t.ntiles * s
 // Spreading tables: per tile, the blobs whose stencil reaches it and their
 // per-axis Gaussian factors at the tile's coordinates, built once per
 // configuration (after tile_sort) into `tabs` (spread_table_bytes bytes);
-// tab_start / tab_count (ntiles each) locate each tile's entries, `claimed`
-// is 16 bytes of scratch.
+// tab_start / tab_count (ntiles each) locate each tile's entries, `order`
+// (4 ntiles ints) receives the launch order of the tiles for spread,
+// `claimed` is spread_claim_bytes() of scratch (the room counter, then the
+// hit-count histogram and its cursors).
+constexpr int ORDER_BUCKETS = 256;
+constexpr size_t spread_claim_bytes() { return 16 + 2 * ORDER_BUCKETS * sizeof(unsigned int); }
 size_t spread_table_bytes(const GridGeom& g, const TileGeom& t, int M, int precision);
 template <typename R>
 int spread_prepare(const GridGeom& g, const TileGeom& t, const void* rec, const int* off, void* tabs,
-                   int* tab_start, int* tab_count, unsigned int* claimed, hipStream_t s, bool zeroed = false);
+                   int* tab_start, int* tab_count, int* order, unsigned int* claimed, hipStream_t s,
+                   bool zeroed = false);
 // f = S lam on every grid point (the whole field is written) from the
-// tables of the last spread_prepare.  lam_sorted, when given, holds lam in
-// the sorted order (3 x M) and is read instead.
+// tables and tile order of the last spread_prepare.  lam_sorted, when
+// given, holds lam in the sorted order (3 x M) and is read instead.
 template <typename R>
-int spread(const GridGeom& g, const TileGeom& t, const void* tabs, const int* tab_start, const int* tab_count,
-           const double* lam, const double* lam_sorted, R* f, hipStream_t s, const int* skip = nullptr);
+int spread(const GridGeom& g, const TileGeom& t, const void* tabs, const int* order, const double* lam,
+           const double* lam_sorted, R* f, hipStream_t s, const int* skip = nullptr);
 // v = scale J u, minus U_p + Omega_p x (r_i - Y_p) when V (N x 6) is given.
 // sorted, when given, is the record array of tile_sort for the same
 // positions r: blobs are then visited in the sorted order (same results).

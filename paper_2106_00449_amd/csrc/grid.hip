@@ -601,7 +601,9 @@ __device__ __forceinline__ void table_axis(const GridGeom& G, const TileFrame& F
 
 // Per tile: count its hits, claim room for them in `tabs` (tab_start,
 // tab_count), and write their tables in candidate order.  The order fixes
-// every later summation; the room's place does not matter.
+// every later summation; the room's place does not matter.  Each tile also
+// adds one to bucket min(hits, 255) of the histogram at claimed + 4, from
+// which k_tile_order sets the launch order.
 template <typename R, int WZ>
 __global__ __launch_bounds__(NT) void k_spread_prep(GridGeom G, TileGeom T, const SRec* __restrict__ rec,
                                                     const int* __restrict__ off, HitTab<R, WZ>* __restrict__ tabs,
@@ -633,6 +635,7 @@ __global__ __launch_bounds__(NT) void k_spread_prep(GridGeom G, TileGeom T, cons
     base_s = (int)atomicAdd(claimed, (unsigned)nh);
     tab_start[blockIdx.x] = base_s;
     tab_count[blockIdx.x] = nh;
+    atomicAdd(claimed + 4 + min(nh, ORDER_BUCKETS - 1), 1u);
   }
   __syncthreads();
   const R big = R(1e30);
@@ -669,6 +672,42 @@ __global__ __launch_bounds__(NT) void k_spread_prep(GridGeom G, TileGeom T, cons
     running += nh;
     __syncthreads();
   }
+}
+
+// Launch order of the spreading workgroups: tiles by hit count, largest
+// first, as {tile, start, count, 0}, so that the longest tiles start with
+// the first workgroups instead of ending the launch.  One thread per tile:
+// every workgroup scans the hit-count histogram of k_spread_prep (claimed +
+// 4, descending), and a tile takes the next place of its bucket from the
+// cursors at claimed + 4 + ORDER_BUCKETS.  Ties land in any order; a tile's
+// result does not depend on where it is launched.
+__global__ __launch_bounds__(NT) void k_tile_order(const int* __restrict__ tab_start,
+                                                   const int* __restrict__ tab_count, int ntiles,
+                                                   unsigned int* __restrict__ claimed, int4* __restrict__ order) {
+  static_assert(ORDER_BUCKETS == NT, "one bucket per thread");
+  __shared__ int base[ORDER_BUCKETS], wsum[WAVES];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int t = blockIdx.x * NT + tid;
+  const int c = t < ntiles ? tab_count[t] : 0;
+  const int st = t < ntiles ? tab_start[t] : 0;
+  // thread i takes bucket ORDER_BUCKETS - 1 - i: an exclusive scan in descending count
+  const int v = (int)claimed[4 + ORDER_BUCKETS - 1 - tid];
+  int inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += u;
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  int before = 0;
+  for (int w = 0; w < wave; ++w) before += wsum[w];
+  base[ORDER_BUCKETS - 1 - tid] = before + inc - v;
+  __syncthreads();
+  if (t >= ntiles) return;
+  const int b = min(c, ORDER_BUCKETS - 1);
+  const int slot = base[b] + (int)atomicAdd(claimed + 4 + ORDER_BUCKETS + b, 1u);
+  if (slot < ntiles) order[slot] = make_int4(t, st, c, 0);
 }
 
 // Spreading f = S lambda, one workgroup of 512 threads per tile, from the
@@ -712,8 +751,7 @@ __device__ __forceinline__ double read_lane(double v, int l) {
 
 template <typename R, bool HOIST, int WZ>
 __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, const HitTab<R, WZ>* __restrict__ tabs,
-                                                   const int* __restrict__ tab_start,
-                                                   const int* __restrict__ tab_count, const double* __restrict__ lam,
+                                                   const int4* __restrict__ order, const double* __restrict__ lam,
                                                    const double* __restrict__ lam_sorted, R* __restrict__ f,
                                                    const int* __restrict__ skip) {
   if (skip && *skip) return;
@@ -731,11 +769,12 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
   // wave and half are wave-uniform; readfirstlane makes the per-hit tests scalar branches
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane((tid >> 6) & 3), half = __builtin_amdgcn_readfirstlane(tid >> 8);
-  const int tl = blockIdx.x;
+  // workgroups take the tiles in the order of k_spread_prep, largest first
+  const int4 ord = order[blockIdx.x];
+  const int tl = ord.x, start = ord.y, cnt = ord.z;
   const int t2 = tl % T.nt[2], t1 = (tl / T.nt[2]) % T.nt[1], t0 = tl / (T.nt[1] * T.nt[2]);
   const int ts[3] = {t0 * T.T[0], t1 * T.T[1], t2 * T.T[2]};
   const int te[3] = {min(T.T[0], G.n[0] - ts[0]), min(T.T[1], G.n[1] - ts[1]), min(T.T[2], G.n[2] - ts[2])};
-  const int start = tab_start[tl], cnt = tab_count[tl];
   const R rc2 = R(G.rc2);
   const int j1 = lane >> 3, zl = lane & 7, z = wave * 8 + zl;
   const bool live = j1 < te[1] && z < te[2];
@@ -1074,24 +1113,27 @@ size_t spread_table_bytes(const GridGeom& g, const TileGeom& t, int M, int preci
 
 template <typename R>
 int spread_prepare(const GridGeom& g, const TileGeom& t, const void* rec, const int* off, void* tabs,
-                   int* tab_start, int* tab_count, unsigned int* claimed, hipStream_t s, bool zeroed) {
+                   int* tab_start, int* tab_count, int* order, unsigned int* claimed, hipStream_t s, bool zeroed) {
   if (t.T[0] != 8 || t.T[1] != 8 || t.T[2] > 32) {
     set_error("spread: tiles must be 8 x 8 x (up to 32)");
     return GDC_EINVAL;
   }
-  if (!zeroed) GDC_TRY(fill_zero(claimed, 16, s));
+  if (!zeroed) GDC_TRY(fill_zero(claimed, spread_claim_bytes(), s));
   if (t.wz8)
     hipLaunchKernelGGL((k_spread_prep<R, 8>), dim3(t.ntiles), dim3(NT), 0, s, g, t, (const SRec*)rec, off,
                        (HitTab<R, 8>*)tabs, tab_start, tab_count, claimed);
   else
     hipLaunchKernelGGL((k_spread_prep<R, 32>), dim3(t.ntiles), dim3(NT), 0, s, g, t, (const SRec*)rec, off,
                        (HitTab<R, 32>*)tabs, tab_start, tab_count, claimed);
-  return check_launch("k_spread_prep");
+  GDC_TRY(check_launch("k_spread_prep"));
+  hipLaunchKernelGGL(k_tile_order, dim3((t.ntiles + NT - 1) / NT), dim3(NT), 0, s, tab_start, tab_count, t.ntiles,
+                     claimed, (int4*)order);
+  return check_launch("k_tile_order");
 }
 
 template <typename R>
-int spread(const GridGeom& g, const TileGeom& t, const void* tabs, const int* tab_start, const int* tab_count,
-           const double* lam, const double* lam_sorted, R* f, hipStream_t s, const int* skip) {
+int spread(const GridGeom& g, const TileGeom& t, const void* tabs, const int* order, const double* lam,
+           const double* lam_sorted, R* f, hipStream_t s, const int* skip) {
   if (t.T[0] != 8 || t.T[1] != 8 || t.T[2] > 32) {
     set_error("spread: tiles must be 8 x 8 x (up to 32)");
     return GDC_EINVAL;
@@ -1102,7 +1144,7 @@ int spread(const GridGeom& g, const TileGeom& t, const void* tabs, const int* ta
   const bool hoist = t.one_round && sizeof(R) == 4;
 #define GDC_SPREAD_(H, W)                                                                                     \
   hipExtLaunchKernelGGL((k_spread_tab<R, H, W>), dim3(t.ntiles), dim3(NTS), 0, s, pe.start, pe.stop, 0, g, t, \
-                        (const HitTab<R, W>*)tabs, tab_start, tab_count, lam, lam_sorted, f, skip)
+                        (const HitTab<R, W>*)tabs, (const int4*)order, lam, lam_sorted, f, skip)
   if (t.wz8) {
     if (hoist) GDC_SPREAD_(true, 8); else GDC_SPREAD_(false, 8);
   } else {
@@ -1143,13 +1185,13 @@ int interp_fd(const GridGeom& g, const double* r, const double* dr, int NP, cons
 }
 
 template int spread_prepare<float>(const GridGeom&, const TileGeom&, const void*, const int*, void*, int*, int*,
-                                   unsigned int*, hipStream_t, bool);
+                                   int*, unsigned int*, hipStream_t, bool);
 template int spread_prepare<double>(const GridGeom&, const TileGeom&, const void*, const int*, void*, int*, int*,
-                                    unsigned int*, hipStream_t, bool);
-template int spread<float>(const GridGeom&, const TileGeom&, const void*, const int*, const int*, const double*,
-                           const double*, float*, hipStream_t, const int*);
-template int spread<double>(const GridGeom&, const TileGeom&, const void*, const int*, const int*, const double*,
-                            const double*, double*, hipStream_t, const int*);
+                                    int*, unsigned int*, hipStream_t, bool);
+template int spread<float>(const GridGeom&, const TileGeom&, const void*, const int*, const double*, const double*,
+                           float*, hipStream_t, const int*);
+template int spread<double>(const GridGeom&, const TileGeom&, const void*, const int*, const double*, const double*,
+                            double*, hipStream_t, const int*);
 template int interp<float>(const GridGeom&, const double*, const float*, double*, int, double, const int*,
                            const double*, const double*, hipStream_t, const int*, const void*);
 template int interp<double>(const GridGeom&, const double*, const double*, double*, int, double, const int*,
