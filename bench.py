@@ -52,9 +52,9 @@ BYTES_PER_BLOB = 56
 # of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, averaged
 # over the spreading dispatches that did work), each scaled by the 256 MiB
 # copy that --copy-calibration adds (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0):
-# 8,673,778 B read + 25,165,824 B written.  Set back to None whenever
+# 9,109,743 B read + 25,165,824 B written.  Set back to None whenever
 # k_spread_tab changes, until the counters are taken again.
-TRAFFIC_BYTES = 33839602
+TRAFFIC_BYTES = 34275567
 
 WORKLOAD_TEXT = {
     "rods1000": "rods1000: 1,000 rods x 10 blobs (10,000 blobs), L=128a, grid 128^3, FP32 grid / FP64 bodies "
