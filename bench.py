@@ -13,7 +13,8 @@ parity-tested against the FP64 oracle), on the first state with a probe force
 F ~ N(0,1) per body.
 
 Beside the headline figure the JSON line carries:
-  roofline      the dominant kernel (Gaussian spreading) against HBM peak;
+  roofline      the step's dominant kernel (at 128^3 the inverse plane pass of
+                the 3D transform) against HBM peak;
   kernels       achieved bandwidth of spreading, averaging and each FFT pass;
   fp64_single   the same suspension on the plain FP64 path;
   rheology      effective viscosity of 500 rods under the sinusoidal forcing;
@@ -40,21 +41,34 @@ sys.path.insert(0, ROOT)
 METRIC = "blob-steps/sec of gDC step at 1e-5 rel mobility error; p50/p99 step latency"
 HBM_PEAK_GBS = 8000.0
 
-# Dominant kernel of the step (largest share of GPU time in the kernel-trace
-# summary): Gaussian spreading S lambda.  Its algorithmic traffic per launch is
-# the FP32 force field written once (3 components x 4 B per grid point) plus,
-# per blob, its sorted stencil record (32 B) and its force (3 x 8 B).
-DOMINANT = "spread"
+# Dominant kernel of each workload's step (largest share of GPU time in its
+# kernel trace) as (probe family, kernel, algorithmic bytes per launch from G
+# grid points and M blobs).  At 128^3 it is the inverse plane pass of the
+# three-pass transform (inverse FFT along axis 1 and C2R along axis 2 of a
+# whole plane), run once per GMRES iteration and once for the random
+# velocity field: it reads the three half spectra (G/2 complex FP32 values
+# each) and writes the three real components (G FP32 values each), 24 G
+# bytes.  The larger grids take the five-pass transform, whose longest pass
+# moves 24 G bytes too.
+DOMINANT = {
+    "rods1000": ("fft_plane_inv", "k_plane_inv", lambda G, M: 24 * G),
+    "mixed4096": ("fft_c2r", "k_c2r_axis2", lambda G, M: 24 * G),
+    "rods32768": ("fft_project", "k_axis0_project", lambda G, M: 24 * G),
+}
+# Spreading, for the kernel table: the FP32 force field written once
+# (3 components x 4 B per grid point) plus, per blob, its sorted stencil
+# record (32 B) and its force (3 x 8 B).
 BYTES_PER_POINT = 12
 BYTES_PER_BLOB = 56
 
-# HBM traffic of the dominant kernel per launch from two rocprofv3 --pmc runs
-# of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, averaged
-# over the spreading dispatches that did work), each scaled by the 256 MiB
-# copy that --copy-calibration adds (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0):
-# 9,109,743 B read + 25,165,824 B written.  Set back to None whenever
-# k_spread_tab changes, until the counters are taken again.
-TRAFFIC_BYTES = 34275567
+# HBM traffic of the 1,000-rod workload's dominant kernel per launch from two
+# rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch, averaged over the dispatches of the instantiation the timed
+# region runs), each scaled by the 256 MiB copy that --copy-calibration adds
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0): 24,239,605 B read + 25,165,824 B
+# written.  Set back to None whenever that kernel changes, until the
+# counters are taken again.  Other workloads report no traffic.
+TRAFFIC_BYTES = 49405429
 
 WORKLOAD_TEXT = {
     "rods1000": "rods1000: 1,000 rods x 10 blobs (10,000 blobs), L=128a, grid 128^3, FP32 grid / FP64 bodies "
@@ -447,7 +461,8 @@ def main():
     if args.warmup:
         s.step(Y, q, args.warmup)
     torch.cuda.synchronize()
-    g.probe_kernel(DOMINANT)
+    dom_family, dom_kernel, dom_bytes = DOMINANT[args.workload]
+    g.probe_kernel(dom_family)
     total, lat_ms, its, nust = timed_steps(g, s, Y, q, args.steps, 0)
     if len(lat_ms) == 0:   # one timed step: its latency is the call's time
         lat_ms = np.array([total * 1e3])
@@ -455,12 +470,13 @@ def main():
     g.probe_kernel(None)
     value = w.M * args.steps / total
     G = int(np.prod(w.n))
-    alg_bytes = BYTES_PER_POINT * G + BYTES_PER_BLOB * w.M
+    alg_bytes = dom_bytes(G, w.M)
     avg_s = k_ms * 1e-3 / max(k_launches, 1)
     achieved = alg_bytes / avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES,
-                "kernel": "k_spread_tab", "launches": k_launches, "avg_us": avg_s * 1e6,
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": TRAFFIC_BYTES if args.workload == "rods1000" else None,
+                "kernel": dom_kernel, "launches": k_launches, "avg_us": avg_s * 1e6,
                 "algorithmic_bytes": alg_bytes}
     # the whole step against the byte model of the method's grid traffic:
     # G (60 + 72 k) bytes per FP32 step with k operator applies (GMRES
