@@ -416,8 +416,8 @@ def main():
                     help="run one 256 MiB device copy first (counter calibration for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the sharding design); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(its sharding is a design, not code); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

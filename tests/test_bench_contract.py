@@ -1,0 +1,48 @@
+"""bench.py's command-line contract and its roofline table, on the CPU (no
+GPU run: only argument handling and static tables)."""
+import glob
+import os
+import re
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402  (defines tables; main() runs only as a script)
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""   # no JSON line for a run that did not happen
+
+
+def _kernels_in_sources():
+    names = set()
+    for path in glob.glob(os.path.join(ROOT, "paper_2106_00449_amd", "csrc", "*.hip")):
+        names.update(re.findall(r"__global__(?:\s+__launch_bounds__\([^)]*\))?\s+void\s+(k_\w+)\s*\(",
+                                open(path).read()))
+    return names
+
+
+def test_every_workload_names_an_existing_dominant_kernel():
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    m = re.search(r'"--workload", default="rods1000", choices=\[([^\]]*)\]', src)
+    assert m, "workload choices not found"
+    choices = re.findall(r'"(\w+)"', m.group(1))
+    kernels = _kernels_in_sources()
+    assert set(bench.DOMINANT) == set(choices)
+    for w, (family, kernel, nbytes) in bench.DOMINANT.items():
+        assert kernel in kernels, (w, kernel)
+        assert family.startswith("fft_") or family in ("spread", "interp")
+        # the grid term of every dominant pass: 24 bytes per grid point
+        assert nbytes(128 ** 3, 10_000) == 24 * 128 ** 3
+
+
+def test_traffic_figure_belongs_to_the_measured_kernel():
+    # the measured traffic is quoted against the 1,000-rod workload's kernel
+    # and must be within a factor 2 of its algorithmic bytes
+    assert bench.TRAFFIC_BYTES is None or 0.5 < bench.TRAFFIC_BYTES / (24 * 128 ** 3) < 2.0
