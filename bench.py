@@ -95,7 +95,8 @@ def calibrate(g, wl, w, Y0, q0, target=1e-5):
     Vref = ref.mobility_apply("body", Y0, q0, F)
     ref.close()
     chosen = None
-    for tol in [1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7]:
+    # eight rungs per decade (ratio 10^(1/8) = 1.33), 1e-3 down to 1e-7
+    for tol in [float(f"{1e-3 * 10 ** (-k / 8):.2g}") for k in range(33)]:
         s = g.Suspension(**wl.library_kwargs(w, precision="fp32", gmres_tol=tol, gmres_maxit=500))
         V = s.mobility_apply("body", Y0, q0, F, allow_notconv=True)
         s.close()
