@@ -61,14 +61,17 @@ DOMINANT = {
 BYTES_PER_POINT = 12
 BYTES_PER_BLOB = 56
 
-# HBM traffic of the 1,000-rod workload's dominant kernel per launch from two
+# HBM traffic of each workload's dominant kernel per launch from two
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per
 # dispatch, averaged over the dispatches of the instantiation the timed
 # region runs), each scaled by the 256 MiB copy that --copy-calibration adds
-# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0): 24,239,605 B read + 25,165,824 B
-# written.  Set back to None whenever that kernel changes, until the
-# counters are taken again.  Other workloads report no traffic.
-TRAFFIC_BYTES = 49405429
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Read + written bytes:
+#   rods1000   k_plane_inv       24,239,605 + 25,165,824
+#   mixed4096  k_c2r_axis2      201,405,760 + 201,326,608
+#   rods32768  k_axis0_project  679,632,001 + 679,477,248
+# A workload's entry goes back to None whenever its kernel changes, until
+# the counters are taken again.
+TRAFFIC_BYTES = {"rods1000": 49405429, "mixed4096": 402732368, "rods32768": 1359109249}
 
 WORKLOAD_TEXT = {
     "rods1000": "rods1000: 1,000 rods x 10 blobs (10,000 blobs), L=128a, grid 128^3, FP32 grid / FP64 bodies "
@@ -476,7 +479,7 @@ def main():
     achieved = alg_bytes / avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
-                "traffic": TRAFFIC_BYTES if args.workload == "rods1000" else None,
+                "traffic": TRAFFIC_BYTES.get(args.workload),
                 "kernel": dom_kernel, "launches": k_launches, "avg_us": avg_s * 1e6,
                 "algorithmic_bytes": alg_bytes}
     # the whole step against the byte model of the method's grid traffic:

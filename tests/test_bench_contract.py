@@ -42,7 +42,13 @@ def test_every_workload_names_an_existing_dominant_kernel():
         assert nbytes(128 ** 3, 10_000) == 24 * 128 ** 3
 
 
-def test_traffic_figure_belongs_to_the_measured_kernel():
-    # the measured traffic is quoted against the 1,000-rod workload's kernel
-    # and must be within a factor 2 of its algorithmic bytes
-    assert bench.TRAFFIC_BYTES is None or 0.5 < bench.TRAFFIC_BYTES / (24 * 128 ** 3) < 2.0
+def test_traffic_figures_belong_to_the_measured_kernels():
+    # each measured traffic figure is quoted against its workload's dominant
+    # kernel and must be within a factor 2 of that kernel's algorithmic bytes
+    grids = {"rods1000": 128, "mixed4096": 256, "rods32768": 384}
+    assert set(bench.TRAFFIC_BYTES) <= set(bench.DOMINANT)
+    for w, t in bench.TRAFFIC_BYTES.items():
+        if t is None:
+            continue
+        alg = bench.DOMINANT[w][2](grids[w] ** 3, 0)
+        assert 0.5 < t / alg < 2.0, (w, t, alg)
