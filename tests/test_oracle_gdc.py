@@ -8,7 +8,7 @@ import numpy as np
 
 import workloads as wl
 from oracle import fcm, gdc, rigid
-from oracle.quaternion import qexp, qmul
+from oracle.quaternion import cross_matrix, qexp, qmul, rotation_matrix
 
 ETA = 1.0 / (6.0 * math.pi)
 
@@ -56,40 +56,177 @@ def test_step_preserves_quaternion_norm_and_is_deterministic():
     assert not np.array_equal(Y1, Y3)
 
 
-def test_fd_divergence_matches_analytic_derivative():
-    # translational part: d/dY_a calV_a = [(K^T K)^+ K^T dv/dY_a]_a with
-    # dv_i/dY_a = dV sum_g u_g Delta_i(x_g) (x_g - r_i)_a / sigma^2 (exact
-    # derivative of the Gaussian, no truncation crossing for this state)
-    cfg = _cfg([wl.boomerang()], [0])
-    Y, q = _state(cfg, 2)
-    ufl = gdc.fluct_field(cfg, 0)
-    b = cfg.susp.bodies
-    p = cfg.susp.fcm
-    r = rigid.blob_positions(b, Y, q)
+# ---------------------------------------------------------------- exact derivatives
+# The divergence of eq. FD perturbs body p by a translation Y_p += theta e_a
+# or a rotation q_p <- exp(theta e_a) q_p (the Lie-algebra coordinate of the
+# midpoint and update moves, reset to 0 at x^n).  Below, the exact theta-
+# derivatives at theta = 0, written from the chain rule on their own:
+#   blob motion  dr_i = e_a (translation) or e_a x (r_i - Y_p) (rotation);
+#   averaging    dv_i = dV sum_g u_g Delta_i(x_g) (x_g - r_i) . dr_i / sigma^2;
+#   rigid map    dK rows [0, -[d(r_i - Y_p) x]];
+#   pseudo-inverse of A = K^T K at constant rank (Golub and Pereyra 1973):
+#     dA^+ = -A^+ dA A^+ + A^+ A^+ dA (I - A A^+) + (I - A A^+) dA A^+ A^+.
+# They pin the oracle's finite differences, including the choice of axis
+# (lab-frame e_a, left multiplication) that nothing else fixes.
+
+
+def _pinv_derivative(A, dA):
+    Ap = np.linalg.pinv(A, rcond=rigid.PINV_RCOND)
+    PN = np.eye(A.shape[0]) - A @ Ap
+    return -Ap @ dA @ Ap + Ap @ Ap @ dA @ PN + PN @ dA @ Ap @ Ap
+
+
+def _stencil_offsets(p, r):
+    """(blob, grid point, weight, x_g - r_i minimum image) over all stencils."""
     bi, gi, w = fcm.blob_stencils(r, p.grid, p.sigma, p.rc)
-    gidx = np.stack(np.unravel_index(gi, p.grid.n), 1) * p.grid.dx
-    dvec = gidx - (r[bi] - p.grid.L * np.floor(r[bi] / p.grid.L))
-    dvec -= p.grid.L * np.round(dvec / p.grid.L)
-    uflat = ufl.reshape(3, -1)[:, gi].T
-    Lp = gdc.body_length(b.shapes[0], 1.0)
-    K = rigid.body_K(r - Y[0])
-    Pinv = np.linalg.pinv(K.T @ K)
-    ana = 0.0
-    for a in range(3):
-        dv = np.zeros((b.M, 3))
-        np.add.at(dv, bi, p.grid.dV * uflat * (w * dvec[:, a] / p.sigma ** 2)[:, None])
-        ana += (Pinv @ K.T @ dv.ravel())[a]
-    fd = 0.0
-    calV = rigid.lsq_velocity(b, Y, r, gdc.averaged(cfg, r, ufl))
-    for a in range(3):
-        Yp = Y.copy()
-        Yp[0, a] += 1e-6 * Lp
-        rp = rigid.blob_positions(b, Yp, q)
-        fd += (rigid.lsq_velocity(b, Yp, rp, gdc.averaged(cfg, rp, ufl))[0, a] - calV[0, a]) / (1e-6 * Lp)
-    assert abs(fd - ana) < 1e-4 * abs(ana) + 1e-6
-    # and the predictor's d_p includes exactly this translational sum
-    cfg_rot_only = gdc.predictor(cfg, Y, q, ufl)[1]
-    assert np.isfinite(cfg_rot_only).all()
+    xg = np.stack(np.unravel_index(gi, p.grid.n), 1) * p.grid.dx
+    d = xg - (r[bi] - p.grid.L * np.floor(r[bi] / p.grid.L))
+    return bi, gi, w, d - p.grid.L * np.round(d / p.grid.L)
+
+
+def _blob_motion(rel, kind, a, axis_frame=None):
+    """dr_i of the body's blobs (rel_i = r_i - Y_p) for a unit translation
+    or rotation along e_a; axis_frame rotates the axis (R(q) e_a is the
+    body-frame reading, used only to show that the pins tell them apart)."""
+    e = np.zeros(3)
+    e[a] = 1.0
+    if kind == "t":
+        return np.tile(e, (rel.shape[0], 1))
+    if axis_frame is not None:
+        e = axis_frame @ e
+    return np.cross(e, rel)
+
+
+def _dcalV(cfg, Y, q, ufl, p, kind, a, axis_frame=None):
+    """Exact d calV_p / d theta for body p's perturbation (kind, a)."""
+    b, P = cfg.susp.bodies, cfg.susp.fcm
+    r = rigid.blob_positions(b, Y, q)
+    o, c = b.offsets[p], b.counts[p]
+    rel = r[o:o + c] - Y[p]
+    dr_b = _blob_motion(rel, kind, a, axis_frame)
+    drel = np.zeros_like(rel) if kind == "t" else dr_b
+    bi, gi, w, d = _stencil_offsets(P, r)
+    on = (bi >= o) & (bi < o + c)
+    uf = ufl.reshape(3, -1)[:, gi[on]].T
+    coef = P.grid.dV * w[on] * (d[on] * dr_b[bi[on] - o]).sum(1) / P.sigma ** 2
+    dv = np.zeros((c, 3))
+    np.add.at(dv, bi[on] - o, uf * coef[:, None])
+    v = gdc.averaged(cfg, r, ufl)[o:o + c].reshape(-1)
+    K = rigid.body_K(rel)
+    dK = np.zeros_like(K)
+    for i in range(c):
+        dK[3 * i:3 * i + 3, 3:] = -cross_matrix(drel[i])
+    A = K.T @ K
+    Ap = np.linalg.pinv(A, rcond=rigid.PINV_RCOND)
+    return _pinv_derivative(A, dK.T @ K + K.T @ dK) @ (K.T @ v) + Ap @ (dK.T @ v + K.T @ dv.reshape(-1))
+
+
+def _cutoff_crossings(P, r0, r1):
+    """Grid points whose distance to a blob crosses the cut-off radius between
+    positions r0 and r1 (each crossing is a jump of the truncated envelope)."""
+    bi, gi, _ = fcm.blob_stencils(r0, P.grid, P.sigma, P.rc + 0.05)
+    xg = np.stack(np.unravel_index(gi, P.grid.n), 1) * P.grid.dx
+
+    def dist(r):
+        d = xg - (r[bi] - P.grid.L * np.floor(r[bi] / P.grid.L))
+        d -= P.grid.L * np.round(d / P.grid.L)
+        return np.sqrt((d * d).sum(1))
+    return int(np.count_nonzero((dist(r0) <= P.rc) != (dist(r1) <= P.rc)))
+
+
+def test_fd_divergence_matches_exact_derivative():
+    # eq. FD term by term: a boomerang and a tetrahedron (full rank) and a
+    # straight rod (K^T K of rank 5: the pseudo-inverse derivative), at
+    # generic positions (a blob on a grid point has lattice points exactly
+    # at the cut-off, where the quotient grows like 1/delta)
+    cfg = _cfg([wl.boomerang(), wl.tetrahedron(), wl.rod(3)], [0, 1, 2], L=16.0, n=16)
+    rng = np.random.default_rng(7)
+    Y = np.array([[3.13, 4.27, 5.31], [10.52, 9.07, 7.71], [5.09, 12.03, 11.41]])
+    q = rng.standard_normal((3, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    ufl = gdc.fluct_field(cfg, 0)
+    b, P = cfg.susp.bodies, cfg.susp.fcm
+    r0 = rigid.blob_positions(b, Y, q)
+    delta = cfg.fd_delta
+    for p in range(b.N):
+        Lp = gdc.body_length(b.shapes[b.body_shape[p]], 1.0)
+        for a in range(3):
+            Yp = Y.copy()
+            Yp[p, a] += delta * Lp
+            e = np.zeros((b.N, 3))
+            e[p, a] = delta
+            assert _cutoff_crossings(P, r0, rigid.blob_positions(b, Yp, q)) == 0
+            assert _cutoff_crossings(P, r0, rigid.blob_positions(b, Y, qmul(qexp(e), q))) == 0
+    _, d = gdc.predictor(cfg, Y, q, ufl)
+    for p in range(b.N):
+        trans = sum(_dcalV(cfg, Y, q, ufl, p, "t", a)[a] for a in range(3))
+        rot = sum(_dcalV(cfg, Y, q, ufl, p, "r", a)[3 + a] for a in range(3))
+        # the forward difference is first order in delta = 1e-6
+        assert abs(d[p] - (trans + rot)) < 1e-4 * abs(trans + rot), (p, d[p], trans, rot)
+        # both halves matter, and the body-frame axis (q exp(delta e)) would
+        # be caught: its rotational sum differs by far more than the bound
+        assert abs(rot) > 0.2 * abs(trans + rot) or abs(trans) > 0.2 * abs(trans + rot)
+        R = rotation_matrix(q[p])
+        rot_body = sum(_dcalV(cfg, Y, q, ufl, p, "r", a, axis_frame=R)[3 + a] for a in range(3))
+        assert abs(rot_body - rot) > 100 * 1e-4 * abs(trans + rot), (p, rot, rot_body)
+
+
+def test_mobility_divergence_matches_exact_derivative():
+    # d_x . N by the chain rule on N = (K^T M^-1 K)^-1 with M = J L^-1 S:
+    # dM = dJ L^-1 S + (dJ L^-1 S)^T (J = dV S^T, L^-1 symmetric),
+    # dN = -N (dK^T M^-1 K + K^T M^-1 dK - K^T M^-1 dM M^-1 K) N; column
+    # (p, a) of dN under body p's perturbation a, summed over all (p, a).
+    cfg = _cfg([wl.tetrahedron(), wl.boomerang()], [0, 1], L=16.0, n=16)
+    b, P = cfg.susp.bodies, cfg.susp.fcm
+    g = P.grid
+    Y = np.array([[5.13, 7.27, 6.31], [9.52, 8.07, 9.71]])
+    q = np.array([[0.9, 0.3, 0.2, 0.1], [0.7, -0.2, 0.5, 0.3]])
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    r = rigid.blob_positions(b, Y, q)
+    M = b.M
+    W = fcm.weight_matrix(r, g, P.sigma, P.rc)
+    U = np.empty((3 * M, 3, g.G))
+    for j in range(3 * M):
+        lam = np.zeros(3 * M)
+        lam[j] = 1.0
+        U[j] = fcm.stokes_solve(fcm.spread(W, lam.reshape(M, 3), g), g, P.eta).reshape(3, -1)
+    Mm = g.dV * np.einsum("ig,jcg->icj", W.toarray(), U).reshape(3 * M, 3 * M)
+    bi, gi, w, d = _stencil_offsets(P, r)
+    K = np.zeros((3 * M, 6 * b.N))
+    for p, sl, rel in rigid.per_body(b, Y, r):
+        K[3 * sl.start:3 * sl.stop, 6 * p:6 * p + 6] = rigid.body_K(rel)
+    Minv = np.linalg.inv(Mm)
+    N = np.linalg.inv(K.T @ Minv @ K)
+
+    def divergence(axis_frames=None):
+        div = np.zeros(6 * b.N)
+        for p, sl, rel in rigid.per_body(b, Y, r):
+            for a in range(6):
+                fr = None if axis_frames is None else axis_frames[p]
+                drb = _blob_motion(rel, "t" if a < 3 else "r", a % 3, fr)
+                dr = np.zeros((M, 3))
+                dr[sl] = drb
+                dJ = np.zeros((M, g.G))
+                np.add.at(dJ, (bi, gi), g.dV * w * (d * dr[bi]).sum(1) / P.sigma ** 2)
+                D = np.einsum("ig,jcg->icj", dJ, U).reshape(3 * M, 3 * M)
+                dK = np.zeros_like(K)
+                if a >= 3:
+                    for k, i in enumerate(range(sl.start, sl.stop)):
+                        dK[3 * i:3 * i + 3, 6 * p + 3:6 * p + 6] = -cross_matrix(drb[k])
+                dB = dK.T @ Minv @ K + K.T @ Minv @ dK - K.T @ Minv @ (D + D.T) @ Minv @ K
+                div += (-N @ dB @ N)[:, 6 * p + a]
+        return div
+
+    exact = divergence()
+    fd = gdc.mobility_divergence(cfg, Y, q, h=1e-4)
+    # central differences: O(h^2) plus cut-off crossings (none at this state)
+    assert np.abs(fd - exact).max() < 1e-5 * np.abs(exact).max(), np.abs(fd - exact).max()
+    # rotational columns carry a resolvable share, and the body-frame axis
+    # reading gives a different divergence
+    rot_idx = np.array([6 * p + a for p in range(b.N) for a in range(3, 6)])
+    assert np.abs(exact[rot_idx]).max() > 0.1 * np.abs(exact).max()
+    body = divergence(axis_frames=rotation_matrix(q))
+    assert np.abs(body - exact).max() > 100 * 1e-5 * np.abs(exact).max()
 
 
 def test_fd_first_order_in_delta():
