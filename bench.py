@@ -296,7 +296,7 @@ def fp64_single(g, wl, w, Y0, q0, tol, stream, steps):
 def rheology_bench(g, wl, tol, stream, steps=100):
     """Effective viscosity under the sinusoidal forcing f0 sin(k y) e_x:
     eta_eff = f0 / (k^2 v_x), v_x the per-step sine amplitude of the fluid
-    x-velocity averaged over the run (Sec. 6.3)."""
+    x-velocity averaged over the run (Sec. 6.4)."""
     import numpy as np
     import torch
     progress("rheology")

@@ -74,7 +74,7 @@ typedef struct {
  *   shear_rate: background flow u(r) = rate (y - L1/2) e_x at each blob, y
  *     measured from the body's wrapped reference point (not Lees-Edwards).
  *   sine_force: f0 of the periodic force density f0 sin(k y) e_x on the
- *     fluid, k = 2 pi / L1 (the rheology forcing of Sec. 6.3); its flow
+ *     fluid, k = 2 pi / L1 (the rheology forcing of Sec. 6.4); its flow
  *     f0/(eta k^2) sin(k y) e_x, averaged at each blob, enters the step-5
  *     slip, and each step reports the sine amplitude v_x of the fluid's
  *     x-velocity (gdc_stats.sine_vx), so that eta_eff = f0 / (k^2 v_x). */
@@ -88,7 +88,8 @@ typedef struct {
 
 /* Suspension and solver parameters (Sec. 2-4, Sec. 6.1).
  *   L[3], n[3]: periodic box and grid; each n_d even, of the form 2^a 3^b,
- *     8 <= n_d <= 512.
+ *     8 <= n_d <= 384 (8, 12, 16, 24, 32, 48, 64, 96,
+ *     128, 192, 256, 384).
  *   a: blob radius; sigma: Gaussian envelope width (0 -> a/sqrt(pi), Sec. 4.2);
  *   trunc: envelope cutoff radius (0 -> 3a, Sec. 6.1), below min(L)/2.
  *   eta, kT, dt: viscosity, thermal energy, time step.
@@ -138,6 +139,10 @@ typedef struct {
   double nu_mean;            /* mean nu over the call's steps (1 for EM) */
   double nu_std;             /* standard deviation of nu over the call's steps */
   double nu_min, nu_max;     /* extremes of nu over the call's steps */
+  int status;                /* this handle's own outcome of the steps completed
+                                in the call: GDC_OK, GDC_ENOTCONV (a solve missed
+                                the tolerance) or GDC_ENUMERIC (non-finite state,
+                                pair-force cell overflow) */
 } gdc_stats;
 
 typedef struct gdc_handle gdc_handle;
@@ -200,14 +205,20 @@ int gdc_get_state(gdc_handle* h, double* Y, double* q, int memspace);
  *     decrements it.
  *   until: GDC_UNTIL_ALL returns when every entry of steps is 0;
  *     GDC_UNTIL_ANY as soon as one handle that had steps left at entry has
- *     none.  max_ms > 0 also returns once that much wall time has passed
+ *     none.  A handle whose state turns non-finite (or whose pair-force cell
+ *     list overflows) is not advanced further in the call and counts as
+ *     done for both conditions; its status is GDC_ENUMERIC.  max_ms > 0 also returns once that much wall time has passed
  *     (0: no limit).  A handle left in the middle of a step keeps its place:
  *     its queued kernels continue on the device, and the next
  *     gdc_batch_step call resumes it; every other call on that handle except
  *     gdc_free returns GDC_EINVAL until the step is finished.
- *   st[nh] (optional): per-handle statistics of this call.
+ *   st[nh] (optional): per-handle statistics of this call; st[i].status is
+ *     handle i's own outcome, so a failed solve is attributed to the
+ *     suspension that produced it.  Each call counts only the steps it
+ *     completes.
  * Errors: GDC_EINVAL; GDC_ENOTCONV / GDC_ENUMERIC (as gdc_step, for the
- * first handle that hit one; the steps are still taken); GDC_EDEVICE. */
+ * first handle that hit one; the steps are still taken; st[i].status names
+ * every handle's); GDC_EDEVICE. */
 int gdc_batch_step(gdc_handle* const* hs, int nh, int* steps, int until, double max_ms, gdc_stats* st);
 
 /* Completion times of the handle's steps, in milliseconds of the host's

@@ -42,7 +42,7 @@ class Forces:
       measured from the body's wrapped centre so the flow is continuous
       across each body (not Lees-Edwards);
     sine_force: f0 of the periodic force density f0 sin(k y) e_x on the
-      fluid, k = 2 pi / L_y (Sec. 6.3, rheology)."""
+      fluid, k = 2 pi / L_y (Sec. 6.4, rheology)."""
     steric_k: float = 0.0
     steric_cutoff: float = 0.0
     const_force: np.ndarray = field(default_factory=lambda: np.zeros(6))

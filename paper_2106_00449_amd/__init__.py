@@ -67,7 +67,7 @@ class _Stats(ctypes.Structure):
                 ("nu_nonpositive", ctypes.c_int), ("ms", ctypes.c_double),
                 ("sine_vx", ctypes.c_double), ("gmres_iterations_mean", ctypes.c_double),
                 ("nu_mean", ctypes.c_double), ("nu_std", ctypes.c_double), ("nu_min", ctypes.c_double),
-                ("nu_max", ctypes.c_double)]
+                ("nu_max", ctypes.c_double), ("status", ctypes.c_int)]
 
 
 def _load():
@@ -217,20 +217,23 @@ def batch_step(susps, steps, until="all", max_ms=0.0):
     """Advance resident suspensions together (gdc_batch_step).
 
     steps: steps still to take per suspension.  Returns (steps left,
-    per-suspension statistics, return code); GDC_ENOTCONV is returned, not
-    raised, other errors raise."""
+    per-suspension statistics, return code).  A suspension's own outcome is
+    its statistics' "status" (GDC_OK, GDC_ENOTCONV or GDC_ENUMERIC), so the
+    step errors of one suspension are returned, not raised; argument and
+    device errors raise."""
     nh = len(susps)
     hs = (ctypes.c_void_p * max(nh, 1))(*[s._h for s in susps])
     st_in = (ctypes.c_int * max(nh, 1))(*[int(x) for x in steps])
     stats = (_Stats * max(nh, 1))()
     rc = lib.gdc_batch_step(hs, nh, st_in, {"all": GDC_UNTIL_ALL, "any": GDC_UNTIL_ANY}[until],
                             float(max_ms), stats)
-    if rc not in (GDC_OK, GDC_ENOTCONV):
+    if rc not in (GDC_OK, GDC_ENOTCONV, GDC_ENUMERIC):
         _check(rc)
     out = [{"steps_done": x.steps_done, "gmres_iterations": x.gmres_iterations,
             "gmres_relres": x.gmres_relres, "nu": x.nu, "nu_nonpositive": x.nu_nonpositive,
             "ms": x.ms, "sine_vx": x.sine_vx, "gmres_iterations_mean": x.gmres_iterations_mean,
-            "nu_mean": x.nu_mean, "nu_std": x.nu_std, "nu_min": x.nu_min, "nu_max": x.nu_max}
+            "nu_mean": x.nu_mean, "nu_std": x.nu_std, "nu_min": x.nu_min, "nu_max": x.nu_max,
+            "status": x.status}
            for x in stats[:nh]]
     return [int(x) for x in st_in[:nh]], out, rc
 

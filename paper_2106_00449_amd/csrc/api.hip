@@ -411,7 +411,7 @@ int validate(const gdc_config* c) {
   for (int d = 0; d < 3; ++d) {
     if (!(c->L[d] > 0.0)) return bad("L must be positive");
     if (c->n[d] % 2 != 0 || !fft_size_supported(c->n[d]))
-      return bad("grid size must be even, 2^a 3^b and in [8, 512]");
+      return bad("grid size must be even, 2^a 3^b and in [8, 384] (every such size the transforms take is parity-tested)");
   }
   if (!(c->a > 0.0) || c->sigma < 0.0 || c->trunc < 0.0) return bad("a must be > 0, sigma and trunc >= 0");
   if (!(c->eta > 0.0) || c->kT < 0.0 || !(c->dt > 0.0)) return bad("eta, dt must be > 0 and kT >= 0");
@@ -858,6 +858,7 @@ void fill_stats(const gdc_handle* h, gdc_stats* st) {
   st->nu_std = h->done_n ? std::sqrt(std::max(0.0, h->nu_acc2 / h->done_n - st->nu_mean * st->nu_mean)) : 0.0;
   st->nu_min = h->nu_lo;
   st->nu_max = h->nu_hi;
+  st->status = step_errors(h);
 }
 
 int require_idle(const gdc_handle* h) {
@@ -880,8 +881,7 @@ int copy_out(gdc_handle* h, double* dst, const double* src, size_t count, int me
   return GDC_OK;
 }
 
-int check_quaternions(const gdc_handle* h, const double* Y, const double* q, int memspace) {
-  if (memspace != GDC_HOST) return GDC_OK;
+int check_quaternions(const gdc_handle* h, const double* Y, const double* q) {
   for (long long k = 0; k < 3LL * h->N; ++k)
     if (!std::isfinite(Y[k])) {
       set_error("non-finite position of body " + std::to_string(k / 3));
@@ -898,6 +898,10 @@ int check_quaternions(const gdc_handle* h, const double* Y, const double* q, int
   return GDC_OK;
 }
 
+// Host arrays are checked on the host before anything is copied.  Device
+// arrays are copied into the midpoint buffers (free between steps), checked
+// there by a kernel whose flags the host reads back, and only then become
+// the state: a rejected state leaves the handle's state as it was.
 int load_state(gdc_handle* h, const double* Y, const double* q, int memspace) {
   if (!Y || !q) {
     set_error("Y and q are required");
@@ -907,9 +911,28 @@ int load_state(gdc_handle* h, const double* Y, const double* q, int memspace) {
     set_error("memspace must be GDC_HOST or GDC_DEVICE");
     return GDC_EINVAL;
   }
-  GDC_TRY(check_quaternions(h, Y, q, memspace));
-  GDC_TRY(copy_in(h, h->Y, Y, 3 * (size_t)h->N, memspace));
-  return copy_in(h, h->q, q, 4 * (size_t)h->N, memspace);
+  if (memspace == GDC_HOST) {
+    GDC_TRY(check_quaternions(h, Y, q));
+    GDC_TRY(copy_in(h, h->Y, Y, 3 * (size_t)h->N, memspace));
+    return copy_in(h, h->q, q, 4 * (size_t)h->N, memspace);
+  }
+  GDC_TRY(copy_in(h, h->Ym, Y, 3 * (size_t)h->N, memspace));
+  GDC_TRY(copy_in(h, h->qm, q, 4 * (size_t)h->N, memspace));
+  GDC_TRY(fill_zero(h->flags, 16, h->stream));
+  GDC_TRY(check_state(h->Ym, h->qm, h->N, 1e-6, h->flags + 2, h->stream));
+  int* fl = reinterpret_cast<int*>(h->hhost + 4 * HCOLS + 16);
+  GDC_HIP(hipMemcpyAsync(fl, h->flags + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  GDC_HIP(hipStreamSynchronize(h->stream));
+  if (fl[0]) {
+    set_error("non-finite position in the device array Y");
+    return GDC_EINVAL;
+  }
+  if (fl[1]) {
+    set_error("a quaternion of the device array q is not of unit norm");
+    return GDC_EINVAL;
+  }
+  GDC_TRY(copy_in(h, h->Y, h->Ym, 3 * (size_t)h->N, GDC_DEVICE));
+  return copy_in(h, h->q, h->qm, 4 * (size_t)h->N, GDC_DEVICE);
 }
 
 int finish(gdc_handle* h) {
@@ -1440,7 +1463,9 @@ int gdc_batch_step(gdc_handle* const* hs, int nh, int* steps, int until, double 
   int prev_dev = -1;
   if (hipGetDevice(&prev_dev) != hipSuccess) prev_dev = -1;
   const double t0 = now_ms();
-  std::vector<int> watched(nh, 0), done_here(nh, 0);
+  // failed: the handle's state went non-finite (or its pair-force cell list
+  // overflowed) in this call; it is not advanced further
+  std::vector<int> watched(nh, 0), done_here(nh, 0), failed(nh, 0);
   std::vector<double> t_last(nh, 0.0);
   bool any_watched = false;
   for (int i = 0; i < nh; ++i) {
@@ -1455,7 +1480,7 @@ int gdc_batch_step(gdc_handle* const* hs, int nh, int* steps, int until, double 
     bool progressed = false;
     for (int i = 0; i < nh && rc == GDC_OK; ++i) {
       gdc_handle* h = hs[i];
-      if (steps[i] == 0) continue;
+      if (steps[i] == 0 || failed[i]) continue;
       if (h->device != cur_dev) {
         if (hipSetDevice(h->device) != hipSuccess) {
           set_error("hipSetDevice failed");
@@ -1479,37 +1504,48 @@ int gdc_batch_step(gdc_handle* const* hs, int nh, int* steps, int until, double 
           --steps[i];
           ++done_here[i];
           t_last[i] = h->step_log.back() - t0;
+          if (h->n_nonfinite || h->n_overflow) {
+            failed[i] = 1;
+            break;
+          }
         }
       }
     }
     if (rc != GDC_OK) break;
     bool all_zero = true, any_hit = false;
     for (int i = 0; i < nh; ++i) {
-      all_zero = all_zero && steps[i] == 0;
-      any_hit = any_hit || (watched[i] && steps[i] == 0);
+      all_zero = all_zero && (steps[i] == 0 || failed[i]);
+      any_hit = any_hit || (watched[i] && (steps[i] == 0 || failed[i]));
     }
     if (all_zero || (until == GDC_UNTIL_ANY && any_hit)) break;
     if (max_ms > 0.0 && now_ms() - t0 >= max_ms) break;
     if (!progressed) std::this_thread::yield();
   }
   if (prev_dev >= 0) (void)hipSetDevice(prev_dev);
+  // every handle's own outcome first; the message names the first failing
+  // handle (or keeps the call's own error)
+  const std::string call_error = rc != GDC_OK ? gdc_last_error() : std::string();
   int first_err = GDC_OK;
+  std::string first_msg;
   for (int i = 0; i < nh; ++i) {
     gdc_handle* h = hs[i];
+    const int e = step_errors(h);
+    if (e != GDC_OK && first_err == GDC_OK) {
+      first_err = e;
+      first_msg = "handle " + std::to_string(i) + ": " + gdc_last_error();
+    }
     if (st) {
       st[i].steps_done = done_here[i];
       fill_stats(h, &st[i]);
       st[i].ms = t_last[i];
     }
-    if (rc == GDC_OK && first_err == GDC_OK) {
-      const int e = step_errors(h);
-      if (e != GDC_OK) {
-        set_error("handle " + std::to_string(i) + ": " + gdc_last_error());
-        first_err = e;
-      }
-    }
   }
-  return rc != GDC_OK ? rc : first_err;
+  if (rc != GDC_OK) {
+    set_error(call_error);
+    return rc;
+  }
+  set_error(first_msg);
+  return first_err;
 }
 
 int gdc_step_log(gdc_handle* h, double* t_ms, int cap, int* count) {

@@ -677,7 +677,26 @@ __global__ void k_check_finite(const double* __restrict__ x, long long n, int* _
   if (bad) atomicMax(flag, 1);
 }
 
+// A caller's state on the device: flag[0] = 1 if some Y is not finite,
+// flag[1] = 1 if some |q| differs from 1 by more than qtol (or is not finite).
+__global__ void k_check_state(const double* __restrict__ Y, const double* __restrict__ q, int N, double qtol,
+                              int* __restrict__ flag) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const double* y = Y + 3LL * p;
+  if (!(isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]))) atomicMax(flag, 1);
+  const double* qp = q + 4LL * p;
+  const double nrm = sqrt(qp[0] * qp[0] + qp[1] * qp[1] + qp[2] * qp[2] + qp[3] * qp[3]);
+  if (!(fabs(nrm - 1.0) <= qtol)) atomicMax(flag + 1, 1);
+}
+
 }  // namespace
+
+int check_state(const double* Y, const double* q, int N, double qtol, int* flag, hipStream_t s) {
+  if (N <= 0) return GDC_OK;
+  hipLaunchKernelGGL(k_check_state, dim3((N + 255) / 256), dim3(256), 0, s, Y, q, N, qtol, flag);
+  return check_launch("k_check_state");
+}
 
 int blob_positions(const BodyTables& b, const double* Y, const double* q, double* r, hipStream_t s) {
   if (b.M == 0) return GDC_OK;

@@ -787,7 +787,7 @@ __global__ __launch_bounds__(NTH) void k_axis0_plane(Cx<R>* __restrict__ Z, cons
 
 // ------------------------------------------------------------ dispatch
 
-#define GDC_FFT_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+#define GDC_FFT_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384)
 
 // Every pass takes its workgroup size (threads) at run time from the grid's
 // FftShape; the instantiated sizes are 256 and 512 (and 1024 for the plane

@@ -327,6 +327,10 @@ inline size_t cell_count_bytes(const int nc[3]) {
 int body_forces(const BodyTables& b, const double* Y, const double* r, const double* fblob,
                 const double* cforce, double* F, hipStream_t s);
 int check_finite(const double* x, long long n, int* flag, hipStream_t s);
+// Sets flag[0] if a position of Y (N x 3) is not finite and flag[1] if a
+// quaternion of q (N x 4) is off unit norm by more than qtol (flags zeroed
+// by the caller).
+int check_state(const double* Y, const double* q, int N, double qtol, int* flag, hipStream_t s);
 
 // Krylov vector kernels (solver.hip).
 constexpr int DOT_MAX_BLOCKS = 512;

@@ -13,10 +13,14 @@ else is in the mix: its kernels, their order and its noise are its own.
 
 Reported per request: admission, finish and step completion times; per-step
 latency is the time between consecutive step completions of the same
-suspension (the first from its admission).
+suspension (the first from its admission).  Step errors are the
+suspension's own (the library reports an outcome per handle): a suspension
+whose state became non-finite (or whose pair-force cell list overflowed) is
+stopped and reported at once without disturbing the others; one whose
+solve missed the tolerance runs to the end and is reported as failed.
 
-The executor is pluggable (footprint / open / step / close) so that the
-admission logic can be exercised without a GPU.
+The executor is pluggable (footprint / open / step / close / discard) so
+that the admission logic can be exercised without a GPU.
 """
 
 import collections
@@ -24,6 +28,9 @@ import time
 from dataclasses import dataclass, field
 
 import numpy as np
+
+# per-suspension outcomes of a batched step (include/gdc.h)
+GDC_OK, GDC_ENOTCONV, GDC_ENUMERIC = 0, -3, -4
 
 
 @dataclass
@@ -73,8 +80,9 @@ class LibraryExecutor:
         return s
 
     def step(self, handles, steps, until, max_ms):
-        left, _, rc = self.g.batch_step(handles, steps, until=until, max_ms=max_ms)
-        return left, rc
+        """Returns (steps left, each handle's outcome for this call)."""
+        left, stats, _ = self.g.batch_step(handles, steps, until=until, max_ms=max_ms)
+        return left, [x["status"] for x in stats]
 
     def step_log(self, h):
         return h.step_log()
@@ -85,6 +93,11 @@ class LibraryExecutor:
         h.close()
         return Y, q, log
 
+    def discard(self, h):
+        """Release a failed suspension (steps may still be queued; freeing
+        waits for them)."""
+        h.close()
+
 
 @dataclass
 class _Active:
@@ -92,6 +105,7 @@ class _Active:
     handle: object
     fp: int
     left: int
+    notconv: int = 0      # calls in which one of its solves missed the tolerance
     times: list = field(default_factory=list)
 
 
@@ -162,14 +176,26 @@ class Server:
             max_ms = 0.0
             if pending and not queue:
                 max_ms = max((pending[0].arrival - now()) * 1e3, 1e-3)
-            left, rc = self.ex.step([a.handle for a in active], [a.left for a in active], "any", max_ms)
+            left, status = self.ex.step([a.handle for a in active], [a.left for a in active], "any", max_ms)
             still = []
-            for a, lft in zip(active, left):
+            for a, lft, code in zip(active, left, status):
                 a.left = lft
+                res = results[a.req.rid]
+                if code not in (GDC_OK, GDC_ENOTCONV):
+                    # this suspension's state is unusable: stop it now
+                    res.error = f"step failed with code {code} after {a.req.n_steps - lft} steps"
+                    res.finished = now()
+                    try:
+                        self.ex.discard(a.handle)
+                    except Exception as e:   # noqa: BLE001
+                        res.error += f"; release failed: {e}"
+                    used -= a.fp
+                    continue
+                if code == GDC_ENOTCONV:
+                    a.notconv += 1
                 if lft > 0:
                     still.append(a)
                     continue
-                res = results[a.req.rid]
                 try:
                     Y, q, log = self.ex.close(a.handle)
                     res.Y, res.q = Y, q
@@ -178,8 +204,8 @@ class Server:
                 except Exception as e:   # noqa: BLE001
                     res.error = f"readback failed: {e}"
                     res.finished = now()
-                if rc != 0 and not res.error:
-                    res.error = f"step return code {rc}"
+                if a.notconv and not res.error:
+                    res.error = f"GMRES missed the tolerance in {a.notconv} batched calls"
                 used -= a.fp
             active = still
         return results

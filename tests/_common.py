@@ -30,23 +30,52 @@ def gpu_available():
         return False
 
 
-def fd_nu_roundoff_bound(o, info, divergence="fd", safety=16.0):
-    """Bound on the rounding error of the oracle's drift factor nu.
+def fd_roundoff(o, Y, q, ufl, divergence="fd", step=0, safety=8.0):
+    """Rounding of the oracle's FP64 divergence terms d_p and of nu.
 
-    The oracle forms each forward difference calV(x + delta e) - calV(x) in FP64
-    with delta = 1e-6, so every quotient carries about
-    2 eps sqrt(n) |calV| / delta_k of rounding (n = stencil points summed per
-    blob average, delta_k = delta L_p for translations and delta for
-    rotations); nu sums 6 such quotients per body, times dt/2.  RFD weights
-    each quotient by |W~| (<~ 3)."""
-    calV = np.asarray(info["calV"])
-    b = o.susp.bodies
-    grid = o.susp.fcm.grid
-    npts = (4.0 / 3.0) * np.pi * (o.susp.fcm.rc ** 3) / grid.dV
-    eps = np.finfo(np.float64).eps
-    tot = 0.0
-    for p in range(b.N):
-        Lp = gdc.body_length(b.shapes[b.body_shape[p]], o.susp.a)
-        per = 2.0 * eps * np.sqrt(npts) * np.abs(calV[p]).max()
-        tot += per * (3.0 / (o.fd_delta * Lp) + 3.0 / o.fd_delta) * (3.0 if divergence == "rfd" else 1.0)
-    return safety * 0.5 * o.dt * tot
+    The oracle forms each forward difference calV(x + delta e) - calV(x) from
+    two separately rounded averages, so with delta = 1e-6 each quotient
+    carries rounding of order eps |v| sqrt(S) / delta (S stencil points).
+    Its size is measured rather than modelled: translating every body by a
+    whole grid cell and rolling the field with it leaves d_p unchanged in
+    exact arithmetic but changes every rounded operand, so the spread of d_p
+    over three such translations is the oracle's own rounding.  Returns
+    (per-body bound on |d_gpu - d_oracle|, bound on |nu_gpu - nu_oracle|),
+    each `safety` times the largest change seen."""
+    from oracle import gdc
+    Y = np.asarray(Y, dtype=np.float64).reshape(-1, 3)
+    calV, d = gdc.predictor(o, Y, q, ufl)
+    if divergence == "rfd":
+        d = gdc.rfd_divergence(o, Y, q, ufl, calV, step)
+    dx = o.susp.fcm.grid.dx
+    dd, dnu = np.zeros_like(d), 0.0
+    for sh in [(1, 0, 0), (0, 1, 0), (0, 0, 1)]:
+        Y1 = Y + np.asarray(sh) * dx
+        u1 = np.roll(ufl, sh, axis=(1, 2, 3))
+        c1, d1 = gdc.predictor(o, Y1, q, u1)
+        if divergence == "rfd":
+            d1 = gdc.rfd_divergence(o, Y1, q, u1, c1, step)
+        dd = np.maximum(dd, np.abs(d1 - d))
+        dnu = max(dnu, 0.5 * o.dt * abs(float(np.sum(d1 - d))))
+    floor = 1e-14 * max(1.0, float(np.abs(d).max()))
+    return safety * np.maximum(dd, floor), safety * max(dnu, 0.5 * o.dt * floor)
+
+
+def max_rel(a, b):
+    """Element-wise error relative to the reference's scale: max |a - b| / max |b|."""
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    m = np.abs(b).max() if b.size else 0.0
+    return float(np.abs(a - b).max() / (m if m > 0 else 1.0)) if b.size else 0.0
+
+
+def check_close(what, got, ref, tol, elem_tol=None):
+    """Relative L2 over the whole vector within tol, and every element within
+    elem_tol (default 4 tol) of the reference's largest magnitude, so that a
+    few bad entries cannot hide in a long vector.  Prints both figures."""
+    e2, em = rel_l2(got, ref), max_rel(got, ref)
+    et = 4.0 * tol if elem_tol is None else elem_tol
+    print(f"[err] {what}: rel L2 {e2:.3e} (tol {tol:.1e}), element max {em:.3e} (tol {et:.1e})", flush=True)
+    assert e2 < tol, (what, e2, tol)
+    assert em < et, (what, em, et)
+    return e2, em

@@ -1,8 +1,12 @@
 """Parity of the HIP library (through the C ABI) with the FP64 oracle.
 
-Tolerances (relative L2 over the whole output): deterministic mobility
-<= 1e-12 in FP64 and <= 1e-5 in FP32; one-step increments <= 1e-10 (FP64) and
-<= 1e-5 (FP32); noise normals bit-identical.
+Tolerances: relative L2 over the whole output, and every element within
+4x that of the output's largest magnitude (check_close).  Deterministic
+mobility <= 1e-12 in FP64 (GMRES to 1e-13 for the body mode) and <= 1e-5 in
+FP32; the least-squares velocity calV <= 1e-12 (FP64) and 1e-5 (FP32);
+one-step increments <= 1e-10 (FP64) and <= 1e-5 (FP32); the FP64 divergence
+terms d_p and nu within 8x the oracle's own rounding of its forward
+differences (fd_roundoff); noise normals bit-identical.
 """
 import math
 import sys
@@ -13,7 +17,7 @@ import pytest
 import workloads as wl
 from oracle import fcm, gdc, noise, philox, rigid
 from oracle.quaternion import qexp, qmul
-from tests._common import fd_nu_roundoff_bound, oracle_config, rel_l2
+from tests._common import check_close, fd_roundoff, oracle_config, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -68,7 +72,7 @@ def test_fluct_velocity_field(lib, prec, n, L):
         u = s.fluct_velocity(step)
         ref = noise.fourier_field(fcm.Grid(w.L, w.n), w.kT, w.eta, w.dt, w.noise_seed, step)
         tol = 1e-12 if prec == "fp64" else 1e-5
-        assert rel_l2(u, ref) < tol
+        check_close(f"u_brev {prec} {n} step {step}", u, ref, tol)
 
 
 # ------------------------------------------------------------------ mobility
@@ -86,6 +90,9 @@ CASES = [
     # one 8x8x8 tile holding 80 blobs: the spreading hit loop takes two
     # rounds of 64 and the tile sort ranks more records than a wave
     ("dense8", 8, 12.0, [wl.rod(5)]),
+    # 96^3: the three-pass plane transforms at their largest radix-3 size
+    # (FP32) and the five-pass transforms (FP64)
+    ("rods96", 96, 96.0, [wl.rod(10)]),
 ]
 
 
@@ -93,7 +100,7 @@ CASES = [
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_blob_mobility(lib, prec, case):
     name, n, L, shapes = case
-    nb = {"small8": 3, "dense8": 16}.get(name, 12)
+    nb = {"small8": 3, "dense8": 16, "rods96": 60}.get(name, 12)
     w = wl.small_case(name, n_bodies=nb, n=n, L=L, shapes=shapes, precision=prec, seed=3)
     Y, q, lam, _ = _rand_blobs(w, 1)
     _say("blob", name, prec, w.M)
@@ -103,7 +110,7 @@ def test_blob_mobility(lib, prec, case):
     r = rigid.blob_positions(o.susp.bodies, Y, q)
     ref = fcm.mobility_apply(r, lam, o.susp.fcm)
     tol = 1e-12 if prec == "fp64" else 1e-5
-    assert rel_l2(v, ref) < tol
+    check_close(f"blob {name} {prec}", v, ref, tol)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -118,8 +125,8 @@ def test_body_mobility(lib, prec, case):
     o = oracle_config(w)
     r = rigid.blob_positions(o.susp.bodies, Y, q)
     _, Vref, _ = rigid.solve_saddle(o.susp, Y, r, np.zeros((w.M, 3)), F, tol=1e-14)
-    tol = 1e-11 if prec == "fp64" else 1e-5
-    assert rel_l2(V, Vref) < tol
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    check_close(f"body {name} {prec}", V, Vref, tol)
 
 
 # ------------------------------------------------------------------ gDC pieces
@@ -137,11 +144,17 @@ def test_predictor(lib, prec):
     ufl = gdc.fluct_field(o, 4)
     cref, dref = gdc.predictor(o, Y, q, ufl)
     if prec == "fp64":
-        assert rel_l2(calV, cref) < 1e-11
-        assert rel_l2(d, dref) < 1e-7
+        check_close("predictor calV fp64", calV, cref, 1e-12)
+        # d_p: the oracle's forward differences carry their own rounding
+        # (fd_roundoff); the library forms the differences from weight
+        # differences, far more accurately
+        bound, _ = fd_roundoff(o, Y, q, ufl)
+        gap = np.abs(d - dref)
+        print(f"[err] predictor d fp64: max |gap| / bound {np.max(gap / bound):.3f}", flush=True)
+        assert np.all(gap <= bound), (gap, bound)
     else:
-        assert rel_l2(calV, cref) < 1e-5
-        assert rel_l2(d, dref) < 1e-4
+        check_close("predictor calV fp32", calV, cref, 1e-5)
+        check_close("predictor d fp32", d, dref, 1e-5)
 
 
 STEP_CASES = [
@@ -182,23 +195,28 @@ def test_one_step_increment(lib, prec, case, scheme, div):
         dx_gpu = np.concatenate([(Y - Y0).ravel(), (q - q0).ravel()])
         dx_ref = np.concatenate([(Yr - Y0).ravel(), (qr - q0).ravel()])
         if prec == "fp32":
-            assert rel_l2(dx_gpu, dx_ref) < 1e-5, (step, st, info.get("nu"))
+            check_close(f"step {name} {scheme}-{div} fp32 #{step}", dx_gpu, dx_ref, 1e-5)
             if scheme == "gdc":
                 assert abs(st["nu"] - info["nu"]) < 1e-5 * max(1.0, abs(info["nu"]))
         else:
             # nu: the oracle's forward differences at delta = 1e-6 carry FP64
-            # rounding of order eps |calV| / delta; the bound is derived in
-            # fd_nu_roundoff_bound.  The rest of the step is checked with the
-            # library's nu substituted into the oracle's update, to 1e-10.
+            # rounding, measured by fd_roundoff.  The rest of the step is
+            # checked with the library's nu substituted into the oracle's
+            # update, to 1e-10, and the whole increment to 1e-10 plus the
+            # relative nu gap.
             nu_g = st["nu"] if scheme == "gdc" else 1.0
             if scheme == "gdc":
-                assert abs(nu_g - info["nu"]) <= fd_nu_roundoff_bound(o, info, div), (nu_g, info["nu"])
+                _, nu_bound = fd_roundoff(o, Y0, q0, gdc.fluct_field(o, step), div, step)
+                print(f"[err] nu fp64 {name} {div} #{step}: gap {abs(nu_g - info['nu']):.3e} "
+                      f"bound {nu_bound:.3e}", flush=True)
+                assert abs(nu_g - info["nu"]) <= nu_bound, (nu_g, info["nu"], nu_bound)
             V = info["V"]
             Ya = Y0 + nu_g * w.dt * V[:, :3]
             qa = qmul(qexp(nu_g * w.dt * V[:, 3:]), q0)
             dx_alt = np.concatenate([(Ya - Y0).ravel(), (qa - q0).ravel()])
-            assert rel_l2(dx_gpu, dx_alt) < 1e-10, (step, st, info.get("nu"))
-            assert rel_l2(dx_gpu, dx_ref) < 1e-10 + abs(nu_g - info.get("nu", 1.0)) / abs(info.get("nu", 1.0))
+            check_close(f"step {name} {scheme}-{div} fp64 #{step} (library nu)", dx_gpu, dx_alt, 1e-10)
+            nu_rel = abs(nu_g - info.get("nu", 1.0)) / abs(info.get("nu", 1.0))
+            check_close(f"step {name} {scheme}-{div} fp64 #{step}", dx_gpu, dx_ref, 1e-10 + nu_rel)
         assert s.step_counter == step + 1
 
 
@@ -213,7 +231,7 @@ def test_zero_temperature_step_is_deterministic(lib):
     assert st["nu"] == 1.0
     o = oracle_config(w)
     Yr, qr, _ = gdc.gdc_step(o, Y0, q0, 0, tol=1e-13)
-    assert rel_l2(Y - Y0, Yr - Y0) < 1e-10
+    check_close("kT0 step fp64", Y - Y0, Yr - Y0, 1e-10)
     assert np.abs(np.linalg.norm(q, axis=1) - 1).max() < 1e-14
 
 
@@ -258,5 +276,5 @@ def test_sine_forcing_step(lib, prec, kT):
     dx = np.concatenate([(Y - Y0).ravel(), (q - q0).ravel()])
     dr = np.concatenate([(Yr - Y0).ravel(), (qr - q0).ravel()])
     tol = 1e-10 if prec == "fp64" else 1e-5
-    assert rel_l2(dx, dr) < tol
+    check_close(f"sine step {prec} kT {kT}", dx, dr, tol)
     assert abs(st["sine_vx"] - info["sine_vx"]) < tol * abs(info["sine_vx"])

@@ -37,29 +37,41 @@ class SimExecutor:
         return h
 
     def step(self, handles, steps, until, max_ms):
+        """Like the library: each handle's outcome counts only the steps
+        completed in this call; kwargs["fail_at"] = (step, code) makes that
+        step of the suspension report the code."""
         assert until == "any"
         self.calls.append(len(handles))
         left = list(steps)
+        status = [0] * len(handles)
         deadline = self.clock() + max_ms / 1e3 if max_ms > 0 else float("inf")
         while True:
             i = min(range(len(handles)), key=lambda k: handles[k]["next"] if left[k] > 0 else float("inf"))
             t_next = handles[i]["next"]
             if t_next > deadline:
                 self.clock.t = deadline
-                return left, 0
+                return left, status
             self.clock.t = t_next
             h = handles[i]
             h["done"] += 1
             h["log"].append(t_next * 1e3)
             left[i] -= 1
             h["next"] = t_next + h["req"].kwargs["step_s"]
+            fail = h["req"].kwargs.get("fail_at")
+            if fail and fail[0] == h["done"]:
+                status[i] = fail[1]
+                if fail[1] == -4:     # a failed handle counts as done
+                    return left, status
             if left[i] == 0:
-                return left, 0
+                return left, status
 
     def close(self, h):
         self.live.discard(id(h))
         r = h["req"]
         return r.Y0 + h["done"], r.q0.copy(), h["log"]
+
+    def discard(self, h):
+        self.live.discard(id(h))
 
 
 def _req(rid, arrival, n_steps, step_s, nbytes):
@@ -123,3 +135,23 @@ def test_summary_figures():
     assert s["completed"] == 4 and s["rejected"] == 0
     assert abs(s["step_latency_p50_ms"] - 1.0) < 1e-9
     assert abs(s["blob_steps_per_s"] - 4 * 20 * 4 / 0.004) < 1e-6
+
+
+def test_step_errors_are_attributed_to_their_own_suspension():
+    # request 1's third step goes non-finite while request 0 finishes and
+    # request 2 misses a solve tolerance: 1 is stopped at once and its
+    # memory released, 0 completes untouched, 2 runs to its end and is
+    # reported; requests admitted later (3) still run
+    reqs = [_req(0, 0.0, 4, 0.001, 300), _req(1, 0.0, 50, 0.0015, 300), _req(2, 0.0, 6, 0.002, 300),
+            _req(3, 0.0, 3, 0.001, 300)]
+    reqs[1].kwargs["fail_at"] = (3, -4)
+    reqs[2].kwargs["fail_at"] = (2, -3)
+    srv, ex, res = _serve(reqs, budget=900, slots=3)
+    assert not ex.live
+    assert not res[0].error and np.array_equal(res[0].Y, reqs[0].Y0 + 4)
+    assert "code -4" in res[1].error and res[1].Y is None
+    assert res[1].finished < 0.005     # stopped at its third step, not after 50
+    assert "tolerance" in res[2].error and res[2].Y is not None
+    assert not res[3].error and np.array_equal(res[3].Y, reqs[3].Y0 + 3)
+    s = summarise(res)
+    assert s["completed"] == 2 and s["rejected"] == 2

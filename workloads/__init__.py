@@ -136,7 +136,7 @@ def rods32768(steric=True):
 def rheology500(sine_force=0.002):
     """Sinusoidal-forcing rheology: 500 rods x 10 blobs (8% blob volume
     fraction), L = 64a, grid 64^3, fluid forced by f0 sin(2 pi y / L) e_x;
-    the paper's suspension (Sec. 6.3) is the same forcing on a denser box of
+    the paper's suspension (Sec. 6.4) is the same forcing on a denser box of
     19-blob particles whose geometry the text does not give."""
     return Workload("rheology500", (64.0,) * 3, (64,) * 3, [rod(10)], np.zeros(500, np.int64),
                     dt=0.005, steps=200, noise_seed=6, placement_seed=1006, sine_force=sine_force,
