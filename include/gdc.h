@@ -273,6 +273,17 @@ int gdc_predictor(gdc_handle* h, const double* Y, const double* q, uint64_t step
 int gdc_philox_normals(gdc_handle* h, uint64_t seed, uint32_t c1, uint64_t step,
                        uint32_t c0_begin, int count, double* out);
 
+/* gdc_philox_normals without any device allocation, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same normals, bit for bit, staged
+ * through a fixed device array that the library holds per GPU until the
+ * process ends (2 MiB: count <= 65536 groups of four normals; larger
+ * counts return GDC_EINVAL).  Every call on one GPU shares that array, so
+ * calls that overlap on one GPU (from several threads or handles) race;
+ * the call waits for its copy before returning.  out: host, count x 4. */
+int gdc_philox_normals_noalloc(gdc_handle* h, uint64_t seed, uint32_t c1, uint64_t step, uint32_t c0_begin,
+                               int count, double* out);
+
 /* Measurement helpers (process-wide, not tied to a handle).
  * gdc_probe_kernel(family): from now on, every launch of the named kernel
  * family carries a start and a stop HIP event that the dispatch itself

@@ -87,6 +87,7 @@ def _load():
     L.gdc_fluct_velocity.argtypes = [P, U64, P, I]
     L.gdc_predictor.argtypes = [P, P, P, U64, P, P, I]
     L.gdc_philox_normals.argtypes = [P, U64, U32, U64, U32, I, D]
+    L.gdc_philox_normals_noalloc.argtypes = [P, U64, U32, U64, U32, I, D]
     L.gdc_probe_kernel.argtypes = [ctypes.c_char_p]
     L.gdc_probe_read.argtypes = [D, ctypes.POINTER(ctypes.c_longlong)]
     L.gdc_set_state.argtypes = [P, P, P, I]
@@ -99,7 +100,8 @@ def _load():
     L.gdc_get_launch_config.argtypes = [P, ctypes.POINTER(I), I]
     L.gdc_set_launch_config.argtypes = [P, ctypes.POINTER(I), I]
     for name in ["gdc_init", "gdc_mobility_apply", "gdc_step", "gdc_get_step", "gdc_set_step",
-                 "gdc_fluct_velocity", "gdc_predictor", "gdc_philox_normals", "gdc_probe_kernel",
+                 "gdc_fluct_velocity", "gdc_predictor", "gdc_philox_normals", "gdc_philox_normals_noalloc",
+                 "gdc_probe_kernel",
                  "gdc_probe_read", "gdc_set_state", "gdc_get_state", "gdc_batch_step", "gdc_step_log",
                  "gdc_footprint", "gdc_device_bytes",
                  "gdc_get_launch_config", "gdc_set_launch_config"]:
@@ -385,4 +387,12 @@ class Suspension:
         out = np.empty((count, 4))
         _check(lib.gdc_philox_normals(self._h, int(seed), int(c1), int(step), int(c0_begin), int(count),
                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def philox_normals_noalloc(self, seed, c1, step, c0_begin, count):
+        """philox_normals staged through the library's fixed per-GPU array
+        (no device allocation; count <= 65536)."""
+        out = np.empty((count, 4))
+        _check(lib.gdc_philox_normals_noalloc(self._h, int(seed), int(c1), int(step), int(c0_begin), int(count),
+                                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out

@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <thread>
 
@@ -20,6 +21,44 @@ namespace gdc {
 
 namespace {
 thread_local std::string g_last_error;
+}
+
+// Staging memory of gdc_philox_normals_noalloc: a file-scope device array,
+// one copy per GPU, held until the process ends.  Host code never uses the
+// array's name as an address (on the host it is only a stand-in for the
+// symbol); it uses the device address looked up per device below.
+constexpr int NOALLOC_MAX_NORMAL_GROUPS = 65536;   // 4 normals each: 2 MiB
+static __device__ __align__(256) double scratch[4 * NOALLOC_MAX_NORMAL_GROUPS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current (every GPU holds its own copy at its own address).
+int scratch_address(int device, void** out) {
+  if (device < 0 || device >= MAX_DEVICES) {
+    set_error("device ordinal out of range for the staging array");
+    return GDC_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    hipError_t e = hipSetDevice(device);
+    void* p = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (prev >= 0) (void)hipSetDevice(prev);
+    if (e != hipSuccess || !p) {
+      set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      return GDC_EDEVICE;
+    }
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return GDC_OK;
 }
 
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -1068,6 +1107,10 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
       return GDC_EINVAL;
     }
     GDC_HIP(hipSetDevice(c.device));
+    {
+      void* sp = nullptr;
+      GDC_TRY(scratch_address(c.device, &sp));
+    }
     if (c.stream) {
       h->stream = (hipStream_t)c.stream;
     } else {
@@ -1750,6 +1793,30 @@ int gdc_philox_normals(gdc_handle* h, uint64_t seed, uint32_t c1, uint64_t step,
   }
   (void)hipFree(d);
   return rc;
+}
+
+int gdc_philox_normals_noalloc(gdc_handle* h, uint64_t seed, uint32_t c1, uint64_t step, uint32_t c0_begin,
+                               int count, double* out) {
+  if (!h || !out || count < 0) {
+    set_error("handle, output and count >= 0 are required");
+    return GDC_EINVAL;
+  }
+  if (count > NOALLOC_MAX_NORMAL_GROUPS) {
+    set_error("gdc_philox_normals_noalloc: count " + std::to_string(count) + " exceeds the staging limit of " +
+              std::to_string(NOALLOC_MAX_NORMAL_GROUPS) + " groups of four normals");
+    return GDC_EINVAL;
+  }
+  if (count == 0) return GDC_OK;
+  DeviceGuard dg(h->device);
+  void* sp = nullptr;
+  GDC_TRY(scratch_address(h->device, &sp));
+  double* d = static_cast<double*>(sp);
+  // every staged value is written by the kernel before it is copied out:
+  // nothing to clear
+  GDC_TRY(philox_normals_dev(seed, c1, step, c0_begin, count, d, h->stream));
+  GDC_HIP(hipMemcpyAsync(out, d, 4 * (size_t)count * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  GDC_HIP(hipStreamSynchronize(h->stream));
+  return GDC_OK;
 }
 
 }  // extern "C"
