@@ -1,33 +1,43 @@
 """Throughput of the gDC step on one MI355X: blob-steps/s with p50/p99 step
-latency, on the 1,000-rod suspension (10,000 blobs, L = 128a, grid 128^3,
-FP32 grid with FP64 body algebra, harmonic pair repulsion, dt = 0.005).
+latency, on the largest suspension that fits one GPU: 32,768 rods of 10
+blobs (327,680 blobs), L = 384a, grid 384^3, axes within 15 degrees of z,
+background shear 0.1 and harmonic pair repulsion, dt = 0.005, FP32 grid with
+FP64 body algebra and Krylov vectors.
 
 One step is the whole hot path: stress noise and the random velocity field,
 the least-squares velocity and the finite-difference drift factor, the
 midpoint move, pair forces, the full saddle solve by GMRES, and the update.
 Inputs stay resident in HBM (device tensors) for the timed region.
 
-The GMRES tolerance is the loosest in a ladder whose FP32 body-mobility
-solve stays within 1e-5 (relative L2) of the library's FP64 solve (itself
-parity-tested against the FP64 oracle), on the first state with a probe force
-F ~ N(0,1) per body.
+"At 1e-5 relative mobility error": the GMRES tolerance is the loosest of a
+ladder (eight rungs per decade) whose FP32 body-mobility solve, on the first
+state with a probe force F ~ N(0, 1) per body, stays within 1e-5 (relative
+L2) of a reference solve: the library's FP64 path at 1e-12 for the 384^3
+suspension (whose FP32 first step is parity-tested against the FP64 oracle
+at full size), the FP64 oracle's own solve (1e-10) wherever the oracle fits
+in the run (the 1,000-rod suspension and the serving buckets).
 
 Beside the headline figure the JSON line carries:
-  roofline      the step's dominant kernel (at 128^3 the inverse plane pass of
-                the 3D transform) against HBM peak;
+  roofline      the step's dominant kernel (at 384^3 the projection pass of the
+                five-pass 3D transform) against HBM peak, duration measured
+                live with dispatch-stamped events on its launch stream;
   kernels       achieved bandwidth of spreading, averaging and each FFT pass;
   fp64_single   the same suspension on the plain FP64 path;
+  rods1000      the 1,000-rod suspension (128^3), calibrated against the
+                oracle, with its own roofline (inverse plane pass);
   rheology      effective viscosity of 500 rods under the sinusoidal forcing;
   serving       256 independent suspensions (N log-uniform in [8, 2048] rods,
                 grids 32^3..128^3, 50 steps each) served with continuous
-                batching: saturation throughput (all requests queued at
-                once), a Poisson stream at that rate with p50/p99 step
-                latency, and the same requests stepped one at a time on the
-                plain FP64 and FP32 paths (a sample of 16);
-  cpu_baseline  the FP64 oracle on one step of the headline suspension.
+                batching, each grid bucket at its own calibrated tolerance:
+                saturation throughput, a Poisson sweep with p50/p99 step
+                latency, and the same requests one at a time on the plain
+                FP64 and FP32 paths (a sample of 16);
+  cpu_baseline  the FP64 oracle on a bounded sample of the headline
+                suspension (one full-size mobility apply), scaled to
+                blob-steps/s.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--no-serving] [--serving-requests R]
+                       [--no-serving] [--no-extras] [--workload NAME]
 """
 import argparse
 import json
@@ -40,16 +50,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "blob-steps/sec of gDC step at 1e-5 rel mobility error; p50/p99 step latency"
 HBM_PEAK_GBS = 8000.0
+TARGET_ERR = 1e-5
 
 # Dominant kernel of each workload's step (largest share of GPU time in its
 # kernel trace) as (probe family, kernel, algorithmic bytes per launch from G
-# grid points and M blobs).  At 128^3 it is the inverse plane pass of the
-# three-pass transform (inverse FFT along axis 1 and C2R along axis 2 of a
-# whole plane), run once per GMRES iteration and once for the random
-# velocity field: it reads the three half spectra (G/2 complex FP32 values
-# each) and writes the three real components (G FP32 values each), 24 G
-# bytes.  The larger grids take the five-pass transform, whose longest pass
-# moves 24 G bytes too.
+# grid points and M blobs).  At 384^3 it is the projection pass of the
+# five-pass transform (FFT along axis 0, Stokes projection, inverse FFT along
+# axis 0, the spectrum read once and written once: three half spectra of
+# G/2 complex FP32 values each, in and out, 24 G bytes), once per GMRES
+# iteration.  At 256^3 the C2R pass moves the same 24 G; at 128^3 the inverse
+# plane pass of the three-pass transform reads the three half spectra and
+# writes the three real components, 24 G as well.
 DOMINANT = {
     "rods1000": ("fft_plane_inv", "k_plane_inv", lambda G, M: 24 * G),
     "mixed4096": ("fft_c2r", "k_c2r_axis2", lambda G, M: 24 * G),
@@ -79,72 +90,89 @@ WORKLOAD_TEXT = {
     "mixed4096": "mixed4096: 1,366 rods(10) + 1,365 boomerangs(15) + 1,365 tetrahedra(4) (39,595 blobs), "
                  "L=256a, grid 256^3, FP32 grid / FP64 bodies, force e_z on every body, dt=0.005",
     "rods32768": "rods32768: 32,768 rods x 10 blobs (327,680 blobs), L=384a, grid 384^3, axes within 15 deg "
-                 "of z, shear 0.1 + harmonic pair repulsion, FP32 grid / FP64 bodies, dt=0.005",
+                 "of z, shear 0.1 + harmonic pair repulsion, FP32 grid / FP64 bodies and Krylov, dt=0.005",
 }
 
 SERVING_BUDGET = 32 << 30
 SERVING_SLOTS = 16
+LADDER = [float(f"{1e-3 * 10 ** (-k / 8):.2g}") for k in range(33)]   # 1e-3 .. 1e-7, ratio 10^(1/8)
 
 
 def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def calibrate(g, wl, w, Y0, q0, target=1e-5):
+def probe_force(w):
     import numpy as np
-    rng = np.random.default_rng(1234)
-    F = rng.standard_normal((w.N, 6))
-    ref = g.Suspension(**wl.library_kwargs(w, precision="fp64", gmres_tol=1e-12, gmres_maxit=1000))
-    Vref = ref.mobility_apply("body", Y0, q0, F)
-    ref.close()
-    chosen = None
-    # eight rungs per decade (ratio 10^(1/8) = 1.33), 1e-3 down to 1e-7
-    for tol in [float(f"{1e-3 * 10 ** (-k / 8):.2g}") for k in range(33)]:
-        s = g.Suspension(**wl.library_kwargs(w, precision="fp32", gmres_tol=tol, gmres_maxit=500))
-        V = s.mobility_apply("body", Y0, q0, F, allow_notconv=True)
-        s.close()
-        err = float(np.linalg.norm(V - Vref) / np.linalg.norm(Vref))
-        if err <= target:
-            chosen = (tol, err)
-            break
-    if chosen is None:
-        raise RuntimeError("no GMRES tolerance reaches the target mobility error")
-    return chosen
+    return np.random.default_rng(1234).standard_normal((w.N, 6))
 
 
-def mobility_error(g, wl, w, Y0, q0, tol, precision="fp32"):
-    """Relative L2 error of the body mobility at GMRES tolerance tol against
-    the library's FP64 solve at 1e-12."""
+def reference_body(g, wl, w, Y0, q0, source):
+    """V = N F for the probe force: the FP64 oracle's saddle solve (GMRES to
+    1e-10) or the library's FP64 path (GMRES to 1e-12)."""
     import numpy as np
-    F = np.random.default_rng(1234).standard_normal((w.N, 6))
+    F = probe_force(w)
+    if source == "oracle":
+        from oracle import fcm, rigid
+        fcm.DEFAULT_WORKERS = len(os.sched_getaffinity(0))
+        p = fcm.FcmParams(fcm.Grid(w.L, w.n), w.eta, w.sigma, w.rc)
+        susp = rigid.Suspension(p, rigid.Bodies(w.shapes, w.body_shape), w.a)
+        r = rigid.blob_positions(susp.bodies, Y0, q0)
+        _, V, _ = rigid.solve_saddle(susp, Y0, r, np.zeros((w.M, 3)), F, tol=1e-10)
+        return V
     ref = g.Suspension(**wl.library_kwargs(w, precision="fp64", gmres_tol=1e-12, gmres_maxit=1000))
-    Vref = ref.mobility_apply("body", Y0, q0, F)
+    V = ref.mobility_apply("body", Y0, q0, F)
     ref.close()
+    return V
+
+
+def body_error(g, wl, w, Y0, q0, Vref, tol, precision="fp32"):
+    import numpy as np
     s = g.Suspension(**wl.library_kwargs(w, precision=precision, gmres_tol=tol, gmres_maxit=500))
-    V = s.mobility_apply("body", Y0, q0, F, allow_notconv=True)
+    V = s.mobility_apply("body", Y0, q0, probe_force(w), allow_notconv=True)
     s.close()
     return float(np.linalg.norm(V - Vref) / np.linalg.norm(Vref))
 
 
-def cpu_baseline(w, Y0, q0, tol):
-    """The FP64 oracle, as it stands, on the first steps of the same workload."""
+def calibrate(g, wl, cases, target=TARGET_ERR):
+    """The loosest ladder tolerance at which every case's FP32 body solve is
+    within target of its reference.  cases: [(workload, Y0, q0, Vref)].
+    Returns (tol, [error per case])."""
+    for tol in LADDER:
+        errs = []
+        for (w, Y0, q0, Vref) in cases:
+            errs.append(body_error(g, wl, w, Y0, q0, Vref, tol))
+            if errs[-1] > target:
+                break
+        if len(errs) == len(cases) and max(errs) <= target:
+            return tol, errs
+    raise RuntimeError("no GMRES tolerance reaches the target mobility error")
+
+
+def cpu_baseline(w, Y0, q0, gpu_iterations):
+    """The FP64 oracle, as it stands, on a bounded sample of the same
+    suspension: one application of its FCM mobility J L^-1 S at the full
+    size (weights of all blobs, spreading, the 3D FFT solve, averaging), the
+    unit of work of every GMRES iteration.  A step needs at least
+    (GMRES iterations + 1) such applies (the +1 is the random-field solve),
+    so blob-steps/s is bounded above by M / ((k + 1) t_apply); the oracle's
+    averages, least-squares and preconditioner work are not counted."""
     import numpy as np
-    from oracle import fcm, gdc, rigid
+    from oracle import fcm, rigid
     cores = len(os.sched_getaffinity(0))
     fcm.DEFAULT_WORKERS = cores
     p = fcm.FcmParams(fcm.Grid(w.L, w.n), w.eta, w.sigma, w.rc)
-    cfg = gdc.Config(rigid.Suspension(p, rigid.Bodies(w.shapes, w.body_shape), w.a), w.kT, w.dt,
-                     w.noise_seed, gdc.Forces(w.steric_k, w.steric_cutoff,
-                                              np.asarray(w.const_force, dtype=np.float64), w.shear_rate))
-    n_steps = 2
+    r = rigid.blob_positions(rigid.Bodies(w.shapes, w.body_shape), Y0, q0)
+    lam = np.random.default_rng(7).standard_normal((w.M, 3))
     t0 = time.perf_counter()
-    Y, q = Y0, q0
-    for k in range(n_steps):
-        Y, q, _ = gdc.gdc_step(cfg, Y, q, k, tol=tol)
-    dt = time.perf_counter() - t0
-    return {"value": w.M * n_steps / dt, "unit": "blob-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"the first {n_steps} gDC steps of the same 1,000-rod suspension from the same state, "
-                      f"GMRES tol {tol:g}, {dt:.1f} s"}
+    fcm.mobility_apply(r, lam, p)
+    t_apply = time.perf_counter() - t0
+    applies = float(gpu_iterations) + 1.0
+    return {"value": w.M / (applies * t_apply), "unit": "blob-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"one FP64 oracle mobility apply J L^-1 S on the full {w.name} suspension "
+                      f"({w.M:,} blobs, grid {w.n[0]}^3): {t_apply:.1f} s on {cores} threads, scaled to a step "
+                      f"of {applies:.1f} applies (the GPU's mean GMRES iterations + the random-field solve); "
+                      f"an upper bound on the oracle's rate"}
 
 
 def oracle_timings(wl, tol):
@@ -248,7 +276,8 @@ def timed_steps(g, s, Y, q, steps, warmup):
 
 def kernel_bandwidth(g, s, Y, q, w, cov):
     """Average duration and achieved algorithmic bandwidth of each grid
-    kernel family over 4 steps (HIP events on the launch stream)."""
+    kernel family over 4 steps (dispatch-stamped HIP events on the launch
+    stream)."""
     G = int(w.G)
     fams = {
         "spread": ("k_spread_tab", BYTES_PER_POINT * G + BYTES_PER_BLOB * w.M),
@@ -276,21 +305,63 @@ def kernel_bandwidth(g, s, Y, q, w, cov):
     return out
 
 
-def fp64_single(g, wl, w, Y0, q0, tol, stream, steps):
-    """The plain FP64 path on the same suspension at the same tolerance."""
+def time_workload(g, wl, name, w, Y0, q0, tol, stream, steps, warmup):
+    """Times `steps` steps of workload w at GMRES tolerance tol (after
+    `warmup`), with the dominant kernel probed over the timed region."""
     import numpy as np
     import torch
+    s = g.Suspension(**wl.library_kwargs(w, gmres_tol=tol, gmres_maxit=500, stream=stream.cuda_stream))
+    Y = torch.tensor(Y0, dtype=torch.float64, device="cuda")
+    q = torch.tensor(q0, dtype=torch.float64, device="cuda")
+    if warmup:
+        s.step(Y, q, warmup)
+    torch.cuda.synchronize()
+    fam, kname, nbytes = DOMINANT[name]
+    g.probe_kernel(fam)
+    total, lat_ms, its, st = timed_steps(g, s, Y, q, steps, 0)
+    if len(lat_ms) == 0:   # one timed step: its latency is the call's time
+        lat_ms = np.array([total * 1e3])
+    k_ms, k_launches = g.probe_read()
+    g.probe_kernel(None)
+    G = int(np.prod(w.n))
+    alg_bytes = nbytes(G, w.M)
+    avg_s = k_ms * 1e-3 / max(k_launches, 1)
+    achieved = alg_bytes / avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES.get(name),
+                "kernel": kname, "launches": k_launches, "avg_us": avg_s * 1e6, "algorithmic_bytes": alg_bytes}
+    # the whole step against the byte model of the method's grid traffic:
+    # G (60 + 72 k) bytes per FP32 step with k operator applies (GMRES
+    # iterations), each 3D transform counted once read and once written
+    step_bytes = G * (60.0 + 72.0 * float(its))
+    step_gbs = step_bytes / (total / steps) / 1e9
+    res = {
+        "value": w.M * steps / total, "ms_per_step": total * 1e3 / steps, "gmres_iterations_mean": float(its),
+        "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+        "nu_mean": st["nu_mean"], "nu_std": st["nu_std"], "nu_min": st["nu_min"], "nu_max": st["nu_max"],
+        "nu_nonpositive": st["nu_nonpositive"],
+        "fft_passes": 3 if (max(w.n) <= 128 and w.n[1] == w.n[2]) else 5,
+        "fft_workgroup_sizes": s.launch_config,
+        "roofline": roofline,
+        "step_roofline": {"model": "G (60 + 72 k) bytes per step, k = mean GMRES iterations",
+                          "bytes_per_step": step_bytes, "achieved": step_gbs, "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS},
+    }
+    return s, Y, q, res
+
+
+def fp64_single(g, wl, w, Y0, q0, tol, stream, steps):
+    """The plain FP64 path on the same suspension at the same tolerance."""
+    import torch
     progress("plain FP64 path")
-    k = max(5, steps // 3)
     s64 = g.Suspension(**wl.library_kwargs(w, precision="fp64", gmres_tol=tol, gmres_maxit=500,
                                            stream=stream.cuda_stream))
     Y64 = torch.tensor(Y0, dtype=torch.float64, device="cuda")
     q64 = torch.tensor(q0, dtype=torch.float64, device="cuda")
-    t64, _, its64, _ = timed_steps(g, s64, Y64, q64, k, 2)
+    t64, _, its64, _ = timed_steps(g, s64, Y64, q64, steps, 1)
     s64.close()
-    return {"blob_steps_per_s": w.M * k / t64, "ms_per_step": t64 * 1e3 / k,
-            "gmres_iterations_mean": float(its64),
-            "mobility_rel_err": mobility_error(g, wl, w, Y0, q0, tol, precision="fp64")}
+    return {"blob_steps_per_s": w.M * steps / t64, "ms_per_step": t64 * 1e3 / steps, "steps": steps,
+            "gmres_iterations_mean": float(its64)}
 
 
 def rheology_bench(g, wl, tol, stream, steps=100):
@@ -327,21 +398,34 @@ def rheology_bench(g, wl, tol, stream, steps=100):
                     "rheology measurement"}
 
 
-def serving_bench(g, wl, reqs, states, tol, budget, slots):
+def serving_bench(g, wl, reqs, states, budget, slots):
+    """Continuous batching of the serving stream.  Each grid bucket
+    (32^3 .. 128^3) runs at its own tolerance: the loosest ladder rung at
+    which the bucket's smallest and largest requests both solve the body
+    mobility within 1e-5 of the FP64 oracle."""
     import numpy as np
     from paper_2106_00449_amd.serving import Request, Server, summarise
+
+    buckets = sorted(set(int(w.n[0]) for w in reqs))
+    tols, bucket_err = {}, {}
+    for n in buckets:
+        idx = [i for i, w in enumerate(reqs) if w.n[0] == n]
+        pick = sorted(set([min(idx, key=lambda i: reqs[i].M), max(idx, key=lambda i: reqs[i].M)]))
+        progress(f"serving: calibrating the {n}^3 bucket on requests {pick}")
+        cases = [(reqs[i], *states[i], reference_body(g, wl, reqs[i], *states[i], "oracle")) for i in pick]
+        tol, errs = calibrate(g, wl, cases)
+        tols[n] = tol
+        bucket_err[f"{n}^3"] = {"gmres_tol": tol, "requests": len(idx),
+                                "calibrated_on": [{"request": int(i), "bodies": reqs[i].N, "rel_err": e}
+                                                  for i, e in zip(pick, errs)]}
 
     def requests(rate):
         out = []
         for i, (w, (Y, q)) in enumerate(zip(reqs, states)):
             arr = w.extra["arrival"] / rate if rate else 0.0
-            out.append(Request(i, wl.library_kwargs(w, gmres_tol=tol, gmres_maxit=500), Y, q, w.steps, arr,
-                               blobs=w.M))
+            out.append(Request(i, wl.library_kwargs(w, gmres_tol=tols[w.n[0]], gmres_maxit=500), Y, q, w.steps,
+                               arr, blobs=w.M))
         return out
-
-    # the tolerance checked on the smallest and the largest request
-    order = np.argsort([w.M for w in reqs])
-    errs = [mobility_error(g, wl, reqs[i], *states[i], tol) for i in (order[0], order[-1])]
 
     progress("serving: saturation run")
     srv = Server(hbm_budget=budget, max_slots=slots)
@@ -350,7 +434,6 @@ def serving_bench(g, wl, reqs, states, tol, budget, slots):
     sat = summarise(res, makespan=time.perf_counter() - t0)
     sat.update(peak_bytes=srv.peak_bytes, peak_slots=srv.peak_slots)
     rate = len(reqs) / sat["makespan_s"]
-    # Poisson arrivals at 0.5x, 1x and 2x the saturation request rate
     sweep = {}
     for f in (0.5, 1.0, 2.0):
         progress(f"serving: Poisson run at {f * rate:.1f} requests/s ({f:g}x saturation)")
@@ -359,9 +442,9 @@ def serving_bench(g, wl, reqs, states, tol, budget, slots):
         summ = summarise(res)
         summ.update(arrival_rate_per_s=f * rate, peak_bytes=srv.peak_bytes, peak_slots=srv.peak_slots)
         sweep[f"{f:g}x"] = summ
-    poisson = sweep["1x"]
 
     # one at a time on the plain paths, same requests (a sample)
+    order = np.argsort([w.M for w in reqs])
     sample = order[:: max(1, len(order) // 16)][:16]
     seq = {}
     for prec in ["fp64", "fp32"]:
@@ -370,7 +453,7 @@ def serving_bench(g, wl, reqs, states, tol, budget, slots):
         for i in sample:
             w = reqs[i]
             Y, q = (x.copy() for x in states[i])
-            s = g.Suspension(**wl.library_kwargs(w, precision=prec, gmres_tol=tol, gmres_maxit=500))
+            s = g.Suspension(**wl.library_kwargs(w, precision=prec, gmres_tol=tols[w.n[0]], gmres_maxit=500))
             s.step(Y, q, 1)
             t0 = time.perf_counter()
             for _ in range(w.steps):
@@ -388,9 +471,9 @@ def serving_bench(g, wl, reqs, states, tol, budget, slots):
         "workload": f"{len(reqs)} suspensions of N rods x 10 blobs, N log-uniform in [8, 2048] "
                     f"({sum(w.M for w in reqs):,} blobs), 5% blob volume fraction, grids "
                     f"{min(w.n[0] for w in reqs)}^3..{max(w.n[0] for w in reqs)}^3, 50 gDC steps each, FP32",
-        "gmres_tol": tol, "mobility_rel_err_smallest_largest": errs,
+        "tolerance_per_bucket": bucket_err,
         "hbm_budget_bytes": budget, "max_slots": slots,
-        "saturation": sat, "poisson_at_saturation_rate": poisson, "poisson_rate_sweep": sweep,
+        "saturation": sat, "poisson_at_saturation_rate": sweep["1x"], "poisson_rate_sweep": sweep,
         "sequential_fp64_sample": seq["fp64"], "sequential_fp32_sample": seq["fp32"],
         "served_over_sequential_fp64": sat["blob_steps_per_s"] / seq["fp64"]["blob_steps_per_s"],
     }
@@ -399,18 +482,20 @@ def serving_bench(g, wl, reqs, states, tol, budget, slots):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline only: no kernel table, FP64 path, 1,000-rod object or rheology")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="same as --no-extras --no-serving --no-cpu-baseline")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-slots", type=int, default=SERVING_SLOTS)
     ap.add_argument("--gmres-tol", type=float, default=0.0,
                     help="use this GMRES tolerance instead of calibrating one (profiling runs)")
-    ap.add_argument("--only-headline", action="store_true",
-                    help="time the headline suspension only (no kernel table, FP64 path or serving)")
-    ap.add_argument("--workload", default="rods1000", choices=["rods1000", "mixed4096", "rods32768"],
-                    help="suspension to time (the headline figure is quoted on rods1000)")
+    ap.add_argument("--workload", default="rods32768", choices=["rods32768", "rods1000", "mixed4096"],
+                    help="suspension of the headline figure (default: the largest, 384^3)")
     ap.add_argument("--oracle-timings", action="store_true",
                     help="time the oracle on every measurement configuration instead (host only, ~20 min; "
                          "no GPU work)")
@@ -423,6 +508,8 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(its sharding is a design, not code); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.only_headline:
+        args.no_extras = args.no_serving = args.no_cpu_baseline = True
 
     import numpy as np
     import workloads as wl
@@ -433,13 +520,18 @@ def main():
         return
 
     # initial states first, in worker processes, before anything touches the GPU
-    w = {"rods1000": lambda: wl.rods1000("fp32"), "mixed4096": wl.mixed4096,
-         "rods32768": wl.rods32768}[args.workload]()
+    make = {"rods1000": lambda: wl.rods1000("fp32"), "mixed4096": wl.mixed4096, "rods32768": wl.rods32768}
+    w = make[args.workload]()
     Y0, q0 = wl.initial_state(w)
+    c2 = None
+    if not args.no_extras and args.workload != "rods1000":
+        c2 = wl.rods1000("fp32")
+        Y2, q2 = wl.initial_state(c2)
     reqs, states = [], []
-    if not (args.no_serving or args.only_headline):
+    if not args.no_serving:
         reqs = wl.serving_requests(args.serving_requests)
         states = wl.initial_states(reqs)
+    cov = grid_coverage(w, Y0, q0)
 
     import torch
     import paper_2106_00449_amd as g
@@ -451,82 +543,58 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    source = "oracle" if args.workload == "rods1000" else "fp64"
     if args.gmres_tol > 0.0:
         tol, err = args.gmres_tol, None
     else:
-        progress("calibrating the GMRES tolerance")
-        tol, err = calibrate(g, wl, w, Y0, q0)
-    progress(f"tolerance {tol:g}; timing {args.steps} steps")
-
+        progress(f"calibrating the GMRES tolerance against the {source} reference")
+        tol, errs = calibrate(g, wl, [(w, Y0, q0, reference_body(g, wl, w, Y0, q0, source))])
+        err = errs[0]
+    progress(f"tolerance {tol:g}; timing {args.steps} steps of {w.name}")
     stream = torch.cuda.current_stream()
-    s = g.Suspension(**wl.library_kwargs(w, gmres_tol=tol, gmres_maxit=500, stream=stream.cuda_stream))
-    Y = torch.tensor(Y0, dtype=torch.float64, device="cuda")
-    q = torch.tensor(q0, dtype=torch.float64, device="cuda")
-    if args.warmup:
-        s.step(Y, q, args.warmup)
-    torch.cuda.synchronize()
-    dom_family, dom_kernel, dom_bytes = DOMINANT[args.workload]
-    g.probe_kernel(dom_family)
-    total, lat_ms, its, nust = timed_steps(g, s, Y, q, args.steps, 0)
-    if len(lat_ms) == 0:   # one timed step: its latency is the call's time
-        lat_ms = np.array([total * 1e3])
-    k_ms, k_launches = g.probe_read()
-    g.probe_kernel(None)
-    value = w.M * args.steps / total
-    G = int(np.prod(w.n))
-    alg_bytes = dom_bytes(G, w.M)
-    avg_s = k_ms * 1e-3 / max(k_launches, 1)
-    achieved = alg_bytes / avg_s / 1e9
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS,
-                "traffic": TRAFFIC_BYTES.get(args.workload),
-                "kernel": dom_kernel, "launches": k_launches, "avg_us": avg_s * 1e6,
-                "algorithmic_bytes": alg_bytes}
-    # the whole step against the byte model of the method's grid traffic:
-    # G (60 + 72 k) bytes per FP32 step with k operator applies (GMRES
-    # iterations), each 3D transform counted once read and once written
-    step_bytes = G * (60.0 + 72.0 * float(its))
-    step_gbs = step_bytes / (total / args.steps) / 1e9
-    step_roofline = {"model": "G (60 + 72 k) bytes per step, k = mean GMRES iterations",
-                     "bytes_per_step": step_bytes, "achieved": step_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": step_gbs / HBM_PEAK_GBS}
-    launch = s.launch_config
-    cov = grid_coverage(w, Y0, q0)
-    kernels, fp64 = {}, {}
-    if not args.only_headline or args.kernel_table:
+    s, Y, q, head = time_workload(g, wl, args.workload, w, Y0, q0, tol, stream, args.steps, args.warmup)
+    kernels = {}
+    if not args.no_extras or args.kernel_table:
         progress("kernel bandwidths")
         kernels = kernel_bandwidth(g, s, Y, q, w, cov)
     s.close()
 
-    rheo = {}
-    if not args.only_headline:
-        fp64 = fp64_single(g, wl, w, Y0, q0, tol, stream, args.steps)
-        rheo = rheology_bench(g, wl, tol, stream)
     out = {
-        "metric": METRIC, "value": value, "unit": "blob-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": total * 1e3 / args.steps,
+        "metric": METRIC, "value": head["value"], "unit": "blob-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "gmres_tol": tol, "mobility_rel_err": err,
-                   "gmres_iterations_mean": float(its),
-                   "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
-                   "nu_mean": nust["nu_mean"], "nu_std": nust["nu_std"], "nu_min": nust["nu_min"],
-                   "nu_max": nust["nu_max"], "interp_grid_coverage": cov,
-                   "fft_passes": 3 if (max(w.n) <= 128 and w.n[1] == w.n[2]) else 5,
-                   "fft_workgroup_sizes": launch},
-        "roofline": roofline,
-        "step_roofline": step_roofline,
+                   "mobility_reference": {"oracle": "FP64 oracle saddle solve (GMRES 1e-10)",
+                                          "fp64": "the library's FP64 path (GMRES 1e-12)"}[source],
+                   "gmres_iterations_mean": head["gmres_iterations_mean"],
+                   "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
+                   "nu_mean": head["nu_mean"], "nu_std": head["nu_std"], "nu_min": head["nu_min"],
+                   "nu_max": head["nu_max"], "nu_nonpositive_steps": head["nu_nonpositive"],
+                   "interp_grid_coverage": cov, "fft_passes": head["fft_passes"],
+                   "fft_workgroup_sizes": head["fft_workgroup_sizes"]},
+        "roofline": head["roofline"],
+        "step_roofline": head["step_roofline"],
         "kernels": kernels,
-        "fp64_single": fp64,
-        "rheology": rheo,
     }
+    if not args.no_extras:
+        out["fp64_single"] = fp64_single(g, wl, w, Y0, q0, tol, stream, max(5, args.steps // 4))
+        if c2 is not None:
+            progress("1,000-rod suspension: calibrating against the oracle")
+            tol2, errs2 = calibrate(g, wl, [(c2, Y2, q2, reference_body(g, wl, c2, Y2, q2, "oracle"))])
+            s2, _, _, r2 = time_workload(g, wl, "rods1000", c2, Y2, q2, tol2, stream, 30, 3)
+            s2.close()
+            r2.update(workload=WORKLOAD_TEXT["rods1000"], gmres_tol=tol2, mobility_rel_err=errs2[0],
+                      mobility_reference="FP64 oracle saddle solve (GMRES 1e-10)")
+            out["rods1000"] = r2
+        out["rheology"] = rheology_bench(g, wl, 1e-5, stream)
     if reqs:
         progress(f"serving {len(reqs)} requests")
-        out["serving"] = serving_bench(g, wl, reqs, states, tol, SERVING_BUDGET, args.serving_slots)
+        out["serving"] = serving_bench(g, wl, reqs, states, SERVING_BUDGET, args.serving_slots)
     if not args.no_cpu_baseline:
         progress("oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(w, Y0, q0, tol)
+        out["cpu_baseline"] = cpu_baseline(w, Y0, q0, head["gmres_iterations_mean"])
     print(json.dumps(out))
 
 

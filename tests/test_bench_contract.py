@@ -30,7 +30,7 @@ def _kernels_in_sources():
 
 def test_every_workload_names_an_existing_dominant_kernel():
     src = open(os.path.join(ROOT, "bench.py")).read()
-    m = re.search(r'"--workload", default="rods1000", choices=\[([^\]]*)\]', src)
+    m = re.search(r'"--workload", default="rods32768", choices=\[([^\]]*)\]', src)
     assert m, "workload choices not found"
     choices = re.findall(r'"(\w+)"', m.group(1))
     kernels = _kernels_in_sources()
