@@ -17,7 +17,14 @@ What is computed (all FP64):
     every mode with an index at n_d/2 set to zero;
   * averaging v_i = J[u]_i = dV sum_g u(x_g) Delta_i(x_g) (eq. averaging, the
     trapezoidal rule), so that J = dV S^T exactly;
-  * M_FCM lambda = J L^-1 S lambda (Sec. 4.2).
+  * M_FCM lambda = J L^-1 S lambda (Sec. 4.2);
+  * the slip channel of Sec. 6.3: walls at y = 0 and y = L_y/2 of a box of
+    height L_y (the computational domain twice the channel), the flow kept
+    mirror-symmetric about them by an image system: every blob force
+    lambda_i at r_i has an image R lambda_i at sigma(r_i), sigma(x, y, z) =
+    (x, L_y - y, z), R = diag(1, -1, 1).  A mirror-symmetric field has
+    u_y = 0 and d u_x/dy = d u_z/dy = 0 on both mirror planes, the slip
+    conditions; averaging reads the real blobs only.
 
 Oracle code: test infrastructure only.
 """
@@ -151,25 +158,56 @@ class FcmParams:
     eta: float
     sigma: float
     rc: float
+    channel: bool = False   # slip walls at y = 0 and y = L_y/2 by images (Sec. 6.3)
+
+
+# R: the mirror image of a force about a plane y = const flips its y component
+MIRROR = np.array([1.0, -1.0, 1.0])
+
+
+def mirror_positions(r, grid):
+    """sigma(r) = (x, L_y - y, z): the image of each blob about the wall
+    y = L_y/2 (equivalently about y = 0, the box being periodic in y)."""
+    m = np.array(r, dtype=np.float64).reshape(-1, 3)
+    m[:, 1] = grid.L[1] - m[:, 1]
+    return m
+
+
+def weights(r, p: FcmParams):
+    """(W, W_image): weight matrices of the blobs and, in the slip channel,
+    of their images (None in a periodic box)."""
+    W = weight_matrix(r, p.grid, p.sigma, p.rc)
+    Wm = weight_matrix(mirror_positions(r, p.grid), p.grid, p.sigma, p.rc) if p.channel else None
+    return W, Wm
+
+
+def spread_forces(Ws, lam, p: FcmParams):
+    """f = S lambda, plus the image forces R lambda_i at sigma(r_i) in the
+    slip channel."""
+    W, Wm = Ws
+    f = spread(W, lam, p.grid)
+    if Wm is not None:
+        f = f + spread(Wm, np.asarray(lam, dtype=np.float64).reshape(-1, 3) * MIRROR, p.grid)
+    return f
 
 
 def mobility_apply(r, lam, p: FcmParams, workers=None):
-    """M_FCM lambda = J L^-1 S lambda (Sec. 4.2).  r, lam: (M, 3) -> (M, 3)."""
-    W = weight_matrix(r, p.grid, p.sigma, p.rc)
-    f = spread(W, lam, p.grid)
-    u = stokes_solve(f, p.grid, p.eta, workers)
-    return interp(W, u, p.grid)
+    """M_FCM lambda = J L^-1 S lambda (Sec. 4.2), with the images of the slip
+    channel when p.channel.  r, lam: (M, 3) -> (M, 3)."""
+    Ws = weights(r, p)
+    u = stokes_solve(spread_forces(Ws, lam, p), p.grid, p.eta, workers)
+    return interp(Ws[0], u, p.grid)
 
 
 def dense_mobility(r, p: FcmParams):
     """The 3M x 3M matrix M_FCM, assembled column by column (small M only)."""
     r = np.asarray(r, dtype=np.float64).reshape(-1, 3)
     M = r.shape[0]
-    W = weight_matrix(r, p.grid, p.sigma, p.rc)
+    Ws = weights(r, p)
     out = np.empty((3 * M, 3 * M))
     for j in range(3 * M):
         lam = np.zeros(3 * M)
         lam[j] = 1.0
-        f = spread(W, lam.reshape(M, 3), p.grid)
-        out[:, j] = interp(W, stokes_solve(f, p.grid, p.eta), p.grid).reshape(-1)
+        f = spread_forces(Ws, lam.reshape(M, 3), p)
+        out[:, j] = interp(Ws[0], stokes_solve(f, p.grid, p.eta), p.grid).reshape(-1)
     return out

@@ -42,12 +42,17 @@ class Forces:
       measured from the body's wrapped centre so the flow is continuous
       across each body (not Lees-Edwards);
     sine_force: f0 of the periodic force density f0 sin(k y) e_x on the
-      fluid, k = 2 pi / L_y (Sec. 6.4, rheology)."""
+      fluid, k = 2 pi / L_y (Sec. 6.4, rheology);
+    wall_k, wall_cutoff: in the slip channel, the harmonic blob-wall
+      repulsion V(h) = (k/2)(h - b)^2 for h < b, h the blob's distance from
+      the wall y = 0 or y = L_y/2 (Sec. 6.3: b = 2.2a, k = 40 kT/(a b))."""
     steric_k: float = 0.0
     steric_cutoff: float = 0.0
     const_force: np.ndarray = field(default_factory=lambda: np.zeros(6))
     shear_rate: float = 0.0
     sine_force: float = 0.0
+    wall_k: float = 0.0
+    wall_cutoff: float = 0.0
 
 
 @dataclass
@@ -98,10 +103,29 @@ def steric_blob_forces(cfg: Config, r):
     return f
 
 
+def wall_blob_forces(cfg: Config, r):
+    """Blob forces of the harmonic wall repulsion of the slip channel (Sec.
+    6.3): along +y, k (b - y) when y < b (wall y = 0); along -y,
+    k (b - (H - y)) when H - y < b (wall y = H, H = L_y/2 the channel
+    height).  y is the blob's coordinate as stepped (not wrapped), so a blob
+    pushed through a wall feels a force that grows with the depth.  -> (M, 3)."""
+    f = np.zeros_like(r)
+    F = cfg.forces
+    if not cfg.susp.fcm.channel or F.wall_k == 0.0 or F.wall_cutoff <= 0.0:
+        return f
+    H = 0.5 * cfg.susp.fcm.grid.L[1]
+    y = r[:, 1]
+    lo = y < F.wall_cutoff
+    hi = H - y < F.wall_cutoff
+    f[lo, 1] += F.wall_k * (F.wall_cutoff - y[lo])
+    f[hi, 1] -= F.wall_k * (F.wall_cutoff - (H - y[hi]))
+    return f
+
+
 def body_forces(cfg: Config, Y, r):
     """F^m: (N, 6) force and torque on each body = K^T f_blob + constant."""
     b = cfg.susp.bodies
-    F = rigid.KT_apply(b, Y, r, steric_blob_forces(cfg, r))
+    F = rigid.KT_apply(b, Y, r, steric_blob_forces(cfg, r) + wall_blob_forces(cfg, r))
     return F + np.asarray(cfg.forces.const_force, dtype=np.float64)[None, :]
 
 
@@ -156,7 +180,11 @@ def background_flow(cfg: Config, Y, r):
 
 
 def fluct_field(cfg: Config, step):
+    """u_brev of the step: the canonical field, or the mirror-symmetric one of
+    the slip channel."""
     p = cfg.susp.fcm
+    if p.channel:
+        return noise.channel_field(p.grid, cfg.kT, p.eta, cfg.dt, cfg.seed, step)
     return noise.fourier_field(p.grid, cfg.kT, p.eta, cfg.dt, cfg.seed, step)
 
 

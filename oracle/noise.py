@@ -27,6 +27,12 @@ stored half spectrum), c1 = 16*stage + call (call 0..2 gives 12 normals per
 mode), (c2, c3) = step; key = seed.  Normals 2c and 2c+1 are Re and Im of
 component c in the order xx, yy, zz, xy, xz, yz.
 
+Slip channel (Sec. 6.3): the stress is given its image in the mirror half
+of the box, W'(x) = (W(x) + R W(sigma x) R) / sqrt(2) (R W R flips the
+xy and yz components), which keeps the random velocity mirror-symmetric
+and gives Cov(J u_brev) = (2 kT/dt) M of the channel.  The oracle applies the
+reflection in real space to the canonical stress field (channel_field).
+
 Oracle code: test infrastructure only.
 """
 
@@ -127,3 +133,23 @@ def real_space_field(grid: Grid, kT, eta, dt, rng):
     Wr = real_space_stress(grid, kT, eta, dt, rng)
     Wh = scipy.fft.rfftn(Wr, axes=(1, 2, 3))
     return fluct_velocity_from_spectrum(Wh, grid, eta)
+
+
+def mirror_stress(Wr):
+    """(W + R W(sigma x) R) / sqrt(2) of a real-space stress field (6, n0, n1,
+    n2): sigma maps grid row j1 to (n1 - j1) mod n1 (y -> L_y - y), and
+    R W R flips the sign of the xy and yz components."""
+    Wm = np.roll(Wr[:, :, ::-1, :], 1, axis=2)    # row j1 <- row (n1 - j1) mod n1
+    sign = np.array([1.0, 1.0, 1.0, -1.0, 1.0, -1.0])[:, None, None, None]
+    return (Wr + sign * Wm) / np.sqrt(2.0)
+
+
+def channel_field(grid: Grid, kT, eta, dt, seed, step):
+    """Random velocity field of the slip channel: the canonical stress
+    spectrum taken to real space, reflected there (mirror_stress), and
+    transformed back before the divergence and projection."""
+    Wh = fourier_stress(grid, kT, eta, dt, seed, step)
+    Wr = scipy.fft.irfftn(Wh, s=grid.n, axes=(1, 2, 3), workers=fcm.DEFAULT_WORKERS)
+    Wh2 = scipy.fft.rfftn(mirror_stress(Wr), axes=(1, 2, 3), workers=fcm.DEFAULT_WORKERS)
+    _, keep = wavevectors(grid)
+    return fluct_velocity_from_spectrum(Wh2 * keep[None], grid, eta)

@@ -187,16 +187,16 @@ def unknowns(bodies):
     return 3 * bodies.M + 6 * bodies.N
 
 
-def saddle_apply(s: Suspension, Y, r, x, W=None):
+def saddle_apply(s: Suspension, Y, r, x, Ws=None):
     """[[M, -K], [-K^T, -Pi]] [lambda; V] (eq. lin_sys_RMB with the frozen
-    null space).  x: flat (3M + 6N,)."""
+    null space).  x: flat (3M + 6N,).  Ws: fcm.weights(r) if precomputed."""
     b = s.bodies
     lam = x[:3 * b.M].reshape(-1, 3)
     V = x[3 * b.M:].reshape(-1, 6)
-    if W is None:
-        W = fcm.weight_matrix(r, s.fcm.grid, s.fcm.sigma, s.fcm.rc)
-    f = fcm.spread(W, lam, s.fcm.grid)
-    Mlam = fcm.interp(W, fcm.stokes_solve(f, s.fcm.grid, s.fcm.eta), s.fcm.grid)
+    if Ws is None:
+        Ws = fcm.weights(r, s.fcm)
+    f = fcm.spread_forces(Ws, lam, s.fcm)
+    Mlam = fcm.interp(Ws[0], fcm.stokes_solve(f, s.fcm.grid, s.fcm.eta), s.fcm.grid)
     top = Mlam - K_apply(b, Y, r, V)
     bot = -KT_apply(b, Y, r, lam)
     for p, sl, rel in per_body(b, Y, r):
@@ -298,10 +298,10 @@ def solve_saddle(s: Suspension, Y, r, v_slip, F, tol=1e-12, dense=None):
     n = unknowns(b)
     if dense is None:
         dense = n <= 1500
-    W = fcm.weight_matrix(r, s.fcm.grid, s.fcm.sigma, s.fcm.rc)
+    Ws = fcm.weights(r, s.fcm)
 
     def A(x):
-        return saddle_apply(s, Y, r, x, W)
+        return saddle_apply(s, Y, r, x, Ws)
     if dense:
         Amat = np.empty((n, n))
         for j in range(n):

@@ -75,7 +75,7 @@ def test_gmres_equals_dense_and_preconditioner_free():
     lam_g, V_g, info = rigid.solve_saddle(s, Y, r, slip, F, dense=False, tol=1e-13)
     assert np.abs(V_g - V_d).max() < 1e-10 * np.abs(V_d).max()
     # plain (unpreconditioned) GMRES converges to the same answer
-    W = fcm.weight_matrix(r, s.fcm.grid, s.fcm.sigma, s.fcm.rc)
+    W = fcm.weights(r, s.fcm)
     rhs = rigid.saddle_rhs(s, Y, r, slip, F)
     x, its, rr = rigid.gmres(lambda x: rigid.saddle_apply(s, Y, r, x, W), rhs, None, tol=1e-13, restart=200)
     assert np.abs(x[3 * s.bodies.M:].reshape(-1, 6) - V_d).max() < 1e-9 * np.abs(V_d).max()
