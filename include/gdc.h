@@ -77,13 +77,19 @@ typedef struct {
  *     fluid, k = 2 pi / L1 (the rheology forcing of Sec. 6.4); its flow
  *     f0/(eta k^2) sin(k y) e_x, averaged at each blob, enters the step-5
  *     slip, and each step reports the sine amplitude v_x of the fluid's
- *     x-velocity (gdc_stats.sine_vx), so that eta_eff = f0 / (k^2 v_x). */
+ *     x-velocity (gdc_stats.sine_vx), so that eta_eff = f0 / (k^2 v_x).
+ *   wall_k, wall_cutoff: in the slip channel (gdc_config.channel), the
+ *     harmonic blob-wall repulsion V(h) = k/2 (h - cutoff)^2 for h < cutoff,
+ *     h the blob's distance from the wall y = 0 or y = L1/2 (Sec. 6.3:
+ *     cutoff 2.2a, k = 40 kT/(a cutoff)); 0 disables it. */
 typedef struct {
   double steric_k;
   double steric_cutoff;
   double const_force[6];
   double shear_rate;
   double sine_force;
+  double wall_k;
+  double wall_cutoff;
 } gdc_forces;
 
 /* Suspension and solver parameters (Sec. 2-4, Sec. 6.1).
@@ -99,6 +105,12 @@ typedef struct {
  *   precision: GDC_FP32 (grid in FP32, bodies and Krylov in FP64) or GDC_FP64.
  *   scheme: GDC_SCHEME_GDC (Sec. 3) or GDC_SCHEME_EM (Appendix D).
  *   divergence: GDC_DIV_FD (eq. FD) or GDC_DIV_RFD (eq. rfd_div).
+ *   channel: 0 for the periodic box; 1 for the slip channel of Sec. 6.3:
+ *     free-slip walls at y = 0 and y = L1/2 (u_y = 0, no tangential stress),
+ *     the box of height L1 being twice the channel, kept by an image system:
+ *     every blob force has its mirror image R lambda at (x, L1 - y, z),
+ *     R = diag(1, -1, 1), and the stress noise is mirrored the same way.
+ *     Bodies belong in 0 < y < L1/2; no shear or sine forcing there.
  *   seed: Philox4x32-10 key of every random number of the run.
  *   shapes[n_shapes]; body_shape[n_bodies]: shape index of each body.
  *   device: HIP device ordinal; stream: a hipStream_t or NULL (the library
@@ -109,7 +121,7 @@ typedef struct {
   double a, sigma, trunc, eta, kT, dt, fd_delta;
   double gmres_tol;
   int gmres_maxit, gmres_restart;
-  int precision, scheme, divergence;
+  int precision, scheme, divergence, channel;
   uint64_t seed;
   int n_shapes;
   const gdc_shape* shapes;

@@ -45,7 +45,7 @@ class _Shape(ctypes.Structure):
 class _Forces(ctypes.Structure):
     _fields_ = [("steric_k", ctypes.c_double), ("steric_cutoff", ctypes.c_double),
                 ("const_force", ctypes.c_double * 6), ("shear_rate", ctypes.c_double),
-                ("sine_force", ctypes.c_double)]
+                ("sine_force", ctypes.c_double), ("wall_k", ctypes.c_double), ("wall_cutoff", ctypes.c_double)]
 
 
 class _Config(ctypes.Structure):
@@ -55,6 +55,7 @@ class _Config(ctypes.Structure):
                 ("fd_delta", ctypes.c_double), ("gmres_tol", ctypes.c_double),
                 ("gmres_maxit", ctypes.c_int), ("gmres_restart", ctypes.c_int),
                 ("precision", ctypes.c_int), ("scheme", ctypes.c_int), ("divergence", ctypes.c_int),
+                ("channel", ctypes.c_int),
                 ("seed", ctypes.c_uint64),
                 ("n_shapes", ctypes.c_int), ("shapes", ctypes.POINTER(_Shape)),
                 ("n_bodies", ctypes.c_int), ("body_shape", ctypes.POINTER(ctypes.c_int)),
@@ -170,8 +171,10 @@ def _make_config(L, n, shapes, body_shape, *, a=1.0, sigma=0.0, trunc=0.0,
                  eta=1.0 / (6.0 * np.pi), kT=1.0, dt=0.01, fd_delta=0.0, gmres_tol=0.0,
                  gmres_maxit=0, gmres_restart=0, precision="fp32", scheme="gdc",
                  divergence="fd", seed=0, steric_k=0.0, steric_cutoff=0.0,
-                 const_force=(0, 0, 0, 0, 0, 0), shear_rate=0.0, sine_force=0.0, device=0, stream=None):
-    """A gdc_config and the arrays it points into (kept alive by the caller)."""
+                 const_force=(0, 0, 0, 0, 0, 0), shear_rate=0.0, sine_force=0.0, channel=False, wall_k=0.0,
+                 wall_cutoff=0.0, device=0, stream=None):
+    """A gdc_config and the arrays it points into (kept alive by the caller).
+    channel=True: the slip channel (walls at y = 0 and y = L[1]/2)."""
     shape_arrays = [np.ascontiguousarray(np.asarray(s, dtype=np.float64).reshape(-1, 3)) for s in shapes]
     bshape = np.ascontiguousarray(np.asarray(body_shape, dtype=np.int32))
     sh = (_Shape * len(shapes))()
@@ -189,6 +192,7 @@ def _make_config(L, n, shapes, body_shape, *, a=1.0, sigma=0.0, trunc=0.0,
     c.precision = {"fp32": GDC_FP32, "fp64": GDC_FP64}[precision]
     c.scheme = {"gdc": GDC_SCHEME_GDC, "em": GDC_SCHEME_EM}[scheme]
     c.divergence = {"fd": GDC_DIV_FD, "rfd": GDC_DIV_RFD}[divergence]
+    c.channel = 1 if channel else 0
     c.seed = int(seed)
     c.n_shapes = len(shapes)
     c.shapes = ctypes.cast(sh, ctypes.POINTER(_Shape))
@@ -199,6 +203,7 @@ def _make_config(L, n, shapes, body_shape, *, a=1.0, sigma=0.0, trunc=0.0,
         c.forces.const_force[k] = float(const_force[k])
     c.forces.shear_rate = shear_rate
     c.forces.sine_force = sine_force
+    c.forces.wall_k, c.forces.wall_cutoff = wall_k, wall_cutoff
     c.device = int(device)
     c.stream = stream
     keep = {"shapes": shape_arrays, "body_shape": bshape, "shapes_c": sh, "N": int(bshape.size),

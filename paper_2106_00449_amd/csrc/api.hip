@@ -354,6 +354,7 @@ using namespace gdc;
 struct gdc_handle {
   gdc_config cfg{};
   int N = 0, M = 0;
+  int Ms = 0;           // spreading blobs: M, or 2M in the slip channel (the images M .. 2M - 1)
   long long nx = 0;
   int device = 0;
   hipStream_t stream = nullptr;
@@ -386,6 +387,7 @@ struct gdc_handle {
   int *tile_ids = nullptr, *tile_count = nullptr, *tile_off = nullptr, *tile_cursor = nullptr;
   double* trec = nullptr;
   int* spos = nullptr;
+  double* rs = nullptr;          // slip channel: blob and image positions (2M x 3) for spreading
   double* zsorted = nullptr;
   void* tabs = nullptr;          // spreading tables of the current configuration
   int *tab_start = nullptr, *tab_count = nullptr, *tab_order = nullptr;
@@ -471,6 +473,15 @@ int validate(const gdc_config* c) {
   }
   if (M > (1LL << 30)) return bad("too many blobs");
   if (c->forces.steric_k < 0.0 || c->forces.steric_cutoff < 0.0) return bad("steric parameters must be >= 0");
+  if (c->channel != 0 && c->channel != 1) return bad("channel must be 0 or 1");
+  if (c->forces.wall_k < 0.0 || c->forces.wall_cutoff < 0.0) return bad("wall parameters must be >= 0");
+  if (c->channel) {
+    if (c->forces.shear_rate != 0.0 || c->forces.sine_force != 0.0)
+      return bad("the slip channel takes no background shear or sine forcing");
+    if (2 * M > (1LL << 30)) return bad("too many blobs");
+  } else if (c->forces.wall_k > 0.0) {
+    return bad("wall forces need the slip channel (channel = 1)");
+  }
   return GDC_OK;
 }
 
@@ -484,7 +495,13 @@ const Cx<R>* const* tw_of(gdc_handle* h) {
 // zeroed: the tile counts and the table claim counter were cleared already
 // (by the step's opening clear).
 int prepare_positions(gdc_handle* h, const double* r, bool zeroed = false) {
-  GDC_TRY(tile_sort(h->geom, h->tg, r, h->M, h->tile_ids, h->tile_count, h->tile_off, h->tile_cursor, h->trec,
+  const double* rsp = r;
+  if (h->geom.channel) {
+    // the images of the slip channel are spread too (blobs M .. 2M - 1)
+    GDC_TRY(mirror_positions(r, h->M, h->geom.L[1], h->rs, h->stream));
+    rsp = h->rs;
+  }
+  GDC_TRY(tile_sort(h->geom, h->tg, rsp, h->Ms, h->tile_ids, h->tile_count, h->tile_off, h->tile_cursor, h->trec,
                     h->spos, h->stream, zeroed));
   if (h->precision == GDC_FP64)
     return spread_prepare<double>(h->geom, h->tg, h->trec, h->tile_off, h->tabs, h->tab_start, h->tab_count,
@@ -492,6 +509,11 @@ int prepare_positions(gdc_handle* h, const double* r, bool zeroed = false) {
   return spread_prepare<float>(h->geom, h->tg, h->trec, h->tile_off, h->tabs, h->tab_start, h->tab_count,
                                h->tab_order, h->tab_claimed, h->stream, zeroed);
 }
+
+// The tile-sorted records averaging may visit blobs by (the real blobs only:
+// in the slip channel the records also hold the images, so blobs are visited
+// in index order instead; the sums are the same).
+inline const void* sorted_records(const gdc_handle* h) { return h->geom.channel ? nullptr : h->trec; }
 
 // out = M_FCM lam at blob positions r (prepared by prepare_positions), minus
 // U_p + Omega_p x (r_i - Y_p) when V (N x 6) is given.
@@ -503,7 +525,7 @@ int apply_mobility(gdc_handle* h, const double* r, const double* lam, double* ou
   R* f = (R*)h->grid[0];
   GDC_TRY(spread<R>(g, h->tg, h->tabs, h->tab_order, lam, lam_sorted, f, h->stream, skip));
   GDC_TRY(stokes_solve<R>(g, tw_of<R>(h), f, (Cx<R>*)h->grid[1], (Cx<R>*)h->grid[2], h->stream, skip));
-  return interp<R>(g, r, f, out, h->M, g.dV, h->bt.blob_body, Y, V, h->stream, skip, h->trec);
+  return interp<R>(g, r, f, out, h->M, g.dV, h->bt.blob_body, Y, V, h->stream, skip, sorted_records(h));
 }
 
 // z = P^-1 x and y = A z, A = [[M, -K], [-K^T, -Pi]] at (Y, q, r).
@@ -511,7 +533,8 @@ template <typename R>
 int apply_saddle_precond(gdc_handle* h, const double* Y, const double* q, const double* r, const double* x,
                          double* z, double* y, const int* skip = nullptr) {
   const long long m3 = 3LL * h->M;
-  GDC_TRY(precond_apply(h->bt, q, x, z, y + m3, h->spos, h->zsorted, h->maxdim, h->stream, skip));
+  GDC_TRY(precond_apply(h->bt, q, x, z, y + m3, h->spos, h->zsorted, h->maxdim, h->stream, skip,
+                        h->geom.channel ? h->M : 0));
   return apply_mobility<R>(h, r, z, y, Y, z + m3, h->zsorted, skip);
 }
 
@@ -700,6 +723,10 @@ int forces_at(gdc_handle* h, const double* Y, const double* r, bool zeroed = fal
                           h->cell_cap, h->nc, h->flags, h->fblob, h->stream, zeroed));
     fb = h->fblob;
   }
+  if (h->geom.channel && f.wall_k > 0.0 && f.wall_cutoff > 0.0) {
+    GDC_TRY(wall_forces(r, h->M, 0.5 * h->geom.L[1], f.wall_k, f.wall_cutoff, h->fblob, fb != nullptr, h->stream));
+    fb = h->fblob;
+  }
   return body_forces(h->bt, Y, r, fb, h->cforce, h->F, h->stream);
 }
 
@@ -804,10 +831,10 @@ int step_advance(gdc_handle* h, bool block, int& adv) {
     GDC_TRY(forces_at(h, Ym, h->rm, true));
     GDC_TRY(prepare_positions(h, h->rm, true));
     GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_fl, h->v, h->M, h->geom.dV, nullptr, nullptr, nullptr, s,
-                      nullptr, h->trec));
+                      nullptr, sorted_records(h)));
     if (h->vbg)
       GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_sine, h->vbg, h->M, h->geom.dV, nullptr, nullptr,
-                        nullptr, s, nullptr, h->trec));
+                        nullptr, s, nullptr, sorted_records(h)));
     GDC_TRY(rhs_build(h->bt, qm, Ym, h->rm, h->v, h->vbg, h->sine_scale, h->F, h->cfg.forces.shear_rate,
                       h->geom.L[1], h->rhs, s));
     GDC_TRY(solve_begin<R>(h, Ym, qm, h->rm));
@@ -1059,6 +1086,7 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
   g.inv2s2 = 1.0 / (2.0 * c.sigma * c.sigma);
   g.wnorm = std::pow(2.0 * 3.14159265358979323846 * c.sigma * c.sigma, -1.5);
   g.tiled = (g.n[0] % 8 == 0 && g.n[1] % 8 == 0 && g.n[2] % 32 == 0) ? 1 : 0;
+  g.channel = c.channel;
 
   // shapes and bodies
   h->N = cfg->n_bodies;
@@ -1097,6 +1125,7 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
       blob_local[body_off[p] + k] = k;
     }
   h->nx = 3LL * h->M + 6LL * h->N;
+  h->Ms = h->M * (c.channel ? 2 : 1);
 
   // device (a footprint query touches none)
   if (!h->dry) {
@@ -1258,16 +1287,18 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
     const int cols = std::min(t.T[1], g.P[1]) * std::min(t.T[2], g.P[2]);
     t.S = 1;
     while (t.S < cols) t.S *= 2;
-    GDC_TRY(h->alloc(&h->tile_ids, (size_t)h->M));
-    GDC_TRY(h->alloc(&h->trec, 2 * (size_t)h->M * tile_record_bytes() / sizeof(double)));
-    GDC_TRY(h->alloc(&h->spos, (size_t)h->M));
-    GDC_TRY(h->alloc(&h->zsorted, 3 * (size_t)h->M));
+    const size_t Ms = (size_t)h->Ms;
+    GDC_TRY(h->alloc(&h->tile_ids, Ms));
+    GDC_TRY(h->alloc(&h->trec, 2 * Ms * tile_record_bytes() / sizeof(double)));
+    GDC_TRY(h->alloc(&h->spos, Ms));
+    GDC_TRY(h->alloc(&h->zsorted, 3 * Ms));
+    if (c.channel) GDC_TRY(h->alloc(&h->rs, 3 * Ms));
     GDC_TRY(h->alloc(&h->tile_count, (size_t)(t.ntiles + 4)));
     GDC_TRY(h->alloc(&h->tile_off, (size_t)(t.ntiles + 1)));
     GDC_TRY(h->alloc(&h->tile_cursor, (size_t)t.ntiles));
     {
       double* tabs = nullptr;
-      GDC_TRY(h->alloc(&tabs, (spread_table_bytes(g, t, h->M, h->precision) + 7) / 8));
+      GDC_TRY(h->alloc(&tabs, (spread_table_bytes(g, t, h->Ms, h->precision) + 7) / 8));
       h->tabs = tabs;
     }
     GDC_TRY(h->alloc(&h->tab_start, (size_t)t.ntiles));
@@ -1379,10 +1410,17 @@ int gdc_mobility_apply(gdc_handle* h, int mode, const double* Y, const double* q
   if (mode == GDC_BLOB) {
     GDC_TRY(copy_in(h, h->io, in, 3 * (size_t)h->M, memspace));
     GDC_TRY(prepare_positions(h, h->r));
+    // in the slip channel spreading reads the forces (and their images) in
+    // the sorted order
+    const double* lsort = nullptr;
+    if (h->geom.channel) {
+      GDC_TRY(sort_forces(h->io, h->spos, h->M, h->M, h->zsorted, s));
+      lsort = h->zsorted;
+    }
     if (h->precision == GDC_FP64) {
-      GDC_TRY(apply_mobility<double>(h, h->r, h->io, h->v));
+      GDC_TRY(apply_mobility<double>(h, h->r, h->io, h->v, nullptr, nullptr, lsort));
     } else {
-      GDC_TRY(apply_mobility<float>(h, h->r, h->io, h->v));
+      GDC_TRY(apply_mobility<float>(h, h->r, h->io, h->v, nullptr, nullptr, lsort));
     }
     GDC_TRY(check_finite(h->v, 3LL * h->M, h->flags + 1, s));
     GDC_TRY(copy_out(h, out, h->v, 3 * (size_t)h->M, memspace));

@@ -75,7 +75,8 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_precond_mfma(BodyTables B, const double* __restrict__ q,
                                                      const double* __restrict__ x, double* __restrict__ z,
                                                      double* __restrict__ yV, const int* __restrict__ spos,
-                                                     double* __restrict__ zs, const int* __restrict__ skip) {
+                                                     double* __restrict__ zs, const int* __restrict__ skip,
+                                                     int mirror) {
   if (skip && *skip) return;
   constexpr int DP = PREC_MFMA_MAXDIM;
   __shared__ double X[DP][16];
@@ -158,6 +159,12 @@ __global__ __launch_bounds__(256) void k_precond_mfma(BodyTables B, const double
       d2[0] = w[0];
       d2[1] = w[1];
       d2[2] = w[2];
+      if (mirror) {   // the image's force R w
+        double* d3 = zs + 3LL * spos[mirror + off + v];
+        d3[0] = w[0];
+        d3[1] = -w[1];
+        d3[2] = w[2];
+      }
     }
   }
   if (!yV) return;
@@ -197,7 +204,8 @@ __global__ __launch_bounds__(256) void k_precond_mfma(BodyTables B, const double
 __global__ __launch_bounds__(64) void k_precond(BodyTables B, const double* __restrict__ q,
                                                 const double* __restrict__ x, double* __restrict__ z,
                                                 double* __restrict__ yV, const int* __restrict__ spos,
-                                                double* __restrict__ zs, const int* __restrict__ skip) {
+                                                double* __restrict__ zs, const int* __restrict__ skip,
+                                                int mirror) {
   if (skip && *skip) return;
   extern __shared__ double sh[];
   const int p = blockIdx.x;
@@ -240,6 +248,12 @@ __global__ __launch_bounds__(64) void k_precond(BodyTables B, const double* __re
       d2[0] = w[0];
       d2[1] = w[1];
       d2[2] = w[2];
+      if (mirror) {   // the image's force R w
+        double* d3 = zs + 3LL * spos[mirror + off + k];
+        d3[0] = w[0];
+        d3[1] = -w[1];
+        d3[2] = w[2];
+      }
     }
   }
   if (!yV) return;
@@ -690,6 +704,54 @@ __global__ void k_check_state(const double* __restrict__ Y, const double* __rest
   if (!(fabs(nrm - 1.0) <= qtol)) atomicMax(flag + 1, 1);
 }
 
+// Slip channel: rs = [r; sigma(r)], the image of blob i at (x, L1 - y, z).
+__global__ void k_mirror_positions(const double* __restrict__ r, int M, double L1, double* __restrict__ rs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const double x = r[3LL * i], y = r[3LL * i + 1], z = r[3LL * i + 2];
+  rs[3LL * i] = x;
+  rs[3LL * i + 1] = y;
+  rs[3LL * i + 2] = z;
+  rs[3LL * (M + i)] = x;
+  rs[3LL * (M + i) + 1] = L1 - y;
+  rs[3LL * (M + i) + 2] = z;
+}
+
+__global__ void k_sort_forces(const double* __restrict__ lam, const int* __restrict__ spos, int M, int mirror,
+                              double* __restrict__ zs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const double l0 = lam[3LL * i], l1 = lam[3LL * i + 1], l2 = lam[3LL * i + 2];
+  double* d = zs + 3LL * spos[i];
+  d[0] = l0;
+  d[1] = l1;
+  d[2] = l2;
+  if (mirror) {
+    double* e = zs + 3LL * spos[mirror + i];
+    e[0] = l0;
+    e[1] = -l1;
+    e[2] = l2;
+  }
+}
+
+// Harmonic blob-wall repulsion (Sec. 6.3), y component of each blob force.
+__global__ void k_wall_forces(const double* __restrict__ r, int M, double H, double k, double b,
+                              double* __restrict__ f, int add) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const double y = r[3LL * i + 1];
+  double fy = 0.0;
+  if (y < b) fy += k * (b - y);
+  if (H - y < b) fy -= k * (b - (H - y));
+  if (add) {
+    f[3LL * i + 1] += fy;
+  } else {
+    f[3LL * i] = 0.0;
+    f[3LL * i + 1] = fy;
+    f[3LL * i + 2] = 0.0;
+  }
+}
+
 }  // namespace
 
 int check_state(const double* Y, const double* q, int N, double qtol, int* flag, hipStream_t s) {
@@ -705,14 +767,32 @@ int blob_positions(const BodyTables& b, const double* Y, const double* q, double
 }
 
 int precond_apply(const BodyTables& b, const double* q, const double* x, double* z, double* yV, const int* spos,
-                  double* zs, int maxdim, hipStream_t s, const int* skip) {
+                  double* zs, int maxdim, hipStream_t s, const int* skip, int mirror) {
   if (b.mfma && maxdim <= PREC_MFMA_MAXDIM) {
-    hipLaunchKernelGGL(k_precond_mfma, dim3(b.n_groups), dim3(256), 0, s, b, q, x, z, yV, spos, zs, skip);
+    hipLaunchKernelGGL(k_precond_mfma, dim3(b.n_groups), dim3(256), 0, s, b, q, x, z, yV, spos, zs, skip, mirror);
     return check_launch("k_precond_mfma");
   }
   const size_t shm = (2 * (size_t)maxdim + 8) * sizeof(double);
-  hipLaunchKernelGGL(k_precond, dim3(b.N), dim3(64), shm, s, b, q, x, z, yV, spos, zs, skip);
+  hipLaunchKernelGGL(k_precond, dim3(b.N), dim3(64), shm, s, b, q, x, z, yV, spos, zs, skip, mirror);
   return check_launch("k_precond");
+}
+
+int mirror_positions(const double* r, int M, double L1, double* rs, hipStream_t s) {
+  if (M <= 0) return GDC_OK;
+  hipLaunchKernelGGL(k_mirror_positions, dim3(nblk(M)), dim3(NT), 0, s, r, M, L1, rs);
+  return check_launch("k_mirror_positions");
+}
+
+int sort_forces(const double* lam, const int* spos, int M, int mirror, double* zs, hipStream_t s) {
+  if (M <= 0) return GDC_OK;
+  hipLaunchKernelGGL(k_sort_forces, dim3(nblk(M)), dim3(NT), 0, s, lam, spos, M, mirror, zs);
+  return check_launch("k_sort_forces");
+}
+
+int wall_forces(const double* r, int M, double H, double k, double b, double* fblob, bool add, hipStream_t s) {
+  if (M <= 0) return GDC_OK;
+  hipLaunchKernelGGL(k_wall_forces, dim3(nblk(M)), dim3(NT), 0, s, r, M, H, k, b, fblob, add ? 1 : 0);
+  return check_launch("k_wall_forces");
 }
 
 int fd_displacements(const BodyTables& b, const double* q, double delta, int mode, uint64_t seed,

@@ -429,15 +429,17 @@ struct ProjParams {
   // noise
   uint64_t seed, step;
   double sdiag, soff;      // sqrt(G var / 2) of diagonal / off-diagonal components
+  int channel;             // slip channel: the stress is given its mirror image in y
 };
 
 __device__ __forceinline__ int signed_index(int j, int n) { return j < n / 2 ? j : j - n; }
 
-// Velocity spectrum of the stress noise at stored mode (j0, j1, j2), already
-// projected and scaled by 1/(eta |k|^2 G).  Returns false for removed modes.
-__device__ bool noise_mode(const ProjParams& P, int j0, int j1, int j2, double ur[3], double ui[3]) {
+// The stress spectrum W(k) at stored mode (j0, j1, j2) (not a removed one):
+// Philox normals of the canonical member of the mode's +/-k pair (the
+// conjugate on the k2 = 0 plane when the mode is not canonical), scaled;
+// components xx, yy, zz, xy, xz, yz.
+__device__ __forceinline__ void stress_mode(const ProjParams& P, int j0, int j1, int j2, double wr[6], double wi[6]) {
   const int n0 = P.n0, n1 = P.n1;
-  if (j0 == n0 / 2 || j1 == n1 / 2 || (j0 == 0 && j1 == 0 && j2 == 0)) return false;
   const int m0 = signed_index(j0, n0), m1 = signed_index(j1, n1);
   int c0 = j0, c1 = j1;
   bool conj = false;
@@ -450,13 +452,37 @@ __device__ bool noise_mode(const ProjParams& P, int j0, int j1, int j2, double u
   double z[12];
 #pragma unroll
   for (int call = 0; call < 3; ++call) four_normals(P.seed, idx, (uint32_t)call, P.step, z + 4 * call);
-  // W components xx, yy, zz, xy, xz, yz
-  double wr[6], wi[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
     const double sc = c < 3 ? P.sdiag : P.soff;
     wr[c] = sc * z[2 * c];
     wi[c] = conj ? -sc * z[2 * c + 1] : sc * z[2 * c + 1];
+  }
+}
+
+// Velocity spectrum of the stress noise at stored mode (j0, j1, j2), already
+// projected and scaled by 1/(eta |k|^2 G).  Returns false for removed modes.
+// In the slip channel the stress is W'(k) = (W(k) + R W(k') R) / sqrt(2),
+// k' = (k0, -k1, k2) the mirror mode and R W R the stress with its xy and yz
+// components negated: the Fourier form of adding, in real space, the
+// reflection of the stress about the walls (Sec. 6.3), which keeps the
+// velocity mirror-symmetric with Cov(J u) = (2 kT/dt) M of the channel.
+__device__ bool noise_mode(const ProjParams& P, int j0, int j1, int j2, double ur[3], double ui[3]) {
+  const int n0 = P.n0, n1 = P.n1;
+  if (j0 == n0 / 2 || j1 == n1 / 2 || (j0 == 0 && j1 == 0 && j2 == 0)) return false;
+  const int m0 = signed_index(j0, n0), m1 = signed_index(j1, n1);
+  double wr[6], wi[6];
+  stress_mode(P, j0, j1, j2, wr, wi);
+  if (P.channel) {
+    double vr[6], vi[6];
+    stress_mode(P, j0, (n1 - j1) % n1, j2, vr, vi);
+    constexpr double h = 0.70710678118654752440;   // 1/sqrt(2)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double sg = (c == 3 || c == 5) ? -1.0 : 1.0;
+      wr[c] = (wr[c] + sg * vr[c]) * h;
+      wi[c] = (wi[c] + sg * vi[c]) * h;
+    }
   }
   const double k[3] = {P.kf0 * m0, P.kf1 * m1, P.kf2 * j2};
   // g_a = i sum_b k_b W_ab
@@ -1013,6 +1039,7 @@ int fluct_field(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, 
   const double base = kT * g.eta / (g.dV * dt);
   P.sdiag = std::sqrt((double)g.G * 4.0 * base / 2.0);
   P.soff = std::sqrt((double)g.G * 2.0 * base / 2.0);
+  P.channel = g.channel;
   if (plane_path<R>(g)) {
     GDC_TRY((launch_proj_plane<R, true>(n0, X, tw[0], P, f.proj_plane, s, nullptr)));
     return launch_plane<R>(true, n1, X, real, tw[1], tw[2], n0, g.tiled, f.plane_inv, s, nullptr);

@@ -153,6 +153,10 @@ struct GridGeom {
   // contiguously as [i0 % 8][i1 % 8][i2 % 32].  A spreading workgroup then
   // writes its tile as one contiguous block.
   int tiled;
+  // Slip channel (Sec. 6.3): walls at y = 0 and y = L1/2, kept by images in
+  // the upper half of the box; spreading then also carries the M image blobs
+  // (numbered M .. 2M - 1), and the stress noise is mirrored.
+  int channel;
   FftShape fft;       // host side: launch shapes of the transform passes
 };
 
@@ -294,8 +298,20 @@ constexpr int PREC_GROUP = 4;
 // given, the body rows of the saddle operator at z: yV = -K^T z_lam - Pi z_V.
 // When zs is given, z_lam is also written in the spreading order:
 // zs[3 spos[i] + c] = z_lam[3 i + c].
+// With mirror = M (slip channel), blob i's image (spreading blob M + i) also
+// gets its force R z_lam in the spreading order: zs[3 spos[M + i] + c].
 int precond_apply(const BodyTables& b, const double* q, const double* x, double* z, double* yV,
-                  const int* spos, double* zs, int maxdim, hipStream_t s, const int* skip = nullptr);
+                  const int* spos, double* zs, int maxdim, hipStream_t s, const int* skip = nullptr,
+                  int mirror = 0);
+// Slip channel: rs = [r; sigma(r)] (2M x 3), sigma(x, y, z) = (x, L1 - y, z).
+int mirror_positions(const double* r, int M, double L1, double* rs, hipStream_t s);
+// Blob forces lam in the spreading order of the last tile sort: zs[3 spos[i] +
+// c] = lam[3 i + c] and, with mirror = M, the images' R lam at spos[M + i].
+int sort_forces(const double* lam, const int* spos, int M, int mirror, double* zs, hipStream_t s);
+// Harmonic blob-wall repulsion of the slip channel (Sec. 6.3) on the y
+// component of fblob (M x 3): k (b - y) for y < b, -k (b - (H - y)) for
+// H - y < b; add: add to fblob (else fblob is overwritten).
+int wall_forces(const double* r, int M, double H, double k, double b, double* fblob, bool add, hipStream_t s);
 // FD / RFD perturbations: displacements of each blob (M x NP x 3) and, for
 // RFD, the Philox normals of each body (N x 6).
 int fd_displacements(const BodyTables& b, const double* q, double delta, int mode,

@@ -7,10 +7,10 @@ from oracle import fcm, gdc, rigid
 
 
 def oracle_config(w: wl.Workload, kT=None, dt=None, divergence="fd", fd_delta=1e-6):
-    p = fcm.FcmParams(fcm.Grid(w.L, w.n), w.eta, w.sigma, w.rc)
+    p = fcm.FcmParams(fcm.Grid(w.L, w.n), w.eta, w.sigma, w.rc, channel=w.channel)
     s = rigid.Suspension(p, rigid.Bodies(w.shapes, w.body_shape), w.a)
     F = gdc.Forces(w.steric_k, w.steric_cutoff, np.asarray(w.const_force, dtype=np.float64), w.shear_rate,
-                   w.sine_force)
+                   w.sine_force, w.wall_k, w.wall_cutoff)
     return gdc.Config(s, w.kT if kT is None else kT, w.dt if dt is None else dt, w.noise_seed, F,
                       fd_delta=fd_delta, divergence=divergence)
 

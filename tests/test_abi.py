@@ -48,7 +48,7 @@ def test_python_binding_marshals_config_layout():
     import paper_2106_00449_amd as g
     c = g._Config
     assert c.L.offset == 0 and c.n.offset == 24
-    assert ctypes.sizeof(g._Forces) == 8 * 10
+    assert ctypes.sizeof(g._Forces) == 8 * 12
     off = c.forces.offset
     assert off % 8 == 0 and c.device.offset == off + ctypes.sizeof(g._Forces)
 

@@ -84,6 +84,9 @@ class Workload:
     const_force: tuple = (0.0, 0.0, 0.0, 0.0, 0.0, 0.0)
     shear_rate: float = 0.0
     sine_force: float = 0.0          # f0 of the rheology forcing f0 sin(2 pi y / L_y) e_x
+    channel: bool = False            # slip walls at y = 0 and y = L_y/2 (images in the upper half)
+    wall_k: float = 0.0              # blob-wall harmonic repulsion of the channel
+    wall_cutoff: float = 0.0
     nematic_cap_deg: float = 0.0     # 0: orientations uniform on S^3
     placement: str = "sequential"    # or "batch" (see initial_state)
     extra: dict = field(default_factory=dict)
@@ -382,6 +385,7 @@ def library_kwargs(w: Workload, **over):
     kw = dict(L=w.L, n=w.n, shapes=w.shapes, body_shape=w.body_shape, a=w.a, sigma=w.sigma,
               trunc=w.rc, eta=w.eta, kT=w.kT, dt=w.dt, precision=w.precision, seed=w.noise_seed,
               steric_k=w.steric_k, steric_cutoff=w.steric_cutoff, const_force=w.const_force,
-              shear_rate=w.shear_rate, sine_force=w.sine_force)
+              shear_rate=w.shear_rate, sine_force=w.sine_force, channel=w.channel, wall_k=w.wall_k,
+              wall_cutoff=w.wall_cutoff)
     kw.update(over)
     return kw
