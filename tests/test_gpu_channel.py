@@ -97,7 +97,7 @@ def test_channel_blob_and_body_mobility(lib, prec, case):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_channel_step_with_wall_and_pair_forces(lib, prec):
-    w = _channel_case("chstep", (24, 32, 24), (20.0, 28.0, 20.0), [wl.rod(4), wl.boomerang(), wl.tetrahedron()],
+    w = _channel_case("chstep", (20.0, 28.0, 20.0), (24, 32, 24), [wl.rod(4), wl.boomerang(), wl.tetrahedron()],
                       9, prec, 45, dt=0.005, steric_k=40.0 / 2.2, steric_cutoff=2.2,
                       const_force=(0.2, -0.5, 0.3, 0.0, 0.05, 0.0))
     w.wall_k, w.wall_cutoff = 40.0 / 2.2, 2.2
