@@ -49,7 +49,7 @@ struct Tiles {
   // Lines per workgroup in passes A, B, B', A' (128-byte segments in the
   // transposed accesses) and per component in pass C.
   static constexpr int TL = sizeof(R) == 4 ? 16 : 8;
-  static constexpr int TC = sizeof(R) == 4 ? 4 : 2;
+  static constexpr int TC = sizeof(R) == 4 ? 8 : 2;
 };
 
 constexpr int next_radix(int n) {
