@@ -72,6 +72,22 @@ DOMINANT = {
 BYTES_PER_POINT = 12
 BYTES_PER_BLOB = 56
 
+
+def working_launches(each_ms):
+    """Split probed launches into those that did the work and those that
+    returned at the solver's done flag: the solver queues GMRES iteration
+    k + 1 before it has read the convergence test of iteration k, so one
+    launch per solve reads the flag and exits (a few microseconds against
+    hundreds).  A launch is counted as working if it took at least a tenth
+    of the 90th-percentile duration.  Returns (count, total ms, early-exit
+    count)."""
+    import numpy as np
+    d = np.asarray(each_ms, dtype=np.float64)
+    if d.size == 0:
+        return 0, 0.0, 0
+    full = d >= 0.1 * np.percentile(d, 90)
+    return int(full.sum()), float(d[full].sum()), int((~full).sum())
+
 # HBM traffic of each workload's dominant kernel per launch from two
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per
 # dispatch, averaged over the dispatches of the instantiation the timed
@@ -294,14 +310,15 @@ def kernel_bandwidth(g, s, Y, q, w, cov):
     for fam, (kname, nbytes) in fams.items():
         g.probe_kernel(fam)
         s.step(Y, q, 4)
-        ms, n = g.probe_read()
+        _, _, each = g.probe_read(each=True)
         g.probe_kernel(None)
+        n, ms, early = working_launches(each)
         if n == 0:
             continue
         avg = ms * 1e-3 / n
         gbs = nbytes / avg / 1e9
-        out[fam] = {"kernel": kname, "launches": n, "avg_us": avg * 1e6, "algorithmic_bytes": nbytes,
-                    "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+        out[fam] = {"kernel": kname, "launches": n, "early_exits": early, "avg_us": avg * 1e6,
+                    "algorithmic_bytes": nbytes, "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
     return out
 
 
@@ -321,15 +338,17 @@ def time_workload(g, wl, name, w, Y0, q0, tol, stream, steps, warmup):
     total, lat_ms, its, st = timed_steps(g, s, Y, q, steps, 0)
     if len(lat_ms) == 0:   # one timed step: its latency is the call's time
         lat_ms = np.array([total * 1e3])
-    k_ms, k_launches = g.probe_read()
+    _, _, each = g.probe_read(each=True)
     g.probe_kernel(None)
+    k_launches, k_ms, k_early = working_launches(each)
     G = int(np.prod(w.n))
     alg_bytes = nbytes(G, w.M)
     avg_s = k_ms * 1e-3 / max(k_launches, 1)
     achieved = alg_bytes / avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES.get(name),
-                "kernel": kname, "launches": k_launches, "avg_us": avg_s * 1e6, "algorithmic_bytes": alg_bytes}
+                "kernel": kname, "launches": k_launches, "early_exits": k_early, "avg_us": avg_s * 1e6,
+                "algorithmic_bytes": alg_bytes}
     # the whole step against the byte model of the method's grid traffic:
     # G (60 + 72 k) bytes per FP32 step with k operator applies (GMRES
     # iterations), each 3D transform counted once read and once written
@@ -503,6 +522,8 @@ def main():
                     help="with --only-headline, still measure the per-kernel bandwidth table")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device copy first (counter calibration for profiling)")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch every GMRES iteration kernel by kernel (no HIP graph replay)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -536,6 +557,7 @@ def main():
     import torch
     import paper_2106_00449_amd as g
 
+    g.GRAPHS_DEFAULT = not args.no_graphs
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -573,7 +595,8 @@ def main():
                    "nu_mean": head["nu_mean"], "nu_std": head["nu_std"], "nu_min": head["nu_min"],
                    "nu_max": head["nu_max"], "nu_nonpositive_steps": head["nu_nonpositive"],
                    "interp_grid_coverage": cov, "fft_passes": head["fft_passes"],
-                   "fft_workgroup_sizes": head["fft_workgroup_sizes"]},
+                   "fft_workgroup_sizes": head["fft_workgroup_sizes"],
+                   "gmres_iteration_graphs": g.GRAPHS_DEFAULT},
         "roofline": head["roofline"],
         "step_roofline": head["step_roofline"],
         "kernels": kernels,

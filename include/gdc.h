@@ -259,6 +259,16 @@ enum { GDC_FFT_PASSES = 8 };
 int gdc_get_launch_config(const gdc_handle* h, int* threads, int n);
 int gdc_set_launch_config(gdc_handle* h, const int* threads, int n);
 
+/* Launch mode of the GMRES iterations (the step-5 solve of Sec. 3): with
+ * graphs on (the default) the launches of each Krylov column's iteration
+ * are captured once into a HIP graph and replayed, one launch instead of
+ * about ten, which takes most of the host's launch work off a step; off,
+ * every kernel is launched on its own.  Results are the same bit for bit.
+ * While gdc_probe_kernel watches a family, kernels launch on their own so
+ * the probe can stamp them.  Errors: GDC_EINVAL (NULL, step in flight). */
+int gdc_set_graphs(gdc_handle* h, int on);
+int gdc_get_graphs(const gdc_handle* h, int* on);
+
 /* Internal step counter (checkpoint / resume: with the same state and
  * counter a resumed run repeats an uninterrupted one exactly). */
 int gdc_get_step(const gdc_handle* h, uint64_t* step);
@@ -305,9 +315,14 @@ int gdc_philox_normals_noalloc(gdc_handle* h, uint64_t seed, uint32_t c1, uint64
  * "fft_plane_inv", "fft_noise"; NULL or "" switches probing off; at most
  * 8192 launches are kept).  gdc_probe_read: total elapsed milliseconds and number
  * of probed launches since the last read (waits for the last stop event),
- * then clears the record. */
+ * and, when each_ms is not NULL, the duration of each launch in launch
+ * order (host array; the first `capacity` are written), then clears the
+ * record.  Launches of a GMRES iteration queued ahead of the convergence
+ * test return at the solver's done flag and take microseconds: the
+ * per-launch durations let a caller tell them from launches that did the
+ * work. */
 int gdc_probe_kernel(const char* family);
-int gdc_probe_read(double* total_ms, long long* launches);
+int gdc_probe_read(double* total_ms, long long* launches, float* each_ms, long long capacity);
 
 #ifdef __cplusplus
 }

@@ -90,7 +90,8 @@ def _load():
     L.gdc_philox_normals.argtypes = [P, U64, U32, U64, U32, I, D]
     L.gdc_philox_normals_noalloc.argtypes = [P, U64, U32, U64, U32, I, D]
     L.gdc_probe_kernel.argtypes = [ctypes.c_char_p]
-    L.gdc_probe_read.argtypes = [D, ctypes.POINTER(ctypes.c_longlong)]
+    L.gdc_probe_read.argtypes = [D, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_float),
+                                 ctypes.c_longlong]
     L.gdc_set_state.argtypes = [P, P, P, I]
     L.gdc_get_state.argtypes = [P, P, P, I]
     L.gdc_batch_step.argtypes = [ctypes.POINTER(P), I, ctypes.POINTER(I), I, ctypes.c_double,
@@ -99,13 +100,15 @@ def _load():
     L.gdc_footprint.argtypes = [ctypes.POINTER(_Config), ctypes.POINTER(ctypes.c_size_t)]
     L.gdc_device_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
     L.gdc_get_launch_config.argtypes = [P, ctypes.POINTER(I), I]
+    L.gdc_set_graphs.argtypes = [P, I]
+    L.gdc_get_graphs.argtypes = [P, ctypes.POINTER(I)]
     L.gdc_set_launch_config.argtypes = [P, ctypes.POINTER(I), I]
     for name in ["gdc_init", "gdc_mobility_apply", "gdc_step", "gdc_get_step", "gdc_set_step",
                  "gdc_fluct_velocity", "gdc_predictor", "gdc_philox_normals", "gdc_philox_normals_noalloc",
                  "gdc_probe_kernel",
                  "gdc_probe_read", "gdc_set_state", "gdc_get_state", "gdc_batch_step", "gdc_step_log",
                  "gdc_footprint", "gdc_device_bytes",
-                 "gdc_get_launch_config", "gdc_set_launch_config"]:
+                 "gdc_get_launch_config", "gdc_set_launch_config", "gdc_set_graphs", "gdc_get_graphs"]:
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -159,12 +162,19 @@ def probe_kernel(family):
     _check(lib.gdc_probe_kernel(family.encode() if family else None))
 
 
-def probe_read():
-    """(total ms, launches) of the probed family since the last read."""
+PROBE_CAPACITY = 8192
+
+
+def probe_read(each=False):
+    """(total ms, launches) of the probed family since the last read; with
+    each=True also the per-launch durations (ms, launch order)."""
     ms = ctypes.c_double()
     n = ctypes.c_longlong()
-    _check(lib.gdc_probe_read(ctypes.byref(ms), ctypes.byref(n)))
-    return ms.value, n.value
+    buf = (ctypes.c_float * PROBE_CAPACITY)() if each else None
+    _check(lib.gdc_probe_read(ctypes.byref(ms), ctypes.byref(n), buf, PROBE_CAPACITY if each else 0))
+    if not each:
+        return ms.value, n.value
+    return ms.value, n.value, np.array(buf[:min(n.value, PROBE_CAPACITY)], dtype=np.float64)
 
 
 def _make_config(L, n, shapes, body_shape, *, a=1.0, sigma=0.0, trunc=0.0,
@@ -245,13 +255,19 @@ def batch_step(susps, steps, until="all", max_ms=0.0):
     return [int(x) for x in st_in[:nh]], out, rc
 
 
+# whether new suspensions replay GMRES iterations from HIP graphs
+GRAPHS_DEFAULT = True
+
+
 class Suspension:
     """A suspension of rigid multiblob bodies in a periodic box on one GPU.
 
     shapes: list of (n_b, 3) body-frame blob offsets; body_shape: (N,) ints.
-    Remaining keyword arguments follow gdc_config (include/gdc.h)."""
+    graphs: replay GMRES iterations from captured HIP graphs (None: the
+    module's GRAPHS_DEFAULT).  Remaining keyword arguments follow gdc_config
+    (include/gdc.h)."""
 
-    def __init__(self, L, n, shapes, body_shape, **kw):
+    def __init__(self, L, n, shapes, body_shape, graphs=None, **kw):
         c, keep = _make_config(L, n, shapes, body_shape, **kw)
         self._keep = keep
         self._cfg = c
@@ -262,6 +278,9 @@ class Suspension:
         h = ctypes.c_void_p()
         _check(lib.gdc_init(ctypes.byref(c), ctypes.byref(h)))
         self._h = h
+        on = GRAPHS_DEFAULT if graphs is None else graphs
+        if not on:
+            self.graphs = False
 
     def close(self):
         if getattr(self, "_h", None):
@@ -362,6 +381,17 @@ class Suspension:
         b = ctypes.c_size_t()
         _check(lib.gdc_device_bytes(self._h, ctypes.byref(b)))
         return int(b.value)
+
+    @property
+    def graphs(self):
+        """Whether GMRES iterations are replayed from captured HIP graphs."""
+        on = ctypes.c_int()
+        _check(lib.gdc_get_graphs(self._h, ctypes.byref(on)))
+        return bool(on.value)
+
+    @graphs.setter
+    def graphs(self, on):
+        _check(lib.gdc_set_graphs(self._h, 1 if on else 0))
 
     @property
     def step_counter(self):

@@ -87,6 +87,8 @@ ProbeEvents probe_claim(const char* family) {
   return pe;
 }
 
+bool probe_active() { return !g_probe.family.empty(); }
+
 int check_launch(const char* what) {
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
@@ -399,6 +401,17 @@ struct gdc_handle {
   hipEvent_t gm_ev[2] = {nullptr, nullptr};
   hipEvent_t step_ev[2] = {nullptr, nullptr};   // end of a step's update and readback, per slot
 
+  // One HIP graph per Krylov column k of a GMRES iteration (preconditioner,
+  // mobility apply, Arnoldi), captured the first time column k runs with a
+  // given set of configuration arrays and replayed after; graphs = false
+  // launches every kernel on its own.
+  struct IterGraph {
+    hipGraphExec_t exec = nullptr;
+    const double *Y = nullptr, *q = nullptr, *r = nullptr;
+  };
+  std::vector<IterGraph> iter_graph;
+  bool graphs = true;
+
   bool dry = false;               // footprint query: count device bytes, touch no device
   size_t dev_bytes = 0;           // device memory held by the handle
   bool has_state = false;         // Y, q hold a state (gdc_set_state or gdc_step)
@@ -418,6 +431,8 @@ struct gdc_handle {
   int done_n = 0;
 
   ~gdc_handle() {
+    for (IterGraph& g : iter_graph)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
     for (void* p : allocs) (void)hipFree(p);
     if (hhost) (void)hipHostFree(hhost);
     if (gm_host) (void)hipHostFree(gm_host);
@@ -580,6 +595,60 @@ int poll_status(gdc_handle* h, int slot, bool block, bool& ready, GmStatus& st) 
   return GDC_OK;
 }
 
+// Queues GMRES iteration k of the current cycle: z = P^-1 V_k, w = A z (the
+// mobility apply), and the Arnoldi step that writes V_{k+1}, the Hessenberg
+// column and the status slot (k + 1) & 1.  With graphs on (and no kernel
+// probe active) the launches of column k are captured once into a HIP graph
+// and replayed on later cycles and steps: one launch instead of about ten.
+// Every pointer the iteration uses is fixed for the handle except the
+// configuration arrays (Y, q, r), which key the graph.
+template <typename R>
+int queue_iteration(gdc_handle* h, int k) {
+  SolveRun& sv = h->sv;
+  const long long n = h->nx;
+  const int m = h->restart;
+  hipStream_t s = h->stream;
+  double* Vk = h->Vb + n * k;
+  double* Vk1 = h->Vb + n * (k + 1);
+  const int slot = (k + 1) & 1;
+  auto enqueue = [&]() -> int {
+    GDC_TRY(apply_saddle_precond<R>(h, sv.Y, sv.q, sv.r, Vk, h->z, h->w, &h->gm->done));
+    return arnoldi_orthogonalise(h->w, h->Vb, n, k + 1, n, h->partial, h->partial2, Vk1, h->hdev,
+                                 h->hdev + HCOLS, s, &h->gm->done, h->gm, m, h->gm_host_dev + 32 * slot);
+  };
+  if (!h->graphs || probe_active()) return enqueue();
+  if ((int)h->iter_graph.size() < m) h->iter_graph.resize(m);
+  gdc_handle::IterGraph& ig = h->iter_graph[k];
+  if (!ig.exec || ig.Y != sv.Y || ig.q != sv.q || ig.r != sv.r) {
+    if (ig.exec) {
+      (void)hipGraphExecDestroy(ig.exec);
+      ig.exec = nullptr;
+    }
+    GDC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    const int rc = enqueue();
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &graph);   // always leave capture mode
+    if (rc != GDC_OK || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      if (rc != GDC_OK) return rc;
+      set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      return GDC_EDEVICE;
+    }
+    const hipError_t e2 = hipGraphInstantiate(&ig.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) {
+      ig.exec = nullptr;
+      set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+      return GDC_EDEVICE;
+    }
+    ig.Y = sv.Y;
+    ig.q = sv.q;
+    ig.r = sv.r;
+  }
+  GDC_HIP(hipGraphLaunch(ig.exec, s));
+  return GDC_OK;
+}
+
 // Right-preconditioned restarted GMRES (Saad & Schultz) on the saddle system
 // with classical Gram-Schmidt and one reorthogonalisation, zero initial
 // guess.  Solution (x = P^-1 u) written to h->sol.
@@ -641,12 +710,8 @@ int solve_advance(gdc_handle* h, bool block, int& adv) {
       const int k = sv.k;
       bool enq = false;
       if (!sv.queued) {
-        double* Vk = h->Vb + n * k;
-        double* Vk1 = h->Vb + n * (k + 1);
-        GDC_TRY(apply_saddle_precond<R>(h, sv.Y, sv.q, sv.r, Vk, h->z, h->w, &h->gm->done));
         const int slot = (k + 1) & 1;
-        GDC_TRY(arnoldi_orthogonalise(h->w, h->Vb, n, k + 1, n, h->partial, h->partial2, Vk1, h->hdev,
-                                      h->hdev + HCOLS, s, &h->gm->done, h->gm, m, h->gm_host_dev + 32 * slot));
+        GDC_TRY(queue_iteration<R>(h, k));
         GDC_HIP(hipEventRecord(h->gm_ev[slot], s));
         sv.queued = enq = true;
       }
@@ -1685,9 +1750,9 @@ int gdc_probe_kernel(const char* family) {
   return GDC_OK;
 }
 
-int gdc_probe_read(double* total_ms, long long* launches) {
-  if (!total_ms || !launches) {
-    set_error("outputs are required");
+int gdc_probe_read(double* total_ms, long long* launches, float* each_ms, long long capacity) {
+  if (!total_ms || !launches || (each_ms && capacity < 0)) {
+    set_error("outputs are required (and capacity >= 0 with each_ms)");
     return GDC_EINVAL;
   }
   double tot = 0.0;
@@ -1696,6 +1761,7 @@ int gdc_probe_read(double* total_ms, long long* launches) {
     GDC_HIP(hipEventSynchronize(g_probe.ev[k + 1]));
     float ms = 0.f;
     GDC_HIP(hipEventElapsedTime(&ms, g_probe.ev[k], g_probe.ev[k + 1]));
+    if (each_ms && n < capacity) each_ms[n] = ms;
     tot += ms;
     ++n;
   }
@@ -1739,6 +1805,25 @@ int gdc_set_launch_config(gdc_handle* h, const int* threads, int n) {
   f.proj = threads[5];
   f.inv1 = threads[6];
   f.c2r = threads[7];
+  return GDC_OK;
+}
+
+int gdc_set_graphs(gdc_handle* h, int on) {
+  if (!h) {
+    set_error("handle is required");
+    return GDC_EINVAL;
+  }
+  GDC_TRY(require_idle(h));
+  h->graphs = on != 0;
+  return GDC_OK;
+}
+
+int gdc_get_graphs(const gdc_handle* h, int* on) {
+  if (!h || !on) {
+    set_error("handle and output are required");
+    return GDC_EINVAL;
+  }
+  *on = h->graphs ? 1 : 0;
   return GDC_OK;
 }
 

@@ -831,7 +831,7 @@ int launch_r2c(int n2, const R* in, Cx<R>* X, const Cx<R>* tw, int n0, int n1, i
   if (!nth_ok(nth, false)) return GDC_EINVAL;
   dim3 grid((n1 + Tiles<R>::TL - 1) / Tiles<R>::TL, n0, 3);
   const ProbeEvents pe = probe_claim("fft_r2c");
-#define L_(N, T) hipExtLaunchKernelGGL((k_r2c_axis2<R, N, T>), grid, dim3(T), 0, s, pe.start, pe.stop, 0, in, X, tw, n0, n1, tiled, skip)
+#define L_(N, T) GDC_LAUNCH_PROBED((k_r2c_axis2<R, N, T>), grid, dim3(T), 0, s, pe, in, X, tw, n0, n1, tiled, skip)
   switch (n2) {
 #define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
     GDC_FFT_SIZES(X_)
@@ -848,7 +848,7 @@ int launch_fwd1(int n1, const Cx<R>* X, Cx<R>* Y, const Cx<R>* tw, int n0, int H
   if (!nth_ok(nth, false)) return GDC_EINVAL;
   dim3 grid((n0 + Tiles<R>::TL - 1) / Tiles<R>::TL, H, 3);
   const ProbeEvents pe = probe_claim("fft_fwd1");
-#define L_(N, T) hipExtLaunchKernelGGL((k_fwd_axis1<R, N, T>), grid, dim3(T), 0, s, pe.start, pe.stop, 0, X, Y, tw, n0, H, skip)
+#define L_(N, T) GDC_LAUNCH_PROBED((k_fwd_axis1<R, N, T>), grid, dim3(T), 0, s, pe, X, Y, tw, n0, H, skip)
   switch (n1) {
 #define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
     GDC_FFT_SIZES(X_)
@@ -865,7 +865,7 @@ int launch_inv1(int n1, const Cx<R>* Y, Cx<R>* X, const Cx<R>* tw, int n0, int H
   if (!nth_ok(nth, false)) return GDC_EINVAL;
   dim3 grid((n0 + Tiles<R>::TL - 1) / Tiles<R>::TL, H, 3);
   const ProbeEvents pe = probe_claim("fft_inv1");
-#define L_(N, T) hipExtLaunchKernelGGL((k_inv_axis1<R, N, T>), grid, dim3(T), 0, s, pe.start, pe.stop, 0, Y, X, tw, n0, H, skip)
+#define L_(N, T) GDC_LAUNCH_PROBED((k_inv_axis1<R, N, T>), grid, dim3(T), 0, s, pe, Y, X, tw, n0, H, skip)
   switch (n1) {
 #define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
     GDC_FFT_SIZES(X_)
@@ -882,7 +882,7 @@ int launch_c2r(int n2, const Cx<R>* X, R* out, const Cx<R>* tw, int n0, int n1, 
   if (!nth_ok(nth, false)) return GDC_EINVAL;
   dim3 grid((n1 + Tiles<R>::TL - 1) / Tiles<R>::TL, n0, 3);
   const ProbeEvents pe = probe_claim("fft_c2r");
-#define L_(N, T) hipExtLaunchKernelGGL((k_c2r_axis2<R, N, T>), grid, dim3(T), 0, s, pe.start, pe.stop, 0, X, out, tw, n0, n1, tiled, skip)
+#define L_(N, T) GDC_LAUNCH_PROBED((k_c2r_axis2<R, N, T>), grid, dim3(T), 0, s, pe, X, out, tw, n0, n1, tiled, skip)
   switch (n2) {
 #define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
     GDC_FFT_SIZES(X_)
@@ -898,7 +898,7 @@ int launch_proj(int n0, Cx<R>* Y, const Cx<R>* tw, const ProjParams& P, int nth,
   if (!nth_ok(nth, false)) return GDC_EINVAL;
   dim3 grid((P.n1 + Tiles<R>::TC - 1) / Tiles<R>::TC, P.n2h, 1);
   const ProbeEvents pe = probe_claim(NOISE ? "fft_noise" : "fft_project");
-#define L_(N, T) hipExtLaunchKernelGGL((k_axis0_project<R, N, NOISE, T>), grid, dim3(T), 0, s, pe.start, pe.stop, 0, Y, tw, P, skip)
+#define L_(N, T) GDC_LAUNCH_PROBED((k_axis0_project<R, N, NOISE, T>), grid, dim3(T), 0, s, pe, Y, tw, P, skip)
   switch (n0) {
 #define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
     GDC_FFT_SIZES(X_)
@@ -938,7 +938,7 @@ int launch_plane(bool inverse, int n, const void* in, void* out, const Cx<R>* tw
     return GDC_EINVAL;
   } else {
     if (!inverse) {
-#define L_(N, T) hipExtLaunchKernelGGL((k_plane_fwd<R, N, N, T>), grid, dim3(T), 0, s, pe.start, pe.stop, 0, (const R*)in, (Cx<R>*)out, tw1, tw2, n0, tiled, skip)
+#define L_(N, T) GDC_LAUNCH_PROBED((k_plane_fwd<R, N, N, T>), grid, dim3(T), 0, s, pe, (const R*)in, (Cx<R>*)out, tw1, tw2, n0, tiled, skip)
       switch (n) {
 #define X_(N) case N: if (nth == 1024) L_(N, 1024); else if (nth == 512) L_(N, 512); else L_(N, 256); break;
         GDC_PLANE_SIZES(X_)
@@ -948,7 +948,7 @@ int launch_plane(bool inverse, int n, const void* in, void* out, const Cx<R>* tw
 #undef L_
       return check_launch("k_plane_fwd");
     }
-#define L_(N, T) hipExtLaunchKernelGGL((k_plane_inv<R, N, N, T>), grid, dim3(T), 0, s, pe.start, pe.stop, 0, (const Cx<R>*)in, (R*)out, tw1, tw2, n0, tiled, skip)
+#define L_(N, T) GDC_LAUNCH_PROBED((k_plane_inv<R, N, N, T>), grid, dim3(T), 0, s, pe, (const Cx<R>*)in, (R*)out, tw1, tw2, n0, tiled, skip)
     switch (n) {
 #define X_(N) case N: if (nth == 1024) L_(N, 1024); else if (nth == 512) L_(N, 512); else L_(N, 256); break;
       GDC_PLANE_SIZES(X_)
@@ -970,7 +970,7 @@ int launch_proj_plane(int n0, Cx<R>* Z, const Cx<R>* tw, const ProjParams& P, in
     set_error("plane transforms are FP32 only");
     return GDC_EINVAL;
   } else {
-#define L_(N, T) hipExtLaunchKernelGGL((k_axis0_plane<R, N, NOISE, T>), grid, dim3(T), 0, s, pe.start, pe.stop, 0, Z, tw, P, skip)
+#define L_(N, T) GDC_LAUNCH_PROBED((k_axis0_plane<R, N, NOISE, T>), grid, dim3(T), 0, s, pe, Z, tw, P, skip)
     switch (n0) {
 #define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
       GDC_PLANE_SIZES(X_)

@@ -50,6 +50,19 @@ struct ProbeEvents {
   hipEvent_t start = nullptr, stop = nullptr;
 };
 ProbeEvents probe_claim(const char* family);
+// Whether a kernel family is being probed (launches then stay out of graphs).
+bool probe_active();
+
+// A launch that carries the probe's events when a probe claimed it (the
+// dispatch stamps them: hipExtLaunchKernelGGL), a plain launch otherwise, so
+// that unprobed launches can be captured into a HIP graph.
+#define GDC_LAUNCH_PROBED(kernel, grid, block, shm, stream, pe, ...)                                 \
+  do {                                                                                                \
+    if ((pe).start)                                                                                   \
+      hipExtLaunchKernelGGL(kernel, grid, block, shm, stream, (pe).start, (pe).stop, 0, __VA_ARGS__); \
+    else                                                                                              \
+      hipLaunchKernelGGL(kernel, grid, block, shm, stream, __VA_ARGS__);                              \
+  } while (0)
 
 // ------------------------------------------------------------ complex values
 

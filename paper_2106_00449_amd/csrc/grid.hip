@@ -1143,7 +1143,7 @@ int spread(const GridGeom& g, const TileGeom& t, const void* tabs, const int* or
   // FP64 tables would need 150 registers a lane hoisted: always the lean one
   const bool hoist = t.one_round && sizeof(R) == 4;
 #define GDC_SPREAD_(H, W)                                                                                     \
-  hipExtLaunchKernelGGL((k_spread_tab<R, H, W>), dim3(t.ntiles), dim3(NTS), 0, s, pe.start, pe.stop, 0, g, t, \
+  GDC_LAUNCH_PROBED((k_spread_tab<R, H, W>), dim3(t.ntiles), dim3(NTS), 0, s, pe, g, t, \
                         (const HitTab<R, W>*)tabs, (const int4*)order, lam, lam_sorted, f, skip)
   if (t.wz8) {
     if (hoist) GDC_SPREAD_(true, 8); else GDC_SPREAD_(false, 8);
@@ -1161,7 +1161,7 @@ int interp(const GridGeom& g, const double* r, const R* u, double* v, int M, dou
   if (M <= 0) return GDC_OK;
   RigidTerm K{blob_body, Y, V};
   const ProbeEvents pe = probe_claim("interp");
-  hipExtLaunchKernelGGL((k_interp<R>), dim3(blocks_for(M)), dim3(NT), 0, s, pe.start, pe.stop, 0, g, r, u, v, M, scale, K, skip,
+  GDC_LAUNCH_PROBED((k_interp<R>), dim3(blocks_for(M)), dim3(NT), 0, s, pe, g, r, u, v, M, scale, K, skip,
                      (const SRec*)sorted);
   return check_launch("k_interp");
 }

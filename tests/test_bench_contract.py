@@ -52,3 +52,13 @@ def test_traffic_figures_belong_to_the_measured_kernels():
             continue
         alg = bench.DOMINANT[w][2](grids[w] ** 3, 0)
         assert 0.5 < t / alg < 2.0, (w, t, alg)
+
+
+def test_early_exit_launches_are_not_averaged():
+    # one launch per solve returns at the done flag: it must not lower the
+    # average that the roofline divides the algorithmic bytes by
+    each = [370.0, 5.0, 372.0, 368.0, 5.5, 371.0]
+    n, ms, early = bench.working_launches([x * 1e-3 for x in each])
+    assert (n, early) == (4, 2)
+    assert abs(ms - 1.481) < 1e-12
+    assert bench.working_launches([]) == (0, 0.0, 0)

@@ -194,3 +194,36 @@ def test_every_fft_launch_shape_gives_identical_results(lib, prec, n, L):
     with pytest.raises(lib.GdcError):
         s.launch_config = {"r2c": 1024}
     s.close()
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_graph_replay_equals_eager_launches(lib, k):
+    # GMRES iterations replayed from captured HIP graphs against every kernel
+    # launched on its own: the same results bit for bit over several steps
+    # with restart cycles (restart 4, so every column's graph is replayed
+    # across cycles), eager work between the replays (a body solve at another
+    # configuration re-keys the graphs), and batched stepping
+    w = _mix()[k]
+    Y0, q0 = wl.initial_state(w)
+    F = np.random.default_rng(3).standard_normal((w.N, 6))
+    out = {}
+    for graphs in (False, True):
+        _say("graphs", w.name, graphs)
+        s = lib.Suspension(**wl.library_kwargs(w, gmres_tol=1e-6, gmres_restart=4, gmres_maxit=400))
+        s.graphs = graphs
+        assert s.graphs == graphs
+        Y, q = Y0.copy(), q0.copy()
+        st1 = s.step(Y, q, 3)
+        assert st1["gmres_iterations"] > 4          # more than one restart cycle
+        V = s.mobility_apply("body", Y, q, F, allow_notconv=True)
+        st2 = s.step(Y, q, 2)
+        s.set_state(Y, q)
+        left = [2]
+        while any(left):
+            left, _, rc = lib.batch_step([s], left)
+            assert rc == 0
+        Yb, qb = s.get_state()
+        out[graphs] = (Y, q, V, Yb, qb, st1["gmres_iterations"], st2["nu"], st2["gmres_iterations_mean"])
+        s.close()
+    for a, b in zip(out[False], out[True]):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
