@@ -98,6 +98,36 @@ __device__ __forceinline__ int wrap(int g, int n) {
   return g;
 }
 
+constexpr int QB = 8;   // stencil points along axis 0 per load round
+
+// Loads of one field component through a buffer resource: the component's
+// base and size sit in scalar registers and each load takes a 32-bit byte
+// offset, one register per point for all three components instead of a
+// 64-bit address per load.  (Offsets past the component would read 0; every
+// offset used is a grid index below G.)
+constexpr int BUF_DWORD3 = 0x00020000;   // raw 32-bit loads on gfx9-family parts
+
+template <typename R>
+struct Component;
+template <>
+struct Component<float> {
+  __amdgpu_buffer_rsrc_t rs;
+  __device__ Component(const float* p, long long n)
+      : rs(__builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)(n * 4), BUF_DWORD3)) {}
+  __device__ float operator()(unsigned i) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(i * 4u), 0, 0));
+  }
+};
+template <>
+struct Component<double> {
+  __amdgpu_buffer_rsrc_t rs;
+  __device__ Component(const double* p, long long n)
+      : rs(__builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)(n * 8), BUF_DWORD3)) {}
+  __device__ double operator()(unsigned i) const {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(i * 8u), 0, 0));
+  }
+};
+
 // Stencil walk in columns: lane l owns the (a1, a2) pairs l, l + 64, ... of
 // the P1 x P2 cross-section and loops over a0, so consecutive lanes read
 // consecutive grid points along axis 2 and no division happens in the loop.
@@ -161,7 +191,7 @@ __global__ __launch_bounds__(NT) void k_interp(GridGeom G, const double* __restr
     kvel[2] = Vp[2] + (Vp[3] * rel[1] - Vp[4] * rel[0]);
   }
   const int P0 = G.P[0], P1 = G.P[1], P2 = G.P[2];
-  const long long Gs = G.G;
+  const Component<R> u0(u, G.G), u1(u + G.G, G.G), u2(u + 2 * G.G, G.G);
   const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
   const R wn = R(G.wnorm), i2 = R(G.inv2s2);
   R s0 = 0, s1 = 0, s2 = 0;
@@ -171,29 +201,31 @@ __global__ __launch_bounds__(NT) void k_interp(GridGeom G, const double* __restr
     const double d12 = d1 * d1 + d2 * d2;
     if (d12 > G.rc2) continue;
     const long long col = field_col_off(G.tiled, n2, wrap(B.g[1] + a1, n1), wrap(B.g[2] + a2, n2));
-    // four points of the column per round, all loads issued before use
-    for (int a0 = 0; a0 < P0; a0 += 4) {
-      R wv[4];
-      long long ix[4];
+    // QB points of the column per round, all loads issued before use: with
+    // P0 <= QB (the usual 7 points) a lane has all 3 P0 of its loads in flight
+    // at once, one memory round trip per blob
+    for (int a0 = 0; a0 < P0; a0 += QB) {
+      R wv[QB];
+      unsigned ix[QB];   // index within one component (its byte offset is below 2^31)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < QB; ++q) {
         const int aa = a0 + q;
         const int gg = wrap(B.g[0] + aa, n0);
         const double d0 = B.e[0] + aa * G.dx[0];
         const double dd = d0 * d0 + d12;
         const bool ok = (aa < P0) && (dd <= G.rc2);
         wv[q] = ok ? wn * gexp<R>(-R(dd) * i2) : R(0);
-        ix[q] = field_plane_off(G.tiled, n1, n2, ok ? gg : B.g[0]) + col;
+        ix[q] = (unsigned)(field_plane_off(G.tiled, n1, n2, ok ? gg : B.g[0]) + col);
       }
-      R x0[4], x1[4], x2[4];
+      R x0[QB], x1[QB], x2[QB];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        x0[q] = u[ix[q]];
-        x1[q] = u[Gs + ix[q]];
-        x2[q] = u[2 * Gs + ix[q]];
+      for (int q = 0; q < QB; ++q) {
+        x0[q] = u0(ix[q]);
+        x1[q] = u1(ix[q]);
+        x2[q] = u2(ix[q]);
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < QB; ++q) {
         s0 += wv[q] * x0[q];
         s1 += wv[q] * x1[q];
         s2 += wv[q] * x2[q];

@@ -93,6 +93,9 @@ CASES = [
     # 96^3: the three-pass plane transforms at their largest radix-3 size
     # (FP32) and the five-pass transforms (FP64)
     ("rods96", 96, 96.0, [wl.rod(10)]),
+    # grid spacing 0.375a: a 10-blob rod is longer than the 24 spacings an
+    # averaging cluster may span, so its blobs are averaged in two clusters
+    ("fine64", 64, 24.0, [wl.rod(10), wl.boomerang()]),
 ]
 
 
@@ -100,7 +103,7 @@ CASES = [
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_blob_mobility(lib, prec, case):
     name, n, L, shapes = case
-    nb = {"small8": 3, "dense8": 16, "rods96": 60}.get(name, 12)
+    nb = {"small8": 3, "dense8": 16, "rods96": 60, "fine64": 8}.get(name, 12)
     w = wl.small_case(name, n_bodies=nb, n=n, L=L, shapes=shapes, precision=prec, seed=3)
     Y, q, lam, _ = _rand_blobs(w, 1)
     _say("blob", name, prec, w.M)
