@@ -98,39 +98,49 @@ __device__ __forceinline__ int wrap(int g, int n) {
   return g;
 }
 
-constexpr int QB = 8;   // stencil points along axis 0 per load round
-
 // Loads of one field component through a buffer resource: the component's
 // base and size sit in scalar registers and each load takes a 32-bit byte
-// offset, one register per point for all three components instead of a
-// 64-bit address per load.  (Offsets past the component would read 0; every
-// offset used is a grid index below G.)
-constexpr int BUF_DWORD3 = 0x00020000;   // raw 32-bit loads on gfx9-family parts
+// offset.  chunk(i) returns the 16 bytes at grid index i (CW consecutive
+// points along axis 2; i a multiple of CW), one load instruction for four
+// FP32 or two FP64 values.
+constexpr int BUF_DWORD3 = 0x00020000;   // raw loads on gfx9-family parts
 
 template <typename R>
 struct Component;
 template <>
 struct Component<float> {
+  static constexpr int CW = 4;
   __amdgpu_buffer_rsrc_t rs;
   __device__ Component(const float* p, long long n)
       : rs(__builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)(n * 4), BUF_DWORD3)) {}
-  __device__ float operator()(unsigned i) const {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(i * 4u), 0, 0));
+  __device__ void chunk(unsigned i, float* x) const {
+    const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(i * 4u), 0, 0));
+    x[0] = v.x;
+    x[1] = v.y;
+    x[2] = v.z;
+    x[3] = v.w;
   }
 };
 template <>
 struct Component<double> {
+  static constexpr int CW = 2;
   __amdgpu_buffer_rsrc_t rs;
   __device__ Component(const double* p, long long n)
       : rs(__builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)(n * 8), BUF_DWORD3)) {}
-  __device__ double operator()(unsigned i) const {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(i * 8u), 0, 0));
+  __device__ void chunk(unsigned i, double* x) const {
+    const double2 v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(i * 8u), 0, 0));
+    x[0] = v.x;
+    x[1] = v.y;
   }
 };
 
-// Stencil walk in columns: lane l owns the (a1, a2) pairs l, l + 64, ... of
-// the P1 x P2 cross-section and loops over a0, so consecutive lanes read
-// consecutive grid points along axis 2 and no division happens in the loop.
+// Stencil walk in chunks: the P2 points of each (a0, a1) row of the stencil
+// lie in nck aligned chunks of CW points along axis 2 (the field is
+// contiguous along axis 2 in runs of 32 points, and every grid size is a
+// multiple of 4), and lane tasks are (a0, a1, chunk): one 16-byte load per
+// component and task.  Rows outside the cutoff sphere are skipped.  Loads,
+// not bytes, bound a gather of scattered short runs, so fewer and wider
+// loads are what shortens it.
 
 // A blob's record in the tile-sorted order: the FP64 offsets and grid index
 // (10 bits per axis) of its first stencil point, as blob_base gives them, and
@@ -194,42 +204,36 @@ __global__ __launch_bounds__(NT) void k_interp(GridGeom G, const double* __restr
   const Component<R> u0(u, G.G), u1(u + G.G, G.G), u2(u + 2 * G.G, G.G);
   const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
   const R wn = R(G.wnorm), i2 = R(G.inv2s2);
+  constexpr int CW = Component<R>::CW;
+  const int first2 = B.g[2] & ~(CW - 1);   // aligned chunk holding the first point
+  const int skew = B.g[2] - first2;
+  const int nck = (skew + P2 - 1) / CW + 1;
+  const int per0 = P1 * nck;
   R s0 = 0, s1 = 0, s2 = 0;
-  for (int pr = lane; pr < P1 * P2; pr += 64) {
-    const int a1 = pr / P2, a2 = pr - a1 * P2;
-    const double d1 = B.e[1] + a1 * G.dx[1], d2 = B.e[2] + a2 * G.dx[2];
-    const double d12 = d1 * d1 + d2 * d2;
-    if (d12 > G.rc2) continue;
-    const long long col = field_col_off(G.tiled, n2, wrap(B.g[1] + a1, n1), wrap(B.g[2] + a2, n2));
-    // QB points of the column per round, all loads issued before use: with
-    // P0 <= QB (the usual 7 points) a lane has all 3 P0 of its loads in flight
-    // at once, one memory round trip per blob
-    for (int a0 = 0; a0 < P0; a0 += QB) {
-      R wv[QB];
-      unsigned ix[QB];   // index within one component (its byte offset is below 2^31)
+  for (int task = lane; task < P0 * per0; task += 64) {
+    const int a0 = task / per0, rem = task - a0 * per0;
+    const int a1 = rem / nck, c = rem - a1 * nck;
+    const double d0 = B.e[0] + a0 * G.dx[0], d1 = B.e[1] + a1 * G.dx[1];
+    const double d00 = d0 * d0, d11 = d1 * d1;
+    if (d00 + d11 > G.rc2) continue;   // the row misses the cutoff sphere
+    int c2 = first2 + c * CW;          // below 2 n2: first2 < n2, c CW < CW + P2 - 1
+    c2 -= (c2 >= n2) ? n2 : 0;
+    const unsigned ix = (unsigned)(field_plane_off(G.tiled, n1, n2, wrap(B.g[0] + a0, n0)) +
+                                   field_col_off(G.tiled, n2, wrap(B.g[1] + a1, n1), c2));
+    R x0[CW], x1[CW], x2[CW];
+    u0.chunk(ix, x0);
+    u1.chunk(ix, x1);
+    u2.chunk(ix, x2);
 #pragma unroll
-      for (int q = 0; q < QB; ++q) {
-        const int aa = a0 + q;
-        const int gg = wrap(B.g[0] + aa, n0);
-        const double d0 = B.e[0] + aa * G.dx[0];
-        const double dd = d0 * d0 + d12;
-        const bool ok = (aa < P0) && (dd <= G.rc2);
-        wv[q] = ok ? wn * gexp<R>(-R(dd) * i2) : R(0);
-        ix[q] = (unsigned)(field_plane_off(G.tiled, n1, n2, ok ? gg : B.g[0]) + col);
-      }
-      R x0[QB], x1[QB], x2[QB];
-#pragma unroll
-      for (int q = 0; q < QB; ++q) {
-        x0[q] = u0(ix[q]);
-        x1[q] = u1(ix[q]);
-        x2[q] = u2(ix[q]);
-      }
-#pragma unroll
-      for (int q = 0; q < QB; ++q) {
-        s0 += wv[q] * x0[q];
-        s1 += wv[q] * x1[q];
-        s2 += wv[q] * x2[q];
-      }
+    for (int j = 0; j < CW; ++j) {
+      const int a2 = c * CW + j - skew;
+      const double d2 = B.e[2] + a2 * G.dx[2];
+      const double dd = d00 + (d11 + d2 * d2);
+      const bool ok = a2 >= 0 && a2 < P2 && dd <= G.rc2;
+      const R wv = ok ? wn * gexp<R>(-R(dd) * i2) : R(0);
+      s0 += wv * x0[j];
+      s1 += wv * x1[j];
+      s2 += wv * x2[j];
     }
   }
   s0 = wave_sum(s0);
@@ -1191,6 +1195,10 @@ int interp(const GridGeom& g, const double* r, const R* u, double* v, int M, dou
            const int* blob_body, const double* Y, const double* V, hipStream_t s, const int* skip,
            const void* sorted) {
   if (M <= 0) return GDC_OK;
+  if (g.n[2] % 4 != 0) {
+    set_error("interp: the grid's axis 2 must be a multiple of 4 (16-byte chunks)");
+    return GDC_EINVAL;
+  }
   RigidTerm K{blob_body, Y, V};
   const ProbeEvents pe = probe_claim("interp");
   GDC_LAUNCH_PROBED((k_interp<R>), dim3(blocks_for(M)), dim3(NT), 0, s, pe, g, r, u, v, M, scale, K, skip,
