@@ -1344,10 +1344,6 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
       }
       t.ntiles *= t.nt[d];
     }
-    int ncu = 256;
-    if (!h->dry && hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess)
-      ncu = 256;
-    t.one_round = t.ntiles <= 4 * ncu ? 1 : 0;
     t.wz8 = (g.P[2] <= 8 && t.nt[2] >= 2) ? 1 : 0;
     const int cols = std::min(t.T[1], g.P[1]) * std::min(t.T[2], g.P[2]);
     t.S = 1;

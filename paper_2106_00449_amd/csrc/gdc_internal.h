@@ -192,7 +192,6 @@ struct TileGeom {
   int H[3];
   int ntiles;
   int S;       // work-item slots per blob: a power of two >= min(T1, P1) min(T2, P2)
-  int one_round;   // at most 4 tiles per CU: spreading is bound by each tile's latency, not occupancy
   int wz8;         // spreading tables keep 8 axis-2 entries per hit (stencil <= 8 points, >= 2 tiles on axis 2)
 };
 

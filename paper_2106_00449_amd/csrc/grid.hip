@@ -758,21 +758,12 @@ __global__ __launch_bounds__(NT) void k_tile_order(const int* __restrict__ tab_s
 // goes out with 16-byte stores, whole 128-byte rows at a time.  No atomics and
 // a fixed summation order: results repeat bit for bit.
 // Each round of up to 64 hits is staged in LDS; every wave keeps the round's
-// hit masks and forces in its lanes and takes them with readlane.  HOIST
-// reads all of a hit's table values into registers before its tests (one
-// LDS wait per hit, more registers: for few tiles per CU); without it the
-// plane factors are read where used (fewer registers, more workgroups per
-// CU: for many tiles per CU).  Both add the same terms in the same order.
+// hit masks and forces in its lanes and takes them with readlane.  A hit's
+// axis-0 factors (f0, s0: the same for every lane) come from the table in
+// global memory through scalar loads into scalar registers, one load per hit;
+// each lane reads its four axis-1 and axis-2 factors from LDS together,
+// before any test, so a hit costs one LDS round trip.
 constexpr int NTS = 512;   // threads of a spreading workgroup
-
-// Marks values as needed here: the compiler keeps their loads ahead of this
-// point instead of moving each into the branch that uses it.
-template <typename R>
-__device__ __forceinline__ void pin_values(R (&a)[8], R (&b)[8], R c, R d, R e, R f) {
-#pragma unroll
-  for (int k = 0; k < 8; ++k) asm volatile("" ::"v"(a[k]), "v"(b[k]));
-  asm volatile("" ::"v"(c), "v"(d), "v"(e), "v"(f));
-}
 
 // Value of v in lane l (l wave-uniform), without LDS.
 __device__ __forceinline__ float read_lane(float v, int l) {
@@ -785,7 +776,7 @@ __device__ __forceinline__ double read_lane(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <typename R, bool HOIST, int WZ>
+template <typename R, int WZ>
 __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, const HitTab<R, WZ>* __restrict__ tabs,
                                                    const int4* __restrict__ order, const double* __restrict__ lam,
                                                    const double* __restrict__ lam_sorted, R* __restrict__ f,
@@ -818,7 +809,6 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
 #pragma unroll
   for (int k = 0; k < TX; ++k) acc[k][0] = acc[k][1] = acc[k][2] = R(0);
   constexpr int V16 = (int)(sizeof(HitTab<R, WZ>) / 16);
-  constexpr int LPT = (HR * V16 + NTS - 1) / NTS;   // 16-byte table loads per thread and round
   for (int hb = 0; hb < cnt; hb += HR) {
     const int nr = min(HR, cnt - hb);
     // the round's table loads and the forces of its hits (record position,
@@ -827,17 +817,9 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
     const u32x4* src = reinterpret_cast<const u32x4*>(tabs + start + hb);
     u32x4* dstv = reinterpret_cast<u32x4*>(sh);
-    // (the register variant copies one vector at a time: the staged
-    // vectors would be live beside the accumulators)
-    constexpr int LPS = HOIST ? LPT : 1;
-    u32x4 tv[LPS];
-    if constexpr (!HOIST)
-      for (int v = tid; v < nr * V16; v += NTS) dstv[v] = src[v];
-#pragma unroll
-    for (int m = 0; m < LPS; ++m) {
-      const int v = tid + m * NTS;
-      if (HOIST && v < nr * V16) tv[m] = src[v];
-    }
+    // (one vector at a time: staged vectors would be live beside the
+    // accumulators and cost a workgroup per CU)
+    for (int v = tid; v < nr * V16; v += NTS) dstv[v] = src[v];
     double lv[3] = {0.0, 0.0, 0.0};
     if (tid < nr) {
       const HitTab<R, WZ>& g = tabs[start + hb + tid];
@@ -845,11 +827,6 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
       const double* ls = lam_sorted ? lam_sorted : lam;
 #pragma unroll
       for (int q = 0; q < 3; ++q) lv[q] = ls[base + q];
-    }
-#pragma unroll
-    for (int m = 0; m < LPS; ++m) {
-      const int v = tid + m * NTS;
-      if (HOIST && v < nr * V16) dstv[v] = tv[m];
     }
     if (tid < nr) {
 #pragma unroll
@@ -868,49 +845,36 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
       const int hm = __builtin_amdgcn_readlane(hmask, h);
       if (!((hm >> wave) & 1)) continue;
       const R l0 = read_lane(hl0, h), l1 = read_lane(hl1, h), l2 = read_lane(hl2, h);
+      // the hit's axis-0 factors, the same for every lane: scalar loads from
+      // the table in global memory (h is wave-uniform)
+      const HitTab<R, WZ>& tg = tabs[start + hb + h];
+      R f0s[TX], s0s[TX];
+#pragma unroll
+      for (int k = 0; k < TX; ++k) {
+        f0s[k] = tg.f0[k];
+        s0s[k] = tg.s0[k];
+      }
       const HitTab<R, WZ>& t = tab[h];
       // this lane's entry of the hit's axis-2 window (outside it: no weight)
       const int zz = z - (WZ == 32 ? 0 : __builtin_amdgcn_readlane(hzlo, h));
       const bool zin = (unsigned)zz < (unsigned)WZ;
       const int zi = zin ? zz : 0;
-      if constexpr (HOIST) {
-        // every table value of the hit in registers before any test, so
-        // that one LDS wait serves the hit (a load left under a test costs
-        // a round trip per plane); 16 more registers per lane
-        R f0v[TX], s0v[TX];
+      // the lane's axis-1 and axis-2 factors, all four read before any test
+      // (the empty asm marks them as needed here, so the compiler does not
+      // move the second pair into the branch: one LDS round trip per hit)
+      const R s1v = t.s1[j1], szv = t.sz[zi], f1v = t.f1[j1], fzv = t.fz[zi];
+      asm volatile("" ::"v"(s1v), "v"(szv), "v"(f1v), "v"(fzv));
+      if (!live || !zin) continue;
+      const R s12 = s1v + szv;
+      if (s12 > rc2) continue;
+      const R f12 = f1v * fzv;
 #pragma unroll
-        for (int k = 0; k < TX; ++k) {
-          f0v[k] = t.f0[k];
-          s0v[k] = t.s0[k];
-        }
-        const R s1v = t.s1[j1], szv = zin ? t.sz[zi] : R(1e30), f1v = t.f1[j1], fzv = t.fz[zi];
-        pin_values(f0v, s0v, s1v, szv, f1v, fzv);
-        const R s12 = s1v + szv;
-        if (!live || s12 > rc2) continue;
-        const R f12 = f1v * fzv;
-#pragma unroll
-        for (int k = 0; k < TX; ++k) {
-          if (!((hm >> (8 + k)) & 1)) continue;
-          const R w = (s0v[k] + s12 <= rc2) ? f12 * f0v[k] : R(0);
-          acc[k][0] += w * l0;
-          acc[k][1] += w * l1;
-          acc[k][2] += w * l2;
-        }
-      } else {
-        // plane factors read where they are used: fewer registers, more
-        // workgroups per CU when the tiles run in many rounds
-        if (!live || !zin) continue;
-        const R s12 = t.s1[j1] + t.sz[zi];
-        if (s12 > rc2) continue;
-        const R f12 = t.f1[j1] * t.fz[zi];
-#pragma unroll
-        for (int k = 0; k < TX; ++k) {
-          if (!((hm >> (8 + k)) & 1)) continue;
-          const R w = (t.s0[k] + s12 <= rc2) ? f12 * t.f0[k] : R(0);
-          acc[k][0] += w * l0;
-          acc[k][1] += w * l1;
-          acc[k][2] += w * l2;
-        }
+      for (int k = 0; k < TX; ++k) {
+        if (!((hm >> (8 + k)) & 1)) continue;
+        const R w = (s0s[k] + s12 <= rc2) ? f12 * f0s[k] : R(0);
+        acc[k][0] += w * l0;
+        acc[k][1] += w * l1;
+        acc[k][2] += w * l2;
       }
     }
     __syncthreads();
@@ -1175,17 +1139,13 @@ int spread(const GridGeom& g, const TileGeom& t, const void* tabs, const int* or
     return GDC_EINVAL;
   }
   const ProbeEvents pe = probe_claim("spread");
-  // both variants add the same terms in the same order: identical results.
-  // FP64 tables would need 150 registers a lane hoisted: always the lean one
-  const bool hoist = t.one_round && sizeof(R) == 4;
-#define GDC_SPREAD_(H, W)                                                                                     \
-  GDC_LAUNCH_PROBED((k_spread_tab<R, H, W>), dim3(t.ntiles), dim3(NTS), 0, s, pe, g, t, \
-                        (const HitTab<R, W>*)tabs, (const int4*)order, lam, lam_sorted, f, skip)
-  if (t.wz8) {
-    if (hoist) GDC_SPREAD_(true, 8); else GDC_SPREAD_(false, 8);
-  } else {
-    if (hoist) GDC_SPREAD_(true, 32); else GDC_SPREAD_(false, 32);
-  }
+#define GDC_SPREAD_(W)                                                                          \
+  GDC_LAUNCH_PROBED((k_spread_tab<R, W>), dim3(t.ntiles), dim3(NTS), 0, s, pe, g, t, (const HitTab<R, W>*)tabs, \
+                    (const int4*)order, lam, lam_sorted, f, skip)
+  if (t.wz8)
+    GDC_SPREAD_(8);
+  else
+    GDC_SPREAD_(32);
 #undef GDC_SPREAD_
   return check_launch("k_spread_tab");
 }
