@@ -1254,15 +1254,21 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
   B.shape_precT = d_prec;
   B.shape_prec_off = d_poff;
   {
-    // bodies grouped by shape, PREC_GROUP per group, for the matrix-core preconditioner
+    // bodies grouped by shape for the matrix-core preconditioner: as many
+    // per group (4, 8 or 16, the columns of one MFMA tile) as leave at least
+    // PREC_MIN_GROUPS groups, so that large suspensions stage each shape
+    // block for 16 bodies and small ones keep enough workgroups to hide the
+    // gather latency.  A body's result does not depend on its group.
+    int grp = PREC_GROUP_MIN;
+    while (2 * grp <= PREC_GROUP_MAX && (long long)h->N >= (long long)PREC_MIN_GROUPS * 2 * grp) grp *= 2;
     std::vector<int> gbody, gfirst, gcount, gshape;
     for (int sh = 0; sh < cfg->n_shapes; ++sh) {
       const int first = (int)gbody.size();
       for (int p = 0; p < h->N; ++p)
         if (h->body_shape[p] == sh) gbody.push_back(p);
-      for (int k = first; k < (int)gbody.size(); k += PREC_GROUP) {
+      for (int k = first; k < (int)gbody.size(); k += grp) {
         gfirst.push_back(k);
-        gcount.push_back(std::min(PREC_GROUP, (int)gbody.size() - k));
+        gcount.push_back(std::min(grp, (int)gbody.size() - k));
         gshape.push_back(sh);
       }
     }

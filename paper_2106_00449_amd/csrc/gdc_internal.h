@@ -209,7 +209,7 @@ struct BodyTables {
   const double* shape_Lp;     // n_shapes: max blob-blob distance (or a)
   const double* shape_precT;  // concatenated transposed preconditioner inverses
   const long long* shape_prec_off;  // n_shapes
-  // Groups of up to PREC_GROUP bodies of one shape for the matrix-core
+  // Groups of up to PREC_GROUP_MAX bodies of one shape for the matrix-core
   // preconditioner: group g covers bodies group_body[group_first[g] ..
   // group_first[g] + group_count[g]) of shape group_shape[g].
   int n_groups;
@@ -302,10 +302,13 @@ int blob_positions(const BodyTables& b, const double* Y, const double* q, double
                    hipStream_t s);
 // Largest preconditioner block (3 n_b + 6) the matrix-core kernel takes.
 constexpr int PREC_MFMA_MAXDIM = 64;
-// Bodies per workgroup of the matrix-core preconditioner (<= 16, the
-// columns of one MFMA tile): fewer bodies give more workgroups to hide the
-// gather and scatter latency.
-constexpr int PREC_GROUP = 4;
+// Bodies per workgroup of the matrix-core preconditioner: between 4 and 16
+// (the columns of one MFMA tile), the most that leave PREC_MIN_GROUPS
+// workgroups (fewer bodies give more workgroups to hide the gather and
+// scatter latency; more amortise staging the shape's block).
+constexpr int PREC_GROUP_MIN = 4;
+constexpr int PREC_GROUP_MAX = 16;
+constexpr int PREC_MIN_GROUPS = 1024;
 // z = P^-1 x (block-diagonal preconditioner, Sec. 2.2) and, when yV is
 // given, the body rows of the saddle operator at z: yV = -K^T z_lam - Pi z_V.
 // When zs is given, z_lam is also written in the spreading order:
