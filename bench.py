@@ -424,7 +424,7 @@ def serving_bench(g, wl, reqs, states, budget, slots):
     which the bucket's smallest and largest requests both solve the body
     mobility within 1e-5 of the FP64 oracle."""
     import numpy as np
-    from paper_2106_00449_amd.serving import Request, Server, summarise
+    from paper_2106_00449_amd.serving import LibraryExecutor, Request, Server, summarise
 
     buckets = sorted(set(int(w.n[0]) for w in reqs))
     tols, bucket_err = {}, {}
@@ -453,6 +453,12 @@ def serving_bench(g, wl, reqs, states, budget, slots):
     res = srv.run(requests(None))
     sat = summarise(res, makespan=time.perf_counter() - t0)
     sat.update(peak_bytes=srv.peak_bytes, peak_slots=srv.peak_slots)
+    progress("serving: saturation run, GMRES iterations fused over the resident suspensions")
+    srv = Server(hbm_budget=budget, max_slots=slots, executor=LibraryExecutor(fusion=True))
+    t0 = time.perf_counter()
+    res = srv.run(requests(None))
+    sat_fused = summarise(res, makespan=time.perf_counter() - t0)
+    sat_fused.update(peak_bytes=srv.peak_bytes, peak_slots=srv.peak_slots)
     rate = len(reqs) / sat["makespan_s"]
     sweep = {}
     for f in (0.5, 1.0, 2.0):
@@ -493,7 +499,8 @@ def serving_bench(g, wl, reqs, states, budget, slots):
                     f"{min(w.n[0] for w in reqs)}^3..{max(w.n[0] for w in reqs)}^3, 50 gDC steps each, FP32",
         "tolerance_per_bucket": bucket_err,
         "hbm_budget_bytes": budget, "max_slots": slots,
-        "saturation": sat, "poisson_at_saturation_rate": sweep["1x"], "poisson_rate_sweep": sweep,
+        "saturation": sat, "saturation_fused": sat_fused,
+        "poisson_at_saturation_rate": sweep["1x"], "poisson_rate_sweep": sweep,
         "sequential_fp64_sample": seq["fp64"], "sequential_fp32_sample": seq["fp32"],
         "served_over_sequential_fp64": sat["blob_steps_per_s"] / seq["fp64"]["blob_steps_per_s"],
     }

@@ -155,6 +155,9 @@ typedef struct {
                                 in the call: GDC_OK, GDC_ENOTCONV (a solve missed
                                 the tolerance) or GDC_ENUMERIC (non-finite state,
                                 pair-force cell overflow) */
+  int fused_iterations;      /* GMRES iterations of this handle launched fused
+                                with other suspensions' in the call
+                                (gdc_batch_step, gdc_set_fusion) */
 } gdc_stats;
 
 typedef struct gdc_handle gdc_handle;
@@ -268,6 +271,23 @@ int gdc_set_launch_config(gdc_handle* h, const int* threads, int n);
  * the probe can stamp them.  Errors: GDC_EINVAL (NULL, step in flight). */
 int gdc_set_graphs(gdc_handle* h, int on);
 int gdc_get_graphs(const gdc_handle* h, int* on);
+
+/* Fused batching (the GMRES iterations of Sec. 3 step 5 over several
+ * suspensions): with fusion on, a handle stepped by gdc_batch_step does not
+ * launch its GMRES iterations itself.  After each pass over its handles the
+ * call launches every kernel of an iteration (preconditioner, spreading,
+ * the three plane passes of the transform, averaging, the three Arnoldi
+ * kernels) once for all the fused handles that have an iteration ready,
+ * each at its own Krylov column, grouped by what the kernels are
+ * instantiated for (grid size, transform workgroup sizes, spreading-table
+ * width, vector-length class).  Each suspension's arithmetic is unchanged:
+ * results equal the unfused ones bit for bit.  Only handles on the FP32
+ * plane-path transforms (grids up to 128^3) with the matrix-core
+ * preconditioner, outside the slip channel, are fused; others run as
+ * before, and so does gdc_step.  Off by default.  Errors: GDC_EINVAL (NULL,
+ * step in flight). */
+int gdc_set_fusion(gdc_handle* h, int on);
+int gdc_get_fusion(const gdc_handle* h, int* on);
 
 /* Internal step counter (checkpoint / resume: with the same state and
  * counter a resumed run repeats an uninterrupted one exactly). */

@@ -68,7 +68,7 @@ class _Stats(ctypes.Structure):
                 ("nu_nonpositive", ctypes.c_int), ("ms", ctypes.c_double),
                 ("sine_vx", ctypes.c_double), ("gmres_iterations_mean", ctypes.c_double),
                 ("nu_mean", ctypes.c_double), ("nu_std", ctypes.c_double), ("nu_min", ctypes.c_double),
-                ("nu_max", ctypes.c_double), ("status", ctypes.c_int)]
+                ("nu_max", ctypes.c_double), ("status", ctypes.c_int), ("fused_iterations", ctypes.c_int)]
 
 
 def _load():
@@ -102,13 +102,16 @@ def _load():
     L.gdc_get_launch_config.argtypes = [P, ctypes.POINTER(I), I]
     L.gdc_set_graphs.argtypes = [P, I]
     L.gdc_get_graphs.argtypes = [P, ctypes.POINTER(I)]
+    L.gdc_set_fusion.argtypes = [P, I]
+    L.gdc_get_fusion.argtypes = [P, ctypes.POINTER(I)]
     L.gdc_set_launch_config.argtypes = [P, ctypes.POINTER(I), I]
     for name in ["gdc_init", "gdc_mobility_apply", "gdc_step", "gdc_get_step", "gdc_set_step",
                  "gdc_fluct_velocity", "gdc_predictor", "gdc_philox_normals", "gdc_philox_normals_noalloc",
                  "gdc_probe_kernel",
                  "gdc_probe_read", "gdc_set_state", "gdc_get_state", "gdc_batch_step", "gdc_step_log",
                  "gdc_footprint", "gdc_device_bytes",
-                 "gdc_get_launch_config", "gdc_set_launch_config", "gdc_set_graphs", "gdc_get_graphs"]:
+                 "gdc_get_launch_config", "gdc_set_launch_config", "gdc_set_graphs", "gdc_get_graphs",
+                 "gdc_set_fusion", "gdc_get_fusion"]:
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -250,7 +253,7 @@ def batch_step(susps, steps, until="all", max_ms=0.0):
             "gmres_relres": x.gmres_relres, "nu": x.nu, "nu_nonpositive": x.nu_nonpositive,
             "ms": x.ms, "sine_vx": x.sine_vx, "gmres_iterations_mean": x.gmres_iterations_mean,
             "nu_mean": x.nu_mean, "nu_std": x.nu_std, "nu_min": x.nu_min, "nu_max": x.nu_max,
-            "status": x.status}
+            "status": x.status, "fused_iterations": x.fused_iterations}
            for x in stats[:nh]]
     return [int(x) for x in st_in[:nh]], out, rc
 
@@ -392,6 +395,18 @@ class Suspension:
     @graphs.setter
     def graphs(self, on):
         _check(lib.gdc_set_graphs(self._h, 1 if on else 0))
+
+    @property
+    def fusion(self):
+        """Whether batch_step fuses this suspension's GMRES iterations with
+        other suspensions' (one launch per kernel for all of them)."""
+        on = ctypes.c_int()
+        _check(lib.gdc_get_fusion(self._h, ctypes.byref(on)))
+        return bool(on.value)
+
+    @fusion.setter
+    def fusion(self, on):
+        _check(lib.gdc_set_fusion(self._h, 1 if on else 0))
 
     @property
     def step_counter(self):

@@ -8,10 +8,12 @@
 #include "gdc_internal.h"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -320,6 +322,7 @@ struct SolveRun {
   bool first = true;    // first cycle: the residual is the right-hand side
   int k = 0;            // Arnoldi column of the current cycle
   bool queued = false;  // iteration k is on the stream
+  bool deferred = false;  // iteration k waits for a launch fused with other suspensions
   GmStatus st{};
   GmresResult res{};
 };
@@ -412,6 +415,15 @@ struct gdc_handle {
   std::vector<IterGraph> iter_graph;
   bool graphs = true;
 
+  // Launches fused over suspensions (gdc_set_fusion): inside gdc_batch_step a
+  // fused handle does not launch its GMRES iterations itself; the call
+  // launches each iteration kernel once for all the handles that are ready
+  // (fuse_live while such a call runs).  join_ev marks the handle's stream
+  // for the shared stream of the fused launches.
+  bool fuse = false;
+  bool fuse_live = false;
+  hipEvent_t join_ev = nullptr;
+
   bool dry = false;               // footprint query: count device bytes, touch no device
   size_t dev_bytes = 0;           // device memory held by the handle
   bool has_state = false;         // Y, q hold a state (gdc_set_state or gdc_step)
@@ -420,6 +432,7 @@ struct gdc_handle {
   std::vector<double> step_log;   // completion times of steps (ms, monotonic clock)
   // error counts of the steps completed since the last gdc_step / gdc_batch_step entry
   int n_overflow = 0, n_nonfinite = 0, n_notconv = 0, n_nonpos = 0;
+  int n_fused = 0;   // GMRES iterations launched fused since the last reset_errors
   // sine forcing: the field (sin(k y), 0, 0) on the grid, its average at
   // each blob, f0/(eta k^2), and the amplitudes v_x of this call's steps
   void* grid_sine = nullptr;
@@ -440,6 +453,7 @@ struct gdc_handle {
       if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : step_ev)
       if (e) (void)hipEventDestroy(e);
+    if (join_ev) (void)hipEventDestroy(join_ev);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 
@@ -595,6 +609,15 @@ int poll_status(gdc_handle* h, int slot, bool block, bool& ready, GmStatus& st) 
   return GDC_OK;
 }
 
+// Whether a GMRES iteration of h may be fused with other suspensions' now:
+// inside gdc_batch_step, for a fused handle on the FP32 plane-path
+// transforms with the matrix-core preconditioner, outside the slip channel
+// and while no probe watches a kernel family.
+bool fusable_now(const gdc_handle* h) {
+  return h->fuse_live && !h->geom.channel && stokes_fusable(h->geom, h->precision) &&
+         precond_fusable(h->bt, h->maxdim) && !probe_active();
+}
+
 // Queues GMRES iteration k of the current cycle: z = P^-1 V_k, w = A z (the
 // mobility apply), and the Arnoldi step that writes V_{k+1}, the Hessenberg
 // column and the status slot (k + 1) & 1.  With graphs on (and no kernel
@@ -709,7 +732,18 @@ int solve_advance(gdc_handle* h, bool block, int& adv) {
     case SolveRun::ITER: {
       const int k = sv.k;
       bool enq = false;
+      if (sv.deferred) {   // waiting for the fused launch of this iteration
+        adv = ADV_BLOCKED;
+        return GDC_OK;
+      }
       if (!sv.queued) {
+        if (fusable_now(h)) {
+          // gdc_batch_step launches it with the other ready suspensions and
+          // then records gm_ev[(k + 1) & 1] on this handle's stream
+          sv.queued = sv.deferred = true;
+          adv = ADV_BLOCKED;
+          return GDC_OK;
+        }
         const int slot = (k + 1) & 1;
         GDC_TRY(queue_iteration<R>(h, k));
         GDC_HIP(hipEventRecord(h->gm_ev[slot], s));
@@ -968,6 +1002,7 @@ int step_errors(const gdc_handle* h) {
 
 void reset_errors(gdc_handle* h) {
   h->n_overflow = h->n_nonfinite = h->n_notconv = h->n_nonpos = 0;
+  h->n_fused = 0;
   h->sine_acc = 0.0;
   h->sine_n = 0;
   h->its_acc = h->nu_acc = h->nu_acc2 = h->nu_lo = h->nu_hi = 0.0;
@@ -990,6 +1025,7 @@ void fill_stats(const gdc_handle* h, gdc_stats* st) {
   st->nu_min = h->nu_lo;
   st->nu_max = h->nu_hi;
   st->status = step_errors(h);
+  st->fused_iterations = h->n_fused;
 }
 
 int require_idle(const gdc_handle* h) {
@@ -1380,6 +1416,7 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
     GDC_HIP(hipHostGetDevicePointer((void**)&h->gm_host_dev, h->gm_host, 0));
     for (hipEvent_t& e : h->gm_ev) GDC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     for (hipEvent_t& e : h->step_ev) GDC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    GDC_HIP(hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming));
   }
 
   if (h->precision == GDC_FP64) {
@@ -1580,6 +1617,229 @@ int gdc_get_state(gdc_handle* h, double* Y, double* q, int memspace) {
   return finish(h);
 }
 
+namespace {
+
+// Staging of fused launches: argument tables go from a pinned host slot to a
+// device slot in one copy on a stream shared by the fused launches of one
+// GPU; slots are used in turn, and a slot is reused only once its event
+// (recorded after the launches that read it) has completed.
+struct FuseSlot {
+  void* host = nullptr;
+  void* dev = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool used = false;
+};
+struct FuseDevice {
+  hipStream_t stream = nullptr;
+  std::vector<FuseSlot> slots;
+  int next = 0;
+};
+std::mutex g_fuse_mutex;
+std::map<int, FuseDevice> g_fuse;
+constexpr int FUSE_SLOTS = 8;
+
+int fuse_slot(int device, size_t bytes, FuseDevice*& fd, FuseSlot*& slot) {
+  fd = &g_fuse[device];
+  if (!fd->stream) {
+    GDC_HIP(hipStreamCreateWithFlags(&fd->stream, hipStreamNonBlocking));
+    fd->slots.resize(FUSE_SLOTS);
+  }
+  slot = &fd->slots[fd->next];
+  fd->next = (fd->next + 1) % FUSE_SLOTS;
+  if (slot->used) GDC_HIP(hipEventSynchronize(slot->ev));   // its launches are long done in practice
+  if (!slot->ev) GDC_HIP(hipEventCreateWithFlags(&slot->ev, hipEventDisableTiming));
+  if (slot->cap < bytes) {
+    if (slot->host) GDC_HIP(hipHostFree(slot->host));
+    if (slot->dev) GDC_HIP(hipFree(slot->dev));
+    slot->host = slot->dev = nullptr;
+    slot->cap = 0;
+    const size_t cap = std::max<size_t>(bytes, 64 << 10);
+    GDC_HIP(hipHostMalloc(&slot->host, cap, hipHostMallocDefault));
+    GDC_HIP(hipMalloc(&slot->dev, cap));
+    slot->cap = cap;
+  }
+  return GDC_OK;
+}
+
+// Byte layout of one fused iteration's tables: per kernel an argument array
+// (ns entries) and the first block of every suspension (ns ints).
+struct FuseLayout {
+  size_t pre, spr, fwd, prj, inv, itp, arn;            // argument arrays
+  size_t f_pre, f_spr, f_pl, f_prj, f_itp, f_dot, f_axp, f_fin;   // first-block arrays
+  size_t bytes;
+  explicit FuseLayout(int ns) {
+    size_t o = 0;
+    auto take = [&](size_t b) {
+      const size_t at = o;
+      o = (o + b + 255) & ~size_t(255);
+      return at;
+    };
+    pre = take(ns * sizeof(PrecondArgs));
+    spr = take(ns * sizeof(SpreadArgs));
+    fwd = take(ns * sizeof(PlaneArgs));
+    prj = take(ns * sizeof(ProjPlaneArgs));
+    inv = take(ns * sizeof(PlaneArgs));
+    itp = take(ns * sizeof(InterpArgs));
+    arn = take(ns * sizeof(ArnoldiArgs));
+    f_pre = take(ns * sizeof(int));
+    f_spr = take(ns * sizeof(int));
+    f_pl = take(ns * sizeof(int));
+    f_prj = take(ns * sizeof(int));
+    f_itp = take(ns * sizeof(int));
+    f_dot = take(ns * sizeof(int));
+    f_axp = take(ns * sizeof(int));
+    f_fin = take(ns * sizeof(int));
+    bytes = o;
+  }
+};
+
+int blocks_of(const LocalGrid& g) { return g.gx * g.gy * g.gz; }
+
+// One fused GMRES iteration for handles that can share every kernel
+// instantiation (same grid, workgroup sizes, table width and vector-length
+// class), each at its own Krylov column: the same arithmetic, per
+// suspension, as queue_iteration.
+int fuse_group(const std::vector<gdc_handle*>& g) {
+  const int ns = (int)g.size();
+  const FuseLayout L(ns);
+  std::lock_guard<std::mutex> lk(g_fuse_mutex);
+  FuseDevice* fd = nullptr;
+  FuseSlot* slot = nullptr;
+  GDC_TRY(fuse_slot(g[0]->device, L.bytes, fd, slot));
+  unsigned char* hb = (unsigned char*)slot->host;
+  unsigned char* db = (unsigned char*)slot->dev;
+  auto* pa = (PrecondArgs*)(hb + L.pre);
+  auto* sa = (SpreadArgs*)(hb + L.spr);
+  auto* fa = (PlaneArgs*)(hb + L.fwd);
+  auto* qa = (ProjPlaneArgs*)(hb + L.prj);
+  auto* ia = (PlaneArgs*)(hb + L.inv);
+  auto* ta = (InterpArgs*)(hb + L.itp);
+  auto* aa = (ArnoldiArgs*)(hb + L.arn);
+  int* f_pre = (int*)(hb + L.f_pre);
+  int* f_spr = (int*)(hb + L.f_spr);
+  int* f_pl = (int*)(hb + L.f_pl);
+  int* f_prj = (int*)(hb + L.f_prj);
+  int* f_itp = (int*)(hb + L.f_itp);
+  int* f_dot = (int*)(hb + L.f_dot);
+  int* f_axp = (int*)(hb + L.f_axp);
+  int* f_fin = (int*)(hb + L.f_fin);
+  int t_pre = 0, t_spr = 0, t_pl = 0, t_prj = 0, t_itp = 0, t_dot = 0, t_axp = 0, t_fin = 0;
+  for (int j = 0; j < ns; ++j) {
+    gdc_handle* h = g[j];
+    SolveRun& sv = h->sv;
+    const long long n = h->nx;
+    const int k = sv.k;
+    const long long m3 = 3LL * h->M;
+    double* Vk = h->Vb + n * k;
+    double* Vk1 = h->Vb + n * (k + 1);
+    const int* skip = &h->gm->done;
+    precond_describe(pa[j], h->bt, sv.q, Vk, h->z, h->w + m3, h->spos, h->zsorted, skip, 0);
+    spread_describe(sa[j], h->geom, h->tg, h->tabs, h->tab_order, h->z, h->zsorted, h->grid[0], skip);
+    StokesArgs st;
+    stokes_describe(st, h->geom, (const void* const*)h->tw, h->grid[0], h->grid[1], skip);
+    fa[j] = st.fwd;
+    qa[j] = st.proj;
+    ia[j] = st.inv;
+    interp_describe(ta[j], h->geom, sv.r, h->grid[0], h->w, h->M, h->geom.dV, h->bt.blob_body, sv.Y, h->z + m3,
+                    skip, sorted_records(h));
+    GDC_TRY(arnoldi_describe(aa[j], h->w, h->Vb, n, k + 1, n, h->partial, h->partial2, Vk1, h->hdev,
+                             h->hdev + HCOLS, skip, h->gm, h->restart, h->gm_host_dev + 32 * ((k + 1) & 1)));
+    f_pre[j] = t_pre;
+    t_pre += blocks_of(pa[j].grid);
+    f_spr[j] = t_spr;
+    t_spr += blocks_of(sa[j].grid);
+    f_pl[j] = t_pl;
+    t_pl += blocks_of(fa[j].grid);
+    f_prj[j] = t_prj;
+    t_prj += blocks_of(qa[j].grid);
+    f_itp[j] = t_itp;
+    t_itp += blocks_of(ta[j].grid);
+    f_dot[j] = t_dot;
+    t_dot += blocks_of(aa[j].g_dot);
+    f_axp[j] = t_axp;
+    t_axp += blocks_of(aa[j].g_axpy);
+    f_fin[j] = t_fin;
+    t_fin += blocks_of(aa[j].g_fin);
+  }
+  hipStream_t fs = fd->stream;
+  // the fused launches follow each handle's queued work
+  for (gdc_handle* h : g) {
+    GDC_HIP(hipEventRecord(h->join_ev, h->stream));
+    GDC_HIP(hipStreamWaitEvent(fs, h->join_ev, 0));
+  }
+  GDC_HIP(hipMemcpyAsync(db, hb, L.bytes, hipMemcpyHostToDevice, fs));
+  const gdc_handle* h0 = g[0];
+  GDC_TRY(precond_fused((const PrecondArgs*)(db + L.pre), ns, (const int*)(db + L.f_pre), t_pre, fs));
+  GDC_TRY(spread_fused<float>((const SpreadArgs*)(db + L.spr), ns, h0->tg.wz8, (const int*)(db + L.f_spr), t_spr,
+                              fs));
+  GDC_TRY(stokes_fused(h0->geom, (const PlaneArgs*)(db + L.fwd), (const ProjPlaneArgs*)(db + L.prj),
+                       (const PlaneArgs*)(db + L.inv), ns, (const int*)(db + L.f_pl), t_pl,
+                       (const int*)(db + L.f_prj), t_prj, fs));
+  GDC_TRY(interp_fused<float>((const InterpArgs*)(db + L.itp), ns, (const int*)(db + L.f_itp), t_itp, fs));
+  GDC_TRY(arnoldi_fused((const ArnoldiArgs*)(db + L.arn), ns, aa[0].shortv, (const int*)(db + L.f_dot), t_dot,
+                        (const int*)(db + L.f_axp), t_axp, (const int*)(db + L.f_fin), t_fin, fs));
+  GDC_HIP(hipEventRecord(slot->ev, fs));
+  slot->used = true;
+  // each handle's later work follows the fused launches; gm_ev marks the
+  // iteration's status as solve_advance expects
+  for (gdc_handle* h : g) {
+    GDC_HIP(hipStreamWaitEvent(h->stream, slot->ev, 0));
+    GDC_HIP(hipEventRecord(h->gm_ev[(h->sv.k + 1) & 1], h->stream));
+    h->sv.deferred = false;
+    ++h->n_fused;
+  }
+  return GDC_OK;
+}
+
+// Launches the deferred iterations of hs: one fused launch per kernel for
+// each group of handles that share every kernel instantiation.  Returns the
+// number of handles launched in `launched`.
+int fuse_flush(gdc_handle* const* hs, int nh, int& launched) {
+  launched = 0;
+  std::map<std::array<int, 9>, std::vector<gdc_handle*>> groups;
+  for (int i = 0; i < nh; ++i) {
+    gdc_handle* h = hs[i];
+    if (!h->sv.deferred) continue;
+    const FftShape& f = h->geom.fft;
+    const int shortv = h->nx <= (long long)DOT_MAX_BLOCKS * 256 ? 1 : 0;
+    groups[{h->device, h->geom.n[0], h->geom.n[1], h->geom.n[2], f.plane_fwd, f.proj_plane, f.plane_inv,
+            h->tg.wz8, shortv}]
+        .push_back(h);
+  }
+  int cur = -1;
+  for (auto& kv : groups) {
+    if (kv.first[0] != cur) {
+      GDC_HIP(hipSetDevice(kv.first[0]));
+      cur = kv.first[0];
+    }
+    GDC_TRY(fuse_group(kv.second));
+    launched += (int)kv.second.size();
+  }
+  return GDC_OK;
+}
+
+}  // namespace
+
+int gdc_set_fusion(gdc_handle* h, int on) {
+  if (!h) {
+    set_error("handle is required");
+    return GDC_EINVAL;
+  }
+  GDC_TRY(require_idle(h));
+  h->fuse = on != 0;
+  return GDC_OK;
+}
+
+int gdc_get_fusion(const gdc_handle* h, int* on) {
+  if (!h || !on) {
+    set_error("handle and output are required");
+    return GDC_EINVAL;
+  }
+  *on = h->fuse ? 1 : 0;
+  return GDC_OK;
+}
+
 int gdc_batch_step(gdc_handle* const* hs, int nh, int* steps, int until, double max_ms, gdc_stats* st) {
   if (nh < 0 || (nh > 0 && (!hs || !steps)) || (until != GDC_UNTIL_ALL && until != GDC_UNTIL_ANY) ||
       !(max_ms >= 0.0)) {
@@ -1621,6 +1881,7 @@ int gdc_batch_step(gdc_handle* const* hs, int nh, int* steps, int until, double 
     any_watched = any_watched || watched[i];
     hs[i]->sr.to_start = steps[i] - (hs[i]->sr.phase == StepRun::SOLVE ? 1 : 0) - hs[i]->sr.pend;
     reset_errors(hs[i]);
+    hs[i]->fuse_live = hs[i]->fuse;
   }
   int rc = GDC_OK;
   int cur_dev = -1;
@@ -1659,6 +1920,19 @@ int gdc_batch_step(gdc_handle* const* hs, int nh, int* steps, int until, double 
         }
       }
     }
+    if (rc == GDC_OK) {
+      // the iterations the fused handles deferred in this pass
+      int launched = 0;
+      const int r = fuse_flush(hs, nh, launched);
+      if (r != GDC_OK) {
+        set_error(std::string("gdc_batch_step: fused launch: ") + gdc_last_error());
+        rc = r;
+      }
+      if (launched) {
+        progressed = true;
+        cur_dev = -1;
+      }
+    }
     if (rc != GDC_OK) break;
     bool all_zero = true, any_hit = false;
     for (int i = 0; i < nh; ++i) {
@@ -1668,6 +1942,14 @@ int gdc_batch_step(gdc_handle* const* hs, int nh, int* steps, int until, double 
     if (all_zero || (until == GDC_UNTIL_ANY && any_hit)) break;
     if (max_ms > 0.0 && now_ms() - t0 >= max_ms) break;
     if (!progressed) std::this_thread::yield();
+  }
+  for (int i = 0; i < nh; ++i) {
+    hs[i]->fuse_live = false;
+    // an error between a deferral and its launch leaves nothing half-queued
+    if (hs[i]->sv.deferred) {
+      hs[i]->sv.deferred = false;
+      hs[i]->sv.queued = false;
+    }
   }
   if (prev_dev >= 0) (void)hipSetDevice(prev_dev);
   // every handle's own outcome first; the message names the first failing

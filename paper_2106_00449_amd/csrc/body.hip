@@ -72,11 +72,11 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // passes A[16 rb + l % 16][4 t + l / 16] and X[4 t + l / 16][l % 16] and gets
 // Y[16 rb + l / 16 + 4 r][l % 16], r < 4); then rotated back and scattered
 // exactly as k_precond does.  D = 3 n_b + 6 <= PREC_MFMA_MAXDIM.
-__global__ __launch_bounds__(256) void k_precond_mfma(BodyTables B, const double* __restrict__ q,
-                                                     const double* __restrict__ x, double* __restrict__ z,
-                                                     double* __restrict__ yV, const int* __restrict__ spos,
-                                                     double* __restrict__ zs, const int* __restrict__ skip,
-                                                     int mirror) {
+__device__ __forceinline__ void precond_mfma_body(const BodyTables& B, const double* __restrict__ q,
+                                                  const double* __restrict__ x, double* __restrict__ z,
+                                                  double* __restrict__ yV, const int* __restrict__ spos,
+                                                  double* __restrict__ zs, const int* __restrict__ skip,
+                                                  int mirror, const BlockIx& bi) {
   if (skip && *skip) return;
   constexpr int DP = PREC_MFMA_MAXDIM;
   __shared__ double X[DP][16];
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_precond_mfma(BodyTables B, const double
   __shared__ double Rm[16][9];
   __shared__ double Tb[16][6];
   __shared__ int pb[16];
-  const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = bi.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int s = B.group_shape[g], first = B.group_first[g], cnt = B.group_count[g];
   const int off_s = B.shape_boff[s], nb = B.shape_boff[s + 1] - off_s;
   const int D = 3 * nb + 6, nv = nb + 2;
@@ -199,6 +199,23 @@ __global__ __launch_bounds__(256) void k_precond_mfma(BodyTables B, const double
       dst[2] = w[2];
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_precond_mfma(BodyTables B, const double* __restrict__ q,
+                                                     const double* __restrict__ x, double* __restrict__ z,
+                                                     double* __restrict__ yV, const int* __restrict__ spos,
+                                                     double* __restrict__ zs, const int* __restrict__ skip,
+                                                     int mirror) {
+  precond_mfma_body(B, q, x, z, yV, spos, zs, skip, mirror, hw_block());
+}
+
+// The same, fused over several suspensions (one PrecondArgs each).
+__global__ __launch_bounds__(256) void k_precond_mfma_fused(const PrecondArgs* __restrict__ a,
+                                                           const int* __restrict__ first, int ns) {
+  const int sidx = fused_suspension(first, ns, blockIdx.x);
+  const PrecondArgs& A = a[sidx];
+  precond_mfma_body(A.B, A.q, A.x, A.z, A.yV, A.spos, A.zs, A.skip, A.mirror,
+                    fused_block(A.grid, (int)blockIdx.x - first[sidx]));
 }
 
 __global__ __launch_bounds__(64) void k_precond(BodyTables B, const double* __restrict__ q,
@@ -766,9 +783,31 @@ int blob_positions(const BodyTables& b, const double* Y, const double* q, double
   return check_launch("k_blob_positions");
 }
 
+bool precond_fusable(const BodyTables& b, int maxdim) { return b.mfma && maxdim <= PREC_MFMA_MAXDIM; }
+
+void precond_describe(PrecondArgs& a, const BodyTables& b, const double* q, const double* x, double* z, double* yV,
+                      const int* spos, double* zs, const int* skip, int mirror) {
+  a.B = b;
+  a.q = q;
+  a.x = x;
+  a.z = z;
+  a.yV = yV;
+  a.spos = spos;
+  a.zs = zs;
+  a.skip = skip;
+  a.mirror = mirror;
+  a.grid = LocalGrid{b.n_groups, 1, 1};
+}
+
+int precond_fused(const PrecondArgs* dev_args, int ns, const int* first, int total, hipStream_t s) {
+  if (ns <= 0) return GDC_OK;
+  hipLaunchKernelGGL(k_precond_mfma_fused, dim3(total), dim3(256), 0, s, dev_args, first, ns);
+  return check_launch("k_precond_mfma_fused");
+}
+
 int precond_apply(const BodyTables& b, const double* q, const double* x, double* z, double* yV, const int* spos,
                   double* zs, int maxdim, hipStream_t s, const int* skip, int mirror) {
-  if (b.mfma && maxdim <= PREC_MFMA_MAXDIM) {
+  if (precond_fusable(b, maxdim)) {
     hipLaunchKernelGGL(k_precond_mfma, dim3(b.n_groups), dim3(256), 0, s, b, q, x, z, yV, spos, zs, skip, mirror);
     return check_launch("k_precond_mfma");
   }

@@ -421,17 +421,6 @@ __global__ void k_philox_normals(uint64_t seed, uint32_t c1, uint64_t step, uint
 }
 
 // ------------------------------------------------------------ pass C
-struct ProjParams {
-  int n0, n1, n2h;
-  double kf0, kf1, kf2;    // 2 pi / L_d
-  double inv_eta;
-  double invG;
-  // noise
-  uint64_t seed, step;
-  double sdiag, soff;      // sqrt(G var / 2) of diagonal / off-diagonal components
-  int channel;             // slip channel: the stress is given its mirror image in y
-};
-
 __device__ __forceinline__ int signed_index(int j, int n) { return j < n / 2 ? j : j - n; }
 
 // The stress spectrum W(k) at stored mode (j0, j1, j2) (not a removed one):
@@ -605,16 +594,16 @@ struct PlaneLds {
 // Z, row 2p has A(k) = (Z(k) + conj Z(N2-k))/2 and row 2p+1 has
 // B(k) = (Z(k) - conj Z(N2-k))/(2i), k < N2/2.  Then FFT along axis 1.
 template <typename R, int N1, int N2, int NTH>
-__global__ __launch_bounds__(NTH) void k_plane_fwd(const R* __restrict__ in, Cx<R>* __restrict__ Z,
-                                                   const Cx<R>* __restrict__ tw1g, const Cx<R>* __restrict__ tw2g,
-                                                   int n0, int tiled, const int* __restrict__ skip) {
+__device__ __forceinline__ void plane_fwd_body(const R* __restrict__ in, Cx<R>* __restrict__ Z,
+                                               const Cx<R>* __restrict__ tw1g, const Cx<R>* __restrict__ tw2g,
+                                               int n0, int tiled, const int* __restrict__ skip, const BlockIx& bi) {
   if (skip && *skip) return;
   using L = PlaneLds<N1, N2>;
   constexpr int H = L::H, NP = N1 / 2;
   __shared__ Cx<R> buf[L::SIZE];
   __shared__ Cx<R> tw1[N1], tw2[N2];
   const int tid = threadIdx.x;
-  const int i0 = blockIdx.x, c = blockIdx.y;
+  const int i0 = bi.x, c = bi.y;
   load_twiddles<R, N1, NTH>(tw1, tw1g);
   load_twiddles<R, N2, NTH>(tw2, tw2g);
   const R* src = in + (long long)c * n0 * N1 * N2 + field_plane_off(tiled, N1, N2, i0);
@@ -668,16 +657,32 @@ __global__ __launch_bounds__(NTH) void k_plane_fwd(const R* __restrict__ in, Cx<
 // one complex line Z(k) = A(k) + i B(k) with the Hermitian extensions (the
 // k = 0 term keeps real parts, the Nyquist term is zero) and inverse FFT.
 template <typename R, int N1, int N2, int NTH>
-__global__ __launch_bounds__(NTH) void k_plane_inv(const Cx<R>* __restrict__ Z, R* __restrict__ out,
+__global__ __launch_bounds__(NTH) void k_plane_fwd(const R* __restrict__ in, Cx<R>* __restrict__ Z,
                                                    const Cx<R>* __restrict__ tw1g, const Cx<R>* __restrict__ tw2g,
                                                    int n0, int tiled, const int* __restrict__ skip) {
+  plane_fwd_body<R, N1, N2, NTH>(in, Z, tw1g, tw2g, n0, tiled, skip, hw_block());
+}
+
+template <typename R, int N1, int N2, int NTH>
+__global__ __launch_bounds__(NTH) void k_plane_fwd_fused(const PlaneArgs* __restrict__ a,
+                                                         const int* __restrict__ first, int ns) {
+  const int sidx = fused_suspension(first, ns, blockIdx.x);
+  const PlaneArgs& A = a[sidx];
+  plane_fwd_body<R, N1, N2, NTH>((const R*)A.in, (Cx<R>*)A.out, (const Cx<R>*)A.tw1, (const Cx<R>*)A.tw2, A.n0,
+                                 A.tiled, A.skip, fused_block(A.grid, (int)blockIdx.x - first[sidx]));
+}
+
+template <typename R, int N1, int N2, int NTH>
+__device__ __forceinline__ void plane_inv_body(const Cx<R>* __restrict__ Z, R* __restrict__ out,
+                                               const Cx<R>* __restrict__ tw1g, const Cx<R>* __restrict__ tw2g,
+                                               int n0, int tiled, const int* __restrict__ skip, const BlockIx& bi) {
   if (skip && *skip) return;
   using L = PlaneLds<N1, N2>;
   constexpr int H = L::H, NP = N1 / 2;
   __shared__ Cx<R> buf[L::SIZE];
   __shared__ Cx<R> tw1[N1], tw2[N2];
   const int tid = threadIdx.x;
-  const int i0 = blockIdx.x, c = blockIdx.y;
+  const int i0 = bi.x, c = bi.y;
   load_twiddles<R, N1, NTH>(tw1, tw1g);
   load_twiddles<R, N2, NTH>(tw2, tw2g);
   const Cx<R>* src = Z + ((long long)c * n0 + i0) * H * N1;
@@ -735,15 +740,32 @@ __global__ __launch_bounds__(NTH) void k_plane_inv(const Cx<R>* __restrict__ Z, 
 // each component per workgroup.
 constexpr int TCP = 16;
 
+template <typename R, int N1, int N2, int NTH>
+__global__ __launch_bounds__(NTH) void k_plane_inv(const Cx<R>* __restrict__ Z, R* __restrict__ out,
+                                                   const Cx<R>* __restrict__ tw1g, const Cx<R>* __restrict__ tw2g,
+                                                   int n0, int tiled, const int* __restrict__ skip) {
+  plane_inv_body<R, N1, N2, NTH>(Z, out, tw1g, tw2g, n0, tiled, skip, hw_block());
+}
+
+template <typename R, int N1, int N2, int NTH>
+__global__ __launch_bounds__(NTH) void k_plane_inv_fused(const PlaneArgs* __restrict__ a,
+                                                         const int* __restrict__ first, int ns) {
+  const int sidx = fused_suspension(first, ns, blockIdx.x);
+  const PlaneArgs& A = a[sidx];
+  plane_inv_body<R, N1, N2, NTH>((const Cx<R>*)A.in, (R*)A.out, (const Cx<R>*)A.tw1, (const Cx<R>*)A.tw2, A.n0,
+                                 A.tiled, A.skip, fused_block(A.grid, (int)blockIdx.x - first[sidx]));
+}
+
 template <typename R, int N0, bool NOISE, int NTH>
-__global__ __launch_bounds__(NTH) void k_axis0_plane(Cx<R>* __restrict__ Z, const Cx<R>* __restrict__ twg,
-                                                    ProjParams P, const int* __restrict__ skip) {
+__device__ __forceinline__ void axis0_plane_body(Cx<R>* __restrict__ Z, const Cx<R>* __restrict__ twg,
+                                                 const ProjParams& P, const int* __restrict__ skip,
+                                                 const BlockIx& bi) {
   if (skip && *skip) return;
   constexpr int NLn = 3 * TCP, LS = N0 + 1;
   __shared__ Cx<R> buf[NLn * LS];
   __shared__ Cx<R> tw[N0];
   const int tid = threadIdx.x;
-  const int k2 = blockIdx.y, k1b = blockIdx.x * TCP;
+  const int k2 = bi.y, k1b = bi.x * TCP;
   const int nl = min(TCP, P.n1 - k1b);
   const int H = P.n2h, n1 = P.n1;
   load_twiddles<R, N0, NTH>(tw, twg);
@@ -809,6 +831,21 @@ __global__ __launch_bounds__(NTH) void k_axis0_plane(Cx<R>* __restrict__ Z, cons
         const int x = rest % N0, c = rest / N0;
         if (t < nl) Z[(((long long)c * N0 + x) * H + k2) * n1 + k1b + t] = z;
       });
+}
+
+template <typename R, int N0, bool NOISE, int NTH>
+__global__ __launch_bounds__(NTH) void k_axis0_plane(Cx<R>* __restrict__ Z, const Cx<R>* __restrict__ twg,
+                                                    ProjParams P, const int* __restrict__ skip) {
+  axis0_plane_body<R, N0, NOISE, NTH>(Z, twg, P, skip, hw_block());
+}
+
+template <typename R, int N0, int NTH>
+__global__ __launch_bounds__(NTH) void k_axis0_plane_fused(const ProjPlaneArgs* __restrict__ a,
+                                                           const int* __restrict__ first, int ns) {
+  const int sidx = fused_suspension(first, ns, blockIdx.x);
+  const ProjPlaneArgs& A = a[sidx];
+  axis0_plane_body<R, N0, false, NTH>((Cx<R>*)A.Z, (const Cx<R>*)A.tw, A.P, A.skip,
+                                      fused_block(A.grid, (int)blockIdx.x - first[sidx]));
 }
 
 // ------------------------------------------------------------ dispatch
@@ -1023,6 +1060,54 @@ int stokes_solve(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X,
   GDC_TRY(launch_inv1<R>(n1, Y, X, tw[1], n0, H, f.inv1, s, skip));
   GDC_TRY(launch_c2r<R>(n2, X, real, tw[2], n0, n1, g.tiled, f.c2r, s, skip));
   return GDC_OK;
+}
+
+bool stokes_fusable(const GridGeom& g, int precision) {
+  return precision != GDC_FP64 && plane_path<float>(g);
+}
+
+void stokes_describe(StokesArgs& a, const GridGeom& g, const void* const tw[3], void* real, void* X,
+                     const int* skip) {
+  const int n0 = g.n[0];
+  a.fwd = PlaneArgs{real, X, tw[1], tw[2], n0, g.tiled, skip, LocalGrid{n0, 3, 1}};
+  a.proj = ProjPlaneArgs{X, tw[0], proj_params(g), skip, LocalGrid{(g.n[1] + TCP - 1) / TCP, g.n2h, 1}};
+  a.inv = PlaneArgs{X, real, tw[1], tw[2], n0, g.tiled, skip, LocalGrid{n0, 3, 1}};
+}
+
+int stokes_fused(const GridGeom& g, const PlaneArgs* fwd, const ProjPlaneArgs* proj, const PlaneArgs* inv, int ns,
+                 const int* first_plane, int tot_plane, const int* first_proj, int tot_proj, hipStream_t s) {
+  if (ns <= 0) return GDC_OK;
+  using R = float;
+  const FftShape& f = g.fft;
+  const int n = g.n[1];
+  if (!plane_path<R>(g) || !nth_ok(f.plane_fwd, true) || !nth_ok(f.plane_inv, true) || !nth_ok(f.proj_plane, false))
+    return GDC_EINVAL;
+  const dim3 gp(tot_plane), gq(tot_proj);
+#define L_(K, N, T, ARGS, FIRST) hipLaunchKernelGGL((K<R, N, N, T>), (FIRST == first_plane ? gp : gq), dim3(T), 0, s, ARGS, FIRST, ns)
+#define SW_(K, NTH, ARGS, FIRST)                                                        \
+  switch (n) {                                                                          \
+    GDC_PLANE_SIZES(X_)                                                                 \
+    default: set_error("unsupported plane size"); return GDC_EINVAL;                    \
+  }
+#define X_(N) case N: if (f.plane_fwd == 1024) L_(k_plane_fwd_fused, N, 1024, fwd, first_plane); \
+                      else if (f.plane_fwd == 512) L_(k_plane_fwd_fused, N, 512, fwd, first_plane); \
+                      else L_(k_plane_fwd_fused, N, 256, fwd, first_plane); break;
+  SW_(k_plane_fwd_fused, f.plane_fwd, fwd, first_plane)
+#undef X_
+  GDC_TRY(check_launch("k_plane_fwd_fused"));
+#define X_(N) case N: if (f.proj_plane == 512) hipLaunchKernelGGL((k_axis0_plane_fused<R, N, 512>), gq, dim3(512), 0, s, proj, first_proj, ns); \
+                      else hipLaunchKernelGGL((k_axis0_plane_fused<R, N, 256>), gq, dim3(256), 0, s, proj, first_proj, ns); break;
+  SW_(k_axis0_plane_fused, f.proj_plane, proj, first_proj)
+#undef X_
+  GDC_TRY(check_launch("k_axis0_plane_fused"));
+#define X_(N) case N: if (f.plane_inv == 1024) L_(k_plane_inv_fused, N, 1024, inv, first_plane); \
+                      else if (f.plane_inv == 512) L_(k_plane_inv_fused, N, 512, inv, first_plane); \
+                      else L_(k_plane_inv_fused, N, 256, inv, first_plane); break;
+  SW_(k_plane_inv_fused, f.plane_inv, inv, first_plane)
+#undef X_
+#undef SW_
+#undef L_
+  return check_launch("k_plane_inv_fused");
 }
 
 template <typename R>

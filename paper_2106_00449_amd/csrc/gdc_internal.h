@@ -64,6 +64,42 @@ bool probe_active();
       hipLaunchKernelGGL(kernel, grid, block, shm, stream, __VA_ARGS__);                              \
   } while (0)
 
+// ------------------------------------------------------------ block coordinates
+// A kernel body takes its block coordinates as a BlockIx: from the hardware
+// in an ordinary launch, or, in a launch fused over several suspensions,
+// from the flat block index through the table of each suspension's first
+// block.  A block's arithmetic does not depend on which.
+struct BlockIx {
+  int x, y, z;
+  int gx, gy, gz;
+};
+__device__ __forceinline__ BlockIx hw_block() {
+  return BlockIx{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z,
+                 (int)gridDim.x,  (int)gridDim.y,  (int)gridDim.z};
+}
+
+// One suspension's grid in a fused launch.
+struct LocalGrid {
+  int gx, gy, gz;
+};
+
+// Suspension of flat block b: first[s] is suspension s's first block (first
+// is nondecreasing, first[0] = 0, ns entries).
+__device__ __forceinline__ int fused_suspension(const int* __restrict__ first, int ns, int b) {
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ BlockIx fused_block(const LocalGrid& g, int local) {
+  const int x = local % g.gx, yz = local / g.gx;
+  return BlockIx{x, yz % g.gy, yz / g.gy, g.gx, g.gy, g.gz};
+}
+
 // ------------------------------------------------------------ complex values
 
 template <typename R>
@@ -222,6 +258,54 @@ struct BodyTables {
 
 // ------------------------------------------------------------ launchers
 
+// Parameters of the projection pass: grid, wavenumber scales 2 pi / L_d,
+// 1/eta and 1/G; for the noise pass also the Philox key and counter and the
+// stress scales.
+struct ProjParams {
+  int n0, n1, n2h;
+  double kf0, kf1, kf2;    // 2 pi / L_d
+  double inv_eta;
+  double invG;
+  // noise
+  uint64_t seed, step;
+  double sdiag, soff;      // sqrt(G var / 2) of diagonal / off-diagonal components
+  int channel;             // slip channel: the stress is given its mirror image in y
+};
+
+// Arguments and grids of the three plane passes of one stokes_solve (FP32,
+// plane path), for launches fused over several suspensions of one grid
+// size and one set of workgroup sizes.
+struct PlaneArgs {
+  const void* in;
+  void* out;
+  const void *tw1, *tw2;
+  int n0, tiled;
+  const int* skip;
+  LocalGrid grid;
+};
+struct ProjPlaneArgs {
+  void* Z;
+  const void* tw;
+  ProjParams P;
+  const int* skip;
+  LocalGrid grid;
+};
+struct StokesArgs {
+  PlaneArgs fwd;
+  ProjPlaneArgs proj;
+  PlaneArgs inv;
+};
+// Whether stokes_solve of this geometry runs the FP32 plane path (the
+// fusable one).
+bool stokes_fusable(const GridGeom& g, int precision);
+void stokes_describe(StokesArgs& a, const GridGeom& g, const void* const tw[3], void* real, void* X,
+                     const int* skip);
+// fwd / inv and proj: ns argument sets each on the device; first_plane
+// (shared by the forward and inverse passes) and first_proj: the first
+// block of every suspension.
+int stokes_fused(const GridGeom& g, const PlaneArgs* fwd, const ProjPlaneArgs* proj, const PlaneArgs* inv, int ns,
+                 const int* first_plane, int tot_plane, const int* first_proj, int tot_proj, hipStream_t s);
+
 // FFT / projection / noise (fft.hip).  The three grid buffers hold 3 G values
 // of R each; `real` is the real-space field (spread output in, velocity out),
 // X and Y are the two transposed half-spectrum layouts.
@@ -280,6 +364,41 @@ template <typename R>
 int interp(const GridGeom& g, const double* r, const R* u, double* v, int M, double scale,
            const int* blob_body, const double* Y, const double* V, hipStream_t s,
            const int* skip = nullptr, const void* sorted = nullptr);
+// Arguments and grids of one spread / interp launch, for launches fused over
+// several suspensions of one precision (and, for spreading, one table
+// width wz8).  The fields follow spread's and interp's parameters.
+struct SpreadArgs {
+  GridGeom G;
+  TileGeom T;
+  const void* tabs;
+  const int4* order;
+  const double *lam, *lam_sorted;
+  void* f;
+  const int* skip;
+  LocalGrid grid;
+};
+struct InterpArgs {
+  GridGeom G;
+  const double* r;
+  const void* u;
+  double* v;
+  int M;
+  double scale;
+  const int* blob_body;
+  const double *Y, *V;
+  const int* skip;
+  const void* rec;
+  LocalGrid grid;
+};
+void spread_describe(SpreadArgs& a, const GridGeom& g, const TileGeom& t, const void* tabs, const int* order,
+                     const double* lam, const double* lam_sorted, void* f, const int* skip);
+template <typename R>
+int spread_fused(const SpreadArgs* dev_args, int ns, int wz8, const int* first, int total, hipStream_t s);
+void interp_describe(InterpArgs& a, const GridGeom& g, const double* r, const void* u, double* v, int M,
+                     double scale, const int* blob_body, const double* Y, const double* V, const int* skip,
+                     const void* sorted);
+template <typename R>
+int interp_fused(const InterpArgs* dev_args, int ns, const int* first, int total, hipStream_t s);
 // v (M x 3) and the NP differences J(r + dr_k) u - J(r) u into vd (M x NP x 3),
 // dr given per blob as M x NP x 3.
 template <typename R>
@@ -318,6 +437,24 @@ constexpr int PREC_MIN_GROUPS = 1024;
 int precond_apply(const BodyTables& b, const double* q, const double* x, double* z, double* yV,
                   const int* spos, double* zs, int maxdim, hipStream_t s, const int* skip = nullptr,
                   int mirror = 0);
+// The arguments and grid of one matrix-core precond_apply, for launches fused
+// over several suspensions.
+struct PrecondArgs {
+  BodyTables B;
+  const double* q;
+  const double* x;
+  double *z, *yV;
+  const int* spos;
+  double* zs;
+  const int* skip;
+  int mirror;
+  LocalGrid grid;
+};
+// Whether precond_apply runs on the matrix cores (the fusable kernel).
+bool precond_fusable(const BodyTables& b, int maxdim);
+void precond_describe(PrecondArgs& a, const BodyTables& b, const double* q, const double* x, double* z, double* yV,
+                      const int* spos, double* zs, const int* skip, int mirror);
+int precond_fused(const PrecondArgs* dev_args, int ns, const int* first, int total, hipStream_t s);
 // Slip channel: rs = [r; sigma(r)] (2M x 3), sigma(x, y, z) = (x, L1 - y, z).
 int mirror_positions(const double* r, int M, double L1, double* rs, hipStream_t s);
 // Blob forces lam in the spreading order of the last tile sort: zs[3 spos[i] +
@@ -403,6 +540,30 @@ constexpr size_t GM_STATUS_BYTES = 24;
 int arnoldi_orthogonalise(double* w, const double* V, long long ld, int k, long long n, double* partial1,
                           double* partial2, double* out, double* h1, double* h2s, hipStream_t s,
                           const int* skip, GmresState* st, int m, unsigned char* hstat);
+
+// The arguments and grids of one arnoldi_orthogonalise, for launches fused
+// over several suspensions (the fields follow arnoldi_orthogonalise's
+// parameters; shortv selects the kernels' chunk length).
+struct ArnoldiArgs {
+  double* w;
+  const double* V;
+  long long ld, n;
+  int k, m, nchunk, shortv;
+  double *partial1, *partial2, *out, *h1, *h2s;
+  const int* skip;
+  GmresState* st;
+  unsigned char* hstat;
+  LocalGrid g_dot, g_axpy, g_fin;
+};
+int arnoldi_describe(ArnoldiArgs& a, double* w, const double* V, long long ld, int k, long long n,
+                     double* partial1, double* partial2, double* out, double* h1, double* h2s, const int* skip,
+                     GmresState* st, int m, unsigned char* hstat);
+// One fused launch of each Arnoldi kernel over ns suspensions with the same
+// shortv: dev_args (ns entries) and, for each kernel, the first block of
+// every suspension (first_dot, first_axpy, first_fin: ns entries) on the
+// device; tot_* the total block counts.
+int arnoldi_fused(const ArnoldiArgs* dev_args, int ns, int shortv, const int* first_dot, int tot_dot,
+                  const int* first_axpy, int tot_axpy, const int* first_fin, int tot_fin, hipStream_t s);
 
 // y = H^-1 g over the cycle, then x += V y.
 int gm_finish_cycle(GmresState* st, double* x, const double* V, long long ld, long long n, hipStream_t s);

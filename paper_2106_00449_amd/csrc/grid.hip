@@ -102,6 +102,10 @@ __device__ __forceinline__ int xcd_block(int nb_padded) {
   const int per = nb_padded / NXCD;
   return (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
 }
+__device__ __forceinline__ int xcd_block(const BlockIx& bi) {
+  const int per = bi.gx / NXCD;
+  return (bi.x % NXCD) * per + bi.x / NXCD;
+}
 
 // Index of stencil point g + a (g in [0, n), 0 <= a <= n + 1).
 __device__ __forceinline__ int wrap(int g, int n) {
@@ -176,14 +180,14 @@ struct RigidTerm {
 // of the box and the stencils it reads stay in that XCD's L2; the arithmetic
 // of each blob is unchanged.
 template <typename R>
-__global__ __launch_bounds__(NT) void k_interp(GridGeom G, const double* __restrict__ r,
-                                               const R* __restrict__ u, double* __restrict__ v, int M,
-                                               double scale, RigidTerm K, const int* __restrict__ skip,
-                                               const SRec* __restrict__ rec) {
+__device__ __forceinline__ void interp_body(const GridGeom& G, const double* __restrict__ r,
+                                            const R* __restrict__ u, double* __restrict__ v, int M, double scale,
+                                            const RigidTerm& K, const int* __restrict__ skip,
+                                            const SRec* __restrict__ rec, const BlockIx& bi) {
   if (skip && *skip) return;
   // wave-uniform by construction; readfirstlane tells the compiler, so the
   // blob's record and body data come through scalar loads
-  const int place = xcd_block(gridDim.x) * WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int place = xcd_block(bi) * WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (place >= M) return;
   int blob;
@@ -262,6 +266,25 @@ __global__ __launch_bounds__(NT) void k_interp(GridGeom G, const double* __restr
     v[3LL * blob + 1] = o[1];
     v[3LL * blob + 2] = o[2];
   }
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT) void k_interp(GridGeom G, const double* __restrict__ r,
+                                               const R* __restrict__ u, double* __restrict__ v, int M,
+                                               double scale, RigidTerm K, const int* __restrict__ skip,
+                                               const SRec* __restrict__ rec) {
+  interp_body<R>(G, r, u, v, M, scale, K, skip, rec, hw_block());
+}
+
+// Averaging fused over several suspensions (one InterpArgs each).
+template <typename R>
+__global__ __launch_bounds__(NT) void k_interp_fused(const InterpArgs* __restrict__ a,
+                                                     const int* __restrict__ first, int ns) {
+  const int sidx = fused_suspension(first, ns, blockIdx.x);
+  const InterpArgs& A = a[sidx];
+  const RigidTerm K{A.blob_body, A.Y, A.V};
+  interp_body<R>(A.G, A.r, (const R*)A.u, A.v, A.M, A.scale, K, A.skip, (const SRec*)A.rec,
+                 fused_block(A.grid, (int)blockIdx.x - first[sidx]));
 }
 
 template <typename R, int NP>
@@ -789,10 +812,11 @@ __device__ __forceinline__ double read_lane(double v, int l) {
 }
 
 template <typename R, int WZ>
-__global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, const HitTab<R, WZ>* __restrict__ tabs,
-                                                   const int4* __restrict__ order, const double* __restrict__ lam,
-                                                   const double* __restrict__ lam_sorted, R* __restrict__ f,
-                                                   const int* __restrict__ skip) {
+__device__ __forceinline__ void spread_tab_body(const GridGeom& G, const TileGeom& T,
+                                                const HitTab<R, WZ>* __restrict__ tabs,
+                                                const int4* __restrict__ order, const double* __restrict__ lam,
+                                                const double* __restrict__ lam_sorted, R* __restrict__ f,
+                                                const int* __restrict__ skip, const BlockIx& bi) {
   if (skip && *skip) return;
   constexpr int HR = 64;                // hits per round
   constexpr int TX = 8, TZ = 32;
@@ -809,7 +833,7 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane((tid >> 6) & 3), half = __builtin_amdgcn_readfirstlane(tid >> 8);
   // workgroups take the tiles in the order of k_spread_prep, largest first
-  const int4 ord = order[blockIdx.x];
+  const int4 ord = order[bi.x];
   const int tl = ord.x, start = ord.y, cnt = ord.z;
   const int t2 = tl % T.nt[2], t1 = (tl / T.nt[2]) % T.nt[1], t0 = tl / (T.nt[1] * T.nt[2]);
   const int ts[3] = {t0 * T.T[0], t1 * T.T[1], t2 * T.T[2]};
@@ -947,6 +971,24 @@ __global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, cons
       for (int v = 0; zv + v < te[2]; ++v) f[idx + v] = srcv[v];
     }
   }
+}
+
+template <typename R, int WZ>
+__global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, const HitTab<R, WZ>* __restrict__ tabs,
+                                                   const int4* __restrict__ order, const double* __restrict__ lam,
+                                                   const double* __restrict__ lam_sorted, R* __restrict__ f,
+                                                   const int* __restrict__ skip) {
+  spread_tab_body<R, WZ>(G, T, tabs, order, lam, lam_sorted, f, skip, hw_block());
+}
+
+// Spreading fused over several suspensions (one SpreadArgs each).
+template <typename R, int WZ>
+__global__ __launch_bounds__(NTS) void k_spread_tab_fused(const SpreadArgs* __restrict__ a,
+                                                         const int* __restrict__ first, int ns) {
+  const int sidx = fused_suspension(first, ns, blockIdx.x);
+  const SpreadArgs& A = a[sidx];
+  spread_tab_body<R, WZ>(A.G, A.T, (const HitTab<R, WZ>*)A.tabs, A.order, A.lam, A.lam_sorted, (R*)A.f, A.skip,
+                         fused_block(A.grid, (int)blockIdx.x - first[sidx]));
 }
 
 __global__ void k_fill_zero(uint4* __restrict__ p, long long n16) {
@@ -1143,6 +1185,53 @@ int spread_prepare(const GridGeom& g, const TileGeom& t, const void* rec, const 
   return check_launch("k_tile_order");
 }
 
+void spread_describe(SpreadArgs& a, const GridGeom& g, const TileGeom& t, const void* tabs, const int* order,
+                     const double* lam, const double* lam_sorted, void* f, const int* skip) {
+  a.G = g;
+  a.T = t;
+  a.tabs = tabs;
+  a.order = (const int4*)order;
+  a.lam = lam;
+  a.lam_sorted = lam_sorted;
+  a.f = f;
+  a.skip = skip;
+  a.grid = LocalGrid{t.ntiles, 1, 1};
+}
+
+template <typename R>
+int spread_fused(const SpreadArgs* dev_args, int ns, int wz8, const int* first, int total, hipStream_t s) {
+  if (ns <= 0) return GDC_OK;
+  if (wz8)
+    hipLaunchKernelGGL((k_spread_tab_fused<R, 8>), dim3(total), dim3(NTS), 0, s, dev_args, first, ns);
+  else
+    hipLaunchKernelGGL((k_spread_tab_fused<R, 32>), dim3(total), dim3(NTS), 0, s, dev_args, first, ns);
+  return check_launch("k_spread_tab_fused");
+}
+
+void interp_describe(InterpArgs& a, const GridGeom& g, const double* r, const void* u, double* v, int M,
+                     double scale, const int* blob_body, const double* Y, const double* V, const int* skip,
+                     const void* sorted) {
+  a.G = g;
+  a.r = r;
+  a.u = u;
+  a.v = v;
+  a.M = M;
+  a.scale = scale;
+  a.blob_body = blob_body;
+  a.Y = Y;
+  a.V = V;
+  a.skip = skip;
+  a.rec = sorted;
+  a.grid = LocalGrid{(int)blocks_for(M), 1, 1};
+}
+
+template <typename R>
+int interp_fused(const InterpArgs* dev_args, int ns, const int* first, int total, hipStream_t s) {
+  if (ns <= 0) return GDC_OK;
+  hipLaunchKernelGGL((k_interp_fused<R>), dim3(total), dim3(NT), 0, s, dev_args, first, ns);
+  return check_launch("k_interp_fused");
+}
+
 template <typename R>
 int spread(const GridGeom& g, const TileGeom& t, const void* tabs, const int* order, const double* lam,
            const double* lam_sorted, R* f, hipStream_t s, const int* skip) {
@@ -1204,6 +1293,10 @@ template int spread<float>(const GridGeom&, const TileGeom&, const void*, const 
                            float*, hipStream_t, const int*);
 template int spread<double>(const GridGeom&, const TileGeom&, const void*, const int*, const double*, const double*,
                             double*, hipStream_t, const int*);
+template int spread_fused<float>(const SpreadArgs*, int, int, const int*, int, hipStream_t);
+template int spread_fused<double>(const SpreadArgs*, int, int, const int*, int, hipStream_t);
+template int interp_fused<float>(const InterpArgs*, int, const int*, int, hipStream_t);
+template int interp_fused<double>(const InterpArgs*, int, const int*, int, hipStream_t);
 template int interp<float>(const GridGeom&, const double*, const float*, double*, int, double, const int*,
                            const double*, const double*, hipStream_t, const int*, const void*);
 template int interp<double>(const GridGeom&, const double*, const double*, double*, int, double, const int*,

@@ -92,14 +92,15 @@ __device__ __forceinline__ void wave_reduce_to(double v, double* slot) {
 // row j = k (when kk = k + 1) is w . w.  One vector per block keeps every
 // load of a block independent.
 template <int EPT>
-__global__ __launch_bounds__(NT) void k_dot2d(const double* __restrict__ V, long long ld, int k,
-                                              const double* __restrict__ w, long long n,
-                                              double* __restrict__ partial, const int* __restrict__ skip) {
+__device__ __forceinline__ void dot2d_body(const double* __restrict__ V, long long ld, int k,
+                                           const double* __restrict__ w, long long n,
+                                           double* __restrict__ partial, const int* __restrict__ skip,
+                                           const BlockIx& bi) {
   if (skip && *skip) return;
   __shared__ double sh[NT / 64];
-  const int j = blockIdx.y;
+  const int j = bi.y;
   const double* v = j < k ? V + ld * j : w;
-  const long long lo = (long long)blockIdx.x * (EPT * NT);
+  const long long lo = (long long)bi.x * (EPT * NT);
   double a = 0.0;
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
@@ -111,8 +112,15 @@ __global__ __launch_bounds__(NT) void k_dot2d(const double* __restrict__ V, long
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int q = 0; q < NT / 64; ++q) t += sh[q];
-    partial[(long long)j * gridDim.x + blockIdx.x] = t;
+    partial[(long long)j * bi.gx + bi.x] = t;
   }
+}
+
+template <int EPT>
+__global__ __launch_bounds__(NT) void k_dot2d(const double* __restrict__ V, long long ld, int k,
+                                              const double* __restrict__ w, long long n,
+                                              double* __restrict__ partial, const int* __restrict__ skip) {
+  dot2d_body<EPT>(V, ld, k, w, n, partial, skip, hw_block());
 }
 
 // Reduces rows j < k of partial (ncol columns) into hs[j]: wave w takes
@@ -157,19 +165,20 @@ __device__ __forceinline__ void reduce_rows(const double* __restrict__ partial, 
 // and across the block's waves in a fixed order.  The dot rows go eight at a
 // time so that their loads are in flight together.
 template <int EPT>
-__global__ __launch_bounds__(NT) void k_axpy_dot(double* __restrict__ w, const double* __restrict__ V,
-                                                 long long ld, int k, const double* __restrict__ partial1,
-                                                 long long n, double* __restrict__ hout,
-                                                 double* __restrict__ partial2, const int* __restrict__ skip) {
+__device__ __forceinline__ void axpy_dot_body(double* __restrict__ w, const double* __restrict__ V,
+                                              long long ld, int k, const double* __restrict__ partial1,
+                                              long long n, double* __restrict__ hout,
+                                              double* __restrict__ partial2, const int* __restrict__ skip,
+                                              const BlockIx& bi) {
   if (skip && *skip) return;
   constexpr int JB = 8;
   __shared__ double hs[MAXK];
   __shared__ double wp[MAXK][NT / 64];
-  reduce_rows(partial1, k, gridDim.x, hs);
+  reduce_rows(partial1, k, bi.gx, hs);
   __syncthreads();
-  if (blockIdx.x == 0)
+  if (bi.x == 0)
     for (int j = threadIdx.x; j < k; j += NT) hout[j] = hs[j];
-  const long long lo = (long long)blockIdx.x * (EPT * NT);
+  const long long lo = (long long)bi.x * (EPT * NT);
   double xw[EPT];
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
@@ -209,8 +218,16 @@ __global__ __launch_bounds__(NT) void k_axpy_dot(double* __restrict__ w, const d
   for (int j = threadIdx.x; j <= k; j += NT) {
     double t = 0.0;
     for (int q = 0; q < NT / 64; ++q) t += wp[j][q];
-    partial2[(long long)j * gridDim.x + blockIdx.x] = t;
+    partial2[(long long)j * bi.gx + bi.x] = t;
   }
+}
+
+template <int EPT>
+__global__ __launch_bounds__(NT) void k_axpy_dot(double* __restrict__ w, const double* __restrict__ V,
+                                                 long long ld, int k, const double* __restrict__ partial1,
+                                                 long long n, double* __restrict__ hout,
+                                                 double* __restrict__ partial2, const int* __restrict__ skip) {
+  axpy_dot_body<EPT>(w, V, ld, k, partial1, n, hout, partial2, skip, hw_block());
 }
 
 // Column k of the Hessenberg matrix from the Gram-Schmidt coefficients, by
@@ -302,11 +319,12 @@ __device__ void gm_column_block(GmresState* st, int k, int m, const double* __re
 // `done` before it may set it, and an iteration past the end of a cycle only
 // writes a basis vector that is never used.
 template <int EPT>
-__global__ __launch_bounds__(NT) void k_ortho_finish2(const double* __restrict__ w, const double* __restrict__ V,
-                                                      long long ld, int k, const double* __restrict__ partial2,
-                                                      int ncol, long long n, double* __restrict__ out,
-                                                      double* __restrict__ hout, GmresState* st, int m,
-                                                      const double* __restrict__ h1, unsigned char* hstat) {
+__device__ __forceinline__ void ortho_finish2_body(const double* __restrict__ w, const double* __restrict__ V,
+                                                   long long ld, int k, const double* __restrict__ partial2,
+                                                   int ncol, long long n, double* __restrict__ out,
+                                                   double* __restrict__ hout, GmresState* st, int m,
+                                                   const double* __restrict__ h1, unsigned char* hstat,
+                                                   const BlockIx& bi) {
   __shared__ double hs[MAXK];
   __shared__ double scale;
   reduce_rows(partial2, k + 1, ncol, hs);
@@ -317,15 +335,15 @@ __global__ __launch_bounds__(NT) void k_ortho_finish2(const double* __restrict__
     const double nrm2 = hs[k] - hh;
     scale = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
   }
-  const int nchunk = gridDim.x - 1;
-  if (blockIdx.x == nchunk) {
+  const int nchunk = bi.gx - 1;
+  if (bi.x == nchunk) {
     for (int j = threadIdx.x; j <= k; j += NT) hout[j] = hs[j];
     if (st) gm_column_block(st, k - 1, m, h1, hs, hstat);
     return;
   }
   __syncthreads();
   const double a = scale;
-  const long long lo = (long long)blockIdx.x * (EPT * NT);
+  const long long lo = (long long)bi.x * (EPT * NT);
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
     const long long e = lo + threadIdx.x + m * NT;
@@ -336,6 +354,45 @@ __global__ __launch_bounds__(NT) void k_ortho_finish2(const double* __restrict__
       out[e] = a * x;
     }
   }
+}
+
+template <int EPT>
+__global__ __launch_bounds__(NT) void k_ortho_finish2(const double* __restrict__ w, const double* __restrict__ V,
+                                                      long long ld, int k, const double* __restrict__ partial2,
+                                                      int ncol, long long n, double* __restrict__ out,
+                                                      double* __restrict__ hout, GmresState* st, int m,
+                                                      const double* __restrict__ h1, unsigned char* hstat) {
+  ortho_finish2_body<EPT>(w, V, ld, k, partial2, ncol, n, out, hout, st, m, h1, hstat, hw_block());
+}
+
+// The three Arnoldi launches fused over several suspensions (one ArnoldiArgs
+// each): block b belongs to the suspension s with first[s] <= b <
+// first[s + 1], and runs that suspension's block b - first[s].
+template <int EPT>
+__global__ __launch_bounds__(NT) void k_dot2d_fused(const ArnoldiArgs* __restrict__ a,
+                                                    const int* __restrict__ first, int ns) {
+  const int sidx = fused_suspension(first, ns, blockIdx.x);
+  const ArnoldiArgs& A = a[sidx];
+  dot2d_body<EPT>(A.V, A.ld, A.k, A.w, A.n, A.partial1, A.skip,
+                  fused_block(A.g_dot, (int)blockIdx.x - first[sidx]));
+}
+
+template <int EPT>
+__global__ __launch_bounds__(NT) void k_axpy_dot_fused(const ArnoldiArgs* __restrict__ a,
+                                                       const int* __restrict__ first, int ns) {
+  const int sidx = fused_suspension(first, ns, blockIdx.x);
+  const ArnoldiArgs& A = a[sidx];
+  axpy_dot_body<EPT>(A.w, A.V, A.ld, A.k, A.partial1, A.n, A.h1, A.partial2, A.skip,
+                     fused_block(A.g_axpy, (int)blockIdx.x - first[sidx]));
+}
+
+template <int EPT>
+__global__ __launch_bounds__(NT) void k_ortho_finish2_fused(const ArnoldiArgs* __restrict__ a,
+                                                            const int* __restrict__ first, int ns) {
+  const int sidx = fused_suspension(first, ns, blockIdx.x);
+  const ArnoldiArgs& A = a[sidx];
+  ortho_finish2_body<EPT>(A.w, A.V, A.ld, A.k, A.partial2, A.nchunk, A.n, A.out, A.h2s, A.st, A.m, A.h1,
+                          A.hstat, fused_block(A.g_fin, (int)blockIdx.x - first[sidx]));
 }
 
 // w += sign * sum_j h_j V_j
@@ -522,9 +579,9 @@ int ortho_finish(const double* w, const double* V, long long ld, int k, const do
   return check_launch("k_ortho_finish");
 }
 
-int arnoldi_orthogonalise(double* w, const double* V, long long ld, int k, long long n, double* partial1,
-                          double* partial2, double* out, double* h1, double* h2s, hipStream_t s,
-                          const int* skip, GmresState* st, int m, unsigned char* hstat) {
+int arnoldi_describe(ArnoldiArgs& a, double* w, const double* V, long long ld, int k, long long n,
+                     double* partial1, double* partial2, double* out, double* h1, double* h2s, const int* skip,
+                     GmresState* st, int m, unsigned char* hstat) {
   if (k < 1 || k + 1 >= MAXK) {
     set_error("arnoldi_orthogonalise: basis size out of range");
     return GDC_EINVAL;
@@ -540,27 +597,67 @@ int arnoldi_orthogonalise(double* w, const double* V, long long ld, int k, long 
     set_error("arnoldi_orthogonalise: column out of range");
     return GDC_EINVAL;
   }
-  if (shortv) {
-    hipLaunchKernelGGL(k_dot2d<1>, dim3(nchunk, k), dim3(NT), 0, s, V, ld, k, (const double*)w, n, partial1, skip);
+  a.w = w;
+  a.V = V;
+  a.ld = ld;
+  a.n = n;
+  a.k = k;
+  a.m = m;
+  a.nchunk = (int)nchunk;
+  a.shortv = shortv ? 1 : 0;
+  a.partial1 = partial1;
+  a.partial2 = partial2;
+  a.out = out;
+  a.h1 = h1;
+  a.h2s = h2s;
+  a.skip = skip;
+  a.st = st;
+  a.hstat = hstat;
+  a.g_dot = LocalGrid{(int)nchunk, k, 1};
+  a.g_axpy = LocalGrid{(int)nchunk, 1, 1};
+  // the finishing pass is a plain scaled update: with short vectors, longer
+  // chunks and fewer blocks reducing the partial sums
+  const unsigned nfin = shortv ? (unsigned)((n + EPT_LONG * NT - 1) / (EPT_LONG * NT)) : nchunk;
+  a.g_fin = LocalGrid{(int)nfin + 1, 1, 1};
+  return GDC_OK;
+}
+
+int arnoldi_orthogonalise(double* w, const double* V, long long ld, int k, long long n, double* partial1,
+                          double* partial2, double* out, double* h1, double* h2s, hipStream_t s,
+                          const int* skip, GmresState* st, int m, unsigned char* hstat) {
+  ArnoldiArgs a;
+  GDC_TRY(arnoldi_describe(a, w, V, ld, k, n, partial1, partial2, out, h1, h2s, skip, st, m, hstat));
+  const dim3 gd(a.g_dot.gx, a.g_dot.gy), ga(a.g_axpy.gx), gf(a.g_fin.gx);
+  if (a.shortv) {
+    hipLaunchKernelGGL(k_dot2d<1>, gd, dim3(NT), 0, s, V, ld, k, (const double*)w, n, partial1, skip);
     GDC_TRY(check_launch("k_dot2d"));
-    hipLaunchKernelGGL(k_axpy_dot<1>, dim3(nchunk), dim3(NT), 0, s, w, V, ld, k, partial1, n, h1, partial2, skip);
-    GDC_TRY(check_launch("k_axpy_dot"));
-    // the finishing pass is a plain scaled update: longer chunks, fewer
-    // blocks reducing the partial sums
-    const unsigned nfin = (unsigned)((n + EPT_LONG * NT - 1) / (EPT_LONG * NT));
-    hipLaunchKernelGGL(k_ortho_finish2<EPT_LONG>, dim3(nfin + 1), dim3(NT), 0, s, w, V, ld, k, partial2, (int)nchunk,
-                       n, out, h2s, st, m, (const double*)h1, hstat);
+    hipLaunchKernelGGL(k_axpy_dot<1>, ga, dim3(NT), 0, s, w, V, ld, k, partial1, n, h1, partial2, skip);
   } else {
-    hipLaunchKernelGGL(k_dot2d<EPT_LONG>, dim3(nchunk, k), dim3(NT), 0, s, V, ld, k, (const double*)w, n, partial1,
-                       skip);
+    hipLaunchKernelGGL(k_dot2d<EPT_LONG>, gd, dim3(NT), 0, s, V, ld, k, (const double*)w, n, partial1, skip);
     GDC_TRY(check_launch("k_dot2d"));
-    hipLaunchKernelGGL(k_axpy_dot<EPT_LONG>, dim3(nchunk), dim3(NT), 0, s, w, V, ld, k, partial1, n, h1, partial2,
-                       skip);
-    GDC_TRY(check_launch("k_axpy_dot"));
-    hipLaunchKernelGGL(k_ortho_finish2<EPT_LONG>, dim3(nchunk + 1), dim3(NT), 0, s, w, V, ld, k, partial2,
-                       (int)nchunk, n, out, h2s, st, m, (const double*)h1, hstat);
+    hipLaunchKernelGGL(k_axpy_dot<EPT_LONG>, ga, dim3(NT), 0, s, w, V, ld, k, partial1, n, h1, partial2, skip);
   }
+  GDC_TRY(check_launch("k_axpy_dot"));
+  hipLaunchKernelGGL(k_ortho_finish2<EPT_LONG>, gf, dim3(NT), 0, s, w, V, ld, k, partial2, a.nchunk, n, out, h2s,
+                     st, m, (const double*)h1, hstat);
   return check_launch("k_ortho_finish2");
+}
+
+int arnoldi_fused(const ArnoldiArgs* dev_args, int ns, int shortv, const int* first_dot, int tot_dot,
+                  const int* first_axpy, int tot_axpy, const int* first_fin, int tot_fin, hipStream_t s) {
+  if (ns <= 0) return GDC_OK;
+  if (shortv) {
+    hipLaunchKernelGGL(k_dot2d_fused<1>, dim3(tot_dot), dim3(NT), 0, s, dev_args, first_dot, ns);
+    GDC_TRY(check_launch("k_dot2d_fused"));
+    hipLaunchKernelGGL(k_axpy_dot_fused<1>, dim3(tot_axpy), dim3(NT), 0, s, dev_args, first_axpy, ns);
+  } else {
+    hipLaunchKernelGGL(k_dot2d_fused<EPT_LONG>, dim3(tot_dot), dim3(NT), 0, s, dev_args, first_dot, ns);
+    GDC_TRY(check_launch("k_dot2d_fused"));
+    hipLaunchKernelGGL(k_axpy_dot_fused<EPT_LONG>, dim3(tot_axpy), dim3(NT), 0, s, dev_args, first_axpy, ns);
+  }
+  GDC_TRY(check_launch("k_axpy_dot_fused"));
+  hipLaunchKernelGGL(k_ortho_finish2_fused<EPT_LONG>, dim3(tot_fin), dim3(NT), 0, s, dev_args, first_fin, ns);
+  return check_launch("k_ortho_finish2_fused");
 }
 
 

@@ -65,11 +65,14 @@ class Result:
 
 
 class LibraryExecutor:
-    """Runs requests on the HIP library (one handle and stream each)."""
+    """Runs requests on the HIP library (one handle and stream each).  With
+    fusion, the suspensions' GMRES iterations are launched fused: one launch
+    per kernel for all the ready suspensions of a grid size."""
 
-    def __init__(self):
+    def __init__(self, fusion=False):
         import paper_2106_00449_amd as g
         self.g = g
+        self.fusion = bool(fusion)
 
     def footprint(self, req):
         return self.g.footprint(**req.kwargs)
@@ -77,6 +80,8 @@ class LibraryExecutor:
     def open(self, req):
         s = self.g.Suspension(**req.kwargs)
         s.set_state(req.Y0, req.q0)
+        if self.fusion:
+            s.fusion = True
         return s
 
     def step(self, handles, steps, until, max_ms):

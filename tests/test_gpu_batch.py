@@ -227,3 +227,63 @@ def test_graph_replay_equals_eager_launches(lib, k):
         s.close()
     for a, b in zip(out[False], out[True]):
         assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
+def _fuse_mix():
+    # four fusable suspensions (FP32, plane-path grids, matrix-core
+    # preconditioner) in two groups by grid size, and an FP64 one that runs
+    # unfused beside them
+    return [
+        wl.small_case("f_rods", n_bodies=12, n=32, L=24.0, shapes=[wl.rod(5)], precision="fp32", seed=31,
+                      dt=0.005),
+        wl.small_case("f_mixed", n_bodies=20, n=32, L=28.0, shapes=[wl.rod(3), wl.tetrahedron()],
+                      precision="fp32", seed=32, dt=0.005, const_force=(0.0, 0.0, 1.0, 0.0, 0.0, 0.0)),
+        wl.small_case("f_boom", n_bodies=7, n=32, L=20.0, shapes=[wl.boomerang()], precision="fp32", seed=33,
+                      dt=0.005),
+        wl.small_case("f_48", n_bodies=16, n=48, L=32.0, shapes=[wl.rod(5)], precision="fp32", seed=34,
+                      dt=0.005),
+        wl.small_case("f_64", n_bodies=6, n=32, L=20.0, shapes=[wl.rod(3)], precision="fp64", seed=35,
+                      dt=0.005),
+    ]
+
+
+@pytest.mark.parametrize("until", ["all", "any"])
+def test_fused_batch_equals_each_alone(lib, until):
+    # GMRES iterations launched once per kernel for all ready suspensions
+    # (each at its own Krylov column: restart 4 makes cycles end at
+    # different times) give every suspension the result of stepping it
+    # alone, bit for bit
+    ws = _fuse_mix()
+    n_steps = [3, 2, 4, 3, 2]
+    kw = dict(gmres_tol=1e-6, gmres_restart=4, gmres_maxit=400)
+    ref = []
+    for w, k in zip(ws, n_steps):
+        Y, q = wl.initial_state(w)
+        s = lib.Suspension(**wl.library_kwargs(w, **kw))
+        s.step(Y, q, k)
+        s.close()
+        ref.append((Y, q))
+    _say("fused batch", until)
+    ss = []
+    for w in ws:
+        s = lib.Suspension(**wl.library_kwargs(w, **kw))
+        Y, q = wl.initial_state(w)
+        s.set_state(Y, q)
+        s.fusion = True
+        assert s.fusion
+        ss.append(s)
+    left = list(n_steps)
+    fused = [0] * len(ws)
+    while any(left):
+        left, stats, _ = lib.batch_step(ss, left, until=until)
+        for i, x in enumerate(stats):
+            assert x["status"] in (lib.GDC_OK,), (ws[i].name, x)
+            fused[i] += x["fused_iterations"]
+    for i, (s, w) in enumerate(zip(ss, ws)):
+        Y, q = s.get_state()
+        assert np.array_equal(Y, ref[i][0]), w.name
+        assert np.array_equal(q, ref[i][1]), w.name
+        s.close()
+    # every FP32 suspension had its iterations fused; the FP64 one none
+    assert all(f > 0 for f in fused[:4]), fused
+    assert fused[4] == 0, fused
