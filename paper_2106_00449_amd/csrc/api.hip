@@ -418,11 +418,18 @@ struct gdc_handle {
   // Launches fused over suspensions (gdc_set_fusion): inside gdc_batch_step a
   // fused handle does not launch its GMRES iterations itself; the call
   // launches each iteration kernel once for all the handles that are ready
-  // (fuse_live while such a call runs).  join_ev marks the handle's stream
-  // for the shared stream of the fused launches.
+  // (fuse_live while such a call runs), on a stream of its own per group.
+  // The two streams are joined only where work crosses: own_dirty says the
+  // handle's stream holds work the fused stream has not waited for (join_ev
+  // marks it); fuse_pending says the handle's stream has not yet waited for
+  // its last fused iteration, whose end gm_ev[fuse_evslot] marks on fuse_on.
   bool fuse = false;
   bool fuse_live = false;
   hipEvent_t join_ev = nullptr;
+  bool own_dirty = true;
+  bool fuse_pending = false;
+  int fuse_evslot = 0;
+  hipStream_t fuse_on = nullptr;
 
   bool dry = false;               // footprint query: count device bytes, touch no device
   size_t dev_bytes = 0;           // device memory held by the handle
@@ -739,7 +746,7 @@ int solve_advance(gdc_handle* h, bool block, int& adv) {
       if (!sv.queued) {
         if (fusable_now(h)) {
           // gdc_batch_step launches it with the other ready suspensions and
-          // then records gm_ev[(k + 1) & 1] on this handle's stream
+          // then records gm_ev[(k + 1) & 1] on the fused launches' stream
           sv.queued = sv.deferred = true;
           adv = ADV_BLOCKED;
           return GDC_OK;
@@ -1619,10 +1626,14 @@ int gdc_get_state(gdc_handle* h, double* Y, double* q, int memspace) {
 
 namespace {
 
-// Staging of fused launches: argument tables go from a pinned host slot to a
-// device slot in one copy on a stream shared by the fused launches of one
-// GPU; slots are used in turn, and a slot is reused only once its event
-// (recorded after the launches that read it) has completed.
+// Staging of fused launches.  Each group of handles that share every kernel
+// instantiation (its key) launches on a stream of its own, one of up to
+// FUSE_STREAMS per GPU, so the groups of different grid sizes overlap.  The
+// argument tables go from a pinned host slot to a device slot in one copy
+// on that stream; a stream's slots are used in turn, and a slot is reused
+// only once its event (recorded after the launches that read it) has
+// completed.
+using FuseKey = std::array<int, 8>;
 struct FuseSlot {
   void* host = nullptr;
   void* dev = nullptr;
@@ -1630,23 +1641,40 @@ struct FuseSlot {
   hipEvent_t ev = nullptr;
   bool used = false;
 };
-struct FuseDevice {
+struct FuseStream {
   hipStream_t stream = nullptr;
   std::vector<FuseSlot> slots;
   int next = 0;
 };
+struct FuseDevice {
+  std::vector<FuseStream> streams;
+  std::map<FuseKey, int> of_key;
+};
 std::mutex g_fuse_mutex;
 std::map<int, FuseDevice> g_fuse;
+constexpr int FUSE_STREAMS = 4;
 constexpr int FUSE_SLOTS = 8;
 
-int fuse_slot(int device, size_t bytes, FuseDevice*& fd, FuseSlot*& slot) {
-  fd = &g_fuse[device];
-  if (!fd->stream) {
-    GDC_HIP(hipStreamCreateWithFlags(&fd->stream, hipStreamNonBlocking));
-    fd->slots.resize(FUSE_SLOTS);
+// The stream of group `key` on `device` (the current device) and its next
+// staging slot, with room for `bytes`.
+int fuse_slot(int device, const FuseKey& key, size_t bytes, FuseStream*& fst, FuseSlot*& slot) {
+  FuseDevice& fd = g_fuse[device];
+  auto it = fd.of_key.find(key);
+  int si;
+  if (it != fd.of_key.end()) {
+    si = it->second;
+  } else {
+    si = (int)(fd.of_key.size() % FUSE_STREAMS);
+    fd.of_key[key] = si;
   }
-  slot = &fd->slots[fd->next];
-  fd->next = (fd->next + 1) % FUSE_SLOTS;
+  if ((int)fd.streams.size() <= si) fd.streams.resize(si + 1);
+  fst = &fd.streams[si];
+  if (!fst->stream) {
+    GDC_HIP(hipStreamCreateWithFlags(&fst->stream, hipStreamNonBlocking));
+    fst->slots.resize(FUSE_SLOTS);
+  }
+  slot = &fst->slots[fst->next];
+  fst->next = (fst->next + 1) % FUSE_SLOTS;
   if (slot->used) GDC_HIP(hipEventSynchronize(slot->ev));   // its launches are long done in practice
   if (!slot->ev) GDC_HIP(hipEventCreateWithFlags(&slot->ev, hipEventDisableTiming));
   if (slot->cap < bytes) {
@@ -1662,8 +1690,25 @@ int fuse_slot(int device, size_t bytes, FuseDevice*& fd, FuseSlot*& slot) {
   return GDC_OK;
 }
 
+// Whether the handle's next advance queues nothing on its own stream: inside
+// a GMRES cycle it only defers its next iteration to a fused launch or polls
+// the status of one.
+bool fused_only(const gdc_handle* h) {
+  return h->sr.phase == StepRun::SOLVE && h->sv.phase == SolveRun::ITER && fusable_now(h);
+}
+
+// The handle's stream waits for its last fused iteration (before the handle
+// queues work of its own there).
+int join_fused(gdc_handle* h) {
+  if (!h->fuse_pending) return GDC_OK;
+  GDC_HIP(hipStreamWaitEvent(h->stream, h->gm_ev[h->fuse_evslot], 0));
+  h->fuse_pending = false;
+  return GDC_OK;
+}
+
 // Byte layout of one fused iteration's tables: per kernel an argument array
-// (ns entries) and the first block of every suspension (ns ints).
+// (ns entries) and the first block of every suspension (ns ints; for
+// spreading, one table per spreading-table width).
 struct FuseLayout {
   size_t pre, spr, fwd, prj, inv, itp, arn;            // argument arrays
   size_t f_pre, f_spr, f_pl, f_prj, f_itp, f_dot, f_axp, f_fin;   // first-block arrays
@@ -1697,16 +1742,17 @@ struct FuseLayout {
 int blocks_of(const LocalGrid& g) { return g.gx * g.gy * g.gz; }
 
 // One fused GMRES iteration for handles that can share every kernel
-// instantiation (same grid, workgroup sizes, table width and vector-length
-// class), each at its own Krylov column: the same arithmetic, per
-// suspension, as queue_iteration.
-int fuse_group(const std::vector<gdc_handle*>& g) {
+// instantiation but spreading's (same grid, workgroup sizes and
+// vector-length class), each at its own Krylov column: the same arithmetic,
+// per suspension, as queue_iteration.  g lists the handles with 8-wide
+// spreading tables first; spreading is launched once per table width.
+int fuse_group(const FuseKey& key, const std::vector<gdc_handle*>& g) {
   const int ns = (int)g.size();
   const FuseLayout L(ns);
   std::lock_guard<std::mutex> lk(g_fuse_mutex);
-  FuseDevice* fd = nullptr;
+  FuseStream* fst = nullptr;
   FuseSlot* slot = nullptr;
-  GDC_TRY(fuse_slot(g[0]->device, L.bytes, fd, slot));
+  GDC_TRY(fuse_slot(g[0]->device, key, L.bytes, fst, slot));
   unsigned char* hb = (unsigned char*)slot->host;
   unsigned char* db = (unsigned char*)slot->dev;
   auto* pa = (PrecondArgs*)(hb + L.pre);
@@ -1724,7 +1770,8 @@ int fuse_group(const std::vector<gdc_handle*>& g) {
   int* f_dot = (int*)(hb + L.f_dot);
   int* f_axp = (int*)(hb + L.f_axp);
   int* f_fin = (int*)(hb + L.f_fin);
-  int t_pre = 0, t_spr = 0, t_pl = 0, t_prj = 0, t_itp = 0, t_dot = 0, t_axp = 0, t_fin = 0;
+  int t_pre = 0, t_pl = 0, t_prj = 0, t_itp = 0, t_dot = 0, t_axp = 0, t_fin = 0;
+  int n8 = 0, t_spr[2] = {0, 0};   // spreading: handles with 8-wide tables, blocks per width
   for (int j = 0; j < ns; ++j) {
     gdc_handle* h = g[j];
     SolveRun& sv = h->sv;
@@ -1747,8 +1794,10 @@ int fuse_group(const std::vector<gdc_handle*>& g) {
                              h->hdev + HCOLS, skip, h->gm, h->restart, h->gm_host_dev + 32 * ((k + 1) & 1)));
     f_pre[j] = t_pre;
     t_pre += blocks_of(pa[j].grid);
-    f_spr[j] = t_spr;
-    t_spr += blocks_of(sa[j].grid);
+    const int w = h->tg.wz8 ? 0 : 1;
+    if (w == 0) ++n8;
+    f_spr[j] = t_spr[w];
+    t_spr[w] += blocks_of(sa[j].grid);
     f_pl[j] = t_pl;
     t_pl += blocks_of(fa[j].grid);
     f_prj[j] = t_prj;
@@ -1762,18 +1811,24 @@ int fuse_group(const std::vector<gdc_handle*>& g) {
     f_fin[j] = t_fin;
     t_fin += blocks_of(aa[j].g_fin);
   }
-  hipStream_t fs = fd->stream;
-  // the fused launches follow each handle's queued work
+  hipStream_t fs = fst->stream;
+  // the fused launches follow what each handle queued on its own stream
+  // since the last join, and its previous fused iteration
   for (gdc_handle* h : g) {
-    GDC_HIP(hipEventRecord(h->join_ev, h->stream));
-    GDC_HIP(hipStreamWaitEvent(fs, h->join_ev, 0));
+    if (h->own_dirty) {
+      GDC_HIP(hipEventRecord(h->join_ev, h->stream));
+      GDC_HIP(hipStreamWaitEvent(fs, h->join_ev, 0));
+      h->own_dirty = false;
+    }
+    if (h->fuse_pending && h->fuse_on != fs) GDC_HIP(hipStreamWaitEvent(fs, h->gm_ev[h->fuse_evslot], 0));
   }
   GDC_HIP(hipMemcpyAsync(db, hb, L.bytes, hipMemcpyHostToDevice, fs));
-  const gdc_handle* h0 = g[0];
+  const int* df_spr = (const int*)(db + L.f_spr);
+  const auto* dsa = (const SpreadArgs*)(db + L.spr);
   GDC_TRY(precond_fused((const PrecondArgs*)(db + L.pre), ns, (const int*)(db + L.f_pre), t_pre, fs));
-  GDC_TRY(spread_fused<float>((const SpreadArgs*)(db + L.spr), ns, h0->tg.wz8, (const int*)(db + L.f_spr), t_spr,
-                              fs));
-  GDC_TRY(stokes_fused(h0->geom, (const PlaneArgs*)(db + L.fwd), (const ProjPlaneArgs*)(db + L.prj),
+  GDC_TRY(spread_fused<float>(dsa, n8, 1, df_spr, t_spr[0], fs));
+  GDC_TRY(spread_fused<float>(dsa + n8, ns - n8, 0, df_spr + n8, t_spr[1], fs));
+  GDC_TRY(stokes_fused(g[0]->geom, (const PlaneArgs*)(db + L.fwd), (const ProjPlaneArgs*)(db + L.prj),
                        (const PlaneArgs*)(db + L.inv), ns, (const int*)(db + L.f_pl), t_pl,
                        (const int*)(db + L.f_prj), t_prj, fs));
   GDC_TRY(interp_fused<float>((const InterpArgs*)(db + L.itp), ns, (const int*)(db + L.f_itp), t_itp, fs));
@@ -1781,11 +1836,15 @@ int fuse_group(const std::vector<gdc_handle*>& g) {
                         (const int*)(db + L.f_axp), t_axp, (const int*)(db + L.f_fin), t_fin, fs));
   GDC_HIP(hipEventRecord(slot->ev, fs));
   slot->used = true;
-  // each handle's later work follows the fused launches; gm_ev marks the
-  // iteration's status as solve_advance expects
+  // gm_ev marks the iteration's status, as solve_advance expects, on the
+  // fused stream; the handle's own stream waits for it only before the
+  // handle's next work of its own (join_fused)
   for (gdc_handle* h : g) {
-    GDC_HIP(hipStreamWaitEvent(h->stream, slot->ev, 0));
-    GDC_HIP(hipEventRecord(h->gm_ev[(h->sv.k + 1) & 1], h->stream));
+    const int st = (h->sv.k + 1) & 1;
+    GDC_HIP(hipEventRecord(h->gm_ev[st], fs));
+    h->fuse_pending = true;
+    h->fuse_evslot = st;
+    h->fuse_on = fs;
     h->sv.deferred = false;
     ++h->n_fused;
   }
@@ -1793,18 +1852,17 @@ int fuse_group(const std::vector<gdc_handle*>& g) {
 }
 
 // Launches the deferred iterations of hs: one fused launch per kernel for
-// each group of handles that share every kernel instantiation.  Returns the
-// number of handles launched in `launched`.
+// each group of handles that share every kernel instantiation but
+// spreading's.  Returns the number of handles launched in `launched`.
 int fuse_flush(gdc_handle* const* hs, int nh, int& launched) {
   launched = 0;
-  std::map<std::array<int, 9>, std::vector<gdc_handle*>> groups;
+  std::map<FuseKey, std::vector<gdc_handle*>> groups;
   for (int i = 0; i < nh; ++i) {
     gdc_handle* h = hs[i];
     if (!h->sv.deferred) continue;
     const FftShape& f = h->geom.fft;
     const int shortv = h->nx <= (long long)DOT_MAX_BLOCKS * 256 ? 1 : 0;
-    groups[{h->device, h->geom.n[0], h->geom.n[1], h->geom.n[2], f.plane_fwd, f.proj_plane, f.plane_inv,
-            h->tg.wz8, shortv}]
+    groups[{h->device, h->geom.n[0], h->geom.n[1], h->geom.n[2], f.plane_fwd, f.proj_plane, f.plane_inv, shortv}]
         .push_back(h);
   }
   int cur = -1;
@@ -1813,8 +1871,10 @@ int fuse_flush(gdc_handle* const* hs, int nh, int& launched) {
       GDC_HIP(hipSetDevice(kv.first[0]));
       cur = kv.first[0];
     }
-    GDC_TRY(fuse_group(kv.second));
-    launched += (int)kv.second.size();
+    std::vector<gdc_handle*>& g = kv.second;
+    std::stable_partition(g.begin(), g.end(), [](const gdc_handle* h) { return h->tg.wz8 != 0; });
+    GDC_TRY(fuse_group(kv.first, g));
+    launched += (int)g.size();
   }
   return GDC_OK;
 }
@@ -1882,6 +1942,7 @@ int gdc_batch_step(gdc_handle* const* hs, int nh, int* steps, int until, double 
     hs[i]->sr.to_start = steps[i] - (hs[i]->sr.phase == StepRun::SOLVE ? 1 : 0) - hs[i]->sr.pend;
     reset_errors(hs[i]);
     hs[i]->fuse_live = hs[i]->fuse;
+    hs[i]->own_dirty = true;
   }
   int rc = GDC_OK;
   int cur_dev = -1;
@@ -1901,6 +1962,15 @@ int gdc_batch_step(gdc_handle* const* hs, int nh, int* steps, int until, double 
       // queue all the work this handle can take before it must wait
       while (steps[i] > 0) {
         int adv = ADV_BLOCKED;
+        if (!fused_only(h)) {
+          // this advance may queue work on the handle's own stream
+          const int r = join_fused(h);
+          if (r != GDC_OK) {
+            rc = r;
+            break;
+          }
+          h->own_dirty = true;
+        }
         const int r = step_advance_any(h, false, adv);
         if (r != GDC_OK) {
           set_error("gdc_batch_step: handle " + std::to_string(i) + ": " + gdc_last_error());
@@ -1950,6 +2020,10 @@ int gdc_batch_step(gdc_handle* const* hs, int nh, int* steps, int until, double 
       hs[i]->sv.deferred = false;
       hs[i]->sv.queued = false;
     }
+    // later calls find all of the handle's work behind its own stream
+    if (hs[i]->device != cur_dev && hipSetDevice(hs[i]->device) == hipSuccess) cur_dev = hs[i]->device;
+    const int r = join_fused(hs[i]);
+    if (r != GDC_OK && rc == GDC_OK) rc = r;
   }
   if (prev_dev >= 0) (void)hipSetDevice(prev_dev);
   // every handle's own outcome first; the message names the first failing

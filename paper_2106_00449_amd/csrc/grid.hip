@@ -973,18 +973,23 @@ __device__ __forceinline__ void spread_tab_body(const GridGeom& G, const TileGeo
   }
 }
 
+// The FP32 kernels are held to 8 waves per SIMD (four workgroups per CU):
+// without the target the compiler gives the body up to 100 SGPRs, which
+// leaves room for three.  A few SGPRs then live in VGPR lanes.
+#define GDC_SPREAD_OCCUPANCY __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 8 : 1)))
+
 template <typename R, int WZ>
-__global__ __launch_bounds__(NTS) void k_spread_tab(GridGeom G, TileGeom T, const HitTab<R, WZ>* __restrict__ tabs,
-                                                   const int4* __restrict__ order, const double* __restrict__ lam,
-                                                   const double* __restrict__ lam_sorted, R* __restrict__ f,
-                                                   const int* __restrict__ skip) {
+__global__ __launch_bounds__(NTS) GDC_SPREAD_OCCUPANCY void k_spread_tab(
+    GridGeom G, TileGeom T, const HitTab<R, WZ>* __restrict__ tabs, const int4* __restrict__ order,
+    const double* __restrict__ lam, const double* __restrict__ lam_sorted, R* __restrict__ f,
+    const int* __restrict__ skip) {
   spread_tab_body<R, WZ>(G, T, tabs, order, lam, lam_sorted, f, skip, hw_block());
 }
 
 // Spreading fused over several suspensions (one SpreadArgs each).
 template <typename R, int WZ>
-__global__ __launch_bounds__(NTS) void k_spread_tab_fused(const SpreadArgs* __restrict__ a,
-                                                         const int* __restrict__ first, int ns) {
+__global__ __launch_bounds__(NTS) GDC_SPREAD_OCCUPANCY void k_spread_tab_fused(
+    const SpreadArgs* __restrict__ a, const int* __restrict__ first, int ns) {
   const int sidx = fused_suspension(first, ns, blockIdx.x);
   const SpreadArgs& A = a[sidx];
   spread_tab_body<R, WZ>(A.G, A.T, (const HitTab<R, WZ>*)A.tabs, A.order, A.lam, A.lam_sorted, (R*)A.f, A.skip,

@@ -147,21 +147,22 @@ def test_batch_step_resumes_a_step_left_in_flight(lib):
         s.close()
 
 
-def test_served_results_equal_alone(lib):
-    from paper_2106_00449_amd.serving import Request, Server, summarise
-    ws = _mix()
-    n_steps = [6, 4, 5, 6]
+@pytest.mark.parametrize("fusion", [False, True])
+def test_served_results_equal_alone(lib, fusion):
+    from paper_2106_00449_amd.serving import LibraryExecutor, Request, Server, summarise
+    ws = _mix() + (_fuse_mix()[:3] if fusion else [])
+    n_steps = [6, 4, 5, 6] + ([5, 3, 4] if fusion else [])
     reqs = []
     for i, (w, k) in enumerate(zip(ws, n_steps)):
         Y, q = wl.initial_state(w)
         reqs.append(Request(i, wl.library_kwargs(w, gmres_tol=1e-6), Y, q, k, arrival=0.002 * i, blobs=w.M))
-    _say("serve mix")
-    # a budget that holds three of the four at once, so admission binds
+    _say("serve mix", "fused" if fusion else "streams")
+    # a budget that holds all but the smallest at once, so admission binds
     fps = sorted(lib.footprint(**r.kwargs) for r in reqs)
-    srv = Server(hbm_budget=sum(fps[1:]), max_slots=8)
+    srv = Server(hbm_budget=sum(fps[1:]), max_slots=8, executor=LibraryExecutor(fusion=fusion))
     res = srv.run(reqs)
     summ = summarise(res)
-    assert summ["completed"] == 4, summ
+    assert summ["completed"] == len(ws), summ
     assert srv.peak_bytes <= srv.budget
     for r, w in zip(reqs, ws):
         Y0, Yr, qr = _alone(lib, w, r.n_steps)
