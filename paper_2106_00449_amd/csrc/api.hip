@@ -1697,6 +1697,29 @@ bool fused_only(const gdc_handle* h) {
   return h->sr.phase == StepRun::SOLVE && h->sv.phase == SolveRun::ITER && fusable_now(h);
 }
 
+// Whether group `key` already has two fused iterations in flight on its
+// stream: its ready handles then wait for the next pass, so that more of the
+// group's handles join the launch while the GPU still has work queued.
+bool fuse_busy(int device, const FuseKey& key) {
+  std::lock_guard<std::mutex> lk(g_fuse_mutex);
+  auto d = g_fuse.find(device);
+  if (d == g_fuse.end()) return false;
+  auto it = d->second.of_key.find(key);
+  if (it == d->second.of_key.end() || it->second >= (int)d->second.streams.size()) return false;
+  const FuseStream& fst = d->second.streams[it->second];
+  int pending = 0;
+  for (int back = 1; back <= 2; ++back) {
+    const FuseSlot& sl = fst.slots[(fst.next + FUSE_SLOTS - back) % FUSE_SLOTS];
+    if (!sl.used) continue;
+    const hipError_t q = hipEventQuery(sl.ev);
+    if (q == hipErrorNotReady) {
+      (void)hipGetLastError();
+      ++pending;
+    }
+  }
+  return pending >= 2;
+}
+
 // The handle's stream waits for its last fused iteration (before the handle
 // queues work of its own there).
 int join_fused(gdc_handle* h) {
@@ -1853,8 +1876,9 @@ int fuse_group(const FuseKey& key, const std::vector<gdc_handle*>& g) {
 
 // Launches the deferred iterations of hs: one fused launch per kernel for
 // each group of handles that share every kernel instantiation but
-// spreading's.  Returns the number of handles launched in `launched`.
-int fuse_flush(gdc_handle* const* hs, int nh, int& launched) {
+// spreading's; with hold set, not for a group with two fused iterations in
+// flight.  Returns the number of handles launched in `launched`.
+int fuse_flush(gdc_handle* const* hs, int nh, int& launched, bool hold) {
   launched = 0;
   std::map<FuseKey, std::vector<gdc_handle*>> groups;
   for (int i = 0; i < nh; ++i) {
@@ -1871,6 +1895,7 @@ int fuse_flush(gdc_handle* const* hs, int nh, int& launched) {
       GDC_HIP(hipSetDevice(kv.first[0]));
       cur = kv.first[0];
     }
+    if (hold && fuse_busy(kv.first[0], kv.first)) continue;
     std::vector<gdc_handle*>& g = kv.second;
     std::stable_partition(g.begin(), g.end(), [](const gdc_handle* h) { return h->tg.wz8 != 0; });
     GDC_TRY(fuse_group(kv.first, g));
@@ -1993,7 +2018,7 @@ int gdc_batch_step(gdc_handle* const* hs, int nh, int* steps, int until, double 
     if (rc == GDC_OK) {
       // the iterations the fused handles deferred in this pass
       int launched = 0;
-      const int r = fuse_flush(hs, nh, launched);
+      const int r = fuse_flush(hs, nh, launched, true);
       if (r != GDC_OK) {
         set_error(std::string("gdc_batch_step: fused launch: ") + gdc_last_error());
         rc = r;
@@ -2154,6 +2179,12 @@ int gdc_set_launch_config(gdc_handle* h, const int* threads, int n) {
       return GDC_EINVAL;
     }
   }
+  // captured iterations hold the old kernels
+  for (gdc_handle::IterGraph& g : h->iter_graph)
+    if (g.exec) {
+      (void)hipGraphExecDestroy(g.exec);
+      g.exec = nullptr;
+    }
   FftShape& f = h->geom.fft;
   f.plane_fwd = threads[0];
   f.proj_plane = threads[1];
