@@ -907,6 +907,10 @@ __device__ __forceinline__ void spread_tab_body(const GridGeom& G, const TileGeo
 #pragma unroll
       for (int k = 0; k < TX; ++k) {
         if (!((hm >> (8 + k)) & 1)) continue;
+        // a hit touches only some of the tile's 8 planes: the empty asm keeps
+        // this a scalar branch (the compiler would otherwise evaluate all
+        // eight planes and select, about 20% slower per launch)
+        asm volatile("");
         const R w = (s0s[k] + s12 <= rc2) ? f12 * f0s[k] : R(0);
         acc[k][0] += w * l0;
         acc[k][1] += w * l1;
@@ -973,9 +977,9 @@ __device__ __forceinline__ void spread_tab_body(const GridGeom& G, const TileGeo
   }
 }
 
-// The FP32 kernels are held to 8 waves per SIMD (four workgroups per CU):
-// without the target the compiler gives the body up to 100 SGPRs, which
-// leaves room for three.  A few SGPRs then live in VGPR lanes.
+// The FP32 kernels are held to 8 waves per SIMD (four workgroups per CU);
+// the ordinary launch needs 48 VGPRs and 76 SGPRs, the fused one more
+// without the target.
 #define GDC_SPREAD_OCCUPANCY __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 8 : 1)))
 
 template <typename R, int WZ>
