@@ -414,6 +414,13 @@ struct gdc_handle {
   };
   std::vector<IterGraph> iter_graph;
   bool graphs = true;
+  // The set-up of a step (noise, predictor, forces, tables, right-hand side,
+  // |b|^2) captured once: its launches read the step from the device counter
+  // step_dev, which the graph advances at its end; step_dev_val is the value
+  // the counter holds for work queued next (UINT64_MAX: unknown).
+  hipGraphExec_t setup_graph = nullptr;
+  uint64_t* step_dev = nullptr;
+  uint64_t step_dev_val = UINT64_MAX;
 
   // Launches fused over suspensions (gdc_set_fusion): inside gdc_batch_step a
   // fused handle does not launch its GMRES iterations itself; the call
@@ -453,6 +460,7 @@ struct gdc_handle {
   ~gdc_handle() {
     for (IterGraph& g : iter_graph)
       if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (setup_graph) (void)hipGraphExecDestroy(setup_graph);
     for (void* p : allocs) (void)hipFree(p);
     if (hhost) (void)hipHostFree(hhost);
     if (gm_host) (void)hipHostFree(gm_host);
@@ -693,19 +701,28 @@ int queue_iteration(gdc_handle* h, int k) {
 // work or reads the next status (waiting for it when block is set, else
 // reporting ADV_BLOCKED while it is not there yet) and reports ADV_DONE once
 // h->sol is queued.
-template <typename R>
-int solve_begin(gdc_handle* h, const double* Y, const double* q, const double* r) {
+//
+// The device part of solve_begin: |b|^2 and, in the same launch, the GMRES
+// state; the solution accumulator is cleared by the first cycle's start.
+int solve_begin_queue(gdc_handle* h) {
   const long long n = h->nx;
-  hipStream_t s = h->stream;
-  // |b|^2 and, in the same launch, the GMRES state; the solution
-  // accumulator is cleared by the first cycle's start
-  GDC_TRY(multi_dot(nullptr, n, 0, h->rhs, n, true, h->partial, h->dot_counter, h->hdev, s, h->gm, h->tol,
-                    h->maxit));
+  return multi_dot(nullptr, n, 0, h->rhs, n, true, h->partial, h->dot_counter, h->hdev, h->stream, h->gm, h->tol,
+                   h->maxit);
+}
+
+// The host part: the solve's resumable state.
+void solve_begin_host(gdc_handle* h, const double* Y, const double* q, const double* r) {
   h->sv = SolveRun{};
   h->sv.Y = Y;
   h->sv.q = q;
   h->sv.r = r;
   h->sv.phase = SolveRun::CYCLE;
+}
+
+template <typename R>
+int solve_begin(gdc_handle* h, const double* Y, const double* q, const double* r) {
+  GDC_TRY(solve_begin_queue(h));
+  solve_begin_host(h, Y, q, r);
   return GDC_OK;
 }
 
@@ -837,20 +854,22 @@ int forces_at(gdc_handle* h, const double* Y, const double* r, bool zeroed = fal
 }
 
 // Random velocity field of step `step` into h->grid_fl.
+// step_ptr: the step is read from this device counter instead (captured set-up).
 template <typename R>
-int make_fluct(gdc_handle* h, uint64_t step) {
+int make_fluct(gdc_handle* h, uint64_t step, const uint64_t* step_ptr = nullptr) {
   const GridGeom& g = h->geom;
   if (h->cfg.kT == 0.0) return fill_zero(h->grid_fl, 3 * (size_t)g.G * sizeof(R), h->stream);
   return fluct_field<R>(g, tw_of<R>(h), (R*)h->grid_fl, (Cx<R>*)h->grid[1], (Cx<R>*)h->grid[2], h->cfg.seed,
-                        step, h->cfg.kT, h->cfg.dt, h->stream);
+                        step, h->cfg.kT, h->cfg.dt, h->stream, step_ptr);
 }
 
 // Steps 2-3 at the state in (h->Y, h->q): calV, d_p and nu on the device.
 template <typename R>
-int predictor_dev(gdc_handle* h, uint64_t step) {
+int predictor_dev(gdc_handle* h, uint64_t step, const uint64_t* step_ptr = nullptr) {
   hipStream_t s = h->stream;
   const int mode = h->cfg.divergence == GDC_DIV_RFD ? 1 : 0;
-  GDC_TRY(fd_displacements(h->bt, h->q, h->cfg.fd_delta, mode, h->cfg.seed, step, h->dr, h->wrfd, s, h->Y, h->r));
+  GDC_TRY(fd_displacements(h->bt, h->q, h->cfg.fd_delta, mode, h->cfg.seed, step, h->dr, h->wrfd, s, h->Y, h->r,
+                           step_ptr));
   GDC_TRY(interp_fd<R>(h->geom, h->r, h->dr, mode == 1 ? 1 : 6, (const R*)h->grid_fl, h->v, h->vd, h->M, s));
   return body_lsq_div(h->bt, h->q, h->v, h->vd, h->wrfd, h->cfg.fd_delta, mode, h->calV, h->dp,
                       h->dot_counter + 1, 0.5 * h->cfg.dt, h->nu, s);
@@ -887,6 +906,83 @@ void retire_step(gdc_handle* h, bool gdc_scheme) {
   --sr.pend;
 }
 
+// Steps 1-5 of a step and the start of its solve, at the state (h->Y, h->q):
+// the random field, the predictor and midpoint (or the blob positions), the
+// forces, the tables of the midpoint configuration, the right-hand side and
+// |b|^2.  The random numbers are those of `step`, or, with step_ptr, of the
+// value in that device counter when the launches run.
+template <typename R>
+int enqueue_setup(gdc_handle* h, uint64_t step, const uint64_t* step_ptr) {
+  hipStream_t s = h->stream;
+  const bool gdc_scheme = h->cfg.scheme == GDC_SCHEME_GDC;
+  // the step's counters in one launch: error flags, pair-force cell
+  // counts, tile counts, spreading-table claim (none is read again before
+  // this step uses it)
+  {
+    void* zp[4] = {h->flags, h->tile_count, h->tab_claimed, h->cell_count};
+    const size_t zb[4] = {16, tile_count_bytes(h->tg), spread_claim_bytes(),
+                          steric_on(h) ? cell_count_bytes(h->nc) : 0};
+    GDC_TRY(fill_zero_many(zp, zb, 4, s));
+  }
+  GDC_TRY(make_fluct<R>(h, step, step_ptr));
+  const double* Ym = h->Y;
+  const double* qm = h->q;
+  if (gdc_scheme) {
+    GDC_TRY(predictor_dev<R>(h, step, step_ptr));
+    GDC_TRY(midpoint_positions(h->bt, h->Y, h->q, h->calV, 0.5 * h->cfg.dt, h->Ym, h->qm, h->rm, s));
+    Ym = h->Ym;
+    qm = h->qm;
+  } else {
+    GDC_TRY(blob_positions(h->bt, Ym, qm, h->rm, s));
+  }
+  GDC_TRY(forces_at(h, Ym, h->rm, true));
+  GDC_TRY(prepare_positions(h, h->rm, true));
+  GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_fl, h->v, h->M, h->geom.dV, nullptr, nullptr, nullptr, s,
+                    nullptr, sorted_records(h)));
+  if (h->vbg)
+    GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_sine, h->vbg, h->M, h->geom.dV, nullptr, nullptr,
+                      nullptr, s, nullptr, sorted_records(h)));
+  GDC_TRY(rhs_build(h->bt, qm, Ym, h->rm, h->v, h->vbg, h->sine_scale, h->F, h->cfg.forces.shear_rate,
+                    h->geom.L[1], h->rhs, s));
+  return solve_begin_queue(h);
+}
+
+// Queues the set-up of step `step`.  With graphs on (and no kernel probe
+// active) its launches are captured once into a HIP graph, with the step
+// read from the handle's device counter, which the graph then advances; a
+// replay is one launch (two when the counter has to be set first, after
+// gdc_set_step or steps taken without the graph).  Every pointer the set-up
+// uses is fixed for the handle.
+template <typename R>
+int queue_setup(gdc_handle* h, uint64_t step) {
+  hipStream_t s = h->stream;
+  if (!h->graphs || probe_active()) return enqueue_setup<R>(h, step, nullptr);
+  if (!h->setup_graph) {
+    GDC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    int rc = enqueue_setup<R>(h, step, h->step_dev);
+    if (rc == GDC_OK) rc = step_counter_bump(h->step_dev, s);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &graph);   // always leave capture mode
+    if (rc != GDC_OK || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      if (rc != GDC_OK) return rc;
+      set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      return GDC_EDEVICE;
+    }
+    const hipError_t e2 = hipGraphInstantiate(&h->setup_graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) {
+      h->setup_graph = nullptr;
+      set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+      return GDC_EDEVICE;
+    }
+  }
+  if (h->step_dev_val != step) GDC_TRY(step_counter_set(h->step_dev, step, s));
+  GDC_HIP(hipGraphLaunch(h->setup_graph, s));
+  h->step_dev_val = step + 1;
+  return GDC_OK;
+}
+
 // Time steps of the resident state (h->Y, h->q) as a resumable, pipelined
 // run.  Each advance does one thing:
 //   - retires the oldest queued step whose readback has landed (ADV_DONE);
@@ -914,36 +1010,10 @@ int step_advance(gdc_handle* h, bool block, int& adv) {
   }
   if (sr.phase == StepRun::IDLE && sr.to_start > 0 && sr.pend < 2) {
     const uint64_t step = h->step;
-    // the step's counters in one launch: error flags, pair-force cell
-    // counts, tile counts, spreading-table claim (none is read again before
-    // this step uses it)
-    {
-      void* zp[4] = {h->flags, h->tile_count, h->tab_claimed, h->cell_count};
-      const size_t zb[4] = {16, tile_count_bytes(h->tg), spread_claim_bytes(),
-                            steric_on(h) ? cell_count_bytes(h->nc) : 0};
-      GDC_TRY(fill_zero_many(zp, zb, 4, s));
-    }
-    GDC_TRY(make_fluct<R>(h, step));
-    const double* Ym = h->Y;
-    const double* qm = h->q;
-    if (gdc_scheme) {
-      GDC_TRY(predictor_dev<R>(h, step));
-      GDC_TRY(midpoint_positions(h->bt, h->Y, h->q, h->calV, 0.5 * h->cfg.dt, h->Ym, h->qm, h->rm, s));
-      Ym = h->Ym;
-      qm = h->qm;
-    } else {
-      GDC_TRY(blob_positions(h->bt, Ym, qm, h->rm, s));
-    }
-    GDC_TRY(forces_at(h, Ym, h->rm, true));
-    GDC_TRY(prepare_positions(h, h->rm, true));
-    GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_fl, h->v, h->M, h->geom.dV, nullptr, nullptr, nullptr, s,
-                      nullptr, sorted_records(h)));
-    if (h->vbg)
-      GDC_TRY(interp<R>(h->geom, h->rm, (const R*)h->grid_sine, h->vbg, h->M, h->geom.dV, nullptr, nullptr,
-                        nullptr, s, nullptr, sorted_records(h)));
-    GDC_TRY(rhs_build(h->bt, qm, Ym, h->rm, h->v, h->vbg, h->sine_scale, h->F, h->cfg.forces.shear_rate,
-                      h->geom.L[1], h->rhs, s));
-    GDC_TRY(solve_begin<R>(h, Ym, qm, h->rm));
+    const double* Ym = gdc_scheme ? h->Ym : h->Y;
+    const double* qm = gdc_scheme ? h->qm : h->q;
+    GDC_TRY(queue_setup<R>(h, step));
+    solve_begin_host(h, Ym, qm, h->rm);
     --sr.to_start;
     sr.phase = StepRun::SOLVE;
     return GDC_OK;
@@ -1417,6 +1487,7 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
     GDC_TRY(h->alloc(&h->tab_claimed, spread_claim_bytes() / sizeof(unsigned int)));
   }
   GDC_TRY(h->alloc(&h->gm, 1));
+  GDC_TRY(h->alloc(&h->step_dev, 2));
   if (!h->dry) {
     GDC_HIP(hipHostMalloc((void**)&h->hhost, 5 * HCOLS * sizeof(double), hipHostMallocDefault));
     GDC_HIP(hipHostMalloc((void**)&h->gm_host, 64, hipHostMallocMapped | hipHostMallocCoherent));
@@ -2179,12 +2250,16 @@ int gdc_set_launch_config(gdc_handle* h, const int* threads, int n) {
       return GDC_EINVAL;
     }
   }
-  // captured iterations hold the old kernels
+  // captured iterations and set-ups hold the old kernels
   for (gdc_handle::IterGraph& g : h->iter_graph)
     if (g.exec) {
       (void)hipGraphExecDestroy(g.exec);
       g.exec = nullptr;
     }
+  if (h->setup_graph) {
+    (void)hipGraphExecDestroy(h->setup_graph);
+    h->setup_graph = nullptr;
+  }
   FftShape& f = h->geom.fft;
   f.plane_fwd = threads[0];
   f.proj_plane = threads[1];

@@ -314,9 +314,10 @@ __global__ __launch_bounds__(64) void k_precond(BodyTables B, const double* __re
 __global__ void k_fd_displacements(BodyTables B, const double* __restrict__ q, double delta, int mode,
                                    uint64_t seed, uint64_t step, double* __restrict__ dr,
                                    double* __restrict__ wrfd, const double* __restrict__ Y,
-                                   double* __restrict__ r) {
+                                   double* __restrict__ r, const uint64_t* __restrict__ step_ptr) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= B.M) return;
+  if (step_ptr) step = *step_ptr;
   const int p = B.blob_body[i], s = B.body_shape[p];
   const double Lp = B.shape_Lp[s];
   double b[3], R[9];
@@ -835,10 +836,25 @@ int wall_forces(const double* r, int M, double H, double k, double b, double* fb
 }
 
 int fd_displacements(const BodyTables& b, const double* q, double delta, int mode, uint64_t seed,
-                     uint64_t step, double* dr, double* wrfd, hipStream_t s, const double* Y, double* r) {
+                     uint64_t step, double* dr, double* wrfd, hipStream_t s, const double* Y, double* r,
+                     const uint64_t* step_ptr) {
   hipLaunchKernelGGL(k_fd_displacements, dim3(nblk(b.M)), dim3(NT), 0, s, b, q, delta, mode, seed, step, dr, wrfd,
-                     Y, r);
+                     Y, r, step_ptr);
   return check_launch("k_fd_displacements");
+}
+
+__global__ void k_step_counter(uint64_t* __restrict__ c, uint64_t v, int bump) {
+  if (threadIdx.x == 0) *c = bump ? *c + 1 : v;
+}
+
+int step_counter_set(uint64_t* c, uint64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_counter, dim3(1), dim3(64), 0, s, c, v, 0);
+  return check_launch("k_step_counter");
+}
+
+int step_counter_bump(uint64_t* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_counter, dim3(1), dim3(64), 0, s, c, (uint64_t)0, 1);
+  return check_launch("k_step_counter");
 }
 
 int body_lsq_div(const BodyTables& b, const double* q, const double* v, const double* vd, const double* wrfd,

@@ -438,9 +438,10 @@ __device__ __forceinline__ void stress_mode(const ProjParams& P, int j0, int j1,
     conj = true;
   }
   const uint32_t idx = (uint32_t)(((long long)c0 * n1 + c1) * P.n2h + j2);
+  const uint64_t step = P.step_ptr ? *P.step_ptr : P.step;
   double z[12];
 #pragma unroll
-  for (int call = 0; call < 3; ++call) four_normals(P.seed, idx, (uint32_t)call, P.step, z + 4 * call);
+  for (int call = 0; call < 3; ++call) four_normals(P.seed, idx, (uint32_t)call, step, z + 4 * call);
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
     const double sc = c < 3 ? P.sdiag : P.soff;
@@ -1112,12 +1113,13 @@ int stokes_fused(const GridGeom& g, const PlaneArgs* fwd, const ProjPlaneArgs* p
 
 template <typename R>
 int fluct_field(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, Cx<R>* Y,
-                uint64_t seed, uint64_t step, double kT, double dt, hipStream_t s) {
+                uint64_t seed, uint64_t step, double kT, double dt, hipStream_t s, const uint64_t* step_ptr) {
   const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], H = g.n2h;
   const FftShape& f = g.fft;
   ProjParams P = proj_params(g);
   P.seed = seed;
   P.step = step;
+  P.step_ptr = step_ptr;
   // real-space variances 4 kT eta/(dV dt) (diagonal) and 2 kT eta/(dV dt)
   // (off-diagonal) of the stress at a grid point; per stored mode, real and
   // imaginary parts each carry G var / 2.
@@ -1246,9 +1248,10 @@ template int stokes_solve<float>(const GridGeom&, const Cx<float>* const[3], flo
 template int stokes_solve<double>(const GridGeom&, const Cx<double>* const[3], double*, Cx<double>*,
                                    Cx<double>*, hipStream_t, const int*);
 template int fluct_field<float>(const GridGeom&, const Cx<float>* const[3], float*, Cx<float>*,
-                                Cx<float>*, uint64_t, uint64_t, double, double, hipStream_t);
+                                Cx<float>*, uint64_t, uint64_t, double, double, hipStream_t, const uint64_t*);
 template int fluct_field<double>(const GridGeom&, const Cx<double>* const[3], double*, Cx<double>*,
-                                 Cx<double>*, uint64_t, uint64_t, double, double, hipStream_t);
+                                 Cx<double>*, uint64_t, uint64_t, double, double, hipStream_t,
+                                 const uint64_t*);
 template int fft_autotune<float>(GridGeom&, const Cx<float>* const[3], float*, Cx<float>*, Cx<float>*,
                                  hipStream_t);
 template int fft_autotune<double>(GridGeom&, const Cx<double>* const[3], double*, Cx<double>*, Cx<double>*,

@@ -268,6 +268,7 @@ struct ProjParams {
   double invG;
   // noise
   uint64_t seed, step;
+  const uint64_t* step_ptr;   // when set, the step is read from here (graph replays)
   double sdiag, soff;      // sqrt(G var / 2) of diagonal / off-diagonal components
   int channel;             // slip channel: the stress is given its mirror image in y
 };
@@ -315,8 +316,11 @@ template <typename R>
 int stokes_solve(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, Cx<R>* Y,
                  hipStream_t s, const int* skip = nullptr);
 template <typename R>
+// step_ptr (optional): a device counter the kernels read the step from at
+// run time instead of `step`, for launches replayed from a captured graph.
 int fluct_field(const GridGeom& g, const Cx<R>* const tw[3], R* real, Cx<R>* X, Cx<R>* Y,
-                uint64_t seed, uint64_t step, double kT, double dt, hipStream_t s);
+                uint64_t seed, uint64_t step, double kT, double dt, hipStream_t s,
+                const uint64_t* step_ptr = nullptr);
 bool fft_size_supported(int n);
 // Times every workgroup size of each pass of g's transform on the given
 // buffers (zeroed first) and stores the fastest in g.fft; cached per grid and
@@ -465,10 +469,13 @@ int sort_forces(const double* lam, const int* spos, int M, int mirror, double* z
 // H - y < b; add: add to fblob (else fblob is overwritten).
 int wall_forces(const double* r, int M, double H, double k, double b, double* fblob, bool add, hipStream_t s);
 // FD / RFD perturbations: displacements of each blob (M x NP x 3) and, for
-// RFD, the Philox normals of each body (N x 6).
+// RFD, the Philox normals of each body (N x 6); step_ptr as in fluct_field.
 int fd_displacements(const BodyTables& b, const double* q, double delta, int mode,
                      uint64_t seed, uint64_t step, double* dr, double* wrfd, hipStream_t s,
-                     const double* Y = nullptr, double* r = nullptr);
+                     const double* Y = nullptr, double* r = nullptr, const uint64_t* step_ptr = nullptr);
+// The device step counter of a handle: set to v, or advanced by one.
+int step_counter_set(uint64_t* c, uint64_t v, hipStream_t s);
+int step_counter_bump(uint64_t* c, hipStream_t s);
 // calV, d_p and (same launch) nu = 1 + half_dt sum_p d_p; counter: one
 // zeroed unsigned int, left at zero.
 int body_lsq_div(const BodyTables& b, const double* q, const double* v, const double* vd,

@@ -199,11 +199,13 @@ def test_every_fft_launch_shape_gives_identical_results(lib, prec, n, L):
 
 @pytest.mark.parametrize("k", [0, 1, 2])
 def test_graph_replay_equals_eager_launches(lib, k):
-    # GMRES iterations replayed from captured HIP graphs against every kernel
-    # launched on its own: the same results bit for bit over several steps
-    # with restart cycles (restart 4, so every column's graph is replayed
-    # across cycles), eager work between the replays (a body solve at another
-    # configuration re-keys the graphs), and batched stepping
+    # GMRES iterations and step set-ups replayed from captured HIP graphs
+    # against every kernel launched on its own: the same results bit for bit
+    # over several steps with restart cycles (restart 4, so every column's
+    # graph is replayed across cycles), eager work between the replays (a body
+    # solve at another configuration re-keys the graphs), a jump of the step
+    # counter (the set-up graph reads it from the device), and batched
+    # stepping
     w = _mix()[k]
     Y0, q0 = wl.initial_state(w)
     F = np.random.default_rng(3).standard_normal((w.N, 6))
@@ -217,6 +219,7 @@ def test_graph_replay_equals_eager_launches(lib, k):
         st1 = s.step(Y, q, 3)
         assert st1["gmres_iterations"] > 4          # more than one restart cycle
         V = s.mobility_apply("body", Y, q, F, allow_notconv=True)
+        s.step_counter = s.step_counter + 7
         st2 = s.step(Y, q, 2)
         s.set_state(Y, q)
         left = [2]
