@@ -421,6 +421,8 @@ struct gdc_handle {
   hipGraphExec_t setup_graph = nullptr;
   uint64_t* step_dev = nullptr;
   uint64_t step_dev_val = UINT64_MAX;
+  // The end of a step (update and readback into slot k) captured once per slot.
+  hipGraphExec_t done_graph[2] = {nullptr, nullptr};
 
   // Launches fused over suspensions (gdc_set_fusion): inside gdc_batch_step a
   // fused handle does not launch its GMRES iterations itself; the call
@@ -461,6 +463,8 @@ struct gdc_handle {
     for (IterGraph& g : iter_graph)
       if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (setup_graph) (void)hipGraphExecDestroy(setup_graph);
+    for (hipGraphExec_t g : done_graph)
+      if (g) (void)hipGraphExecDestroy(g);
     for (void* p : allocs) (void)hipFree(p);
     if (hhost) (void)hipHostFree(hhost);
     if (gm_host) (void)hipHostFree(gm_host);
@@ -591,8 +595,13 @@ GmStatus read_status(const unsigned char* p) {
 
 // Queues a copy of the device status into pinned slot `slot` and an event
 // after it.
-int post_status(gdc_handle* h, int slot) {
+int post_status_copy(gdc_handle* h, int slot) {
   GDC_HIP(hipMemcpyAsync(h->gm_host + 32 * slot, h->gm, GM_STATUS_BYTES, hipMemcpyDeviceToHost, h->stream));
+  return GDC_OK;
+}
+
+int post_status(gdc_handle* h, int slot) {
+  GDC_TRY(post_status_copy(h, slot));
   GDC_HIP(hipEventRecord(h->gm_ev[slot], h->stream));
   return GDC_OK;
 }
@@ -912,7 +921,7 @@ void retire_step(gdc_handle* h, bool gdc_scheme) {
 // |b|^2.  The random numbers are those of `step`, or, with step_ptr, of the
 // value in that device counter when the launches run.
 template <typename R>
-int enqueue_setup(gdc_handle* h, uint64_t step, const uint64_t* step_ptr) {
+int enqueue_setup(gdc_handle* h, uint64_t step, const uint64_t* step_ptr, bool cycle_start) {
   hipStream_t s = h->stream;
   const bool gdc_scheme = h->cfg.scheme == GDC_SCHEME_GDC;
   // the step's counters in one launch: error flags, pair-force cell
@@ -944,7 +953,13 @@ int enqueue_setup(gdc_handle* h, uint64_t step, const uint64_t* step_ptr) {
                       nullptr, s, nullptr, sorted_records(h)));
   GDC_TRY(rhs_build(h->bt, qm, Ym, h->rm, h->v, h->vbg, h->sine_scale, h->F, h->cfg.forces.shear_rate,
                     h->geom.L[1], h->rhs, s));
-  return solve_begin_queue(h);
+  GDC_TRY(solve_begin_queue(h));
+  if (!cycle_start) return GDC_OK;
+  // the first cycle's start, as solve_advance queues it (V_0 = b / |b|, its
+  // status into slot 0; the caller records the status event)
+  const long long n = h->nx;
+  GDC_TRY(scale_by_inv_sqrt(h->rhs, h->hdev, h->Vb, n, s, h->gm, h->xacc, n));
+  return post_status_copy(h, 0);
 }
 
 // Queues the set-up of step `step`.  With graphs on (and no kernel probe
@@ -954,12 +969,13 @@ int enqueue_setup(gdc_handle* h, uint64_t step, const uint64_t* step_ptr) {
 // gdc_set_step or steps taken without the graph).  Every pointer the set-up
 // uses is fixed for the handle.
 template <typename R>
-int queue_setup(gdc_handle* h, uint64_t step) {
+int queue_setup(gdc_handle* h, uint64_t step, bool& cycle_started) {
   hipStream_t s = h->stream;
-  if (!h->graphs || probe_active()) return enqueue_setup<R>(h, step, nullptr);
+  cycle_started = false;
+  if (!h->graphs || probe_active()) return enqueue_setup<R>(h, step, nullptr, false);
   if (!h->setup_graph) {
     GDC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-    int rc = enqueue_setup<R>(h, step, h->step_dev);
+    int rc = enqueue_setup<R>(h, step, h->step_dev, true);
     if (rc == GDC_OK) rc = step_counter_bump(h->step_dev, s);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(s, &graph);   // always leave capture mode
@@ -980,6 +996,51 @@ int queue_setup(gdc_handle* h, uint64_t step) {
   if (h->step_dev_val != step) GDC_TRY(step_counter_set(h->step_dev, step, s));
   GDC_HIP(hipGraphLaunch(h->setup_graph, s));
   h->step_dev_val = step + 1;
+  cycle_started = true;
+  return GDC_OK;
+}
+
+// Queues the end of a step into readback slot k: the sine sum (forced
+// rheology), the update (step 6) and the copies of nu and the error flags.
+// With graphs on (and no probe) it is captured once per slot.
+int queue_step_end(gdc_handle* h, int k) {
+  hipStream_t s = h->stream;
+  const bool gdc_scheme = h->cfg.scheme == GDC_SCHEME_GDC;
+  double* rb = readback(h, k);
+  auto enqueue = [&]() -> int {
+    if (h->vbg) {
+      // sum_i lambda_ix J[sin(k y)](r_i) of the midpoint solve, for v_x
+      GDC_TRY(blob_dot_x(h->sol, h->vbg, h->M, h->nu + 1, s));
+      GDC_HIP(hipMemcpyAsync(rb + 3, h->nu + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    GDC_TRY(update(h->bt, h->Y, h->q, h->sol + 3LL * h->M, gdc_scheme ? h->nu : nullptr, h->cfg.dt,
+                   h->flags + 1, s));
+    GDC_HIP(hipMemcpyAsync(rb, h->nu, sizeof(double), hipMemcpyDeviceToHost, s));
+    GDC_HIP(hipMemcpyAsync(rb + 1, h->flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    return GDC_OK;
+  };
+  if (!h->graphs || probe_active()) return enqueue();
+  hipGraphExec_t& ge = h->done_graph[k];
+  if (!ge) {
+    GDC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    const int rc = enqueue();
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &graph);   // always leave capture mode
+    if (rc != GDC_OK || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      if (rc != GDC_OK) return rc;
+      set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      return GDC_EDEVICE;
+    }
+    const hipError_t e2 = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) {
+      ge = nullptr;
+      set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+      return GDC_EDEVICE;
+    }
+  }
+  GDC_HIP(hipGraphLaunch(ge, s));
   return GDC_OK;
 }
 
@@ -1012,8 +1073,17 @@ int step_advance(gdc_handle* h, bool block, int& adv) {
     const uint64_t step = h->step;
     const double* Ym = gdc_scheme ? h->Ym : h->Y;
     const double* qm = gdc_scheme ? h->qm : h->q;
-    GDC_TRY(queue_setup<R>(h, step));
+    bool cycle_started = false;
+    GDC_TRY(queue_setup<R>(h, step, cycle_started));
     solve_begin_host(h, Ym, qm, h->rm);
+    if (cycle_started) {
+      // the captured set-up also started the first GMRES cycle
+      GDC_HIP(hipEventRecord(h->gm_ev[0], s));
+      h->sv.first = false;
+      h->sv.k = 0;
+      h->sv.queued = false;
+      h->sv.phase = SolveRun::ITER;
+    }
     --sr.to_start;
     sr.phase = StepRun::SOLVE;
     return GDC_OK;
@@ -1025,18 +1095,9 @@ int step_advance(gdc_handle* h, bool block, int& adv) {
     GDC_TRY(solve_advance<R>(h, block && sr.pend == 0, a));
     if (a == ADV_DONE) {
       const int k = (sr.head + sr.pend) & 1;
-      double* rb = readback(h, k);
       sr.slot_gr[k] = h->sv.res;
       h->sv.phase = SolveRun::IDLE;
-      if (h->vbg) {
-        // sum_i lambda_ix J[sin(k y)](r_i) of the midpoint solve, for v_x
-        GDC_TRY(blob_dot_x(h->sol, h->vbg, h->M, h->nu + 1, s));
-        GDC_HIP(hipMemcpyAsync(rb + 3, h->nu + 1, sizeof(double), hipMemcpyDeviceToHost, s));
-      }
-      GDC_TRY(update(h->bt, h->Y, h->q, h->sol + 3LL * h->M, gdc_scheme ? h->nu : nullptr, h->cfg.dt,
-                     h->flags + 1, s));
-      GDC_HIP(hipMemcpyAsync(rb, h->nu, sizeof(double), hipMemcpyDeviceToHost, s));
-      GDC_HIP(hipMemcpyAsync(rb + 1, h->flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+      GDC_TRY(queue_step_end(h, k));
       GDC_HIP(hipEventRecord(h->step_ev[k], s));
       ++sr.pend;
       h->step += 1;   // the next step draws the next noise
