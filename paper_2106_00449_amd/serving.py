@@ -67,12 +67,19 @@ class Result:
 class LibraryExecutor:
     """Runs requests on the HIP library (one handle and stream each).  With
     fusion, the suspensions' GMRES iterations are launched fused: one launch
-    per kernel for all the ready suspensions of a grid size."""
+    per kernel for all the ready suspensions of a grid size.  fusion is a
+    bool, or an int: the largest grid edge whose suspensions are fused
+    (smaller grids gain from fusion, larger ones from concurrent streams)."""
 
     def __init__(self, fusion=False):
         import paper_2106_00449_amd as g
         self.g = g
-        self.fusion = bool(fusion)
+        self.fusion = fusion if isinstance(fusion, int) and not isinstance(fusion, bool) else bool(fusion)
+
+    def _fused(self, req):
+        if isinstance(self.fusion, bool):
+            return self.fusion
+        return max(int(x) for x in np.atleast_1d(req.kwargs["n"])) <= self.fusion
 
     def footprint(self, req):
         return self.g.footprint(**req.kwargs)
@@ -80,7 +87,7 @@ class LibraryExecutor:
     def open(self, req):
         s = self.g.Suspension(**req.kwargs)
         s.set_state(req.Y0, req.q0)
-        if self.fusion:
+        if self._fused(req):
             s.fusion = True
         return s
 
