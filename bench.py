@@ -29,9 +29,9 @@ Beside the headline figure the JSON line carries:
   serving       256 independent suspensions (N log-uniform in [8, 2048] rods,
                 grids 32^3..128^3, 50 steps each) served with continuous
                 batching, each grid bucket at its own calibrated tolerance:
-                saturation throughput (on concurrent streams, and with the
-                GMRES iterations fused over the resident suspensions of all
-                grids or of 32^3 only), a Poisson sweep with p50/p99 step
+                saturation throughput (GMRES iterations of the 32^3
+                suspensions fused, the rest on concurrent streams; also all
+                on streams and all fused), a Poisson sweep with p50/p99 step
                 latency, and the same requests one at a time on the plain
                 FP64 and FP32 paths (a sample of 16);
   cpu_baseline  the FP64 oracle on a bounded sample of the headline
@@ -449,15 +449,15 @@ def serving_bench(g, wl, reqs, states, budget, slots):
                                arr, blobs=w.M))
         return out
 
-    progress("serving: saturation run")
+    progress("serving: saturation run (GMRES iterations of the 32^3 suspensions fused)")
     srv = Server(hbm_budget=budget, max_slots=slots)
     t0 = time.perf_counter()
     res = srv.run(requests(None))
     sat = summarise(res, makespan=time.perf_counter() - t0)
-    sat.update(peak_bytes=srv.peak_bytes, peak_slots=srv.peak_slots)
+    sat.update(peak_bytes=srv.peak_bytes, peak_slots=srv.peak_slots, fused_grids="32^3")
     sat_fused = {}
-    for key, fusion in (("all", True), ("32^3", 32)):
-        progress(f"serving: saturation run, GMRES iterations fused over the resident suspensions ({key})")
+    for key, fusion in (("none", False), ("all", True)):
+        progress(f"serving: saturation run, GMRES iterations fused over the resident suspensions: {key}")
         srv = Server(hbm_budget=budget, max_slots=slots, executor=LibraryExecutor(fusion=fusion))
         t0 = time.perf_counter()
         res = srv.run(requests(None))
@@ -503,7 +503,7 @@ def serving_bench(g, wl, reqs, states, budget, slots):
                     f"{min(w.n[0] for w in reqs)}^3..{max(w.n[0] for w in reqs)}^3, 50 gDC steps each, FP32",
         "tolerance_per_bucket": bucket_err,
         "hbm_budget_bytes": budget, "max_slots": slots,
-        "saturation": sat, "saturation_fused": sat_fused["all"], "saturation_fused_32": sat_fused["32^3"],
+        "saturation": sat, "saturation_streams": sat_fused["none"], "saturation_fused": sat_fused["all"],
         "poisson_at_saturation_rate": sweep["1x"], "poisson_rate_sweep": sweep,
         "sequential_fp64_sample": seq["fp64"], "sequential_fp32_sample": seq["fp32"],
         "served_over_sequential_fp64": sat["blob_steps_per_s"] / seq["fp64"]["blob_steps_per_s"],
