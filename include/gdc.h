@@ -262,25 +262,32 @@ enum { GDC_FFT_PASSES = 8 };
 int gdc_get_launch_config(const gdc_handle* h, int* threads, int n);
 int gdc_set_launch_config(gdc_handle* h, const int* threads, int n);
 
-/* Launch mode of the GMRES iterations (the step-5 solve of Sec. 3): with
- * graphs on (the default) the launches of each Krylov column's iteration
- * are captured once into a HIP graph and replayed, one launch instead of
- * about ten, which takes most of the host's launch work off a step; off,
- * every kernel is launched on its own.  Results are the same bit for bit.
- * While gdc_probe_kernel watches a family, kernels launch on their own so
- * the probe can stamp them.  Errors: GDC_EINVAL (NULL, step in flight). */
+/* Launch mode of a step (Sec. 3): with graphs on (the default) the step's
+ * set-up (steps 1-5 and the first GMRES cycle's start), each Krylov
+ * column's iteration of the step-5 solve, and the step's end (update and
+ * readback) are captured once into HIP graphs and replayed, a few launches
+ * per step instead of about a hundred; the set-up graph reads the step
+ * counter from device memory, which the library keeps equal to the
+ * handle's.  Off, every kernel is launched on its own.  Results are the same
+ * bit for bit.  While gdc_probe_kernel watches a family, kernels launch on
+ * their own so the probe can stamp them; gdc_set_launch_config drops the
+ * captured graphs.  Errors: GDC_EINVAL (NULL, step in flight). */
 int gdc_set_graphs(gdc_handle* h, int on);
 int gdc_get_graphs(const gdc_handle* h, int* on);
 
 /* Fused batching (the GMRES iterations of Sec. 3 step 5 over several
  * suspensions): with fusion on, a handle stepped by gdc_batch_step does not
  * launch its GMRES iterations itself.  After each pass over its handles the
- * call launches every kernel of an iteration (preconditioner, spreading,
- * the three plane passes of the transform, averaging, the three Arnoldi
- * kernels) once for all the fused handles that have an iteration ready,
- * each at its own Krylov column, grouped by what the kernels are
- * instantiated for (grid size, transform workgroup sizes, spreading-table
- * width, vector-length class).  Each suspension's arithmetic is unchanged:
+ * call launches every kernel of an iteration (preconditioner, spreading
+ * once per table width, the three plane passes of the transform,
+ * averaging, the three Arnoldi kernels) once for all the fused handles that
+ * have an iteration ready, each at its own Krylov column, grouped by what
+ * the kernels are instantiated for (grid size, transform workgroup sizes,
+ * vector-length class); each group launches on a library stream of its own
+ * (up to four per GPU), and waits while two of its fused iterations are
+ * still in flight.  The handle's stream and the group's are joined only
+ * where work crosses them, and the handle's stream follows all of its work
+ * when the call returns.  Each suspension's arithmetic is unchanged:
  * results equal the unfused ones bit for bit.  Only handles on the FP32
  * plane-path transforms (grids up to 128^3) with the matrix-core
  * preconditioner, outside the slip channel, are fused; others run as
