@@ -40,6 +40,7 @@ Beside the headline figure the JSON line carries:
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                        [--no-serving] [--no-extras] [--workload NAME]
+       python bench.py --fusion-table   (fused against streamed batching per grid)
 """
 import argparse
 import json
@@ -510,6 +511,40 @@ def serving_bench(g, wl, reqs, states, budget, slots):
     }
 
 
+def fusion_table(g, wl, reps=2, warm=4, steps=6, tol=1e-5):
+    """Fused GMRES iterations against concurrent streams, per serving grid
+    bucket: batch_step over the first K requests of the bucket (all of one
+    grid size), `steps` timed steps after `warm`, each setting in turn and
+    in alternating order over `reps` repetitions."""
+    import numpy as np
+    reqs = wl.serving_requests()
+    out = []
+    for rep in range(reps):
+        for K, n in [(24, 32), (24, 48), (16, 64), (8, 96), (8, 128)]:
+            ws = [w for w in reqs if w.n[0] == n][:K]
+            for fusion in ((False, True) if rep % 2 == 0 else (True, False)):
+                ss = []
+                for w in ws:
+                    Y, q = wl.initial_state(w)
+                    s = g.Suspension(**wl.library_kwargs(w, gmres_tol=tol, gmres_maxit=400))
+                    s.fusion = fusion
+                    s.set_state(Y, q)
+                    ss.append(s)
+                g.batch_step(ss, [warm] * len(ss))
+                t0 = time.perf_counter()
+                _, stats, _ = g.batch_step(ss, [steps] * len(ss))
+                dt = time.perf_counter() - t0
+                blobs = sum(w.M for w in ws)
+                row = {"rep": rep, "grid": n, "suspensions": len(ws), "blobs": blobs, "fused": fusion,
+                       "ms": dt * 1e3, "blob_steps_per_s": blobs * steps / dt,
+                       "fused_iterations": int(sum(x["fused_iterations"] for x in stats))}
+                progress(f"fusion table: {row}")
+                out.append(row)
+                for s in ss:
+                    s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -536,6 +571,8 @@ def main():
                     help="run one 256 MiB device copy first (counter calibration for profiling)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every GMRES iteration kernel by kernel (no HIP graph replay)")
+    ap.add_argument("--fusion-table", action="store_true",
+                    help="instead: fused GMRES iterations against concurrent streams per serving grid bucket")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -550,6 +587,11 @@ def main():
     if args.oracle_timings:
         tol = args.gmres_tol if args.gmres_tol > 0.0 else 1e-5
         print(json.dumps({"oracle_timings": oracle_timings(wl, tol)}))
+        return
+    if args.fusion_table:
+        import paper_2106_00449_amd as g
+        g.GRAPHS_DEFAULT = not args.no_graphs
+        print(json.dumps({"fusion_table": fusion_table(g, wl)}))
         return
 
     # initial states first, in worker processes, before anything touches the GPU
