@@ -122,8 +122,59 @@ __device__ __forceinline__ Cx<R> twiddle(const Cx<R>* tw, int e) {
   return w;
 }
 
+// cos and sin of 2 pi e / n (0 <= e < n), for twiddles whose index is known
+// when the code is compiled (the in-register DFTs below, fully unrolled):
+// the angle is reduced to [0, pi/4] by quarter turns and the octant
+// symmetry, and the Taylor series of cos and sin there is summed in FP64 to
+// far below FP64 rounding; quarter turns come out exactly 0 and +-1.
+struct CosSin {
+  double c, s;
+};
+__host__ __device__ constexpr CosSin cos_sin_turn(int e, int n) {
+  e %= n;
+  const int q = (4 * e) / n, r = 4 * e - q * n;   // e / n = (q + r / n) / 4
+  const bool mirror = 2 * r > n;                   // past an eighth turn
+  const double phi = 1.57079632679489661923 * (double)(mirror ? n - r : r) / (double)n;
+  double c = 0.0, s = 0.0, tc = 1.0, ts = phi;
+  for (int j = 0; j < 12; ++j) {    // terms phi^(2j) / (2j)! and phi^(2j+1) / (2j+1)!
+    c += tc;
+    s += ts;
+    tc *= -phi * phi / (double)((2 * j + 1) * (2 * j + 2));
+    ts *= -phi * phi / (double)((2 * j + 2) * (2 * j + 3));
+  }
+  if (mirror) {
+    const double t = c;
+    c = s;
+    s = t;
+  }
+  for (int j = 0; j < q; ++j) {     // a quarter turn: (c, s) -> (-s, c)
+    const double t = c;
+    c = -s;
+    s = t;
+  }
+  return CosSin{c, s};
+}
+
+// a times w_n^e = e^{-+2 pi i e/n} (forward / inverse) with e and n known at
+// compile time: multiplications by 0 and +-1 are left out.
+template <typename R, bool INV>
+__device__ __forceinline__ Cx<R> cmul_turn(Cx<R> a, int e, int n) {
+  const CosSin w = cos_sin_turn(e, n);
+  const double wr = w.c, wi = INV ? w.s : -w.s;
+  if (wi == 0.0) {
+    if (wr == 1.0) return a;
+    if (wr == -1.0) return Cx<R>{-a.x, -a.y};
+  }
+  if (wr == 0.0) {
+    if (wi == 1.0) return Cx<R>{-a.y, a.x};
+    if (wi == -1.0) return Cx<R>{a.y, -a.x};
+  }
+  return cmul(a, Cx<R>{R(wr), R(wi)});
+}
+
 // In-register DFT of A values v[j] (natural order in and out); tw is the
-// e^{-2 pi i k/N} table of the full line length N (A divides N).
+// e^{-2 pi i k/N} table of the full line length N (A divides N); the
+// twiddles inside the DFT (powers of w_A) are compile-time constants.
 template <typename R, int A, int N, bool INV>
 struct RegDFT {
   static constexpr int RAD = next_radix(A), S = A / RAD;
@@ -140,7 +191,7 @@ struct RegDFT {
       Cx<R> t[RAD];
 #pragma unroll
       for (int p = 0; p < RAD; ++p)
-        t[p] = (p * k == 0) ? sub[p][k] : cmul(sub[p][k], twiddle<R, INV>(tw, (p * k * (N / A)) % N));
+        t[p] = (p * k == 0) ? sub[p][k] : cmul_turn<R, INV>(sub[p][k], (p * k) % A, A);
       Bfly<R, RAD, INV>::run(t);
 #pragma unroll
       for (int q = 0; q < RAD; ++q) v[k + S * q] = t[q];
