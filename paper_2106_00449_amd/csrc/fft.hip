@@ -240,7 +240,8 @@ __device__ __forceinline__ void fft_lines(Cx<R>* buf, const Cx<R>* tw) {
     RegDFT<R, A, N, INV>::run(v, tw);
 #pragma unroll
     for (int k1 = 0; k1 < A; ++k1) {
-      const Cx<R> w = (B > 1 && k1 > 0 && b > 0) ? cmul(v[k1], twiddle<R, INV>(tw, (b * k1) % N)) : v[k1];
+      // b k1 <= (B - 1)(A - 1) < N: the index needs no reduction
+      const Cx<R> w = (B > 1 && k1 > 0 && b > 0) ? cmul(v[k1], twiddle<R, INV>(tw, b * k1)) : v[k1];
       line[b + B * k1] = w;
     }
   }
@@ -563,16 +564,18 @@ __global__ __launch_bounds__(NTH) void k_axis0_project(Cx<R>* __restrict__ Y, co
   const int nl = min(TC, P.n1 - k1b);
   const int H = P.n2h, n1 = P.n1;
   load_twiddles<R, N0, NTH>(tw, twg);
+  // component c's TC lines are one contiguous run of TC N0 values
+  const long long cstride = (long long)H * n1 * N0;
+  const Cx<R>* Yk = Y + ((long long)k2 * n1 + k1b) * N0;
   if (!NOISE) {
     staged_copy<NLn * N0, NTH>(
         [&](int e) {
-          const int l = e / N0, x = e - l * N0;
-          const int c = l / TC, t = l - c * TC;
-          return (t < nl) ? Y[(((long long)c * H + k2) * n1 + k1b + t) * N0 + x] : Cx<R>{R(0), R(0)};
+          const int c = e / (TC * N0), r = e - c * (TC * N0);   // r = t N0 + x
+          return (r < nl * N0) ? Yk[c * cstride + r] : Cx<R>{R(0), R(0)};
         },
         [&](int e, Cx<R> z) {
-          const int l = e / N0, x = e - l * N0;
-          buf[l * LS + x] = z;
+          // l LS + x with l = e / N0, x = e - l N0
+          buf[e + (e / N0) * (LS - N0)] = z;
         });
     __syncthreads();
     fft_lines<R, N0, NLn, LS, false, NTH>(buf, tw);
@@ -613,10 +616,10 @@ __global__ __launch_bounds__(NTH) void k_axis0_project(Cx<R>* __restrict__ Y, co
   }
   __syncthreads();
   fft_lines<R, N0, NLn, LS, true, NTH>(buf, tw);
+  Cx<R>* Yo = Y + ((long long)k2 * n1 + k1b) * N0;
   for (int e = tid; e < NLn * N0; e += NTH) {
-    const int l = e / N0, x = e - l * N0;
-    const int c = l / TC, t = l - c * TC;
-    if (t < nl) Y[(((long long)c * H + k2) * n1 + k1b + t) * N0 + x] = buf[l * LS + x];
+    const int c = e / (TC * N0), r = e - c * (TC * N0);
+    if (r < nl * N0) Yo[c * cstride + r] = buf[e + (e / N0) * (LS - N0)];
   }
 }
 
