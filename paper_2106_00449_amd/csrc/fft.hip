@@ -322,16 +322,28 @@ __global__ __launch_bounds__(NTH) void k_r2c_axis2(const R* __restrict__ in, Cx<
   const int nl = min(TL, n1 - i1b);
   load_twiddles<R, N2, NTH>(tw, twg);
   const R* src = in + (long long)c * n0 * n1 * N2 + field_plane_off(tiled, n1, N2, i0);
-  staged_copy<NLc * N2, NTH>(
-      [&](int e) {
-        const int p = e / N2, x = e - p * N2;
-        const R re = (2 * p < nl) ? src[field_col_off(tiled, N2, i1b + 2 * p, x)] : R(0);
-        const R im = (2 * p + 1 < nl) ? src[field_col_off(tiled, N2, i1b + 2 * p + 1, x)] : R(0);
-        return Cx<R>{re, im};
+  // items of four consecutive points of both lines of a pair (N2 is a
+  // multiple of 4, and of 32 in the tiled layout: a row's runs of 32 points
+  // are contiguous), one 4-vector load per line
+  typedef R R4 __attribute__((ext_vector_type(4)));
+  typedef R R8 __attribute__((ext_vector_type(8)));
+  constexpr int Q = N2 / 4;
+  staged_copy<NLc * Q, NTH>(
+      [&](int g) {
+        const int p = g / Q, x = (g - p * Q) * 4;
+        const R4 z4 = {R(0), R(0), R(0), R(0)};
+        const R4 a = (2 * p < nl) ? *reinterpret_cast<const R4*>(src + field_col_off(tiled, N2, i1b + 2 * p, x)) : z4;
+        const R4 b =
+            (2 * p + 1 < nl) ? *reinterpret_cast<const R4*>(src + field_col_off(tiled, N2, i1b + 2 * p + 1, x)) : z4;
+        return R8{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
       },
-      [&](int e, Cx<R> z) {
-        const int p = e / N2, x = e - p * N2;
-        buf[p * LS + x] = z;
+      [&](int g, R8 v) {
+        const int p = g / Q, x = (g - p * Q) * 4;
+        Cx<R>* d = buf + p * LS + x;
+        d[0] = Cx<R>{v.s0, v.s4};
+        d[1] = Cx<R>{v.s1, v.s5};
+        d[2] = Cx<R>{v.s2, v.s6};
+        d[3] = Cx<R>{v.s3, v.s7};
       });
   __syncthreads();
   fft_lines<R, N2, NLc, LS, false, NTH>(buf, tw);
@@ -365,20 +377,22 @@ __global__ __launch_bounds__(NTH) void k_fwd_axis1(const Cx<R>* __restrict__ X, 
   const int c = blockIdx.z, k2 = blockIdx.y, i0b = blockIdx.x * TL;
   const int nl = min(TL, n0 - i0b);
   load_twiddles<R, N1, NTH>(tw, twg);
+  // line t of the workgroup starts H N1 values after line t - 1; element
+  // e = t N1 + x sits at e + t (H - 1) N1 there and at e + t (LS - N1) in LDS
+  const Cx<R>* Xl = X + (((long long)c * n0 + i0b) * H + k2) * N1;
+  const long long gap = (long long)(H - 1) * N1;
   staged_copy<TL * N1, NTH>(
       [&](int e) {
-        const int t = e / N1, x = e - t * N1;
-        return (t < nl) ? X[(((long long)c * n0 + i0b + t) * H + k2) * N1 + x] : Cx<R>{R(0), R(0)};
+        const int t = e / N1;
+        return (t < nl) ? Xl[e + t * gap] : Cx<R>{R(0), R(0)};
       },
-      [&](int e, Cx<R> z) {
-        const int t = e / N1, x = e - t * N1;
-        buf[t * LS + x] = z;
-      });
+      [&](int e, Cx<R> z) { buf[e + (e / N1) * (LS - N1)] = z; });
   __syncthreads();
   fft_lines<R, N1, TL, LS, false, NTH>(buf, tw);
+  Cx<R>* Yl = Y + ((long long)c * H + k2) * N1 * n0 + i0b;
   for (int e = tid; e < N1 * TL; e += NTH) {
     const int k1 = e / TL, t = e - k1 * TL;
-    if (t < nl) Y[(((long long)c * H + k2) * N1 + k1) * n0 + i0b + t] = buf[t * LS + k1];
+    if (t < nl) Yl[(long long)k1 * n0 + t] = buf[t * LS + k1];
   }
 }
 
@@ -395,10 +409,11 @@ __global__ __launch_bounds__(NTH) void k_inv_axis1(const Cx<R>* __restrict__ Y, 
   const int c = blockIdx.z, k2 = blockIdx.y, i0b = blockIdx.x * TL;
   const int nl = min(TL, n0 - i0b);
   load_twiddles<R, N1, NTH>(tw, twg);
+  const Cx<R>* Yl = Y + ((long long)c * H + k2) * N1 * n0 + i0b;
   staged_copy<N1 * TL, NTH>(
       [&](int e) {
         const int k1 = e / TL, t = e - k1 * TL;
-        return (t < nl) ? Y[(((long long)c * H + k2) * N1 + k1) * n0 + i0b + t] : Cx<R>{R(0), R(0)};
+        return (t < nl) ? Yl[(long long)k1 * n0 + t] : Cx<R>{R(0), R(0)};
       },
       [&](int e, Cx<R> z) {
         const int k1 = e / TL, t = e - k1 * TL;
@@ -406,9 +421,12 @@ __global__ __launch_bounds__(NTH) void k_inv_axis1(const Cx<R>* __restrict__ Y, 
       });
   __syncthreads();
   fft_lines<R, N1, TL, LS, true, NTH>(buf, tw);
+  // as the loads of pass B: element e = t N1 + x at e + t (H - 1) N1
+  Cx<R>* Xl = X + (((long long)c * n0 + i0b) * H + k2) * N1;
+  const long long gap = (long long)(H - 1) * N1;
   for (int e = tid; e < TL * N1; e += NTH) {
-    const int t = e / N1, x = e - t * N1;
-    if (t < nl) X[(((long long)c * n0 + i0b + t) * H + k2) * N1 + x] = buf[t * LS + x];
+    const int t = e / N1;
+    if (t < nl) Xl[e + t * gap] = buf[e + t * (LS - N1)];
   }
 }
 
@@ -454,11 +472,18 @@ __global__ __launch_bounds__(NTH) void k_c2r_axis2(const Cx<R>* __restrict__ X, 
   __syncthreads();
   fft_lines<R, N2, NLc, LS, true, NTH>(buf, tw);
   R* dst = out + (long long)c * n0 * n1 * N2 + field_plane_off(tiled, n1, N2, i0);
-  for (int e = tid; e < NLc * N2; e += NTH) {
-    const int p = e / N2, x = e - p * N2;
-    const Cx<R> z = buf[p * LS + x];
-    if (2 * p < nl) dst[field_col_off(tiled, N2, i1b + 2 * p, x)] = z.x;
-    if (2 * p + 1 < nl) dst[field_col_off(tiled, N2, i1b + 2 * p + 1, x)] = z.y;
+  // four consecutive points of both lines of a pair per item, one 4-vector
+  // store per line (as the loads of pass A)
+  typedef R R4v __attribute__((ext_vector_type(4)));
+  constexpr int Q = N2 / 4;
+  for (int g = tid; g < NLc * Q; g += NTH) {
+    const int p = g / Q, x = (g - p * Q) * 4;
+    const Cx<R>* s4 = buf + p * LS + x;
+    const Cx<R> z0 = s4[0], z1 = s4[1], z2 = s4[2], z3 = s4[3];
+    if (2 * p < nl)
+      *reinterpret_cast<R4v*>(dst + field_col_off(tiled, N2, i1b + 2 * p, x)) = R4v{z0.x, z1.x, z2.x, z3.x};
+    if (2 * p + 1 < nl)
+      *reinterpret_cast<R4v*>(dst + field_col_off(tiled, N2, i1b + 2 * p + 1, x)) = R4v{z0.y, z1.y, z2.y, z3.y};
   }
 }
 
