@@ -687,14 +687,24 @@ __device__ __forceinline__ void plane_fwd_body(const R* __restrict__ in, Cx<R>* 
   load_twiddles<R, N1, NTH>(tw1, tw1g);
   load_twiddles<R, N2, NTH>(tw2, tw2g);
   const R* src = in + (long long)c * n0 * N1 * N2 + field_plane_off(tiled, N1, N2, i0);
-  staged_copy<NP * N2, NTH>(
-      [&](int e) {
-        const int p = e / N2, x = e - p * N2;
-        return Cx<R>{src[field_col_off(tiled, N2, 2 * p, x)], src[field_col_off(tiled, N2, 2 * p + 1, x)]};
+  // four consecutive points of both rows of a pair per item (as pass A)
+  typedef R R4 __attribute__((ext_vector_type(4)));
+  typedef R R8 __attribute__((ext_vector_type(8)));
+  constexpr int Q = N2 / 4;
+  staged_copy<NP * Q, NTH>(
+      [&](int g) {
+        const int p = g / Q, x = (g - p * Q) * 4;
+        const R4 a = *reinterpret_cast<const R4*>(src + field_col_off(tiled, N2, 2 * p, x));
+        const R4 b = *reinterpret_cast<const R4*>(src + field_col_off(tiled, N2, 2 * p + 1, x));
+        return R8{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
       },
-      [&](int e, Cx<R> z) {
-        const int p = e / N2, x = e - p * N2;
-        buf[p * L::LA + x] = z;
+      [&](int g, R8 v) {
+        const int p = g / Q, x = (g - p * Q) * 4;
+        Cx<R>* d = buf + p * L::LA + x;
+        d[0] = Cx<R>{v.s0, v.s4};
+        d[1] = Cx<R>{v.s1, v.s5};
+        d[2] = Cx<R>{v.s2, v.s6};
+        d[3] = Cx<R>{v.s3, v.s7};
       });
   __syncthreads();
   fft_lines<R, N2, NP, L::LA, false, NTH>(buf, tw2);
@@ -725,12 +735,9 @@ __device__ __forceinline__ void plane_fwd_body(const R* __restrict__ in, Cx<R>* 
   __syncthreads();
   fft_lines<R, N1, H, L::LB, false, NTH>(buf, tw1);
   Cx<R>* dst = Z + ((long long)c * n0 + i0) * H * N1;
-  staged_copy<H * N1, NTH>(
-      [&](int e) {
-        const int k = e / N1, x = e - k * N1;
-        return buf[k * L::LB + x];
-      },
-      [&](int e, Cx<R> z) { dst[e] = z; });
+  // line k of element e = k N1 + x starts LB - N1 values later per line in LDS
+  staged_copy<H * N1, NTH>([&](int e) { return buf[e + (e / N1) * (L::LB - N1)]; },
+                           [&](int e, Cx<R> z) { dst[e] = z; });
 }
 
 // Inverse of k_plane_fwd: iFFT along axis 1, then rows (2p, 2p+1) rebuilt as
@@ -767,10 +774,7 @@ __device__ __forceinline__ void plane_inv_body(const Cx<R>* __restrict__ Z, R* _
   load_twiddles<R, N2, NTH>(tw2, tw2g);
   const Cx<R>* src = Z + ((long long)c * n0 + i0) * H * N1;
   staged_copy<H * N1, NTH>([&](int e) { return src[e]; },
-                           [&](int e, Cx<R> z) {
-                             const int k = e / N1, x = e - k * N1;
-                             buf[k * L::LB + x] = z;
-                           });
+                           [&](int e, Cx<R> z) { buf[e + (e / N1) * (L::LB - N1)] = z; });
   __syncthreads();
   fft_lines<R, N1, H, L::LB, true, NTH>(buf, tw1);
   constexpr int ITEMS = NP * H, PER = (ITEMS + NTH - 1) / NTH;
@@ -804,15 +808,21 @@ __device__ __forceinline__ void plane_inv_body(const Cx<R>* __restrict__ Z, R* _
   __syncthreads();
   fft_lines<R, N2, NP, L::LA, true, NTH>(buf, tw2);
   R* dst = out + (long long)c * n0 * N1 * N2 + field_plane_off(tiled, N1, N2, i0);
-  staged_copy<NP * N2, NTH>(
-      [&](int e) {
-        const int p = e / N2, x = e - p * N2;
-        return buf[p * L::LA + x];
+  // four consecutive points of both rows of a pair per item (as pass A')
+  typedef R R8 __attribute__((ext_vector_type(8)));
+  typedef R R4v __attribute__((ext_vector_type(4)));
+  constexpr int Q = N2 / 4;
+  staged_copy<NP * Q, NTH>(
+      [&](int g) {
+        const int p = g / Q, x = (g - p * Q) * 4;
+        const Cx<R>* s4 = buf + p * L::LA + x;
+        const Cx<R> z0 = s4[0], z1 = s4[1], z2 = s4[2], z3 = s4[3];
+        return R8{z0.x, z1.x, z2.x, z3.x, z0.y, z1.y, z2.y, z3.y};
       },
-      [&](int e, Cx<R> z) {
-        const int p = e / N2, x = e - p * N2;
-        dst[field_col_off(tiled, N2, 2 * p, x)] = z.x;
-        dst[field_col_off(tiled, N2, 2 * p + 1, x)] = z.y;
+      [&](int g, R8 v) {
+        const int p = g / Q, x = (g - p * Q) * 4;
+        *reinterpret_cast<R4v*>(dst + field_col_off(tiled, N2, 2 * p, x)) = R4v{v.s0, v.s1, v.s2, v.s3};
+        *reinterpret_cast<R4v*>(dst + field_col_off(tiled, N2, 2 * p + 1, x)) = R4v{v.s4, v.s5, v.s6, v.s7};
       });
 }
 
@@ -849,18 +859,18 @@ __device__ __forceinline__ void axis0_plane_body(Cx<R>* __restrict__ Z, const Cx
   const int nl = min(TCP, P.n1 - k1b);
   const int H = P.n2h, n1 = P.n1;
   load_twiddles<R, N0, NTH>(tw, twg);
+  // element e = (c N0 + x) TCP + t: in Z at Zk[(c N0 + x) H n1 + t], in LDS
+  // at (c TCP + t) LS + x
+  Cx<R>* Zk = Z + (long long)k2 * n1 + k1b;
+  const long long hs = (long long)H * n1;
+  auto lds_at = [&](int rest, int t) { return rest + t * LS + (rest / N0) * (TCP * LS - N0); };
   if (!NOISE) {
     staged_copy<NLn * N0, NTH>(
         [&](int e) {
           const int t = e % TCP, rest = e / TCP;
-          const int x = rest % N0, c = rest / N0;
-          return (t < nl) ? Z[(((long long)c * N0 + x) * H + k2) * n1 + k1b + t] : Cx<R>{R(0), R(0)};
+          return (t < nl) ? Zk[rest * hs + t] : Cx<R>{R(0), R(0)};
         },
-        [&](int e, Cx<R> z) {
-          const int t = e % TCP, rest = e / TCP;
-          const int x = rest % N0, c = rest / N0;
-          buf[(c * TCP + t) * LS + x] = z;
-        });
+        [&](int e, Cx<R> z) { buf[lds_at(e / TCP, e % TCP)] = z; });
     __syncthreads();
     fft_lines<R, N0, NLn, LS, false, NTH>(buf, tw);
   } else {
@@ -900,17 +910,11 @@ __device__ __forceinline__ void axis0_plane_body(Cx<R>* __restrict__ Z, const Cx
   }
   __syncthreads();
   fft_lines<R, N0, NLn, LS, true, NTH>(buf, tw);
-  staged_copy<NLn * N0, NTH>(
-      [&](int e) {
-        const int t = e % TCP, rest = e / TCP;
-        const int x = rest % N0, c = rest / N0;
-        return buf[(c * TCP + t) * LS + x];
-      },
-      [&](int e, Cx<R> z) {
-        const int t = e % TCP, rest = e / TCP;
-        const int x = rest % N0, c = rest / N0;
-        if (t < nl) Z[(((long long)c * N0 + x) * H + k2) * n1 + k1b + t] = z;
-      });
+  staged_copy<NLn * N0, NTH>([&](int e) { return buf[lds_at(e / TCP, e % TCP)]; },
+                             [&](int e, Cx<R> z) {
+                               const int t = e % TCP;
+                               if (t < nl) Zk[(e / TCP) * hs + t] = z;
+                             });
 }
 
 template <typename R, int N0, bool NOISE, int NTH>
