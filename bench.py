@@ -97,12 +97,12 @@ def working_launches(each_ms):
 # region runs that did work), each scaled by the 256 MiB copy that
 # --copy-calibration adds (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Read +
 # written bytes:
-#   rods1000   k_plane_inv       24,239,605 + 25,165,824
-#   mixed4096  k_c2r_axis2      201,405,760 + 201,326,608
-#   rods32768  k_axis0_project  679,910,498 + 679,477,248 (eight lines per workgroup)
+#   rods1000   k_plane_inv       24,477,771 + 25,165,824
+#   mixed4096  k_c2r_axis2      201,422,909 + 201,326,592
+#   rods32768  k_axis0_project  679,732,859 + 679,477,248 (eight lines per workgroup)
 # A workload's entry goes back to None whenever its kernel changes, until
 # the counters are taken again.
-TRAFFIC_BYTES = {"rods1000": 49405429, "mixed4096": 402732368, "rods32768": 1359387746}
+TRAFFIC_BYTES = {"rods1000": 49643595, "mixed4096": 402749501, "rods32768": 1359210107}
 
 WORKLOAD_TEXT = {
     "rods1000": "rods1000: 1,000 rods x 10 blobs (10,000 blobs), L=128a, grid 128^3, FP32 grid / FP64 bodies "
