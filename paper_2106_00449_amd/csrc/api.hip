@@ -1315,6 +1315,10 @@ int init_impl(const gdc_config* cfg, gdc_handle* h) {
     }
     g.P[d] = (int)std::floor(2.0 * c.trunc / g.dx[d]) + 1;
   }
+  if (g.P[2] > 58) {   // averaging keeps a blob's axis-2 factors in 64 entries
+    set_error("the envelope spans " + std::to_string(g.P[2]) + " grid points along axis 2; at most 58 are supported");
+    return GDC_EINVAL;
+  }
   g.n2h = g.n[2] / 2;
   g.G = (long long)g.n[0] * g.n[1] * g.n[2];
   g.dV = g.dx[0] * g.dx[1] * g.dx[2];

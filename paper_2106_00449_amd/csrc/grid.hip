@@ -225,13 +225,38 @@ __device__ __forceinline__ void interp_body(const GridGeom& G, const double* __r
   const int skew = B.g[2] - first2;
   const int nck = (skew + P2 - 1) / CW + 1;
   const int per0 = P1 * nck;
+  // The axis-2 factors of the blob, one per entry i = a2 + skew of its
+  // nck CW points along axis 2 (lane i computes entry i): the squared
+  // distance d2^2 (FP64; +inf outside the stencil) and exp(-d2^2 / 2 sigma^2).
+  // The weight of a point is then wn exp(-(d0^2 + d1^2) / 2 sigma^2) times
+  // its entry's factor, one exponential per task instead of one per point.
+  __shared__ __align__(16) double q2s[WAVES][64];
+  __shared__ __align__(16) R e2s[WAVES][64];
+  const int wv_ix = threadIdx.x >> 6;
+  {
+    const int a2 = lane - skew;
+    double q = __builtin_huge_val();
+    R f = R(0);
+    if (a2 >= 0 && a2 < P2) {
+      const double d2 = B.e[2] + a2 * G.dx[2];
+      q = d2 * d2;
+      f = gexp<R>(-R(q) * i2);
+    }
+    q2s[wv_ix][lane] = q;
+    e2s[wv_ix][lane] = f;
+  }
+  __builtin_amdgcn_wave_barrier();
+  // tasks (a0, a1, c) by the reciprocals of per0 and nck: the exact quotient
+  // of task + 1/2 lies at least 1/(2 per0) from an integer, far beyond FP32
+  // rounding at these sizes
+  const float rp0 = 1.0f / (float)per0, rnck = 1.0f / (float)nck;
   R s0 = 0, s1 = 0, s2 = 0;
   for (int task = lane; task < P0 * per0; task += 64) {
-    const int a0 = task / per0, rem = task - a0 * per0;
-    const int a1 = rem / nck, c = rem - a1 * nck;
+    const int a0 = (int)(((float)task + 0.5f) * rp0), rem = task - a0 * per0;
+    const int a1 = (int)(((float)rem + 0.5f) * rnck), c = rem - a1 * nck;
     const double d0 = B.e[0] + a0 * G.dx[0], d1 = B.e[1] + a1 * G.dx[1];
-    const double d00 = d0 * d0, d11 = d1 * d1;
-    if (d00 + d11 > G.rc2) continue;   // the row misses the cutoff sphere
+    const double d01 = d0 * d0 + d1 * d1;
+    if (d01 > G.rc2) continue;         // the row misses the cutoff sphere
     int c2 = first2 + c * CW;          // below 2 n2: first2 < n2, c CW < CW + P2 - 1
     c2 -= (c2 >= n2) ? n2 : 0;
     const unsigned ix = (unsigned)(field_plane_off(G.tiled, n1, n2, wrap(B.g[0] + a0, n0)) +
@@ -240,13 +265,12 @@ __device__ __forceinline__ void interp_body(const GridGeom& G, const double* __r
     u0.chunk(ix, x0);
     u1.chunk(ix, x1);
     u2.chunk(ix, x2);
+    const R e01 = wn * gexp<R>(-R(d01) * i2);
 #pragma unroll
     for (int j = 0; j < CW; ++j) {
-      const int a2 = c * CW + j - skew;
-      const double d2 = B.e[2] + a2 * G.dx[2];
-      const double dd = d00 + (d11 + d2 * d2);
-      const bool ok = a2 >= 0 && a2 < P2 && dd <= G.rc2;
-      const R wv = ok ? wn * gexp<R>(-R(dd) * i2) : R(0);
+      const int i = c * CW + j;
+      const bool ok = d01 + q2s[wv_ix][i] <= G.rc2;
+      const R wv = ok ? e01 * e2s[wv_ix][i] : R(0);
       s0 += wv * x0[j];
       s1 += wv * x1[j];
       s2 += wv * x2[j];
@@ -1267,6 +1291,10 @@ int interp(const GridGeom& g, const double* r, const R* u, double* v, int M, dou
   if (M <= 0) return GDC_OK;
   if (g.n[2] % 4 != 0) {
     set_error("interp: the grid's axis 2 must be a multiple of 4 (16-byte chunks)");
+    return GDC_EINVAL;
+  }
+  if (g.P[2] + 2 * Component<R>::CW - 2 > 64) {
+    set_error("interp: the stencil is too wide along axis 2 for the 64 per-blob factors");
     return GDC_EINVAL;
   }
   RigidTerm K{blob_body, Y, V};
