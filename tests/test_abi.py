@@ -73,3 +73,17 @@ def test_ctypes_layout_matches_c_compiler(tmp_path):
     c = g._Config
     assert vals == [ctypes.sizeof(c), c.seed.offset, c.shapes.offset, c.forces.offset, c.device.offset,
                     c.stream.offset, ctypes.sizeof(g._Stats), ctypes.sizeof(g._Shape)]
+
+
+def test_footprint_rejects_stencils_too_wide_for_averaging():
+    # averaging keeps a blob's axis-2 factors in 64 entries: an envelope
+    # spanning more than 58 grid points along axis 2 is refused at set-up
+    # (gdc_footprint runs the same validation without a device)
+    import pytest
+    import paper_2106_00449_amd as g
+    import workloads as wl
+    w = wl.small_case("wide", n_bodies=4, n=(32, 32, 256), L=(24.0, 24.0, 24.0), precision="fp32")
+    kw = wl.library_kwargs(w)
+    g.footprint(**dict(kw, trunc=2.0))          # 2 trunc / dx + 1 = 43 points: accepted
+    with pytest.raises(RuntimeError, match="at most 58"):
+        g.footprint(**dict(kw, trunc=2.8))      # 60 points
