@@ -1001,9 +1001,10 @@ __device__ __forceinline__ void spread_tab_body(const GridGeom& G, const TileGeo
   }
 }
 
-// The FP32 kernels are held to 8 waves per SIMD (four workgroups per CU);
-// the ordinary launch needs 48 VGPRs and 76 SGPRs, the fused one more
-// without the target.
+// The ordinary FP32 launch is held to 8 waves per SIMD (four workgroups per
+// CU; it needs 48 VGPRs and 76 SGPRs).  The fused launch, with its
+// per-suspension arguments in registers, is left to the compiler: held to
+// the same target it would spill.
 #define GDC_SPREAD_OCCUPANCY __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 8 : 1)))
 
 template <typename R, int WZ>
@@ -1016,7 +1017,7 @@ __global__ __launch_bounds__(NTS) GDC_SPREAD_OCCUPANCY void k_spread_tab(
 
 // Spreading fused over several suspensions (one SpreadArgs each).
 template <typename R, int WZ>
-__global__ __launch_bounds__(NTS) GDC_SPREAD_OCCUPANCY void k_spread_tab_fused(
+__global__ __launch_bounds__(NTS) void k_spread_tab_fused(
     const SpreadArgs* __restrict__ a, const int* __restrict__ first, int ns) {
   const int sidx = fused_suspension(first, ns, blockIdx.x);
   const SpreadArgs& A = a[sidx];
