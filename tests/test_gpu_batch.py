@@ -147,7 +147,9 @@ def test_batch_step_resumes_a_step_left_in_flight(lib):
         s.close()
 
 
-@pytest.mark.parametrize("fusion", [False, True])
+# fusion: none, every suspension, or the server's default (32^3 grids only:
+# fused and unfused handles in the same batch calls)
+@pytest.mark.parametrize("fusion", [False, True, 32])
 def test_served_results_equal_alone(lib, fusion):
     from paper_2106_00449_amd.serving import LibraryExecutor, Request, Server, summarise
     ws = _mix() + (_fuse_mix()[:3] if fusion else [])
@@ -156,7 +158,7 @@ def test_served_results_equal_alone(lib, fusion):
     for i, (w, k) in enumerate(zip(ws, n_steps)):
         Y, q = wl.initial_state(w)
         reqs.append(Request(i, wl.library_kwargs(w, gmres_tol=1e-6), Y, q, k, arrival=0.002 * i, blobs=w.M))
-    _say("serve mix", "fused" if fusion else "streams")
+    _say("serve mix", {False: "streams", True: "fused"}.get(fusion, f"fused up to {fusion}^3"))
     # a budget that holds all but the smallest at once, so admission binds
     fps = sorted(lib.footprint(**r.kwargs) for r in reqs)
     srv = Server(hbm_budget=sum(fps[1:]), max_slots=8, executor=LibraryExecutor(fusion=fusion))
