@@ -155,3 +155,20 @@ def test_step_errors_are_attributed_to_their_own_suspension():
     assert not res[3].error and np.array_equal(res[3].Y, reqs[3].Y0 + 3)
     s = summarise(res)
     assert s["completed"] == 2 and s["rejected"] == 2
+
+
+def test_library_executor_fusion_policy():
+    # the executor fuses every suspension, none, or those whose grid edge is
+    # at most the given size (the default: 32^3 grids)
+    from paper_2106_00449_amd.serving import FUSE_MAX_GRID, LibraryExecutor
+
+    def req(n):
+        return Request(0, {"n": n}, np.zeros((1, 3)), np.zeros((1, 4)), 1)
+
+    assert LibraryExecutor().fusion == FUSE_MAX_GRID == 32
+    small, cubic48, mixed = req(32), req((48, 48, 48)), req((24, 32, 48))
+    assert LibraryExecutor()._fused(small) and not LibraryExecutor()._fused(cubic48)
+    assert not LibraryExecutor()._fused(mixed)
+    assert LibraryExecutor(fusion=48)._fused(cubic48)
+    assert all(LibraryExecutor(fusion=True)._fused(r) for r in (small, cubic48, mixed))
+    assert not any(LibraryExecutor(fusion=False)._fused(r) for r in (small, cubic48, mixed))
