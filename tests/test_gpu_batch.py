@@ -253,12 +253,13 @@ def _fuse_mix():
     ]
 
 
-@pytest.mark.parametrize("until", ["all", "any"])
-def test_fused_batch_equals_each_alone(lib, until):
+@pytest.mark.parametrize("until,graphs", [("all", True), ("any", True), ("all", False)])
+def test_fused_batch_equals_each_alone(lib, until, graphs):
     # GMRES iterations launched once per kernel for all ready suspensions
     # (each at its own Krylov column: restart 4 makes cycles end at
     # different times) give every suspension the result of stepping it
-    # alone, bit for bit
+    # alone, bit for bit; with graphs off the rest of each step is launched
+    # kernel by kernel beside the fused iterations
     ws = _fuse_mix()
     n_steps = [3, 2, 4, 3, 2]
     kw = dict(gmres_tol=1e-6, gmres_restart=4, gmres_maxit=400)
@@ -269,10 +270,11 @@ def test_fused_batch_equals_each_alone(lib, until):
         s.step(Y, q, k)
         s.close()
         ref.append((Y, q))
-    _say("fused batch", until)
+    _say("fused batch", until, "graphs" if graphs else "eager")
     ss = []
     for w in ws:
         s = lib.Suspension(**wl.library_kwargs(w, **kw))
+        s.graphs = graphs
         Y, q = wl.initial_state(w)
         s.set_state(Y, q)
         s.fusion = True
