@@ -306,6 +306,79 @@ __device__ __forceinline__ void staged_copy(Ld ld, St st) {
   }
 }
 
+// FP32 lines whose length N is a multiple of 128 move between HBM and a
+// workgroup's LDS lines (stride LS) in whole-wave runs: 128 consecutive values
+// of one line per wave, two per lane (one 16-byte access).  Line l of the NL
+// lines sits at (l / TC) cstride + (l % TC) lstride values from g.  A run's
+// line and address are wave-uniform, so the per-value index arithmetic is
+// scalar.  Lines at l % TC >= nl load as zeros and are not stored.
+template <int N, int NL, int TC, int LS, int NTH, bool STORE>
+__device__ __forceinline__ void move_runs(Cx<float>* buf, Cx<float>* g, long long cstride, long long lstride,
+                                          int nl) {
+  typedef float F4 __attribute__((ext_vector_type(4)));
+  constexpr int W = NTH / 64, RPL = N / 128, NR = NL * RPL, PW = NR / W;
+  static_assert(N % 128 == 0 && NR % W == 0, "runs per wave");
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (!STORE) {
+    F4 v[PW];
+#pragma unroll
+    for (int m = 0; m < PW; ++m) {
+      const int run = wv + m * W, l = run / RPL, x = (run - l * RPL) * 128 + 2 * lane;
+      const int c = l / TC, t = l - c * TC;
+      v[m] = t < nl ? *reinterpret_cast<const F4*>(g + c * cstride + t * lstride + x) : F4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int m = 0; m < PW; ++m) {
+      const int run = wv + m * W, l = run / RPL, x = (run - l * RPL) * 128 + 2 * lane;
+      Cx<float>* p = buf + l * LS + x;
+      p[0] = Cx<float>{v[m].x, v[m].y};
+      p[1] = Cx<float>{v[m].z, v[m].w};
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < PW; ++m) {
+      const int run = wv + m * W, l = run / RPL, x = (run - l * RPL) * 128 + 2 * lane;
+      const int c = l / TC, t = l - c * TC;
+      if (t < nl) {
+        const Cx<float>* p = buf + l * LS + x;
+        const Cx<float> a = p[0], b = p[1];
+        *reinterpret_cast<F4*>(g + c * cstride + t * lstride + x) = F4{a.x, a.y, b.x, b.y};
+      }
+    }
+  }
+}
+
+// The transposed side of the axis-1 passes (FP32, 16 lines per workgroup):
+// value k of line t sits at g[k cs + t], the 16 lines' values of one k being
+// one 128-byte segment.  A wave moves 4 consecutive k of all 16 lines per
+// run, one value per lane (lanes across lines, as the generic loops): the
+// lane's offset is fixed and a run adds a wave-uniform base.
+template <int N, int LS, int NTH, bool STORE>
+__device__ __forceinline__ void move_cols(Cx<float>* buf, Cx<float>* g, int cs, int nl) {
+  constexpr int W = NTH / 64, NR = N / 4, PW = NR / W;
+  static_assert(N % 4 == 0 && NR % W == 0, "runs per wave");
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int t = lane & 15, kl = lane >> 4;
+  const int goff = kl * cs + t;
+  const bool in = t < nl;
+  if (!STORE) {
+    Cx<float> v[PW];
+#pragma unroll
+    for (int m = 0; m < PW; ++m) {
+      const int k0 = 4 * (wv + m * W);
+      v[m] = in ? g[k0 * cs + goff] : Cx<float>{0.f, 0.f};
+    }
+#pragma unroll
+    for (int m = 0; m < PW; ++m) buf[t * LS + 4 * (wv + m * W) + kl] = v[m];
+  } else {
+#pragma unroll
+    for (int m = 0; m < PW; ++m) {
+      const int k0 = 4 * (wv + m * W);
+      if (in) g[k0 * cs + goff] = buf[t * LS + k0 + kl];
+    }
+  }
+}
+
 // ------------------------------------------------------------ pass A: R2C, axis 2
 // Two real lines packed as one complex line z = a + i b; after the FFT,
 // A(k) = (Z(k) + conj Z(N-k))/2 and B(k) = (Z(k) - conj Z(N-k))/(2i).
@@ -380,6 +453,14 @@ __global__ __launch_bounds__(NTH) void k_fwd_axis1(const Cx<R>* __restrict__ X, 
   // line t of the workgroup starts H N1 values after line t - 1; element
   // e = t N1 + x sits at e + t (H - 1) N1 there and at e + t (LS - N1) in LDS
   const Cx<R>* Xl = X + (((long long)c * n0 + i0b) * H + k2) * N1;
+  Cx<R>* Yl = Y + ((long long)c * H + k2) * N1 * n0 + i0b;
+  if constexpr (sizeof(R) == 4 && N1 % 128 == 0) {
+    move_runs<N1, TL, TL, LS, NTH, false>(buf, const_cast<Cx<R>*>(Xl), 0, (long long)H * N1, nl);
+    __syncthreads();
+    fft_lines<R, N1, TL, LS, false, NTH>(buf, tw);
+    move_cols<N1, LS, NTH, true>(buf, Yl, n0, nl);
+    return;
+  }
   const long long gap = (long long)(H - 1) * N1;
   staged_copy<TL * N1, NTH>(
       [&](int e) {
@@ -389,7 +470,6 @@ __global__ __launch_bounds__(NTH) void k_fwd_axis1(const Cx<R>* __restrict__ X, 
       [&](int e, Cx<R> z) { buf[e + (e / N1) * (LS - N1)] = z; });
   __syncthreads();
   fft_lines<R, N1, TL, LS, false, NTH>(buf, tw);
-  Cx<R>* Yl = Y + ((long long)c * H + k2) * N1 * n0 + i0b;
   for (int e = tid; e < N1 * TL; e += NTH) {
     const int k1 = e / TL, t = e - k1 * TL;
     if (t < nl) Yl[(long long)k1 * n0 + t] = buf[t * LS + k1];
@@ -410,6 +490,14 @@ __global__ __launch_bounds__(NTH) void k_inv_axis1(const Cx<R>* __restrict__ Y, 
   const int nl = min(TL, n0 - i0b);
   load_twiddles<R, N1, NTH>(tw, twg);
   const Cx<R>* Yl = Y + ((long long)c * H + k2) * N1 * n0 + i0b;
+  Cx<R>* Xl = X + (((long long)c * n0 + i0b) * H + k2) * N1;
+  if constexpr (sizeof(R) == 4 && N1 % 128 == 0) {
+    move_cols<N1, LS, NTH, false>(buf, const_cast<Cx<R>*>(Yl), n0, nl);
+    __syncthreads();
+    fft_lines<R, N1, TL, LS, true, NTH>(buf, tw);
+    move_runs<N1, TL, TL, LS, NTH, true>(buf, Xl, 0, (long long)H * N1, nl);
+    return;
+  }
   staged_copy<N1 * TL, NTH>(
       [&](int e) {
         const int k1 = e / TL, t = e - k1 * TL;
@@ -422,7 +510,6 @@ __global__ __launch_bounds__(NTH) void k_inv_axis1(const Cx<R>* __restrict__ Y, 
   __syncthreads();
   fft_lines<R, N1, TL, LS, true, NTH>(buf, tw);
   // as the loads of pass B: element e = t N1 + x at e + t (H - 1) N1
-  Cx<R>* Xl = X + (((long long)c * n0 + i0b) * H + k2) * N1;
   const long long gap = (long long)(H - 1) * N1;
   for (int e = tid; e < TL * N1; e += NTH) {
     const int t = e / N1;
@@ -577,11 +664,46 @@ __device__ bool noise_mode(const ProjParams& P, int j0, int j1, int j2, double u
   return true;
 }
 
+// The Stokes projection of the TC spectrum lines in LDS (FP32, N0 a multiple
+// of 128), in whole-wave runs of 64 modes of one line: a run's j1, its k_y,
+// its first signed index along axis 0 and the tests for removed modes are
+// wave-uniform.  u = (c/k^2) (f - k (k.f)/k^2), c = 1/(eta G), with 1/k^2 from
+// the hardware reciprocal (1 ulp); removed modes (Nyquist along axis 0 or 1,
+// k = 0) and lines past n1 get a zero factor.
+template <int N0, int TC, int LS, int NTH>
+__device__ __forceinline__ void project_runs(Cx<float>* buf, const ProjParams& P, int k2, int k1b, int nl) {
+  constexpr int W = NTH / 64, RPL = N0 / 64, NR = TC * RPL;
+  static_assert(N0 % 128 == 0 && NR % W == 0, "runs per wave");
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int n1 = P.n1;
+  const float fl = (float)lane, kz = float(P.kf2) * float(k2), c0 = float(P.inv_eta * P.invG);
+  const float kf0 = float(P.kf0), kf1 = float(P.kf1);
+#pragma unroll
+  for (int m = 0; m < NR / W; ++m) {
+    const int run = wv + m * W, t = run / RPL, jr = run - t * RPL, j1 = k1b + t;
+    const int m0 = jr < RPL / 2 ? 64 * jr : 64 * jr - N0;
+    const float ky = kf1 * float(signed_index(j1, n1));
+    const float kx = kf0 * (fl + float(m0));
+    const float kk = fused_ma(kx, kx, fused_ma(ky, ky, kz * kz));
+    const bool drop = t >= nl || j1 == n1 / 2 || (lane == 0 && (jr == RPL / 2 || (jr == 0 && j1 == 0 && k2 == 0)));
+    const float ik = drop ? 0.f : __builtin_amdgcn_rcpf(kk);
+    const float s1 = c0 * ik, s2 = s1 * ik;
+    Cx<float>* p = buf + t * LS + 64 * jr + lane;
+    const Cx<float> f0 = p[0], f1 = p[TC * LS], f2 = p[2 * TC * LS];
+    const float dr = fused_ma(kx, f0.x, fused_ma(ky, f1.x, kz * f2.x)) * s2;
+    const float di = fused_ma(kx, f0.y, fused_ma(ky, f1.y, kz * f2.y)) * s2;
+    p[0] = Cx<float>{fused_ma(-kx, dr, s1 * f0.x), fused_ma(-kx, di, s1 * f0.y)};
+    p[TC * LS] = Cx<float>{fused_ma(-ky, dr, s1 * f1.x), fused_ma(-ky, di, s1 * f1.y)};
+    p[2 * TC * LS] = Cx<float>{fused_ma(-kz, dr, s1 * f2.x), fused_ma(-kz, di, s1 * f2.y)};
+  }
+}
+
 template <typename R, int N0, bool NOISE, int NTH>
 __global__ __launch_bounds__(NTH) void k_axis0_project(Cx<R>* __restrict__ Y, const Cx<R>* __restrict__ twg,
                                                       ProjParams P, const int* __restrict__ skip) {
   if (skip && *skip) return;
   constexpr int TC = Tiles<R>::TC, NLn = 3 * TC, LS = N0 + 1;
+  constexpr bool RUNS = sizeof(R) == 4 && N0 % 128 == 0;
   __shared__ Cx<R> buf[NLn * LS];
   __shared__ Cx<R> tw[N0];
   const int tid = threadIdx.x;
@@ -592,6 +714,17 @@ __global__ __launch_bounds__(NTH) void k_axis0_project(Cx<R>* __restrict__ Y, co
   // component c's TC lines are one contiguous run of TC N0 values
   const long long cstride = (long long)H * n1 * N0;
   const Cx<R>* Yk = Y + ((long long)k2 * n1 + k1b) * N0;
+  if constexpr (RUNS && !NOISE) {
+    move_runs<N0, 3 * TC, TC, LS, NTH, false>(buf, Y + ((long long)k2 * n1 + k1b) * N0, cstride, N0, nl);
+    __syncthreads();
+    fft_lines<R, N0, NLn, LS, false, NTH>(buf, tw);
+    __syncthreads();
+    project_runs<N0, TC, LS, NTH>(buf, P, k2, k1b, nl);
+    __syncthreads();
+    fft_lines<R, N0, NLn, LS, true, NTH>(buf, tw);
+    move_runs<N0, 3 * TC, TC, LS, NTH, true>(buf, Y + ((long long)k2 * n1 + k1b) * N0, cstride, N0, nl);
+    return;
+  }
   if (!NOISE) {
     staged_copy<NLn * N0, NTH>(
         [&](int e) {
@@ -642,9 +775,13 @@ __global__ __launch_bounds__(NTH) void k_axis0_project(Cx<R>* __restrict__ Y, co
   __syncthreads();
   fft_lines<R, N0, NLn, LS, true, NTH>(buf, tw);
   Cx<R>* Yo = Y + ((long long)k2 * n1 + k1b) * N0;
-  for (int e = tid; e < NLn * N0; e += NTH) {
-    const int c = e / (TC * N0), r = e - c * (TC * N0);
-    if (r < nl * N0) Yo[c * cstride + r] = buf[e + (e / N0) * (LS - N0)];
+  if constexpr (RUNS) {
+    move_runs<N0, 3 * TC, TC, LS, NTH, true>(buf, Yo, cstride, N0, nl);
+  } else {
+    for (int e = tid; e < NLn * N0; e += NTH) {
+      const int c = e / (TC * N0), r = e - c * (TC * N0);
+      if (r < nl * N0) Yo[c * cstride + r] = buf[e + (e / N0) * (LS - N0)];
+    }
   }
 }
 
