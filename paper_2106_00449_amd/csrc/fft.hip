@@ -379,6 +379,13 @@ __device__ __forceinline__ void move_cols(Cx<float>* buf, Cx<float>* g, int cs, 
   }
 }
 
+// Offset of a lane's two points in a 128-point run of a real row: point
+// 128 jr + 2 lane of row i1 sits at field_col_off(i1, 128 jr) plus this (in
+// the tiled layout a row's runs of 32 points are 2048 values apart).
+__device__ __forceinline__ int run_lane_off(int tiled, int lane) {
+  return tiled ? ((lane >> 4) << 11) + 2 * (lane & 15) : 2 * lane;
+}
+
 // ------------------------------------------------------------ pass A: R2C, axis 2
 // Two real lines packed as one complex line z = a + i b; after the FFT,
 // A(k) = (Z(k) + conj Z(N-k))/2 and B(k) = (Z(k) - conj Z(N-k))/(2i).
@@ -400,6 +407,47 @@ __global__ __launch_bounds__(NTH) void k_r2c_axis2(const R* __restrict__ in, Cx<
   // are contiguous), one 4-vector load per line
   typedef R R4 __attribute__((ext_vector_type(4)));
   typedef R R8 __attribute__((ext_vector_type(8)));
+  Cx<R>* dst = X + ((long long)c * n0 + i0) * H * n1 + i1b;
+  if constexpr (sizeof(R) == 4 && N2 % 128 == 0) {
+    // whole-wave runs: 128 points of both rows of a line pair per run, two
+    // per lane; the transposed store of the split spectra four k (all 16
+    // lines) per run, lanes across the lines
+    typedef float F2 __attribute__((ext_vector_type(2)));
+    constexpr int W = NTH / 64, RPL = N2 / 128, NR = NLc * RPL, PW = NR / W, PK = H / 4 / W;
+    static_assert(NR % W == 0 && (H / 4) % W == 0, "runs per wave");
+    const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lo = run_lane_off(tiled, lane);
+    F2 va[PW], vb[PW];
+#pragma unroll
+    for (int m = 0; m < PW; ++m) {
+      const int run = wv + m * W, p = run / RPL, jr = run - p * RPL, i1 = i1b + 2 * p;
+      va[m] = 2 * p < nl ? *reinterpret_cast<const F2*>(src + field_col_off(tiled, N2, i1, 128 * jr) + lo)
+                         : F2{0.f, 0.f};
+      vb[m] = 2 * p + 1 < nl ? *reinterpret_cast<const F2*>(src + field_col_off(tiled, N2, i1 + 1, 128 * jr) + lo)
+                             : F2{0.f, 0.f};
+    }
+#pragma unroll
+    for (int m = 0; m < PW; ++m) {
+      const int run = wv + m * W, p = run / RPL, jr = run - p * RPL;
+      Cx<R>* d = buf + p * LS + 128 * jr + 2 * lane;
+      d[0] = Cx<R>{va[m].x, vb[m].x};
+      d[1] = Cx<R>{va[m].y, vb[m].y};
+    }
+    __syncthreads();
+    fft_lines<R, N2, NLc, LS, false, NTH>(buf, tw);
+    const int t = lane & 15, kl = lane >> 4, q = t >> 1, goff = kl * n1 + t;
+#pragma unroll
+    for (int m = 0; m < PK; ++m) {
+      const int k0 = 4 * (wv + m * W), k = k0 + kl;
+      if (t < nl) {
+        const Cx<R> z = buf[q * LS + k];
+        const Cx<R> zc = buf[q * LS + (k == 0 ? 0 : N2 - k)];
+        dst[k0 * n1 + goff] = (t & 1) ? Cx<R>{R(0.5) * (z.y + zc.y), R(0.5) * (zc.x - z.x)}
+                                      : Cx<R>{R(0.5) * (z.x + zc.x), R(0.5) * (z.y - zc.y)};
+      }
+    }
+    return;
+  }
   constexpr int Q = N2 / 4;
   staged_copy<NLc * Q, NTH>(
       [&](int g) {
@@ -420,7 +468,6 @@ __global__ __launch_bounds__(NTH) void k_r2c_axis2(const R* __restrict__ in, Cx<
       });
   __syncthreads();
   fft_lines<R, N2, NLc, LS, false, NTH>(buf, tw);
-  Cx<R>* dst = X + ((long long)c * n0 + i0) * H * n1 + i1b;
   for (int e = tid; e < H * TL; e += NTH) {
     const int k = e / TL, t = e - k * TL;
     if (t < nl) {
@@ -537,6 +584,49 @@ __global__ __launch_bounds__(NTH) void k_c2r_axis2(const Cx<R>* __restrict__ X, 
   const Cx<R> zero{R(0), R(0)};
   // the two values of an item as one native 4-vector (kept in registers)
   typedef R R4 __attribute__((ext_vector_type(4)));
+  R* dst = out + (long long)c * n0 * n1 * N2 + field_plane_off(tiled, n1, N2, i0);
+  if constexpr (sizeof(R) == 4 && N2 % 128 == 0) {
+    // the transposed load eight k (all 8 line pairs) per run, a lane's pair
+    // in one 16-byte load; the real rows in whole-wave runs of 128 points of
+    // both rows of a pair, two per lane
+    typedef float F2 __attribute__((ext_vector_type(2)));
+    constexpr int W = NTH / 64, PK = H / 8 / W, RPL = N2 / 128, NR = NLc * RPL, PW = NR / W;
+    static_assert((H / 8) % W == 0 && NR % W == 0, "runs per wave");
+    const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int q = lane & 7, kl = lane >> 3, goff = kl * n1 + 2 * q;
+    R4 v[PK];
+#pragma unroll
+    for (int m = 0; m < PK; ++m) {
+      const Cx<R>* sp = src + 8 * (wv + m * W) * n1 + goff;
+      v[m] = 2 * q + 1 < nl ? *reinterpret_cast<const R4*>(sp)
+                            : (2 * q < nl ? R4{sp[0].x, sp[0].y, R(0), R(0)} : R4{R(0), R(0), R(0), R(0)});
+    }
+#pragma unroll
+    for (int m = 0; m < PK; ++m) {
+      const int k = 8 * (wv + m * W) + kl;
+      const Cx<R> a{v[m].x, v[m].y}, b{v[m].z, v[m].w};
+      if (k == 0) {
+        buf[q * LS] = Cx<R>{a.x, b.x};
+        buf[q * LS + H] = zero;
+      } else {
+        buf[q * LS + k] = Cx<R>{a.x - b.y, a.y + b.x};
+        buf[q * LS + N2 - k] = Cx<R>{a.x + b.y, b.x - a.y};
+      }
+    }
+    __syncthreads();
+    fft_lines<R, N2, NLc, LS, true, NTH>(buf, tw);
+    const int lo = run_lane_off(tiled, lane);
+#pragma unroll
+    for (int m = 0; m < PW; ++m) {
+      const int run = wv + m * W, p = run / RPL, jr = run - p * RPL, i1 = i1b + 2 * p;
+      const Cx<R>* s2 = buf + p * LS + 128 * jr + 2 * lane;
+      const Cx<R> z0 = s2[0], z1 = s2[1];
+      if (2 * p < nl) *reinterpret_cast<F2*>(dst + field_col_off(tiled, N2, i1, 128 * jr) + lo) = F2{z0.x, z1.x};
+      if (2 * p + 1 < nl)
+        *reinterpret_cast<F2*>(dst + field_col_off(tiled, N2, i1 + 1, 128 * jr) + lo) = F2{z0.y, z1.y};
+    }
+    return;
+  }
   staged_copy<H * NLc, NTH>(
       [&](int e) {
         const int k = e / NLc, p = e - k * NLc;
@@ -558,7 +648,6 @@ __global__ __launch_bounds__(NTH) void k_c2r_axis2(const Cx<R>* __restrict__ X, 
       });
   __syncthreads();
   fft_lines<R, N2, NLc, LS, true, NTH>(buf, tw);
-  R* dst = out + (long long)c * n0 * n1 * N2 + field_plane_off(tiled, n1, N2, i0);
   // four consecutive points of both lines of a pair per item, one 4-vector
   // store per line (as the loads of pass A)
   typedef R R4v __attribute__((ext_vector_type(4)));

@@ -65,7 +65,8 @@ def test_philox_normals_bit_identical(lib):
                                       ("fp32", (48, 48, 48), (32.0, 32.0, 32.0)),
                                       ("fp64", (48, 48, 48), (32.0, 32.0, 32.0)),
                                       ("fp32", (128, 12, 24), (96.0, 12.0, 19.0)),
-                                      ("fp32", (24, 128, 256), (18.0, 96.0, 192.0))])
+                                      ("fp32", (24, 128, 256), (18.0, 96.0, 192.0)),
+                                      ("fp32", (12, 12, 128), (9.0, 9.0, 96.0))])
 def test_fluct_velocity_field(lib, prec, n, L):
     w = wl.small_case(n=n, L=L, precision=prec, seed=11)
     _say("fluct", prec, n)
@@ -106,6 +107,9 @@ CASES = [
     # 256 (whole-wave runs) and n0 = 24: the last workgroup of axis-1 lines
     # holds 8 of its 16
     ("wide128", (24, 128, 256), (18.0, 96.0, 192.0), [wl.rod(4), wl.boomerang()]),
+    # axis-2 lines of 128 in the untiled field layout (8 does not divide
+    # n0 = n1 = 12), six of a workgroup's eight line pairs present
+    ("slab12", (12, 12, 128), (9.0, 9.0, 96.0), [wl.rod(3), wl.tetrahedron()]),
 ]
 
 
