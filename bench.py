@@ -57,17 +57,18 @@ TARGET_ERR = 1e-5
 
 # Dominant kernel of each workload's step (largest share of GPU time in its
 # kernel trace) as (probe family, kernel, algorithmic bytes per launch from G
-# grid points and M blobs).  At 384^3 it is the projection pass of the
-# five-pass transform (FFT along axis 0, Stokes projection, inverse FFT along
-# axis 0, the spectrum read once and written once: three half spectra of
-# G/2 complex FP32 values each, in and out, 24 G bytes), once per GMRES
-# iteration.  At 256^3 the C2R pass moves the same 24 G; at 128^3 the inverse
+# grid points and M blobs).  At 384^3 it is the inverse axis-1 pass of the
+# five-pass transform (three half spectra of G/2 complex FP32 values read
+# and written once, 24 G bytes), once per GMRES iteration and once per step
+# in the noise field's transform; per launch it ties with the projection
+# pass (FFT along axis 0, Stokes projection, inverse FFT along axis 0, also
+# 24 G).  At 256^3 the C2R pass moves the same 24 G; at 128^3 the inverse
 # plane pass of the three-pass transform reads the three half spectra and
 # writes the three real components, 24 G as well.
 DOMINANT = {
     "rods1000": ("fft_plane_inv", "k_plane_inv", lambda G, M: 24 * G),
     "mixed4096": ("fft_c2r", "k_c2r_axis2", lambda G, M: 24 * G),
-    "rods32768": ("fft_project", "k_axis0_project", lambda G, M: 24 * G),
+    "rods32768": ("fft_inv1", "k_inv_axis1", lambda G, M: 24 * G),
 }
 # Spreading, for the kernel table: the FP32 force field written once
 # (3 components x 4 B per grid point) plus, per blob, its sorted stencil
@@ -98,11 +99,11 @@ def working_launches(each_ms):
 # --copy-calibration adds (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Read +
 # written bytes:
 #   rods1000   k_plane_inv       24,477,771 + 25,165,824
-#   mixed4096  k_c2r_axis2      201,422,909 + 201,326,592
-#   rods32768  k_axis0_project  679,732,859 + 679,477,248 (eight lines per workgroup)
+#   mixed4096  k_c2r_axis2      201,412,082 + 201,326,592 (whole-wave runs, 256 threads)
+#   rods32768  k_inv_axis1      679,552,906 + 679,477,248 (whole-wave runs, 512 threads)
 # A workload's entry goes back to None whenever its kernel changes, until
 # the counters are taken again.
-TRAFFIC_BYTES = {"rods1000": 49643595, "mixed4096": 402749501, "rods32768": 1359210107}
+TRAFFIC_BYTES = {"rods1000": 49643595, "mixed4096": 402738674, "rods32768": 1359030154}
 
 WORKLOAD_TEXT = {
     "rods1000": "rods1000: 1,000 rods x 10 blobs (10,000 blobs), L=128a, grid 128^3, FP32 grid / FP64 bodies "

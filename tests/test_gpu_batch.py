@@ -179,7 +179,9 @@ def test_served_results_equal_alone(lib, fusion):
 @pytest.mark.parametrize("prec,n,L", [("fp32", 32, 24.0), ("fp32", (24, 32, 48), (20.0, 24.0, 36.0)),
                                       ("fp64", 32, 24.0),
                                       # five-pass, every pass moving whole-wave runs
-                                      ("fp32", (128, 128, 256), (96.0, 96.0, 192.0))])
+                                      ("fp32", (128, 128, 256), (96.0, 96.0, 192.0)),
+                                      # ragged lines along axis 1 in the projection pass
+                                      ("fp32", (128, 12, 24), (96.0, 12.0, 19.0))])
 def test_every_fft_launch_shape_gives_identical_results(lib, prec, n, L):
     # the autotuner only chooses among workgroup sizes that distribute the
     # same arithmetic: forcing each size must give the same mobility bit for bit
