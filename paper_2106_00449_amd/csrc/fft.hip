@@ -348,14 +348,16 @@ __device__ __forceinline__ void move_runs(Cx<float>* buf, Cx<float>* g, long lon
   }
 }
 
-// The transposed side of the axis-1 passes (FP32, 16 lines per workgroup):
-// value k of line t sits at g[k cs + t], the 16 lines' values of one k being
-// one 128-byte segment.  A wave moves 4 consecutive k of all 16 lines per
-// run, one value per lane (lanes across lines, as the generic loops): the
-// lane's offset is fixed and a run adds a wave-uniform base.
-template <int N, int LS, int NTH, bool STORE>
-__device__ __forceinline__ void move_cols(Cx<float>* buf, Cx<float>* g, int cs, int nl) {
-  constexpr int W = NTH / 64, NR = N / 4, PW = NR / W;
+// The transposed side of the axis-1 passes and of the plane projection
+// (FP32, 16 lines per component and workgroup): value k of line t of
+// component c sits at g[c gcs + k cs + t] (the 16 lines' values of one k are
+// one 128-byte segment) and at buf[c bcs + t LS + k] in LDS.  A wave moves 4
+// consecutive k of the 16 lines of one component per run, one value per lane
+// (lanes across lines, as the generic loops): the lane's offset is fixed and
+// a run adds a wave-uniform base.
+template <int N, int NC, int LS, int NTH, bool STORE>
+__device__ __forceinline__ void move_cols(Cx<float>* buf, Cx<float>* g, int cs, long long gcs, int bcs, int nl) {
+  constexpr int W = NTH / 64, RPC = N / 4, NR = NC * RPC, PW = NR / W;
   static_assert(N % 4 == 0 && NR % W == 0, "runs per wave");
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int t = lane & 15, kl = lane >> 4;
@@ -365,16 +367,19 @@ __device__ __forceinline__ void move_cols(Cx<float>* buf, Cx<float>* g, int cs, 
     Cx<float> v[PW];
 #pragma unroll
     for (int m = 0; m < PW; ++m) {
-      const int k0 = 4 * (wv + m * W);
-      v[m] = in ? g[k0 * cs + goff] : Cx<float>{0.f, 0.f};
+      const int run = wv + m * W, c = run / RPC, k0 = 4 * (run - c * RPC);
+      v[m] = in ? g[c * gcs + k0 * cs + goff] : Cx<float>{0.f, 0.f};
     }
 #pragma unroll
-    for (int m = 0; m < PW; ++m) buf[t * LS + 4 * (wv + m * W) + kl] = v[m];
+    for (int m = 0; m < PW; ++m) {
+      const int run = wv + m * W, c = run / RPC, k0 = 4 * (run - c * RPC);
+      buf[c * bcs + t * LS + k0 + kl] = v[m];
+    }
   } else {
 #pragma unroll
     for (int m = 0; m < PW; ++m) {
-      const int k0 = 4 * (wv + m * W);
-      if (in) g[k0 * cs + goff] = buf[t * LS + k0 + kl];
+      const int run = wv + m * W, c = run / RPC, k0 = 4 * (run - c * RPC);
+      if (in) g[c * gcs + k0 * cs + goff] = buf[c * bcs + t * LS + k0 + kl];
     }
   }
 }
@@ -505,7 +510,7 @@ __global__ __launch_bounds__(NTH) void k_fwd_axis1(const Cx<R>* __restrict__ X, 
     move_runs<N1, TL, TL, LS, NTH, false>(buf, const_cast<Cx<R>*>(Xl), 0, (long long)H * N1, nl);
     __syncthreads();
     fft_lines<R, N1, TL, LS, false, NTH>(buf, tw);
-    move_cols<N1, LS, NTH, true>(buf, Yl, n0, nl);
+    move_cols<N1, 1, LS, NTH, true>(buf, Yl, n0, 0, 0, nl);
     return;
   }
   const long long gap = (long long)(H - 1) * N1;
@@ -539,7 +544,7 @@ __global__ __launch_bounds__(NTH) void k_inv_axis1(const Cx<R>* __restrict__ Y, 
   const Cx<R>* Yl = Y + ((long long)c * H + k2) * N1 * n0 + i0b;
   Cx<R>* Xl = X + (((long long)c * n0 + i0b) * H + k2) * N1;
   if constexpr (sizeof(R) == 4 && N1 % 128 == 0) {
-    move_cols<N1, LS, NTH, false>(buf, const_cast<Cx<R>*>(Yl), n0, nl);
+    move_cols<N1, 1, LS, NTH, false>(buf, const_cast<Cx<R>*>(Yl), n0, 0, 0, nl);
     __syncthreads();
     fft_lines<R, N1, TL, LS, true, NTH>(buf, tw);
     move_runs<N1, TL, TL, LS, NTH, true>(buf, Xl, 0, (long long)H * N1, nl);
@@ -754,15 +759,17 @@ __device__ bool noise_mode(const ProjParams& P, int j0, int j1, int j2, double u
 }
 
 // The Stokes projection of the TC spectrum lines in LDS (FP32, N0 a multiple
-// of 128), in whole-wave runs of 64 modes of one line: a run's j1, its k_y,
-// its first signed index along axis 0 and the tests for removed modes are
-// wave-uniform.  u = (c/k^2) (f - k (k.f)/k^2), c = 1/(eta G), with 1/k^2 from
-// the hardware reciprocal (1 ulp); removed modes (Nyquist along axis 0 or 1,
-// k = 0) and lines past n1 get a zero factor.
+// of 64), in whole-wave runs of 64 modes of one line: a run's j1, its k_y and
+// the tests for removed modes along axis 1 are wave-uniform, and so is its
+// first signed index along axis 0 when N0 is a multiple of 128 (a run then
+// lies within one half of the line).  u = (c/k^2) (f - k (k.f)/k^2),
+// c = 1/(eta G), with 1/k^2 from the hardware reciprocal (1 ulp); removed
+// modes (Nyquist along axis 0 or 1, k = 0) and lines past n1 get a zero
+// factor.
 template <int N0, int TC, int LS, int NTH>
 __device__ __forceinline__ void project_runs(Cx<float>* buf, const ProjParams& P, int k2, int k1b, int nl) {
   constexpr int W = NTH / 64, RPL = N0 / 64, NR = TC * RPL;
-  static_assert(N0 % 128 == 0 && NR % W == 0, "runs per wave");
+  static_assert(N0 % 64 == 0 && NR % W == 0, "runs per wave");
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int n1 = P.n1;
   const float fl = (float)lane, kz = float(P.kf2) * float(k2), c0 = float(P.inv_eta * P.invG);
@@ -770,11 +777,20 @@ __device__ __forceinline__ void project_runs(Cx<float>* buf, const ProjParams& P
 #pragma unroll
   for (int m = 0; m < NR / W; ++m) {
     const int run = wv + m * W, t = run / RPL, jr = run - t * RPL, j1 = k1b + t;
-    const int m0 = jr < RPL / 2 ? 64 * jr : 64 * jr - N0;
     const float ky = kf1 * float(signed_index(j1, n1));
-    const float kx = kf0 * (fl + float(m0));
+    float kx;
+    bool nyq;
+    if constexpr (N0 % 128 == 0) {
+      const int m0 = jr < RPL / 2 ? 64 * jr : 64 * jr - N0;
+      kx = kf0 * (fl + float(m0));   // the sum is an exact small integer
+      nyq = lane == 0 && jr == RPL / 2;
+    } else {
+      const int j0 = 64 * jr + lane;
+      kx = kf0 * float(j0 < N0 / 2 ? j0 : j0 - N0);
+      nyq = j0 == N0 / 2;
+    }
     const float kk = fused_ma(kx, kx, fused_ma(ky, ky, kz * kz));
-    const bool drop = t >= nl || j1 == n1 / 2 || (lane == 0 && (jr == RPL / 2 || (jr == 0 && j1 == 0 && k2 == 0)));
+    const bool drop = t >= nl || j1 == n1 / 2 || nyq || (lane == 0 && jr == 0 && j1 == 0 && k2 == 0);
     const float ik = drop ? 0.f : __builtin_amdgcn_rcpf(kk);
     const float s1 = c0 * ik, s2 = s1 * ik;
     Cx<float>* p = buf + t * LS + 64 * jr + lane;
@@ -1090,7 +1106,15 @@ __device__ __forceinline__ void axis0_plane_body(Cx<R>* __restrict__ Z, const Cx
   Cx<R>* Zk = Z + (long long)k2 * n1 + k1b;
   const long long hs = (long long)H * n1;
   auto lds_at = [&](int rest, int t) { return rest + t * LS + (rest / N0) * (TCP * LS - N0); };
-  if (!NOISE) {
+  // FP32 lines of a length that splits into runs: the moves in whole-wave
+  // runs, and the projection in runs of 64 modes when 64 divides the length
+  constexpr bool COLS = sizeof(R) == 4 && N0 % 32 == 0;
+  constexpr bool PRUNS = sizeof(R) == 4 && N0 % 64 == 0;
+  if constexpr (COLS && !NOISE) {
+    move_cols<N0, 3, LS, NTH, false>(buf, Zk, (int)hs, N0 * hs, TCP * LS, nl);
+    __syncthreads();
+    fft_lines<R, N0, NLn, LS, false, NTH>(buf, tw);
+  } else if (!NOISE) {
     staged_copy<NLn * N0, NTH>(
         [&](int e) {
           const int t = e % TCP, rest = e / TCP;
@@ -1102,6 +1126,9 @@ __device__ __forceinline__ void axis0_plane_body(Cx<R>* __restrict__ Z, const Cx
   } else {
     __syncthreads();
   }
+  if constexpr (PRUNS && !NOISE) {
+    project_runs<N0, TCP, LS, NTH>(buf, P, k2, k1b, nl);
+  } else {
   for (int e = tid; e < TCP * N0; e += NTH) {
     const int t = e / N0, j0 = e - t * N0;
     const int j1 = k1b + t;
@@ -1134,13 +1161,18 @@ __device__ __forceinline__ void axis0_plane_body(Cx<R>* __restrict__ Z, const Cx
 #pragma unroll
     for (int a = 0; a < 3; ++a) buf[(a * TCP + t) * LS + j0] = u[a];
   }
+  }
   __syncthreads();
   fft_lines<R, N0, NLn, LS, true, NTH>(buf, tw);
-  staged_copy<NLn * N0, NTH>([&](int e) { return buf[lds_at(e / TCP, e % TCP)]; },
-                             [&](int e, Cx<R> z) {
-                               const int t = e % TCP;
-                               if (t < nl) Zk[(e / TCP) * hs + t] = z;
-                             });
+  if constexpr (COLS) {
+    move_cols<N0, 3, LS, NTH, true>(buf, Zk, (int)hs, N0 * hs, TCP * LS, nl);
+  } else {
+    staged_copy<NLn * N0, NTH>([&](int e) { return buf[lds_at(e / TCP, e % TCP)]; },
+                               [&](int e, Cx<R> z) {
+                                 const int t = e % TCP;
+                                 if (t < nl) Zk[(e / TCP) * hs + t] = z;
+                               });
+  }
 }
 
 template <typename R, int N0, bool NOISE, int NTH>
