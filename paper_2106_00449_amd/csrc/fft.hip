@@ -355,6 +355,43 @@ __device__ __forceinline__ void move_runs(Cx<float>* buf, Cx<float>* g, long lon
 // consecutive k of the 16 lines of one component per run, one value per lane
 // (lanes across lines, as the generic loops): the lane's offset is fixed and
 // a run adds a wave-uniform base.
+// The loads of such a move into registers (cols_fetch) and their LDS
+// writes (cols_put), apart, so that a workgroup can fetch its next tile
+// while it works on the current one.
+template <int N, int NC, int NTH>
+struct ColsRegs {
+  static constexpr int W = NTH / 64, RPC = N / 4, NR = NC * RPC, PW = NR / W;
+  static_assert(N % 4 == 0 && NR % W == 0, "runs per wave");
+  Cx<float> v[PW];
+};
+
+template <int N, int NC, int NTH>
+__device__ __forceinline__ void cols_fetch(ColsRegs<N, NC, NTH>& r, const Cx<float>* g, int cs, long long gcs,
+                                           int nl) {
+  using C = ColsRegs<N, NC, NTH>;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int t = lane & 15, kl = lane >> 4;
+  const int goff = kl * cs + t;
+  const bool in = t < nl;
+#pragma unroll
+  for (int m = 0; m < C::PW; ++m) {
+    const int run = wv + m * C::W, c = run / C::RPC, k0 = 4 * (run - c * C::RPC);
+    r.v[m] = in ? g[c * gcs + k0 * cs + goff] : Cx<float>{0.f, 0.f};
+  }
+}
+
+template <int N, int NC, int LS, int NTH>
+__device__ __forceinline__ void cols_put(Cx<float>* buf, const ColsRegs<N, NC, NTH>& r, int bcs) {
+  using C = ColsRegs<N, NC, NTH>;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int t = lane & 15, kl = lane >> 4;
+#pragma unroll
+  for (int m = 0; m < C::PW; ++m) {
+    const int run = wv + m * C::W, c = run / C::RPC, k0 = 4 * (run - c * C::RPC);
+    buf[c * bcs + t * LS + k0 + kl] = r.v[m];
+  }
+}
+
 template <int N, int NC, int LS, int NTH, bool STORE>
 __device__ __forceinline__ void move_cols(Cx<float>* buf, Cx<float>* g, int cs, long long gcs, int bcs, int nl) {
   constexpr int W = NTH / 64, RPC = N / 4, NR = NC * RPC, PW = NR / W;
@@ -364,17 +401,9 @@ __device__ __forceinline__ void move_cols(Cx<float>* buf, Cx<float>* g, int cs, 
   const int goff = kl * cs + t;
   const bool in = t < nl;
   if (!STORE) {
-    Cx<float> v[PW];
-#pragma unroll
-    for (int m = 0; m < PW; ++m) {
-      const int run = wv + m * W, c = run / RPC, k0 = 4 * (run - c * RPC);
-      v[m] = in ? g[c * gcs + k0 * cs + goff] : Cx<float>{0.f, 0.f};
-    }
-#pragma unroll
-    for (int m = 0; m < PW; ++m) {
-      const int run = wv + m * W, c = run / RPC, k0 = 4 * (run - c * RPC);
-      buf[c * bcs + t * LS + k0 + kl] = v[m];
-    }
+    ColsRegs<N, NC, NTH> r;
+    cols_fetch<N, NC, NTH>(r, g, cs, gcs, nl);
+    cols_put<N, NC, LS, NTH>(buf, r, bcs);
   } else {
 #pragma unroll
     for (int m = 0; m < PW; ++m) {
@@ -528,6 +557,13 @@ __global__ __launch_bounds__(NTH) void k_fwd_axis1(const Cx<R>* __restrict__ X, 
   }
 }
 
+// Tiles of Tiles<R>::TL lines per workgroup of the inverse axis-1 pass: two
+// on the FP32 run path (the second fetched during the first's transform).
+template <typename R, int N1>
+constexpr int inv1_tiles() {
+  return (sizeof(R) == 4 && N1 % 128 == 0) ? 2 : 1;
+}
+
 // ------------------------------------------------------------ pass B': iFFT, axis 1
 template <typename R, int N1, int NTH>
 __global__ __launch_bounds__(NTH) void k_inv_axis1(const Cx<R>* __restrict__ Y, Cx<R>* __restrict__ X,
@@ -543,11 +579,27 @@ __global__ __launch_bounds__(NTH) void k_inv_axis1(const Cx<R>* __restrict__ Y, 
   load_twiddles<R, N1, NTH>(tw, twg);
   const Cx<R>* Yl = Y + ((long long)c * H + k2) * N1 * n0 + i0b;
   Cx<R>* Xl = X + (((long long)c * n0 + i0b) * H + k2) * N1;
-  if constexpr (sizeof(R) == 4 && N1 % 128 == 0) {
-    move_cols<N1, 1, LS, NTH, false>(buf, const_cast<Cx<R>*>(Yl), n0, 0, 0, nl);
+  if constexpr (inv1_tiles<R, N1>() == 2) {
+    // two tiles of TL lines per workgroup (i0 blocks 2 x and 2 x + 1): the
+    // second tile's loads go to registers before the first tile's
+    // transform, so that their latency overlaps that work
+    const int i0a = blockIdx.x * 2 * TL, i0c = i0a + TL;
+    const int nla = min(TL, n0 - i0a), nlc = min(TL, n0 - i0c);
+    const Cx<R>* Ya = Y + ((long long)c * H + k2) * N1 * n0 + i0a;
+    ColsRegs<N1, 1, NTH> next;
+    move_cols<N1, 1, LS, NTH, false>(buf, const_cast<Cx<R>*>(Ya), n0, 0, 0, nla);
+    if (nlc > 0) cols_fetch<N1, 1, NTH>(next, Ya + TL, n0, 0, nlc);
     __syncthreads();
     fft_lines<R, N1, TL, LS, true, NTH>(buf, tw);
-    move_runs<N1, TL, TL, LS, NTH, true>(buf, Xl, 0, (long long)H * N1, nl);
+    move_runs<N1, TL, TL, LS, NTH, true>(buf, X + (((long long)c * n0 + i0a) * H + k2) * N1, 0, (long long)H * N1,
+                                         nla);
+    if (nlc <= 0) return;
+    __syncthreads();
+    cols_put<N1, 1, LS, NTH>(buf, next, 0);
+    __syncthreads();
+    fft_lines<R, N1, TL, LS, true, NTH>(buf, tw);
+    move_runs<N1, TL, TL, LS, NTH, true>(buf, X + (((long long)c * n0 + i0c) * H + k2) * N1, 0, (long long)H * N1,
+                                         nlc);
     return;
   }
   staged_copy<N1 * TL, NTH>(
@@ -1242,9 +1294,11 @@ template <typename R>
 int launch_inv1(int n1, const Cx<R>* Y, Cx<R>* X, const Cx<R>* tw, int n0, int H, int nth, hipStream_t s,
                 const int* skip) {
   if (!nth_ok(nth, false)) return GDC_EINVAL;
-  dim3 grid((n0 + Tiles<R>::TL - 1) / Tiles<R>::TL, H, 3);
+  const int tiles = (n0 + Tiles<R>::TL - 1) / Tiles<R>::TL;
   const ProbeEvents pe = probe_claim("fft_inv1");
-#define L_(N, T) GDC_LAUNCH_PROBED((k_inv_axis1<R, N, T>), grid, dim3(T), 0, s, pe, Y, X, tw, n0, H, skip)
+#define L_(N, T)                                                                                           \
+  GDC_LAUNCH_PROBED((k_inv_axis1<R, N, T>), dim3((tiles + inv1_tiles<R, N>() - 1) / inv1_tiles<R, N>(), H, 3), \
+                    dim3(T), 0, s, pe, Y, X, tw, n0, H, skip)
   switch (n1) {
 #define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
     GDC_FFT_SIZES(X_)
