@@ -60,9 +60,9 @@ TARGET_ERR = 1e-5
 # grid points and M blobs).  At 384^3 it is the inverse axis-1 pass of the
 # five-pass transform (three half spectra of G/2 complex FP32 values read
 # and written once, 24 G bytes), once per GMRES iteration and once per step
-# in the noise field's transform; per launch it ties with the projection
-# pass (FFT along axis 0, Stokes projection, inverse FFT along axis 0, also
-# 24 G).  At 256^3 the C2R pass moves the same 24 G; at 128^3 the inverse
+# in the noise field's transform, which gives it a slightly larger share of
+# the step than the projection pass (FFT along axis 0, Stokes projection,
+# inverse FFT along axis 0, also 24 G), a little longer per launch.  At 256^3 the C2R pass moves the same 24 G; at 128^3 the inverse
 # plane pass of the three-pass transform reads the three half spectra and
 # writes the three real components, 24 G as well.
 DOMINANT = {
@@ -100,10 +100,10 @@ def working_launches(each_ms):
 # written bytes:
 #   rods1000   k_plane_inv       24,477,771 + 25,165,824
 #   mixed4096  k_c2r_axis2      201,412,082 + 201,326,592 (whole-wave runs, 256 threads)
-#   rods32768  k_inv_axis1      679,552,906 + 679,477,248 (whole-wave runs, 512 threads)
+#   rods32768  k_inv_axis1      679,681,496 + 679,477,248 (two tiles per workgroup, 512 threads)
 # A workload's entry goes back to None whenever its kernel changes, until
 # the counters are taken again.
-TRAFFIC_BYTES = {"rods1000": 49643595, "mixed4096": 402738674, "rods32768": 1359030154}
+TRAFFIC_BYTES = {"rods1000": 49643595, "mixed4096": 402738674, "rods32768": 1359158744}
 
 WORKLOAD_TEXT = {
     "rods1000": "rods1000: 1,000 rods x 10 blobs (10,000 blobs), L=128a, grid 128^3, FP32 grid / FP64 bodies "
