@@ -621,6 +621,13 @@ __global__ __launch_bounds__(NTH) void k_inv_axis1(const Cx<R>* __restrict__ Y, 
   }
 }
 
+// Blocks of Tiles<R>::TL lines per workgroup of the C2R pass: two on the
+// FP32 run path (the second fetched during the first's transform).
+template <typename R, int N2>
+constexpr int c2r_tiles() {
+  return (sizeof(R) == 4 && N2 % 128 == 0) ? 2 : 1;
+}
+
 // ------------------------------------------------------------ pass A': C2R, axis 2
 // Z(k) = A(k) + i B(k) with the Hermitian extension A(N-k) = conj A(k); the
 // k = 0 term keeps only real parts (as a real inverse transform does) and the
@@ -642,46 +649,68 @@ __global__ __launch_bounds__(NTH) void k_c2r_axis2(const Cx<R>* __restrict__ X, 
   // the two values of an item as one native 4-vector (kept in registers)
   typedef R R4 __attribute__((ext_vector_type(4)));
   R* dst = out + (long long)c * n0 * n1 * N2 + field_plane_off(tiled, n1, N2, i0);
-  if constexpr (sizeof(R) == 4 && N2 % 128 == 0) {
+  if constexpr (c2r_tiles<R, N2>() == 2) {
     // the transposed load eight k (all 8 line pairs) per run, a lane's pair
     // in one 16-byte load; the real rows in whole-wave runs of 128 points of
-    // both rows of a pair, two per lane
+    // both rows of a pair, two per lane.  Two blocks of TL lines per
+    // workgroup (2 x and 2 x + 1 along axis 1): the second block's loads go
+    // to registers before the first block's transform, so that their
+    // latency overlaps that work.
     typedef float F2 __attribute__((ext_vector_type(2)));
     constexpr int W = NTH / 64, PK = H / 8 / W, RPL = N2 / 128, NR = NLc * RPL, PW = NR / W;
     static_assert((H / 8) % W == 0 && NR % W == 0, "runs per wave");
     const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int q = lane & 7, kl = lane >> 3, goff = kl * n1 + 2 * q;
-    R4 v[PK];
+    const int i1a = blockIdx.x * 2 * TL, i1c = i1a + TL;
+    const int nla = min(TL, n1 - i1a), nlc = min(TL, n1 - i1c);
+    const Cx<R>* srca = X + ((long long)c * n0 + i0) * H * n1 + i1a;
+    auto fetch = [&](R4* v, const Cx<R>* sb, int nlb) {
 #pragma unroll
-    for (int m = 0; m < PK; ++m) {
-      const Cx<R>* sp = src + 8 * (wv + m * W) * n1 + goff;
-      v[m] = 2 * q + 1 < nl ? *reinterpret_cast<const R4*>(sp)
-                            : (2 * q < nl ? R4{sp[0].x, sp[0].y, R(0), R(0)} : R4{R(0), R(0), R(0), R(0)});
-    }
-#pragma unroll
-    for (int m = 0; m < PK; ++m) {
-      const int k = 8 * (wv + m * W) + kl;
-      const Cx<R> a{v[m].x, v[m].y}, b{v[m].z, v[m].w};
-      if (k == 0) {
-        buf[q * LS] = Cx<R>{a.x, b.x};
-        buf[q * LS + H] = zero;
-      } else {
-        buf[q * LS + k] = Cx<R>{a.x - b.y, a.y + b.x};
-        buf[q * LS + N2 - k] = Cx<R>{a.x + b.y, b.x - a.y};
+      for (int m = 0; m < PK; ++m) {
+        const Cx<R>* sp = sb + 8 * (wv + m * W) * n1 + goff;
+        v[m] = 2 * q + 1 < nlb ? *reinterpret_cast<const R4*>(sp)
+                               : (2 * q < nlb ? R4{sp[0].x, sp[0].y, R(0), R(0)} : R4{R(0), R(0), R(0), R(0)});
       }
-    }
+    };
+    auto put = [&](const R4* v) {
+#pragma unroll
+      for (int m = 0; m < PK; ++m) {
+        const int k = 8 * (wv + m * W) + kl;
+        const Cx<R> a{v[m].x, v[m].y}, b{v[m].z, v[m].w};
+        if (k == 0) {
+          buf[q * LS] = Cx<R>{a.x, b.x};
+          buf[q * LS + H] = zero;
+        } else {
+          buf[q * LS + k] = Cx<R>{a.x - b.y, a.y + b.x};
+          buf[q * LS + N2 - k] = Cx<R>{a.x + b.y, b.x - a.y};
+        }
+      }
+    };
+    const int lo = run_lane_off(tiled, lane);
+    auto store = [&](int i1s, int nlb) {
+#pragma unroll
+      for (int m = 0; m < PW; ++m) {
+        const int run = wv + m * W, p = run / RPL, jr = run - p * RPL, i1 = i1s + 2 * p;
+        const Cx<R>* s2 = buf + p * LS + 128 * jr + 2 * lane;
+        const Cx<R> z0 = s2[0], z1 = s2[1];
+        if (2 * p < nlb) *reinterpret_cast<F2*>(dst + field_col_off(tiled, N2, i1, 128 * jr) + lo) = F2{z0.x, z1.x};
+        if (2 * p + 1 < nlb)
+          *reinterpret_cast<F2*>(dst + field_col_off(tiled, N2, i1 + 1, 128 * jr) + lo) = F2{z0.y, z1.y};
+      }
+    };
+    R4 va[PK], vc[PK];
+    fetch(va, srca, nla);
+    put(va);
+    if (nlc > 0) fetch(vc, srca + TL, nlc);
     __syncthreads();
     fft_lines<R, N2, NLc, LS, true, NTH>(buf, tw);
-    const int lo = run_lane_off(tiled, lane);
-#pragma unroll
-    for (int m = 0; m < PW; ++m) {
-      const int run = wv + m * W, p = run / RPL, jr = run - p * RPL, i1 = i1b + 2 * p;
-      const Cx<R>* s2 = buf + p * LS + 128 * jr + 2 * lane;
-      const Cx<R> z0 = s2[0], z1 = s2[1];
-      if (2 * p < nl) *reinterpret_cast<F2*>(dst + field_col_off(tiled, N2, i1, 128 * jr) + lo) = F2{z0.x, z1.x};
-      if (2 * p + 1 < nl)
-        *reinterpret_cast<F2*>(dst + field_col_off(tiled, N2, i1 + 1, 128 * jr) + lo) = F2{z0.y, z1.y};
-    }
+    store(i1a, nla);
+    if (nlc <= 0) return;
+    __syncthreads();
+    put(vc);
+    __syncthreads();
+    fft_lines<R, N2, NLc, LS, true, NTH>(buf, tw);
+    store(i1c, nlc);
     return;
   }
   staged_copy<H * NLc, NTH>(
@@ -1313,9 +1342,11 @@ template <typename R>
 int launch_c2r(int n2, const Cx<R>* X, R* out, const Cx<R>* tw, int n0, int n1, int tiled, int nth, hipStream_t s,
                const int* skip) {
   if (!nth_ok(nth, false)) return GDC_EINVAL;
-  dim3 grid((n1 + Tiles<R>::TL - 1) / Tiles<R>::TL, n0, 3);
+  const int tiles = (n1 + Tiles<R>::TL - 1) / Tiles<R>::TL;
   const ProbeEvents pe = probe_claim("fft_c2r");
-#define L_(N, T) GDC_LAUNCH_PROBED((k_c2r_axis2<R, N, T>), grid, dim3(T), 0, s, pe, X, out, tw, n0, n1, tiled, skip)
+#define L_(N, T)                                                                                          \
+  GDC_LAUNCH_PROBED((k_c2r_axis2<R, N, T>), dim3((tiles + c2r_tiles<R, N>() - 1) / c2r_tiles<R, N>(), n0, 3), \
+                    dim3(T), 0, s, pe, X, out, tw, n0, n1, tiled, skip)
   switch (n2) {
 #define X_(N) case N: if (nth == 512) L_(N, 512); else L_(N, 256); break;
     GDC_FFT_SIZES(X_)
