@@ -99,11 +99,11 @@ def working_launches(each_ms):
 # --copy-calibration adds (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Read +
 # written bytes:
 #   rods1000   k_plane_inv       24,477,771 + 25,165,824
-#   mixed4096  k_c2r_axis2      201,412,082 + 201,326,592 (whole-wave runs, 256 threads)
+#   mixed4096  k_c2r_axis2      201,495,749 + 201,326,592 (two blocks per workgroup, 256 threads)
 #   rods32768  k_inv_axis1      679,681,496 + 679,477,248 (two tiles per workgroup, 512 threads)
 # A workload's entry goes back to None whenever its kernel changes, until
 # the counters are taken again.
-TRAFFIC_BYTES = {"rods1000": 49643595, "mixed4096": 402738674, "rods32768": 1359158744}
+TRAFFIC_BYTES = {"rods1000": 49643595, "mixed4096": 402822341, "rods32768": 1359158744}
 
 WORKLOAD_TEXT = {
     "rods1000": "rods1000: 1,000 rods x 10 blobs (10,000 blobs), L=128a, grid 128^3, FP32 grid / FP64 bodies "
