@@ -354,10 +354,9 @@ __device__ __forceinline__ void move_runs(Cx<float>* buf, Cx<float>* g, long lon
 // one 128-byte segment) and at buf[c bcs + t LS + k] in LDS.  A wave moves 4
 // consecutive k of the 16 lines of one component per run, one value per lane
 // (lanes across lines, as the generic loops): the lane's offset is fixed and
-// a run adds a wave-uniform base.
-// The loads of such a move into registers (cols_fetch) and their LDS
-// writes (cols_put), apart, so that a workgroup can fetch its next tile
-// while it works on the current one.
+// a run adds a wave-uniform base.  The loads of a move go into registers
+// (cols_fetch) apart from their LDS writes (cols_put), so that a workgroup
+// can fetch its next block of lines while it works on the current one.
 template <int N, int NC, int NTH>
 struct ColsRegs {
   static constexpr int W = NTH / 64, RPC = N / 4, NR = NC * RPC, PW = NR / W;
