@@ -905,16 +905,16 @@ __device__ __forceinline__ void spread_tab_body(const GridGeom& G, const TileGeo
       const int hm = __builtin_amdgcn_readlane(hmask, h);
       if (!((hm >> wave) & 1)) continue;
       const R l0 = read_lane(hl0, h), l1 = read_lane(hl1, h), l2 = read_lane(hl2, h);
-      // the hit's axis-0 factors, the same for every lane: scalar loads from
-      // the table in global memory (h is wave-uniform)
-      const HitTab<R, WZ>& tg = tabs[start + hb + h];
+      const HitTab<R, WZ>& t = tab[h];
+      // the hit's axis-0 factors, the same for every lane: read from the
+      // round's table in LDS at one address for the whole wave (h is
+      // wave-uniform)
       R f0s[TX], s0s[TX];
 #pragma unroll
       for (int k = 0; k < TX; ++k) {
-        f0s[k] = tg.f0[k];
-        s0s[k] = tg.s0[k];
+        f0s[k] = t.f0[k];
+        s0s[k] = t.s0[k];
       }
-      const HitTab<R, WZ>& t = tab[h];
       // this lane's entry of the hit's axis-2 window (outside it: no weight)
       const int zz = z - (WZ == 32 ? 0 : __builtin_amdgcn_readlane(hzlo, h));
       const bool zin = (unsigned)zz < (unsigned)WZ;
