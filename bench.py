@@ -18,9 +18,10 @@ at full size), the FP64 oracle's own solve (1e-10) wherever the oracle fits
 in the run (the 1,000-rod suspension and the serving buckets).
 
 Beside the headline figure the JSON line carries:
-  roofline      the step's dominant kernel (at 384^3 the projection pass of the
-                five-pass 3D transform) against HBM peak, duration measured
-                live with dispatch-stamped events on its launch stream;
+  roofline      the step's dominant kernel (at 384^3 the inverse axis-1 pass of
+                the five-pass 3D transform) against HBM peak, duration
+                measured live with dispatch-stamped events on its launch
+                stream;
   kernels       achieved bandwidth of spreading, averaging and each FFT pass;
   fp64_single   the same suspension on the plain FP64 path;
   rods1000      the 1,000-rod suspension (128^3), calibrated against the
